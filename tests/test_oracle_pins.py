@@ -1,0 +1,332 @@
+"""Pins of the FP64 oracle against facts that do not come from the oracle itself:
+special-case delays, the impulse response, a point scatterer produced by the
+independent forward model, invariants of a linear beamformer, closed forms of
+DMAS, and a brute-force re-evaluation that interpolates with numpy.interp.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from synth import Geometry, point_phantom, simulate_rf
+
+
+def small_geom(**kw):
+    base = dict(n_channels=16, n_samples=512, angles_deg=(0.0,), nx=12, nz=20,
+                x_min=-2.4e-3, x_max=2.4e-3, z_min=4e-3, z_max=12e-3, f_number=1.0)
+    base.update(kw)
+    return Geometry(**base)
+
+
+# ----------------------------------------------------------------------- delays
+def test_interp_matches_numpy_interp_on_zero_padded_record():
+    rng = np.random.default_rng(0)
+    u = rng.standard_normal(9)
+    padded = np.concatenate([[0.0], u, [0.0]])
+    grid = np.arange(-1, len(u) + 1, dtype=np.float64)
+    for s in [-3.0, -1.0, -0.75, -0.25, 0.0, 0.5, 3.25, 7.999, 8.0, 8.5, 9.0, 12.0]:
+        ref = np.interp(s, grid, padded, left=0.0, right=0.0)
+        assert oracle.interp(u, s) == pytest.approx(ref, abs=1e-15)
+
+
+def test_delay_on_axis_is_round_trip():
+    # non-steered, pixel straight below element e: down and back along z
+    g = small_geom()
+    for e in [0, 5, 15]:
+        for z in [1e-3, 7.3e-3, 30e-3]:
+            s = oracle.tof_samples(g, 0, e, g.elem_x[e], z)
+            assert s == pytest.approx(2 * z * g.fs / g.c, rel=1e-14)
+
+
+def test_delay_3_4_5_triangle():
+    g = small_geom()
+    e = 3
+    x = g.elem_x[e] + 3e-3
+    s = oracle.tof_samples(g, 0, e, x, 4e-3)
+    assert s == pytest.approx((4e-3 + 5e-3) * g.fs / g.c, rel=1e-14)
+    x = g.elem_x[e] - 3e-3  # the receive path is symmetric in x - x_e
+    assert oracle.tof_samples(g, 0, e, x, 4e-3) == pytest.approx(s, rel=1e-14)
+
+
+@pytest.mark.parametrize("deg", [30.0, -30.0])
+def test_delay_steered_wave_reaches_each_element_when_it_fires(deg):
+    # A plane wave steered by theta is launched by delaying element e by
+    # (x_e - x_first) sin(theta) / c; for a point on the array face at element
+    # e the receive path is zero, so the total is exactly that firing delay.
+    g = small_geom(angles_deg=(deg,))
+    first = g.elem_x[0] if deg > 0 else g.elem_x[-1]
+    for e in [0, 7, 15]:
+        s = oracle.tof_samples(g, 0, e, g.elem_x[e], 0.0)
+        expect = (g.elem_x[e] - first) * math.sin(math.radians(deg)) * g.fs / g.c
+        assert s == pytest.approx(expect, abs=1e-12)
+        assert s >= -1e-12  # nothing fires before time zero
+
+
+def test_delay_t0_shifts_sample_index():
+    g = small_geom(angles_deg=(0.0, 6.0), t0=(0.0, 1.25e-6))
+    s_a = oracle.tof_samples(g.replace(t0=(0.0, 0.0)), 1, 4, 1e-3, 8e-3)
+    s_b = oracle.tof_samples(g, 1, 4, 1e-3, 8e-3)
+    assert s_a - s_b == pytest.approx(1.25e-6 * g.fs, rel=1e-12)
+
+
+# ----------------------------------------------------------------- apodization
+def test_hann_apodization_points():
+    g = small_geom(f_number=1.5)
+    e = 6
+    z = 9e-3
+    a = z / (2 * 1.5)  # half-aperture
+    xe = g.elem_x[e]
+    assert oracle.apod_weight(g, e, xe, z) == pytest.approx(1.0)
+    assert oracle.apod_weight(g, e, xe + a / 2, z) == pytest.approx(0.5, abs=1e-15)
+    assert oracle.apod_weight(g, e, xe - a / 2, z) == pytest.approx(0.5, abs=1e-15)
+    assert oracle.apod_weight(g, e, xe + a, z) == 0.0
+    assert oracle.apod_weight(g, e, xe + 1.01 * a, z) == 0.0
+    assert oracle.apod_weight(g, e, xe, 0.0) == 0.0
+    assert oracle.apod_weight(g, e, xe, -1e-3) == 0.0
+    rng = np.random.default_rng(1)
+    for d in rng.uniform(0, a, 20):
+        # Hann as a squared cosine over the half-aperture: cos^2(pi d / (2 a))
+        assert oracle.apod_weight(g, e, xe + d, z) == pytest.approx(
+            math.cos(math.pi * d / (2 * a)) ** 2, abs=1e-14)
+
+
+def test_boxcar_and_none_apodization():
+    g = small_geom(apod="boxcar", f_number=2.0)
+    z = 8e-3
+    assert oracle.apod_weight(g, 2, g.elem_x[2] + 1.9e-3, z) == 1.0
+    assert oracle.apod_weight(g, 2, g.elem_x[2] + 2.1e-3, z) == 0.0
+    g = small_geom(apod="none")
+    assert oracle.apod_weight(g, 2, 50e-3, -3e-3) == 1.0
+
+
+# ------------------------------------------------------------- impulse response
+@pytest.mark.parametrize("deg", [0.0, 7.0])
+def test_impulse_response_is_weighted_triangle_on_isodelay_arc(deg):
+    g = small_geom(angles_deg=(deg,), nx=10, nz=200, z_min=2e-3, z_max=14e-3)
+    e, nstar = 9, 150
+    rf = np.zeros((1, g.n_channels, g.n_samples))
+    rf[0, e, nstar] = 1.0
+    img = oracle.das(g, rf, 0)
+    expect = np.zeros_like(img)
+    for ix, x in enumerate(g.x_pix):
+        for iz, z in enumerate(g.z_pix):
+            s = oracle.tof_samples(g, 0, e, x, z)
+            expect[ix, iz] = oracle.apod_weight(g, e, x, z) * max(0.0, 1.0 - abs(s - nstar))
+    np.testing.assert_allclose(img, expect, atol=1e-14)
+    assert np.count_nonzero(img) > 10  # the arc crosses the grid
+
+
+# ---------------------------------------------------------------- point target
+@pytest.mark.parametrize("deg,ix,iz", [(0.0, 20, 30), (8.0, 13, 41), (-8.0, 29, 22),
+                                       (0.0, 3, 50)])
+def test_point_scatterer_peaks_at_its_own_pixel(deg, ix, iz):
+    # The echo is generated by the independent forward model in synth; the
+    # beamformed image of one noise-free scatterer placed on a pixel centre must
+    # peak at that pixel.
+    g = Geometry(n_channels=48, n_samples=1024, angles_deg=(deg,), nx=40, nz=64,
+                 x_min=-6e-3, x_max=6e-3, z_min=8e-3, z_max=14.4e-3, f_number=1.0)
+    ph = point_phantom([[g.x_pix[ix], g.z_pix[iz]]], amp=1.0)
+    rf = simulate_rf(g, ph, snr_db=None, quantize=False)["master"]
+    img = np.abs(oracle.das(g, rf, 0))
+    assert np.unravel_index(np.argmax(img), img.shape) == (ix, iz)
+    env = oracle.envelope_z(oracle.das(g, rf, 0))
+    assert np.unravel_index(np.argmax(env), env.shape) == (ix, iz)
+
+
+def test_point_scatterer_compound_peaks_at_its_own_pixel():
+    g = Geometry(n_channels=48, n_samples=1024, angles_deg=(-10.0, -4.0, 2.0, 10.0), nx=40,
+                 nz=64, x_min=-6e-3, x_max=6e-3, z_min=8e-3, z_max=14.4e-3, f_number=1.0)
+    ph = point_phantom([[g.x_pix[25], g.z_pix[17]]])
+    rf = simulate_rf(g, ph, snr_db=None, quantize=False)["master"]
+    for a in range(g.n_angles):
+        img = np.abs(oracle.das(g, rf, a))
+        assert np.unravel_index(np.argmax(img), img.shape) == (25, 17)
+    img = np.abs(oracle.das(g, rf, -1))
+    assert np.unravel_index(np.argmax(img), img.shape) == (25, 17)
+
+
+# ------------------------------------------------------------------ invariants
+def _rand_rf(g, seed):
+    return np.random.default_rng(seed).standard_normal((g.n_angles, g.n_channels, g.n_samples))
+
+
+def test_das_is_linear_in_rf():
+    g = small_geom(angles_deg=(-5.0, 3.0))
+    a, b = _rand_rf(g, 1), _rand_rf(g, 2)
+    lhs = oracle.das(g, 2.5 * a - 0.75 * b, -1)
+    rhs = 2.5 * oracle.das(g, a, -1) - 0.75 * oracle.das(g, b, -1)
+    np.testing.assert_allclose(lhs, rhs, atol=1e-11 * np.abs(rhs).max())
+
+
+def test_das_channel_superposition():
+    g = small_geom(n_channels=6)
+    rf = _rand_rf(g, 3)
+    total = oracle.das(g, rf, 0)
+    parts = np.zeros_like(total)
+    for e in range(g.n_channels):
+        one = np.zeros_like(rf)
+        one[:, e] = rf[:, e]
+        parts += oracle.das(g, one, 0)
+    np.testing.assert_allclose(total, parts, atol=1e-12 * np.abs(total).max())
+
+
+def test_compound_is_sum_of_angles():
+    g = small_geom(angles_deg=(-10.0, 0.0, 4.0))
+    rf = _rand_rf(g, 4)
+    per = sum(oracle.das(g.replace(angles_deg=(g.angles_deg[a],)), rf[a:a + 1], 0)
+              for a in range(3))
+    np.testing.assert_allclose(oracle.das(g, rf, -1), per, atol=1e-12 * np.abs(per).max())
+    perd = sum(oracle.dmas(g.replace(angles_deg=(g.angles_deg[a],)), rf[a:a + 1], 0)
+               for a in range(3))
+    np.testing.assert_allclose(oracle.compound(g, rf, "dmas"), perd,
+                               atol=1e-12 * np.abs(perd).max())
+
+
+@pytest.mark.parametrize("mode", ["das", "dmas"])
+def test_mirror_symmetry(mode):
+    # A symmetric array and grid: mirroring x, the steering angle and the element
+    # order mirrors the image along x.
+    g = small_geom(angles_deg=(6.0,), x_min=-2.4e-3, x_max=2.4e-3)
+    gm = g.replace(angles_deg=(-6.0,))
+    rf = _rand_rf(g, 5)
+    rfm = rf[:, ::-1, :]
+    f = oracle.das if mode == "das" else oracle.dmas
+    img = f(g, rf, 0)
+    imgm = f(gm, rfm, 0)
+    np.testing.assert_allclose(imgm[::-1, :], img, atol=1e-11 * np.abs(img).max())
+
+
+# ------------------------------------------------------------------------ DMAS
+@pytest.mark.parametrize("apod,deg", [("hann", 0.0), ("none", 5.0), ("boxcar", -3.0)])
+def test_dmas_pairs_equal_identity(apod, deg):
+    g = small_geom(apod=apod, angles_deg=(deg,), n_channels=24)
+    rf = _rand_rf(g, 6)
+    p = oracle.dmas(g, rf, 0, "pairs")
+    i = oracle.dmas(g, rf, 0, "identity")
+    np.testing.assert_allclose(i, p, atol=1e-11 * np.abs(p).max())
+
+
+def test_dmas_of_equal_signals():
+    # every delayed sample equal to u (w = 1): each of the N(N-1)/2 pairs gives |u|
+    g = small_geom(apod="none", n_channels=10, n_samples=2048)
+    u = -3.7
+    rf = np.full((1, g.n_channels, g.n_samples), u)
+    img = oracle.dmas(g, rf, 0)
+    n = g.n_channels
+    np.testing.assert_allclose(img, n * (n - 1) / 2 * abs(u), rtol=1e-13)
+
+
+def test_dmas_two_channels_closed_form():
+    # N = 2: y = w1 w2 sign(v1 v2) sqrt|v1 v2|; the weight stays outside the root
+    g = small_geom(n_channels=2, f_number=0.6, x_min=-1.2e-3, x_max=1.2e-3)
+    rf = _rand_rf(g, 7)
+    gn = g.replace(apod="none")
+    v = []
+    for e in range(2):
+        one = np.zeros_like(rf)
+        one[:, e] = rf[:, e]
+        v.append(oracle.das(gn, one, 0))
+    w = np.zeros((2, g.nx, g.nz))
+    for e in range(2):
+        for ix, x in enumerate(g.x_pix):
+            for iz, z in enumerate(g.z_pix):
+                w[e, ix, iz] = oracle.apod_weight(g, e, x, z)
+    expect = w[0] * w[1] * np.sign(v[0] * v[1]) * np.sqrt(np.abs(v[0] * v[1]))
+    assert np.count_nonzero(w[0] * w[1]) > 10
+    np.testing.assert_allclose(oracle.dmas(g, rf, 0), expect, atol=1e-13)
+
+
+# ------------------------------------------------------------ brute force 4x4
+def brute_das_dmas(g, rf):
+    """Independent evaluation: numpy.interp on a zero-padded record, Hann as a
+    squared cosine, angle-outer loop order."""
+    A, N, Ns = rf.shape
+    das = np.zeros((g.nx, g.nz))
+    dmas = np.zeros((g.nx, g.nz))
+    grid = np.arange(-1, Ns + 1, dtype=np.float64)
+    for a in range(A):
+        th = math.radians(g.angles_deg[a])
+        fire = g.elem_x * math.sin(th)
+        fire = fire - fire.min()  # firing delay of each element, in metres of path
+        for ix in range(g.nx):
+            x = g.x_min + (ix + 0.5) * (g.x_max - g.x_min) / g.nx
+            for iz in range(g.nz):
+                z = g.z_min + (iz + 0.5) * (g.z_max - g.z_min) / g.nz
+                # transmit path measured from the first-firing element's wavefront
+                path_tx = x * math.sin(th) + z * math.cos(th) - (g.elem_x * math.sin(th)).min()
+                sh = []
+                for e in range(N):
+                    path_rx = math.hypot(x - g.elem_x[e], z)
+                    s = (path_tx + path_rx) / g.c * g.fs - g.t0_s[a] * g.fs
+                    padded = np.concatenate([[0.0], rf[a, e], [0.0]])
+                    v = float(np.interp(s, grid, padded, left=0.0, right=0.0))
+                    half = z / (2 * g.f_number)
+                    d = abs(x - g.elem_x[e])
+                    w = math.cos(math.pi * d / (2 * half)) ** 2 if (z > 0 and d < half) else 0.0
+                    das[ix, iz] += w * v
+                    sh.append(w * math.copysign(math.sqrt(abs(v)), v) if v != 0 else 0.0)
+                for i in range(N):
+                    for j in range(i + 1, N):
+                        dmas[ix, iz] += sh[i] * sh[j]
+    return das, dmas
+
+
+@pytest.mark.parametrize("seed,angles", [(11, (0.0,)), (12, (-9.0, 3.0, 10.0))])
+def test_brute_force_4x4(seed, angles):
+    g = Geometry(n_channels=8, n_samples=400, angles_deg=angles, nx=4, nz=4, x_min=-1e-3,
+                 x_max=1.4e-3, z_min=5e-3, z_max=6.2e-3, f_number=0.8, t0=(0.3e-6,) * len(angles))
+    rf = _rand_rf(g, seed)
+    bd, bm = brute_das_dmas(g, rf)
+    np.testing.assert_allclose(oracle.das(g, rf, -1), bd, atol=1e-12 * np.abs(bd).max())
+    np.testing.assert_allclose(oracle.compound(g, rf, "dmas"), bm, atol=1e-12 * np.abs(bm).max())
+    assert np.abs(bd).max() > 0 and np.abs(bm).max() > 0
+
+
+# ------------------------------------------------------------- post-processing
+@pytest.mark.parametrize("nz", [16, 64, 256, 1024])
+def test_envelope_of_integer_bin_tone_is_one(nz):
+    n = np.arange(nz)
+    cols = np.stack([np.cos(2 * np.pi * k * n / nz + ph) for k, ph in
+                     [(1, 0.0), (3, 0.4), (nz // 4, 1.0), (nz // 2 - 1, -0.3)]])
+    np.testing.assert_allclose(oracle.envelope_z(cols), 1.0, atol=1e-12)
+
+
+def test_envelope_of_am_tone():
+    # Bedrosian: a slow modulation times a faster carrier keeps its modulation as envelope
+    nz = 512
+    n = np.arange(nz)
+    m = 1.0 + 0.5 * np.cos(2 * np.pi * 3 * n / nz)
+    col = m * np.cos(2 * np.pi * 40 * n / nz + 0.2)
+    np.testing.assert_allclose(oracle.envelope_z(col[None])[0], m, atol=1e-12)
+
+
+def test_bandpass_keeps_band_and_removes_rest():
+    nz, dz, c, f0 = 512, 25e-6, 1540.0, 5e6
+    n = np.arange(nz)
+    fbin = c / (2 * nz * dz)  # round-trip frequency of one bin
+    k_in = int(round(2 * f0 / fbin))  # 2 f0, in band
+    k_lo = int(math.floor(0.5 * f0 / fbin))  # below f0
+    k_hi = int(math.ceil(3.0 * f0 / fbin)) + 2  # just above 3 f0
+    assert k_hi < nz // 2
+    tone_in = np.cos(2 * np.pi * k_in * n / nz + 0.3)
+    out = oracle.bandpass_z((tone_in + 0.7 * np.cos(2 * np.pi * k_lo * n / nz)
+                             + 0.2 * np.sin(2 * np.pi * k_hi * n / nz) + 1.5)[None], dz, c, f0)
+    np.testing.assert_allclose(out[0], tone_in, atol=1e-12)
+    # the edges of the band are inclusive
+    mask = oracle.band_bins(nz, dz, c, f0)
+    k = np.arange(nz // 2)
+    f = k * fbin
+    np.testing.assert_array_equal(mask[:nz // 2], (f >= f0) & (f <= 3 * f0))
+
+
+def test_log_compress():
+    env = np.array([[0.0, 1e-5, 1e-3, 0.1, 2.0], [1.0, 0.5, 2e-4, 2.0, 1.999]])
+    out = oracle.log_compress(env, -70.0)
+    assert out[0, 4] == 0.0 and out[1, 3] == 0.0
+    assert out[0, 0] == -70.0 and out[0, 1] == -70.0
+    assert out[0, 2] == pytest.approx(20 * math.log10(1e-3 / 2))
+    assert out[1, 1] == pytest.approx(-20 * math.log10(4))
+    np.testing.assert_array_equal(oracle.log_compress(np.zeros((3, 4))), -70.0)
+    assert oracle.log_compress(env, -40.0).min() == -40.0
