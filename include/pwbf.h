@@ -1,0 +1,210 @@
+/* pwbf.h - plane-wave receive beamformer for MI355X (gfx950), C ABI.
+ *
+ * The library computes, for every pixel of a 2-D grid, the delay-and-sum of
+ * the paper's Eq. (1) over the receive channels of a linear array insonified by
+ * steered plane waves, and the RF delay-multiply-and-sum variant built on the
+ * squared-sum structure of Eq. (4) with the signed-root compression of Eq. (2);
+ * optional depth-wise post-processing gives the band-passed image, the envelope
+ * (magnitude of the analytic signal) and the log-compressed image displayed at
+ * -70 dB (Fig. 3).
+ *
+ * Conventions shared by every entry point
+ *  - RF is one contiguous device buffer RF[n_angles][n_channels][n_samples],
+ *    sample index fastest, stored as int16, IEEE binary16 or float32
+ *    (pwbf_dtype). Sample n of angle a was acquired at time t0[a] + n / fs.
+ *  - Elements lie on z = 0 at elem_x[e]. A steered plane wave of angle theta
+ *    leaves the first-firing element at time 0. The sample position of pixel
+ *    (x, z) for element e and angle a is
+ *       s = fs * ((x sin th + z cos th - min_k x_k sin th) / c
+ *                 + sqrt((x - x_e)^2 + z^2) / c - t0[a]),
+ *    which at th = 0 is the transmit depth plus the receive path; the paper's
+ *    delay text after Eq. (1) is the same receive path.
+ *  - The delayed sample is the linear interpolation between samples floor(s)
+ *    and floor(s) + 1, with the record taken as zero outside [0, n_samples).
+ *  - Receive apodization (the paper's predefined weights w_i[p]): Hann over a
+ *    half-aperture z / (2 F#), w = 0.5 (1 + cos(pi |x - x_e| / a)) for
+ *    |x - x_e| < a and z > 0, else 0; or boxcar, or none (w = 1).
+ *  - Images are float32 [nx][nz], depth fastest. Pixel (ix, iz) is centred at
+ *    (x0 + ix dx, z0 + iz dz).
+ *  - All arithmetic on the GPU is float32 (no float64 on the device). Geometry
+ *    is taken in float64 on the host and rounded once to float32 in sample units.
+ *  - Every call validates its arguments on the host before any HIP call; on a
+ *    validation error nothing is enqueued and nothing is written. Work is
+ *    enqueued on the caller's HIP stream (NULL = the null stream) and the call
+ *    returns once it is enqueued. Device faults surface at the caller's next
+ *    synchronisation. No call allocates or frees device memory, keeps a pointer
+ *    after it returns, prints, or throws. Calls on different streams from
+ *    different threads may overlap; calls that share a workspace must not.
+ *  - Return value: PWBF_OK (0) or a negative PWBF_E_* code; pwbf_last_error()
+ *    gives a thread-local description of the last failure on the calling thread.
+ */
+#ifndef PWBF_H
+#define PWBF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PWBF_ABI_VERSION 1u
+
+#ifndef PWBF_API
+#define PWBF_API __attribute__((visibility("default")))
+#endif
+
+#define PWBF_OK 0
+#define PWBF_E_INVALID (-1)     /* bad pointer, size, enum or geometry */
+#define PWBF_E_UNSUPPORTED (-2) /* valid but outside what the kernels handle */
+#define PWBF_E_NOMEM (-3)       /* host or device allocation failed (batch objects only) */
+#define PWBF_E_DEVICE (-4)      /* a HIP runtime call failed */
+
+/* Storage type of the RF samples. */
+#define PWBF_I16 0
+#define PWBF_F16 1
+#define PWBF_F32 2
+
+/* Beamformer. */
+#define PWBF_DAS 0
+#define PWBF_DMAS 1
+
+/* Apodization. */
+#define PWBF_APOD_HANN 0
+#define PWBF_APOD_BOXCAR 1
+#define PWBF_APOD_NONE 2
+
+/* Limits of this build. */
+#define PWBF_MAX_ANGLES 32
+#define PWBF_MAX_CHANNELS 256
+#define PWBF_MAX_NZ_POST 4096 /* longest depth column the post-processing handles */
+
+/* Acquisition and grid. Host pointers are read during the call only. */
+typedef struct pwbf_geometry {
+  uint32_t abi_version;     /* must be PWBF_ABI_VERSION */
+  int32_t n_angles;         /* 1 .. PWBF_MAX_ANGLES */
+  int32_t n_channels;       /* 1 .. PWBF_MAX_CHANNELS (>= 2 for DMAS) */
+  int32_t n_samples;        /* >= 2 */
+  const double *elem_x;     /* host [n_channels], element centres, m */
+  const double *angle_rad;  /* host [n_angles], steering angles, |th| < pi/2 */
+  const double *t0;         /* host [n_angles], s, time of sample 0; NULL = all 0 */
+  double c;                 /* speed of sound, m/s, > 0 */
+  double fs;                /* sampling rate, Hz, > 0 */
+  double f0;                /* centre frequency, Hz (band-pass only) */
+  int32_t nx, nz;           /* grid size, >= 1 each */
+  double x0, dx;            /* centre of column 0 and lateral pitch, m (dx > 0) */
+  double z0, dz;            /* centre of row 0 and depth pitch, m (dz > 0) */
+  double f_number;          /* > 0 for Hann and boxcar */
+  int32_t apod;             /* PWBF_APOD_* */
+  int32_t bandpass;         /* 1: keep round-trip band [f0, 3 f0] along depth before
+                               the envelope (needs dz <= c / (12 f0)); 0: none */
+  double log_floor_db;      /* floor of the log image, dB, < 0 (e.g. -70) */
+} pwbf_geometry;
+
+/* Output planes, each a device float32 [nx][nz] buffer owned by the caller.
+ * rf is required; the others may be NULL. filtered needs bandpass = 1. The
+ * envelope and the log image are taken from the band-passed image when
+ * bandpass = 1, else from rf. */
+typedef struct pwbf_outputs {
+  float *rf;       /* beamformed image: DAS sum, or raw DMAS */
+  float *filtered; /* band-passed image */
+  float *env;      /* envelope along depth */
+  float *logimg;   /* 20 log10(env / max env), clipped at log_floor_db */
+} pwbf_outputs;
+
+/* Launch shape of the beamforming kernel. Zeros select the library default. */
+typedef struct pwbf_tile {
+  int32_t cpw;   /* lane groups per wavefront sharing one pixel column: 1, 2 or 4;
+                    each group sums a subset of the channels, reduced in-wave */
+  int32_t wz;    /* wavefronts stacked along depth in a tile */
+  int32_t wx;    /* wavefronts side by side along x in a tile; wz * wx in 1..8 */
+  int32_t chunk; /* channels staged in LDS at a time (0 = as many as fit) */
+} pwbf_tile;
+
+/* ABI version of the loaded library (PWBF_ABI_VERSION). */
+PWBF_API uint32_t pwbf_abi_version(void);
+
+/* Thread-local text of the last error on this thread ("" if none). Valid until
+ * the next pwbf_* call on the same thread. */
+PWBF_API const char *pwbf_last_error(void);
+
+/* Bytes of device workspace the calls below need for these outputs (0 when no
+ * log image is requested). Returns 0 and sets the last error on invalid input. */
+PWBF_API size_t pwbf_workspace_bytes(const pwbf_geometry *g, const pwbf_outputs *out);
+
+/* Delay-and-sum for one steering angle: Eq. (1), y[p] = sum_e w_e[p] u_e(s_e[p]).
+ *  rf        device RF[n_angles][n_channels][n_samples] of rf_dtype; slab `angle` is used
+ *  angle     0 .. n_angles - 1
+ *  out       output planes (see pwbf_outputs)
+ *  workspace device buffer of at least pwbf_workspace_bytes(g, out) bytes, or NULL
+ *            when that is 0; the call overwrites it
+ *  stream    hipStream_t as void*, NULL for the null stream
+ * Errors: PWBF_E_INVALID, PWBF_E_UNSUPPORTED, PWBF_E_DEVICE. */
+PWBF_API int pwbf_beamform_das(const pwbf_geometry *g, const void *rf, int32_t rf_dtype, int32_t angle,
+                      const pwbf_outputs *out, void *workspace, size_t workspace_bytes,
+                      void *stream);
+
+/* RF delay-multiply-and-sum for one angle: with s_e = w_e sign(v_e) sqrt|v_e| for
+ * the delayed samples v_e (the weight outside the root, as in Eq. (2)),
+ * y = sum_{e<f} s_e s_f, computed as ((sum_e s_e)^2 - sum_e s_e^2) / 2 (the
+ * squared-sum form of Eq. (4) without its 1/N). Arguments and errors as for
+ * pwbf_beamform_das; needs n_channels >= 2. */
+PWBF_API int pwbf_beamform_dmas(const pwbf_geometry *g, const void *rf, int32_t rf_dtype,
+                       int32_t angle, const pwbf_outputs *out, void *workspace,
+                       size_t workspace_bytes, void *stream);
+
+/* Coherent compounding: the unweighted sum over all n_angles of the per-angle
+ * DAS (mode PWBF_DAS) or DMAS (mode PWBF_DMAS) images, in one pass that shares
+ * each pixel's receive delays and weights across the angles. Before
+ * post-processing, compound(mode) equals the sum of beamform_<mode>(a) over a
+ * (up to float32 summation order). Other arguments and errors as above. */
+PWBF_API int pwbf_compound(const pwbf_geometry *g, const void *rf, int32_t rf_dtype, int32_t mode,
+                  const pwbf_outputs *out, void *workspace, size_t workspace_bytes,
+                  void *stream);
+
+/* pwbf_compound (angle == -1) or the single-angle call (angle >= 0) with an explicit
+ * launch shape; tile == NULL behaves as the plain calls. Used by the tuner and
+ * by tests that sweep launch shapes. */
+PWBF_API int pwbf_beamform_ex(const pwbf_geometry *g, const void *rf, int32_t rf_dtype, int32_t mode,
+                     int32_t angle, const pwbf_tile *tile, const pwbf_outputs *out,
+                     void *workspace, size_t workspace_bytes, void *stream);
+
+/* Every host-side check of pwbf_beamform_ex with the same arguments, without
+ * enqueuing anything: returns what that call would return before it reaches the
+ * device (PWBF_OK when the call would be enqueued). Pointers are only checked
+ * for NULL and alignment, never dereferenced. */
+PWBF_API int pwbf_validate_call(const pwbf_geometry *g, const void *rf, int32_t rf_dtype,
+                                int32_t mode, int32_t angle, const pwbf_tile *tile,
+                                const pwbf_outputs *out, const void *workspace,
+                                size_t workspace_bytes);
+
+/* The resolved launch of a beamforming call and the float32 constants its kernel
+ * uses (all lengths in samples: metres * fs / c). Diagnostic: lets a caller see
+ * the LDS use and tile grid, and lets tests re-derive the kernel's window bounds
+ * on the CPU. */
+typedef struct pwbf_plan_info {
+  int32_t cpw, wz, wx, chunk; /* resolved launch shape */
+  int32_t win;                /* LDS entries per (channel, angle) window */
+  int32_t tiles_z, tiles_x;   /* tile grid; a tile is (64 / cpw * wz) x wx pixels */
+  int32_t threads_per_block;
+  int32_t blocks;             /* blocks launched (a multiple of 8) */
+  int32_t n_angles_used;      /* angles the kernel sums (1 for single-angle calls) */
+  int64_t lds_bytes;          /* LDS per block */
+  float X0, DX, Z0, DZ;       /* pixel (0, 0) centre and pitches */
+  float ap_k;                 /* 2 F# (0 when apod is none) */
+  float sa[PWBF_MAX_ANGLES];  /* sin(theta) per angle used */
+  float ca[PWBF_MAX_ANGLES];  /* cos(theta) */
+  float to[PWBF_MAX_ANGLES];  /* transmit offset: first-firing term + t0 * fs */
+  float xe[PWBF_MAX_CHANNELS]; /* element x */
+} pwbf_plan_info;
+
+/* Fill *info for a call with this geometry, mode, angle (-1 = compound) and tile
+ * (NULL = default). No device work; returns PWBF_OK or a validation error. */
+PWBF_API int pwbf_describe_plan(const pwbf_geometry *g, int32_t mode, int32_t angle,
+                       const pwbf_tile *tile, pwbf_plan_info *info);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PWBF_H */

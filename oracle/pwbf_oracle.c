@@ -55,18 +55,28 @@ typedef struct {
 
 enum { ORA_OK = 0, ORA_BAD = -1 };
 
-/* Time of flight in samples from transmit to the echo of (x, z) reaching element e. */
-double ora_tof_samples(const ora_geom *g, int32_t a, int32_t e, double x, double z) {
+/* min_e(x_e sin th): the lateral term of the first-firing element for angle a. */
+static double first_fire(const ora_geom *g, int32_t a) {
   double th = g->angle[a];
   double first = g->elem_x[0] * sin(th);
   for (int32_t k = 1; k < g->n_channels; ++k) {
     double v = g->elem_x[k] * sin(th);
     if (v < first) first = v;
   }
+  return first;
+}
+
+static double tof(const ora_geom *g, int32_t a, double first, int32_t e, double x, double z) {
+  double th = g->angle[a];
   double t_tx = (x * sin(th) + z * cos(th) - first) / g->c;
   double dxe = x - g->elem_x[e];
   double t_rx = sqrt(dxe * dxe + z * z) / g->c;
   return (t_tx + t_rx - g->t0[a]) * g->fs;
+}
+
+/* Time of flight in samples from transmit to the echo of (x, z) reaching element e. */
+double ora_tof_samples(const ora_geom *g, int32_t a, int32_t e, double x, double z) {
+  return tof(g, a, first_fire(g, a), e, x, z);
 }
 
 /* Receive apodization weight of element e for the pixel at (x, z). */
@@ -90,8 +100,11 @@ double ora_interp(const double *u, int32_t ns, double s) {
   return (1.0 - f) * a + f * b;
 }
 
+#define ORA_MAX_ANGLES 256
+
 static int check(const ora_geom *g, int32_t angle) {
   if (!g || g->n_angles < 1 || g->n_channels < 1 || g->n_samples < 1) return ORA_BAD;
+  if (g->n_angles > ORA_MAX_ANGLES) return ORA_BAD;
   if (angle < -1 || angle >= g->n_angles) return ORA_BAD;
   return ORA_OK;
 }
@@ -103,30 +116,31 @@ static void pixel_xz(const ora_geom *g, int64_t p, double *x, double *z) {
 }
 
 /* Delayed, interpolated sample of element e for angle a at pixel (x, z). */
-static double delayed(const ora_geom *g, const double *rf, int32_t a, int32_t e, double x,
-                      double z) {
+static double delayed(const ora_geom *g, const double *rf, int32_t a, double first, int32_t e,
+                      double x, double z) {
   const double *u = rf + ((int64_t)a * g->n_channels + e) * g->n_samples;
-  return ora_interp(u, g->n_samples, ora_tof_samples(g, a, e, x, z));
+  return ora_interp(u, g->n_samples, tof(g, a, first, e, x, z));
 }
 
 /* Eq. (1) for one angle. */
-static double das_one_angle(const ora_geom *g, const double *rf, int32_t a, double x, double z) {
+static double das_one_angle(const ora_geom *g, const double *rf, int32_t a, double first,
+                            double x, double z) {
   double y = 0.0;
   for (int32_t e = 0; e < g->n_channels; ++e)
-    y += ora_apod_weight(g, e, x, z) * delayed(g, rf, a, e, x, z);
+    y += ora_apod_weight(g, e, x, z) * delayed(g, rf, a, first, e, x, z);
   return y;
 }
 
 static double sgn(double v) { return (v > 0.0) - (v < 0.0); }
 
 /* RF DMAS for one angle; form 0 = pair sum, form 1 = squared-sum identity. */
-static double dmas_one_angle(const ora_geom *g, const double *rf, int32_t a, double x, double z,
-                             int32_t form) {
+static double dmas_one_angle(const ora_geom *g, const double *rf, int32_t a, double first,
+                             double x, double z, int32_t form) {
   int32_t n = g->n_channels;
   double s[1024];
   if (n > 1024) return NAN;
   for (int32_t e = 0; e < n; ++e) {
-    double v = delayed(g, rf, a, e, x, z);
+    double v = delayed(g, rf, a, first, e, x, z);
     s[e] = ora_apod_weight(g, e, x, z) * sgn(v) * sqrt(fabs(v));
   }
   if (form == 0) {
@@ -151,6 +165,8 @@ int ora_das(const ora_geom *g, const double *rf, int32_t angle, const int64_t *p
   if (check(g, angle) != ORA_OK || !rf || !out) return ORA_BAD;
   int64_t total = (int64_t)g->nx * g->nz;
   if (!pix) npix = total;
+  double first[ORA_MAX_ANGLES];
+  for (int32_t a = 0; a < g->n_angles; ++a) first[a] = first_fire(g, a);
   for (int64_t k = 0; k < npix; ++k) {
     int64_t p = pix ? pix[k] : k;
     if (p < 0 || p >= total) return ORA_BAD;
@@ -158,9 +174,9 @@ int ora_das(const ora_geom *g, const double *rf, int32_t angle, const int64_t *p
     pixel_xz(g, p, &x, &z);
     double y = 0.0;
     if (angle >= 0) {
-      y = das_one_angle(g, rf, angle, x, z);
+      y = das_one_angle(g, rf, angle, first[angle], x, z);
     } else {
-      for (int32_t a = 0; a < g->n_angles; ++a) y += das_one_angle(g, rf, a, x, z);
+      for (int32_t a = 0; a < g->n_angles; ++a) y += das_one_angle(g, rf, a, first[a], x, z);
     }
     out[k] = y;
   }
@@ -172,6 +188,8 @@ int ora_dmas(const ora_geom *g, const double *rf, int32_t angle, int32_t form, c
   if (check(g, angle) != ORA_OK || !rf || !out || (form != 0 && form != 1)) return ORA_BAD;
   int64_t total = (int64_t)g->nx * g->nz;
   if (!pix) npix = total;
+  double first[ORA_MAX_ANGLES];
+  for (int32_t a = 0; a < g->n_angles; ++a) first[a] = first_fire(g, a);
   for (int64_t k = 0; k < npix; ++k) {
     int64_t p = pix ? pix[k] : k;
     if (p < 0 || p >= total) return ORA_BAD;
@@ -179,9 +197,10 @@ int ora_dmas(const ora_geom *g, const double *rf, int32_t angle, int32_t form, c
     pixel_xz(g, p, &x, &z);
     double y = 0.0;
     if (angle >= 0) {
-      y = dmas_one_angle(g, rf, angle, x, z, form);
+      y = dmas_one_angle(g, rf, angle, first[angle], x, z, form);
     } else {
-      for (int32_t a = 0; a < g->n_angles; ++a) y += dmas_one_angle(g, rf, a, x, z, form);
+      for (int32_t a = 0; a < g->n_angles; ++a)
+        y += dmas_one_angle(g, rf, a, first[a], x, z, form);
     }
     out[k] = y;
   }

@@ -1,0 +1,18 @@
+"""MI355X plane-wave receive beamformer: HIP kernels behind a C ABI (libpwbf.so).
+
+    from paper_2311_00482_amd import compound, beamform_das, beamform_dmas
+    planes = compound(geometry, rf_tensor, "das", want=("rf", "env", "log"))
+"""
+
+from ._abi import PwbfError, lib  # noqa: F401
+from .api import (  # noqa: F401
+    GeometryArg,
+    Tile,
+    alloc_outputs,
+    beamform,
+    beamform_das,
+    beamform_dmas,
+    compound,
+    describe_plan,
+    workspace_bytes,
+)

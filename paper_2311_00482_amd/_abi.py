@@ -1,0 +1,123 @@
+"""ctypes view of include/pwbf.h and the loader of libpwbf.so.
+
+The loader never falls back to anything: if the HIP library is not built it
+raises, so no result can come from a CPU path by accident.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpwbf.so")
+
+ABI_VERSION = 1
+OK, E_INVALID, E_UNSUPPORTED, E_NOMEM, E_DEVICE = 0, -1, -2, -3, -4
+I16, F16, F32 = 0, 1, 2
+DAS, DMAS = 0, 1
+APOD_HANN, APOD_BOXCAR, APOD_NONE = 0, 1, 2
+MAX_ANGLES, MAX_CHANNELS, MAX_NZ_POST = 32, 256, 4096
+
+ERROR_NAMES = {E_INVALID: "PWBF_E_INVALID", E_UNSUPPORTED: "PWBF_E_UNSUPPORTED",
+               E_NOMEM: "PWBF_E_NOMEM", E_DEVICE: "PWBF_E_DEVICE"}
+
+
+class Geometry(ctypes.Structure):
+    _fields_ = [
+        ("abi_version", ctypes.c_uint32),
+        ("n_angles", ctypes.c_int32),
+        ("n_channels", ctypes.c_int32),
+        ("n_samples", ctypes.c_int32),
+        ("elem_x", ctypes.POINTER(ctypes.c_double)),
+        ("angle_rad", ctypes.POINTER(ctypes.c_double)),
+        ("t0", ctypes.POINTER(ctypes.c_double)),
+        ("c", ctypes.c_double),
+        ("fs", ctypes.c_double),
+        ("f0", ctypes.c_double),
+        ("nx", ctypes.c_int32),
+        ("nz", ctypes.c_int32),
+        ("x0", ctypes.c_double),
+        ("dx", ctypes.c_double),
+        ("z0", ctypes.c_double),
+        ("dz", ctypes.c_double),
+        ("f_number", ctypes.c_double),
+        ("apod", ctypes.c_int32),
+        ("bandpass", ctypes.c_int32),
+        ("log_floor_db", ctypes.c_double),
+    ]
+
+
+class Outputs(ctypes.Structure):
+    _fields_ = [("rf", ctypes.c_void_p), ("filtered", ctypes.c_void_p),
+                ("env", ctypes.c_void_p), ("logimg", ctypes.c_void_p)]
+
+
+class Tile(ctypes.Structure):
+    _fields_ = [("cpw", ctypes.c_int32), ("wz", ctypes.c_int32), ("wx", ctypes.c_int32),
+                ("chunk", ctypes.c_int32)]
+
+
+class PlanInfo(ctypes.Structure):
+    _fields_ = [
+        ("cpw", ctypes.c_int32), ("wz", ctypes.c_int32), ("wx", ctypes.c_int32),
+        ("chunk", ctypes.c_int32), ("win", ctypes.c_int32), ("tiles_z", ctypes.c_int32),
+        ("tiles_x", ctypes.c_int32), ("threads_per_block", ctypes.c_int32),
+        ("blocks", ctypes.c_int32), ("n_angles_used", ctypes.c_int32),
+        ("lds_bytes", ctypes.c_int64),
+        ("X0", ctypes.c_float), ("DX", ctypes.c_float), ("Z0", ctypes.c_float),
+        ("DZ", ctypes.c_float), ("ap_k", ctypes.c_float),
+        ("sa", ctypes.c_float * MAX_ANGLES), ("ca", ctypes.c_float * MAX_ANGLES),
+        ("to", ctypes.c_float * MAX_ANGLES), ("xe", ctypes.c_float * MAX_CHANNELS),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    """Load libpwbf.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is missing: build the HIP library first "
+            "(python -m paper_2311_00482_amd.build)")
+    L = ctypes.CDLL(LIB_PATH)
+    G, O, T, PI = (ctypes.POINTER(Geometry), ctypes.POINTER(Outputs), ctypes.POINTER(Tile),
+                   ctypes.POINTER(PlanInfo))
+    vp, sz, i32 = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32
+    L.pwbf_abi_version.restype = ctypes.c_uint32
+    L.pwbf_abi_version.argtypes = []
+    L.pwbf_last_error.restype = ctypes.c_char_p
+    L.pwbf_last_error.argtypes = []
+    L.pwbf_workspace_bytes.restype = sz
+    L.pwbf_workspace_bytes.argtypes = [G, O]
+    for name in ("pwbf_beamform_das", "pwbf_beamform_dmas"):
+        f = getattr(L, name)
+        f.restype = ctypes.c_int
+        f.argtypes = [G, vp, i32, i32, O, vp, sz, vp]
+    L.pwbf_compound.restype = ctypes.c_int
+    L.pwbf_compound.argtypes = [G, vp, i32, i32, O, vp, sz, vp]
+    L.pwbf_beamform_ex.restype = ctypes.c_int
+    L.pwbf_beamform_ex.argtypes = [G, vp, i32, i32, i32, T, O, vp, sz, vp]
+    L.pwbf_validate_call.restype = ctypes.c_int
+    L.pwbf_validate_call.argtypes = [G, vp, i32, i32, i32, T, O, vp, sz]
+    L.pwbf_describe_plan.restype = ctypes.c_int
+    L.pwbf_describe_plan.argtypes = [G, i32, i32, T, PI]
+    if L.pwbf_abi_version() != ABI_VERSION:
+        raise ImportError(f"libpwbf ABI {L.pwbf_abi_version()} != binding {ABI_VERSION}")
+    _lib = L
+    return L
+
+
+class PwbfError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERROR_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+def check(rc: int) -> None:
+    if rc != OK:
+        raise PwbfError(rc, lib().pwbf_last_error().decode())

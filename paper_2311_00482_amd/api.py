@@ -1,0 +1,181 @@
+"""Python binding of libpwbf with the C ABI's names.
+
+Argument marshalling only: geometry objects become ``pwbf_geometry``, torch
+tensors become device pointers, the current torch stream becomes the HIP
+stream. Every step of the beamformer runs in the HIP kernels of libpwbf.so;
+torch provides device memory and streams.
+"""
+
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+from typing import Dict, Iterable, Optional
+
+import numpy as np
+
+from . import _abi
+
+_DTYPES = {"int16": _abi.I16, "float16": _abi.F16, "float32": _abi.F32}
+_MODES = {"das": _abi.DAS, "dmas": _abi.DMAS}
+_APODS = {"hann": _abi.APOD_HANN, "boxcar": _abi.APOD_BOXCAR, "none": _abi.APOD_NONE}
+PLANES = ("rf", "filtered", "env", "log")
+
+
+class GeometryArg:
+    """A ``pwbf_geometry`` plus the host arrays it points to.
+
+    ``g`` is any object with the attributes elem_x, angles_rad, n_samples, c,
+    fs, f0, nx, nz, x0, dx, z0, dz, f_number and apod (name) or apod_code;
+    t0_s (per-angle time of sample 0) is optional.
+    """
+
+    def __init__(self, g, bandpass: bool = False, log_floor_db: float = -70.0):
+        self.elem_x = np.ascontiguousarray(g.elem_x, dtype=np.float64)
+        self.angles = np.ascontiguousarray(g.angles_rad, dtype=np.float64)
+        t0 = getattr(g, "t0_s", None)
+        self.t0 = None if t0 is None else np.ascontiguousarray(t0, dtype=np.float64)
+        apod = getattr(g, "apod_code", None)
+        if apod is None:
+            apod = _APODS[g.apod]
+        dp = ctypes.POINTER(ctypes.c_double)
+        self.s = _abi.Geometry(
+            _abi.ABI_VERSION, len(self.angles), len(self.elem_x), int(g.n_samples),
+            self.elem_x.ctypes.data_as(dp), self.angles.ctypes.data_as(dp),
+            self.t0.ctypes.data_as(dp) if self.t0 is not None else None,
+            float(g.c), float(g.fs), float(g.f0), int(g.nx), int(g.nz), float(g.x0),
+            float(g.dx), float(g.z0), float(g.dz), float(g.f_number), int(apod),
+            1 if bandpass else 0, float(log_floor_db))
+        self.nx, self.nz = int(g.nx), int(g.nz)
+        self.shape_rf = (len(self.angles), len(self.elem_x), int(g.n_samples))
+
+    @property
+    def ref(self):
+        return ctypes.byref(self.s)
+
+
+def _as_geom(g, bandpass=False, log_floor_db=-70.0) -> GeometryArg:
+    return g if isinstance(g, GeometryArg) else GeometryArg(g, bandpass, log_floor_db)
+
+
+def _stream_ptr(stream, device):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream(device)
+    return ctypes.c_void_p(int(stream.cuda_stream))
+
+
+def _rf_code(rf) -> int:
+    name = str(rf.dtype).replace("torch.", "")
+    if name not in _DTYPES:
+        raise TypeError(f"RF dtype {rf.dtype} not supported (int16, float16, float32)")
+    return _DTYPES[name]
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else int(t.data_ptr())
+
+
+@dataclass
+class Tile:
+    cpw: int = 0
+    wz: int = 0
+    wx: int = 0
+    chunk: int = 0
+
+    def c(self) -> _abi.Tile:
+        return _abi.Tile(self.cpw, self.wz, self.wx, self.chunk)
+
+
+def workspace_bytes(g, want: Iterable[str] = ("rf",), bandpass=False) -> int:
+    ga = _as_geom(g, bandpass)
+    want = set(want)
+    o = _abi.Outputs(1, 1 if "filtered" in want else None, 1 if "env" in want else None,
+                     1 if "log" in want else None)
+    n = _abi.lib().pwbf_workspace_bytes(ga.ref, ctypes.byref(o))
+    err = _abi.lib().pwbf_last_error().decode()
+    if err:
+        raise _abi.PwbfError(_abi.E_INVALID, err)
+    return int(n)
+
+
+def describe_plan(g, mode: str = "das", angle: int = -1, tile: Optional[Tile] = None,
+                  bandpass: bool = False) -> Dict:
+    """The resolved launch shape and float32 constants of a call (no device work)."""
+    ga = _as_geom(g, bandpass)
+    info = _abi.PlanInfo()
+    t = tile.c() if tile is not None else None
+    _abi.check(_abi.lib().pwbf_describe_plan(ga.ref, _MODES[mode], angle,
+                                             ctypes.byref(t) if t is not None else None,
+                                             ctypes.byref(info)))
+    out = {k: getattr(info, k) for k, _ in _abi.PlanInfo._fields_}
+    for k in ("sa", "ca", "to", "xe"):
+        out[k] = np.array(out[k][:], dtype=np.float32)
+    return out
+
+
+def alloc_outputs(g, want: Iterable[str], device) -> Dict[str, "object"]:
+    import torch
+    ga = _as_geom(g)
+    return {k: torch.empty((ga.nx, ga.nz), dtype=torch.float32, device=device) for k in want}
+
+
+def beamform(g, rf, mode: str = "das", angle: int = -1, tile: Optional[Tile] = None,
+             want: Iterable[str] = ("rf",), out: Optional[Dict] = None, workspace=None,
+             stream=None, bandpass: bool = False, log_floor_db: float = -70.0) -> Dict:
+    """Run one frame through libpwbf. angle -1 = compound over all angles.
+
+    ``rf``: CUDA tensor [n_angles, n_channels, n_samples] of int16/float16/float32.
+    ``want``: planes among "rf", "filtered", "env", "log" (rf is always made).
+    ``out``: preallocated planes (float32 [nx, nz] CUDA tensors) by name.
+    Returns the dict of output planes. Work is enqueued on ``stream`` (default:
+    torch's current stream) and not waited for.
+    """
+    import torch
+    ga = _as_geom(g, bandpass, log_floor_db)
+    if bandpass and not ga.s.bandpass:
+        ga.s.bandpass = 1
+    if not rf.is_cuda or not rf.is_contiguous():
+        raise ValueError("rf must be a contiguous CUDA tensor")
+    if tuple(rf.shape) != ga.shape_rf:
+        raise ValueError(f"rf shape {tuple(rf.shape)} != {ga.shape_rf}")
+    want = set(want) | {"rf"}
+    unknown = want - set(PLANES)
+    if unknown:
+        raise ValueError(f"unknown output planes {sorted(unknown)}")
+    out = dict(out or {})
+    for k in want:
+        if k not in out:
+            out[k] = torch.empty((ga.nx, ga.nz), dtype=torch.float32, device=rf.device)
+    o = _abi.Outputs(_ptr(out.get("rf")), _ptr(out.get("filtered")), _ptr(out.get("env")),
+                     _ptr(out.get("log")))
+    need = _abi.lib().pwbf_workspace_bytes(ga.ref, ctypes.byref(o))
+    if need and workspace is None:
+        workspace = torch.empty(need, dtype=torch.uint8, device=rf.device)
+    ws_ptr = _ptr(workspace)
+    ws_bytes = 0 if workspace is None else workspace.numel() * workspace.element_size()
+    t = tile.c() if tile is not None else None
+    rc = _abi.lib().pwbf_beamform_ex(ga.ref, _ptr(rf), _rf_code(rf), _MODES[mode], angle,
+                                     ctypes.byref(t) if t is not None else None, ctypes.byref(o),
+                                     ws_ptr, ws_bytes, _stream_ptr(stream, rf.device))
+    _abi.check(rc)
+    return out
+
+
+def beamform_das(g, rf, angle: int, **kw) -> Dict:
+    """pwbf_beamform_das: DAS (Eq. 1) for one steering angle."""
+    if angle < 0:
+        raise ValueError("angle must be >= 0")
+    return beamform(g, rf, "das", angle, **kw)
+
+
+def beamform_dmas(g, rf, angle: int, **kw) -> Dict:
+    """pwbf_beamform_dmas: RF DMAS for one steering angle."""
+    if angle < 0:
+        raise ValueError("angle must be >= 0")
+    return beamform(g, rf, "dmas", angle, **kw)
+
+
+def compound(g, rf, mode: str = "das", **kw) -> Dict:
+    """pwbf_compound: coherent sum over all angles of the per-angle DAS or DMAS."""
+    return beamform(g, rf, mode, -1, **kw)

@@ -1,0 +1,142 @@
+// extern "C" entry points of libpwbf: validation, plan, enqueue.
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "../../include/pwbf.h"
+#include "plan_host.h"
+
+namespace pwbf {
+hipError_t launch_beamform(const FramePlan &P, hipStream_t stream);
+hipError_t launch_post(const PostPlan &Q, hipStream_t stream);
+}  // namespace pwbf
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int set_error(int code, const std::string &msg) {
+  g_last_error = msg;
+  return code;
+}
+
+int run(const pwbf_geometry *g, const void *rf, int32_t dtype, int32_t mode, int32_t angle,
+        const pwbf_tile *tile, const pwbf_outputs *out, void *ws, size_t ws_bytes, void *stream) {
+  g_last_error.clear();
+  pwbf::FramePlan P;
+  std::string err;
+  int rc = pwbf::build_plan(g, rf, dtype, mode, angle, tile, out, ws, ws_bytes, &P, &err);
+  if (rc) return set_error(rc, err);
+  pwbf::PostPlan Q;
+  const bool post = pwbf::post_needed(out);
+  if (post) pwbf::build_post_plan(g, out, ws, &Q);
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = pwbf::launch_beamform(P, s);
+  if (e != hipSuccess)
+    return set_error(PWBF_E_DEVICE, std::string("beamform launch: ") + hipGetErrorString(e));
+  if (post) {
+    e = pwbf::launch_post(Q, s);
+    if (e != hipSuccess)
+      return set_error(PWBF_E_DEVICE, std::string("post-processing launch: ") +
+                                          hipGetErrorString(e));
+  }
+  return PWBF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+uint32_t pwbf_abi_version(void) { return PWBF_ABI_VERSION; }
+
+const char *pwbf_last_error(void) { return g_last_error.c_str(); }
+
+size_t pwbf_workspace_bytes(const pwbf_geometry *g, const pwbf_outputs *out) {
+  g_last_error.clear();
+  std::string err;
+  int rc = pwbf::validate_geometry(g, &err);
+  if (rc) {
+    set_error(rc, err);
+    return 0;
+  }
+  if (!out) {
+    set_error(PWBF_E_INVALID, "outputs is NULL");
+    return 0;
+  }
+  return pwbf::workspace_bytes(g, out);
+}
+
+int pwbf_beamform_das(const pwbf_geometry *g, const void *rf, int32_t rf_dtype, int32_t angle,
+                      const pwbf_outputs *out, void *workspace, size_t workspace_bytes,
+                      void *stream) {
+  if (angle < 0) return set_error(PWBF_E_INVALID, "angle must be >= 0");
+  return run(g, rf, rf_dtype, pwbf::kDas, angle, nullptr, out, workspace, workspace_bytes,
+             stream);
+}
+
+int pwbf_beamform_dmas(const pwbf_geometry *g, const void *rf, int32_t rf_dtype, int32_t angle,
+                       const pwbf_outputs *out, void *workspace, size_t workspace_bytes,
+                       void *stream) {
+  if (angle < 0) return set_error(PWBF_E_INVALID, "angle must be >= 0");
+  return run(g, rf, rf_dtype, pwbf::kDmas, angle, nullptr, out, workspace, workspace_bytes,
+             stream);
+}
+
+int pwbf_compound(const pwbf_geometry *g, const void *rf, int32_t rf_dtype, int32_t mode,
+                  const pwbf_outputs *out, void *workspace, size_t workspace_bytes,
+                  void *stream) {
+  return run(g, rf, rf_dtype, mode, -1, nullptr, out, workspace, workspace_bytes, stream);
+}
+
+int pwbf_beamform_ex(const pwbf_geometry *g, const void *rf, int32_t rf_dtype, int32_t mode,
+                     int32_t angle, const pwbf_tile *tile, const pwbf_outputs *out,
+                     void *workspace, size_t workspace_bytes, void *stream) {
+  return run(g, rf, rf_dtype, mode, angle, tile, out, workspace, workspace_bytes, stream);
+}
+
+int pwbf_validate_call(const pwbf_geometry *g, const void *rf, int32_t rf_dtype, int32_t mode,
+                       int32_t angle, const pwbf_tile *tile, const pwbf_outputs *out,
+                       const void *workspace, size_t workspace_bytes) {
+  g_last_error.clear();
+  pwbf::FramePlan P;
+  std::string err;
+  int rc = pwbf::build_plan(g, rf, rf_dtype, mode, angle, tile, out, (void *)workspace,
+                            workspace_bytes, &P, &err);
+  if (rc) return set_error(rc, err);
+  return PWBF_OK;
+}
+
+int pwbf_describe_plan(const pwbf_geometry *g, int32_t mode, int32_t angle,
+                       const pwbf_tile *tile, pwbf_plan_info *info) {
+  g_last_error.clear();
+  if (!info) return set_error(PWBF_E_INVALID, "info is NULL");
+  pwbf::FramePlan P;
+  std::string err;
+  int rc = pwbf::plan_frame(g, pwbf::kF32, mode, angle, tile, &P, &err);
+  if (rc) return set_error(rc, err);
+  info->cpw = P.cpw;
+  info->wz = P.wz;
+  info->wx = P.wx;
+  info->chunk = P.chunk;
+  info->win = P.win;
+  info->tiles_z = P.tiles_z;
+  info->tiles_x = P.tiles_x;
+  info->threads_per_block = pwbf::kWave * P.wz * P.wx;
+  info->blocks = 8 * P.tiles_per_xcd;
+  info->n_angles_used = P.n_angles;
+  info->lds_bytes = (int64_t)pwbf::plan_lds_bytes(P);
+  info->X0 = P.X0;
+  info->DX = P.DX;
+  info->Z0 = P.Z0;
+  info->DZ = P.DZ;
+  info->ap_k = P.ap_k;
+  for (int a = 0; a < PWBF_MAX_ANGLES; ++a) {
+    info->sa[a] = P.sa[a];
+    info->ca[a] = P.ca[a];
+    info->to[a] = P.to[a];
+  }
+  for (int e = 0; e < PWBF_MAX_CHANNELS; ++e) info->xe[e] = P.xe[e];
+  return PWBF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,333 @@
+// Host-side validation and plan construction (no HIP calls).
+//
+// Everything a kernel needs is derived here in double precision and rounded
+// once to float32 in sample units. The LDS window length per (channel, angle)
+// comes from a bound on how far a tile's delays can spread:
+//   - the transmit term X sin(th) + Z cos(th) is linear, so over a tile of
+//     TX x TZ pixels it spans |sin th| (TX-1) DX + |cos th| (TZ-1) DZ;
+//   - the receive term is a Euclidean distance, 1-Lipschitz in the pixel
+//     position, so it spans at most the tile diagonal.
+// The kernel starts each window at floor(min transmit) - 1 plus
+// floor(min receive) - 1, so every interpolation pair of every pixel of the
+// tile lies inside ceil(spread) + 6 entries.
+#include "plan_host.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+
+namespace pwbf {
+
+namespace {
+
+bool finite(double v) { return std::isfinite(v); }
+
+int fail(std::string *err, int code, const char *fmt, ...) __attribute__((format(printf, 3, 4)));
+int fail(std::string *err, int code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (err) *err = buf;
+  return code;
+}
+
+bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
+}  // namespace
+
+size_t dtype_bytes(int dtype) { return dtype == kF32 ? 4 : 2; }
+
+int validate_geometry(const pwbf_geometry *g, std::string *err) {
+  if (!g) return fail(err, PWBF_E_INVALID, "geometry is NULL");
+  if (g->abi_version != PWBF_ABI_VERSION)
+    return fail(err, PWBF_E_INVALID, "geometry abi_version %u != library %u", g->abi_version,
+                PWBF_ABI_VERSION);
+  if (g->n_angles < 1 || g->n_angles > kMaxAngles)
+    return fail(err, g->n_angles < 1 ? PWBF_E_INVALID : PWBF_E_UNSUPPORTED,
+                "n_angles %d outside 1..%d", g->n_angles, kMaxAngles);
+  if (g->n_channels < 1 || g->n_channels > kMaxChannels)
+    return fail(err, g->n_channels < 1 ? PWBF_E_INVALID : PWBF_E_UNSUPPORTED,
+                "n_channels %d outside 1..%d", g->n_channels, kMaxChannels);
+  if (g->n_samples < 2) return fail(err, PWBF_E_INVALID, "n_samples %d < 2", g->n_samples);
+  if (g->n_samples > (1 << 24))
+    return fail(err, PWBF_E_UNSUPPORTED, "n_samples %d > 2^24", g->n_samples);
+  if (!g->elem_x || !g->angle_rad) return fail(err, PWBF_E_INVALID, "elem_x or angle_rad NULL");
+  for (int e = 0; e < g->n_channels; ++e)
+    if (!finite(g->elem_x[e])) return fail(err, PWBF_E_INVALID, "elem_x[%d] not finite", e);
+  for (int a = 0; a < g->n_angles; ++a) {
+    double th = g->angle_rad[a];
+    if (!finite(th) || !(std::fabs(th) < M_PI / 2))
+      return fail(err, PWBF_E_INVALID, "angle_rad[%d] = %g not in (-pi/2, pi/2)", a, th);
+    if (g->t0 && !finite(g->t0[a])) return fail(err, PWBF_E_INVALID, "t0[%d] not finite", a);
+  }
+  if (!(g->c > 0) || !finite(g->c)) return fail(err, PWBF_E_INVALID, "c must be > 0");
+  if (!(g->fs > 0) || !finite(g->fs)) return fail(err, PWBF_E_INVALID, "fs must be > 0");
+  if (g->nx < 1 || g->nz < 1) return fail(err, PWBF_E_INVALID, "grid %d x %d", g->nx, g->nz);
+  if ((int64_t)g->nx * g->nz > (int64_t)1 << 30)
+    return fail(err, PWBF_E_UNSUPPORTED, "grid larger than 2^30 pixels");
+  if (!(g->dx > 0) || !(g->dz > 0) || !finite(g->dx) || !finite(g->dz) || !finite(g->x0) ||
+      !finite(g->z0))
+    return fail(err, PWBF_E_INVALID, "grid origin/pitch invalid (dx, dz must be > 0)");
+  if (g->apod != kHann && g->apod != kBoxcar && g->apod != kNone)
+    return fail(err, PWBF_E_INVALID, "apod %d unknown", g->apod);
+  if (g->apod != kNone && (!(g->f_number > 0) || !finite(g->f_number)))
+    return fail(err, PWBF_E_INVALID, "f_number must be > 0");
+  if (g->bandpass != 0 && g->bandpass != 1)
+    return fail(err, PWBF_E_INVALID, "bandpass must be 0 or 1");
+  if (!(g->log_floor_db < 0) || !finite(g->log_floor_db))
+    return fail(err, PWBF_E_INVALID, "log_floor_db must be < 0");
+  // float32 delays lose precision far from the origin: bound the largest
+  // sample position any pixel can reach.
+  double scale = g->fs / g->c;
+  double xmax = 0, zmax = std::max(std::fabs(g->z0), std::fabs(g->z0 + (g->nz - 1) * g->dz));
+  for (double x : {g->x0, g->x0 + (g->nx - 1) * g->dx})
+    for (int e = 0; e < g->n_channels; ++e) xmax = std::max(xmax, std::fabs(x - g->elem_x[e]));
+  double smax = (2 * zmax + 2 * xmax) * scale;
+  for (int a = 0; a < g->n_angles; ++a) {
+    if (g->t0) smax += std::fabs(g->t0[a]) * g->fs;
+  }
+  if (smax >= (double)(1 << 20))
+    return fail(err, PWBF_E_UNSUPPORTED,
+                "delays reach %.0f samples; float32 delays need < 2^20", smax);
+  return PWBF_OK;
+}
+
+static bool post_requested(const pwbf_outputs *o) {
+  return o->filtered || o->env || o->logimg;
+}
+
+size_t workspace_bytes(const pwbf_geometry *g, const pwbf_outputs *o) {
+  if (!o || !o->logimg) return 0;
+  size_t b = 256;
+  if (!o->env) b += (size_t)g->nx * g->nz * sizeof(float);
+  return b;
+}
+
+int validate_outputs(const pwbf_geometry *g, const pwbf_outputs *o, void *ws, size_t ws_bytes,
+                     std::string *err) {
+  if (!o) return fail(err, PWBF_E_INVALID, "outputs is NULL");
+  if (!o->rf) return fail(err, PWBF_E_INVALID, "outputs->rf is NULL");
+  const float *planes[4] = {o->rf, o->filtered, o->env, o->logimg};
+  for (const float *p : planes)
+    if (p && ((uintptr_t)p % 4)) return fail(err, PWBF_E_INVALID, "output plane not 4-byte aligned");
+  if (o->filtered && !g->bandpass)
+    return fail(err, PWBF_E_INVALID, "filtered output requested without bandpass");
+  if (post_requested(o) || g->bandpass) {
+    if (!is_pow2(g->nz) || g->nz > kMaxNzPost || g->nz < 2)
+      return fail(err, PWBF_E_UNSUPPORTED,
+                  "depth post-processing needs nz a power of two in 2..%d (nz = %d)", kMaxNzPost,
+                  g->nz);
+  }
+  if (g->bandpass) {
+    if (!(g->f0 > 0) || !finite(g->f0)) return fail(err, PWBF_E_INVALID, "bandpass needs f0 > 0");
+    double dz_max = g->c / (12.0 * g->f0);
+    if (g->dz > dz_max * (1 + 1e-9))
+      return fail(err, PWBF_E_UNSUPPORTED,
+                  "bandpass [f0, 3 f0] needs dz <= c / (12 f0) = %.4g m (dz = %.4g m)", dz_max,
+                  g->dz);
+  }
+  size_t need = workspace_bytes(g, o);
+  if (need) {
+    if (!ws) return fail(err, PWBF_E_INVALID, "workspace of %zu bytes required", need);
+    if (ws_bytes < need)
+      return fail(err, PWBF_E_INVALID, "workspace %zu bytes < %zu required", ws_bytes, need);
+    if ((uintptr_t)ws % 256) return fail(err, PWBF_E_INVALID, "workspace not 256-byte aligned");
+  }
+  return PWBF_OK;
+}
+
+pwbf_tile default_tile(const pwbf_geometry *g, int n_angles_used, int mode) {
+  (void)mode;
+  pwbf_tile t;
+  int64_t pixels = (int64_t)g->nx * g->nz;
+  // Small frames split channels across lane groups so there are enough waves.
+  t.cpw = pixels >= 256 * 1024 ? 1 : (pixels >= 64 * 1024 ? 2 : 4);
+  t.wz = 1;
+  t.wx = 8;
+  t.chunk = 0;
+  (void)n_angles_used;
+  return t;
+}
+
+static int window_entries(const FramePlan &p, int TZ, int TX) {
+  double rt = 0;
+  for (int a = 0; a < p.n_angles; ++a) {
+    double v = std::fabs((double)p.sa[a]) * (TX - 1) * p.DX +
+               std::fabs((double)p.ca[a]) * (TZ - 1) * p.DZ;
+    rt = std::max(rt, v);
+  }
+  double rr = std::hypot((TX - 1) * (double)p.DX, (TZ - 1) * (double)p.DZ);
+  return (int)std::ceil(rt + rr) + 6;
+}
+
+// Apply launch shape t to plan P (geometry already filled in): window length,
+// channels per LDS chunk. PWBF_E_UNSUPPORTED when even cpw channels do not fit.
+static int fit_tile(const pwbf_geometry *g, pwbf_tile t, FramePlan *P, std::string *err) {
+  if (t.cpw != 1 && t.cpw != 2 && t.cpw != 4)
+    return fail(err, PWBF_E_INVALID, "tile.cpw %d not in {1, 2, 4}", t.cpw);
+  if (t.wz < 1 || t.wx < 1 || t.wz * t.wx > kMaxWavesPerBlock)
+    return fail(err, PWBF_E_INVALID, "tile %d x %d wavefronts outside 1..%d", t.wz, t.wx,
+                kMaxWavesPerBlock);
+  if (t.chunk < 0 || t.chunk % t.cpw)
+    return fail(err, PWBF_E_INVALID, "tile.chunk %d not a non-negative multiple of cpw",
+                t.chunk);
+  P->cpw = t.cpw;
+  P->wz = t.wz;
+  P->wx = t.wx;
+  const int TZ = (kWave / t.cpw) * t.wz, TX = t.wx;
+  // a tile's pixels never extend past the grid (edge lanes repeat the edge pixel)
+  P->win = window_entries(*P, std::min(TZ, g->nz), std::min(TX, g->nx));
+  const size_t per_channel = (size_t)P->n_angles * P->win * 8 + 8;
+  const size_t fixed = kMaxAngles * 4;
+  int chunk = t.chunk;
+  if (chunk == 0) {
+    int fit = (int)((kMaxLdsBytes - fixed) / per_channel);
+    // as many channels as fit, split evenly over the array
+    int nch = (g->n_channels + t.cpw - 1) / t.cpw * t.cpw;
+    if (fit >= nch) {
+      chunk = nch;
+    } else {
+      int nchunks = (nch + fit - 1) / std::max(fit, 1);
+      chunk = (nch + nchunks - 1) / nchunks;
+      chunk = (chunk + t.cpw - 1) / t.cpw * t.cpw;
+      while (chunk > fit && chunk > t.cpw) chunk -= t.cpw;
+    }
+  }
+  P->chunk = chunk;
+  if (chunk < t.cpw || plan_lds_bytes(*P) > (size_t)kMaxLdsBytes)
+    return fail(err, PWBF_E_UNSUPPORTED,
+                "tile needs %zu bytes of LDS per block (limit %d); use a smaller tile",
+                plan_lds_bytes(*P), kMaxLdsBytes);
+  return PWBF_OK;
+}
+
+int plan_frame(const pwbf_geometry *g, int dtype, int mode, int angle, const pwbf_tile *tile_in,
+               FramePlan *P, std::string *err) {
+  int rc = validate_geometry(g, err);
+  if (rc) return rc;
+  if (dtype != kI16 && dtype != kF16 && dtype != kF32)
+    return fail(err, PWBF_E_INVALID, "rf_dtype %d unknown", dtype);
+  if (mode != kDas && mode != kDmas) return fail(err, PWBF_E_INVALID, "mode %d unknown", mode);
+  if (angle < -1 || angle >= g->n_angles)
+    return fail(err, PWBF_E_INVALID, "angle %d outside 0..%d", angle, g->n_angles - 1);
+  if (mode == kDmas && g->n_channels < 2)
+    return fail(err, PWBF_E_INVALID, "DMAS needs at least 2 channels");
+
+  std::memset(P, 0, sizeof *P);
+  const double scale = g->fs / g->c;
+  const int a0 = angle < 0 ? 0 : angle;
+  const int na = angle < 0 ? g->n_angles : 1;
+  P->dtype = dtype;
+  P->mode = mode;
+  P->apod = g->apod;
+  P->n_angles = na;
+  P->n_channels = g->n_channels;
+  P->n_samples = g->n_samples;
+  P->nx = g->nx;
+  P->nz = g->nz;
+  P->X0 = (float)(g->x0 * scale);
+  P->DX = (float)(g->dx * scale);
+  P->Z0 = (float)(g->z0 * scale);
+  P->DZ = (float)(g->dz * scale);
+  P->ap_k = g->apod == kNone ? 0.0f : (float)(2.0 * g->f_number);
+  for (int e = 0; e < kMaxChannels; ++e)
+    P->xe[e] = (float)(g->elem_x[std::min(e, g->n_channels - 1)] * scale);
+  for (int k = 0; k < na; ++k) {
+    int a = a0 + k;
+    double th = g->angle_rad[a];
+    double first = g->elem_x[0] * std::sin(th);
+    for (int e = 1; e < g->n_channels; ++e) first = std::min(first, g->elem_x[e] * std::sin(th));
+    P->sa[k] = (float)std::sin(th);
+    P->ca[k] = (float)std::cos(th);
+    P->to[k] = (float)(first * scale + (g->t0 ? g->t0[a] : 0.0) * g->fs);
+  }
+
+  // An explicit tile is taken as given; the default falls back to shapes with
+  // shorter tiles (more lane groups, fewer columns) until its windows fit in LDS.
+  pwbf_tile d = default_tile(g, na, mode);
+  pwbf_tile cands[8];
+  int nc = 0;
+  if (tile_in) {
+    pwbf_tile t = *tile_in;
+    if (t.cpw == 0) t.cpw = d.cpw;
+    if (t.wz == 0 && t.wx == 0) {
+      t.wz = d.wz;
+      t.wx = d.wx;
+    }
+    cands[nc++] = t;
+  } else {
+    cands[nc++] = d;
+    const pwbf_tile more[] = {{2, 1, 8, 0}, {4, 1, 8, 0}, {4, 1, 4, 0}, {4, 1, 2, 0},
+                              {4, 1, 1, 0}};
+    for (const pwbf_tile &m : more)
+      if (m.cpw >= d.cpw) cands[nc++] = m;
+  }
+  int rc_fit = PWBF_OK;
+  for (int ci = 0; ci < nc; ++ci) {
+    rc_fit = fit_tile(g, cands[ci], P, err);
+    if (rc_fit != PWBF_E_UNSUPPORTED || tile_in) break;
+  }
+  if (rc_fit) return rc_fit;
+  const int TZ = (kWave / P->cpw) * P->wz, TX = P->wx;
+  P->tiles_z = (g->nz + TZ - 1) / TZ;
+  P->tiles_x = (g->nx + TX - 1) / TX;
+  P->n_tiles = P->tiles_z * P->tiles_x;
+  P->tiles_per_xcd = (P->n_tiles + 7) / 8;
+  return PWBF_OK;
+}
+
+int build_plan(const pwbf_geometry *g, const void *rf, int dtype, int mode, int angle,
+               const pwbf_tile *tile, const pwbf_outputs *o, void *ws, size_t ws_bytes,
+               FramePlan *P, std::string *err) {
+  int rc = plan_frame(g, dtype, mode, angle, tile, P, err);
+  if (rc) return rc;
+  if (!rf) return fail(err, PWBF_E_INVALID, "rf is NULL");
+  if ((uintptr_t)rf % dtype_bytes(dtype))
+    return fail(err, PWBF_E_INVALID, "rf not aligned to its element size");
+  rc = validate_outputs(g, o, ws, ws_bytes, err);
+  if (rc) return rc;
+  const size_t slab = (size_t)g->n_channels * g->n_samples * dtype_bytes(dtype);
+  P->rf = (const char *)rf + (size_t)(angle < 0 ? 0 : angle) * slab;
+  P->out = o->rf;
+  P->ws_max = o->logimg ? (uint32_t *)ws : nullptr;
+  return PWBF_OK;
+}
+
+int build_post_plan(const pwbf_geometry *g, const pwbf_outputs *o, void *ws, PostPlan *Q) {
+  std::memset(Q, 0, sizeof *Q);
+  Q->src = o->rf;
+  Q->filtered = o->filtered;
+  Q->ws_max = o->logimg ? (uint32_t *)ws : nullptr;
+  Q->env = o->env ? o->env : (o->logimg ? (float *)((char *)ws + 256) : nullptr);
+  Q->logimg = o->logimg;
+  Q->nx = g->nx;
+  Q->nz = g->nz;
+  int l = 0;
+  while ((1 << l) < g->nz) ++l;
+  Q->log2nz = l;
+  Q->bandpass = g->bandpass;
+  Q->floor_db = (float)g->log_floor_db;
+  if (g->bandpass) {
+    // The same decision, in double, as the definition: bin k' carries the
+    // round-trip frequency |k'| c / (2 nz dz); keep it when f0 <= f <= 3 f0.
+    int lo = -1, hi = -2;
+    for (int k = 0; k <= g->nz / 2; ++k) {
+      double f = (double)k * g->c / (2.0 * g->nz * g->dz);
+      if (f >= g->f0 && f <= 3.0 * g->f0) {
+        if (lo < 0) lo = k;
+        hi = k;
+      }
+    }
+    Q->k_lo = lo;
+    Q->k_hi = hi;
+  }
+  return PWBF_OK;
+}
+
+bool post_needed(const pwbf_outputs *o) { return post_requested(o); }
+
+}  // namespace pwbf

@@ -1,0 +1,61 @@
+// Launch plans shared by the host library and the HIP kernels.
+//
+// A FramePlan holds everything one frame's beamforming kernel needs, in float32
+// and in *sample units*: every length is multiplied by fs / c, so a pixel at
+// (X, Z) and an element at Xe give the receive delay sqrt((X - Xe)^2 + Z^2)
+// directly in samples. The host computes these constants in double precision
+// and rounds each one once.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+
+namespace pwbf {
+
+constexpr int kMaxAngles = 32;
+constexpr int kMaxChannels = 256;
+constexpr int kWave = 64;
+constexpr int kMaxWavesPerBlock = 8;
+constexpr int kMaxLdsBytes = 64 * 1024;
+constexpr int kMaxNzPost = 4096;
+
+enum Dtype : int32_t { kI16 = 0, kF16 = 1, kF32 = 2 };
+enum Mode : int32_t { kDas = 0, kDmas = 1 };
+enum Apod : int32_t { kHann = 0, kBoxcar = 1, kNone = 2 };
+
+struct FramePlan {
+  const void *rf;  // RF[n_angles][n_channels][n_samples] of dtype (single angle: its slab)
+  float *out;      // [nx][nz] beamformed image
+  uint32_t *ws_max;  // cleared by the beamform kernel when the log image is requested
+  int32_t dtype, mode, apod;
+  int32_t n_angles, n_channels, n_samples;
+  int32_t nx, nz;
+  float X0, DX, Z0, DZ;  // centre of pixel (0, 0) and pitches, samples
+  float ap_k;            // 2 F#: normalised aperture distance r = |X - Xe| * ap_k / Z
+  // launch shape
+  int32_t cpw, wz, wx, chunk;
+  int32_t win;           // LDS entries per (channel, angle) window
+  int32_t tiles_z, tiles_x, n_tiles, tiles_per_xcd;
+  float sa[kMaxAngles];  // sin(theta_a)
+  float ca[kMaxAngles];  // cos(theta_a)
+  float to[kMaxAngles];  // first-firing offset plus t0, samples
+  float xe[kMaxChannels];  // element x, samples (padded with the last element)
+};
+
+struct PostPlan {
+  const float *src;  // [nx][nz] image to post-process
+  float *filtered;   // Re(analytic) of the band-passed column, or null
+  float *env;        // |analytic|, or null
+  float *logimg;     // log image, or null (needs env and ws_max)
+  uint32_t *ws_max;  // bit pattern of the frame's largest envelope value
+  int32_t nx, nz, log2nz;
+  int32_t bandpass, k_lo, k_hi;  // band [k_lo, k_hi] in |signed bin|
+  float floor_db;
+};
+
+// LDS bytes one block of this plan uses.
+inline size_t plan_lds_bytes(const FramePlan &p) {
+  return (size_t)p.chunk * p.n_angles * p.win * 8 + (size_t)p.chunk * 8 + kMaxAngles * 4;
+}
+
+}  // namespace pwbf

@@ -1,0 +1,28 @@
+// Host-side validation and plan construction (no HIP calls; safe without a GPU).
+#pragma once
+
+#include <string>
+
+#include "../../include/pwbf.h"
+#include "plan.h"
+
+namespace pwbf {
+
+size_t dtype_bytes(int dtype);
+int validate_geometry(const pwbf_geometry *g, std::string *err);
+int validate_outputs(const pwbf_geometry *g, const pwbf_outputs *o, void *ws, size_t ws_bytes,
+                     std::string *err);
+size_t workspace_bytes(const pwbf_geometry *g, const pwbf_outputs *o);
+pwbf_tile default_tile(const pwbf_geometry *g, int n_angles_used, int mode);
+// Geometry and launch shape only (no pointers). angle < 0: all angles
+// (compound); angle >= 0: that angle alone.
+int plan_frame(const pwbf_geometry *g, int dtype, int mode, int angle, const pwbf_tile *tile,
+               FramePlan *P, std::string *err);
+// plan_frame plus the pointer, output and workspace checks.
+int build_plan(const pwbf_geometry *g, const void *rf, int dtype, int mode, int angle,
+               const pwbf_tile *tile, const pwbf_outputs *o, void *ws, size_t ws_bytes,
+               FramePlan *P, std::string *err);
+int build_post_plan(const pwbf_geometry *g, const pwbf_outputs *o, void *ws, PostPlan *Q);
+bool post_needed(const pwbf_outputs *o);
+
+}  // namespace pwbf

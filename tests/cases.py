@@ -1,0 +1,67 @@
+"""Small geometries shared by the GPU parity tests and the CPU window-bound check."""
+
+import numpy as np
+
+from synth import Geometry
+
+
+def geom(**kw):
+    base = dict(n_channels=16, n_samples=600, angles_deg=(0.0,), nx=37, nz=100,
+                x_min=-3e-3, x_max=3e-3, z_min=3e-3, z_max=12e-3, f_number=1.2)
+    base.update(kw)
+    return Geometry(**base)
+
+
+def rand_rf(g, seed, kind="f32"):
+    rng = np.random.default_rng(seed)
+    if kind == "i16":
+        return rng.integers(-512, 512, (g.n_angles, g.n_channels, g.n_samples)).astype(np.int16)
+    return rng.standard_normal((g.n_angles, g.n_channels, g.n_samples))
+
+
+SMALL = [
+    # name, geometry kwargs, mode, angle, tile, dtype
+    ("das_1ch", dict(n_channels=1), "das", 0, None, "f32"),
+    ("das_ragged_cpw1", dict(nx=37, nz=100), "das", 0, (1, 1, 4, 0), "f32"),
+    ("das_ragged_cpw2", dict(nx=13, nz=257), "das", 0, (2, 2, 2, 6), "i16"),
+    ("das_ragged_cpw4", dict(nx=9, nz=33, n_channels=7), "das", 0, (4, 1, 3, 4), "f32"),
+    ("das_one_pixel", dict(nx=1, nz=1), "das", 0, None, "f32"),
+    ("das_one_column", dict(nx=1, nz=300), "das", 0, (1, 3, 1, 0), "f32"),
+    ("das_boxcar", dict(apod="boxcar"), "das", 0, None, "f32"),
+    ("das_no_apod_near_array", dict(apod="none", z_min=-1e-3, z_max=4e-3), "das", 0, None, "f32"),
+    ("das_record_too_short", dict(n_samples=120), "das", 0, None, "f32"),
+    ("compound_3a", dict(angles_deg=(-12.0, 0.0, 9.0)), "das", -1, None, "f32"),
+    ("compound_7a_t0", dict(angles_deg=(-15., -10., -5., 0., 5., 10., 15.),
+                            t0=(0.5e-6, 0.0, -0.3e-6, 1e-6, 0.0, 0.2e-6, 0.0)), "das", -1,
+     (1, 2, 2, 0), "f32"),
+    ("compound_17a_generic", dict(angles_deg=tuple(range(-16, 18, 2)), nx=11, nz=70), "das",
+     -1, None, "f32"),
+    ("compound_32a_generic", dict(angles_deg=tuple(np.linspace(-20, 20, 32)), nx=6, nz=40,
+                                  n_channels=8), "das", -1, (1, 1, 2, 0), "f32"),
+    ("angle_slab", dict(angles_deg=(-8.0, 4.0, 11.0)), "das", 2, None, "i16"),
+    ("dmas_2ch", dict(n_channels=2), "dmas", 0, None, "f32"),
+    ("dmas_ragged_cpw2", dict(nx=21, nz=77, n_channels=12), "dmas", 0, (2, 1, 4, 4), "f32"),
+    ("dmas_compound_5a", dict(angles_deg=(-10., -5., 0., 5., 10.)), "dmas", -1, None, "i16"),
+    ("dmas_compound_generic", dict(angles_deg=tuple(range(-18, 18, 2)), nx=7, nz=40,
+                                   n_channels=6), "dmas", -1, (4, 1, 2, 0), "f32"),
+]
+
+
+
+TILE_SWEEP = geom(angles_deg=(-6.0, 0.0, 6.0, 12.0), nx=40, nz=140, n_channels=24)
+_SWEEP_ALL = [(cpw, wz, wx, chunk) for cpw in (1, 2, 4)
+              for wz, wx in ((1, 1), (1, 8), (2, 4), (4, 2), (8, 1))
+              for chunk in (0, cpw, 3 * cpw)]
+
+
+def tile_sweep_shapes():
+    """The sweep's launch shapes whose LDS windows fit (the others are rejected)."""
+    from paper_2311_00482_amd import PwbfError, Tile, describe_plan
+    ok = []
+    for sh in _SWEEP_ALL:
+        try:
+            describe_plan(TILE_SWEEP, "das", -1, Tile(*sh))
+            ok.append(sh)
+        except PwbfError:
+            pass
+    return ok

@@ -1,0 +1,200 @@
+"""The C ABI on the CPU: the library loads, exports every declared symbol, and
+rejects invalid arguments on the host before any HIP call.
+
+Argument checks go through pwbf_validate_call, which runs every host-side check
+of the beamforming entry points and never enqueues work, so the fake device
+addresses below are never used. The real entry points are only called with
+arguments that fail their very first check.
+"""
+
+import ctypes
+import os
+import re
+import threading
+
+import numpy as np
+import pytest
+
+from paper_2311_00482_amd import _abi
+from paper_2311_00482_amd.api import GeometryArg, Tile, describe_plan
+from synth import config_c1, config_c2, config_c3
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+FAKE = 0x10000  # an aligned address that validation accepts but is never used
+
+
+def declared_symbols():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", fn)).read()
+            names |= set(re.findall(r"PWBF_API\s+[\w\s\*]+?\b(pwbf_\w+)\s*\(", txt))
+    return sorted(names)
+
+
+def test_library_exports_every_declared_symbol():
+    L = _abi.lib()
+    names = declared_symbols()
+    assert len(names) >= 8
+    for n in names:
+        assert hasattr(L, n), n
+    assert L.pwbf_abi_version() == _abi.ABI_VERSION
+
+
+def _call(g, rf=FAKE, dtype=_abi.I16, mode=_abi.DAS, angle=-1, tile=None, out=None, ws=None,
+          ws_bytes=0):
+    if out is None:
+        out = _abi.Outputs(FAKE, None, None, None)
+    L = _abi.lib()
+    t = ctypes.byref(tile) if tile is not None else None
+    o = ctypes.byref(out) if out is not False else None
+    gref = g.ref if g is not None else None
+    rc = L.pwbf_validate_call(gref, rf, dtype, mode, angle, t, o, ws, ws_bytes)
+    return rc, L.pwbf_last_error().decode()
+
+
+def test_entry_points_reject_null_geometry_first():
+    L = _abi.lib()
+    o = ctypes.byref(_abi.Outputs(FAKE, None, None, None))
+    assert L.pwbf_beamform_das(None, FAKE, 0, 0, o, None, 0, None) == _abi.E_INVALID
+    assert L.pwbf_beamform_dmas(None, FAKE, 0, 0, o, None, 0, None) == _abi.E_INVALID
+    assert L.pwbf_compound(None, FAKE, 0, 0, o, None, 0, None) == _abi.E_INVALID
+    assert L.pwbf_beamform_ex(None, FAKE, 0, 0, -1, None, o, None, 0, None) == _abi.E_INVALID
+    assert "NULL" in L.pwbf_last_error().decode()
+
+
+def test_valid_call_passes_validation():
+    assert _call(GeometryArg(config_c1()), angle=0) == (0, "")
+
+
+def test_null_and_version_errors():
+    assert _call(None)[0] == _abi.E_INVALID
+    g = GeometryArg(config_c1())
+    g.s.abi_version = 99
+    rc, msg = _call(g)
+    assert rc == _abi.E_INVALID and "abi_version" in msg
+
+
+@pytest.mark.parametrize("field,value,code", [
+    ("n_angles", 0, _abi.E_INVALID), ("n_angles", 33, _abi.E_UNSUPPORTED),
+    ("n_channels", 0, _abi.E_INVALID), ("n_channels", 257, _abi.E_UNSUPPORTED),
+    ("n_samples", 1, _abi.E_INVALID), ("c", 0.0, _abi.E_INVALID), ("fs", -1.0, _abi.E_INVALID),
+    ("nx", 0, _abi.E_INVALID), ("dz", 0.0, _abi.E_INVALID), ("dx", float("nan"), _abi.E_INVALID),
+    ("apod", 7, _abi.E_INVALID), ("f_number", 0.0, _abi.E_INVALID),
+    ("log_floor_db", 3.0, _abi.E_INVALID), ("bandpass", 2, _abi.E_INVALID),
+])
+def test_geometry_validation(field, value, code):
+    g = GeometryArg(config_c1())
+    setattr(g.s, field, value)
+    rc, msg = _call(g)
+    assert rc == code, msg
+    assert msg
+
+
+def test_far_field_rejected_for_float32_delays():
+    g = GeometryArg(config_c1())
+    g.s.z0 = 50.0  # 50 m deep: delays beyond what float32 resolves
+    assert _call(g)[0] == _abi.E_UNSUPPORTED
+
+
+def test_angle_validation():
+    g = config_c1()
+    ga = GeometryArg(g.replace(angles_deg=(0.0, 95.0)))
+    assert _call(ga)[0] == _abi.E_INVALID
+    ga = GeometryArg(g)
+    assert _call(ga, angle=1)[0] == _abi.E_INVALID
+    assert _call(ga, angle=-2)[0] == _abi.E_INVALID
+    L = _abi.lib()
+    o = _abi.Outputs(FAKE, None, None, None)
+    # the single-angle entry point rejects a negative angle before anything else
+    assert L.pwbf_beamform_das(ga.ref, FAKE, 0, -1, ctypes.byref(o), None, 0, None) == \
+        _abi.E_INVALID
+
+
+def test_call_argument_validation():
+    g = GeometryArg(config_c1())
+    assert _call(g, rf=None)[0] == _abi.E_INVALID
+    assert _call(g, rf=FAKE + 1)[0] == _abi.E_INVALID  # int16 needs 2-byte alignment
+    assert _call(g, rf=FAKE + 2, dtype=_abi.F32)[0] == _abi.E_INVALID
+    assert _call(g, dtype=9)[0] == _abi.E_INVALID
+    assert _call(g, mode=3)[0] == _abi.E_INVALID
+    assert _call(g, out=False)[0] == _abi.E_INVALID
+    assert _call(g, out=_abi.Outputs(None, None, None, None))[0] == _abi.E_INVALID
+    assert _call(g, out=_abi.Outputs(FAKE + 2, None, None, None))[0] == _abi.E_INVALID
+    rc, msg = _call(g, out=_abi.Outputs(FAKE, FAKE, None, None))
+    assert rc == _abi.E_INVALID and "bandpass" in msg
+    one = GeometryArg(config_c1().replace(n_channels=1))
+    assert _call(one, mode=_abi.DMAS)[0] == _abi.E_INVALID
+
+
+def test_post_processing_shape_rules():
+    g = GeometryArg(config_c1().replace(nz=250))
+    assert _call(g, out=_abi.Outputs(FAKE, None, FAKE, None))[0] == _abi.E_UNSUPPORTED
+    g = GeometryArg(config_c1().replace(nz=8192, z_max=80e-3))
+    assert _call(g, out=_abi.Outputs(FAKE, None, FAKE, None))[0] == _abi.E_UNSUPPORTED
+    # band-pass needs dz <= c / (12 f0): C1's 156 um grid is too coarse, C2's 25 um is fine
+    g = GeometryArg(config_c1(), bandpass=True)
+    rc, msg = _call(g)
+    assert rc == _abi.E_UNSUPPORTED and "c / (12 f0)" in msg
+
+
+def test_workspace_rules():
+    L = _abi.lib()
+    g = GeometryArg(config_c1())
+    assert L.pwbf_workspace_bytes(g.ref, ctypes.byref(_abi.Outputs(FAKE, None, None, None))) == 0
+    assert L.pwbf_workspace_bytes(g.ref, ctypes.byref(_abi.Outputs(FAKE, None, FAKE, None))) == 0
+    assert L.pwbf_workspace_bytes(g.ref, ctypes.byref(_abi.Outputs(FAKE, None, FAKE, FAKE))) == 256
+    n = L.pwbf_workspace_bytes(g.ref, ctypes.byref(_abi.Outputs(FAKE, None, None, FAKE)))
+    assert n == 256 + 128 * 256 * 4
+    log = _abi.Outputs(FAKE, None, FAKE, FAKE)
+    assert _call(g, out=log)[0] == _abi.E_INVALID  # no workspace
+    assert _call(g, out=log, ws=FAKE, ws_bytes=255)[0] == _abi.E_INVALID
+    assert _call(g, out=log, ws=FAKE + 64, ws_bytes=4096)[0] == _abi.E_INVALID  # alignment
+    g.s.nx = 0
+    assert L.pwbf_workspace_bytes(g.ref, ctypes.byref(log)) == 0
+    assert L.pwbf_last_error().decode()
+
+
+@pytest.mark.parametrize("tile,code", [
+    (Tile(cpw=3), _abi.E_INVALID), (Tile(cpw=1, wz=3, wx=3), _abi.E_INVALID),
+    (Tile(cpw=2, wz=1, wx=1, chunk=3), _abi.E_INVALID),
+    (Tile(cpw=1, wz=1, wx=8, chunk=256), _abi.E_UNSUPPORTED),
+])
+def test_tile_validation(tile, code):
+    g = GeometryArg(config_c3())
+    assert _call(g, tile=tile.c())[0] == code
+
+
+def test_last_error_is_thread_local():
+    g = GeometryArg(config_c1())
+    g.s.n_samples = 1
+    _call(g)
+    main_msg = _abi.lib().pwbf_last_error().decode()
+    seen = []
+
+    def worker():
+        seen.append(_abi.lib().pwbf_last_error().decode())
+
+    t = threading.Thread(target=worker)
+    t.start()
+    t.join()
+    assert main_msg and seen == [""]
+
+
+def test_describe_plan_default_shapes():
+    p = describe_plan(config_c3())
+    assert p["n_angles_used"] == 11 and p["cpw"] == 1
+    assert p["threads_per_block"] == 64 * p["wz"] * p["wx"]
+    assert p["blocks"] % 8 == 0 and p["blocks"] >= p["tiles_z"] * p["tiles_x"]
+    assert p["lds_bytes"] <= 64 * 1024
+    assert p["chunk"] * 1 >= 1
+    p1 = describe_plan(config_c1(), angle=0)
+    assert p1["n_angles_used"] == 1
+    sc = 20e6 / 1540.0
+    g = config_c1()
+    assert p1["X0"] == pytest.approx(g.x0 * sc, rel=1e-6)
+    assert p1["DZ"] == pytest.approx(g.dz * sc, rel=1e-6)
+    np.testing.assert_allclose(p1["xe"][:64], (g.elem_x * sc).astype(np.float32))
+    assert p1["xe"][200] == p1["xe"][63]
+    p2 = describe_plan(config_c2(), "dmas", bandpass=True)
+    assert p2["n_angles_used"] == 1

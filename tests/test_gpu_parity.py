@@ -1,0 +1,293 @@
+"""GPU parity: the HIP path against the FP64 oracle, element by element.
+
+Bars (max-normalised error e = max|gpu - oracle| / max|oracle| per plane):
+float32 compute on int16 or float32 RF: e <= 1e-5; float16-stored RF:
+e <= 1e-3 and |dL| <= 0.1 dB on the log image where the oracle is at or above
+-40 dB. Full-size workloads are checked on sampled pixels and whole sampled
+depth columns in the launch configuration the benchmark times.
+"""
+
+import json
+import os
+import zlib
+
+import numpy as np
+import pytest
+
+import oracle
+from synth import Geometry, config_c1, config_c2, config_c3, make_frame, paper_geometry
+from synth.phantom import phantom_scaled, simulate_rf
+
+from cases import SMALL, TILE_SWEEP, geom, rand_rf, tile_sweep_shapes
+
+pytestmark = pytest.mark.gpu
+
+TOL32 = 1e-5
+TOL16 = 1e-3
+TOL_DB = 0.1
+REPORT = {}
+
+
+def _torch():
+    import torch
+    assert torch.cuda.is_available(), "these tests need the GPU"
+    return torch
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _report():
+    yield
+    path = os.environ.get("PWBF_PARITY_REPORT")
+    if path:
+        with open(path, "w") as f:
+            json.dump(REPORT, f, indent=1, sort_keys=True)
+
+
+def err(gpu, ora):
+    gpu = np.asarray(gpu, np.float64)
+    ora = np.asarray(ora, np.float64)
+    m = np.abs(ora).max()
+    if m == 0:
+        return float(np.abs(gpu).max())
+    return float(np.abs(gpu - ora).max() / m)
+
+
+def to_dev(a, dtype=None):
+    torch = _torch()
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.cuda()
+
+
+def run(g, rf_t, mode="das", angle=-1, want=("rf",), tile=None, bandpass=False):
+    from paper_2311_00482_amd import beamform
+    torch = _torch()
+    out = beamform(g, rf_t, mode, angle, tile=tile, want=want, bandpass=bandpass)
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy().astype(np.float64) for k, v in out.items()}
+
+
+def log_err_db(gpu_log, ora_log, above=-40.0):
+    m = ora_log >= above
+    return float(np.abs(gpu_log[m] - ora_log[m]).max())
+
+
+# ---------------------------------------------------------------- C1: 64 ch, 0 deg
+@pytest.fixture(scope="module")
+def c1():
+    return make_frame(config_c1(), 1001, "c1")
+
+
+def test_c1_das_rf_envelope_log(c1):
+    g = config_c1()
+    out = run(g, to_dev(c1["i16"]), "das", 0, ("rf", "env", "log"))
+    ref = oracle.beamform(g, c1["master"], "das", 0)
+    e_rf, e_env = err(out["rf"], ref["rf"]), err(out["env"], ref["env"])
+    e_db = log_err_db(out["log"], ref["log"])
+    REPORT["c1_das_int16"] = {"rf": e_rf, "env": e_env, "log_db": e_db}
+    assert e_rf <= TOL32 and e_env <= TOL32 and e_db <= TOL_DB
+    assert out["log"].max() == 0.0 and out["log"].min() >= -70.0
+
+
+def test_c1_points_peak_at_their_pixels(c1):
+    # the snapped point targets are the brightest features of the image
+    g = config_c1()
+    env = np.abs(run(g, to_dev(c1["i16"]), "das", 0, ("rf",))["rf"])
+    for x, z in c1["phantom"].points:
+        ix, iz = int(round((x - g.x0) / g.dx)), int(round((z - g.z0) / g.dz))
+        win = env[max(ix - 3, 0):ix + 4, max(iz - 3, 0):iz + 4]
+        jx, jz = np.unravel_index(np.argmax(win), win.shape)
+        assert abs(jx + max(ix - 3, 0) - ix) <= 1 and abs(jz + max(iz - 3, 0) - iz) <= 1
+
+
+# ------------------------------------------------------ C2: 128 ch DMAS, 512x512
+@pytest.fixture(scope="module")
+def c2():
+    return make_frame(config_c2(), 1001, "c1")
+
+
+def test_c2_dmas_raw_bandpass_envelope(c2):
+    g = config_c2()
+    out = run(g, to_dev(c2["i16"]), "dmas", -1, ("rf", "filtered", "env", "log"), bandpass=True)
+    raw = oracle.dmas(g, c2["master"], 0, "identity")
+    filt = oracle.bandpass_z(raw, g.dz, g.c, g.f0)
+    env = oracle.envelope_z(filt)
+    lg = oracle.log_compress(env)
+    rep = {"rf": err(out["rf"], raw), "filtered": err(out["filtered"], filt),
+           "env": err(out["env"], env), "log_db": log_err_db(out["log"], lg)}
+    # the O(N^2) pair form on sampled pixels
+    pix = np.random.default_rng(0).choice(g.nx * g.nz, 1500, replace=False)
+    pairs = oracle.dmas(g, c2["master"], 0, "pairs", pix)
+    rep["rf_vs_pairs"] = float(np.abs(out["rf"].ravel()[pix] - pairs).max() / np.abs(raw).max())
+    REPORT["c2_dmas_int16"] = rep
+    assert rep["rf"] <= TOL32 and rep["filtered"] <= TOL32 and rep["env"] <= TOL32
+    assert rep["rf_vs_pairs"] <= TOL32 and rep["log_db"] <= TOL_DB
+
+
+def test_c2_das_same_grid(c2):
+    g = config_c2()
+    out = run(g, to_dev(c2["i16"]), "das", 0, ("rf", "env"))
+    ref = oracle.das(g, c2["master"], 0)
+    e = err(out["rf"], ref)
+    e_env = err(out["env"], oracle.envelope_z(ref))
+    REPORT["c2_das_int16"] = {"rf": e, "env": e_env}
+    assert e <= TOL32 and e_env <= TOL32
+
+
+def test_c2_dmas_sharpens_points_relative_to_das(c2):
+    # RF DMAS narrows the lateral -6 dB width of the point targets
+    g = config_c2()
+    das = run(g, to_dev(c2["i16"]), "das", 0, ("rf", "env"))["env"]
+    dm = run(g, to_dev(c2["i16"]), "dmas", 0, ("rf", "env"), bandpass=True)["env"]
+    widths = []
+    for x, z in c2["phantom"].points:
+        if not (g.z_min + 1e-3 < z < g.z_max - 1e-3):
+            continue
+        ix, iz = int(round((x - g.x0) / g.dx)), int(round((z - g.z0) / g.dz))
+        w = []
+        for img in (das, dm):
+            col = np.argmax(img[ix, max(iz - 20, 0):iz + 20]) + max(iz - 20, 0)
+            prof = img[:, col]
+            k = np.argmax(prof[max(ix - 10, 0):ix + 11]) + max(ix - 10, 0)
+            half = prof[k] / 2
+            lft = k
+            while lft > 0 and prof[lft] > half:
+                lft -= 1
+            rgt = k
+            while rgt < len(prof) - 1 and prof[rgt] > half:
+                rgt += 1
+            w.append(rgt - lft)
+        widths.append(w)
+    assert widths and all(d <= a for a, d in widths)
+
+
+# ---------------------------------------- C3: 11 angles, 128 ch, 1024x1024, full size
+@pytest.fixture(scope="module")
+def c3():
+    return make_frame(config_c3(), 1003, "c3", quantize=False)
+
+
+def _c3_check(c3, key, rf_t, tol, tol_db):
+    g = config_c3()
+    out = run(g, rf_t, "das", -1, ("rf", "env", "log"))
+    rng = np.random.default_rng(7)
+    pts = c3["phantom"].points
+    pix_pts = [int(round((x - g.x0) / g.dx)) * g.nz + int(round((z - g.z0) / g.dz))
+               for x, z in pts]
+    amax = int(np.argmax(np.abs(out["rf"])))
+    pix = np.unique(np.concatenate([rng.choice(g.nx * g.nz, 3000, replace=False), pix_pts,
+                                    [amax]]))
+    ref = oracle.das(g, c3["master"], -1, pix)
+    norm = np.abs(out["rf"]).max()
+    # the image maximum seen by the GPU is the oracle's at that pixel
+    assert abs(oracle.das(g, c3["master"], -1, [amax])[0]) == pytest.approx(norm, rel=tol)
+    e_rf = float(np.abs(out["rf"].ravel()[pix] - ref).max() / norm)
+    # whole depth columns through three point targets for the envelope and log
+    cols = sorted({int(round((x - g.x0) / g.dx)) for x, _ in pts[:3]})
+    col_pix = np.concatenate([np.arange(g.nz) + ix * g.nz for ix in cols])
+    ref_cols = oracle.das(g, c3["master"], -1, col_pix).reshape(len(cols), g.nz)
+    env_ref = oracle.envelope_z(ref_cols)
+    env_max = out["env"].max()
+    e_env = float(np.abs(out["env"][cols] - env_ref).max() / env_max)
+    lg_ref = np.maximum(20 * np.log10(np.maximum(env_ref, 1e-300) / env_max), -70.0)
+    e_db = log_err_db(out["log"][cols], lg_ref)
+    REPORT[key] = {"rf_sampled": e_rf, "env_columns": e_env, "log_db_columns": e_db,
+                   "n_pixels": int(len(pix)), "columns": cols}
+    assert e_rf <= tol and e_env <= tol and e_db <= tol_db
+
+
+def test_c3_compound_fp32_full_size(c3):
+    _c3_check(c3, "c3_compound_f32", to_dev(c3["f32"]), TOL32, TOL_DB)
+
+
+def test_c3_compound_fp16_full_size(c3):
+    _c3_check(c3, "c3_compound_f16", to_dev(c3["f16"]), TOL16, TOL_DB)
+
+
+# -------------------------------------------------------- small cases, whole images
+@pytest.mark.parametrize("name,kw,mode,angle,tile,kind", SMALL, ids=[s[0] for s in SMALL])
+def test_small_cases_whole_image(name, kw, mode, angle, tile, kind):
+    from paper_2311_00482_amd import Tile
+    torch = _torch()
+    g = geom(**kw)
+    rf = rand_rf(g, zlib.crc32(name.encode()) % 1000, kind)
+    rf_t = to_dev(rf)
+    t = Tile(*tile) if tile else None
+    out = run(g, rf_t, mode, angle, ("rf",), t)["rf"]
+    f = oracle.das if mode == "das" else oracle.dmas
+    ref = f(g, rf.astype(np.float64), angle)
+    e = err(out, ref)
+    REPORT[f"small_{name}"] = e
+    assert e <= TOL32, e
+    if kind == "f32":
+        # the same values stored as float16 (inputs rounded) stay within the fp16 bar
+        out16 = run(g, rf_t.to(torch.float16), mode, angle, ("rf",), t)["rf"]
+        assert err(out16, ref) <= TOL16
+
+
+def test_tile_sweep_same_image():
+    from paper_2311_00482_amd import Tile
+    g = TILE_SWEEP
+    rf = rand_rf(g, 3)
+    ref = oracle.das(g, rf, -1)
+    rf_t = to_dev(rf)
+    for shape in tile_sweep_shapes():
+        out = run(g, rf_t, "das", -1, ("rf",), Tile(*shape))["rf"]
+        e = err(out, ref)
+        assert e <= TOL32, (shape, e)
+
+
+@pytest.mark.parametrize("nx,nz", [(128, 32), (256, 32), (512, 64), (1024, 64), (1750, 64)])
+def test_paper_grids(nx, nz):
+    # the paper's acquisition (64-channel receive, 7.5 MHz, 50 MHz sampling, 3 cm)
+    # on the five grid sizes of its timing study
+    g = paper_geometry(nx, nz)
+    rng = np.random.default_rng(nx + nz)
+    rf = simulate_rf(g, phantom_scaled(g, rng), rng)
+    out = run(g, to_dev(rf["i16"]), "das", 0, ("rf",))["rf"]
+    e = err(out, oracle.das(g, rf["master"], 0))
+    REPORT[f"paper_{nx}x{nz}"] = e
+    assert e <= TOL32
+
+
+# --------------------------------------------------------------------- properties
+def test_compound_equals_sum_of_single_angle_calls():
+    g = geom(angles_deg=(-10.0, -3.0, 5.0, 10.0))
+    rf_t = to_dev(rand_rf(g, 9))
+    for mode in ("das", "dmas"):
+        comp = run(g, rf_t, mode, -1)["rf"]
+        parts = sum(run(g, rf_t, mode, a)["rf"] for a in range(g.n_angles))
+        assert err(comp, parts) <= 1e-6
+
+
+def test_int16_and_exact_fp16_storage_are_bitwise_equal(c1):
+    torch = _torch()
+    g = config_c1()
+    a = run(g, to_dev(c1["i16"]), "das", 0)["rf"]
+    b = run(g, to_dev(c1["i16"]).to(torch.float16), "das", 0)["rf"]
+    c = run(g, to_dev(c1["i16"]).to(torch.float32), "das", 0)["rf"]
+    assert np.array_equal(a, b) and np.array_equal(a, c)
+
+
+def test_repeatable_and_stream_ordered(c1):
+    from paper_2311_00482_amd import beamform
+    torch = _torch()
+    g = config_c1()
+    rf_t = to_dev(c1["i16"])
+    a = run(g, rf_t, "das", 0, ("rf", "env", "log"))
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        out = beamform(g, rf_t, "das", 0, want=("rf", "env", "log"))
+    s.synchronize()
+    for k in ("rf", "env", "log"):
+        assert np.array_equal(a[k], out[k].cpu().numpy())
+
+
+def test_linearity_on_gpu():
+    g = geom(angles_deg=(-4.0, 7.0))
+    ra, rb = rand_rf(g, 1), rand_rf(g, 2)
+    ya = run(g, to_dev(ra), "das", -1)["rf"]
+    yb = run(g, to_dev(rb), "das", -1)["rf"]
+    yab = run(g, to_dev(2.0 * ra - 0.5 * rb), "das", -1)["rf"]
+    assert err(yab, 2.0 * ya - 0.5 * yb) <= 2e-6

@@ -38,8 +38,8 @@ MUTANTS = {
     "hann_half_period": ("return 0.5 * (1.0 + cos(M_PI * d / half_aperture));",
                          "return 0.5 * (1.0 + cos(0.5 * M_PI * d / half_aperture));"),
     "compound_keeps_last": (
-        "for (int32_t a = 0; a < g->n_angles; ++a) y += das_one_angle(g, rf, a, x, z);",
-        "for (int32_t a = 0; a < g->n_angles; ++a) y = das_one_angle(g, rf, a, x, z);"),
+        "for (int32_t a = 0; a < g->n_angles; ++a) y += das_one_angle(g, rf, a, first[a], x, z);",
+        "for (int32_t a = 0; a < g->n_angles; ++a) y = das_one_angle(g, rf, a, first[a], x, z);"),
 }
 
 
