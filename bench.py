@@ -191,7 +191,8 @@ def main():
                                "1024x1024 pixels, FP32-stored RF, RF + envelope + log per frame",
                    "rf_storage": "f32", "pixels": g.nx * g.nz, "channels": g.n_channels,
                    "angles": g.n_angles, "samples": g.n_samples,
-                   "tile": {k: plan[k] for k in ("cpw", "wz", "wx", "chunk", "win")}},
+                   "tile": {k: plan[k] for k in ("cpw", "lz", "wz", "wx", "tile_z", "tile_x",
+                                                  "chunk", "win")}},
         "frames_per_s": args.steps / wall,
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12,

@@ -112,10 +112,14 @@ typedef struct pwbf_outputs {
   float *logimg;   /* 20 log10(env / max env), clipped at log_floor_db */
 } pwbf_outputs;
 
-/* Launch shape of the beamforming kernel. Zeros select the library default. */
+/* Launch shape of the beamforming kernel. Zeros select the library default.
+ * A wavefront (64 lanes) holds cpw lane groups; each group covers the same
+ * lz (depth) x (64 / cpw / lz) (lateral) pixels and sums its share of the
+ * channels, and the groups are reduced in-wave. A tile (one block) is wz x wx
+ * wavefronts, i.e. lz * wz pixels along depth by (64 / cpw / lz) * wx along x. */
 typedef struct pwbf_tile {
-  int32_t cpw;   /* lane groups per wavefront sharing one pixel column: 1, 2 or 4;
-                    each group sums a subset of the channels, reduced in-wave */
+  int32_t cpw;   /* lane groups per wavefront: 1, 2 or 4 */
+  int32_t lz;    /* lanes of a group along depth: a power of two <= 64 / cpw */
   int32_t wz;    /* wavefronts stacked along depth in a tile */
   int32_t wx;    /* wavefronts side by side along x in a tile; wz * wx in 1..8 */
   int32_t chunk; /* channels staged in LDS at a time (0 = as many as fit) */
@@ -183,19 +187,22 @@ PWBF_API int pwbf_validate_call(const pwbf_geometry *g, const void *rf, int32_t 
  * the LDS use and tile grid, and lets tests re-derive the kernel's window bounds
  * on the CPU. */
 typedef struct pwbf_plan_info {
-  int32_t cpw, wz, wx, chunk; /* resolved launch shape */
+  int32_t cpw, lz, wz, wx, chunk; /* resolved launch shape */
+  int32_t tile_z, tile_x;     /* pixels of a tile along depth and x */
   int32_t win;                /* LDS entries per (channel, angle) window */
-  int32_t tiles_z, tiles_x;   /* tile grid; a tile is (64 / cpw * wz) x wx pixels */
+  int32_t tiles_z, tiles_x;   /* tile grid */
   int32_t threads_per_block;
   int32_t blocks;             /* blocks launched (a multiple of 8) */
   int32_t n_angles_used;      /* angles the kernel sums (1 for single-angle calls) */
   int64_t lds_bytes;          /* LDS per block */
-  float X0, DX, Z0, DZ;       /* pixel (0, 0) centre and pitches */
+  /* Geometry constants as float-float pairs: value = hi + lo. */
+  float X0, DX, Z0, DZ;       /* pixel (0, 0) centre and pitches (hi) */
+  float X0l, DXl, Z0l, DZl;   /* ... lo parts */
   float ap_k;                 /* 2 F# (0 when apod is none) */
-  float sa[PWBF_MAX_ANGLES];  /* sin(theta) per angle used */
-  float ca[PWBF_MAX_ANGLES];  /* cos(theta) */
-  float to[PWBF_MAX_ANGLES];  /* transmit offset: first-firing term + t0 * fs */
-  float xe[PWBF_MAX_CHANNELS]; /* element x */
+  float sa[PWBF_MAX_ANGLES], sal[PWBF_MAX_ANGLES]; /* sin(theta) per angle used */
+  float ca[PWBF_MAX_ANGLES], cal[PWBF_MAX_ANGLES]; /* cos(theta) */
+  float to[PWBF_MAX_ANGLES], tol[PWBF_MAX_ANGLES]; /* first-firing term + t0 * fs */
+  float xe[PWBF_MAX_CHANNELS], xel[PWBF_MAX_CHANNELS]; /* element x */
 } pwbf_plan_info;
 
 /* Fill *info for a call with this geometry, mode, angle (-1 = compound) and tile

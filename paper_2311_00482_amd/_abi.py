@@ -54,21 +54,25 @@ class Outputs(ctypes.Structure):
 
 
 class Tile(ctypes.Structure):
-    _fields_ = [("cpw", ctypes.c_int32), ("wz", ctypes.c_int32), ("wx", ctypes.c_int32),
-                ("chunk", ctypes.c_int32)]
+    _fields_ = [("cpw", ctypes.c_int32), ("lz", ctypes.c_int32), ("wz", ctypes.c_int32),
+                ("wx", ctypes.c_int32), ("chunk", ctypes.c_int32)]
 
 
 class PlanInfo(ctypes.Structure):
     _fields_ = [
-        ("cpw", ctypes.c_int32), ("wz", ctypes.c_int32), ("wx", ctypes.c_int32),
-        ("chunk", ctypes.c_int32), ("win", ctypes.c_int32), ("tiles_z", ctypes.c_int32),
+        ("cpw", ctypes.c_int32), ("lz", ctypes.c_int32), ("wz", ctypes.c_int32),
+        ("wx", ctypes.c_int32), ("chunk", ctypes.c_int32), ("tile_z", ctypes.c_int32),
+        ("tile_x", ctypes.c_int32), ("win", ctypes.c_int32), ("tiles_z", ctypes.c_int32),
         ("tiles_x", ctypes.c_int32), ("threads_per_block", ctypes.c_int32),
         ("blocks", ctypes.c_int32), ("n_angles_used", ctypes.c_int32),
         ("lds_bytes", ctypes.c_int64),
         ("X0", ctypes.c_float), ("DX", ctypes.c_float), ("Z0", ctypes.c_float),
-        ("DZ", ctypes.c_float), ("ap_k", ctypes.c_float),
-        ("sa", ctypes.c_float * MAX_ANGLES), ("ca", ctypes.c_float * MAX_ANGLES),
-        ("to", ctypes.c_float * MAX_ANGLES), ("xe", ctypes.c_float * MAX_CHANNELS),
+        ("DZ", ctypes.c_float), ("X0l", ctypes.c_float), ("DXl", ctypes.c_float),
+        ("Z0l", ctypes.c_float), ("DZl", ctypes.c_float), ("ap_k", ctypes.c_float),
+        ("sa", ctypes.c_float * MAX_ANGLES), ("sal", ctypes.c_float * MAX_ANGLES),
+        ("ca", ctypes.c_float * MAX_ANGLES), ("cal", ctypes.c_float * MAX_ANGLES),
+        ("to", ctypes.c_float * MAX_ANGLES), ("tol", ctypes.c_float * MAX_ANGLES),
+        ("xe", ctypes.c_float * MAX_CHANNELS), ("xel", ctypes.c_float * MAX_CHANNELS),
     ]
 
 

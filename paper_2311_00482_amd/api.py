@@ -78,13 +78,15 @@ def _ptr(t) -> Optional[int]:
 
 @dataclass
 class Tile:
+    """Launch shape (see pwbf_tile): lane groups, lanes along depth, waves, chunk."""
     cpw: int = 0
+    lz: int = 0
     wz: int = 0
     wx: int = 0
     chunk: int = 0
 
     def c(self) -> _abi.Tile:
-        return _abi.Tile(self.cpw, self.wz, self.wx, self.chunk)
+        return _abi.Tile(self.cpw, self.lz, self.wz, self.wx, self.chunk)
 
 
 def workspace_bytes(g, want: Iterable[str] = ("rf",), bandpass=False) -> int:
@@ -109,7 +111,7 @@ def describe_plan(g, mode: str = "das", angle: int = -1, tile: Optional[Tile] = 
                                              ctypes.byref(t) if t is not None else None,
                                              ctypes.byref(info)))
     out = {k: getattr(info, k) for k, _ in _abi.PlanInfo._fields_}
-    for k in ("sa", "ca", "to", "xe"):
+    for k in ("sa", "sal", "ca", "cal", "to", "tol", "xe", "xel"):
         out[k] = np.array(out[k][:], dtype=np.float32)
     return out
 

@@ -115,6 +115,9 @@ int pwbf_describe_plan(const pwbf_geometry *g, int32_t mode, int32_t angle,
   int rc = pwbf::plan_frame(g, pwbf::kF32, mode, angle, tile, &P, &err);
   if (rc) return set_error(rc, err);
   info->cpw = P.cpw;
+  info->lz = P.lz;
+  info->tile_z = P.tile_z;
+  info->tile_x = P.tile_x;
   info->wz = P.wz;
   info->wx = P.wx;
   info->chunk = P.chunk;
@@ -129,13 +132,23 @@ int pwbf_describe_plan(const pwbf_geometry *g, int32_t mode, int32_t angle,
   info->DX = P.DX;
   info->Z0 = P.Z0;
   info->DZ = P.DZ;
+  info->X0l = P.X0l;
+  info->DXl = P.DXl;
+  info->Z0l = P.Z0l;
+  info->DZl = P.DZl;
   info->ap_k = P.ap_k;
   for (int a = 0; a < PWBF_MAX_ANGLES; ++a) {
     info->sa[a] = P.sa[a];
+    info->sal[a] = P.sal[a];
     info->ca[a] = P.ca[a];
+    info->cal[a] = P.cal[a];
     info->to[a] = P.to[a];
+    info->tol[a] = P.tol[a];
   }
-  for (int e = 0; e < PWBF_MAX_CHANNELS; ++e) info->xe[e] = P.xe[e];
+  for (int e = 0; e < PWBF_MAX_CHANNELS; ++e) {
+    info->xe[e] = P.xe[e];
+    info->xel[e] = P.xel[e];
+  }
   return PWBF_OK;
 }
 

@@ -37,6 +37,12 @@ int fail(std::string *err, int code, const char *fmt, ...) {
 
 bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 
+// v as a float-float pair: hi = v rounded to float, lo = the rest rounded.
+void split(double v, float *hi, float *lo) {
+  *hi = (float)v;
+  *lo = (float)(v - (double)*hi);
+}
+
 }  // namespace
 
 size_t dtype_bytes(int dtype) { return dtype == kF32 ? 4 : 2; }
@@ -140,16 +146,21 @@ int validate_outputs(const pwbf_geometry *g, const pwbf_outputs *o, void *ws, si
   return PWBF_OK;
 }
 
+// Default launch shape. Tiles are 16 pixels deep: the LDS window of a tile
+// grows as ~2 DZ TZ + DX (1 + |sin|) TX samples, which for a fixed pixel count
+// is smallest near TZ = 16 on the usual grids (dz ~ dx), and shallow tiles keep
+// the per-pixel delay offsets small, which keeps float32 delays accurate. Small
+// frames split channels across lane groups so there are enough waves.
 pwbf_tile default_tile(const pwbf_geometry *g, int n_angles_used, int mode) {
   (void)mode;
+  (void)n_angles_used;
   pwbf_tile t;
   int64_t pixels = (int64_t)g->nx * g->nz;
-  // Small frames split channels across lane groups so there are enough waves.
   t.cpw = pixels >= 256 * 1024 ? 1 : (pixels >= 64 * 1024 ? 2 : 4);
+  t.lz = 16;
   t.wz = 1;
   t.wx = 8;
   t.chunk = 0;
-  (void)n_angles_used;
   return t;
 }
 
@@ -169,6 +180,9 @@ static int window_entries(const FramePlan &p, int TZ, int TX) {
 static int fit_tile(const pwbf_geometry *g, pwbf_tile t, FramePlan *P, std::string *err) {
   if (t.cpw != 1 && t.cpw != 2 && t.cpw != 4)
     return fail(err, PWBF_E_INVALID, "tile.cpw %d not in {1, 2, 4}", t.cpw);
+  const int ppw = kWave / t.cpw;
+  if (t.lz < 1 || t.lz > ppw || (t.lz & (t.lz - 1)))
+    return fail(err, PWBF_E_INVALID, "tile.lz %d not a power of two in 1..%d", t.lz, ppw);
   if (t.wz < 1 || t.wx < 1 || t.wz * t.wx > kMaxWavesPerBlock)
     return fail(err, PWBF_E_INVALID, "tile %d x %d wavefronts outside 1..%d", t.wz, t.wx,
                 kMaxWavesPerBlock);
@@ -176,13 +190,17 @@ static int fit_tile(const pwbf_geometry *g, pwbf_tile t, FramePlan *P, std::stri
     return fail(err, PWBF_E_INVALID, "tile.chunk %d not a non-negative multiple of cpw",
                 t.chunk);
   P->cpw = t.cpw;
+  P->lz = t.lz;
+  P->lx = ppw / t.lz;
   P->wz = t.wz;
   P->wx = t.wx;
-  const int TZ = (kWave / t.cpw) * t.wz, TX = t.wx;
+  const int TZ = P->lz * t.wz, TX = P->lx * t.wx;
+  P->tile_z = TZ;
+  P->tile_x = TX;
   // a tile's pixels never extend past the grid (edge lanes repeat the edge pixel)
   P->win = window_entries(*P, std::min(TZ, g->nz), std::min(TX, g->nx));
-  const size_t per_channel = (size_t)P->n_angles * P->win * 8 + 8;
-  const size_t fixed = kMaxAngles * 4;
+  const size_t per_channel = (size_t)P->n_angles * P->win * 8 + 20;
+  const size_t fixed = kLdsAngleBytes + 16;
   int chunk = t.chunk;
   if (chunk == 0) {
     int fit = (int)((kMaxLdsBytes - fixed) / per_channel);
@@ -198,7 +216,9 @@ static int fit_tile(const pwbf_geometry *g, pwbf_tile t, FramePlan *P, std::stri
     }
   }
   P->chunk = chunk;
-  if (chunk < t.cpw || plan_lds_bytes(*P) > (size_t)kMaxLdsBytes)
+  while (t.chunk == 0 && P->chunk > t.cpw && plan_lds_bytes(*P) > (size_t)kMaxLdsBytes)
+    P->chunk -= t.cpw;
+  if (P->chunk < t.cpw || plan_lds_bytes(*P) > (size_t)kMaxLdsBytes)
     return fail(err, PWBF_E_UNSUPPORTED,
                 "tile needs %zu bytes of LDS per block (limit %d); use a smaller tile",
                 plan_lds_bytes(*P), kMaxLdsBytes);
@@ -229,31 +249,32 @@ int plan_frame(const pwbf_geometry *g, int dtype, int mode, int angle, const pwb
   P->n_samples = g->n_samples;
   P->nx = g->nx;
   P->nz = g->nz;
-  P->X0 = (float)(g->x0 * scale);
-  P->DX = (float)(g->dx * scale);
-  P->Z0 = (float)(g->z0 * scale);
-  P->DZ = (float)(g->dz * scale);
+  split(g->x0 * scale, &P->X0, &P->X0l);
+  split(g->dx * scale, &P->DX, &P->DXl);
+  split(g->z0 * scale, &P->Z0, &P->Z0l);
+  split(g->dz * scale, &P->DZ, &P->DZl);
   P->ap_k = g->apod == kNone ? 0.0f : (float)(2.0 * g->f_number);
   for (int e = 0; e < kMaxChannels; ++e)
-    P->xe[e] = (float)(g->elem_x[std::min(e, g->n_channels - 1)] * scale);
+    split(g->elem_x[std::min(e, g->n_channels - 1)] * scale, &P->xe[e], &P->xel[e]);
   for (int k = 0; k < na; ++k) {
     int a = a0 + k;
     double th = g->angle_rad[a];
     double first = g->elem_x[0] * std::sin(th);
     for (int e = 1; e < g->n_channels; ++e) first = std::min(first, g->elem_x[e] * std::sin(th));
-    P->sa[k] = (float)std::sin(th);
-    P->ca[k] = (float)std::cos(th);
-    P->to[k] = (float)(first * scale + (g->t0 ? g->t0[a] : 0.0) * g->fs);
+    split(std::sin(th), &P->sa[k], &P->sal[k]);
+    split(std::cos(th), &P->ca[k], &P->cal[k]);
+    split(first * scale + (g->t0 ? g->t0[a] : 0.0) * g->fs, &P->to[k], &P->tol[k]);
   }
 
   // An explicit tile is taken as given; the default falls back to shapes with
   // shorter tiles (more lane groups, fewer columns) until its windows fit in LDS.
   pwbf_tile d = default_tile(g, na, mode);
-  pwbf_tile cands[8];
+  pwbf_tile cands[10];
   int nc = 0;
   if (tile_in) {
     pwbf_tile t = *tile_in;
     if (t.cpw == 0) t.cpw = d.cpw;
+    if (t.lz == 0) t.lz = std::min(d.lz, kWave / t.cpw);
     if (t.wz == 0 && t.wx == 0) {
       t.wz = d.wz;
       t.wx = d.wx;
@@ -261,10 +282,11 @@ int plan_frame(const pwbf_geometry *g, int dtype, int mode, int angle, const pwb
     cands[nc++] = t;
   } else {
     cands[nc++] = d;
-    const pwbf_tile more[] = {{2, 1, 8, 0}, {4, 1, 8, 0}, {4, 1, 4, 0}, {4, 1, 2, 0},
-                              {4, 1, 1, 0}};
+    const pwbf_tile more[] = {{d.cpw, 16, 1, 4, 0}, {d.cpw, 16, 1, 2, 0}, {d.cpw, 16, 1, 1, 0},
+                              {d.cpw, 8, 1, 1, 0},  {d.cpw, 4, 1, 1, 0},  {d.cpw, 2, 1, 1, 0},
+                              {d.cpw, 1, 1, 1, 0}};
     for (const pwbf_tile &m : more)
-      if (m.cpw >= d.cpw) cands[nc++] = m;
+      if (m.lz <= kWave / m.cpw) cands[nc++] = m;
   }
   int rc_fit = PWBF_OK;
   for (int ci = 0; ci < nc; ++ci) {
@@ -272,7 +294,7 @@ int plan_frame(const pwbf_geometry *g, int dtype, int mode, int angle, const pwb
     if (rc_fit != PWBF_E_UNSUPPORTED || tile_in) break;
   }
   if (rc_fit) return rc_fit;
-  const int TZ = (kWave / P->cpw) * P->wz, TX = P->wx;
+  const int TZ = P->tile_z, TX = P->tile_x;
   P->tiles_z = (g->nz + TZ - 1) / TZ;
   P->tiles_x = (g->nx + TX - 1) / TX;
   P->n_tiles = P->tiles_z * P->tiles_x;

@@ -10,6 +10,12 @@
 #include <cstddef>
 #include <cstdint>
 
+#if defined(__HIPCC__)
+#define PWBF_HD __host__ __device__
+#else
+#define PWBF_HD
+#endif
+
 namespace pwbf {
 
 constexpr int kMaxAngles = 32;
@@ -30,16 +36,20 @@ struct FramePlan {
   int32_t dtype, mode, apod;
   int32_t n_angles, n_channels, n_samples;
   int32_t nx, nz;
-  float X0, DX, Z0, DZ;  // centre of pixel (0, 0) and pitches, samples
+  // Geometry as float-float pairs (value = hi + lo, |lo| <= ulp(hi)/2), so that
+  // per-tile reference delays can be formed to ~1e-12 relative without float64.
+  float X0, DX, Z0, DZ;      // centre of pixel (0, 0) and pitches, samples (hi)
+  float X0l, DXl, Z0l, DZl;  // ... and their lo parts
   float ap_k;            // 2 F#: normalised aperture distance r = |X - Xe| * ap_k / Z
   // launch shape
-  int32_t cpw, wz, wx, chunk;
+  int32_t cpw, lz, lx, wz, wx, chunk;  // lane groups, lanes along z/x per group, waves
   int32_t win;           // LDS entries per (channel, angle) window
+  int32_t tile_z, tile_x;  // pixels per tile: lz * wz by lx * wx
   int32_t tiles_z, tiles_x, n_tiles, tiles_per_xcd;
-  float sa[kMaxAngles];  // sin(theta_a)
-  float ca[kMaxAngles];  // cos(theta_a)
-  float to[kMaxAngles];  // first-firing offset plus t0, samples
-  float xe[kMaxChannels];  // element x, samples (padded with the last element)
+  float sa[kMaxAngles], sal[kMaxAngles];  // sin(theta_a), hi and lo
+  float ca[kMaxAngles], cal[kMaxAngles];  // cos(theta_a)
+  float to[kMaxAngles], tol[kMaxAngles];  // first-firing offset plus t0, samples
+  float xe[kMaxChannels], xel[kMaxChannels];  // element x, samples (padded with the last)
 };
 
 struct PostPlan {
@@ -53,9 +63,15 @@ struct PostPlan {
   float floor_db;
 };
 
-// LDS bytes one block of this plan uses.
-inline size_t plan_lds_bytes(const FramePlan &p) {
-  return (size_t)p.chunk * p.n_angles * p.win * 8 + (size_t)p.chunk * 8 + kMaxAngles * 4;
+// LDS layout of one block: per-angle tile constants (float txl, int origin),
+// per-channel tile constants (float4) and origins (int), then the windows.
+constexpr size_t kLdsAngleBytes = kMaxAngles * 8;
+PWBF_HD inline size_t plan_lds_chan_bytes(const FramePlan &p) { return (size_t)p.chunk * 20; }
+PWBF_HD inline size_t plan_lds_win_offset(const FramePlan &p) {
+  return (kLdsAngleBytes + plan_lds_chan_bytes(p) + 15) / 16 * 16;
+}
+PWBF_HD inline size_t plan_lds_bytes(const FramePlan &p) {
+  return plan_lds_win_offset(p) + (size_t)p.chunk * p.n_angles * p.win * 8;
 }
 
 }  // namespace pwbf

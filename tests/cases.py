@@ -12,45 +12,58 @@ def geom(**kw):
     return Geometry(**base)
 
 
-def rand_rf(g, seed, kind="f32"):
+def rand_rf(g, seed, kind="f32", white=False):
+    """Seeded random channel data. By default band-limited like ultrasound RF:
+    white Gaussian noise filtered by the transmitted pulse (a two-cycle Gaussian
+    burst at f0), i.e. fully developed speckle. ``white=True`` keeps the raw
+    white noise (content up to Nyquist), the harshest input for interpolation.
+    kind "i16" scales to the 10-bit range and rounds, "f32" returns float32."""
     rng = np.random.default_rng(seed)
+    x = rng.standard_normal((g.n_angles, g.n_channels, g.n_samples))
+    if not white:
+        sigma = (2.0 / g.f0) / (2.0 * np.sqrt(2.0 * np.log(2.0)))
+        t = np.arange(-int(np.ceil(3.5 * sigma * g.fs)), int(np.ceil(3.5 * sigma * g.fs)) + 1) / g.fs
+        pulse = np.exp(-0.5 * (t / sigma) ** 2) * np.cos(2 * np.pi * g.f0 * t)
+        x = np.apply_along_axis(lambda r: np.convolve(r, pulse, mode="same"), -1, x)
+        x /= x.std()
     if kind == "i16":
-        return rng.integers(-512, 512, (g.n_angles, g.n_channels, g.n_samples)).astype(np.int16)
-    return rng.standard_normal((g.n_angles, g.n_channels, g.n_samples))
+        return np.clip(np.rint(x * 511.0 / np.abs(x).max()), -512, 511).astype(np.int16)
+    return x.astype(np.float32)
 
 
 SMALL = [
     # name, geometry kwargs, mode, angle, tile, dtype
     ("das_1ch", dict(n_channels=1), "das", 0, None, "f32"),
-    ("das_ragged_cpw1", dict(nx=37, nz=100), "das", 0, (1, 1, 4, 0), "f32"),
-    ("das_ragged_cpw2", dict(nx=13, nz=257), "das", 0, (2, 2, 2, 6), "i16"),
-    ("das_ragged_cpw4", dict(nx=9, nz=33, n_channels=7), "das", 0, (4, 1, 3, 4), "f32"),
+    ("das_ragged_cpw1", dict(nx=37, nz=100), "das", 0, (1, 64, 1, 4, 0), "f32"),
+    ("das_ragged_cpw2", dict(nx=13, nz=257), "das", 0, (2, 8, 2, 2, 6), "i16"),
+    ("das_ragged_cpw4", dict(nx=9, nz=33, n_channels=7), "das", 0, (4, 16, 1, 3, 4), "f32"),
     ("das_one_pixel", dict(nx=1, nz=1), "das", 0, None, "f32"),
-    ("das_one_column", dict(nx=1, nz=300), "das", 0, (1, 3, 1, 0), "f32"),
+    ("das_one_column", dict(nx=1, nz=300), "das", 0, (1, 64, 3, 1, 0), "f32"),
     ("das_boxcar", dict(apod="boxcar"), "das", 0, None, "f32"),
     ("das_no_apod_near_array", dict(apod="none", z_min=-1e-3, z_max=4e-3), "das", 0, None, "f32"),
     ("das_record_too_short", dict(n_samples=120), "das", 0, None, "f32"),
     ("compound_3a", dict(angles_deg=(-12.0, 0.0, 9.0)), "das", -1, None, "f32"),
     ("compound_7a_t0", dict(angles_deg=(-15., -10., -5., 0., 5., 10., 15.),
                             t0=(0.5e-6, 0.0, -0.3e-6, 1e-6, 0.0, 0.2e-6, 0.0)), "das", -1,
-     (1, 2, 2, 0), "f32"),
+     (1, 16, 2, 2, 0), "f32"),
     ("compound_17a_generic", dict(angles_deg=tuple(range(-16, 18, 2)), nx=11, nz=70), "das",
      -1, None, "f32"),
     ("compound_32a_generic", dict(angles_deg=tuple(np.linspace(-20, 20, 32)), nx=6, nz=40,
-                                  n_channels=8), "das", -1, (1, 1, 2, 0), "f32"),
+                                  n_channels=8), "das", -1, (1, 32, 1, 2, 0), "f32"),
     ("angle_slab", dict(angles_deg=(-8.0, 4.0, 11.0)), "das", 2, None, "i16"),
     ("dmas_2ch", dict(n_channels=2), "dmas", 0, None, "f32"),
-    ("dmas_ragged_cpw2", dict(nx=21, nz=77, n_channels=12), "dmas", 0, (2, 1, 4, 4), "f32"),
+    ("dmas_ragged_cpw2", dict(nx=21, nz=77, n_channels=12), "dmas", 0, (2, 16, 1, 4, 4), "f32"),
     ("dmas_compound_5a", dict(angles_deg=(-10., -5., 0., 5., 10.)), "dmas", -1, None, "i16"),
     ("dmas_compound_generic", dict(angles_deg=tuple(range(-18, 18, 2)), nx=7, nz=40,
-                                   n_channels=6), "dmas", -1, (4, 1, 2, 0), "f32"),
+                                   n_channels=6), "dmas", -1, (4, 4, 1, 2, 0), "f32"),
 ]
 
 
 
 TILE_SWEEP = geom(angles_deg=(-6.0, 0.0, 6.0, 12.0), nx=40, nz=140, n_channels=24)
-_SWEEP_ALL = [(cpw, wz, wx, chunk) for cpw in (1, 2, 4)
-              for wz, wx in ((1, 1), (1, 8), (2, 4), (4, 2), (8, 1))
+_SWEEP_ALL = [(cpw, lz, wz, wx, chunk) for cpw in (1, 2, 4)
+              for lz in sorted({64 // cpw, 16, 4})
+              for wz, wx in ((1, 1), (1, 8), (2, 4), (8, 1))
               for chunk in (0, cpw, 3 * cpw)]
 
 

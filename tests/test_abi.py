@@ -158,6 +158,7 @@ def test_workspace_rules():
 @pytest.mark.parametrize("tile,code", [
     (Tile(cpw=3), _abi.E_INVALID), (Tile(cpw=1, wz=3, wx=3), _abi.E_INVALID),
     (Tile(cpw=2, wz=1, wx=1, chunk=3), _abi.E_INVALID),
+    (Tile(cpw=2, lz=64, wz=1, wx=1), _abi.E_INVALID), (Tile(cpw=1, lz=12), _abi.E_INVALID),
     (Tile(cpw=1, wz=1, wx=8, chunk=256), _abi.E_UNSUPPORTED),
 ])
 def test_tile_validation(tile, code):

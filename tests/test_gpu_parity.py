@@ -226,6 +226,17 @@ def test_small_cases_whole_image(name, kw, mode, angle, tile, kind):
         assert err(out16, ref) <= TOL16
 
 
+def test_white_noise_rf_default_tile():
+    # white noise (content up to Nyquist) maximises the image's sensitivity to
+    # sub-sample delay errors; the default shallow tiles keep it within the bar
+    for angles in ((0.0,), (-7.0, 2.0, 9.0)):
+        g = geom(angles_deg=angles, nx=45, nz=180)
+        rf = rand_rf(g, 21, white=True)
+        e = err(run(g, to_dev(rf), "das", -1)["rf"], oracle.das(g, rf, -1))
+        REPORT[f"white_noise_{len(angles)}a"] = e
+        assert e <= TOL32
+
+
 def test_tile_sweep_same_image():
     from paper_2311_00482_amd import Tile
     g = TILE_SWEEP

@@ -25,9 +25,12 @@ def fma(a, b, c):
 
 
 def window_index_range(g, mode="das", angle=-1, tile=None, channels=None, margin=2e-3):
+    """(min, max) of floor(s) over every pixel, angle and listed channel, and the
+    window length, following the kernel's arithmetic: tile constants in
+    float-float (emulated in float64), per-pixel offsets in float32."""
     p = describe_plan(g, mode, angle, tile)
-    cpw, wz, wx, win = p["cpw"], p["wz"], p["wx"], p["win"]
-    TZ, TX = (64 // cpw) * wz, wx
+    win = p["win"]
+    TZ, TX = p["tile_z"], p["tile_x"]
     ix = np.arange(p["tiles_x"] * TX)
     iz = np.arange(p["tiles_z"] * TZ)
     IX, IZ = np.meshgrid(ix, iz, indexing="ij")
@@ -35,33 +38,51 @@ def window_index_range(g, mode="das", angle=-1, tile=None, channels=None, margin
     iz0 = (IZ // TZ) * TZ
     ixe = np.minimum(ix0 + TX - 1, g.nx - 1)  # tiles stop at the grid edge
     ize = np.minimum(iz0 + TZ - 1, g.nz - 1)
-    X0, DX, Z0, DZ = f32(p["X0"]), f32(p["DX"]), f32(p["Z0"]), f32(p["DZ"])
-    X = fma(np.minimum(IX, ixe).astype(f32), DX, X0)
-    Z = fma(np.minimum(IZ, ize).astype(f32), DZ, Z0)
-    Z2 = (Z * Z).astype(f32)
-    Xlo = fma(ix0.astype(f32), DX, X0)
-    Xhi = fma(ixe.astype(f32), DX, X0)
-    Zlo = fma(iz0.astype(f32), DZ, Z0)
-    Zhi = fma(ize.astype(f32), DZ, Z0)
-    N = g.n_channels
-    chans = range(N) if channels is None else channels
+    ixq = (ix0 + ixe) >> 1
+    izq = (iz0 + ize) >> 1
+    DX, DZ = f32(p["DX"]), f32(p["DZ"])
+    X0d = float(p["X0"]) + float(p["X0l"])
+    Z0d = float(p["Z0"]) + float(p["Z0l"])
+    DXd = float(p["DX"]) + float(p["DXl"])
+    DZd = float(p["DZ"]) + float(p["DZl"])
+    dx = ((np.minimum(IX, ixe) - ixq).astype(f32) * DX).astype(f32)
+    dz = ((np.minimum(IZ, ize) - izq).astype(f32) * DZ).astype(f32)
+    dxlo = ((ix0 - ixq).astype(f32) * DX).astype(f32)
+    dxhi = ((ixe - ixq).astype(f32) * DX).astype(f32)
+    dzlo = ((iz0 - izq).astype(f32) * DZ).astype(f32)
+    dzhi = ((ize - izq).astype(f32) * DZ).astype(f32)
+    Xq = X0d + ixq * DXd  # float64 stands in for the kernel's float-float
+    Zq = Z0d + izq * DZd
+    Zqf = Zq.astype(f32)
+    cp = fma(2 * Zqf, dz, fma(dx, dx, (dz * dz).astype(f32)))
+    dx2 = (2 * dx).astype(f32)
+    chans = range(g.n_channels) if channels is None else channels
     lo, hi = np.inf, -np.inf
     for a in range(p["n_angles_used"]):
-        sa, ca, to = f32(p["sa"][a]), f32(p["ca"][a]), f32(p["to"][a])
-        t = fma(X, sa, fma(Z, ca, -to))
-        xc = Xlo if sa >= 0 else Xhi
-        zc = Zlo if ca >= 0 else Zhi
-        lt = (np.floor(fma(xc, sa, fma(zc, ca, -to))) - 1).astype(f32)
-        txl = (t - lt).astype(f32)
+        sah, cah = f32(p["sa"][a]), f32(p["ca"][a])
+        sa = float(p["sa"][a]) + float(p["sal"][a])
+        ca = float(p["ca"][a]) + float(p["cal"][a])
+        to = float(p["to"][a]) + float(p["tol"][a])
+        txq = Xq * sa + Zq * ca - to
+        dmin = (np.minimum(dxlo * sah, dxhi * sah) + np.minimum(dzlo * cah, dzhi * cah))
+        lt = np.floor(txq + dmin.astype(np.float64)) - 1
+        txl = ((txq - lt).astype(f32) + fma(dx, sah, (dz * cah).astype(f32))).astype(f32)
         for e in chans:
-            xe = f32(p["xe"][e])
-            dxm = np.maximum(np.maximum(Xlo - xe, xe - Xhi), f32(0))
-            dzm = np.where(Zlo > 0, Zlo, np.where(Zhi < 0, -Zhi, f32(0))).astype(f32)
-            rmin = np.sqrt(fma(dxm, dxm, (dzm * dzm).astype(f32))).astype(f32)
-            lr = (np.floor(rmin) - 1).astype(f32)
-            dxe = (X - xe).astype(f32)
-            rx = np.sqrt(fma(dxe, dxe, Z2)).astype(f32)
-            s = (txl + (rx - lr).astype(f32)).astype(f32)
+            xe = float(p["xe"][e]) + float(p["xel"][e])
+            dq = Xq - xe
+            rq2 = dq * dq + Zq * Zq
+            rq = np.sqrt(rq2)
+            dqf = dq.astype(f32)
+            ddx = np.maximum(np.maximum(dqf + dxlo, -(dqf + dxhi)), f32(0))
+            zlo = (Zqf + dzlo).astype(f32)
+            zhi = (Zqf + dzhi).astype(f32)
+            ddz = np.where(zlo > 0, zlo, np.where(zhi < 0, -zhi, f32(0))).astype(f32)
+            rmin = np.sqrt(fma(ddx, ddx, (ddz * ddz).astype(f32))).astype(f32)
+            lr = np.floor(rmin).astype(np.float64) - 1
+            num = fma(dx2, dqf, cp)
+            den = (np.sqrt((rq2.astype(f32) + num).astype(f32)) + rq.astype(f32)).astype(f32)
+            rxl = fma(num, (1 / den.astype(np.float64)).astype(f32), (rq - lr).astype(f32))
+            s = (txl + rxl).astype(f32)
             lo = min(lo, float(np.floor(s - margin).min()))
             hi = max(hi, float(np.floor(s + margin).max()))
     return lo, hi, win
@@ -73,14 +94,15 @@ def edge_channels(n):
 
 CASES = [
     ("c1", config_c1(), "das", 0, None),
-    ("c1_cpw4", config_c1(), "das", 0, Tile(4, 1, 4, 0)),
+    ("c1_cpw4", config_c1(), "das", 0, Tile(4, 16, 1, 4, 0)),
     ("c2", config_c2(), "dmas", 0, None),
     ("c3", config_c3(), "das", -1, None),
-    ("c3_tall", config_c3(), "das", -1, Tile(1, 4, 2, 0)),
-    ("c3_cpw2", config_c3(), "das", -1, Tile(2, 2, 4, 8)),
+    ("c3_tall", config_c3(), "das", -1, Tile(1, 64, 4, 2, 0)),
+    ("c3_cpw2", config_c3(), "das", -1, Tile(2, 32, 2, 4, 8)),
+    ("c3_wide", config_c3(), "das", -1, Tile(1, 4, 1, 8, 0)),
     ("near_array", Geometry(n_channels=32, n_samples=1024, angles_deg=(-20.0, 0.0, 25.0),
                             nx=70, nz=90, x_min=-8e-3, x_max=8e-3, z_min=-2e-3, z_max=6e-3,
-                            t0=(1e-6, 0.0, -2e-6)), "das", -1, Tile(2, 2, 2, 0)),
+                            t0=(1e-6, 0.0, -2e-6)), "das", -1, Tile(2, 8, 2, 2, 0)),
 ]
 
 
@@ -101,7 +123,7 @@ def test_small_gpu_cases_inside_windows(name, kw, mode, angle, tile, kind):
 
 def test_tile_sweep_inside_windows():
     shapes = tile_sweep_shapes()
-    assert len(shapes) >= 40
+    assert len(shapes) >= 60
     for shape in shapes:
         lo, hi, win = window_index_range(TILE_SWEEP, "das", -1, Tile(*shape))
         assert lo >= 0 and hi <= win - 1, (shape, lo, hi, win)
