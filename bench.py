@@ -124,6 +124,9 @@ def main():
                     help="seconds of oracle work for the CPU baseline sample")
     ap.add_argument("--profile-only", action="store_true",
                     help="run only the timed FP32 compound loop (for rocprofv3)")
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="first run 3 plain device-to-device copies of this many MiB "
+                         "(a reference kernel for calibrating HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -156,6 +159,14 @@ def main():
 
     def kernel_only():
         beamform(g, rf32, "das", -1, want=("rf",), out=rf_only)
+
+    if args.copy_mib:
+        src = torch.ones(args.copy_mib << 18, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     print("[bench] timing FP32-stored RF (headline)", file=sys.stderr, flush=True)
     wall, lat, span = time_steps(step32, args.steps, args.warmup, torch)

@@ -190,6 +190,7 @@ typedef struct pwbf_plan_info {
   int32_t cpw, lz, wz, wx, chunk; /* resolved launch shape */
   int32_t tile_z, tile_x;     /* pixels of a tile along depth and x */
   int32_t win;                /* LDS entries per (channel, angle) window */
+  int32_t off_t, off_r;       /* window-delay centring offsets (entries) */
   int32_t tiles_z, tiles_x;   /* tile grid */
   int32_t threads_per_block;
   int32_t blocks;             /* blocks launched (a multiple of 8) */

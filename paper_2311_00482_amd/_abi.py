@@ -62,7 +62,8 @@ class PlanInfo(ctypes.Structure):
     _fields_ = [
         ("cpw", ctypes.c_int32), ("lz", ctypes.c_int32), ("wz", ctypes.c_int32),
         ("wx", ctypes.c_int32), ("chunk", ctypes.c_int32), ("tile_z", ctypes.c_int32),
-        ("tile_x", ctypes.c_int32), ("win", ctypes.c_int32), ("tiles_z", ctypes.c_int32),
+        ("tile_x", ctypes.c_int32), ("win", ctypes.c_int32), ("off_t", ctypes.c_int32),
+        ("off_r", ctypes.c_int32), ("tiles_z", ctypes.c_int32),
         ("tiles_x", ctypes.c_int32), ("threads_per_block", ctypes.c_int32),
         ("blocks", ctypes.c_int32), ("n_angles_used", ctypes.c_int32),
         ("lds_bytes", ctypes.c_int64),

@@ -122,6 +122,8 @@ int pwbf_describe_plan(const pwbf_geometry *g, int32_t mode, int32_t angle,
   info->wx = P.wx;
   info->chunk = P.chunk;
   info->win = P.win;
+  info->off_t = P.off_t;
+  info->off_r = P.off_r;
   info->tiles_z = P.tiles_z;
   info->tiles_x = P.tiles_x;
   info->threads_per_block = pwbf::kWave * P.wz * P.wx;

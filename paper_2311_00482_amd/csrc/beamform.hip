@@ -137,13 +137,15 @@ __device__ __forceinline__ float ff_f(ff a) { return a.hi + a.lo; }
 // channel is the same for the whole wavefront and its address stays scalar.
 //
 // Delays of pixel p are formed relative to the tile's reference pixel q:
-//   transmit  tx(p) - LT = [tx(q) - LT] + dx sin + dz cos,
-//   receive   rx(p) - LR = [rx(q) - LR] + (2 Dq dx + 2 Zq dz + dx^2 + dz^2)
-//                                         / (rx(p) + rx(q)),
+//   transmit  tx(p) - LT - off_t = [tx(q) - LT - off_t] + dx sin + dz cos,
+//   receive   rx(p) - LR - off_r = [rx(q) - LR - off_r]
+//                                  + (2 Dq dx + 2 Zq dz + dx^2 + dz^2) / (rx(p) + rx(q)),
 // with (dx, dz) = p - q, Dq = Xq - Xe, and the bracketed tile constants taken
-// from float-float reference delays. Every float32 quantity on the per-gather
-// path is then a small offset inside the tile's window, accurate to a few 1e-6
-// samples, instead of an absolute delay rounded at ~1e-4 samples.
+// from float-float reference delays; the integer offsets off_t, off_r centre
+// both terms on zero and are added back in the LDS address. Every float32
+// quantity on the per-gather path is then a small offset inside the tile's
+// window, accurate to ~1e-6 samples, instead of an absolute delay rounded at
+// ~1e-4 samples.
 template <int AM, bool PRED, int MODE, bool ONEGRP>
 __device__ __forceinline__ void process_tile(const FramePlan &P, int tz, int tx,
                                              unsigned char *smem) {
@@ -193,7 +195,7 @@ __device__ __forceinline__ void process_tile(const FramePlan &P, int tz, int tx,
     const float dmin = fminf(dxlo * sa.hi, dxhi * sa.hi) + fminf(dzlo * ca.hi, dzhi * ca.hi);
     const float fl = floorf(txq.hi);
     const float lt = fl + floorf((txq.hi - fl) + txq.lo + dmin) - 1.f;
-    s_txq[a] = ff_f(ff_add(txq, {-lt, 0.f}));
+    s_txq[a] = ff_f(ff_add(txq, {-(lt + (float)P.off_t), 0.f}));
     s_lt[a] = (int)lt;
   }
   __syncthreads();
@@ -226,7 +228,8 @@ __device__ __forceinline__ void process_tile(const FramePlan &P, int tz, int tx,
       const float ddz = zlo > 0.f ? zlo : (zhi < 0.f ? -zhi : 0.f);
       const float rmin = sqrtf(fmaf(ddx, ddx, ddz * ddz));
       const float lr = floorf(rmin) - 1.f;
-      s_ch[c] = make_float4(dqf, ff_f(rq2), ff_f(rq) + 1e-20f, ff_f(ff_add(rq, {-lr, 0.f})));
+      s_ch[c] = make_float4(dqf, ff_f(rq2), ff_f(rq) + 1e-20f,
+                            ff_f(ff_add(rq, {-(lr + (float)P.off_r), 0.f})));
       s_lr[c] = (int)lr;
     }
     __syncthreads();
@@ -247,7 +250,8 @@ __device__ __forceinline__ void process_tile(const FramePlan &P, int tz, int tx,
       const float den = __builtin_amdgcn_sqrtf(ch.y + num) + ch.z;
       const float rxl = fmaf(num, __builtin_amdgcn_rcpf(den), ch.w);
       const float w = apod_weight(fabsf(ch.x + dx) * invA, hk, hb);
-      const char *wb = (const char *)(s_pairs + (size_t)c * A * win);
+      // delays are centred: entry n of the window is read as n + off_t + off_r
+      const char *wb = (const char *)(s_pairs + (size_t)c * A * win + P.off_t + P.off_r);
       if constexpr (MODE == kDas) {
         float acc = 0.f;
 #pragma unroll

@@ -164,7 +164,9 @@ pwbf_tile default_tile(const pwbf_geometry *g, int n_angles_used, int mode) {
   return t;
 }
 
-static int window_entries(const FramePlan &p, int TZ, int TX) {
+// Window length for TZ x TX tiles, and the offsets that centre the transmit and
+// receive window delays on zero (the kernel reads entry n + off_t + off_r).
+static int window_entries(FramePlan &p, int TZ, int TX) {
   double rt = 0;
   for (int a = 0; a < p.n_angles; ++a) {
     double v = std::fabs((double)p.sa[a]) * (TX - 1) * p.DX +
@@ -172,6 +174,9 @@ static int window_entries(const FramePlan &p, int TZ, int TX) {
     rt = std::max(rt, v);
   }
   double rr = std::hypot((TX - 1) * (double)p.DX, (TZ - 1) * (double)p.DZ);
+  // window delays relative to the origin lie in [1, r + 2) for each term
+  p.off_t = (int)std::floor(rt / 2) + 1;
+  p.off_r = (int)std::floor(rr / 2) + 1;
   return (int)std::ceil(rt + rr) + 6;
 }
 

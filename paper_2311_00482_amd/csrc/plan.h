@@ -44,6 +44,7 @@ struct FramePlan {
   // launch shape
   int32_t cpw, lz, lx, wz, wx, chunk;  // lane groups, lanes along z/x per group, waves
   int32_t win;           // LDS entries per (channel, angle) window
+  int32_t off_t, off_r;  // centring offsets of the transmit and receive window delays
   int32_t tile_z, tile_x;  // pixels per tile: lz * wz by lx * wx
   int32_t tiles_z, tiles_x, n_tiles, tiles_per_xcd;
   float sa[kMaxAngles], sal[kMaxAngles];  // sin(theta_a), hi and lo

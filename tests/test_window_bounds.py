@@ -66,7 +66,8 @@ def window_index_range(g, mode="das", angle=-1, tile=None, channels=None, margin
         txq = Xq * sa + Zq * ca - to
         dmin = (np.minimum(dxlo * sah, dxhi * sah) + np.minimum(dzlo * cah, dzhi * cah))
         lt = np.floor(txq + dmin.astype(np.float64)) - 1
-        txl = ((txq - lt).astype(f32) + fma(dx, sah, (dz * cah).astype(f32))).astype(f32)
+        ot, orr = p["off_t"], p["off_r"]
+        txl = ((txq - lt - ot).astype(f32) + fma(dx, sah, (dz * cah).astype(f32))).astype(f32)
         for e in chans:
             xe = float(p["xe"][e]) + float(p["xel"][e])
             dq = Xq - xe
@@ -81,10 +82,10 @@ def window_index_range(g, mode="das", angle=-1, tile=None, channels=None, margin
             lr = np.floor(rmin).astype(np.float64) - 1
             num = fma(dx2, dqf, cp)
             den = (np.sqrt((rq2.astype(f32) + num).astype(f32)) + rq.astype(f32)).astype(f32)
-            rxl = fma(num, (1 / den.astype(np.float64)).astype(f32), (rq - lr).astype(f32))
-            s = (txl + rxl).astype(f32)
-            lo = min(lo, float(np.floor(s - margin).min()))
-            hi = max(hi, float(np.floor(s + margin).max()))
+            rxl = fma(num, (1 / den.astype(np.float64)).astype(f32), (rq - lr - orr).astype(f32))
+            s = (txl + rxl).astype(f32)  # centred; the entry read is floor(s) + ot + orr
+            lo = min(lo, float(np.floor(s - margin).min()) + ot + orr)
+            hi = max(hi, float(np.floor(s + margin).max()) + ot + orr)
     return lo, hi, win
 
 
