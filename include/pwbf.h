@@ -211,6 +211,80 @@ typedef struct pwbf_plan_info {
 PWBF_API int pwbf_describe_plan(const pwbf_geometry *g, int32_t mode, int32_t angle,
                        const pwbf_tile *tile, pwbf_plan_info *info);
 
+/* ------------------------------------------------------------------ batches
+ * Frames of uneven size, channel count, angle count, storage type and mode go
+ * into one persistent launch: blocks pull (frame, pixel tile) items, largest
+ * first, from a device work list; the launch sequence (reset, beamform,
+ * depth post-processing, log) is captured once in a HIP graph and replayed.
+ * The batch keeps the frames' device pointers until it is updated or
+ * destroyed; creating it allocates the graph, the descriptor tables and a
+ * small per-frame workspace (PWBF_E_NOMEM on failure). Launch and update must
+ * be enqueued on the same stream (or the caller orders them). */
+typedef struct pwbf_frame {
+  const pwbf_geometry *geom; /* host; read during create / update */
+  const void *rf;            /* device RF of rf_dtype */
+  int32_t rf_dtype;          /* PWBF_I16, PWBF_F16, PWBF_F32 */
+  int32_t mode;              /* PWBF_DAS or PWBF_DMAS */
+  int32_t angle;             /* -1: compound over all angles; else that angle */
+  int32_t reserved;          /* 0 */
+  pwbf_outputs out;          /* device planes, as for the single-frame calls */
+  pwbf_tile tile;            /* zeros: tuned entry if present, else default;
+                                wz * wx must be 8 (batch blocks are 8 wavefronts) */
+} pwbf_frame;
+
+typedef struct pwbf_batch pwbf_batch;
+
+#define PWBF_BATCH_TUNE 1 /* create: tune every shape without a tuned entry first */
+
+typedef struct pwbf_batch_info {
+  int32_t n_frames;
+  int32_t n_items;          /* (frame, tile) work items */
+  int32_t n_columns;        /* depth columns post-processed */
+  int32_t blocks;           /* persistent blocks launched */
+  int32_t blocks_per_cu;
+  int32_t lds_bytes;        /* LDS per block of the persistent kernel */
+  int32_t graph_nodes;
+  int32_t reserved;
+} pwbf_batch_info;
+
+/* Build a batch of n >= 1 frames; *out receives the handle. flags: 0 or
+ * PWBF_BATCH_TUNE (tuning runs the frames on `stream`, overwriting their rf
+ * outputs, and blocks until done). */
+PWBF_API int pwbf_batch_create(const pwbf_frame *frames, int32_t n, int32_t flags, void *stream,
+                               pwbf_batch **out);
+
+/* Point an existing batch at new buffers: the frames must have the same
+ * geometry, storage type, mode, angle selection and requested planes as at
+ * creation (PWBF_E_INVALID otherwise). The new descriptors are copied on
+ * `stream`, ordered before later launches on it. */
+PWBF_API int pwbf_batch_update(pwbf_batch *b, const pwbf_frame *frames, int32_t n, void *stream);
+
+/* Enqueue one execution of the batch graph on `stream`. */
+PWBF_API int pwbf_batch_launch(pwbf_batch *b, void *stream);
+
+/* Shape of the batch launch. */
+PWBF_API int pwbf_batch_describe(const pwbf_batch *b, pwbf_batch_info *info);
+
+/* Release the batch (waits for its outstanding work). NULL is ignored. */
+PWBF_API int pwbf_batch_destroy(pwbf_batch *b);
+
+/* ------------------------------------------------------------------ tuning
+ * Time candidate launch shapes (lane groups, lanes along depth, wavefront
+ * arrangement) for this frame and keep the fastest in the process-wide tuning
+ * table, which single-frame calls with a NULL or all-zero tile and batch frames
+ * consult. waves = 8 restricts to shapes the batch kernel can run; 0 allows
+ * 1..8 wavefronts. Overwrites out->rf; blocks until the timing runs finish.
+ * *best / *best_ms (may be NULL) receive the winner and its time. */
+PWBF_API int pwbf_tune(const pwbf_geometry *g, const void *rf, int32_t rf_dtype, int32_t mode,
+                       int32_t angle, const pwbf_outputs *out, int32_t waves, void *stream,
+                       pwbf_tile *best, float *best_ms);
+
+/* Persist / restore / clear the tuning table (a small JSON file of
+ * shape key -> tile). Load merges into the table. */
+PWBF_API int pwbf_tune_save(const char *path);
+PWBF_API int pwbf_tune_load(const char *path);
+PWBF_API int pwbf_tune_clear(void);
+
 #ifdef __cplusplus
 }
 #endif

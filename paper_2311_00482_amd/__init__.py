@@ -6,6 +6,8 @@
 
 from ._abi import PwbfError, lib  # noqa: F401
 from .api import (  # noqa: F401
+    Batch,
+    FrameSpec,
     GeometryArg,
     Tile,
     alloc_outputs,
@@ -14,5 +16,9 @@ from .api import (  # noqa: F401
     beamform_dmas,
     compound,
     describe_plan,
+    tune,
+    tune_clear,
+    tune_load,
+    tune_save,
     workspace_bytes,
 )

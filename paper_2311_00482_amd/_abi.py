@@ -58,6 +58,22 @@ class Tile(ctypes.Structure):
                 ("wx", ctypes.c_int32), ("chunk", ctypes.c_int32)]
 
 
+class Frame(ctypes.Structure):
+    _fields_ = [("geom", ctypes.POINTER(Geometry)), ("rf", ctypes.c_void_p),
+                ("rf_dtype", ctypes.c_int32), ("mode", ctypes.c_int32),
+                ("angle", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("out", Outputs), ("tile", Tile)]
+
+
+class BatchInfo(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int32) for n in ("n_frames", "n_items", "n_columns", "blocks",
+                                               "blocks_per_cu", "lds_bytes", "graph_nodes",
+                                               "reserved")]
+
+
+BATCH_TUNE = 1
+
+
 class PlanInfo(ctypes.Structure):
     _fields_ = [
         ("cpw", ctypes.c_int32), ("lz", ctypes.c_int32), ("wz", ctypes.c_int32),
@@ -111,6 +127,24 @@ def lib():
     L.pwbf_validate_call.argtypes = [G, vp, i32, i32, i32, T, O, vp, sz]
     L.pwbf_describe_plan.restype = ctypes.c_int
     L.pwbf_describe_plan.argtypes = [G, i32, i32, T, PI]
+    F, BI = ctypes.POINTER(Frame), ctypes.POINTER(BatchInfo)
+    L.pwbf_batch_create.restype = ctypes.c_int
+    L.pwbf_batch_create.argtypes = [F, i32, i32, vp, ctypes.POINTER(vp)]
+    L.pwbf_batch_update.restype = ctypes.c_int
+    L.pwbf_batch_update.argtypes = [vp, F, i32, vp]
+    L.pwbf_batch_launch.restype = ctypes.c_int
+    L.pwbf_batch_launch.argtypes = [vp, vp]
+    L.pwbf_batch_describe.restype = ctypes.c_int
+    L.pwbf_batch_describe.argtypes = [vp, BI]
+    L.pwbf_batch_destroy.restype = ctypes.c_int
+    L.pwbf_batch_destroy.argtypes = [vp]
+    L.pwbf_tune.restype = ctypes.c_int
+    L.pwbf_tune.argtypes = [G, vp, i32, i32, i32, O, i32, vp, T, ctypes.POINTER(ctypes.c_float)]
+    for name in ("pwbf_tune_save", "pwbf_tune_load"):
+        getattr(L, name).restype = ctypes.c_int
+        getattr(L, name).argtypes = [ctypes.c_char_p]
+    L.pwbf_tune_clear.restype = ctypes.c_int
+    L.pwbf_tune_clear.argtypes = []
     if L.pwbf_abi_version() != ABI_VERSION:
         raise ImportError(f"libpwbf ABI {L.pwbf_abi_version()} != binding {ABI_VERSION}")
     _lib = L

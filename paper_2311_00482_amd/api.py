@@ -181,3 +181,108 @@ def beamform_dmas(g, rf, angle: int, **kw) -> Dict:
 def compound(g, rf, mode: str = "das", **kw) -> Dict:
     """pwbf_compound: coherent sum over all angles of the per-angle DAS or DMAS."""
     return beamform(g, rf, mode, -1, **kw)
+
+
+# ------------------------------------------------------------------- tuning
+def tune(g, rf, mode: str = "das", angle: int = -1, waves: int = 0, out_rf=None, stream=None,
+         bandpass: bool = False):
+    """pwbf_tune: time launch shapes for this frame and remember the fastest.
+    Returns (Tile, milliseconds). ``out_rf`` (float32 [nx, nz]) is overwritten."""
+    import torch
+    ga = _as_geom(g, bandpass)
+    if out_rf is None:
+        out_rf = torch.empty((ga.nx, ga.nz), dtype=torch.float32, device=rf.device)
+    o = _abi.Outputs(_ptr(out_rf), None, None, None)
+    best = _abi.Tile()
+    ms = ctypes.c_float()
+    _abi.check(_abi.lib().pwbf_tune(ga.ref, _ptr(rf), _rf_code(rf), _MODES[mode], angle,
+                                    ctypes.byref(o), waves, _stream_ptr(stream, rf.device),
+                                    ctypes.byref(best), ctypes.byref(ms)))
+    return Tile(best.cpw, best.lz, best.wz, best.wx, best.chunk), float(ms.value)
+
+
+def tune_save(path: str) -> None:
+    _abi.check(_abi.lib().pwbf_tune_save(path.encode()))
+
+
+def tune_load(path: str) -> None:
+    _abi.check(_abi.lib().pwbf_tune_load(path.encode()))
+
+
+def tune_clear() -> None:
+    _abi.check(_abi.lib().pwbf_tune_clear())
+
+
+# ------------------------------------------------------------------- batches
+@dataclass
+class FrameSpec:
+    """One frame of a batch: geometry object, CUDA RF tensor, mode, angle
+    (-1 = compound), output planes (dict name -> float32 [nx, nz] CUDA tensor),
+    band-pass flag and optional launch shape."""
+    geom: object
+    rf: object
+    mode: str = "das"
+    angle: int = -1
+    out: Optional[Dict] = None
+    bandpass: bool = False
+    tile: Optional[Tile] = None
+
+
+class Batch:
+    """pwbf_batch: uneven frames in one persistent, graph-captured launch."""
+
+    def __init__(self, frames, tune: bool = False, stream=None):
+        self._keep = []
+        arr = self._frames(frames)
+        handle = ctypes.c_void_p()
+        dev = frames[0].rf.device
+        _abi.check(_abi.lib().pwbf_batch_create(arr, len(frames), _abi.BATCH_TUNE if tune else 0,
+                                                _stream_ptr(stream, dev), ctypes.byref(handle)))
+        self.handle = handle
+        self.device = dev
+        self.frames = list(frames)
+
+    def _frames(self, frames):
+        arr = (_abi.Frame * len(frames))()
+        keep = []
+        for i, f in enumerate(frames):
+            ga = _as_geom(f.geom, f.bandpass)
+            keep.append(ga)
+            if not f.rf.is_cuda or not f.rf.is_contiguous() or tuple(f.rf.shape) != ga.shape_rf:
+                raise ValueError(f"frame {i}: rf must be a contiguous CUDA tensor {ga.shape_rf}")
+            out = f.out or {}
+            if "rf" not in out:
+                raise ValueError(f"frame {i}: out['rf'] is required")
+            t = f.tile.c() if f.tile is not None else _abi.Tile()
+            arr[i] = _abi.Frame(ctypes.pointer(ga.s), _ptr(f.rf), _rf_code(f.rf), _MODES[f.mode],
+                                f.angle, 0, _abi.Outputs(_ptr(out.get("rf")),
+                                                         _ptr(out.get("filtered")),
+                                                         _ptr(out.get("env")),
+                                                         _ptr(out.get("log"))), t)
+        self._keep = keep
+        return arr
+
+    def update(self, frames, stream=None) -> None:
+        arr = self._frames(frames)
+        _abi.check(_abi.lib().pwbf_batch_update(self.handle, arr, len(frames),
+                                                _stream_ptr(stream, self.device)))
+        self.frames = list(frames)
+
+    def launch(self, stream=None) -> None:
+        _abi.check(_abi.lib().pwbf_batch_launch(self.handle, _stream_ptr(stream, self.device)))
+
+    def describe(self) -> Dict:
+        info = _abi.BatchInfo()
+        _abi.check(_abi.lib().pwbf_batch_describe(self.handle, ctypes.byref(info)))
+        return {k: getattr(info, k) for k, _ in _abi.BatchInfo._fields_}
+
+    def close(self) -> None:
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            _abi.check(_abi.lib().pwbf_batch_destroy(self.handle))
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -21,7 +21,8 @@ LIB = os.path.join(HERE, "libpwbf.so")
 ROOT = os.path.dirname(HERE)
 ARCH = os.environ.get("PWBF_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["plan.cpp", "api.cpp", "beamform.hip", "postz.hip"]
+SOURCES = ["plan.cpp", "tune.cpp", "api.cpp", "batch.cpp", "beamform.hip", "postz.hip",
+           "batch.hip"]
 
 COMMON = [
     "-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}",

@@ -20,6 +20,15 @@ int set_error(int code, const std::string &msg) {
   return code;
 }
 
+}  // namespace
+
+namespace pwbf {
+int api_set_error(int code, const std::string &msg) { return set_error(code, msg); }
+void api_clear_error() { g_last_error.clear(); }
+}  // namespace pwbf
+
+namespace {
+
 int run(const pwbf_geometry *g, const void *rf, int32_t dtype, int32_t mode, int32_t angle,
         const pwbf_tile *tile, const pwbf_outputs *out, void *ws, size_t ws_bytes, void *stream) {
   g_last_error.clear();

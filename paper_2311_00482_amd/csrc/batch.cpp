@@ -1,0 +1,410 @@
+// Batches (one persistent, graph-captured launch over uneven frames) and the
+// launch-shape tuner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/pwbf.h"
+#include "plan_host.h"
+
+namespace pwbf {
+hipError_t launch_beamform(const FramePlan &P, hipStream_t stream);
+hipError_t launch_batch(const FramePlan *plans, const PostPlan *post, const int2 *items,
+                        int n_items, const int2 *post_cols, int n_post_cols,
+                        const int2 *log_cols, int n_log_cols, int n_frames, int *counter,
+                        int blocks, size_t lds, int max_nz, hipStream_t stream);
+hipError_t batch_occupancy(size_t lds_bytes, int *blocks_per_cu);
+int batch_waves();
+int batch_max_angles();
+int api_set_error(int code, const std::string &msg);
+void api_clear_error();
+}  // namespace pwbf
+
+using pwbf::api_set_error;
+
+struct pwbf_batch {
+  int n = 0;
+  std::vector<pwbf::FramePlan> plans;  // host copies of the device tables
+  std::vector<pwbf::PostPlan> post;
+  std::vector<std::string> sig;  // per-frame shape signature (update must match)
+  pwbf::FramePlan *d_plans = nullptr;
+  pwbf::PostPlan *d_post = nullptr;
+  int2 *d_items = nullptr, *d_post_cols = nullptr, *d_log_cols = nullptr;
+  int *d_counter = nullptr;
+  unsigned char *d_ws = nullptr;  // per-frame workspaces (envelope maximum, envelope plane)
+  std::vector<size_t> ws_off;
+  void *h_stage = nullptr;  // pinned staging of the descriptor tables for updates
+  hipEvent_t staged = nullptr;
+  bool stage_pending = false;
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int n_items = 0, n_post_cols = 0, n_log_cols = 0, blocks = 0, blocks_per_cu = 0;
+  int lds = 0, max_nz = 0, graph_nodes = 0;
+};
+
+namespace {
+
+int dev_error(hipError_t e, const char *what) {
+  return api_set_error(PWBF_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+bool tile_is_zero(const pwbf_tile &t) { return !t.cpw && !t.lz && !t.wz && !t.wx && !t.chunk; }
+
+// Everything of a frame that a batch's graph and work list depend on.
+std::string frame_signature(const pwbf_frame &f, const pwbf::FramePlan &P) {
+  char buf[512];
+  snprintf(buf, sizeof buf, "%s|a%d|t%d|%d%d%d|tile%d.%d.%d.%d.%d|win%d|bp%d|nz%d",
+           pwbf::shape_key(f.geom, f.rf_dtype, f.mode, f.angle, 8).c_str(), f.angle, f.rf_dtype,
+           f.out.filtered != nullptr, f.out.env != nullptr, f.out.logimg != nullptr, P.cpw, P.lz,
+           P.wz, P.wx, P.chunk, P.win, f.geom->bandpass, f.geom->nz);
+  return buf;
+}
+
+// Plan one batch frame (8-wavefront tiles) with its pointers and workspace.
+int plan_batch_frame(const pwbf_frame &f, unsigned char *ws, pwbf::FramePlan *P,
+                     pwbf::PostPlan *Q, std::string *err) {
+  if (f.reserved != 0) {
+    *err = "pwbf_frame.reserved must be 0";
+    return PWBF_E_INVALID;
+  }
+  const pwbf_tile *t = tile_is_zero(f.tile) ? nullptr : &f.tile;
+  int rc = pwbf::plan_frame(f.geom, f.rf_dtype, f.mode, f.angle, t, P, err, pwbf::batch_waves());
+  if (rc) return rc;
+  if (P->n_angles > pwbf::batch_max_angles()) {
+    *err = "batch frames sum at most " + std::to_string(pwbf::batch_max_angles()) + " angles";
+    return PWBF_E_UNSUPPORTED;
+  }
+  if (!f.rf) {
+    *err = "frame rf is NULL";
+    return PWBF_E_INVALID;
+  }
+  if ((uintptr_t)f.rf % pwbf::dtype_bytes(f.rf_dtype)) {
+    *err = "frame rf not aligned to its element size";
+    return PWBF_E_INVALID;
+  }
+  size_t need = pwbf::workspace_bytes(f.geom, &f.out);
+  rc = pwbf::validate_outputs(f.geom, &f.out, need ? ws : nullptr, need, err);
+  if (rc) return rc;
+  const size_t slab =
+      (size_t)f.geom->n_channels * f.geom->n_samples * pwbf::dtype_bytes(f.rf_dtype);
+  P->rf = (const char *)f.rf + (size_t)(f.angle < 0 ? 0 : f.angle) * slab;
+  P->out = f.out.rf;
+  P->ws_max = nullptr;  // cleared by the batch reset kernel instead
+  std::memset(Q, 0, sizeof *Q);
+  if (pwbf::post_needed(&f.out)) pwbf::build_post_plan(f.geom, &f.out, ws, Q);
+  return PWBF_OK;
+}
+
+void free_batch(pwbf_batch *b) {
+  if (!b) return;
+  if (b->exec) hipGraphExecDestroy(b->exec);
+  if (b->graph) hipGraphDestroy(b->graph);
+  if (b->cap) hipStreamDestroy(b->cap);
+  if (b->staged) hipEventDestroy(b->staged);
+  if (b->h_stage) hipHostFree(b->h_stage);
+  hipFree(b->d_plans);
+  hipFree(b->d_post);
+  hipFree(b->d_items);
+  hipFree(b->d_post_cols);
+  hipFree(b->d_log_cols);
+  hipFree(b->d_counter);
+  hipFree(b->d_ws);
+  delete b;
+}
+
+template <class T>
+hipError_t upload(T **dst, const std::vector<T> &src) {
+  if (src.empty()) return hipSuccess;
+  hipError_t e = hipMalloc((void **)dst, src.size() * sizeof(T));
+  if (e != hipSuccess) return e;
+  return hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice);
+}
+
+}  // namespace
+
+extern "C" {
+
+int pwbf_tune(const pwbf_geometry *g, const void *rf, int32_t rf_dtype, int32_t mode,
+              int32_t angle, const pwbf_outputs *out, int32_t waves, void *stream,
+              pwbf_tile *best, float *best_ms) {
+  pwbf::api_clear_error();
+  if (waves != 0 && waves != pwbf::batch_waves())
+    return api_set_error(PWBF_E_INVALID, "waves must be 0 or 8");
+  if (!out || !out->rf) return api_set_error(PWBF_E_INVALID, "out->rf is required as scratch");
+  const pwbf_outputs rf_only = {out->rf, nullptr, nullptr, nullptr};
+  out = &rf_only;
+  pwbf::FramePlan P;
+  std::string err;
+  // validates geometry, pointers and the default plan before anything runs
+  int rc = pwbf::build_plan(g, rf, rf_dtype, mode, angle, nullptr, out, nullptr, 0, &P, &err);
+  if (rc) return api_set_error(rc, err);
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<pwbf_tile> cands;
+  for (int cpw : {1, 2, 4})
+    for (int lz : {8, 16, 32})
+      for (int arr = 0; arr < 3; ++arr) {
+        if (lz > 64 / cpw) continue;
+        int wz = arr == 0 ? 1 : (arr == 1 ? 2 : 1), wx = arr == 0 ? 8 : (arr == 1 ? 4 : 4);
+        if (waves && wz * wx != waves) continue;
+        cands.push_back({cpw, lz, wz, wx, 0});
+      }
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    return api_set_error(PWBF_E_DEVICE, "event creation failed");
+  float best_t = 1e30f;
+  pwbf_tile best_tile = {0, 0, 0, 0, 0};
+  for (const pwbf_tile &t : cands) {
+    pwbf::FramePlan Q;
+    if (pwbf::build_plan(g, rf, rf_dtype, mode, angle, &t, out, nullptr, 0, &Q, &err)) continue;
+    if (waves && Q.wz * Q.wx != waves) continue;
+    hipError_t e = pwbf::launch_beamform(Q, s);  // warm-up
+    for (int k = 0; k < 3 && e == hipSuccess; ++k) {
+      if (k == 0) hipEventRecord(e0, s);
+      e = pwbf::launch_beamform(Q, s);
+    }
+    hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    if (e != hipSuccess) {
+      hipEventDestroy(e0);
+      hipEventDestroy(e1);
+      return dev_error(e, "tuning launch");
+    }
+    float ms = 0;
+    hipEventElapsedTime(&ms, e0, e1);
+    ms /= 3;
+    if (ms < best_t) {
+      best_t = ms;
+      best_tile = {Q.cpw, Q.lz, Q.wz, Q.wx, 0};
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (best_t >= 1e30f) return api_set_error(PWBF_E_UNSUPPORTED, "no launch shape fits");
+  pwbf::tune_store(pwbf::shape_key(g, rf_dtype, mode, angle, waves), best_tile);
+  if (best) *best = best_tile;
+  if (best_ms) *best_ms = best_t;
+  return PWBF_OK;
+}
+
+int pwbf_tune_save(const char *path) {
+  pwbf::api_clear_error();
+  if (!path) return api_set_error(PWBF_E_INVALID, "path is NULL");
+  std::string err;
+  int rc = pwbf::tune_save(path, &err);
+  return rc ? api_set_error(rc, err) : PWBF_OK;
+}
+
+int pwbf_tune_load(const char *path) {
+  pwbf::api_clear_error();
+  if (!path) return api_set_error(PWBF_E_INVALID, "path is NULL");
+  std::string err;
+  int rc = pwbf::tune_load(path, &err);
+  return rc ? api_set_error(rc, err) : PWBF_OK;
+}
+
+int pwbf_tune_clear(void) {
+  pwbf::api_clear_error();
+  pwbf::tune_clear();
+  return PWBF_OK;
+}
+
+int pwbf_batch_create(const pwbf_frame *frames, int32_t n, int32_t flags, void *stream,
+                      pwbf_batch **out) {
+  pwbf::api_clear_error();
+  if (!out) return api_set_error(PWBF_E_INVALID, "out is NULL");
+  *out = nullptr;
+  if (!frames || n < 1) return api_set_error(PWBF_E_INVALID, "need n >= 1 frames");
+  if (flags & ~PWBF_BATCH_TUNE) return api_set_error(PWBF_E_INVALID, "unknown flags");
+  std::string err;
+  // validate every frame (and its shape) before touching the device
+  for (int i = 0; i < n; ++i) {
+    pwbf::FramePlan P;
+    pwbf::PostPlan Q;
+    static unsigned char fake_ws[1] __attribute__((aligned(256)));
+    int rc = plan_batch_frame(frames[i], fake_ws, &P, &Q, &err);
+    if (rc) return api_set_error(rc, "frame " + std::to_string(i) + ": " + err);
+  }
+  hipStream_t s = (hipStream_t)stream;
+  if (flags & PWBF_BATCH_TUNE) {
+    for (int i = 0; i < n; ++i) {
+      const pwbf_frame &f = frames[i];
+      pwbf_tile t;
+      if (!tile_is_zero(f.tile) ||
+          pwbf::tune_lookup(pwbf::shape_key(f.geom, f.rf_dtype, f.mode, f.angle, 8), &t))
+        continue;
+      pwbf_outputs scratch = {f.out.rf, nullptr, nullptr, nullptr};
+      int rc = pwbf_tune(f.geom, f.rf, f.rf_dtype, f.mode, f.angle, &scratch, 8, stream,
+                         nullptr, nullptr);
+      if (rc) return rc;
+    }
+  }
+  pwbf_batch *b = new pwbf_batch();
+  b->n = n;
+  b->plans.resize(n);
+  b->post.resize(n);
+  b->sig.resize(n);
+  b->ws_off.resize(n);
+  size_t ws_total = 0;
+  for (int i = 0; i < n; ++i) {
+    b->ws_off[i] = ws_total;
+    ws_total += (pwbf::workspace_bytes(frames[i].geom, &frames[i].out) + 255) / 256 * 256;
+  }
+  hipError_t e = hipSuccess;
+  if (ws_total) e = hipMalloc((void **)&b->d_ws, ws_total);
+  if (e != hipSuccess) {
+    free_batch(b);
+    return api_set_error(PWBF_E_NOMEM, "batch workspace allocation failed");
+  }
+  std::vector<int2> items, post_cols, log_cols;
+  std::vector<std::pair<double, int>> order;
+  for (int i = 0; i < n; ++i) {
+    const pwbf_frame &f = frames[i];
+    unsigned char *ws = b->d_ws ? b->d_ws + b->ws_off[i] : nullptr;
+    int rc = plan_batch_frame(f, ws, &b->plans[i], &b->post[i], &err);
+    if (rc) {
+      free_batch(b);
+      return api_set_error(rc, "frame " + std::to_string(i) + ": " + err);
+    }
+    const pwbf::FramePlan &P = b->plans[i];
+    b->sig[i] = frame_signature(f, P);
+    b->lds = std::max(b->lds, (int)pwbf::plan_lds_bytes(P));
+    // cost of one tile: pixels x channels x (angles + per-channel work), DMAS ~2x
+    double cost = (double)P.tile_z * P.tile_x * P.n_channels * (P.n_angles + 2) *
+                  (P.mode == pwbf::kDmas ? 2.0 : 1.0);
+    order.push_back({-cost, i});
+    if (pwbf::post_needed(&f.out)) {
+      b->max_nz = std::max(b->max_nz, f.geom->nz);
+      for (int ix = 0; ix < f.geom->nx; ++ix) post_cols.push_back(make_int2(i, ix));
+      if (f.out.logimg)
+        for (int ix = 0; ix < f.geom->nx; ++ix) log_cols.push_back(make_int2(i, ix));
+    }
+  }
+  std::stable_sort(order.begin(), order.end());
+  for (const auto &o : order)
+    for (int t = 0; t < b->plans[o.second].n_tiles; ++t) items.push_back(make_int2(o.second, t));
+  b->n_items = (int)items.size();
+  b->n_post_cols = (int)post_cols.size();
+  b->n_log_cols = (int)log_cols.size();
+
+  int dev_id = 0, n_cu = 0;
+  e = hipGetDevice(&dev_id);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev_id);
+  if (e == hipSuccess) e = pwbf::batch_occupancy((size_t)b->lds, &b->blocks_per_cu);
+  if (e != hipSuccess) {
+    free_batch(b);
+    return dev_error(e, "device query");
+  }
+  b->blocks = std::max(1, std::min(b->n_items, std::max(1, b->blocks_per_cu) * n_cu));
+
+  e = upload(&b->d_plans, b->plans);
+  if (e == hipSuccess) e = upload(&b->d_post, b->post);
+  if (e == hipSuccess) e = upload(&b->d_items, items);
+  if (e == hipSuccess) e = upload(&b->d_post_cols, post_cols);
+  if (e == hipSuccess) e = upload(&b->d_log_cols, log_cols);
+  if (e == hipSuccess) e = hipMalloc((void **)&b->d_counter, sizeof(int));
+  if (e == hipSuccess)
+    e = hipHostMalloc(&b->h_stage, n * (sizeof(pwbf::FramePlan) + sizeof(pwbf::PostPlan)),
+                      hipHostMallocDefault);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->staged, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    free_batch(b);
+    return api_set_error(PWBF_E_NOMEM, std::string("batch tables: ") + hipGetErrorString(e));
+  }
+  // capture the launch sequence once
+  e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    hipError_t le = pwbf::launch_batch(b->d_plans, b->d_post, b->d_items, b->n_items,
+                                       b->d_post_cols, b->n_post_cols, b->d_log_cols,
+                                       b->n_log_cols, n, b->d_counter, b->blocks, b->lds,
+                                       b->max_nz, b->cap);
+    e = hipStreamEndCapture(b->cap, &b->graph);
+    if (le != hipSuccess) e = le;
+  }
+  if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+  if (e == hipSuccess) {
+    size_t nodes = 0;
+    hipGraphGetNodes(b->graph, nullptr, &nodes);
+    b->graph_nodes = (int)nodes;
+  }
+  if (e != hipSuccess) {
+    free_batch(b);
+    return dev_error(e, "batch graph capture");
+  }
+  (void)s;
+  *out = b;
+  return PWBF_OK;
+}
+
+int pwbf_batch_update(pwbf_batch *b, const pwbf_frame *frames, int32_t n, void *stream) {
+  pwbf::api_clear_error();
+  if (!b || !frames) return api_set_error(PWBF_E_INVALID, "batch or frames is NULL");
+  if (n != b->n) return api_set_error(PWBF_E_INVALID, "frame count differs from the batch");
+  std::vector<pwbf::FramePlan> plans(n);
+  std::vector<pwbf::PostPlan> post(n);
+  std::string err;
+  for (int i = 0; i < n; ++i) {
+    pwbf_frame f = frames[i];
+    // keep the launch shape the batch was built with
+    const pwbf::FramePlan &old = b->plans[i];
+    f.tile = {old.cpw, old.lz, old.wz, old.wx, old.chunk};
+    unsigned char *ws = b->d_ws ? b->d_ws + b->ws_off[i] : nullptr;
+    int rc = plan_batch_frame(f, ws, &plans[i], &post[i], &err);
+    if (rc) return api_set_error(rc, "frame " + std::to_string(i) + ": " + err);
+    if (frame_signature(frames[i], plans[i]) != b->sig[i])
+      return api_set_error(PWBF_E_INVALID,
+                           "frame " + std::to_string(i) + " differs in shape from the batch");
+  }
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = hipSuccess;
+  if (b->stage_pending) e = hipEventSynchronize(b->staged);  // staging buffer free again
+  if (e != hipSuccess) return dev_error(e, "batch update");
+  unsigned char *h = (unsigned char *)b->h_stage;
+  const size_t pb = n * sizeof(pwbf::FramePlan), qb = n * sizeof(pwbf::PostPlan);
+  std::memcpy(h, plans.data(), pb);
+  std::memcpy(h + pb, post.data(), qb);
+  e = hipMemcpyAsync(b->d_plans, h, pb, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(b->d_post, h + pb, qb, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipEventRecord(b->staged, s);
+  if (e != hipSuccess) return dev_error(e, "batch update");
+  b->stage_pending = true;
+  b->plans = plans;
+  b->post = post;
+  return PWBF_OK;
+}
+
+int pwbf_batch_launch(pwbf_batch *b, void *stream) {
+  pwbf::api_clear_error();
+  if (!b) return api_set_error(PWBF_E_INVALID, "batch is NULL");
+  hipError_t e = hipGraphLaunch(b->exec, (hipStream_t)stream);
+  return e == hipSuccess ? PWBF_OK : dev_error(e, "batch graph launch");
+}
+
+int pwbf_batch_describe(const pwbf_batch *b, pwbf_batch_info *info) {
+  pwbf::api_clear_error();
+  if (!b || !info) return api_set_error(PWBF_E_INVALID, "batch or info is NULL");
+  info->n_frames = b->n;
+  info->n_items = b->n_items;
+  info->n_columns = b->n_post_cols;
+  info->blocks = b->blocks;
+  info->blocks_per_cu = b->blocks_per_cu;
+  info->lds_bytes = b->lds;
+  info->graph_nodes = b->graph_nodes;
+  info->reserved = 0;
+  return PWBF_OK;
+}
+
+int pwbf_batch_destroy(pwbf_batch *b) {
+  pwbf::api_clear_error();
+  if (!b) return PWBF_OK;
+  hipError_t e = hipDeviceSynchronize();
+  free_batch(b);
+  return e == hipSuccess ? PWBF_OK : dev_error(e, "batch destroy");
+}
+
+}  // extern "C"

@@ -1,0 +1,308 @@
+#pragma once
+// Device code of the pixel-tiled plane-wave receive beamformer (gfx950),
+// shared by the single-frame kernels and the persistent batch kernel.
+//
+// One block owns a tile of TZ x TX pixels. A wavefront's lanes run along depth
+// first (lz lanes) and then along x, so the LDS gathers of a wave hit nearly
+// consecutive addresses and the image writes are contiguous runs. With cpw > 1
+// a wavefront is split into cpw lane groups that share the same pixels and
+// divide the channels; their partial sums are reduced across lanes at the end.
+//
+// For every chunk of channels the block stages, per (channel, angle), a window
+// of RF samples that covers every delay of every pixel of the tile, as pairs
+// (u[n], u[n+1] - u[n]) so one 8-byte LDS read and one FMA interpolate. Windows
+// start at floor(min transmit delay) - 1 + floor(min receive delay) - 1 over the
+// tile rectangle; outside [0, n_samples) the record is zero (the zero-extended
+// signal of the definition).
+//
+// Per pixel the transmit delays of all angles are kept in registers; per
+// (pixel, channel) the receive delay (one square root) and the apodization
+// weight are computed once and reused for every angle. Per (pixel, channel,
+// angle) the gather costs an add, a floor, a fraction, an address, one LDS read
+// and two accumulate operations. DMAS adds a square root and the signed-root
+// accumulation per gather.
+
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+
+#include "plan.h"
+
+namespace pwbf {
+namespace dev {
+
+template <int DT>
+struct RfT;
+template <>
+struct RfT<kI16> {
+  using T = int16_t;
+  static __device__ __forceinline__ float f(T v) { return (float)v; }
+};
+template <>
+struct RfT<kF16> {
+  using T = __half;
+  static __device__ __forceinline__ float f(T v) { return __half2float(v); }
+};
+template <>
+struct RfT<kF32> {
+  using T = float;
+  static __device__ __forceinline__ float f(T v) { return v; }
+};
+
+// Stage the windows of `rows` = chunk * A (channel, angle) pairs, one row per wavefront.
+template <int DT>
+__device__ __forceinline__ void stage_windows(const FramePlan &P, int e0, const int *s_lt,
+                                              const int *s_lr, float2 *s_pairs) {
+  using R = RfT<DT>;
+  const typename R::T *rf = (const typename R::T *)P.rf;
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  const int nwaves = blockDim.x / kWave;
+  const int A = P.n_angles, N = P.n_channels, Ns = P.n_samples, win = P.win;
+  const int rows = P.chunk * A;
+  for (int r = wave; r < rows; r += nwaves) {
+    const int c = r / A, a = r - c * A;
+    const int e = e0 + c;
+    float2 *dst = s_pairs + (size_t)r * win;
+    if (e < N) {
+      const int base = s_lt[a] + s_lr[c];
+      const typename R::T *src = rf + ((size_t)a * N + e) * Ns;
+      for (int j = lane; j < win; j += kWave) {
+        const int n = base + j;
+        const float u0 = (n >= 0 && n < Ns) ? R::f(src[n]) : 0.f;
+        const float u1 = (n + 1 >= 0 && n + 1 < Ns) ? R::f(src[n + 1]) : 0.f;
+        dst[j] = make_float2(u0, u1 - u0);
+      }
+    } else {
+      for (int j = lane; j < win; j += kWave) dst[j] = make_float2(0.f, 0.f);
+    }
+  }
+}
+
+// floor(s) as an int in one instruction (v_cvt_flr_i32_f32; pure ALU)
+__device__ __forceinline__ int floor_i32(float s) {
+  int n;
+  asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(n) : "v"(s));
+  return n;
+}
+
+// Apodization weight for r = |x - x_e| / half-aperture: hk cos(pi r) + hb inside
+// the aperture (Hann: hk = hb = 1/2; boxcar: hk = 0, hb = 1), 0 outside. r is NaN
+// or inf when z <= 0, which falls outside. "none" passes r = 0, so w = 1. The
+// hardware cosine takes its argument in revolutions; clamping keeps it in range
+// and makes the evaluation unconditional.
+__device__ __forceinline__ float apod_weight(float r, float hk, float hb) {
+  const float c = __builtin_amdgcn_cosf(0.5f * fminf(r, 1.f));
+  return r < 1.f ? fmaf(hk, c, hb) : 0.f;
+}
+
+// Float-float arithmetic (value = hi + lo) from error-free transformations; used
+// only for per-tile reference delays, so that no absolute delay (hundreds to
+// thousands of samples) is ever rounded to float32 on the per-gather path.
+// Floating-point contraction is off inside these helpers: fusing the product
+// of ff_mul into the following sum (allowed by the device default
+// -ffp-contract=fast) would silently drop the error terms.
+struct ff {
+  float hi, lo;
+};
+__device__ __forceinline__ ff two_sum(float a, float b) {
+#pragma clang fp contract(off)
+  const float s = a + b, bb = s - a;
+  return {s, (a - (s - bb)) + (b - bb)};
+}
+__device__ __forceinline__ ff ff_add(ff a, ff b) {
+#pragma clang fp contract(off)
+  ff s = two_sum(a.hi, b.hi);
+  return two_sum(s.hi, s.lo + a.lo + b.lo);
+}
+__device__ __forceinline__ ff ff_mul(ff a, ff b) {
+#pragma clang fp contract(off)
+  const float p = a.hi * b.hi;
+  const float e = fmaf(a.hi, b.hi, -p) + (a.hi * b.lo + a.lo * b.hi);
+  return two_sum(p, e);
+}
+__device__ __forceinline__ ff ff_neg(ff a) { return {-a.hi, -a.lo}; }
+__device__ __forceinline__ ff ff_sqrt(ff a) {
+#pragma clang fp contract(off)
+  if (!(a.hi > 0.f)) return {0.f, 0.f};
+  const float s = sqrtf(a.hi);
+  const float r = fmaf(-s, s, a.hi) + a.lo;
+  return two_sum(s, r / (2.f * s));
+}
+__device__ __forceinline__ float ff_f(ff a) { return a.hi + a.lo; }
+
+// AM: angles handled per pixel; PRED: AM is an upper bound and angles >= A are
+// skipped (generic bucket), else exactly AM == A angles, fully unrolled.
+// ONEGRP: one lane group per wavefront (cpw == 1), so the LDS window of a
+// channel is the same for the whole wavefront and its address stays scalar.
+//
+// Delays of pixel p are formed relative to the tile's reference pixel q:
+//   transmit  tx(p) - LT - off_t = [tx(q) - LT - off_t] + dx sin + dz cos,
+//   receive   rx(p) - LR - off_r = [rx(q) - LR - off_r]
+//                                  + (2 Dq dx + 2 Zq dz + dx^2 + dz^2) / (rx(p) + rx(q)),
+// with (dx, dz) = p - q, Dq = Xq - Xe, and the bracketed tile constants taken
+// from float-float reference delays; the integer offsets off_t, off_r centre
+// both terms on zero and are added back in the LDS address. Every float32
+// quantity on the per-gather path is then a small offset inside the tile's
+// window, accurate to ~1e-6 samples, instead of an absolute delay rounded at
+// ~1e-4 samples.
+template <int AM, bool PRED, int MODE, bool ONEGRP>
+__device__ __forceinline__ void process_tile(const FramePlan &P, int tz, int tx,
+                                             unsigned char *smem) {
+  float *s_txq = (float *)smem;                      // [kMaxAngles] tx(q) - LT
+  int *s_lt = (int *)(smem + kMaxAngles * 4);        // [kMaxAngles] LT
+  float4 *s_ch = (float4 *)(smem + kLdsAngleBytes);  // [chunk] {Dq, rq^2, rq, rx(q) - LR}
+  int *s_lr = (int *)(s_ch + P.chunk);               // [chunk] LR
+  float2 *s_pairs = (float2 *)(smem + plan_lds_win_offset(P));
+
+  const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1), wave = tid / kWave;
+  const int cpw = ONEGRP ? 1 : P.cpw;
+  const int ppw = kWave / cpw;  // lanes per group
+  const int pl = lane & (ppw - 1), grp = ONEGRP ? 0 : lane / ppw;
+  const int lz = P.lz, lx = P.lx;  // a group's pixels: lz along depth by lx along x
+  const int wzi = wave % P.wz, wxi = wave / P.wz;
+  const int TZ = P.tile_z, TX = P.tile_x;
+  const int iz0 = tz * TZ, ix0 = tx * TX;
+  const int iz = iz0 + wzi * lz + (pl & (lz - 1)), ix = ix0 + wxi * lx + pl / lz;
+  const int A = PRED ? P.n_angles : AM;
+  const int N = P.n_channels, win = P.win, chunk = P.chunk;
+  const float hk = P.apod == kHann ? 0.5f : 0.f, hb = 1.f - hk;
+
+  // Tile extent, clipped to the grid: lanes past the edge evaluate the edge
+  // pixel again and write nothing, so every window only spans grid pixels.
+  const int ixe = min(ix0 + TX - 1, P.nx - 1), ize = min(iz0 + TZ - 1, P.nz - 1);
+  const int ixq = (ix0 + ixe) >> 1, izq = (iz0 + ize) >> 1;  // reference pixel q
+  // pixel offsets from q, and the tile's offset range
+  const float dx = (float)(min(ix, ixe) - ixq) * P.DX;
+  const float dz = (float)(min(iz, ize) - izq) * P.DZ;
+  const float dxlo = (float)(ix0 - ixq) * P.DX, dxhi = (float)(ixe - ixq) * P.DX;
+  const float dzlo = (float)(iz0 - izq) * P.DZ, dzhi = (float)(ize - izq) * P.DZ;
+  // reference position in float-float
+  const ff Xq = ff_add(ff_mul({(float)ixq, 0.f}, {P.DX, P.DXl}), {P.X0, P.X0l});
+  const ff Zq = ff_add(ff_mul({(float)izq, 0.f}, {P.DZ, P.DZl}), {P.Z0, P.Z0l});
+  const float Zqf = ff_f(Zq);
+  const float Zp = Zqf + dz;
+  const float invA = P.apod == kNone ? 0.f : (Zp > 0.f ? P.ap_k / Zp : __builtin_inff());
+  const float cp = fmaf(2.f * Zqf, dz, fmaf(dx, dx, dz * dz));
+  const float dx2 = 2.f * dx;
+
+  // Per-angle tile constants: window origin LT = floor(min_tile tx) - 1 and
+  // tx(q) - LT. tx is linear, so its tile minimum is at a corner.
+  for (int a = tid; a < A; a += blockDim.x) {
+    const ff sa = {P.sa[a], P.sal[a]}, ca = {P.ca[a], P.cal[a]}, to = {P.to[a], P.tol[a]};
+    const ff txq = ff_add(ff_add(ff_mul(Xq, sa), ff_mul(Zq, ca)), ff_neg(to));
+    const float dmin = fminf(dxlo * sa.hi, dxhi * sa.hi) + fminf(dzlo * ca.hi, dzhi * ca.hi);
+    const float fl = floorf(txq.hi);
+    const float lt = fl + floorf((txq.hi - fl) + txq.lo + dmin) - 1.f;
+    s_txq[a] = ff_f(ff_add(txq, {-(lt + (float)P.off_t), 0.f}));
+    s_lt[a] = (int)lt;
+  }
+  __syncthreads();
+  float txl[AM];
+#pragma unroll
+  for (int a = 0; a < AM; ++a)
+    if (!PRED || a < A) txl[a] = s_txq[a] + fmaf(dx, P.sa[a], dz * P.ca[a]);
+
+  float total = 0.f;
+  float S[MODE == kDmas ? AM : 1];
+  float Q = 0.f;
+#pragma unroll
+  for (int a = 0; a < (MODE == kDmas ? AM : 1); ++a) S[a] = 0.f;
+
+  for (int e0 = 0; e0 < N; e0 += chunk) {
+    if (e0 > 0) __syncthreads();  // the previous chunk's windows have been read
+    // Per-channel tile constants: window origin LR = floor(min_tile rx) - 1 (the
+    // tile point nearest the element), the reference delay rx(q) in
+    // float-float, and the terms of the receive-delay difference.
+    for (int c = tid; c < chunk; c += blockDim.x) {
+      const int e = min(e0 + c, N - 1);
+      const ff xe = {P.xe[e], P.xel[e]};
+      const ff dq = ff_add(Xq, ff_neg(xe));
+      const ff rq2 = ff_add(ff_mul(dq, dq), ff_mul(Zq, Zq));
+      const ff rq = ff_sqrt(rq2);
+      const float dqf = ff_f(dq);
+      // lateral offsets X - Xe over the tile span [dq + dxlo, dq + dxhi]
+      const float ddx = fmaxf(fmaxf(dqf + dxlo, -(dqf + dxhi)), 0.f);
+      const float zlo = Zqf + dzlo, zhi = Zqf + dzhi;
+      const float ddz = zlo > 0.f ? zlo : (zhi < 0.f ? -zhi : 0.f);
+      const float rmin = sqrtf(fmaf(ddx, ddx, ddz * ddz));
+      const float lr = floorf(rmin) - 1.f;
+      s_ch[c] = make_float4(dqf, ff_f(rq2), ff_f(rq) + 1e-20f,
+                            ff_f(ff_add(rq, {-(lr + (float)P.off_r), 0.f})));
+      s_lr[c] = (int)lr;
+    }
+    __syncthreads();
+    if (P.dtype == kI16)
+      stage_windows<kI16>(P, e0, s_lt, s_lr, s_pairs);
+    else if (P.dtype == kF16)
+      stage_windows<kF16>(P, e0, s_lt, s_lr, s_pairs);
+    else
+      stage_windows<kF32>(P, e0, s_lt, s_lr, s_pairs);
+    __syncthreads();
+
+    const int wstride = win * (int)sizeof(float2);  // bytes between angle windows
+    for (int k = 0; k < chunk; k += cpw) {
+      const int c = ONEGRP ? k : k + grp;
+      const float4 ch = s_ch[c];
+      // receive delay relative to the window origin, as a difference from rx(q)
+      const float num = fmaf(dx2, ch.x, cp);
+      const float den = __builtin_amdgcn_sqrtf(ch.y + num) + ch.z;
+      const float rxl = fmaf(num, __builtin_amdgcn_rcpf(den), ch.w);
+      const float w = apod_weight(fabsf(ch.x + dx) * invA, hk, hb);
+      // delays are centred: entry n of the window is read as n + off_t + off_r
+      const char *wb = (const char *)(s_pairs + (size_t)c * A * win + P.off_t + P.off_r);
+      if constexpr (MODE == kDas) {
+        float acc = 0.f;
+#pragma unroll
+        for (int a = 0; a < AM; ++a) {
+          if (!PRED || a < A) {
+            const float s = txl[a] + rxl;
+            const int n = floor_i32(s);
+            const float f = __builtin_amdgcn_fractf(s);
+            const float2 p = *(const float2 *)(wb + a * wstride + (n << 3));
+            acc += p.x;
+            acc = fmaf(f, p.y, acc);
+          }
+        }
+        total = fmaf(w, acc, total);
+      } else {
+        float q = 0.f;
+#pragma unroll
+        for (int a = 0; a < AM; ++a) {
+          if (!PRED || a < A) {
+            const float s = txl[a] + rxl;
+            const int n = floor_i32(s);
+            const float f = __builtin_amdgcn_fractf(s);
+            const float2 p = *(const float2 *)(wb + a * wstride + (n << 3));
+            const float v = fmaf(f, p.y, p.x);
+            const float r = __builtin_amdgcn_sqrtf(fabsf(v));
+            S[a] = fmaf(w, copysignf(r, v), S[a]);
+            q += fabsf(v);
+          }
+        }
+        Q = fmaf(w * w, q, Q);
+      }
+    }
+  }
+
+  float y;
+  if constexpr (MODE == kDas) {
+    for (int off = ppw; off < kWave; off <<= 1) total += __shfl_xor(total, off);
+    y = total;
+  } else {
+    for (int off = ppw; off < kWave; off <<= 1) Q += __shfl_xor(Q, off);
+    float sq = 0.f;
+#pragma unroll
+    for (int a = 0; a < AM; ++a) {
+      if (!PRED || a < A) {
+        float s = S[a];
+        for (int off = ppw; off < kWave; off <<= 1) s += __shfl_xor(s, off);
+        sq = fmaf(s, s, sq);
+      }
+    }
+    y = 0.5f * (sq - Q);
+  }
+  if (grp == 0 && ix < P.nx && iz < P.nz) P.out[(size_t)ix * P.nz + iz] = y;
+}
+
+}  // namespace dev
+}  // namespace pwbf

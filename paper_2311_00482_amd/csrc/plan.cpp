@@ -231,7 +231,7 @@ static int fit_tile(const pwbf_geometry *g, pwbf_tile t, FramePlan *P, std::stri
 }
 
 int plan_frame(const pwbf_geometry *g, int dtype, int mode, int angle, const pwbf_tile *tile_in,
-               FramePlan *P, std::string *err) {
+               FramePlan *P, std::string *err, int waves) {
   int rc = validate_geometry(g, err);
   if (rc) return rc;
   if (dtype != kI16 && dtype != kF16 && dtype != kF32)
@@ -271,10 +271,19 @@ int plan_frame(const pwbf_geometry *g, int dtype, int mode, int angle, const pwb
     split(first * scale + (g->t0 ? g->t0[a] : 0.0) * g->fs, &P->to[k], &P->tol[k]);
   }
 
-  // An explicit tile is taken as given; the default falls back to shapes with
-  // shorter tiles (more lane groups, fewer columns) until its windows fit in LDS.
+  // An explicit tile is taken as given; an absent or all-zero tile takes the
+  // tuned entry for this shape if there is one, else the default, which falls
+  // back to shallower / narrower tiles until its windows fit in LDS.
   pwbf_tile d = default_tile(g, na, mode);
-  pwbf_tile cands[10];
+  const bool zero_tile = tile_in && !tile_in->cpw && !tile_in->lz && !tile_in->wz &&
+                         !tile_in->wx && !tile_in->chunk;
+  pwbf_tile tuned;
+  if ((!tile_in || zero_tile) && tune_lookup(shape_key(g, dtype, mode, angle, waves), &tuned)) {
+    tile_in = &tuned;
+  } else if (zero_tile) {
+    tile_in = nullptr;
+  }
+  pwbf_tile cands[12];
   int nc = 0;
   if (tile_in) {
     pwbf_tile t = *tile_in;
@@ -285,6 +294,13 @@ int plan_frame(const pwbf_geometry *g, int dtype, int mode, int angle, const pwb
       t.wx = d.wx;
     }
     cands[nc++] = t;
+  } else if (waves == 8) {
+    // batch blocks: always 8 wavefronts; shrink the tile by its lane layout
+    cands[nc++] = d;
+    const pwbf_tile more[] = {{d.cpw, 8, 1, 8, 0}, {d.cpw, 4, 1, 8, 0}, {4, 4, 1, 8, 0},
+                              {4, 2, 1, 8, 0},     {4, 1, 1, 8, 0}};
+    for (const pwbf_tile &m : more)
+      if (m.cpw >= d.cpw && m.lz <= kWave / m.cpw) cands[nc++] = m;
   } else {
     cands[nc++] = d;
     const pwbf_tile more[] = {{d.cpw, 16, 1, 4, 0}, {d.cpw, 16, 1, 2, 0}, {d.cpw, 16, 1, 1, 0},
@@ -295,6 +311,12 @@ int plan_frame(const pwbf_geometry *g, int dtype, int mode, int angle, const pwb
   }
   int rc_fit = PWBF_OK;
   for (int ci = 0; ci < nc; ++ci) {
+    if (waves && cands[ci].wz * cands[ci].wx != waves) {
+      rc_fit = fail(err, PWBF_E_INVALID, "batch tiles need wz * wx = %d (got %d x %d)", waves,
+                    cands[ci].wz, cands[ci].wx);
+      if (tile_in) break;
+      continue;
+    }
     rc_fit = fit_tile(g, cands[ci], P, err);
     if (rc_fit != PWBF_E_UNSUPPORTED || tile_in) break;
   }

@@ -16,12 +16,20 @@ size_t workspace_bytes(const pwbf_geometry *g, const pwbf_outputs *o);
 pwbf_tile default_tile(const pwbf_geometry *g, int n_angles_used, int mode);
 // Geometry and launch shape only (no pointers). angle < 0: all angles
 // (compound); angle >= 0: that angle alone.
+// waves = 8: the batch kernel's fixed 8-wavefront blocks; 0: any 1..8.
 int plan_frame(const pwbf_geometry *g, int dtype, int mode, int angle, const pwbf_tile *tile,
-               FramePlan *P, std::string *err);
+               FramePlan *P, std::string *err, int waves = 0);
 // plan_frame plus the pointer, output and workspace checks.
 int build_plan(const pwbf_geometry *g, const void *rf, int dtype, int mode, int angle,
                const pwbf_tile *tile, const pwbf_outputs *o, void *ws, size_t ws_bytes,
                FramePlan *P, std::string *err);
+// tuning table (tune.cpp)
+std::string shape_key(const pwbf_geometry *g, int dtype, int mode, int angle, int waves);
+bool tune_lookup(const std::string &key, pwbf_tile *t);
+void tune_store(const std::string &key, const pwbf_tile &t);
+int tune_save(const char *path, std::string *err);
+int tune_load(const char *path, std::string *err);
+void tune_clear();
 int build_post_plan(const pwbf_geometry *g, const pwbf_outputs *o, void *ws, PostPlan *Q);
 bool post_needed(const pwbf_outputs *o);
 

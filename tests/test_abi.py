@@ -199,3 +199,78 @@ def test_describe_plan_default_shapes():
     assert p1["xe"][200] == p1["xe"][63]
     p2 = describe_plan(config_c2(), "dmas", bandpass=True)
     assert p2["n_angles_used"] == 1
+
+
+# ------------------------------------------------------------------- batches
+def _frame(g, rf=FAKE, dtype=_abi.I16, mode=_abi.DAS, angle=-1, tile=None, reserved=0):
+    t = tile.c() if tile is not None else _abi.Tile()
+    return _abi.Frame(ctypes.pointer(g.s), rf, dtype, mode, angle, reserved,
+                      _abi.Outputs(FAKE, None, None, None), t)
+
+
+def _create(frames, flags=0):
+    arr = (_abi.Frame * max(1, len(frames)))(*frames)
+    h = ctypes.c_void_p()
+    rc = _abi.lib().pwbf_batch_create(arr, len(frames), flags, None, ctypes.byref(h))
+    return rc, _abi.lib().pwbf_last_error().decode()
+
+
+def test_batch_create_rejects_before_touching_the_device():
+    g = GeometryArg(config_c1())
+    ok = _frame(g)
+    assert _create([])[0] == _abi.E_INVALID
+    assert _create([ok], flags=8)[0] == _abi.E_INVALID
+    assert _create([ok, _frame(g, reserved=1)])[0] == _abi.E_INVALID
+    rc, msg = _create([ok, _frame(g, tile=Tile(1, 16, 1, 4, 0))])
+    assert rc == _abi.E_INVALID and "wz * wx = 8" in msg
+    g20 = GeometryArg(config_c1().replace(angles_deg=tuple(range(-10, 10))))
+    rc, msg = _create([_frame(g20)])
+    assert rc == _abi.E_UNSUPPORTED and "16 angles" in msg
+    bad = GeometryArg(config_c1())
+    bad.s.dz = -1.0
+    assert _create([ok, _frame(bad)])[0] == _abi.E_INVALID
+    assert _create([_frame(g, rf=None)])[0] == _abi.E_INVALID
+    L = _abi.lib()
+    assert L.pwbf_batch_create(None, 1, 0, None, None) == _abi.E_INVALID
+    assert L.pwbf_batch_launch(None, None) == _abi.E_INVALID
+    assert L.pwbf_batch_update(None, None, 1, None) == _abi.E_INVALID
+    assert L.pwbf_batch_destroy(None) == 0
+
+
+def test_tune_argument_errors():
+    L = _abi.lib()
+    g = GeometryArg(config_c1())
+    o = _abi.Outputs(FAKE, None, None, None)
+    assert L.pwbf_tune(g.ref, FAKE, 0, 0, 0, ctypes.byref(o), 3, None, None, None) == \
+        _abi.E_INVALID
+    assert L.pwbf_tune(g.ref, FAKE, 0, 0, 0, None, 0, None, None, None) == _abi.E_INVALID
+    g.s.n_angles = 0
+    assert L.pwbf_tune(g.ref, FAKE, 0, 0, 0, ctypes.byref(o), 0, None, None, None) == \
+        _abi.E_INVALID
+
+
+def test_tuning_table_round_trip_drives_default_plans(tmp_path):
+    import math
+    from paper_2311_00482_amd import tune_clear, tune_load, tune_save
+    g = config_c3()
+    sc = g.fs / g.c
+    smax = max(abs(math.sin(a)) for a in g.angles_rad)
+    # the table key names the shape (see the library's shape_key)
+    key = "m0_t2_a11_n128_s4096_x1024_z1024_dx%.4g_dz%.4g_sin%.3g_w0" % (
+        g.dx * sc, g.dz * sc, smax)
+    path = tmp_path / "tune.json"
+    path.write_text('{\n  "%s": [2, 8, 1, 4, 0]\n}\n' % key)
+    tune_clear()
+    try:
+        assert describe_plan(g)["cpw"] == 1
+        tune_load(str(path))
+        p = describe_plan(g)
+        assert (p["cpw"], p["lz"], p["wz"], p["wx"]) == (2, 8, 1, 4)
+        # an explicit tile still wins over the table
+        assert describe_plan(g, tile=Tile(1, 16, 1, 8, 0))["cpw"] == 1
+        out = tmp_path / "saved.json"
+        tune_save(str(out))
+        assert key in out.read_text()
+    finally:
+        tune_clear()
+    assert describe_plan(g)["cpw"] == 1

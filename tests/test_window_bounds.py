@@ -148,3 +148,44 @@ def test_batch_and_serving_shapes_inside_windows():
         seen.add(key)
         lo, hi, win = window_index_range(g, spec.mode, -1, None, edge_channels(g.n_channels))
         assert lo >= 0 and hi <= win - 1, (g.name, lo, hi, win)
+
+
+def _tuner_shapes():
+    # Of the candidates the tuner times for batch blocks (8 wavefronts), the ones
+    # with the extreme tile extents: deepest (64 x 8), widest (8 x 64), default.
+    return [(1, 32, 2, 4, 0), (1, 8, 1, 8, 0), (1, 16, 1, 8, 0), (4, 16, 1, 8, 0)]
+
+
+@pytest.mark.slow
+def test_tuner_shapes_inside_windows_on_batch_workload():
+    from paper_2311_00482_amd import PwbfError
+    seen = set()
+    for spec in config_c4_frames() + config_c5_probes():
+        g = spec.geom
+        key = (g.n_channels, g.n_angles, g.nx, g.nz, g.z_min, spec.mode)
+        if key in seen:
+            continue
+        seen.add(key)
+        for shape in _tuner_shapes():
+            try:
+                lo, hi, win = window_index_range(g, spec.mode, -1, Tile(*shape),
+                                                 [0, g.n_channels - 1])
+            except PwbfError:
+                continue  # a shape whose windows do not fit is rejected, never launched
+            assert lo >= 0 and hi <= win - 1, (g.name, shape, lo, hi, win)
+
+
+def test_batch_test_shapes_inside_windows():
+    import torch  # noqa: F401  (mixed_frames builds tensors; run on the CPU here)
+    specs = [
+        (geom(angles_deg=(-8.0, 0.0, 8.0), nx=40, nz=128), "das", -1, (1, 16, 1, 8, 0)),
+        (geom(n_channels=32, nx=33, nz=64), "dmas", 0, (2, 16, 2, 4, 0)),
+        (geom(angles_deg=(-10., -5., 0., 5., 10.), nx=21, nz=256, n_channels=24), "das", -1,
+         (4, 16, 1, 8, 0)),
+        (geom(angles_deg=(0.0, 4.0), n_channels=20, nx=64, nz=512, z_min=10e-3,
+              z_max=10e-3 + 512 * 25e-6), "dmas", -1, (1, 8, 1, 8, 0)),
+        (geom(angles_deg=tuple(range(-6, 8, 2)), nx=17, nz=32), "das", 3, (1, 32, 2, 4, 0)),
+    ]
+    for g, mode, angle, shape in specs:
+        lo, hi, win = window_index_range(g, mode, angle, Tile(*shape))
+        assert lo >= 0 and hi <= win - 1, (shape, lo, hi, win)
