@@ -285,6 +285,80 @@ PWBF_API int pwbf_tune_save(const char *path);
 PWBF_API int pwbf_tune_load(const char *path);
 PWBF_API int pwbf_tune_clear(void);
 
+/* ------------------------------------------------------------------ serving
+ * A request loop over fixed probes. Each probe (geometry, mode, angle
+ * selection, output planes) owns ring slots resident in HBM: its RF stored as
+ * FP16 and its output planes. submit() queues a frame of int16 RF from pinned
+ * host memory; a scheduler thread admits queued requests into free slots while
+ * the HBM budget ledger allows (the bytes of the slots in use), uploads them on
+ * a copy stream and converts them to FP16 on the device, and, whenever fewer
+ * than two batches are on the GPU, launches every uploaded request as one
+ * batch (continuous batching: requests that arrive while others run join the
+ * next batch). A frame runs the same kernels with the same plan whether it is
+ * alone or in a mix, so its planes do not depend on the mix. */
+typedef struct pwbf_probe {
+  const pwbf_geometry *geom; /* host; copied at creation */
+  int32_t mode;              /* PWBF_DAS / PWBF_DMAS */
+  int32_t angle;             /* -1: compound; else that angle */
+  int32_t want_env;          /* 1: envelope plane */
+  int32_t want_log;          /* 1: log image (implies the envelope) */
+  int32_t slots;             /* ring slots (0 = 4) */
+  int32_t reserved;          /* 0 */
+} pwbf_probe;
+
+typedef struct pwbf_server pwbf_server;
+
+typedef struct pwbf_result {
+  uint64_t id;            /* as returned by submit */
+  int32_t probe, slot;
+  double t_arrival;       /* seconds on the server clock (pwbf_server_now) */
+  double t_admit;         /* slot assigned, upload enqueued */
+  double t_launch;        /* batch enqueued */
+  double t_done;          /* output planes complete on the device */
+  const float *rf;        /* device planes of the slot, valid until released */
+  const float *env;
+  const float *logimg;
+} pwbf_result;
+
+typedef struct pwbf_server_stats {
+  int64_t submitted, rejected, completed, batches;
+  int64_t queued, in_flight;   /* right now */
+  double mean_batch;           /* requests per batch */
+  size_t budget_bytes, budget_in_use, budget_peak;
+} pwbf_server_stats;
+
+#define PWBF_E_BUSY (-5) /* serving: the probe's queue is full */
+
+/* Create a server for n probes. hbm_budget_bytes caps the bytes of slots in use
+ * (0 = no cap beyond the allocated rings); max_queue bounds each probe's queue
+ * of waiting requests (0 = 1024). Allocates the rings and starts the scheduler. */
+PWBF_API int pwbf_server_create(const pwbf_probe *probes, int32_t n, size_t hbm_budget_bytes,
+                                int32_t max_queue, pwbf_server **out);
+
+/* Queue a frame for probe `probe`: host_rf is int16 RF[n_angles][n_channels][n_samples]
+ * in pinned host memory, read asynchronously until the request completes.
+ * t_arrival < 0 stamps the current server time. *id receives the request id.
+ * PWBF_E_BUSY when the probe's queue is full (the request is dropped). */
+PWBF_API int pwbf_server_submit(pwbf_server *s, int32_t probe, const int16_t *host_rf,
+                                double t_arrival, uint64_t *id);
+
+/* Collect up to max completed requests into results (*n receives the count),
+ * waiting up to wait_ms for at least one. Their slots stay reserved until
+ * pwbf_server_release. */
+PWBF_API int pwbf_server_poll(pwbf_server *s, pwbf_result *results, int32_t max, int32_t *n,
+                              int32_t wait_ms);
+
+/* Free the slot of a completed request. */
+PWBF_API int pwbf_server_release(pwbf_server *s, uint64_t id);
+
+PWBF_API int pwbf_server_stats_get(pwbf_server *s, pwbf_server_stats *st);
+
+/* Seconds on the server's steady clock. */
+PWBF_API double pwbf_server_now(const pwbf_server *s);
+
+/* Stop the scheduler, wait for the device, free everything. NULL is ignored. */
+PWBF_API int pwbf_server_destroy(pwbf_server *s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -8,7 +8,10 @@ from ._abi import PwbfError, lib  # noqa: F401
 from .api import (  # noqa: F401
     Batch,
     FrameSpec,
+    Completed,
     GeometryArg,
+    ProbeSpec,
+    Server,
     Tile,
     alloc_outputs,
     beamform,

@@ -13,14 +13,14 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpwbf.so")
 
 ABI_VERSION = 1
-OK, E_INVALID, E_UNSUPPORTED, E_NOMEM, E_DEVICE = 0, -1, -2, -3, -4
+OK, E_INVALID, E_UNSUPPORTED, E_NOMEM, E_DEVICE, E_BUSY = 0, -1, -2, -3, -4, -5
 I16, F16, F32 = 0, 1, 2
 DAS, DMAS = 0, 1
 APOD_HANN, APOD_BOXCAR, APOD_NONE = 0, 1, 2
 MAX_ANGLES, MAX_CHANNELS, MAX_NZ_POST = 32, 256, 4096
 
 ERROR_NAMES = {E_INVALID: "PWBF_E_INVALID", E_UNSUPPORTED: "PWBF_E_UNSUPPORTED",
-               E_NOMEM: "PWBF_E_NOMEM", E_DEVICE: "PWBF_E_DEVICE"}
+               E_NOMEM: "PWBF_E_NOMEM", E_DEVICE: "PWBF_E_DEVICE", E_BUSY: "PWBF_E_BUSY"}
 
 
 class Geometry(ctypes.Structure):
@@ -74,6 +74,28 @@ class BatchInfo(ctypes.Structure):
 BATCH_TUNE = 1
 
 
+class Probe(ctypes.Structure):
+    _fields_ = [("geom", ctypes.POINTER(Geometry)), ("mode", ctypes.c_int32),
+                ("angle", ctypes.c_int32), ("want_env", ctypes.c_int32),
+                ("want_log", ctypes.c_int32), ("slots", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_uint64), ("probe", ctypes.c_int32), ("slot", ctypes.c_int32),
+                ("t_arrival", ctypes.c_double), ("t_admit", ctypes.c_double),
+                ("t_launch", ctypes.c_double), ("t_done", ctypes.c_double),
+                ("rf", ctypes.c_void_p), ("env", ctypes.c_void_p), ("logimg", ctypes.c_void_p)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("rejected", ctypes.c_int64),
+                ("completed", ctypes.c_int64), ("batches", ctypes.c_int64),
+                ("queued", ctypes.c_int64), ("in_flight", ctypes.c_int64),
+                ("mean_batch", ctypes.c_double), ("budget_bytes", ctypes.c_size_t),
+                ("budget_in_use", ctypes.c_size_t), ("budget_peak", ctypes.c_size_t)]
+
+
 class PlanInfo(ctypes.Structure):
     _fields_ = [
         ("cpw", ctypes.c_int32), ("lz", ctypes.c_int32), ("wz", ctypes.c_int32),
@@ -105,6 +127,12 @@ def lib():
         raise ImportError(
             f"{LIB_PATH} is missing: build the HIP library first "
             "(python -m paper_2311_00482_amd.build)")
+    try:
+        # torch first: libpwbf then binds to the HIP runtime torch already holds
+        # (same soname), so device pointers and streams are shared
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = ctypes.CDLL(LIB_PATH)
     G, O, T, PI = (ctypes.POINTER(Geometry), ctypes.POINTER(Outputs), ctypes.POINTER(Tile),
                    ctypes.POINTER(PlanInfo))
@@ -145,6 +173,21 @@ def lib():
         getattr(L, name).argtypes = [ctypes.c_char_p]
     L.pwbf_tune_clear.restype = ctypes.c_int
     L.pwbf_tune_clear.argtypes = []
+    L.pwbf_server_create.restype = ctypes.c_int
+    L.pwbf_server_create.argtypes = [ctypes.POINTER(Probe), i32, sz, i32, ctypes.POINTER(vp)]
+    L.pwbf_server_submit.restype = ctypes.c_int
+    L.pwbf_server_submit.argtypes = [vp, i32, vp, ctypes.c_double,
+                                     ctypes.POINTER(ctypes.c_uint64)]
+    L.pwbf_server_poll.restype = ctypes.c_int
+    L.pwbf_server_poll.argtypes = [vp, ctypes.POINTER(Result), i32, ctypes.POINTER(i32), i32]
+    L.pwbf_server_release.restype = ctypes.c_int
+    L.pwbf_server_release.argtypes = [vp, ctypes.c_uint64]
+    L.pwbf_server_stats_get.restype = ctypes.c_int
+    L.pwbf_server_stats_get.argtypes = [vp, ctypes.POINTER(ServerStats)]
+    L.pwbf_server_now.restype = ctypes.c_double
+    L.pwbf_server_now.argtypes = [vp]
+    L.pwbf_server_destroy.restype = ctypes.c_int
+    L.pwbf_server_destroy.argtypes = [vp]
     if L.pwbf_abi_version() != ABI_VERSION:
         raise ImportError(f"libpwbf ABI {L.pwbf_abi_version()} != binding {ABI_VERSION}")
     _lib = L

@@ -286,3 +286,117 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+@dataclass
+class ProbeSpec:
+    """One probe of a serving loop (pwbf_probe): geometry, beamformer, planes."""
+    geom: object
+    mode: str = "das"
+    angle: int = -1
+    want: Iterable[str] = ("rf", "env", "log")
+    slots: int = 4
+    bandpass: bool = False
+
+
+@dataclass
+class Completed:
+    """A finished request (pwbf_result); the planes stay valid until release()."""
+    id: int
+    probe: int
+    slot: int
+    t_arrival: float
+    t_admit: float
+    t_launch: float
+    t_done: float
+    rf: int
+    env: Optional[int]
+    logimg: Optional[int]
+
+
+class Server:
+    """pwbf_server: continuous batching of int16 frames over resident HBM rings.
+
+    ``submit`` takes a pinned host int16 tensor [angles, channels, samples] and
+    keeps a reference to it until the request is released. ``planes(result)``
+    views the slot's device planes as torch tensors (no copy)."""
+
+    def __init__(self, probes, hbm_budget_bytes: int = 0, max_queue: int = 0):
+        self._geoms = [_as_geom(p.geom, p.bandpass) for p in probes]
+        arr = (_abi.Probe * len(probes))()
+        for i, (p, ga) in enumerate(zip(probes, self._geoms)):
+            want = set(p.want)
+            arr[i] = _abi.Probe(ctypes.pointer(ga.s), _MODES[p.mode], p.angle,
+                                1 if "env" in want else 0, 1 if "log" in want else 0,
+                                p.slots, 0)
+        handle = ctypes.c_void_p()
+        _abi.check(_abi.lib().pwbf_server_create(arr, len(probes), hbm_budget_bytes, max_queue,
+                                                 ctypes.byref(handle)))
+        self.handle = handle
+        self.probes = list(probes)
+        self._pending = {}
+
+    def submit(self, probe: int, host_rf, t_arrival: float = -1.0) -> int:
+        import torch
+        ga = self._geoms[probe]
+        if (host_rf.dtype != torch.int16 or host_rf.is_cuda or not host_rf.is_contiguous()
+                or tuple(host_rf.shape) != ga.shape_rf):
+            raise ValueError(f"host_rf must be a contiguous host int16 tensor {ga.shape_rf}")
+        rid = ctypes.c_uint64()
+        _abi.check(_abi.lib().pwbf_server_submit(self.handle, probe, host_rf.data_ptr(),
+                                                 t_arrival, ctypes.byref(rid)))
+        self._pending[rid.value] = host_rf
+        return rid.value
+
+    def poll(self, max_results: int = 64, wait_ms: int = 0):
+        res = (_abi.Result * max_results)()
+        n = ctypes.c_int32()
+        _abi.check(_abi.lib().pwbf_server_poll(self.handle, res, max_results, ctypes.byref(n),
+                                               wait_ms))
+        return [Completed(r.id, r.probe, r.slot, r.t_arrival, r.t_admit, r.t_launch, r.t_done,
+                          r.rf, r.env, r.logimg) for r in res[:n.value]]
+
+    def planes(self, result: Completed) -> Dict:
+        """Copies of a completed request's device planes as [nx, nz] float32 tensors."""
+        import torch
+        ga = self._geoms[result.probe]
+        out = {}
+        for name, ptr in (("rf", result.rf), ("env", result.env), ("log", result.logimg)):
+            if ptr:
+                t = torch.empty((ga.nx, ga.nz), dtype=torch.float32, device="cuda")
+                rc = _hip().hipMemcpy(ctypes.c_void_p(t.data_ptr()), ctypes.c_void_p(ptr),
+                                      ctypes.c_size_t(t.numel() * 4), 3)
+                if rc != 0:
+                    raise _abi.PwbfError(_abi.E_DEVICE, f"hipMemcpy of the {name} plane: {rc}")
+                out[name] = t
+        return out
+
+    def release(self, rid: int) -> None:
+        _abi.check(_abi.lib().pwbf_server_release(self.handle, rid))
+        self._pending.pop(rid, None)
+
+    def stats(self) -> Dict:
+        st = _abi.ServerStats()
+        _abi.check(_abi.lib().pwbf_server_stats_get(self.handle, ctypes.byref(st)))
+        return {k: getattr(st, k) for k, _ in _abi.ServerStats._fields_}
+
+    def now(self) -> float:
+        return float(_abi.lib().pwbf_server_now(self.handle))
+
+    def close(self) -> None:
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            _abi.check(_abi.lib().pwbf_server_destroy(self.handle))
+            self.handle = None
+            self._pending.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _hip():
+    """The HIP runtime torch loaded (only for copying library-owned planes)."""
+    import torch  # noqa: F401
+    return ctypes.CDLL("libamdhip64.so.7")

@@ -21,14 +21,14 @@ LIB = os.path.join(HERE, "libpwbf.so")
 ROOT = os.path.dirname(HERE)
 ARCH = os.environ.get("PWBF_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["plan.cpp", "tune.cpp", "api.cpp", "batch.cpp", "beamform.hip", "postz.hip",
-           "batch.hip"]
+SOURCES = ["plan.cpp", "tune.cpp", "api.cpp", "batch.cpp", "serve.cpp", "beamform.hip",
+           "postz.hip", "batch.hip", "serve.hip"]
 
 COMMON = [
     "-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}",
     # no packed-FP32 instructions anywhere in the device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    "-Wall", "-Wno-unused-function", "-fvisibility=hidden",
+    "-Wall", "-Wno-unused-function", "-fvisibility=hidden", "-pthread",
     f"-I{os.path.join(ROOT, 'include')}",
 ]
 
@@ -56,7 +56,7 @@ def build(verbose: bool = False) -> str:
     with cf.ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
         objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
     tmp = LIB + f".tmp{os.getpid()}"
-    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-pthread", "-o", tmp, *objs]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)

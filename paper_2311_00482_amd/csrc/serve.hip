@@ -1,0 +1,152 @@
+// Kernels of the serving loop. A serving batch is a list of active ring slots
+// passed by value; prefix sums of the slots' tile and column counts map a
+// global work index to (slot, tile) or (slot, column), so no per-batch table is
+// uploaded and any mix of probes runs in one persistent launch.
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+
+#include "beamform_device.h"
+#include "postz_device.h"
+#include "serve.h"
+
+namespace pwbf {
+
+namespace {
+
+constexpr int kServeWaves = 8;
+constexpr int kServeMaxAngles = 16;
+
+// index k with start[k] <= i < start[k + 1] (start[0] = 0, n entries)
+__device__ __forceinline__ int find_slot(const int *start, int n, int i) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (start[mid] <= i)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ void k_i16_to_f16(void *buf, size_t n) {
+  // element i is read as int16 and written back as binary16 by the same thread;
+  // 10-bit samples (|v| <= 2048) convert exactly
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x) {
+    const int16_t v = ((const int16_t *)buf)[i];
+    ((__half *)buf)[i] = __int2half_rn((int)v);
+  }
+}
+
+__global__ void k_serve_reset(int *counter, const PostPlan *__restrict__ post, ActiveList al) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) *counter = 0;
+  if (i < al.n) {
+    const PostPlan &Q = post[al.plan[i]];
+    if (Q.ws_max) *Q.ws_max = 0u;
+  }
+}
+
+template <int MODE, bool ONEGRP>
+__device__ __forceinline__ void serve_tile_mode(const FramePlan &P, int tz, int tx,
+                                                unsigned char *smem) {
+  switch (P.n_angles) {
+    case 1: dev::process_tile<1, false, MODE, ONEGRP>(P, tz, tx, smem); break;
+    case 5: dev::process_tile<5, false, MODE, ONEGRP>(P, tz, tx, smem); break;
+    case 11: dev::process_tile<11, false, MODE, ONEGRP>(P, tz, tx, smem); break;
+    default: dev::process_tile<kServeMaxAngles, true, MODE, ONEGRP>(P, tz, tx, smem); break;
+  }
+}
+
+__global__ void __launch_bounds__(kWave * kServeWaves)
+    k_serve_beamform(const FramePlan *__restrict__ plans, const ActiveList al,
+                     int *__restrict__ counter) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int s_item;
+  for (;;) {
+    __syncthreads();
+    if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
+    __syncthreads();
+    const int it = __builtin_amdgcn_readfirstlane(s_item);
+    if (it >= al.tile0[al.n]) break;  // uniform: every wave of the block leaves
+    const int k = find_slot(al.tile0, al.n, it);
+    const FramePlan &P = plans[al.plan[k]];
+    const int t = it - al.tile0[k];
+    const int tz = t / P.tiles_x, tx = t - tz * P.tiles_x;
+    if (P.mode == kDas) {
+      if (P.cpw == 1)
+        serve_tile_mode<kDas, true>(P, tz, tx, smem);
+      else
+        serve_tile_mode<kDas, false>(P, tz, tx, smem);
+    } else {
+      if (P.cpw == 1)
+        serve_tile_mode<kDmas, true>(P, tz, tx, smem);
+      else
+        serve_tile_mode<kDmas, false>(P, tz, tx, smem);
+    }
+  }
+}
+
+__global__ void __launch_bounds__(dev::kPostThreads)
+    k_serve_postz(const PostPlan *__restrict__ post, const ActiveList al) {
+  extern __shared__ __align__(16) float2 sm[];
+  const int b = blockIdx.x;
+  const int k = find_slot(al.col0, al.n, b);
+  dev::postz_column(post[al.plan[k]], b - al.col0[k], sm);
+}
+
+__global__ void __launch_bounds__(256) k_serve_logc(const PostPlan *__restrict__ post,
+                                                    const ActiveList al) {
+  const int b = blockIdx.x;
+  const int k = find_slot(al.log0, al.n, b);
+  const PostPlan &Q = post[al.plan[k]];
+  const float m = __uint_as_float(*Q.ws_max);
+  const size_t base = (size_t)(b - al.log0[k]) * Q.nz;
+  for (int i = threadIdx.x; i < Q.nz; i += blockDim.x)
+    Q.logimg[base + i] = dev::log_db(Q.env[base + i], m, Q.floor_db);
+}
+
+}  // namespace
+
+int serve_waves() { return kServeWaves; }
+int serve_max_angles() { return kServeMaxAngles; }
+
+hipError_t serve_occupancy(size_t lds_bytes, int *blocks_per_cu) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_serve_beamform,
+                                                      kWave * kServeWaves, lds_bytes);
+}
+
+hipError_t launch_i16_to_f16(void *buf, size_t n, hipStream_t stream) {
+  const int threads = 256;
+  const int blocks = (int)std::min<size_t>((n + threads - 1) / threads, 2048);
+  hipLaunchKernelGGL(k_i16_to_f16, dim3(blocks), dim3(threads), 0, stream, buf, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_serve(const FramePlan *plans, const PostPlan *post, const ActiveList &al,
+                        int *counter, int blocks, size_t lds, int max_nz, hipStream_t stream) {
+  hipLaunchKernelGGL(k_serve_reset, dim3((al.n + 255) / 256), dim3(256), 0, stream, counter,
+                     post, al);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int tiles = al.tile0[al.n];
+  hipLaunchKernelGGL(k_serve_beamform, dim3(std::max(1, std::min(blocks, tiles))),
+                     dim3(kWave * kServeWaves), lds, stream, plans, al, counter);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (al.col0[al.n] > 0) {
+    const size_t plds = (size_t)max_nz * sizeof(float2) + (size_t)(max_nz / 2) * sizeof(float2);
+    hipLaunchKernelGGL(k_serve_postz, dim3(al.col0[al.n]), dim3(dev::kPostThreads), plds, stream,
+                       post, al);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (al.log0[al.n] > 0) {
+    hipLaunchKernelGGL(k_serve_logc, dim3(al.log0[al.n]), dim3(256), 0, stream, post, al);
+    e = hipGetLastError();
+  }
+  return e;
+}
+
+}  // namespace pwbf

@@ -237,6 +237,51 @@ def test_batch_create_rejects_before_touching_the_device():
     assert L.pwbf_batch_destroy(None) == 0
 
 
+def _probe(g, mode=_abi.DAS, angle=-1, env=1, log=1, slots=2, reserved=0):
+    return _abi.Probe(ctypes.pointer(g.s) if g is not None else None, mode, angle, env, log,
+                      slots, reserved)
+
+
+def _server_create(probes, budget=0, max_queue=0):
+    L = _abi.lib()
+    arr = (_abi.Probe * max(1, len(probes)))(*probes)
+    h = ctypes.c_void_p()
+    rc = L.pwbf_server_create(arr, len(probes), budget, max_queue, ctypes.byref(h))
+    assert not h.value
+    return rc, L.pwbf_last_error().decode()
+
+
+def test_server_create_rejects_before_touching_the_device():
+    g = GeometryArg(config_c1())
+    ok = _probe(g)
+    assert _server_create([])[0] == _abi.E_INVALID
+    assert _server_create([ok], max_queue=-1)[0] == _abi.E_INVALID
+    assert _server_create([ok, _probe(g, reserved=1)])[0] == _abi.E_INVALID
+    assert _server_create([_probe(g, slots=65)])[0] == _abi.E_INVALID
+    assert _server_create([_probe(g, env=2)])[0] == _abi.E_INVALID
+    assert _server_create([_probe(None)])[0] == _abi.E_INVALID
+    assert _server_create([_probe(g, mode=7)])[0] == _abi.E_INVALID
+    assert _server_create([_probe(g, angle=1)])[0] == _abi.E_INVALID
+    rc, msg = _server_create([ok, _probe(GeometryArg(config_c1().replace(
+        angles_deg=tuple(range(-10, 10)))))])
+    assert rc == _abi.E_UNSUPPORTED and "16 angles" in msg and "probe 1" in msg
+    rc, msg = _server_create([_probe(GeometryArg(config_c1().replace(nz=300)))])
+    assert rc == _abi.E_UNSUPPORTED and "power of two" in msg
+    slot = 64 * 2048 * 2 + 3 * 128 * 256 * 4 + 256  # FP16 RF, rf/env/log planes, frame max
+    rc, msg = _server_create([ok], budget=slot - 1)
+    assert rc == _abi.E_INVALID and f"needs {slot} bytes" in msg
+    L = _abi.lib()
+    assert L.pwbf_server_create(None, 1, 0, 0, None) == _abi.E_INVALID
+    rid = ctypes.c_uint64()
+    assert L.pwbf_server_submit(None, 0, FAKE, -1.0, ctypes.byref(rid)) == _abi.E_INVALID
+    n = ctypes.c_int32()
+    assert L.pwbf_server_poll(None, None, 1, ctypes.byref(n), 0) == _abi.E_INVALID
+    assert L.pwbf_server_release(None, 1) == _abi.E_INVALID
+    assert L.pwbf_server_stats_get(None, None) == _abi.E_INVALID
+    assert L.pwbf_server_now(None) == 0.0
+    assert L.pwbf_server_destroy(None) == 0
+
+
 def test_tune_argument_errors():
     L = _abi.lib()
     g = GeometryArg(config_c1())
