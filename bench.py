@@ -38,16 +38,32 @@ HBM_PEAK = 8e12
 # sample difference, interpolation FMA, accumulate = 6; per (pixel, channel):
 # receive offset, squared distance, square root, aperture ratio, cosine, weight
 # FMA, window test, weight select, weighted accumulate = 9; per (pixel, angle):
-# the transmit delay, 2.
+# the transmit delay, 2. Only (pixel, channel) pairs inside the receive aperture
+# (nonzero apodization weight) count: the others add exactly zero to the sum.
 OPS_PER_GATHER, OPS_PER_PIX_CH, OPS_PER_PIX_ANGLE = 6, 9, 2
-KERNEL_SOURCES = ["paper_2311_00482_amd/csrc/beamform.hip", "paper_2311_00482_amd/csrc/plan.h"]
+KERNEL_SOURCES = ["paper_2311_00482_amd/csrc/beamform.hip",
+                  "paper_2311_00482_amd/csrc/beamform_device.h",
+                  "paper_2311_00482_amd/csrc/plan.h"]
 COUNTERS = os.path.join(ROOT, "profiles", "k_beamform_c3_compound_f32.counters.json")
+
+
+def aperture_pairs(g) -> int:
+    """(pixel, channel) pairs with a nonzero apodization weight: |x - x_e| < z / (2 F#)."""
+    if g.apod == "none":
+        return g.nx * g.nz * g.n_channels
+    xe = np.sort(np.asarray(g.elem_x, dtype=np.float64))
+    h = np.maximum(g.z_pix, 0.0) / (2.0 * g.f_number)
+    X = g.x_pix[:, None]
+    hi = np.searchsorted(xe, (X + h[None, :]).ravel(), "left")
+    lo = np.searchsorted(xe, (X - h[None, :]).ravel(), "right")
+    return int(np.maximum(hi - lo, 0).sum())
 
 
 def algorithmic_ops(g) -> float:
     P = g.nx * g.nz
-    return float(P * g.n_channels * g.n_angles * OPS_PER_GATHER
-                 + P * g.n_channels * OPS_PER_PIX_CH + P * g.n_angles * OPS_PER_PIX_ANGLE)
+    pairs = aperture_pairs(g)
+    return float(pairs * g.n_angles * OPS_PER_GATHER + pairs * OPS_PER_PIX_CH
+                 + P * g.n_angles * OPS_PER_PIX_ANGLE)
 
 
 def kernel_source_hash() -> str:
@@ -114,11 +130,111 @@ def cpu_baseline(g, rf_master, budget_s: float):
             "frames_per_s_equiv": gathers / dt / g.gathers}
 
 
+def systems(dev, torch, steps: int, warmup: int) -> dict:
+    """Single-frame FP32 against batched and served FP16 on the same GPU.
+
+    The RF is the 11-angle frame quantised to 10-bit int16, which FP16 holds
+    exactly, so every form computes on identical sample values (equal accuracy
+    by construction; the batched planes are checked against the single-frame
+    ones). Batched: B frames of the workload (the frame rolled along samples so
+    each is distinct) in one graph-captured persistent launch. Served: four
+    probes (1 angle 64 ch 256x512; 5 angles 128 ch 512x512; the 11-angle
+    1024x1024 workload; DMAS 64 ch 512x512) under Poisson arrivals, int16 RF
+    uploaded from pinned host memory per request; latency = done - arrival.
+    """
+    from paper_2311_00482_amd import (Batch, FrameSpec, GeometryArg, ProbeSpec, PwbfError,
+                                      Server, beamform)
+    from synth import config_c3, config_c5_probes, make_frame
+
+    gs = config_c3()
+    g = GeometryArg(gs)
+    want = ("rf", "env", "log")
+    i16 = torch.from_numpy(make_frame(gs, 1003, "c3", quantize=True)["i16"])
+
+    def planes():
+        return {k: torch.empty((g.nx, g.nz), dtype=torch.float32, device=dev) for k in want}
+
+    out32 = planes()
+    ws = torch.empty(4096, dtype=torch.uint8, device=dev)
+    rf32 = i16.to(torch.float32).to(dev)
+    wall32, lat32, _ = time_steps(
+        lambda: beamform(g, rf32, "das", -1, want=want, out=out32, workspace=ws),
+        steps, warmup, torch)
+    res = {"single_frame_f32": {"frames_per_s": steps / wall32,
+                                "p50_ms": float(np.percentile(lat32, 50)),
+                                "p99_ms": float(np.percentile(lat32, 99))}}
+
+    B = 8
+    frames = [FrameSpec(g, torch.roll(i16, 17 * k, dims=2).to(torch.float16).to(dev), "das", -1,
+                        planes()) for k in range(B)]
+    batch = Batch(frames)
+    nb = max(10, steps // B)
+    wallb, latb, _ = time_steps(batch.launch, nb, max(2, warmup // B), torch)
+    dev_max = max(float((frames[0].out[k] - out32[k]).abs().max()
+                        / out32[k].abs().max().clamp_min(1e-30)) for k in ("rf", "env"))
+    res["batched_f16"] = {"frames_per_launch": B, "frames_per_s": B * nb / wallb,
+                          "ms_per_launch": float(np.percentile(latb, 50)),
+                          "max_rel_diff_vs_single_f32": dev_max}
+    batch.close()
+    del frames
+
+    specs = config_c5_probes()
+    hosts = []
+    for k, sp in enumerate(specs):
+        kind = "c3" if sp.geom.name == "probe_c" else "scaled"
+        hosts.append(torch.from_numpy(make_frame(sp.geom, sp.seed, kind, quantize=True)["i16"])
+                     .pin_memory())
+    srv = Server([ProbeSpec(sp.geom, sp.mode, -1, want, 8, bandpass=(sp.mode == "dmas"))
+                  for sp in specs])
+    rng = np.random.default_rng(42)
+    served = []
+    try:
+        for rate in (500.0, 2000.0, 5000.0):
+            n = int(rate * 1.0)
+            arrivals = np.cumsum(rng.exponential(1.0 / rate, n))
+            which = rng.integers(0, len(specs), n)
+            before = srv.stats()
+            t0 = srv.now() + 0.01
+            lat, k, accepted = [], 0, 0
+            deadline = time.time() + 60
+            while k < n or len(lat) < accepted:
+                if time.time() > deadline:
+                    raise RuntimeError(f"serving run at {rate}/s did not drain")
+                now = srv.now()
+                while k < n and t0 + arrivals[k] <= now:
+                    try:
+                        srv.submit(int(which[k]), hosts[which[k]], t0 + arrivals[k])
+                        accepted += 1
+                    except PwbfError as e:  # a full probe queue drops the request
+                        if e.code != -5:
+                            raise
+                    k += 1
+                for r in srv.poll(64, wait_ms=0 if k < n else 5):
+                    lat.append(r.t_done - r.t_arrival)
+                    srv.release(r.id)
+            wall = srv.now() - t0
+            after = srv.stats()
+            served.append({"offered_per_s": rate, "requests": n,
+                           "completed_per_s": len(lat) / wall,
+                           "p50_ms": float(np.percentile(lat, 50) * 1e3),
+                           "p99_ms": float(np.percentile(lat, 99) * 1e3),
+                           "mean_batch": (after["completed"] - before["completed"])
+                           / max(1, after["batches"] - before["batches"]),
+                           "rejected": after["rejected"] - before["rejected"]})
+            print(f"[bench] served {rate:.0f}/s: {served[-1]}", file=sys.stderr, flush=True)
+    finally:
+        srv.close()
+    res["served_f16"] = {"probes": [sp.geom.name for sp in specs], "runs": served}
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=300)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-systems", action="store_true",
+                    help="skip the batched and served FP16 measurements")
+    ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0,
                     help="seconds of oracle work for the CPU baseline sample")
@@ -136,13 +252,14 @@ def main():
 
     import torch
 
-    from paper_2311_00482_amd import beamform, describe_plan
+    from paper_2311_00482_amd import GeometryArg, beamform, describe_plan
     from synth import config_c3, make_frame
 
     dev = torch.device("cuda:0")
-    g = config_c3()
-    print(f"[bench] simulating {g.name}", file=sys.stderr, flush=True)
-    fr = make_frame(g, 1003, "c3", quantize=False)
+    g = GeometryArg(config_c3())  # marshalled once, as a caller streaming frames would
+    gs = config_c3()
+    print(f"[bench] simulating {gs.name}", file=sys.stderr, flush=True)
+    fr = make_frame(gs, 1003, "c3", quantize=False)
     rf32 = torch.from_numpy(fr["f32"]).to(dev)
     rf16 = torch.from_numpy(fr["f16"]).to(dev)
     want = ("rf", "env", "log")
@@ -179,9 +296,9 @@ def main():
     _, _, kspan = time_steps(kernel_only, args.steps, args.warmup, torch)
     k_ms = kspan / args.steps
 
-    gathers = g.gathers
+    gathers = gs.gathers
     value = gathers * args.steps / wall / 1e9
-    ops = algorithmic_ops(g)
+    ops = algorithmic_ops(gs)
     achieved = ops / (k_ms * 1e-3)
     traffic = traffic_bytes()
     plan = describe_plan(g, "das", -1)
@@ -200,8 +317,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "compound DAS, 11 angles -10..10 deg, 128 ch x 4096 samples, "
                                "1024x1024 pixels, FP32-stored RF, RF + envelope + log per frame",
-                   "rf_storage": "f32", "pixels": g.nx * g.nz, "channels": g.n_channels,
-                   "angles": g.n_angles, "samples": g.n_samples,
+                   "rf_storage": "f32", "pixels": gs.nx * gs.nz, "channels": gs.n_channels,
+                   "angles": gs.n_angles, "samples": gs.n_samples,
                    "tile": {k: plan[k] for k in ("cpw", "lz", "wz", "wx", "tile_z", "tile_x",
                                                   "chunk", "win")}},
         "frames_per_s": args.steps / wall,
@@ -221,9 +338,12 @@ def main():
                                      "latency_ms": {"p50": float(np.percentile(lat16, 50)),
                                                     "p99": float(np.percentile(lat16, 99))}}},
     }
+    if not args.no_systems:
+        print("[bench] batched and served FP16 vs single-frame FP32", file=sys.stderr, flush=True)
+        line["systems"] = systems(dev, torch, args.steps, args.warmup)
     if not args.no_cpu_baseline:
         print("[bench] timing the oracle on the host", file=sys.stderr, flush=True)
-        cb = cpu_baseline(g, fr["master"], args.cpu_budget)
+        cb = cpu_baseline(gs, fr["master"], args.cpu_budget)
         cb["host_cores_available"] = os.cpu_count()
         line["cpu_baseline"] = cb
     print(json.dumps(line))

@@ -10,7 +10,8 @@
 //
 // For every chunk of channels the block stages, per (channel, angle), a window
 // of RF samples that covers every delay of every pixel of the tile, as pairs
-// (u[n], u[n+1] - u[n]) so one 8-byte LDS read and one FMA interpolate. Windows
+// (DAS: the line through u[n] and u[n+1] in the delay coordinate; DMAS: u[n]
+// and u[n+1] - u[n]) so one 8-byte LDS read and one FMA interpolate. Windows
 // start at floor(min transmit delay) - 1 + floor(min receive delay) - 1 over the
 // tile rectangle; outside [0, n_samples) the record is zero (the zero-extended
 // signal of the definition).
@@ -18,9 +19,9 @@
 // Per pixel the transmit delays of all angles are kept in registers; per
 // (pixel, channel) the receive delay (one square root) and the apodization
 // weight are computed once and reused for every angle. Per (pixel, channel,
-// angle) the gather costs an add, a floor, a fraction, an address, one LDS read
-// and two accumulate operations. DMAS adds a square root and the signed-root
-// accumulation per gather.
+// angle) the DAS gather costs an add, a floor, an address, one LDS read and two
+// accumulate operations. DMAS adds the fraction, a square root and the
+// signed-root accumulation per gather.
 
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
@@ -48,32 +49,43 @@ struct RfT<kF32> {
   static __device__ __forceinline__ float f(T v) { return v; }
 };
 
-// Stage the windows of `rows` = chunk * A (channel, angle) pairs, one row per wavefront.
-template <int DT>
-__device__ __forceinline__ void stage_windows(const FramePlan &P, int e0, const int *s_lt,
-                                              const int *s_lr, float2 *s_pairs) {
+// Stage the windows of channels e0 .. e0 + nch - 1: nch * A rows (channel c,
+// angle a) of win entries, flattened over all lanes of the block. Entry j of a
+// row covers samples n = LT_a + LR_c + j and n + 1, i.e. kernel delays s in
+// [m, m + 1) with m = j - off_t - off_r, and holds, with du = u[n+1] - u[n],
+//   DAS:  the line through both samples in s:  (u[n] - m du, du),
+//         so the interpolated value is b + s du (no fraction needed);
+//   DMAS: (u[n], du), interpolated as u[n] + frac(s) du, which keeps the
+//         rounding of v small where the signed square root is steep.
+// Samples outside [0, n_samples) read as zero; rows of channels >= e_end are zero.
+template <int DT, int MODE>
+__device__ __forceinline__ void stage_windows(const FramePlan &P, int e0, int nch, int e_end,
+                                              const int *s_lt, const int *s_lr, float2 *s_pairs) {
   using R = RfT<DT>;
   const typename R::T *rf = (const typename R::T *)P.rf;
-  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
-  const int nwaves = blockDim.x / kWave;
   const int A = P.n_angles, N = P.n_channels, Ns = P.n_samples, win = P.win;
-  const int rows = P.chunk * A;
-  for (int r = wave; r < rows; r += nwaves) {
-    const int c = r / A, a = r - c * A;
+  const int off = P.off_t + P.off_r;
+  const int total = nch * A * win;  // at most kMaxLdsBytes / 8 = 2^13 entries
+  // row = t / win and c = row / A through a float reciprocal: (t + 0.5) / win
+  // lies at least 0.5 / win from an integer, and for t < 2^13 the product errs
+  // by under 1e-3 / win, so truncation yields the exact quotient.
+  const float rw = __builtin_amdgcn_rcpf((float)win), ra = __builtin_amdgcn_rcpf((float)A);
+  for (int t = threadIdx.x; t < total; t += blockDim.x) {
+    const int row = (int)(((float)t + 0.5f) * rw);
+    const int j = t - row * win;
+    const int c = (int)(((float)row + 0.5f) * ra);
+    const int a = row - c * A;
     const int e = e0 + c;
-    float2 *dst = s_pairs + (size_t)r * win;
-    if (e < N) {
-      const int base = s_lt[a] + s_lr[c];
+    float2 v = make_float2(0.f, 0.f);
+    if (e < e_end) {
+      const int n = s_lt[a] + s_lr[c] + j;
       const typename R::T *src = rf + ((size_t)a * N + e) * Ns;
-      for (int j = lane; j < win; j += kWave) {
-        const int n = base + j;
-        const float u0 = (n >= 0 && n < Ns) ? R::f(src[n]) : 0.f;
-        const float u1 = (n + 1 >= 0 && n + 1 < Ns) ? R::f(src[n + 1]) : 0.f;
-        dst[j] = make_float2(u0, u1 - u0);
-      }
-    } else {
-      for (int j = lane; j < win; j += kWave) dst[j] = make_float2(0.f, 0.f);
+      const float u0 = (unsigned)n < (unsigned)Ns ? R::f(src[n]) : 0.f;
+      const float u1 = (unsigned)(n + 1) < (unsigned)Ns ? R::f(src[n + 1]) : 0.f;
+      const float du = u1 - u0;
+      v = make_float2(MODE == kDas ? fmaf((float)(off - j), du, u0) : u0, du);
     }
+    s_pairs[t] = v;
   }
 }
 
@@ -185,6 +197,35 @@ __device__ __forceinline__ void process_tile(const FramePlan &P, int tz, int tx,
   const float cp = fmaf(2.f * Zqf, dz, fmaf(dx, dx, dz * dz));
   const float dx2 = 2.f * dx;
 
+  // Active aperture of the tile. A channel whose apodization weight is zero at
+  // every pixel of the tile adds exactly nothing to any sum (w * acc with w = 0
+  // and finite acc), so the channel loop runs over the hull [e_lo, e_hi) of the
+  // channels that may reach the tile: distance from x_e to the tile's lateral
+  // span below Z_max / (2 F#). The test carries a 1e-3 relative margin, so
+  // float rounding can only add a channel, never drop one; outputs are those
+  // of the loop over all channels.
+  __shared__ int s_erange[2 * kMaxWavesPerBlock];
+  if (P.apod != kNone) {
+    const float zmax = Zqf + dzhi;
+    int lo = N, hi = 0;
+    for (int e = tid; e < N; e += blockDim.x) {
+      const float dq = ff_f(ff_add(Xq, ff_neg({P.xe[e], P.xel[e]})));
+      const float ddx = fmaxf(fmaxf(dq + dxlo, -(dq + dxhi)), 0.f);
+      if (zmax > 0.f && ddx * P.ap_k < zmax * 1.001f) {
+        lo = min(lo, e);
+        hi = max(hi, e + 1);
+      }
+    }
+    for (int off = 1; off < kWave; off <<= 1) {
+      lo = min(lo, __shfl_xor(lo, off));
+      hi = max(hi, __shfl_xor(hi, off));
+    }
+    if (lane == 0) {
+      s_erange[2 * wave] = lo;
+      s_erange[2 * wave + 1] = hi;
+    }
+  }
+
   // Per-angle tile constants: window origin LT = floor(min_tile tx) - 1 and
   // tx(q) - LT. tx is linear, so its tile minimum is at a corner.
   for (int a = tid; a < A; a += blockDim.x) {
@@ -197,6 +238,17 @@ __device__ __forceinline__ void process_tile(const FramePlan &P, int tz, int tx,
     s_lt[a] = (int)lt;
   }
   __syncthreads();
+  int e_lo = 0, e_hi = N;
+  if (P.apod != kNone) {
+    e_hi = 0;
+    e_lo = N;
+    for (int w = 0; w < (int)(blockDim.x / kWave); ++w) {
+      e_lo = min(e_lo, s_erange[2 * w]);
+      e_hi = max(e_hi, s_erange[2 * w + 1]);
+    }
+    e_lo = __builtin_amdgcn_readfirstlane(e_lo);
+    e_hi = __builtin_amdgcn_readfirstlane(e_hi);
+  }
   float txl[AM];
 #pragma unroll
   for (int a = 0; a < AM; ++a)
@@ -208,12 +260,14 @@ __device__ __forceinline__ void process_tile(const FramePlan &P, int tz, int tx,
 #pragma unroll
   for (int a = 0; a < (MODE == kDmas ? AM : 1); ++a) S[a] = 0.f;
 
-  for (int e0 = 0; e0 < N; e0 += chunk) {
-    if (e0 > 0) __syncthreads();  // the previous chunk's windows have been read
+  for (int e0 = e_lo; e0 < e_hi; e0 += chunk) {
+    if (e0 > e_lo) __syncthreads();  // the previous chunk's windows have been read
+    const int cnt = min(chunk, e_hi - e0);                   // channels of this chunk
+    const int cnt_pad = ONEGRP ? cnt : (cnt + cpw - 1) / cpw * cpw;  // rows read
     // Per-channel tile constants: window origin LR = floor(min_tile rx) - 1 (the
     // tile point nearest the element), the reference delay rx(q) in
     // float-float, and the terms of the receive-delay difference.
-    for (int c = tid; c < chunk; c += blockDim.x) {
+    for (int c = tid; c < cnt_pad; c += blockDim.x) {
       const int e = min(e0 + c, N - 1);
       const ff xe = {P.xe[e], P.xel[e]};
       const ff dq = ff_add(Xq, ff_neg(xe));
@@ -232,15 +286,15 @@ __device__ __forceinline__ void process_tile(const FramePlan &P, int tz, int tx,
     }
     __syncthreads();
     if (P.dtype == kI16)
-      stage_windows<kI16>(P, e0, s_lt, s_lr, s_pairs);
+      stage_windows<kI16, MODE>(P, e0, cnt_pad, e_hi, s_lt, s_lr, s_pairs);
     else if (P.dtype == kF16)
-      stage_windows<kF16>(P, e0, s_lt, s_lr, s_pairs);
+      stage_windows<kF16, MODE>(P, e0, cnt_pad, e_hi, s_lt, s_lr, s_pairs);
     else
-      stage_windows<kF32>(P, e0, s_lt, s_lr, s_pairs);
+      stage_windows<kF32, MODE>(P, e0, cnt_pad, e_hi, s_lt, s_lr, s_pairs);
     __syncthreads();
 
     const int wstride = win * (int)sizeof(float2);  // bytes between angle windows
-    for (int k = 0; k < chunk; k += cpw) {
+    for (int k = 0; k < cnt; k += cpw) {
       const int c = ONEGRP ? k : k + grp;
       const float4 ch = s_ch[c];
       // receive delay relative to the window origin, as a difference from rx(q)
@@ -251,16 +305,15 @@ __device__ __forceinline__ void process_tile(const FramePlan &P, int tz, int tx,
       // delays are centred: entry n of the window is read as n + off_t + off_r
       const char *wb = (const char *)(s_pairs + (size_t)c * A * win + P.off_t + P.off_r);
       if constexpr (MODE == kDas) {
-        float acc = 0.f;
+        float acc = -0.f;  // x + (-0) == x for every x: the first add folds away
 #pragma unroll
         for (int a = 0; a < AM; ++a) {
           if (!PRED || a < A) {
             const float s = txl[a] + rxl;
             const int n = floor_i32(s);
-            const float f = __builtin_amdgcn_fractf(s);
             const float2 p = *(const float2 *)(wb + a * wstride + (n << 3));
-            acc += p.x;
-            acc = fmaf(f, p.y, acc);
+            acc += p.x;  // the entry's line at s: b + s du
+            acc = fmaf(s, p.y, acc);
           }
         }
         total = fmaf(w, acc, total);

@@ -17,6 +17,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 
 namespace pwbf {
 
@@ -208,21 +209,13 @@ static int fit_tile(const pwbf_geometry *g, pwbf_tile t, FramePlan *P, std::stri
   const size_t fixed = kLdsAngleBytes + 16;
   int chunk = t.chunk;
   if (chunk == 0) {
-    int fit = (int)((kMaxLdsBytes - fixed) / per_channel);
-    // as many channels as fit, split evenly over the array
-    int nch = (g->n_channels + t.cpw - 1) / t.cpw * t.cpw;
-    if (fit >= nch) {
-      chunk = nch;
-    } else {
-      int nchunks = (nch + fit - 1) / std::max(fit, 1);
-      chunk = (nch + nchunks - 1) / nchunks;
-      chunk = (chunk + t.cpw - 1) / t.cpw * t.cpw;
-      while (chunk > fit && chunk > t.cpw) chunk -= t.cpw;
-    }
+    // as many channels as the default budget holds (each tile walks only its
+    // own active aperture, so the chunks start wherever that begins)
+    const int fit = (int)((kDefaultLdsBytes - fixed) / per_channel) / t.cpw * t.cpw;
+    const int nch = (g->n_channels + t.cpw - 1) / t.cpw * t.cpw;
+    chunk = std::max(t.cpw, std::min(fit, nch));
   }
   P->chunk = chunk;
-  while (t.chunk == 0 && P->chunk > t.cpw && plan_lds_bytes(*P) > (size_t)kMaxLdsBytes)
-    P->chunk -= t.cpw;
   if (P->chunk < t.cpw || plan_lds_bytes(*P) > (size_t)kMaxLdsBytes)
     return fail(err, PWBF_E_UNSUPPORTED,
                 "tile needs %zu bytes of LDS per block (limit %d); use a smaller tile",
@@ -230,8 +223,9 @@ static int fit_tile(const pwbf_geometry *g, pwbf_tile t, FramePlan *P, std::stri
   return PWBF_OK;
 }
 
-int plan_frame(const pwbf_geometry *g, int dtype, int mode, int angle, const pwbf_tile *tile_in,
-               FramePlan *P, std::string *err, int waves) {
+static int plan_frame_uncached(const pwbf_geometry *g, int dtype, int mode, int angle,
+                               const pwbf_tile *tile_in, FramePlan *P, std::string *err,
+                               int waves) {
   int rc = validate_geometry(g, err);
   if (rc) return rc;
   if (dtype != kI16 && dtype != kF16 && dtype != kF32)
@@ -327,6 +321,64 @@ int plan_frame(const pwbf_geometry *g, int dtype, int mode, int angle, const pwb
   P->n_tiles = P->tiles_z * P->tiles_x;
   P->tiles_per_xcd = (P->n_tiles + 7) / 8;
   return PWBF_OK;
+}
+
+// Plans are a pure function of the geometry (scalars and arrays), the call
+// shape and the tuning table, so the last few successful ones are kept, keyed
+// by those bytes; a hit skips validation and planning (a few microseconds of
+// host time per call, which matters when a frame takes a few hundred).
+namespace {
+
+std::string plan_key(const pwbf_geometry *g, int dtype, int mode, int angle,
+                     const pwbf_tile *tile, int waves) {
+  std::string k;
+  if (!g || g->n_channels < 1 || g->n_channels > kMaxChannels || g->n_angles < 1 ||
+      g->n_angles > kMaxAngles || !g->elem_x || !g->angle_rad)
+    return k;  // not cacheable: the uncached path reports the error
+  pwbf_geometry s = *g;
+  s.elem_x = nullptr;
+  s.angle_rad = nullptr;
+  s.t0 = nullptr;
+  const int32_t head[7] = {dtype, mode, angle, waves, g->t0 ? 1 : 0, tile ? 1 : 0,
+                           (int32_t)tune_generation()};
+  k.reserve(sizeof s + sizeof head + sizeof(pwbf_tile) +
+            sizeof(double) * (g->n_channels + 2 * g->n_angles));
+  k.append((const char *)&s, sizeof s);
+  k.append((const char *)head, sizeof head);
+  if (tile) k.append((const char *)tile, sizeof *tile);
+  k.append((const char *)g->elem_x, sizeof(double) * g->n_channels);
+  k.append((const char *)g->angle_rad, sizeof(double) * g->n_angles);
+  if (g->t0) k.append((const char *)g->t0, sizeof(double) * g->n_angles);
+  return k;
+}
+
+constexpr int kPlanCacheSize = 16;
+std::mutex g_plan_mu;
+std::string g_plan_keys[kPlanCacheSize];
+FramePlan g_plans[kPlanCacheSize];
+int g_plan_next = 0;
+
+}  // namespace
+
+int plan_frame(const pwbf_geometry *g, int dtype, int mode, int angle, const pwbf_tile *tile_in,
+               FramePlan *P, std::string *err, int waves) {
+  const std::string key = plan_key(g, dtype, mode, angle, tile_in, waves);
+  if (!key.empty()) {
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    for (int i = 0; i < kPlanCacheSize; ++i)
+      if (g_plan_keys[i] == key) {
+        *P = g_plans[i];
+        return PWBF_OK;
+      }
+  }
+  const int rc = plan_frame_uncached(g, dtype, mode, angle, tile_in, P, err, waves);
+  if (rc == PWBF_OK && !key.empty()) {
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    g_plan_keys[g_plan_next] = key;
+    g_plans[g_plan_next] = *P;
+    g_plan_next = (g_plan_next + 1) % kPlanCacheSize;
+  }
+  return rc;
 }
 
 int build_plan(const pwbf_geometry *g, const void *rf, int dtype, int mode, int angle,

@@ -23,6 +23,9 @@ constexpr int kMaxChannels = 256;
 constexpr int kWave = 64;
 constexpr int kMaxWavesPerBlock = 8;
 constexpr int kMaxLdsBytes = 64 * 1024;
+// Default LDS budget of a block: three blocks fit the 160 KB of a gfx950 CU
+// together with their static LDS, at 512-byte allocation granularity.
+constexpr int kDefaultLdsBytes = 52 * 1024;
 constexpr int kMaxNzPost = 4096;
 
 enum Dtype : int32_t { kI16 = 0, kF16 = 1, kF32 = 2 };

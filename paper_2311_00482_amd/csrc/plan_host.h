@@ -30,6 +30,7 @@ void tune_store(const std::string &key, const pwbf_tile &t);
 int tune_save(const char *path, std::string *err);
 int tune_load(const char *path, std::string *err);
 void tune_clear();
+uint32_t tune_generation();  // changes whenever the table does
 int build_post_plan(const pwbf_geometry *g, const pwbf_outputs *o, void *ws, PostPlan *Q);
 bool post_needed(const pwbf_outputs *o);
 

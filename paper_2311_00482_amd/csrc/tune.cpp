@@ -4,6 +4,7 @@
 // mode, storage type, angle count, channels, samples, grid size and pitches
 // (in samples), steering extent, and whether the batch kernel's fixed
 // 8-wavefront blocks are required.
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -18,7 +19,10 @@ namespace pwbf {
 namespace {
 std::mutex g_mu;
 std::map<std::string, pwbf_tile> g_table;
+std::atomic<uint32_t> g_generation{0};  // bumped on every change of the table
 }  // namespace
+
+uint32_t tune_generation() { return g_generation.load(); }
 
 std::string shape_key(const pwbf_geometry *g, int dtype, int mode, int angle, int waves) {
   double scale = g->fs / g->c;
@@ -42,6 +46,7 @@ bool tune_lookup(const std::string &key, pwbf_tile *t) {
 void tune_store(const std::string &key, const pwbf_tile &t) {
   std::lock_guard<std::mutex> lk(g_mu);
   g_table[key] = t;
+  ++g_generation;
 }
 
 int tune_save(const char *path, std::string *err) {
@@ -82,12 +87,14 @@ int tune_load(const char *path, std::string *err) {
   fclose(f);
   std::lock_guard<std::mutex> lk(g_mu);
   for (const auto &kv : add) g_table[kv.first] = kv.second;
+  ++g_generation;
   return PWBF_OK;
 }
 
 void tune_clear() {
   std::lock_guard<std::mutex> lk(g_mu);
   g_table.clear();
+  ++g_generation;
 }
 
 }  // namespace pwbf
