@@ -136,7 +136,7 @@ int pwbf_describe_plan(const pwbf_geometry *g, int32_t mode, int32_t angle,
   info->tiles_z = P.tiles_z;
   info->tiles_x = P.tiles_x;
   info->threads_per_block = pwbf::kWave * P.wz * P.wx;
-  info->blocks = 8 * P.tiles_per_xcd;
+  info->blocks = P.n_tiles;
   info->n_angles_used = P.n_angles;
   info->lds_bytes = (int64_t)pwbf::plan_lds_bytes(P);
   info->X0 = P.X0;

@@ -1,9 +1,11 @@
 // Single-frame launch of the beamformer: one block per pixel tile. The tile
 // body (staging, delays, gather, reductions) lives in beamform_device.h.
 //
-// Tiles are mapped to blocks XCD-aware: consecutive block ids go round-robin
-// to the 8 XCDs, so block b takes tile (b % 8) * ceil(T/8) + b / 8 and each XCD
-// walks a contiguous range of tile rows, keeping its L2 working set local.
+// Tiles run deepest row first: a tile's cost grows with the receive aperture,
+// which widens with depth, so the costliest tiles start first and the cheap
+// shallow ones fill the end of the launch. Consecutive block ids go
+// round-robin to the 8 XCDs, so every XCD takes every 8th tile of each tile
+// row: an equal share of every depth.
 #include <hip/hip_runtime.h>
 
 #include "beamform_device.h"
@@ -18,17 +20,16 @@ template <int AM, bool PRED, int MODE, bool ONEGRP>
 __global__ void __launch_bounds__(kWave * kMaxWavesPerBlock) k_beamform(const FramePlan P) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int b = blockIdx.x;
-  const int L = (b & 7) * P.tiles_per_xcd + (b >> 3);
-  if (L >= P.n_tiles) return;
   if (P.ws_max && b == 0 && threadIdx.x == 0) *P.ws_max = 0u;
-  const int tz = L / P.tiles_x, tx = L - tz * P.tiles_x;
+  const int q = b / P.tiles_x;
+  const int tz = P.tiles_z - 1 - q, tx = b - q * P.tiles_x;
   process_tile<AM, PRED, MODE, ONEGRP>(P, tz, tx, smem);
 }
 
 template <int AM, bool PRED>
 hipError_t launch_am(const FramePlan &P, hipStream_t stream) {
   const dim3 block(kWave * P.wz * P.wx);
-  const dim3 grid(8 * P.tiles_per_xcd);
+  const dim3 grid(P.n_tiles);
   const size_t lds = plan_lds_bytes(P);
   const bool one = P.cpw == 1;
   if (P.mode == kDas) {

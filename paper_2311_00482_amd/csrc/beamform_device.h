@@ -70,22 +70,25 @@ __device__ __forceinline__ void stage_windows(const FramePlan &P, int e0, int nc
   // lies at least 0.5 / win from an integer, and for t < 2^13 the product errs
   // by under 1e-3 / win, so truncation yields the exact quotient.
   const float rw = __builtin_amdgcn_rcpf((float)win), ra = __builtin_amdgcn_rcpf((float)A);
+  const float hw = 0.5f * rw, ha = 0.5f * ra;
+  const int last = min(e_end, N) - 1;  // channels past it stage zeros
   for (int t = threadIdx.x; t < total; t += blockDim.x) {
-    const int row = (int)(((float)t + 0.5f) * rw);
+    const int row = (int)fmaf((float)t, rw, hw);
     const int j = t - row * win;
-    const int c = (int)(((float)row + 0.5f) * ra);
+    const int c = (int)fmaf((float)row, ra, ha);
     const int a = row - c * A;
     const int e = e0 + c;
-    float2 v = make_float2(0.f, 0.f);
-    if (e < e_end) {
-      const int n = s_lt[a] + s_lr[c] + j;
-      const typename R::T *src = rf + ((size_t)a * N + e) * Ns;
-      const float u0 = (unsigned)n < (unsigned)Ns ? R::f(src[n]) : 0.f;
-      const float u1 = (unsigned)(n + 1) < (unsigned)Ns ? R::f(src[n + 1]) : 0.f;
-      const float du = u1 - u0;
-      v = make_float2(MODE == kDas ? fmaf((float)(off - j), du, u0) : u0, du);
-    }
-    s_pairs[t] = v;
+    // sample n of (a, e); n = -2 stands for a row of zeros. Reads are clamped
+    // into the record (indices fit 32 bits: the RF holds < 2^31 samples) and
+    // samples outside [0, Ns) are replaced by zero, without branches.
+    const int n = e <= last ? s_lt[a] + s_lr[c] + j : -2;
+    const unsigned base = (unsigned)(a * N + min(e, last)) * (unsigned)Ns;
+    const int n0 = min(max(n, 0), Ns - 1), n1 = min(max(n + 1, 0), Ns - 1);
+    const float r0 = R::f(rf[base + (unsigned)n0]), r1 = R::f(rf[base + (unsigned)n1]);
+    const float u0 = (unsigned)n < (unsigned)Ns ? r0 : 0.f;
+    const float u1 = (unsigned)(n + 1) < (unsigned)Ns ? r1 : 0.f;
+    const float du = u1 - u0;
+    s_pairs[t] = make_float2(MODE == kDas ? fmaf((float)(off - j), du, u0) : u0, du);
   }
 }
 

@@ -60,8 +60,12 @@ int validate_geometry(const pwbf_geometry *g, std::string *err) {
     return fail(err, g->n_channels < 1 ? PWBF_E_INVALID : PWBF_E_UNSUPPORTED,
                 "n_channels %d outside 1..%d", g->n_channels, kMaxChannels);
   if (g->n_samples < 2) return fail(err, PWBF_E_INVALID, "n_samples %d < 2", g->n_samples);
-  if (g->n_samples > (1 << 24))
-    return fail(err, PWBF_E_UNSUPPORTED, "n_samples %d > 2^24", g->n_samples);
+  if (g->n_samples >= (1 << 24))
+    return fail(err, PWBF_E_UNSUPPORTED, "n_samples %d > 2^24 - 1", g->n_samples);
+  // sample indices into the RF array are 32-bit in the kernels
+  if ((int64_t)g->n_angles * g->n_channels * g->n_samples >= ((int64_t)1 << 31))
+    return fail(err, PWBF_E_UNSUPPORTED, "RF of %d x %d x %d samples exceeds 2^31 - 1",
+                g->n_angles, g->n_channels, g->n_samples);
   if (!g->elem_x || !g->angle_rad) return fail(err, PWBF_E_INVALID, "elem_x or angle_rad NULL");
   for (int e = 0; e < g->n_channels; ++e)
     if (!finite(g->elem_x[e])) return fail(err, PWBF_E_INVALID, "elem_x[%d] not finite", e);
@@ -150,17 +154,20 @@ int validate_outputs(const pwbf_geometry *g, const pwbf_outputs *o, void *ws, si
 // Default launch shape. Tiles are 16 pixels deep: the LDS window of a tile
 // grows as ~2 DZ TZ + DX (1 + |sin|) TX samples, which for a fixed pixel count
 // is smallest near TZ = 16 on the usual grids (dz ~ dx), and shallow tiles keep
-// the per-pixel delay offsets small, which keeps float32 delays accurate. Small
-// frames split channels across lane groups so there are enough waves.
+// the per-pixel delay offsets small, which keeps float32 delays accurate. A
+// wavefront covers 8 x 8 pixels (2 x 4 wavefronts per 16 x 32 tile): its lanes'
+// delays then span fewer window entries per gather than a 16 x 4 column
+// layout, which measured ~10% faster on gfx950. Small frames split channels
+// across lane groups so there are enough waves.
 pwbf_tile default_tile(const pwbf_geometry *g, int n_angles_used, int mode) {
   (void)mode;
   (void)n_angles_used;
   pwbf_tile t;
   int64_t pixels = (int64_t)g->nx * g->nz;
   t.cpw = pixels >= 256 * 1024 ? 1 : (pixels >= 64 * 1024 ? 2 : 4);
-  t.lz = 16;
-  t.wz = 1;
-  t.wx = 8;
+  t.lz = t.cpw == 1 ? 8 : 16;  // one group: 8 x 8 pixels per wavefront, 2 x 4 wavefronts
+  t.wz = t.cpw == 1 ? 2 : 1;
+  t.wx = t.cpw == 1 ? 4 : 8;
   t.chunk = 0;
   return t;
 }
@@ -319,7 +326,6 @@ static int plan_frame_uncached(const pwbf_geometry *g, int dtype, int mode, int 
   P->tiles_z = (g->nz + TZ - 1) / TZ;
   P->tiles_x = (g->nx + TX - 1) / TX;
   P->n_tiles = P->tiles_z * P->tiles_x;
-  P->tiles_per_xcd = (P->n_tiles + 7) / 8;
   return PWBF_OK;
 }
 

@@ -49,7 +49,7 @@ struct FramePlan {
   int32_t win;           // LDS entries per (channel, angle) window
   int32_t off_t, off_r;  // centring offsets of the transmit and receive window delays
   int32_t tile_z, tile_x;  // pixels per tile: lz * wz by lx * wx
-  int32_t tiles_z, tiles_x, n_tiles, tiles_per_xcd;
+  int32_t tiles_z, tiles_x, n_tiles, reserved_i32;
   float sa[kMaxAngles], sal[kMaxAngles];  // sin(theta_a), hi and lo
   float ca[kMaxAngles], cal[kMaxAngles];  // cos(theta_a)
   float to[kMaxAngles], tol[kMaxAngles];  // first-firing offset plus t0, samples
