@@ -195,7 +195,7 @@ def systems(dev, torch, steps: int, warmup: int) -> dict:
             which = rng.integers(0, len(specs), n)
             before = srv.stats()
             t0 = srv.now() + 0.01
-            lat, k, accepted = [], 0, 0
+            lat, parts, k, accepted = [], [], 0, 0
             deadline = time.time() + 60
             while k < n or len(lat) < accepted:
                 if time.time() > deadline:
@@ -209,15 +209,25 @@ def systems(dev, torch, steps: int, warmup: int) -> dict:
                         if e.code != -5:
                             raise
                     k += 1
-                for r in srv.poll(64, wait_ms=0 if k < n else 5):
+                got = srv.poll(64, wait_ms=0 if k < n else 5)
+                for r in got:
                     lat.append(r.t_done - r.t_arrival)
+                    parts.append((r.t_admit - r.t_arrival, r.t_launch - r.t_admit,
+                                  r.t_done - r.t_launch))
                     srv.release(r.id)
+                if not got and k < n:  # idle until close to the next arrival
+                    gap = t0 + arrivals[k] - srv.now()
+                    if gap > 2e-4:
+                        time.sleep(min(gap - 1e-4, 1e-3))
             wall = srv.now() - t0
+            pq = np.percentile(np.array(parts) * 1e3, 50, axis=0)
             after = srv.stats()
             served.append({"offered_per_s": rate, "requests": n,
                            "completed_per_s": len(lat) / wall,
                            "p50_ms": float(np.percentile(lat, 50) * 1e3),
                            "p99_ms": float(np.percentile(lat, 99) * 1e3),
+                           "p50_parts_ms": {"queue": float(pq[0]), "upload": float(pq[1]),
+                                            "gpu": float(pq[2])},
                            "mean_batch": (after["completed"] - before["completed"])
                            / max(1, after["batches"] - before["batches"]),
                            "rejected": after["rejected"] - before["rejected"]})

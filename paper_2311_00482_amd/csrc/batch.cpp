@@ -261,7 +261,11 @@ int pwbf_batch_create(const pwbf_frame *frames, int32_t n, int32_t flags, void *
     return api_set_error(PWBF_E_NOMEM, "batch workspace allocation failed");
   }
   std::vector<int2> items, post_cols, log_cols;
-  std::vector<std::pair<double, int>> order;
+  struct Work {
+    double cost;
+    int frame, tile;
+  };
+  std::vector<Work> order;
   for (int i = 0; i < n; ++i) {
     const pwbf_frame &f = frames[i];
     unsigned char *ws = b->d_ws ? b->d_ws + b->ws_off[i] : nullptr;
@@ -273,10 +277,7 @@ int pwbf_batch_create(const pwbf_frame *frames, int32_t n, int32_t flags, void *
     const pwbf::FramePlan &P = b->plans[i];
     b->sig[i] = frame_signature(f, P);
     b->lds = std::max(b->lds, (int)pwbf::plan_lds_bytes(P));
-    // cost of one tile: pixels x channels x (angles + per-channel work), DMAS ~2x
-    double cost = (double)P.tile_z * P.tile_x * P.n_channels * (P.n_angles + 2) *
-                  (P.mode == pwbf::kDmas ? 2.0 : 1.0);
-    order.push_back({-cost, i});
+    for (int t = 0; t < P.n_tiles; ++t) order.push_back({pwbf::tile_cost(f.geom, P, t), i, t});
     if (pwbf::post_needed(&f.out)) {
       b->max_nz = std::max(b->max_nz, f.geom->nz);
       for (int ix = 0; ix < f.geom->nx; ++ix) post_cols.push_back(make_int2(i, ix));
@@ -284,9 +285,10 @@ int pwbf_batch_create(const pwbf_frame *frames, int32_t n, int32_t flags, void *
         for (int ix = 0; ix < f.geom->nx; ++ix) log_cols.push_back(make_int2(i, ix));
     }
   }
-  std::stable_sort(order.begin(), order.end());
-  for (const auto &o : order)
-    for (int t = 0; t < b->plans[o.second].n_tiles; ++t) items.push_back(make_int2(o.second, t));
+  // longest tiles first over the whole batch, so the cheap ones fill the tail
+  std::stable_sort(order.begin(), order.end(),
+                   [](const Work &a, const Work &b) { return a.cost > b.cost; });
+  for (const Work &w : order) items.push_back(make_int2(w.frame, w.tile));
   b->n_items = (int)items.size();
   b->n_post_cols = (int)post_cols.size();
   b->n_log_cols = (int)log_cols.size();

@@ -4,8 +4,9 @@
 //   k_batch_reset      clears the work counter and every frame's envelope maximum
 //                      (a kernel, not a memset node, so graph replays stay exact)
 //   k_batch_beamform   persistent: every block repeatedly claims the next
-//                      (frame, tile) item of a work list sorted by cost, largest
-//                      first, and runs the tile body for that frame's plan; all
+//                      (frame, tile) item of a work list sorted by estimated tile
+//                      cost (active aperture x pixels x angles), largest first,
+//                      and runs the tile body for that frame's plan; all
 //                      waves leave when the list is exhausted
 //   k_batch_postz      one block per (frame, depth column) of frames with
 //                      post-processing

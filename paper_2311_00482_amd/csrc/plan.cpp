@@ -404,6 +404,25 @@ int build_plan(const pwbf_geometry *g, const void *rf, int dtype, int mode, int 
   return PWBF_OK;
 }
 
+int tile_active_channels(const pwbf_geometry *g, const FramePlan &P, int tile) {
+  if (g->apod == kNone) return g->n_channels;
+  const int tz = tile / P.tiles_x, tx = tile - tz * P.tiles_x;
+  const double xlo = g->x0 + (double)tx * P.tile_x * g->dx;
+  const double xhi = g->x0 + (double)(std::min((tx + 1) * P.tile_x, g->nx) - 1) * g->dx;
+  const double zmax = g->z0 + (double)(std::min((tz + 1) * P.tile_z, g->nz) - 1) * g->dz;
+  if (!(zmax > 0)) return 0;
+  const double h = zmax / (2.0 * g->f_number);
+  int n = 0;
+  for (int e = 0; e < g->n_channels; ++e)
+    n += (g->elem_x[e] > xlo - h && g->elem_x[e] < xhi + h) ? 1 : 0;
+  return n;
+}
+
+double tile_cost(const pwbf_geometry *g, const FramePlan &P, int tile) {
+  return (double)tile_active_channels(g, P, tile) * P.tile_z * P.tile_x * (P.n_angles + 2) *
+         (P.mode == kDmas ? 2.0 : 1.0);
+}
+
 int build_post_plan(const pwbf_geometry *g, const pwbf_outputs *o, void *ws, PostPlan *Q) {
   std::memset(Q, 0, sizeof *Q);
   Q->src = o->rf;

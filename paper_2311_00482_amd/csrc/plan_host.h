@@ -31,6 +31,10 @@ int tune_save(const char *path, std::string *err);
 int tune_load(const char *path, std::string *err);
 void tune_clear();
 uint32_t tune_generation();  // changes whenever the table does
+// Channels whose receive aperture reaches tile `tile` of plan P (all of them
+// without apodization), and the tile's relative cost for work ordering.
+int tile_active_channels(const pwbf_geometry *g, const FramePlan &P, int tile);
+double tile_cost(const pwbf_geometry *g, const FramePlan &P, int tile);
 int build_post_plan(const pwbf_geometry *g, const pwbf_outputs *o, void *ws, PostPlan *Q);
 bool post_needed(const pwbf_outputs *o);
 

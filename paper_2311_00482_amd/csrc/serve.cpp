@@ -221,7 +221,7 @@ void scheduler(pwbf_server *s) {
       s->cv_work.wait_for(lk, std::chrono::microseconds(50));
       continue;
     }
-    // largest tiles first
+    // slots with the costliest tiles first
     std::stable_sort(ready.begin(), ready.end(), [&](const auto &a, const auto &b) {
       return s->probes[s->slots[a.second].probe].tile_cost >
              s->probes[s->slots[b.second].probe].tile_cost;
@@ -384,8 +384,8 @@ int pwbf_server_create(const pwbf_probe *probes, int32_t n, size_t hbm_budget_by
       p.tiles = P.n_tiles;
       p.cols = pwbf::post_needed(&o) ? g.nx : 0;
       p.log_cols = p.want_log ? g.nx : 0;
-      p.tile_cost = (double)P.tile_z * P.tile_x * P.n_channels * (P.n_angles + 2) *
-                    (pp.mode == pwbf::kDmas ? 2.0 : 1.0);
+      if (k == 0)  // its deepest (first-run) tile row holds the costliest tiles
+        for (int t = 0; t < P.n_tiles; ++t) p.tile_cost = std::max(p.tile_cost, pwbf::tile_cost(&g, P, t));
       s->lds = std::max(s->lds, (int)pwbf::plan_lds_bytes(P));
       if (pwbf::post_needed(&o)) s->max_nz = std::max(s->max_nz, g.nz);
       p.free_slots.insert(p.free_slots.begin(), idx);

@@ -72,8 +72,11 @@ __global__ void __launch_bounds__(kWave * kServeWaves)
     if (it >= al.tile0[al.n]) break;  // uniform: every wave of the block leaves
     const int k = find_slot(al.tile0, al.n, it);
     const FramePlan &P = plans[al.plan[k]];
+    // within a slot, deepest tile row first (the receive aperture, and so the
+    // cost, grows with depth)
     const int t = it - al.tile0[k];
-    const int tz = t / P.tiles_x, tx = t - tz * P.tiles_x;
+    const int q = t / P.tiles_x;
+    const int tz = P.tiles_z - 1 - q, tx = t - q * P.tiles_x;
     if (P.mode == kDas) {
       if (P.cpw == 1)
         serve_tile_mode<kDas, true>(P, tz, tx, smem);
