@@ -32,8 +32,9 @@
  *    validation error nothing is enqueued and nothing is written. Work is
  *    enqueued on the caller's HIP stream (NULL = the null stream) and the call
  *    returns once it is enqueued. Device faults surface at the caller's next
- *    synchronisation. No call allocates or frees device memory, keeps a pointer
- *    after it returns, prints, or throws. Calls on different streams from
+ *    synchronisation. No single-frame call allocates or frees device memory,
+ *    keeps a pointer after it returns, prints, or throws (the batch, tuning and
+ *    serving objects below own memory and say so). Calls on different streams from
  *    different threads may overlap; calls that share a workspace must not.
  *  - Return value: PWBF_OK (0) or a negative PWBF_E_* code; pwbf_last_error()
  *    gives a thread-local description of the last failure on the calling thread.
@@ -84,7 +85,7 @@ typedef struct pwbf_geometry {
   uint32_t abi_version;     /* must be PWBF_ABI_VERSION */
   int32_t n_angles;         /* 1 .. PWBF_MAX_ANGLES */
   int32_t n_channels;       /* 1 .. PWBF_MAX_CHANNELS (>= 2 for DMAS) */
-  int32_t n_samples;        /* >= 2 */
+  int32_t n_samples;        /* 2 .. 2^24 - 1; n_angles * n_channels * n_samples < 2^31 */
   const double *elem_x;     /* host [n_channels], element centres, m */
   const double *angle_rad;  /* host [n_angles], steering angles, |th| < pi/2 */
   const double *t0;         /* host [n_angles], s, time of sample 0; NULL = all 0 */
@@ -329,9 +330,16 @@ typedef struct pwbf_server_stats {
 
 #define PWBF_E_BUSY (-5) /* serving: the probe's queue is full */
 
-/* Create a server for n probes. hbm_budget_bytes caps the bytes of slots in use
- * (0 = no cap beyond the allocated rings); max_queue bounds each probe's queue
- * of waiting requests (0 = 1024). Allocates the rings and starts the scheduler. */
+/* Create a server for n probes. A slot of a probe costs its FP16 RF
+ * (2 n_angles n_channels n_samples bytes), its float32 planes (rf, plus env
+ * when want_env or want_log, plus the log image) and 256 bytes for the frame
+ * maximum. hbm_budget_bytes caps the bytes of slots in use at once (0 = no cap
+ * beyond the allocated rings; PWBF_E_INVALID when one slot of some probe
+ * exceeds it); max_queue bounds each probe's queue of waiting requests
+ * (0 = 1024). Probes are validated like single-frame calls before anything is
+ * allocated (at most 16 summed angles per frame); then the rings are allocated
+ * on the current device (PWBF_E_NOMEM on failure) and the scheduler thread
+ * starts. The functions below may be called from any thread. */
 PWBF_API int pwbf_server_create(const pwbf_probe *probes, int32_t n, size_t hbm_budget_bytes,
                                 int32_t max_queue, pwbf_server **out);
 
