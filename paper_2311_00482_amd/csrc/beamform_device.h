@@ -31,64 +31,103 @@
 namespace pwbf {
 namespace dev {
 
+// RF storage types: element size and a load through a raw buffer resource
+// (32-bit byte offset, scalar base), widened to float.
 template <int DT>
 struct RfT;
 template <>
 struct RfT<kI16> {
-  using T = int16_t;
-  static __device__ __forceinline__ float f(T v) { return (float)v; }
+  static constexpr int kBytes = 2;
+  static __device__ __forceinline__ float load(__amdgpu_buffer_rsrc_t r, unsigned off) {
+    return (float)(short)__builtin_amdgcn_raw_buffer_load_b16(r, (int)off, 0, 0);
+  }
 };
 template <>
 struct RfT<kF16> {
-  using T = __half;
-  static __device__ __forceinline__ float f(T v) { return __half2float(v); }
+  static constexpr int kBytes = 2;
+  static __device__ __forceinline__ float load(__amdgpu_buffer_rsrc_t r, unsigned off) {
+    const unsigned short h = (unsigned short)__builtin_amdgcn_raw_buffer_load_b16(r, (int)off, 0, 0);
+    return __half2float(__ushort_as_half(h));
+  }
 };
 template <>
 struct RfT<kF32> {
-  using T = float;
-  static __device__ __forceinline__ float f(T v) { return v; }
+  static constexpr int kBytes = 4;
+  static __device__ __forceinline__ float load(__amdgpu_buffer_rsrc_t r, unsigned off) {
+    return __int_as_float((int)__builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
+  }
 };
 
+// Buffer resource word 3 for raw (unformatted, unswizzled) loads on gfx9.
+constexpr int kRawBufferWord3 = 0x00020000;
+
 // Stage the windows of channels e0 .. e0 + nch - 1: nch * A rows (channel c,
-// angle a) of win entries, flattened over all lanes of the block. Entry j of a
-// row covers samples n = LT_a + LR_c + j and n + 1, i.e. kernel delays s in
-// [m, m + 1) with m = j - off_t - off_r, and holds, with du = u[n+1] - u[n],
+// angle a) of win entries (win a multiple of 4). Entry j of a row covers
+// samples n = LT_a + LR_c + j and n + 1, i.e. kernel delays s in [m, m + 1)
+// with m = j - off_t - off_r, and holds, with du = u[n+1] - u[n],
 //   DAS:  the line through both samples in s:  (u[n] - m du, du),
 //         so the interpolated value is b + s du (no fraction needed);
 //   DMAS: (u[n], du), interpolated as u[n] + frac(s) du, which keeps the
 //         rounding of v small where the signed square root is steep.
 // Samples outside [0, n_samples) read as zero; rows of channels >= e_end are zero.
+//
+// Each thread fills 4 consecutive entries of a row from 5 consecutive samples,
+// read through one 32-bit buffer offset with immediate increments; where the 5
+// samples straddle an end of the record the reads are clamped into it and the
+// outside samples replaced by zero. Every read stays inside the RF buffer.
 template <int DT, int MODE>
 __device__ __forceinline__ void stage_windows(const FramePlan &P, int e0, int nch, int e_end,
                                               const int *s_lt, const int *s_lr, float2 *s_pairs) {
   using R = RfT<DT>;
-  const typename R::T *rf = (const typename R::T *)P.rf;
+  constexpr int B = R::kBytes;
   const int A = P.n_angles, N = P.n_channels, Ns = P.n_samples, win = P.win;
   const int off = P.off_t + P.off_r;
-  const int total = nch * A * win;  // at most kMaxLdsBytes / 8 = 2^13 entries
-  // row = t / win and c = row / A through a float reciprocal: (t + 0.5) / win
-  // lies at least 0.5 / win from an integer, and for t < 2^13 the product errs
-  // by under 1e-3 / win, so truncation yields the exact quotient.
-  const float rw = __builtin_amdgcn_rcpf((float)win), ra = __builtin_amdgcn_rcpf((float)A);
+  const int W4 = win >> 2;
+  const int total = nch * A * W4;  // at most kMaxLdsBytes / 32 = 2^11 quads
+  // row = q / W4 and c = row / A through a float reciprocal: (q + 0.5) / W4
+  // lies at least 0.5 / W4 from an integer, and for q < 2^11 the product errs
+  // by under 1e-3 / W4, so truncation yields the exact quotient.
+  const float rw = __builtin_amdgcn_rcpf((float)W4), ra = __builtin_amdgcn_rcpf((float)A);
   const float hw = 0.5f * rw, ha = 0.5f * ra;
   const int last = min(e_end, N) - 1;  // channels past it stage zeros
-  for (int t = threadIdx.x; t < total; t += blockDim.x) {
-    const int row = (int)fmaf((float)t, rw, hw);
-    const int j = t - row * win;
+  // the plan's angles only: A * N * Ns * B < 2^31 bytes (checked on the host)
+  const __amdgpu_buffer_rsrc_t res = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<void *>(P.rf), (short)0, A * N * Ns * B, kRawBufferWord3);
+  for (int q = threadIdx.x; q < total; q += blockDim.x) {
+    const int row = (int)fmaf((float)q, rw, hw);
+    const int j0 = (q - __mul24(row, W4)) << 2;
     const int c = (int)fmaf((float)row, ra, ha);
-    const int a = row - c * A;
+    const int a = row - __mul24(c, A);
     const int e = e0 + c;
-    // sample n of (a, e); n = -2 stands for a row of zeros. Reads are clamped
-    // into the record (indices fit 32 bits: the RF holds < 2^31 samples) and
-    // samples outside [0, Ns) are replaced by zero, without branches.
-    const int n = e <= last ? s_lt[a] + s_lr[c] + j : -2;
-    const unsigned base = (unsigned)(a * N + min(e, last)) * (unsigned)Ns;
-    const int n0 = min(max(n, 0), Ns - 1), n1 = min(max(n + 1, 0), Ns - 1);
-    const float r0 = R::f(rf[base + (unsigned)n0]), r1 = R::f(rf[base + (unsigned)n1]);
-    const float u0 = (unsigned)n < (unsigned)Ns ? r0 : 0.f;
-    const float u1 = (unsigned)(n + 1) < (unsigned)Ns ? r1 : 0.f;
-    const float du = u1 - u0;
-    s_pairs[t] = make_float2(MODE == kDas ? fmaf((float)(off - j), du, u0) : u0, du);
+    const int n = s_lt[a] + s_lr[c] + j0;
+    const unsigned base = __umul24((unsigned)(__mul24(a, N) + min(e, last)), (unsigned)Ns);
+    float u[5];
+    if (n >= 0 && n + 4 < Ns) {
+      const unsigned vo = (base + (unsigned)n) * B;
+#pragma unroll
+      for (int k = 0; k < 5; ++k) u[k] = R::load(res, vo + k * B);
+    } else {
+#pragma unroll
+      for (int k = 0; k < 5; ++k) {
+        const int i = n + k;
+        const float v = R::load(res, (base + (unsigned)min(max(i, 0), Ns - 1)) * B);
+        u[k] = (unsigned)i < (unsigned)Ns ? v : 0.f;
+      }
+    }
+    if (e > last) {
+#pragma unroll
+      for (int k = 0; k < 5; ++k) u[k] = 0.f;
+    }
+    float v8[8];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const float du = u[k + 1] - u[k];
+      v8[2 * k] = MODE == kDas ? fmaf((float)(off - j0 - k), du, u[k]) : u[k];
+      v8[2 * k + 1] = du;
+    }
+    float4 *dst = (float4 *)(s_pairs + __mul24(row, win) + j0);
+    dst[0] = make_float4(v8[0], v8[1], v8[2], v8[3]);
+    dst[1] = make_float4(v8[4], v8[5], v8[6], v8[7]);
   }
 }
 

@@ -9,7 +9,7 @@
 //     position, so it spans at most the tile diagonal.
 // The kernel starts each window at floor(min transmit) - 1 plus
 // floor(min receive) - 1, so every interpolation pair of every pixel of the
-// tile lies inside ceil(spread) + 6 entries.
+// tile lies inside ceil(spread) + 6 entries (rounded up to a multiple of 4).
 #include "plan_host.h"
 
 #include <algorithm>
@@ -185,7 +185,8 @@ static int window_entries(FramePlan &p, int TZ, int TX) {
   // window delays relative to the origin lie in [1, r + 2) for each term
   p.off_t = (int)std::floor(rt / 2) + 1;
   p.off_r = (int)std::floor(rr / 2) + 1;
-  return (int)std::ceil(rt + rr) + 6;
+  // a multiple of 4: the staging threads write four entries at a time
+  return ((int)std::ceil(rt + rr) + 6 + 3) & ~3;
 }
 
 // Apply launch shape t to plan P (geometry already filled in): window length,
@@ -242,6 +243,10 @@ static int plan_frame_uncached(const pwbf_geometry *g, int dtype, int mode, int 
     return fail(err, PWBF_E_INVALID, "angle %d outside 0..%d", angle, g->n_angles - 1);
   if (mode == kDmas && g->n_channels < 2)
     return fail(err, PWBF_E_INVALID, "DMAS needs at least 2 channels");
+  // the kernels address the RF bytes with 32-bit buffer offsets
+  if ((int64_t)g->n_angles * g->n_channels * g->n_samples * (int64_t)dtype_bytes(dtype) >=
+      ((int64_t)1 << 31))
+    return fail(err, PWBF_E_UNSUPPORTED, "RF buffer of 2^31 bytes or more");
 
   std::memset(P, 0, sizeof *P);
   const double scale = g->fs / g->c;
