@@ -4,7 +4,7 @@ TEST INFRASTRUCTURE ONLY. This package is what the GPU path is checked against:
 only ``tests/``, the smoke check and the benchmark's CPU-baseline leg may import
 it. It shares no code with the GPU library and never imports it.
 
-The per-pixel beamformers (DAS, compound, RF DMAS in two forms) are plain C in
+The per-pixel beamformers (DAS, compound, RF DMAS in two forms, pDAS) are plain C in
 ``pwbf_oracle.c``, single-threaded FP64; the column post-processing along depth
 (band-pass, Hilbert envelope, log compression) is NumPy FP64 with ``numpy.fft``
 as the transform. Geometry objects are duck-typed: anything with the attributes
@@ -12,7 +12,8 @@ of ``synth.Geometry`` (elem_x, angles_rad, t0_s, c, fs, nx, nz, x0, dx, z0, dz,
 f_number, apod_code, n_samples, f0).
 
 Paper passages followed: Eq. (1) and the delay text after it (DAS); Eq. (2) and
-Eq. (4) for the signed-root compression and the squared-sum form of DMAS; the
+Eq. (4) for the signed-root compression and the squared-sum form of DMAS;
+Eqs. (2)-(3) for pDAS (p-th root before the sum, signed p-th power after); the
 absolute value of the analytic signal for the image; the -70 dB display range
 (Fig. 3 caption). Every function is pinned by CPU tests against closed forms,
 invariants and an independent brute-force evaluation; none is "parity unpinned".
@@ -73,6 +74,9 @@ def _load():
                                 ctypes.c_int64, ctypes.c_void_p]
         lib.ora_dmas.restype = ctypes.c_int
         lib.ora_dmas.argtypes = [P, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
+                                 ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]
+        lib.ora_pdas.restype = ctypes.c_int
+        lib.ora_pdas.argtypes = [P, ctypes.c_void_p, ctypes.c_int32, ctypes.c_double,
                                  ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]
         _lib = lib
     return _lib
@@ -155,10 +159,27 @@ def dmas(g, rf, angle: int = -1, form: str = "identity", pix=None) -> np.ndarray
     return out.reshape(g.nx, g.nz) if p is None else out
 
 
-def compound(g, rf, mode: str = "das", pix=None) -> np.ndarray:
+def pdas(g, rf, angle: int = -1, p: float = 2.0, pix=None) -> np.ndarray:
+    """pDAS (Eqs. 2-3): sum of w sign(v)|v|^(1/p), then its signed p-th power;
+    angle -1 sums the per-angle pDAS values."""
+    b = _Bound(g)
+    rf = _rf64(g, rf)
+    q = _pix(g, pix)
+    n = g.nx * g.nz if q is None else len(q)
+    out = np.empty(n, dtype=np.float64)
+    rc = _load().ora_pdas(b.ref, rf.ctypes.data, angle, float(p),
+                          None if q is None else q.ctypes.data, n, out.ctypes.data)
+    if rc != 0:
+        raise ValueError("ora_pdas rejected its arguments")
+    return out.reshape(g.nx, g.nz) if q is None else out
+
+
+def compound(g, rf, mode: str = "das", pix=None, p: float = 2.0) -> np.ndarray:
     """Coherent compounding: the unweighted sum over angles of the per-angle image."""
     if mode == "das":
         return das(g, rf, -1, pix)
+    if mode == "pdas":
+        return pdas(g, rf, -1, p, pix)
     return dmas(g, rf, -1, "identity", pix)
 
 
@@ -211,9 +232,14 @@ def log_compress(env: np.ndarray, floor_db: float = -70.0) -> np.ndarray:
 
 
 def beamform(g, rf, mode: str = "das", angle: int = -1, bandpass: bool = False,
-             floor_db: float = -70.0) -> dict:
+             floor_db: float = -70.0, p: float = 2.0) -> dict:
     """The whole path for one frame: raw image, optional band-pass, envelope, log."""
-    raw = das(g, rf, angle) if mode == "das" else dmas(g, rf, angle, "identity")
+    if mode == "das":
+        raw = das(g, rf, angle)
+    elif mode == "pdas":
+        raw = pdas(g, rf, angle, p)
+    else:
+        raw = dmas(g, rf, angle, "identity")
     out = {"rf": raw}
     src = raw
     if bandpass:

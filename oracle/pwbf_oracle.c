@@ -28,6 +28,10 @@
  *    the squared-sum structure of Eq. (4) without its 1/N. Computed both as
  *    the O(N^2) pair sum and as ((sum s)^2 - sum s^2) / 2; compounding sums the
  *    per-angle results.
+ *  - pDAS, Eqs. (2)-(3): each delayed sample compressed to sign(v)|v|^(1/p),
+ *    weighted and summed (the weight outside the root), then the sum restored
+ *    by the signed p-th power; compounding sums the per-angle results, as for
+ *    DMAS. p = 1 is DAS.
  *
  * Pins (tests marked "not gpu"): impulse response of a single RF sample
  * (triangle-weighted iso-delay arc), point scatterer simulated independently
@@ -157,6 +161,18 @@ static double dmas_one_angle(const ora_geom *g, const double *rf, int32_t a, dou
   return 0.5 * (sum * sum - sq);
 }
 
+/* pDAS, Eqs. (2)-(3), for one angle: the sum of w_e sign(v_e) |v_e|^(1/p), then
+ * its signed p-th power. */
+static double pdas_one_angle(const ora_geom *g, const double *rf, int32_t a, double first,
+                             double x, double z, double p) {
+  double yt = 0.0;
+  for (int32_t e = 0; e < g->n_channels; ++e) {
+    double v = delayed(g, rf, a, first, e, x, z);
+    yt += ora_apod_weight(g, e, x, z) * sgn(v) * pow(fabs(v), 1.0 / p);
+  }
+  return sgn(yt) * pow(fabs(yt), p);
+}
+
 /* DAS image values. angle >= 0: that angle alone; angle == -1: the compound sum
  * over all angles. pix == NULL evaluates every pixel in [nx][nz] order; otherwise
  * pix[k] is a flat pixel index ix * nz + iz. rf is [n_angles][n_channels][n_samples]. */
@@ -201,6 +217,31 @@ int ora_dmas(const ora_geom *g, const double *rf, int32_t angle, int32_t form, c
     } else {
       for (int32_t a = 0; a < g->n_angles; ++a)
         y += dmas_one_angle(g, rf, a, first[a], x, z, form);
+    }
+    out[k] = y;
+  }
+  return ORA_OK;
+}
+
+/* pDAS image values (Eqs. (2)-(3)) with root order p >= 1; angle and pix as for
+ * ora_das; compounding sums the per-angle pDAS values. */
+int ora_pdas(const ora_geom *g, const double *rf, int32_t angle, double p, const int64_t *pix,
+             int64_t npix, double *out) {
+  if (check(g, angle) != ORA_OK || !rf || !out || !(p >= 1.0)) return ORA_BAD;
+  int64_t total = (int64_t)g->nx * g->nz;
+  if (!pix) npix = total;
+  double first[ORA_MAX_ANGLES];
+  for (int32_t a = 0; a < g->n_angles; ++a) first[a] = first_fire(g, a);
+  for (int64_t k = 0; k < npix; ++k) {
+    int64_t q = pix ? pix[k] : k;
+    if (q < 0 || q >= total) return ORA_BAD;
+    double x, z;
+    pixel_xz(g, q, &x, &z);
+    double y = 0.0;
+    if (angle >= 0) {
+      y = pdas_one_angle(g, rf, angle, first[angle], x, z, p);
+    } else {
+      for (int32_t a = 0; a < g->n_angles; ++a) y += pdas_one_angle(g, rf, a, first[a], x, z, p);
     }
     out[k] = y;
   }

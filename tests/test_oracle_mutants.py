@@ -37,6 +37,14 @@ MUTANTS = {
     "dmas_not_halved": ("return 0.5 * (sum * sum - sq);", "return (sum * sum - sq);"),
     "hann_half_period": ("return 0.5 * (1.0 + cos(M_PI * d / half_aperture));",
                          "return 0.5 * (1.0 + cos(0.5 * M_PI * d / half_aperture));"),
+    "pdas_power_inside": ("yt += ora_apod_weight(g, e, x, z) * sgn(v) * pow(fabs(v), 1.0 / p);",
+                          "yt += ora_apod_weight(g, e, x, z) * sgn(v) * pow(fabs(v), p);"),
+    "pdas_weight_inside_root": (
+        "yt += ora_apod_weight(g, e, x, z) * sgn(v) * pow(fabs(v), 1.0 / p);",
+        "yt += sgn(v) * pow(fabs(ora_apod_weight(g, e, x, z) * v), 1.0 / p);"),
+    "pdas_unsigned_power": ("return sgn(yt) * pow(fabs(yt), p);", "return pow(fabs(yt), p);"),
+    "pdas_root_order": ("return sgn(yt) * pow(fabs(yt), p);",
+                        "return sgn(yt) * pow(fabs(yt), 1.0 / p);"),
     "compound_keeps_last": (
         "for (int32_t a = 0; a < g->n_angles; ++a) y += das_one_angle(g, rf, a, first[a], x, z);",
         "for (int32_t a = 0; a < g->n_angles; ++a) y = das_one_angle(g, rf, a, first[a], x, z);"),

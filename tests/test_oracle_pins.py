@@ -1,7 +1,9 @@
 """Pins of the FP64 oracle against facts that do not come from the oracle itself:
 special-case delays, the impulse response, a point scatterer produced by the
 independent forward model, invariants of a linear beamformer, closed forms of
-DMAS, and a brute-force re-evaluation that interpolates with numpy.interp.
+DMAS and pDAS, relations between the beamformers (pDAS at p = 1 is DAS; at
+p = 2 with boxcar weights and positive data it is 2 DMAS + DAS), and a
+brute-force re-evaluation that interpolates with numpy.interp.
 """
 
 import math
@@ -182,9 +184,13 @@ def test_compound_is_sum_of_angles():
                for a in range(3))
     np.testing.assert_allclose(oracle.compound(g, rf, "dmas"), perd,
                                atol=1e-12 * np.abs(perd).max())
+    perp = sum(oracle.pdas(g.replace(angles_deg=(g.angles_deg[a],)), rf[a:a + 1], 0, 2.5)
+               for a in range(3))
+    np.testing.assert_allclose(oracle.compound(g, rf, "pdas", p=2.5), perp,
+                               atol=1e-12 * np.abs(perp).max())
 
 
-@pytest.mark.parametrize("mode", ["das", "dmas"])
+@pytest.mark.parametrize("mode", ["das", "dmas", "pdas"])
 def test_mirror_symmetry(mode):
     # A symmetric array and grid: mirroring x, the steering angle and the element
     # order mirrors the image along x.
@@ -192,7 +198,7 @@ def test_mirror_symmetry(mode):
     gm = g.replace(angles_deg=(-6.0,))
     rf = _rand_rf(g, 5)
     rfm = rf[:, ::-1, :]
-    f = oracle.das if mode == "das" else oracle.dmas
+    f = {"das": oracle.das, "dmas": oracle.dmas, "pdas": oracle.pdas}[mode]
     img = f(g, rf, 0)
     imgm = f(gm, rfm, 0)
     np.testing.assert_allclose(imgm[::-1, :], img, atol=1e-11 * np.abs(img).max())
@@ -238,13 +244,63 @@ def test_dmas_two_channels_closed_form():
     np.testing.assert_allclose(oracle.dmas(g, rf, 0), expect, atol=1e-13)
 
 
+# ------------------------------------------------------------------------ pDAS
+@pytest.mark.parametrize("apod,deg", [("hann", 0.0), ("boxcar", 6.0), ("none", -4.0)])
+def test_pdas_with_p_one_is_das(apod, deg):
+    g = small_geom(apod=apod, angles_deg=(deg, -2.0))
+    rf = _rand_rf(g, 21)
+    ref = oracle.das(g, rf, -1)
+    np.testing.assert_allclose(oracle.pdas(g, rf, -1, 1.0), ref, atol=1e-12 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("p", [1.5, 2.0, 3.0])
+def test_pdas_single_channel_closed_form(p):
+    # one element: sign(w sign(v)|v|^(1/p)) |w |v|^(1/p)|^p = w^p v = w^(p-1) * DAS
+    g = small_geom(n_channels=1, x_min=-1.5e-3, x_max=1.5e-3, f_number=2.0)
+    rf = _rand_rf(g, 22)
+    das = oracle.das(g, rf, 0)
+    w = np.array([[oracle.apod_weight(g, 0, x, z) for z in g.z_pix] for x in g.x_pix])
+    assert 0 < np.count_nonzero(w) < w.size  # inside and outside the aperture
+    np.testing.assert_allclose(oracle.pdas(g, rf, 0, p), w ** (p - 1) * das,
+                               atol=1e-12 * np.abs(das).max())
+
+
+def test_pdas_is_odd_and_homogeneous_of_degree_one():
+    g = small_geom(angles_deg=(3.0,), n_channels=12)
+    rf = _rand_rf(g, 23)
+    base = oracle.pdas(g, rf, 0, 2.7)
+    np.testing.assert_allclose(oracle.pdas(g, 3.25 * rf, 0, 2.7), 3.25 * base,
+                               atol=1e-11 * np.abs(base).max())
+    np.testing.assert_allclose(oracle.pdas(g, -rf, 0, 2.7), -base, atol=1e-13 * np.abs(base).max())
+
+
+def test_pdas_of_equal_signals():
+    # every delayed sample equal to u (w = 1): y = sign(u) |u| N^p
+    g = small_geom(apod="none", n_channels=7, n_samples=2048)
+    u, p = -2.3, 3.0
+    rf = np.full((1, g.n_channels, g.n_samples), u)
+    np.testing.assert_allclose(oracle.pdas(g, rf, 0, p), -abs(u) * g.n_channels ** p,
+                               rtol=1e-13)
+
+
+def test_pdas_p2_is_twice_dmas_plus_das_for_boxcar_positive_data():
+    # w in {0, 1} and v >= 0: (sum w sqrt v)^2 = 2 sum_{i<j} s_i s_j + sum w v
+    g = small_geom(apod="boxcar", angles_deg=(-4.0,), n_channels=20)
+    rf = np.abs(_rand_rf(g, 24))
+    lhs = oracle.pdas(g, rf, 0, 2.0)
+    rhs = 2.0 * oracle.dmas(g, rf, 0) + oracle.das(g, rf, 0)
+    np.testing.assert_allclose(lhs, rhs, atol=1e-12 * np.abs(rhs).max())
+
+
 # ------------------------------------------------------------ brute force 4x4
-def brute_das_dmas(g, rf):
+def brute_das_dmas(g, rf, p=2.5):
     """Independent evaluation: numpy.interp on a zero-padded record, Hann as a
-    squared cosine, angle-outer loop order."""
+    squared cosine, angle-outer loop order; returns DAS, DMAS (pair sum) and
+    pDAS of order p."""
     A, N, Ns = rf.shape
     das = np.zeros((g.nx, g.nz))
     dmas = np.zeros((g.nx, g.nz))
+    pdas = np.zeros((g.nx, g.nz))
     grid = np.arange(-1, Ns + 1, dtype=np.float64)
     for a in range(A):
         th = math.radians(g.angles_deg[a])
@@ -257,6 +313,7 @@ def brute_das_dmas(g, rf):
                 # transmit path measured from the first-firing element's wavefront
                 path_tx = x * math.sin(th) + z * math.cos(th) - (g.elem_x * math.sin(th)).min()
                 sh = []
+                root_sum = 0.0
                 for e in range(N):
                     path_rx = math.hypot(x - g.elem_x[e], z)
                     s = (path_tx + path_rx) / g.c * g.fs - g.t0_s[a] * g.fs
@@ -267,10 +324,12 @@ def brute_das_dmas(g, rf):
                     w = math.cos(math.pi * d / (2 * half)) ** 2 if (z > 0 and d < half) else 0.0
                     das[ix, iz] += w * v
                     sh.append(w * math.copysign(math.sqrt(abs(v)), v) if v != 0 else 0.0)
+                    root_sum += w * math.copysign(abs(v) ** (1.0 / p), v) if v != 0 else 0.0
                 for i in range(N):
                     for j in range(i + 1, N):
                         dmas[ix, iz] += sh[i] * sh[j]
-    return das, dmas
+                pdas[ix, iz] += math.copysign(abs(root_sum) ** p, root_sum)
+    return das, dmas, pdas
 
 
 @pytest.mark.parametrize("seed,angles", [(11, (0.0,)), (12, (-9.0, 3.0, 10.0))])
@@ -278,10 +337,12 @@ def test_brute_force_4x4(seed, angles):
     g = Geometry(n_channels=8, n_samples=400, angles_deg=angles, nx=4, nz=4, x_min=-1e-3,
                  x_max=1.4e-3, z_min=5e-3, z_max=6.2e-3, f_number=0.8, t0=(0.3e-6,) * len(angles))
     rf = _rand_rf(g, seed)
-    bd, bm = brute_das_dmas(g, rf)
+    bd, bm, bp = brute_das_dmas(g, rf, 2.5)
     np.testing.assert_allclose(oracle.das(g, rf, -1), bd, atol=1e-12 * np.abs(bd).max())
     np.testing.assert_allclose(oracle.compound(g, rf, "dmas"), bm, atol=1e-12 * np.abs(bm).max())
-    assert np.abs(bd).max() > 0 and np.abs(bm).max() > 0
+    np.testing.assert_allclose(oracle.compound(g, rf, "pdas", p=2.5), bp,
+                               atol=1e-12 * np.abs(bp).max())
+    assert np.abs(bd).max() > 0 and np.abs(bm).max() > 0 and np.abs(bp).max() > 0
 
 
 # ------------------------------------------------------------- post-processing
