@@ -59,11 +59,26 @@ def aperture_pairs(g) -> int:
     return int(np.maximum(hi - lo, 0).sum())
 
 
-def algorithmic_ops(g) -> float:
+# The nonlinear beamformers, counted the same way (per gather, per (pixel,
+# channel), per (pixel, angle)). DMAS: delay add, floor, fraction,
+# interpolation FMA, |v|, square root, signed root, weighted accumulate, |v|
+# accumulate = 9; per (pixel, channel) the DAS terms with the weighted
+# accumulate replaced by w^2 and its FMA into Q = 10; per (pixel, angle) the
+# transmit delay and the square of the angle's sum = 3. pDAS: delay add, floor,
+# fraction, interpolation FMA, |v|, log2, times 1/p, exp2, signed root,
+# weighted accumulate = 10; per (pixel, channel) the DAS terms without the
+# weighted accumulate = 8; per (pixel, angle) the transmit delay and the signed
+# p-th power (|t|, log2, times p, exp2, sign, add) = 8.
+MODE_OPS = {"das": (OPS_PER_GATHER, OPS_PER_PIX_CH, OPS_PER_PIX_ANGLE), "dmas": (9, 10, 3),
+            "pdas": (10, 8, 8)}
+
+
+def algorithmic_ops(g, mode: str = "das") -> float:
+    per_gather, per_pix_ch, per_pix_angle = MODE_OPS[mode]
     P = g.nx * g.nz
     pairs = aperture_pairs(g)
-    return float(pairs * g.n_angles * OPS_PER_GATHER + pairs * OPS_PER_PIX_CH
-                 + P * g.n_angles * OPS_PER_PIX_ANGLE)
+    return float(pairs * g.n_angles * per_gather + pairs * per_pix_ch
+                 + P * g.n_angles * per_pix_angle)
 
 
 def kernel_source_hash() -> str:
@@ -128,6 +143,48 @@ def cpu_baseline(g, rf_master, budget_s: float):
                       f"{g.n_channels} ch x {g.n_angles} angles), compound DAS only, "
                       f"{dt:.1f} s", "seconds": dt,
             "frames_per_s_equiv": gathers / dt / g.gathers}
+
+
+def other_modes(dev, torch, steps: int, warmup: int) -> dict:
+    """DMAS and pDAS (p = 2) kernels on the DMAS workload (128 ch, 512 x 512 at
+    dz = 25 um, int16 RF) and pDAS on the 11-angle compound workload (FP32 RF):
+    kernel time from HIP events, the frame rate of the whole path (band-pass,
+    envelope and log for the DMAS workload; envelope and log for compound), and
+    the roofline fraction of each kernel with its own algorithmic op count."""
+    from paper_2311_00482_amd import GeometryArg, beamform
+    from synth import config_c2, config_c3, make_frame
+
+    res = {}
+    cases = [("dmas_128ch_512x512", config_c2(), "dmas", True, "c1", True),
+             ("pdas_p2_128ch_512x512", config_c2(), "pdas", True, "c1", True),
+             ("pdas_p2_compound_11a_1024x1024", config_c3(), "pdas", False, "c3", False)]
+    for name, gs, mode, bp, kind, quant in cases:
+        g = GeometryArg(gs, bandpass=bp, pdas_p=2.0)
+        fr = make_frame(gs, 1001 if kind == "c1" else 1003, kind, quantize=quant)
+        rf = torch.from_numpy(fr["i16"] if quant else fr["f32"]).to(dev)
+        want = ("rf", "filtered", "env", "log") if bp else ("rf", "env", "log")
+        outs = {k: torch.empty((g.nx, g.nz), dtype=torch.float32, device=dev) for k in want}
+        ws = torch.empty(4096, dtype=torch.uint8, device=dev)
+        rf_only = {"rf": outs["rf"]}
+        n = max(20, steps // 3)
+        wall, lat, _ = time_steps(
+            lambda: beamform(g, rf, mode, -1, want=want, out=outs, workspace=ws, bandpass=bp),
+            n, max(5, warmup // 3), torch)
+        _, klat, _ = time_steps(lambda: beamform(g, rf, mode, -1, want=("rf",), out=rf_only),
+                                n, max(5, warmup // 3), torch)
+        k_ms = float(np.mean(klat))  # average launch duration (HIP events around each launch)
+        ops = algorithmic_ops(gs, mode)
+        res[name] = {"frames_per_s": n / wall, "p50_ms": float(np.percentile(lat, 50)),
+                     "p99_ms": float(np.percentile(lat, 99)), "kernel_ms": k_ms,
+                     "value": gs.gathers / (k_ms * 1e-3) / 1e9, "unit": UNIT,
+                     "roofline": {"bound": "alu", "achieved": ops / (k_ms * 1e-3) / 1e12,
+                                  "peak": VALU_LANE_OPS_PEAK / 1e12, "unit": "Tlane-op/s",
+                                  "frac": ops / (k_ms * 1e-3) / VALU_LANE_OPS_PEAK,
+                                  "ops_per_launch": ops},
+                     "rf_storage": "int16" if quant else "f32"}
+        print(f"[bench] {name}: {res[name]['kernel_ms']:.3f} ms kernel, "
+              f"frac {res[name]['roofline']['frac']:.2f}", file=sys.stderr, flush=True)
+    return res
 
 
 def systems(dev, torch, steps: int, warmup: int) -> dict:
@@ -217,8 +274,8 @@ def systems(dev, torch, steps: int, warmup: int) -> dict:
                     srv.release(r.id)
                 if not got and k < n:  # sleep only when the next arrival is far off
                     gap = t0 + arrivals[k] - srv.now()
-                    if gap > 1.5e-3:
-                        time.sleep(gap - 1e-3)
+                    if gap > 3e-3:  # host sleeps can overshoot by a millisecond or more
+                        time.sleep(gap - 2e-3)
             wall = srv.now() - t0
             pq = np.percentile(np.array(parts) * 1e3, 50, axis=0)
             pq99 = np.percentile(np.array(parts) * 1e3, 99, axis=0)
@@ -247,6 +304,13 @@ def main():
     ap.add_argument("--steps", type=int, default=300)
     ap.add_argument("--no-systems", action="store_true",
                     help="skip the batched and served FP16 measurements")
+    ap.add_argument("--no-modes", action="store_true",
+                    help="skip the DMAS and pDAS measurements")
+    ap.add_argument("--profile-mode", default="das", choices=("das", "pdas", "dmas"),
+                    help="with --profile-only: the beamformer of the timed loop (dmas and "
+                         "pdas run on the 128-channel 512 x 512 DMAS workload, pdas also "
+                         "takes the compound workload with --profile-compound)")
+    ap.add_argument("--profile-compound", action="store_true")
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0,
@@ -298,6 +362,22 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    if args.profile_only and args.profile_mode != "das":
+        from synth import config_c2
+        if args.profile_mode == "pdas" and args.profile_compound:
+            gp, rfp, bp = GeometryArg(gs, pdas_p=2.0), rf32, False
+        else:
+            g2 = config_c2()
+            gp, bp = GeometryArg(g2, bandpass=True, pdas_p=2.0), True
+            rfp = torch.from_numpy(make_frame(g2, 1001, "c1")["i16"]).to(dev)
+        wantp = ("rf", "filtered", "env", "log") if bp else ("rf", "env", "log")
+        outp = {k: torch.empty((gp.nx, gp.nz), dtype=torch.float32, device=dev) for k in wantp}
+        wall, _, _ = time_steps(lambda: beamform(gp, rfp, args.profile_mode, -1, want=wantp,
+                                                 out=outp, workspace=ws, bandpass=bp),
+                                args.steps, args.warmup, torch)
+        print(json.dumps({"profile_only": True, "mode": args.profile_mode,
+                          "ms_per_step": wall / args.steps * 1e3}))
+        return
     print("[bench] timing FP32-stored RF (headline)", file=sys.stderr, flush=True)
     wall, lat, span = time_steps(step32, args.steps, args.warmup, torch)
     if args.profile_only:
@@ -306,8 +386,8 @@ def main():
     print("[bench] timing FP16-stored RF", file=sys.stderr, flush=True)
     wall16, lat16, _ = time_steps(step16, args.steps, args.warmup, torch)
     print("[bench] timing the beamform kernel alone", file=sys.stderr, flush=True)
-    _, _, kspan = time_steps(kernel_only, args.steps, args.warmup, torch)
-    k_ms = kspan / args.steps
+    _, klat, _ = time_steps(kernel_only, args.steps, args.warmup, torch)
+    k_ms = float(np.mean(klat))  # average launch duration (HIP events around each launch)
 
     gathers = gs.gathers
     value = gathers * args.steps / wall / 1e9
@@ -351,6 +431,9 @@ def main():
                                      "latency_ms": {"p50": float(np.percentile(lat16, 50)),
                                                     "p99": float(np.percentile(lat16, 99))}}},
     }
+    if not args.no_modes:
+        print("[bench] DMAS and pDAS", file=sys.stderr, flush=True)
+        line["modes"] = other_modes(dev, torch, args.steps, args.warmup)
     if not args.no_systems:
         print("[bench] batched and served FP16 vs single-frame FP32", file=sys.stderr, flush=True)
         line["systems"] = systems(dev, torch, args.steps, args.warmup)

@@ -49,7 +49,7 @@
 extern "C" {
 #endif
 
-#define PWBF_ABI_VERSION 1u
+#define PWBF_ABI_VERSION 2u
 
 #ifndef PWBF_API
 #define PWBF_API __attribute__((visibility("default")))
@@ -69,6 +69,7 @@ extern "C" {
 /* Beamformer. */
 #define PWBF_DAS 0
 #define PWBF_DMAS 1
+#define PWBF_PDAS 2
 
 /* Apodization. */
 #define PWBF_APOD_HANN 0
@@ -100,6 +101,7 @@ typedef struct pwbf_geometry {
   int32_t bandpass;         /* 1: keep round-trip band [f0, 3 f0] along depth before
                                the envelope (needs dz <= c / (12 f0)); 0: none */
   double log_floor_db;      /* floor of the log image, dB, < 0 (e.g. -70) */
+  double pdas_p;            /* root order p of pDAS, 1 .. 16 (PWBF_PDAS only; else ignored) */
 } pwbf_geometry;
 
 /* Output planes, each a device float32 [nx][nz] buffer owned by the caller.
@@ -158,8 +160,16 @@ PWBF_API int pwbf_beamform_dmas(const pwbf_geometry *g, const void *rf, int32_t 
                        int32_t angle, const pwbf_outputs *out, void *workspace,
                        size_t workspace_bytes, void *stream);
 
+/* pDAS for one angle, Eqs. (2)-(3): the delayed samples are compressed to
+ * w_e sign(v_e) |v_e|^(1/p) (p = g->pdas_p), summed, and the sum restored by
+ * its signed p-th power, y = sign(t) |t|^p. p = 1 is DAS. Arguments and errors
+ * as for pwbf_beamform_das; PWBF_E_INVALID unless 1 <= p <= 16. */
+PWBF_API int pwbf_beamform_pdas(const pwbf_geometry *g, const void *rf, int32_t rf_dtype,
+                                int32_t angle, const pwbf_outputs *out, void *workspace,
+                                size_t workspace_bytes, void *stream);
+
 /* Coherent compounding: the unweighted sum over all n_angles of the per-angle
- * DAS (mode PWBF_DAS) or DMAS (mode PWBF_DMAS) images, in one pass that shares
+ * DAS (mode PWBF_DAS), DMAS (PWBF_DMAS) or pDAS (PWBF_PDAS) images, in one pass that shares
  * each pixel's receive delays and weights across the angles. Before
  * post-processing, compound(mode) equals the sum of beamform_<mode>(a) over a
  * (up to float32 summation order). Other arguments and errors as above. */

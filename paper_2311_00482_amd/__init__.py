@@ -17,6 +17,7 @@ from .api import (  # noqa: F401
     beamform,
     beamform_das,
     beamform_dmas,
+    beamform_pdas,
     compound,
     describe_plan,
     tune,

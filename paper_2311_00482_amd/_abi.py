@@ -12,10 +12,10 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpwbf.so")
 
-ABI_VERSION = 1
+ABI_VERSION = 2
 OK, E_INVALID, E_UNSUPPORTED, E_NOMEM, E_DEVICE, E_BUSY = 0, -1, -2, -3, -4, -5
 I16, F16, F32 = 0, 1, 2
-DAS, DMAS = 0, 1
+DAS, DMAS, PDAS = 0, 1, 2
 APOD_HANN, APOD_BOXCAR, APOD_NONE = 0, 1, 2
 MAX_ANGLES, MAX_CHANNELS, MAX_NZ_POST = 32, 256, 4096
 
@@ -44,7 +44,7 @@ class Geometry(ctypes.Structure):
         ("f_number", ctypes.c_double),
         ("apod", ctypes.c_int32),
         ("bandpass", ctypes.c_int32),
-        ("log_floor_db", ctypes.c_double),
+        ("log_floor_db", ctypes.c_double), ("pdas_p", ctypes.c_double),
     ]
 
 
@@ -143,7 +143,7 @@ def lib():
     L.pwbf_last_error.argtypes = []
     L.pwbf_workspace_bytes.restype = sz
     L.pwbf_workspace_bytes.argtypes = [G, O]
-    for name in ("pwbf_beamform_das", "pwbf_beamform_dmas"):
+    for name in ("pwbf_beamform_das", "pwbf_beamform_dmas", "pwbf_beamform_pdas"):
         f = getattr(L, name)
         f.restype = ctypes.c_int
         f.argtypes = [G, vp, i32, i32, O, vp, sz, vp]

@@ -17,7 +17,7 @@ import numpy as np
 from . import _abi
 
 _DTYPES = {"int16": _abi.I16, "float16": _abi.F16, "float32": _abi.F32}
-_MODES = {"das": _abi.DAS, "dmas": _abi.DMAS}
+_MODES = {"das": _abi.DAS, "dmas": _abi.DMAS, "pdas": _abi.PDAS}
 _APODS = {"hann": _abi.APOD_HANN, "boxcar": _abi.APOD_BOXCAR, "none": _abi.APOD_NONE}
 PLANES = ("rf", "filtered", "env", "log")
 
@@ -27,10 +27,12 @@ class GeometryArg:
 
     ``g`` is any object with the attributes elem_x, angles_rad, n_samples, c,
     fs, f0, nx, nz, x0, dx, z0, dz, f_number and apod (name) or apod_code;
-    t0_s (per-angle time of sample 0) is optional.
+    t0_s (per-angle time of sample 0) is optional. ``pdas_p`` is the pDAS root
+    order (used by mode "pdas" only).
     """
 
-    def __init__(self, g, bandpass: bool = False, log_floor_db: float = -70.0):
+    def __init__(self, g, bandpass: bool = False, log_floor_db: float = -70.0,
+                 pdas_p: float = 2.0):
         self.elem_x = np.ascontiguousarray(g.elem_x, dtype=np.float64)
         self.angles = np.ascontiguousarray(g.angles_rad, dtype=np.float64)
         t0 = getattr(g, "t0_s", None)
@@ -45,7 +47,7 @@ class GeometryArg:
             self.t0.ctypes.data_as(dp) if self.t0 is not None else None,
             float(g.c), float(g.fs), float(g.f0), int(g.nx), int(g.nz), float(g.x0),
             float(g.dx), float(g.z0), float(g.dz), float(g.f_number), int(apod),
-            1 if bandpass else 0, float(log_floor_db))
+            1 if bandpass else 0, float(log_floor_db), float(pdas_p))
         self.nx, self.nz = int(g.nx), int(g.nz)
         self.shape_rf = (len(self.angles), len(self.elem_x), int(g.n_samples))
 
@@ -124,8 +126,10 @@ def alloc_outputs(g, want: Iterable[str], device) -> Dict[str, "object"]:
 
 def beamform(g, rf, mode: str = "das", angle: int = -1, tile: Optional[Tile] = None,
              want: Iterable[str] = ("rf",), out: Optional[Dict] = None, workspace=None,
-             stream=None, bandpass: bool = False, log_floor_db: float = -70.0) -> Dict:
+             stream=None, bandpass: bool = False, log_floor_db: float = -70.0,
+             p: Optional[float] = None) -> Dict:
     """Run one frame through libpwbf. angle -1 = compound over all angles.
+    ``mode``: "das", "dmas" or "pdas" (root order ``p``, else the geometry's).
 
     ``rf``: CUDA tensor [n_angles, n_channels, n_samples] of int16/float16/float32.
     ``want``: planes among "rf", "filtered", "env", "log" (rf is always made).
@@ -137,6 +141,8 @@ def beamform(g, rf, mode: str = "das", angle: int = -1, tile: Optional[Tile] = N
     ga = _as_geom(g, bandpass, log_floor_db)
     if bandpass and not ga.s.bandpass:
         ga.s.bandpass = 1
+    if p is not None:
+        ga.s.pdas_p = float(p)
     if not rf.is_cuda or not rf.is_contiguous():
         raise ValueError("rf must be a contiguous CUDA tensor")
     if tuple(rf.shape) != ga.shape_rf:
@@ -176,6 +182,13 @@ def beamform_dmas(g, rf, angle: int, **kw) -> Dict:
     if angle < 0:
         raise ValueError("angle must be >= 0")
     return beamform(g, rf, "dmas", angle, **kw)
+
+
+def beamform_pdas(g, rf, angle: int, p: float = 2.0, **kw) -> Dict:
+    """pwbf_beamform_pdas: pDAS (Eqs. 2-3) of root order p for one steering angle."""
+    if angle < 0:
+        raise ValueError("angle must be >= 0")
+    return beamform(g, rf, "pdas", angle, p=p, **kw)
 
 
 def compound(g, rf, mode: str = "das", **kw) -> Dict:
@@ -226,6 +239,7 @@ class FrameSpec:
     out: Optional[Dict] = None
     bandpass: bool = False
     tile: Optional[Tile] = None
+    p: Optional[float] = None  # pDAS root order (mode "pdas"); None: the geometry's
 
 
 class Batch:
@@ -247,6 +261,8 @@ class Batch:
         keep = []
         for i, f in enumerate(frames):
             ga = _as_geom(f.geom, f.bandpass)
+            if f.p is not None:
+                ga.s.pdas_p = float(f.p)
             keep.append(ga)
             if not f.rf.is_cuda or not f.rf.is_contiguous() or tuple(f.rf.shape) != ga.shape_rf:
                 raise ValueError(f"frame {i}: rf must be a contiguous CUDA tensor {ga.shape_rf}")
@@ -297,6 +313,7 @@ class ProbeSpec:
     want: Iterable[str] = ("rf", "env", "log")
     slots: int = 4
     bandpass: bool = False
+    p: Optional[float] = None  # pDAS root order (mode "pdas")
 
 
 @dataclass
@@ -323,6 +340,9 @@ class Server:
 
     def __init__(self, probes, hbm_budget_bytes: int = 0, max_queue: int = 0):
         self._geoms = [_as_geom(p.geom, p.bandpass) for p in probes]
+        for p, ga in zip(probes, self._geoms):
+            if p.p is not None:
+                ga.s.pdas_p = float(p.p)
         arr = (_abi.Probe * len(probes))()
         for i, (p, ga) in enumerate(zip(probes, self._geoms)):
             want = set(p.want)

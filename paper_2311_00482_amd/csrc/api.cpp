@@ -91,6 +91,14 @@ int pwbf_beamform_dmas(const pwbf_geometry *g, const void *rf, int32_t rf_dtype,
              stream);
 }
 
+int pwbf_beamform_pdas(const pwbf_geometry *g, const void *rf, int32_t rf_dtype, int32_t angle,
+                       const pwbf_outputs *out, void *workspace, size_t workspace_bytes,
+                       void *stream) {
+  if (angle < 0) return set_error(PWBF_E_INVALID, "angle must be >= 0");
+  return run(g, rf, rf_dtype, pwbf::kPdas, angle, nullptr, out, workspace, workspace_bytes,
+             stream);
+}
+
 int pwbf_compound(const pwbf_geometry *g, const void *rf, int32_t rf_dtype, int32_t mode,
                   const pwbf_outputs *out, void *workspace, size_t workspace_bytes,
                   void *stream) {

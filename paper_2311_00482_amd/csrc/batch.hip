@@ -67,11 +67,16 @@ __global__ void __launch_bounds__(kWave * kBatchWaves)
         run_tile_mode<kDas, true>(P, tz, tx, smem);
       else
         run_tile_mode<kDas, false>(P, tz, tx, smem);
-    } else {
+    } else if (P.mode == kDmas) {
       if (P.cpw == 1)
         run_tile_mode<kDmas, true>(P, tz, tx, smem);
       else
         run_tile_mode<kDmas, false>(P, tz, tx, smem);
+    } else {
+      if (P.cpw == 1)
+        run_tile_mode<kPdas, true>(P, tz, tx, smem);
+      else
+        run_tile_mode<kPdas, false>(P, tz, tx, smem);
     }
   }
 }

@@ -37,11 +37,16 @@ hipError_t launch_am(const FramePlan &P, hipStream_t stream) {
       hipLaunchKernelGGL((k_beamform<AM, PRED, kDas, true>), grid, block, lds, stream, P);
     else
       hipLaunchKernelGGL((k_beamform<AM, PRED, kDas, false>), grid, block, lds, stream, P);
-  } else {
+  } else if (P.mode == kDmas) {
     if (one)
       hipLaunchKernelGGL((k_beamform<AM, PRED, kDmas, true>), grid, block, lds, stream, P);
     else
       hipLaunchKernelGGL((k_beamform<AM, PRED, kDmas, false>), grid, block, lds, stream, P);
+  } else {
+    if (one)
+      hipLaunchKernelGGL((k_beamform<AM, PRED, kPdas, true>), grid, block, lds, stream, P);
+    else
+      hipLaunchKernelGGL((k_beamform<AM, PRED, kPdas, false>), grid, block, lds, stream, P);
   }
   return hipGetLastError();
 }

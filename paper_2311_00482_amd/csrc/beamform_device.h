@@ -21,7 +21,8 @@
 // weight are computed once and reused for every angle. Per (pixel, channel,
 // angle) the DAS gather costs an add, a floor, an address, one LDS read and two
 // accumulate operations. DMAS adds the fraction, a square root and the
-// signed-root accumulation per gather.
+// signed-root accumulation per gather; pDAS takes the p-th root through the
+// hardware base-2 logarithm and exponential instead of the square root.
 
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
@@ -297,10 +298,10 @@ __device__ __forceinline__ void process_tile(const FramePlan &P, int tz, int tx,
     if (!PRED || a < A) txl[a] = s_txq[a] + fmaf(dx, P.sa[a], dz * P.ca[a]);
 
   float total = 0.f;
-  float S[MODE == kDmas ? AM : 1];
+  float S[MODE == kDas ? 1 : AM];  // per-angle sums of compressed samples (DMAS, pDAS)
   float Q = 0.f;
 #pragma unroll
-  for (int a = 0; a < (MODE == kDmas ? AM : 1); ++a) S[a] = 0.f;
+  for (int a = 0; a < (MODE == kDas ? 1 : AM); ++a) S[a] = 0.f;
 
   for (int e0 = e_lo; e0 < e_hi; e0 += chunk) {
     if (e0 > e_lo) __syncthreads();  // the previous chunk's windows have been read
@@ -359,6 +360,21 @@ __device__ __forceinline__ void process_tile(const FramePlan &P, int tz, int tx,
           }
         }
         total = fmaf(w, acc, total);
+      } else if constexpr (MODE == kPdas) {
+        // sign(v) |v|^(1/p) = sign(v) 2^(log2|v| / p); |v| = 0 gives 2^-inf = 0
+        const float ip = P.pdas_inv_p;
+#pragma unroll
+        for (int a = 0; a < AM; ++a) {
+          if (!PRED || a < A) {
+            const float s = txl[a] + rxl;
+            const int n = floor_i32(s);
+            const float f = __builtin_amdgcn_fractf(s);
+            const float2 p = *(const float2 *)(wb + a * wstride + (n << 3));
+            const float v = fmaf(f, p.y, p.x);
+            const float r = __builtin_amdgcn_exp2f(ip * __builtin_amdgcn_logf(fabsf(v)));
+            S[a] = fmaf(w, copysignf(r, v), S[a]);
+          }
+        }
       } else {
         float q = 0.f;
 #pragma unroll
@@ -383,6 +399,17 @@ __device__ __forceinline__ void process_tile(const FramePlan &P, int tz, int tx,
   if constexpr (MODE == kDas) {
     for (int off = ppw; off < kWave; off <<= 1) total += __shfl_xor(total, off);
     y = total;
+  } else if constexpr (MODE == kPdas) {
+    // per angle the signed p-th power of the summed roots; the angles add
+    y = 0.f;
+#pragma unroll
+    for (int a = 0; a < AM; ++a) {
+      if (!PRED || a < A) {
+        float t = S[a];
+        for (int off = ppw; off < kWave; off <<= 1) t += __shfl_xor(t, off);
+        y += copysignf(__builtin_amdgcn_exp2f(P.pdas_p * __builtin_amdgcn_logf(fabsf(t))), t);
+      }
+    }
   } else {
     for (int off = ppw; off < kWave; off <<= 1) Q += __shfl_xor(Q, off);
     float sq = 0.f;

@@ -238,7 +238,10 @@ static int plan_frame_uncached(const pwbf_geometry *g, int dtype, int mode, int 
   if (rc) return rc;
   if (dtype != kI16 && dtype != kF16 && dtype != kF32)
     return fail(err, PWBF_E_INVALID, "rf_dtype %d unknown", dtype);
-  if (mode != kDas && mode != kDmas) return fail(err, PWBF_E_INVALID, "mode %d unknown", mode);
+  if (mode != kDas && mode != kDmas && mode != kPdas)
+    return fail(err, PWBF_E_INVALID, "mode %d unknown", mode);
+  if (mode == kPdas && !(g->pdas_p >= 1.0 && g->pdas_p <= 16.0))
+    return fail(err, PWBF_E_INVALID, "pdas_p = %g outside 1..16", g->pdas_p);
   if (angle < -1 || angle >= g->n_angles)
     return fail(err, PWBF_E_INVALID, "angle %d outside 0..%d", angle, g->n_angles - 1);
   if (mode == kDmas && g->n_channels < 2)
@@ -265,6 +268,8 @@ static int plan_frame_uncached(const pwbf_geometry *g, int dtype, int mode, int 
   split(g->z0 * scale, &P->Z0, &P->Z0l);
   split(g->dz * scale, &P->DZ, &P->DZl);
   P->ap_k = g->apod == kNone ? 0.0f : (float)(2.0 * g->f_number);
+  P->pdas_p = mode == kPdas ? (float)g->pdas_p : 1.0f;
+  P->pdas_inv_p = mode == kPdas ? (float)(1.0 / g->pdas_p) : 1.0f;
   for (int e = 0; e < kMaxChannels; ++e)
     split(g->elem_x[std::min(e, g->n_channels - 1)] * scale, &P->xe[e], &P->xel[e]);
   for (int k = 0; k < na; ++k) {
@@ -424,8 +429,10 @@ int tile_active_channels(const pwbf_geometry *g, const FramePlan &P, int tile) {
 }
 
 double tile_cost(const pwbf_geometry *g, const FramePlan &P, int tile) {
+  // a DMAS gather costs about twice a DAS one, a pDAS gather (log and exp) 2.5 times
+  const double mode_factor = P.mode == kDmas ? 2.0 : (P.mode == kPdas ? 2.5 : 1.0);
   return (double)tile_active_channels(g, P, tile) * P.tile_z * P.tile_x * (P.n_angles + 2) *
-         (P.mode == kDmas ? 2.0 : 1.0);
+         mode_factor;
 }
 
 int build_post_plan(const pwbf_geometry *g, const pwbf_outputs *o, void *ws, PostPlan *Q) {

@@ -29,7 +29,7 @@ constexpr int kDefaultLdsBytes = 52 * 1024;
 constexpr int kMaxNzPost = 4096;
 
 enum Dtype : int32_t { kI16 = 0, kF16 = 1, kF32 = 2 };
-enum Mode : int32_t { kDas = 0, kDmas = 1 };
+enum Mode : int32_t { kDas = 0, kDmas = 1, kPdas = 2 };
 enum Apod : int32_t { kHann = 0, kBoxcar = 1, kNone = 2 };
 
 struct FramePlan {
@@ -44,6 +44,7 @@ struct FramePlan {
   float X0, DX, Z0, DZ;      // centre of pixel (0, 0) and pitches, samples (hi)
   float X0l, DXl, Z0l, DZl;  // ... and their lo parts
   float ap_k;            // 2 F#: normalised aperture distance r = |X - Xe| * ap_k / Z
+  float pdas_p, pdas_inv_p;  // pDAS root order p and 1 / p (mode kPdas)
   // launch shape
   int32_t cpw, lz, lx, wz, wx, chunk;  // lane groups, lanes along z/x per group, waves
   int32_t win;           // LDS entries per (channel, angle) window

@@ -82,11 +82,16 @@ __global__ void __launch_bounds__(kWave * kServeWaves)
         serve_tile_mode<kDas, true>(P, tz, tx, smem);
       else
         serve_tile_mode<kDas, false>(P, tz, tx, smem);
-    } else {
+    } else if (P.mode == kDmas) {
       if (P.cpw == 1)
         serve_tile_mode<kDmas, true>(P, tz, tx, smem);
       else
         serve_tile_mode<kDmas, false>(P, tz, tx, smem);
+    } else {
+      if (P.cpw == 1)
+        serve_tile_mode<kPdas, true>(P, tz, tx, smem);
+      else
+        serve_tile_mode<kPdas, false>(P, tz, tx, smem);
     }
   }
 }

@@ -58,6 +58,7 @@ def test_entry_points_reject_null_geometry_first():
     o = ctypes.byref(_abi.Outputs(FAKE, None, None, None))
     assert L.pwbf_beamform_das(None, FAKE, 0, 0, o, None, 0, None) == _abi.E_INVALID
     assert L.pwbf_beamform_dmas(None, FAKE, 0, 0, o, None, 0, None) == _abi.E_INVALID
+    assert L.pwbf_beamform_pdas(None, FAKE, 0, 0, o, None, 0, None) == _abi.E_INVALID
     assert L.pwbf_compound(None, FAKE, 0, 0, o, None, 0, None) == _abi.E_INVALID
     assert L.pwbf_beamform_ex(None, FAKE, 0, 0, -1, None, o, None, 0, None) == _abi.E_INVALID
     assert "NULL" in L.pwbf_last_error().decode()
@@ -125,6 +126,19 @@ def test_call_argument_validation():
     assert rc == _abi.E_INVALID and "bandpass" in msg
     one = GeometryArg(config_c1().replace(n_channels=1))
     assert _call(one, mode=_abi.DMAS)[0] == _abi.E_INVALID
+
+
+@pytest.mark.parametrize("p,code", [(1.0, 0), (2.0, 0), (3.5, 0), (16.0, 0), (0.99, -1),
+                                    (0.0, -1), (16.5, -1), (float("nan"), -1),
+                                    (float("inf"), -1)])
+def test_pdas_root_order_validation(p, code):
+    g = GeometryArg(config_c1(), pdas_p=p)
+    rc, msg = _call(g, mode=_abi.PDAS)
+    assert rc == code, msg
+    if code:
+        assert "pdas_p" in msg
+    # other modes ignore the field
+    assert _call(g, mode=_abi.DAS)[0] == 0
 
 
 def test_post_processing_shape_rules():

@@ -60,6 +60,8 @@ def mixed_frames(dev, seed=0):
          ("rf", "filtered", "env", "log"), True, "f32"),
         (geom(angles_deg=tuple(range(-6, 8, 2)), nx=17, nz=32), "das", 3, Tile(1, 32, 2, 4, 0),
          ("rf", "log"), False, "f32"),
+        (geom(angles_deg=(-5.0, 5.0), n_channels=20, nx=30, nz=64), "pdas", -1,
+         Tile(1, 16, 1, 8, 0), ("rf", "env"), False, "i16"),
     ]
     frames, ref_args = [], []
     for i, (g, mode, angle, tile, want, bp, kind) in enumerate(specs):

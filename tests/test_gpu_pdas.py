@@ -1,0 +1,107 @@
+"""GPU parity of pDAS (Eqs. 2-3) against the FP64 oracle, element by element.
+
+Bars (max-normalised error per plane): as for the other float32 paths, 1e-5,
+widened where the arithmetic says so. The p-th root is steep at zero: a
+perturbation d of a delayed sample near a zero crossing moves its compressed
+value by up to d^(1/p), so relative to the square root of DMAS the bar grows by
+(2^-24)^(1/p - 1/2) for p > 2 (x16 at p = 3); with fewer than 16 channels
+nothing averages that out, and those cases use 3e-5 as DMAS does.
+"""
+
+import zlib
+
+import numpy as np
+import pytest
+
+import oracle
+from synth import config_c2, make_frame
+
+from cases import geom, rand_rf
+
+pytestmark = pytest.mark.gpu
+
+TOL32 = 1e-5
+
+
+def _torch():
+    import torch
+    assert torch.cuda.is_available(), "these tests need the GPU"
+    return torch
+
+
+def run(g, rf_t, angle, p, want=("rf",), tile=None, bandpass=False):
+    from paper_2311_00482_amd import beamform
+    torch = _torch()
+    out = beamform(g, rf_t, "pdas", angle, tile=tile, want=want, bandpass=bandpass, p=p)
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy().astype(np.float64) for k, v in out.items()}
+
+
+def err(gpu, ora):
+    m = np.abs(ora).max()
+    return float(np.abs(gpu - ora).max() / m) if m > 0 else float(np.abs(gpu).max())
+
+
+def tol_pdas(g, p, angle, tile=None):
+    from paper_2311_00482_amd import Tile, describe_plan
+    t = Tile(*tile) if tile else None
+    win = describe_plan(g, "pdas", angle, t)["win"]
+    tol = TOL32 * max(1.0, win / 64.0)
+    if p > 1.0 and g.n_channels < 16:
+        tol = max(tol, 3e-5)
+    if p > 2.0:
+        tol *= 2.0 ** (24.0 * (0.5 - 1.0 / p))
+    return tol
+
+
+PDAS_SMALL = [
+    # name, geometry kwargs, angle, tile, p, dtype
+    ("p2_one_angle", dict(), 0, None, 2.0, "f32"),
+    ("p2_ragged_cpw2", dict(nx=21, nz=77, n_channels=12), 0, (2, 16, 1, 4, 4), 2.0, "f32"),
+    ("p1_compound_is_das", dict(angles_deg=(-6.0, 0.0, 6.0)), -1, None, 1.0, "f32"),
+    ("p3_compound_5a", dict(angles_deg=(-10.0, -5.0, 0.0, 5.0, 10.0), n_channels=24), -1, None,
+     3.0, "i16"),
+    ("p1_5_generic_angles", dict(angles_deg=tuple(range(-18, 18, 2)), nx=7, nz=40,
+                                 n_channels=6), -1, (4, 4, 1, 2, 0), 1.5, "f32"),
+    ("p2_boxcar_cpw4", dict(apod="boxcar", n_channels=20, nx=9, nz=33), 0, (4, 16, 1, 3, 4),
+     2.0, "f32"),
+]
+
+
+@pytest.mark.parametrize("name,kw,angle,tile,p,kind", PDAS_SMALL, ids=[c[0] for c in PDAS_SMALL])
+def test_pdas_small_cases_whole_image(name, kw, angle, tile, p, kind):
+    from paper_2311_00482_amd import Tile
+    torch = _torch()
+    g = geom(**kw)
+    rf = rand_rf(g, zlib.crc32(name.encode()) % 1000, kind)
+    rf_t = torch.from_numpy(rf).cuda()
+    out = run(g, rf_t, angle, p, tile=Tile(*tile) if tile else None)["rf"]
+    ref = oracle.pdas(g, rf.astype(np.float64), angle, p)
+    e = err(out, ref)
+    assert e <= tol_pdas(g, p, angle, tile), e
+    if p == 1.0:
+        # p = 1 is DAS: the DAS oracle is the same reference
+        assert err(out, oracle.das(g, rf.astype(np.float64), angle)) <= tol_pdas(g, p, angle, tile)
+
+
+def test_pdas_full_dmas_workload_grid():
+    # 128 channels, 512 x 512 at dz = 25 um, int16 RF: the whole image against the oracle
+    torch = _torch()
+    g = config_c2()
+    fr = make_frame(g, 1001, "c1")
+    rf_t = torch.from_numpy(fr["i16"]).cuda()
+    out = run(g, rf_t, 0, 2.0, want=("rf", "env"))
+    ref = oracle.pdas(g, fr["master"], 0, 2.0)
+    assert err(out["rf"], ref) <= TOL32
+    env = oracle.envelope_z(ref)
+    assert err(out["env"], env) <= TOL32
+
+
+def test_pdas_odd_in_the_data():
+    torch = _torch()
+    g = geom(angles_deg=(-4.0, 7.0), n_channels=20)
+    rf = rand_rf(g, 77, "i16")
+    a = run(g, torch.from_numpy(rf).cuda(), -1, 2.5)["rf"]
+    b = run(g, torch.from_numpy(-rf).cuda(), -1, 2.5)["rf"]
+    # negating int16 data negates every sample exactly; the image flips sign bit for bit
+    assert np.array_equal(a, -b)
