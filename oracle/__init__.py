@@ -4,7 +4,8 @@ TEST INFRASTRUCTURE ONLY. This package is what the GPU path is checked against:
 only ``tests/``, the smoke check and the benchmark's CPU-baseline leg may import
 it. It shares no code with the GPU library and never imports it.
 
-The per-pixel beamformers (DAS, compound, RF DMAS in two forms, pDAS) are plain C in
+The per-pixel beamformers (DAS, compound, RF DMAS in two forms, pDAS, IQ-DAS and
+BB-DMAS on baseband data) are plain C in
 ``pwbf_oracle.c``, single-threaded FP64; the column post-processing along depth
 (band-pass, Hilbert envelope, log compression) is NumPy FP64 with ``numpy.fft``
 as the transform. Geometry objects are duck-typed: anything with the attributes
@@ -13,7 +14,8 @@ f_number, apod_code, n_samples, f0).
 
 Paper passages followed: Eq. (1) and the delay text after it (DAS); Eq. (2) and
 Eq. (4) for the signed-root compression and the squared-sum form of DMAS;
-Eqs. (2)-(3) for pDAS (p-th root before the sum, signed p-th power after); the
+Eqs. (2)-(3) for pDAS (p-th root before the sum, signed p-th power after);
+Eq. (4) for BB-DMAS on IQ data, with IQ-DAS as Eq. (1) on the same data; the
 absolute value of the analytic signal for the image; the -70 dB display range
 (Fig. 3 caption). Every function is pinned by CPU tests against closed forms,
 invariants and an independent brute-force evaluation; none is "parity unpinned".
@@ -75,6 +77,10 @@ def _load():
         lib.ora_dmas.restype = ctypes.c_int
         lib.ora_dmas.argtypes = [P, ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32,
                                  ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]
+        lib.ora_iq.restype = ctypes.c_int
+        lib.ora_iq.argtypes = [P, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
+                               ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64,
+                               ctypes.c_void_p, ctypes.c_void_p]
         lib.ora_pdas.restype = ctypes.c_int
         lib.ora_pdas.argtypes = [P, ctypes.c_void_p, ctypes.c_int32, ctypes.c_double,
                                  ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]
@@ -172,6 +178,51 @@ def pdas(g, rf, angle: int = -1, p: float = 2.0, pix=None) -> np.ndarray:
     if rc != 0:
         raise ValueError("ora_pdas rejected its arguments")
     return out.reshape(g.nx, g.nz) if q is None else out
+
+
+def iq_demodulate(g, rf, fd: Optional[float] = None) -> np.ndarray:
+    """Baseband (IQ) channel records: the analytic signal of each record (one-sided
+    spectrum along samples: 1 at DC and Nyquist, 2 on positive bins, 0 on
+    negative ones) times exp(-2 pi i fd n / fs), fd = f0 by default; complex128
+    [n_angles][n_channels][n_samples]. n_samples must be even."""
+    rf = _rf64(g, rf)
+    ns = rf.shape[-1]
+    assert ns % 2 == 0
+    fd = float(g.f0 if fd is None else fd)
+    h = np.zeros(ns)
+    h[0] = 1.0
+    h[1:ns // 2] = 2.0
+    h[ns // 2] = 1.0
+    analytic = np.fft.ifft(np.fft.fft(rf, axis=-1) * h, axis=-1)
+    n = np.arange(ns)
+    return analytic * np.exp(-2j * np.pi * fd * n / g.fs)
+
+
+def iq_beamform(g, iq, form: str = "iqdas", angle: int = -1, fd: Optional[float] = None,
+                pix=None) -> np.ndarray:
+    """IQ-DAS ("iqdas") or BB-DMAS ("bbdmas", Eq. 4) from baseband records ``iq``
+    demodulated at fd (f0 by default); complex, [nx, nz] or at ``pix``. angle -1
+    sums the complex per-angle values."""
+    b = _Bound(g)
+    iq = np.asarray(iq)
+    if iq.ndim == 2:
+        iq = iq[None]
+    assert iq.shape == (len(g.angles_rad), len(g.elem_x), g.n_samples), iq.shape
+    re = np.ascontiguousarray(iq.real, dtype=np.float64)
+    im = np.ascontiguousarray(iq.imag, dtype=np.float64)
+    q = _pix(g, pix)
+    n = g.nx * g.nz if q is None else len(q)
+    out_re = np.empty(n)
+    out_im = np.empty(n)
+    fd = float(g.f0 if fd is None else fd)
+    rc = _load().ora_iq(b.ref, re.ctypes.data, im.ctypes.data, fd,
+                        {"iqdas": 0, "bbdmas": 1}[form], angle,
+                        None if q is None else q.ctypes.data, n, out_re.ctypes.data,
+                        out_im.ctypes.data)
+    if rc != 0:
+        raise ValueError("ora_iq rejected its arguments")
+    y = out_re + 1j * out_im
+    return y.reshape(g.nx, g.nz) if q is None else y
 
 
 def compound(g, rf, mode: str = "das", pix=None, p: float = 2.0) -> np.ndarray:

@@ -45,6 +45,17 @@ MUTANTS = {
     "pdas_unsigned_power": ("return sgn(yt) * pow(fabs(yt), p);", "return pow(fabs(yt), p);"),
     "pdas_root_order": ("return sgn(yt) * pow(fabs(yt), p);",
                         "return sgn(yt) * pow(fabs(yt), 1.0 / p);"),
+    "iq_rotation_sign": ("const double ph = 2.0 * M_PI * fd * s / g->fs;",
+                         "const double ph = -2.0 * M_PI * fd * s / g->fs;"),
+    "iq_no_rotation": ("const double ph = 2.0 * M_PI * fd * s / g->fs;",
+                       "const double ph = 0.0 * fd * s;"),
+    "bbdmas_no_root": ("const double k = amp > 0.0 ? 1.0 / sqrt(amp) : 0.0;",
+                       "const double k = 1.0;"),
+    "bbdmas_weight_inside_root": ("    sr += w * vr;\n    si += w * vi;",
+                                  "    sr += (form == 1 ? sqrt(w) : w) * vr;\n"
+                                  "    si += (form == 1 ? sqrt(w) : w) * vi;"),
+    "bbdmas_not_squared": ("    *yr = sr * sr - si * si;\n    *yi = 2.0 * sr * si;",
+                           "    *yr = sr;\n    *yi = si;"),
     "compound_keeps_last": (
         "for (int32_t a = 0; a < g->n_angles; ++a) y += das_one_angle(g, rf, a, first[a], x, z);",
         "for (int32_t a = 0; a < g->n_angles; ++a) y = das_one_angle(g, rf, a, first[a], x, z);"),

@@ -292,6 +292,81 @@ def test_pdas_p2_is_twice_dmas_plus_das_for_boxcar_positive_data():
     np.testing.assert_allclose(lhs, rhs, atol=1e-12 * np.abs(rhs).max())
 
 
+# ------------------------------------------------------------ IQ-DAS, BB-DMAS
+def test_iq_das_without_demodulation_is_das_of_the_analytic_signal():
+    # fd = 0: the baseband record is the analytic signal itself, so IQ-DAS is the
+    # DAS of the record plus i times the DAS of its Hilbert transform (scipy's)
+    from scipy.signal import hilbert
+    g = small_geom(angles_deg=(-3.0, 5.0), n_samples=512)
+    rf = _rand_rf(g, 31)
+    iq = oracle.iq_demodulate(g, rf, fd=0.0)
+    y = oracle.iq_beamform(g, iq, "iqdas", -1, fd=0.0)
+    ref = oracle.das(g, rf, -1) + 1j * oracle.das(g, np.imag(hilbert(rf, axis=-1)), -1)
+    np.testing.assert_allclose(y, ref, atol=1e-11 * np.abs(ref).max())
+
+
+def _tone(g, k, theta):
+    n = np.arange(g.n_samples)
+    u = np.cos(2 * np.pi * k * n / g.n_samples + theta)
+    return np.broadcast_to(u, (g.n_angles, g.n_channels, g.n_samples)).copy()
+
+
+def test_iq_demodulation_of_an_integer_bin_tone_is_constant():
+    g = small_geom(n_samples=512)
+    k, theta = 128, 0.7  # fd = k fs / Ns = fs / 4
+    iq = oracle.iq_demodulate(g, _tone(g, k, theta), fd=k * g.fs / g.n_samples)
+    np.testing.assert_allclose(iq, np.exp(1j * theta), atol=1e-12)
+
+
+def _tone_sums(g, fd, theta):
+    """sum_e w_e exp(i (2 pi fd s_e / fs + theta)) per pixel, from the pinned delay
+    and weight functions."""
+    out = np.zeros((g.nx, g.nz), dtype=complex)
+    for ix, x in enumerate(g.x_pix):
+        for iz, z in enumerate(g.z_pix):
+            for e in range(g.n_channels):
+                s = oracle.tof_samples(g, 0, e, x, z)
+                assert 1.0 < s < g.n_samples - 2
+                out[ix, iz] += oracle.apod_weight(g, e, x, z) * np.exp(
+                    1j * (2 * np.pi * fd * s / g.fs + theta))
+    return out
+
+
+def test_iq_das_and_bb_dmas_of_a_tone_in_closed_form():
+    g = small_geom(angles_deg=(4.0,), n_samples=512, nx=6, nz=7, n_channels=9)
+    k, theta = 128, -1.1
+    fd = k * g.fs / g.n_samples
+    iq = oracle.iq_demodulate(g, _tone(g, k, theta), fd=fd)
+    sums = _tone_sums(g, fd, theta)
+    np.testing.assert_allclose(oracle.iq_beamform(g, iq, "iqdas", 0, fd=fd), sums, atol=1e-9)
+    # |q| = 1 everywhere, so the square root leaves every sample unchanged
+    np.testing.assert_allclose(oracle.iq_beamform(g, iq, "bbdmas", 0, fd=fd), sums ** 2,
+                               atol=1e-8)
+
+
+def test_bb_dmas_single_channel_closed_form():
+    # one element: (w sqrt(a) e^{i phi})^2 = w^2 a e^{2 i phi} = w y_iqdas^2 / |y_iqdas|
+    g = small_geom(n_channels=1, x_min=-1.5e-3, x_max=1.5e-3, f_number=2.0, n_samples=512)
+    rf = _rand_rf(g, 32)
+    iq = oracle.iq_demodulate(g, rf)
+    y1 = oracle.iq_beamform(g, iq, "iqdas", 0)
+    yb = oracle.iq_beamform(g, iq, "bbdmas", 0)
+    w = np.array([[oracle.apod_weight(g, 0, x, z) for z in g.z_pix] for x in g.x_pix])
+    assert 0 < np.count_nonzero(w) < w.size
+    expect = np.where(np.abs(y1) > 0, w * y1 ** 2 / np.where(y1 == 0, 1, np.abs(y1)), 0)
+    np.testing.assert_allclose(yb, expect, atol=1e-12 * np.abs(expect).max())
+
+
+def test_iq_compound_is_sum_of_angles():
+    g = small_geom(angles_deg=(-8.0, 1.0, 6.0), n_samples=512)
+    rf = _rand_rf(g, 33)
+    iq = oracle.iq_demodulate(g, rf)
+    for form in ("iqdas", "bbdmas"):
+        per = sum(oracle.iq_beamform(g, iq, form, a) for a in range(3))
+        np.testing.assert_allclose(oracle.iq_beamform(g, iq, form, -1), per,
+                                   atol=1e-12 * np.abs(per).max())
+
+
 # ------------------------------------------------------------ brute force 4x4
 def brute_das_dmas(g, rf, p=2.5):
     """Independent evaluation: numpy.interp on a zero-padded record, Hann as a
@@ -332,6 +407,41 @@ def brute_das_dmas(g, rf, p=2.5):
     return das, dmas, pdas
 
 
+def brute_iq(g, rf, fd):
+    """Independent IQ path: scipy's analytic signal, numpy.interp on the real and
+    imaginary parts of the zero-padded baseband record, cmath rotation, Hann as a
+    squared cosine; returns IQ-DAS and BB-DMAS (compound sums)."""
+    import cmath
+    from scipy.signal import hilbert
+    A, N, Ns = rf.shape
+    n = np.arange(Ns)
+    iq = hilbert(rf, axis=-1) * np.exp(-2j * np.pi * fd * n / g.fs)
+    grid = np.arange(-1, Ns + 1, dtype=np.float64)
+    yd = np.zeros((g.nx, g.nz), dtype=complex)
+    yb = np.zeros((g.nx, g.nz), dtype=complex)
+    for a in range(A):
+        th = math.radians(g.angles_deg[a])
+        for ix in range(g.nx):
+            x = g.x_min + (ix + 0.5) * (g.x_max - g.x_min) / g.nx
+            for iz in range(g.nz):
+                z = g.z_min + (iz + 0.5) * (g.z_max - g.z_min) / g.nz
+                path_tx = x * math.sin(th) + z * math.cos(th) - (g.elem_x * math.sin(th)).min()
+                sd, sb = 0j, 0j
+                for e in range(N):
+                    s = (path_tx + math.hypot(x - g.elem_x[e], z)) / g.c * g.fs - g.t0_s[a] * g.fs
+                    re = float(np.interp(s, grid, np.concatenate([[0.0], iq[a, e].real, [0.0]])))
+                    im = float(np.interp(s, grid, np.concatenate([[0.0], iq[a, e].imag, [0.0]])))
+                    v = complex(re, im) * cmath.exp(2j * math.pi * fd * s / g.fs)
+                    half = z / (2 * g.f_number)
+                    d = abs(x - g.elem_x[e])
+                    w = math.cos(math.pi * d / (2 * half)) ** 2 if (z > 0 and d < half) else 0.0
+                    sd += w * v
+                    sb += w * (math.sqrt(abs(v)) * cmath.exp(1j * cmath.phase(v)) if v != 0 else 0)
+                yd[ix, iz] += sd
+                yb[ix, iz] += sb * sb
+    return yd, yb
+
+
 @pytest.mark.parametrize("seed,angles", [(11, (0.0,)), (12, (-9.0, 3.0, 10.0))])
 def test_brute_force_4x4(seed, angles):
     g = Geometry(n_channels=8, n_samples=400, angles_deg=angles, nx=4, nz=4, x_min=-1e-3,
@@ -343,6 +453,14 @@ def test_brute_force_4x4(seed, angles):
     np.testing.assert_allclose(oracle.compound(g, rf, "pdas", p=2.5), bp,
                                atol=1e-12 * np.abs(bp).max())
     assert np.abs(bd).max() > 0 and np.abs(bm).max() > 0 and np.abs(bp).max() > 0
+    g2 = g.replace(n_samples=512)
+    rf2 = _rand_rf(g2, seed + 100)
+    yd, yb = brute_iq(g2, rf2, g2.f0)
+    iq = oracle.iq_demodulate(g2, rf2)
+    np.testing.assert_allclose(oracle.iq_beamform(g2, iq, "iqdas", -1), yd,
+                               atol=1e-10 * np.abs(yd).max())
+    np.testing.assert_allclose(oracle.iq_beamform(g2, iq, "bbdmas", -1), yb,
+                               atol=1e-10 * np.abs(yb).max())
 
 
 # ------------------------------------------------------------- post-processing
