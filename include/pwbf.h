@@ -49,7 +49,7 @@
 extern "C" {
 #endif
 
-#define PWBF_ABI_VERSION 2u
+#define PWBF_ABI_VERSION 3u
 
 #ifndef PWBF_API
 #define PWBF_API __attribute__((visibility("default")))
@@ -65,11 +65,14 @@ extern "C" {
 #define PWBF_I16 0
 #define PWBF_F16 1
 #define PWBF_F32 2
+#define PWBF_C32 3 /* complex float32 (re, im interleaved): baseband IQ samples */
 
 /* Beamformer. */
 #define PWBF_DAS 0
 #define PWBF_DMAS 1
 #define PWBF_PDAS 2
+#define PWBF_IQDAS 3  /* DAS on IQ data (input PWBF_C32) */
+#define PWBF_BBDMAS 4 /* BB-DMAS on IQ data, Eq. (4) (input PWBF_C32) */
 
 /* Apodization. */
 #define PWBF_APOD_HANN 0
@@ -107,12 +110,15 @@ typedef struct pwbf_geometry {
 /* Output planes, each a device float32 [nx][nz] buffer owned by the caller.
  * rf is required; the others may be NULL. filtered needs bandpass = 1. The
  * envelope and the log image are taken from the band-passed image when
- * bandpass = 1, else from rf. */
+ * bandpass = 1, else from rf. For the IQ modes the image is complex: rf holds
+ * its real part, imag its imaginary part, env its magnitude (the displayed
+ * image of Eq. (4)); filtered must be NULL. */
 typedef struct pwbf_outputs {
-  float *rf;       /* beamformed image: DAS sum, or raw DMAS */
+  float *rf;       /* beamformed image: DAS sum, raw DMAS or pDAS; real part (IQ modes) */
   float *filtered; /* band-passed image */
-  float *env;      /* envelope along depth */
+  float *env;      /* envelope along depth; |image| (IQ modes) */
   float *logimg;   /* 20 log10(env / max env), clipped at log_floor_db */
+  float *imag;     /* imaginary part of the image (IQ modes only), or NULL */
 } pwbf_outputs;
 
 /* Launch shape of the beamforming kernel. Zeros select the library default.
@@ -168,8 +174,38 @@ PWBF_API int pwbf_beamform_pdas(const pwbf_geometry *g, const void *rf, int32_t 
                                 int32_t angle, const pwbf_outputs *out, void *workspace,
                                 size_t workspace_bytes, void *stream);
 
+/* Baseband (IQ) channel data: for every record RF[a][e][:], the analytic signal
+ * (one-sided spectrum along samples: 1 at DC and Nyquist, 2 on positive bins, 0
+ * on negative ones) times exp(-2 pi i f0 n / fs), sample n of the record; the
+ * demodulation of the IQ path of Section II-B, read without decimation.
+ *  rf   device RF[n_angles][n_channels][n_samples] of rf_dtype (int16, FP16, FP32)
+ *  iq   device complex float32 [n_angles][n_channels][n_samples] (8 bytes per
+ *       sample, re then im), owned by the caller, 8-byte aligned; overwritten
+ * Needs n_samples a power of two in 2..4096 and f0 > 0 (PWBF_E_UNSUPPORTED /
+ * PWBF_E_INVALID). No workspace; enqueued on stream. */
+PWBF_API int pwbf_iq_demodulate(const pwbf_geometry *g, const void *rf, int32_t rf_dtype,
+                                void *iq, void *stream);
+
+/* DAS on IQ data for one angle: with q_e the baseband record of element e
+ * interpolated linearly at the delay s_e and rotated back by exp(2 pi i f0 s_e / fs),
+ * y = sum_e w_e q_e (Eq. (1) on the delay-compensated IQ signals). iq from
+ * pwbf_iq_demodulate (rf_dtype PWBF_C32). Outputs: rf = Re y, imag = Im y,
+ * env = |y|, logimg from env; bandpass must be 0 and filtered NULL. */
+PWBF_API int pwbf_beamform_iqdas(const pwbf_geometry *g, const void *iq, int32_t angle,
+                                 const pwbf_outputs *out, void *workspace,
+                                 size_t workspace_bytes, void *stream);
+
+/* BB-DMAS for one angle, Eq. (4): y = (sum_e w_e sqrt(a_e) exp(i phi_e))^2 with
+ * a_e exp(i phi_e) = q_e the delay-compensated IQ sample (the weight outside the
+ * root as in Eq. (2); the constant 1/N of Eq. (4) is dropped). The image is |y|
+ * (env). Arguments and outputs as for pwbf_beamform_iqdas. */
+PWBF_API int pwbf_beamform_bbdmas(const pwbf_geometry *g, const void *iq, int32_t angle,
+                                  const pwbf_outputs *out, void *workspace,
+                                  size_t workspace_bytes, void *stream);
+
 /* Coherent compounding: the unweighted sum over all n_angles of the per-angle
- * DAS (mode PWBF_DAS), DMAS (PWBF_DMAS) or pDAS (PWBF_PDAS) images, in one pass that shares
+ * DAS (mode PWBF_DAS), DMAS (PWBF_DMAS), pDAS (PWBF_PDAS) images, or of the
+ * complex IQ-DAS (PWBF_IQDAS) or BB-DMAS (PWBF_BBDMAS) values, in one pass that shares
  * each pixel's receive delays and weights across the angles. Before
  * post-processing, compound(mode) equals the sum of beamform_<mode>(a) over a
  * (up to float32 summation order). Other arguments and errors as above. */
@@ -235,10 +271,11 @@ typedef struct pwbf_frame {
   const pwbf_geometry *geom; /* host; read during create / update */
   const void *rf;            /* device RF of rf_dtype */
   int32_t rf_dtype;          /* PWBF_I16, PWBF_F16, PWBF_F32 */
-  int32_t mode;              /* PWBF_DAS or PWBF_DMAS */
+  int32_t mode;              /* PWBF_DAS, PWBF_DMAS or PWBF_PDAS (the IQ modes are
+                                single-frame only: PWBF_E_UNSUPPORTED) */
   int32_t angle;             /* -1: compound over all angles; else that angle */
   int32_t reserved;          /* 0 */
-  pwbf_outputs out;          /* device planes, as for the single-frame calls */
+  pwbf_outputs out;          /* device planes, as for the single-frame calls (imag NULL) */
   pwbf_tile tile;            /* zeros: tuned entry if present, else default;
                                 wz * wx must be 8 (batch blocks are 8 wavefronts) */
 } pwbf_frame;

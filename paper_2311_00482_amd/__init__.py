@@ -17,9 +17,12 @@ from .api import (  # noqa: F401
     beamform,
     beamform_das,
     beamform_dmas,
+    beamform_bbdmas,
+    beamform_iqdas,
     beamform_pdas,
     compound,
     describe_plan,
+    iq_demodulate,
     tune,
     tune_clear,
     tune_load,

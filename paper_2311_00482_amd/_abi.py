@@ -12,10 +12,10 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpwbf.so")
 
-ABI_VERSION = 2
+ABI_VERSION = 3
 OK, E_INVALID, E_UNSUPPORTED, E_NOMEM, E_DEVICE, E_BUSY = 0, -1, -2, -3, -4, -5
-I16, F16, F32 = 0, 1, 2
-DAS, DMAS, PDAS = 0, 1, 2
+I16, F16, F32, C32 = 0, 1, 2, 3
+DAS, DMAS, PDAS, IQDAS, BBDMAS = 0, 1, 2, 3, 4
 APOD_HANN, APOD_BOXCAR, APOD_NONE = 0, 1, 2
 MAX_ANGLES, MAX_CHANNELS, MAX_NZ_POST = 32, 256, 4096
 
@@ -50,7 +50,7 @@ class Geometry(ctypes.Structure):
 
 class Outputs(ctypes.Structure):
     _fields_ = [("rf", ctypes.c_void_p), ("filtered", ctypes.c_void_p),
-                ("env", ctypes.c_void_p), ("logimg", ctypes.c_void_p)]
+                ("env", ctypes.c_void_p), ("logimg", ctypes.c_void_p), ("imag", ctypes.c_void_p)]
 
 
 class Tile(ctypes.Structure):
@@ -147,6 +147,12 @@ def lib():
         f = getattr(L, name)
         f.restype = ctypes.c_int
         f.argtypes = [G, vp, i32, i32, O, vp, sz, vp]
+    L.pwbf_iq_demodulate.restype = ctypes.c_int
+    L.pwbf_iq_demodulate.argtypes = [G, vp, i32, vp, vp]
+    for name in ("pwbf_beamform_iqdas", "pwbf_beamform_bbdmas"):
+        f = getattr(L, name)
+        f.restype = ctypes.c_int
+        f.argtypes = [G, vp, i32, O, vp, sz, vp]
     L.pwbf_compound.restype = ctypes.c_int
     L.pwbf_compound.argtypes = [G, vp, i32, i32, O, vp, sz, vp]
     L.pwbf_beamform_ex.restype = ctypes.c_int

@@ -16,10 +16,11 @@ import numpy as np
 
 from . import _abi
 
-_DTYPES = {"int16": _abi.I16, "float16": _abi.F16, "float32": _abi.F32}
-_MODES = {"das": _abi.DAS, "dmas": _abi.DMAS, "pdas": _abi.PDAS}
+_DTYPES = {"int16": _abi.I16, "float16": _abi.F16, "float32": _abi.F32, "complex64": _abi.C32}
+_MODES = {"das": _abi.DAS, "dmas": _abi.DMAS, "pdas": _abi.PDAS, "iqdas": _abi.IQDAS,
+          "bbdmas": _abi.BBDMAS}
 _APODS = {"hann": _abi.APOD_HANN, "boxcar": _abi.APOD_BOXCAR, "none": _abi.APOD_NONE}
-PLANES = ("rf", "filtered", "env", "log")
+PLANES = ("rf", "filtered", "env", "log", "imag")
 
 
 class GeometryArg:
@@ -70,7 +71,8 @@ def _stream_ptr(stream, device):
 def _rf_code(rf) -> int:
     name = str(rf.dtype).replace("torch.", "")
     if name not in _DTYPES:
-        raise TypeError(f"RF dtype {rf.dtype} not supported (int16, float16, float32)")
+        raise TypeError(f"RF dtype {rf.dtype} not supported (int16, float16, float32, "
+                        "complex64 IQ)")
     return _DTYPES[name]
 
 
@@ -129,7 +131,9 @@ def beamform(g, rf, mode: str = "das", angle: int = -1, tile: Optional[Tile] = N
              stream=None, bandpass: bool = False, log_floor_db: float = -70.0,
              p: Optional[float] = None) -> Dict:
     """Run one frame through libpwbf. angle -1 = compound over all angles.
-    ``mode``: "das", "dmas" or "pdas" (root order ``p``, else the geometry's).
+    ``mode``: "das", "dmas" or "pdas" (root order ``p``, else the geometry's) on
+    RF; "iqdas" or "bbdmas" on complex64 IQ data from ``iq_demodulate`` (planes
+    "rf" = real part, "imag", "env" = magnitude, "log").
 
     ``rf``: CUDA tensor [n_angles, n_channels, n_samples] of int16/float16/float32.
     ``want``: planes among "rf", "filtered", "env", "log" (rf is always made).
@@ -156,7 +160,7 @@ def beamform(g, rf, mode: str = "das", angle: int = -1, tile: Optional[Tile] = N
         if k not in out:
             out[k] = torch.empty((ga.nx, ga.nz), dtype=torch.float32, device=rf.device)
     o = _abi.Outputs(_ptr(out.get("rf")), _ptr(out.get("filtered")), _ptr(out.get("env")),
-                     _ptr(out.get("log")))
+                     _ptr(out.get("log")), _ptr(out.get("imag")))
     need = _abi.lib().pwbf_workspace_bytes(ga.ref, ctypes.byref(o))
     if need and workspace is None:
         workspace = torch.empty(need, dtype=torch.uint8, device=rf.device)
@@ -182,6 +186,36 @@ def beamform_dmas(g, rf, angle: int, **kw) -> Dict:
     if angle < 0:
         raise ValueError("angle must be >= 0")
     return beamform(g, rf, "dmas", angle, **kw)
+
+
+def iq_demodulate(g, rf, out=None, stream=None):
+    """pwbf_iq_demodulate: baseband IQ records (complex64 [A, N, Ns]) of the RF,
+    demodulated at the geometry's f0."""
+    import torch
+    ga = _as_geom(g)
+    if not rf.is_cuda or not rf.is_contiguous() or tuple(rf.shape) != ga.shape_rf:
+        raise ValueError(f"rf must be a contiguous CUDA tensor {ga.shape_rf}")
+    if out is None:
+        out = torch.empty(ga.shape_rf, dtype=torch.complex64, device=rf.device)
+    if out.dtype != torch.complex64 or not out.is_contiguous() or tuple(out.shape) != ga.shape_rf:
+        raise ValueError(f"out must be a contiguous complex64 tensor {ga.shape_rf}")
+    _abi.check(_abi.lib().pwbf_iq_demodulate(ga.ref, _ptr(rf), _rf_code(rf), _ptr(out),
+                                             _stream_ptr(stream, rf.device)))
+    return out
+
+
+def beamform_iqdas(g, iq, angle: int, **kw) -> Dict:
+    """pwbf_beamform_iqdas: DAS of the delay-compensated IQ samples for one angle."""
+    if angle < 0:
+        raise ValueError("angle must be >= 0")
+    return beamform(g, iq, "iqdas", angle, **kw)
+
+
+def beamform_bbdmas(g, iq, angle: int, **kw) -> Dict:
+    """pwbf_beamform_bbdmas: BB-DMAS (Eq. 4) for one angle."""
+    if angle < 0:
+        raise ValueError("angle must be >= 0")
+    return beamform(g, iq, "bbdmas", angle, **kw)
 
 
 def beamform_pdas(g, rf, angle: int, p: float = 2.0, **kw) -> Dict:

@@ -22,7 +22,7 @@ ROOT = os.path.dirname(HERE)
 ARCH = os.environ.get("PWBF_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["plan.cpp", "tune.cpp", "api.cpp", "batch.cpp", "serve.cpp", "beamform.hip",
-           "postz.hip", "batch.hip", "serve.hip"]
+           "postz.hip", "batch.hip", "serve.hip", "iq.hip"]
 
 COMMON = [
     "-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}",

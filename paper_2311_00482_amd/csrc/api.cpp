@@ -1,6 +1,7 @@
 // extern "C" entry points of libpwbf: validation, plan, enqueue.
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <string>
 
 #include "../../include/pwbf.h"
@@ -9,6 +10,10 @@
 namespace pwbf {
 hipError_t launch_beamform(const FramePlan &P, hipStream_t stream);
 hipError_t launch_post(const PostPlan &Q, hipStream_t stream);
+hipError_t launch_logc(const float *env, float *logimg, const uint32_t *ws_max, size_t n,
+                       float floor_db, hipStream_t stream);
+hipError_t launch_iq_demod(const void *rf, int dtype, void *iq, int rows, int log2ns, float r_hi,
+                           float r_lo, hipStream_t stream);
 }  // namespace pwbf
 
 namespace {
@@ -36,10 +41,20 @@ int run(const pwbf_geometry *g, const void *rf, int32_t dtype, int32_t mode, int
   std::string err;
   int rc = pwbf::build_plan(g, rf, dtype, mode, angle, tile, out, ws, ws_bytes, &P, &err);
   if (rc) return set_error(rc, err);
+  hipStream_t s = (hipStream_t)stream;
+  if (pwbf::is_iq_mode(mode)) {
+    // the image's magnitude comes out of the beamform kernel; only the log remains
+    hipError_t e = pwbf::launch_beamform(P, s);
+    if (e == hipSuccess && out->logimg)
+      e = pwbf::launch_logc(P.out_env, out->logimg, P.ws_max, (size_t)g->nx * g->nz,
+                            (float)g->log_floor_db, s);
+    if (e != hipSuccess)
+      return set_error(PWBF_E_DEVICE, std::string("IQ beamform launch: ") + hipGetErrorString(e));
+    return PWBF_OK;
+  }
   pwbf::PostPlan Q;
   const bool post = pwbf::post_needed(out);
   if (post) pwbf::build_post_plan(g, out, ws, &Q);
-  hipStream_t s = (hipStream_t)stream;
   hipError_t e = pwbf::launch_beamform(P, s);
   if (e != hipSuccess)
     return set_error(PWBF_E_DEVICE, std::string("beamform launch: ") + hipGetErrorString(e));
@@ -99,6 +114,49 @@ int pwbf_beamform_pdas(const pwbf_geometry *g, const void *rf, int32_t rf_dtype,
              stream);
 }
 
+int pwbf_beamform_iqdas(const pwbf_geometry *g, const void *iq, int32_t angle,
+                        const pwbf_outputs *out, void *workspace, size_t workspace_bytes,
+                        void *stream) {
+  if (angle < 0) return set_error(PWBF_E_INVALID, "angle must be >= 0");
+  return run(g, iq, pwbf::kC32, pwbf::kIqdas, angle, nullptr, out, workspace, workspace_bytes,
+             stream);
+}
+
+int pwbf_beamform_bbdmas(const pwbf_geometry *g, const void *iq, int32_t angle,
+                         const pwbf_outputs *out, void *workspace, size_t workspace_bytes,
+                         void *stream) {
+  if (angle < 0) return set_error(PWBF_E_INVALID, "angle must be >= 0");
+  return run(g, iq, pwbf::kC32, pwbf::kBbdmas, angle, nullptr, out, workspace, workspace_bytes,
+             stream);
+}
+
+int pwbf_iq_demodulate(const pwbf_geometry *g, const void *rf, int32_t rf_dtype, void *iq,
+                       void *stream) {
+  g_last_error.clear();
+  std::string err;
+  int rc = pwbf::validate_geometry(g, &err);
+  if (rc) return set_error(rc, err);
+  if (rf_dtype != pwbf::kI16 && rf_dtype != pwbf::kF16 && rf_dtype != pwbf::kF32)
+    return set_error(PWBF_E_INVALID, "rf_dtype must be PWBF_I16, PWBF_F16 or PWBF_F32");
+  if (!rf || (uintptr_t)rf % pwbf::dtype_bytes(rf_dtype))
+    return set_error(PWBF_E_INVALID, "rf is NULL or not aligned to its element size");
+  if (!iq || (uintptr_t)iq % 8) return set_error(PWBF_E_INVALID, "iq is NULL or not 8-byte aligned");
+  const int ns = g->n_samples;
+  if (ns < 2 || ns > 4096 || (ns & (ns - 1)))
+    return set_error(PWBF_E_UNSUPPORTED, "IQ demodulation needs n_samples a power of two in 2..4096");
+  if (!(g->f0 > 0.0) || !std::isfinite(g->f0))
+    return set_error(PWBF_E_INVALID, "IQ demodulation needs f0 > 0");
+  int log2ns = 0;
+  while ((1 << log2ns) < ns) ++log2ns;
+  float r_hi, r_lo;
+  pwbf::split_double(g->f0 / g->fs, &r_hi, &r_lo);
+  hipError_t e = pwbf::launch_iq_demod(rf, rf_dtype, iq, g->n_angles * g->n_channels, log2ns, r_hi,
+                                       r_lo, (hipStream_t)stream);
+  if (e != hipSuccess)
+    return set_error(PWBF_E_DEVICE, std::string("IQ demodulation launch: ") + hipGetErrorString(e));
+  return PWBF_OK;
+}
+
 int pwbf_compound(const pwbf_geometry *g, const void *rf, int32_t rf_dtype, int32_t mode,
                   const pwbf_outputs *out, void *workspace, size_t workspace_bytes,
                   void *stream) {
@@ -129,7 +187,8 @@ int pwbf_describe_plan(const pwbf_geometry *g, int32_t mode, int32_t angle,
   if (!info) return set_error(PWBF_E_INVALID, "info is NULL");
   pwbf::FramePlan P;
   std::string err;
-  int rc = pwbf::plan_frame(g, pwbf::kF32, mode, angle, tile, &P, &err);
+  int rc = pwbf::plan_frame(g, pwbf::is_iq_mode(mode) ? pwbf::kC32 : pwbf::kF32, mode, angle,
+                            tile, &P, &err);
   if (rc) return set_error(rc, err);
   info->cpw = P.cpw;
   info->lz = P.lz;

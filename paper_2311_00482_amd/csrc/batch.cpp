@@ -73,6 +73,10 @@ int plan_batch_frame(const pwbf_frame &f, unsigned char *ws, pwbf::FramePlan *P,
     return PWBF_E_INVALID;
   }
   const pwbf_tile *t = tile_is_zero(f.tile) ? nullptr : &f.tile;
+  if (pwbf::is_iq_mode(f.mode)) {
+    *err = "the IQ modes are single-frame only";
+    return PWBF_E_UNSUPPORTED;
+  }
   int rc = pwbf::plan_frame(f.geom, f.rf_dtype, f.mode, f.angle, t, P, err, pwbf::batch_waves());
   if (rc) return rc;
   if (P->n_angles > pwbf::batch_max_angles()) {

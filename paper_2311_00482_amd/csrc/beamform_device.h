@@ -132,6 +132,63 @@ __device__ __forceinline__ void stage_windows(const FramePlan &P, int e0, int nc
   }
 }
 
+// Stage the complex windows of the IQ modes: as stage_windows for DAS, with
+// each entry the lines of the real and imaginary parts, (b_re, d_re, b_im, d_im)
+// (16 bytes), from complex float32 samples.
+__device__ __forceinline__ void stage_windows_iq(const FramePlan &P, int e0, int nch, int e_end,
+                                                 const int *s_lt, const int *s_lr,
+                                                 float4 *s_ent) {
+  const int A = P.n_angles, N = P.n_channels, Ns = P.n_samples, win = P.win;
+  const int off = P.off_t + P.off_r;
+  const int W4 = win >> 2;
+  const int total = nch * A * W4;  // at most kMaxLdsBytes / 64 = 2^10 quads
+  const float rw = __builtin_amdgcn_rcpf((float)W4), ra = __builtin_amdgcn_rcpf((float)A);
+  const float hw = 0.5f * rw, ha = 0.5f * ra;
+  const int last = min(e_end, N) - 1;
+  const __amdgpu_buffer_rsrc_t res = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<void *>(P.rf), (short)0, A * N * Ns * 8, kRawBufferWord3);
+  for (int q = threadIdx.x; q < total; q += blockDim.x) {
+    const int row = (int)fmaf((float)q, rw, hw);
+    const int j0 = (q - __mul24(row, W4)) << 2;
+    const int c = (int)fmaf((float)row, ra, ha);
+    const int a = row - __mul24(c, A);
+    const int e = e0 + c;
+    const int n = s_lt[a] + s_lr[c] + j0;
+    const unsigned base = __umul24((unsigned)(__mul24(a, N) + min(e, last)), (unsigned)Ns);
+    float ur[5], ui[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      const int i = n + k;
+      const unsigned vo = (base + (unsigned)min(max(i, 0), Ns - 1)) * 8u;
+      const float re = __int_as_float((int)__builtin_amdgcn_raw_buffer_load_b32(res, (int)vo, 0, 0));
+      const float im =
+          __int_as_float((int)__builtin_amdgcn_raw_buffer_load_b32(res, (int)(vo + 4u), 0, 0));
+      const bool in = (unsigned)i < (unsigned)Ns && e <= last;
+      ur[k] = in ? re : 0.f;
+      ui[k] = in ? im : 0.f;
+    }
+    float4 *dst = s_ent + __mul24(row, win) + j0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const float m = (float)(off - j0 - k);
+      const float dr = ur[k + 1] - ur[k], di = ui[k + 1] - ui[k];
+      dst[k] = make_float4(fmaf(m, dr, ur[k]), dr, fmaf(m, di, ui[k]), di);
+    }
+  }
+}
+
+// exp(2 pi i r K) for an integer K and r = rh + rl given as a float-float pair:
+// the revolutions K r are reduced modulo 1 exactly enough (~1e-7) for any K the
+// windows use.
+__device__ __forceinline__ float2 carrier_phasor(int K, float rh, float rl) {
+  const float fk = (float)K;
+  const float p = fk * rh;
+  const float rho = (p - floorf(p)) + fmaf(fk, rl, fmaf(fk, rh, -p));
+  float sn, cs;
+  sincospif(2.0f * rho, &sn, &cs);
+  return make_float2(cs, sn);
+}
+
 // floor(s) as an int in one instruction (v_cvt_flr_i32_f32; pure ALU)
 __device__ __forceinline__ int floor_i32(float s) {
   int n;
@@ -202,10 +259,13 @@ __device__ __forceinline__ float ff_f(ff a) { return a.hi + a.lo; }
 template <int AM, bool PRED, int MODE, bool ONEGRP>
 __device__ __forceinline__ void process_tile(const FramePlan &P, int tz, int tx,
                                              unsigned char *smem) {
-  float *s_txq = (float *)smem;                      // [kMaxAngles] tx(q) - LT
-  int *s_lt = (int *)(smem + kMaxAngles * 4);        // [kMaxAngles] LT
-  float4 *s_ch = (float4 *)(smem + kLdsAngleBytes);  // [chunk] {Dq, rq^2, rq, rx(q) - LR}
-  int *s_lr = (int *)(s_ch + P.chunk);               // [chunk] LR
+  constexpr bool IQ = is_iq_mode(MODE);
+  float *s_txq = (float *)smem;                        // [kMaxAngles] tx(q) - LT
+  int *s_lt = (int *)(smem + kMaxAngles * 4);          // [kMaxAngles] LT
+  float2 *s_tph = (float2 *)(smem + kMaxAngles * 8);   // [kMaxAngles] IQ: exp(2 pi i r (LT + off_t))
+  float4 *s_ch = (float4 *)(smem + kLdsAngleBytes);    // [chunk] {Dq, rq^2, rq, rx(q) - LR}
+  float2 *s_ph = (float2 *)(smem + plan_lds_ph_offset(P));  // [chunk] IQ: exp(2 pi i r (LR + off_r))
+  int *s_lr = (int *)(smem + plan_lds_lr_offset(P));   // [chunk] LR
   float2 *s_pairs = (float2 *)(smem + plan_lds_win_offset(P));
 
   const int tid = threadIdx.x;
@@ -279,6 +339,7 @@ __device__ __forceinline__ void process_tile(const FramePlan &P, int tz, int tx,
     const float lt = fl + floorf((txq.hi - fl) + txq.lo + dmin) - 1.f;
     s_txq[a] = ff_f(ff_add(txq, {-(lt + (float)P.off_t), 0.f}));
     s_lt[a] = (int)lt;
+    if constexpr (IQ) s_tph[a] = carrier_phasor((int)lt + P.off_t, P.iq_r, P.iq_rl);
   }
   __syncthreads();
   int e_lo = 0, e_hi = N;
@@ -298,10 +359,13 @@ __device__ __forceinline__ void process_tile(const FramePlan &P, int tz, int tx,
     if (!PRED || a < A) txl[a] = s_txq[a] + fmaf(dx, P.sa[a], dz * P.ca[a]);
 
   float total = 0.f;
-  float S[MODE == kDas ? 1 : AM];  // per-angle sums of compressed samples (DMAS, pDAS)
+  float S[MODE == kDas ? 1 : AM];  // per-angle sums: compressed samples (DMAS, pDAS), Re (IQ)
+  float SI[IQ ? AM : 1];           // per-angle sums, Im (IQ)
   float Q = 0.f;
 #pragma unroll
   for (int a = 0; a < (MODE == kDas ? 1 : AM); ++a) S[a] = 0.f;
+#pragma unroll
+  for (int a = 0; a < (IQ ? AM : 1); ++a) SI[a] = 0.f;
 
   for (int e0 = e_lo; e0 < e_hi; e0 += chunk) {
     if (e0 > e_lo) __syncthreads();  // the previous chunk's windows have been read
@@ -326,9 +390,12 @@ __device__ __forceinline__ void process_tile(const FramePlan &P, int tz, int tx,
       s_ch[c] = make_float4(dqf, ff_f(rq2), ff_f(rq) + 1e-20f,
                             ff_f(ff_add(rq, {-(lr + (float)P.off_r), 0.f})));
       s_lr[c] = (int)lr;
+      if constexpr (IQ) s_ph[c] = carrier_phasor((int)lr + P.off_r, P.iq_r, P.iq_rl);
     }
     __syncthreads();
-    if (P.dtype == kI16)
+    if constexpr (IQ)
+      stage_windows_iq(P, e0, cnt_pad, e_hi, s_lt, s_lr, (float4 *)s_pairs);
+    else if (P.dtype == kI16)
       stage_windows<kI16, MODE>(P, e0, cnt_pad, e_hi, s_lt, s_lr, s_pairs);
     else if (P.dtype == kF16)
       stage_windows<kF16, MODE>(P, e0, cnt_pad, e_hi, s_lt, s_lr, s_pairs);
@@ -336,7 +403,7 @@ __device__ __forceinline__ void process_tile(const FramePlan &P, int tz, int tx,
       stage_windows<kF32, MODE>(P, e0, cnt_pad, e_hi, s_lt, s_lr, s_pairs);
     __syncthreads();
 
-    const int wstride = win * (int)sizeof(float2);  // bytes between angle windows
+    const int wstride = win * P.entry_bytes;  // bytes between angle windows
     for (int k = 0; k < cnt; k += cpw) {
       const int c = ONEGRP ? k : k + grp;
       const float4 ch = s_ch[c];
@@ -346,7 +413,8 @@ __device__ __forceinline__ void process_tile(const FramePlan &P, int tz, int tx,
       const float rxl = fmaf(num, __builtin_amdgcn_rcpf(den), ch.w);
       const float w = apod_weight(fabsf(ch.x + dx) * invA, hk, hb);
       // delays are centred: entry n of the window is read as n + off_t + off_r
-      const char *wb = (const char *)(s_pairs + (size_t)c * A * win + P.off_t + P.off_r);
+      const char *wb = (const char *)s_pairs +
+                       ((size_t)c * A * win + P.off_t + P.off_r) * (IQ ? 16 : 8);
       if constexpr (MODE == kDas) {
         float acc = -0.f;  // x + (-0) == x for every x: the first add folds away
 #pragma unroll
@@ -360,6 +428,32 @@ __device__ __forceinline__ void process_tile(const FramePlan &P, int tz, int tx,
           }
         }
         total = fmaf(w, acc, total);
+      } else if constexpr (IQ) {
+        // receive phasor of this (pixel, channel), weight folded in:
+        // w exp(2 pi i r (LR + off_r + rx(p) - LR - off_r))
+        const float2 pk = s_ph[c];
+        const float rho = P.iq_r * rxl;
+        const float cr = __builtin_amdgcn_cosf(rho), sr = __builtin_amdgcn_sinf(rho);
+        const float Rx = w * (pk.x * cr - pk.y * sr), Ry = w * (pk.x * sr + pk.y * cr);
+#pragma unroll
+        for (int a = 0; a < AM; ++a) {
+          if (!PRED || a < A) {
+            const float s = txl[a] + rxl;
+            const int n = floor_i32(s);
+            const float4 q = *(const float4 *)(wb + a * wstride + (n << 4));
+            const float I = fmaf(s, q.y, q.x), Qv = fmaf(s, q.w, q.z);  // the lines at s
+            float cx = Rx, cy = Ry;
+            if constexpr (MODE == kBbdmas) {
+              // sqrt(amplitude), phase kept: scale by |q|^(-1/2) (0 for q = 0)
+              const float m2 = fmaf(I, I, Qv * Qv);
+              const float k = m2 > 0.f ? __builtin_amdgcn_rsqf(__builtin_amdgcn_sqrtf(m2)) : 0.f;
+              cx *= k;
+              cy *= k;
+            }
+            S[a] = fmaf(cx, I, fmaf(-cy, Qv, S[a]));
+            SI[a] = fmaf(cx, Qv, fmaf(cy, I, SI[a]));
+          }
+        }
       } else if constexpr (MODE == kPdas) {
         // sign(v) |v|^(1/p) = sign(v) 2^(log2|v| / p); |v| = 0 gives 2^-inf = 0
         const float ip = P.pdas_inv_p;
@@ -393,6 +487,54 @@ __device__ __forceinline__ void process_tile(const FramePlan &P, int tz, int tx,
         Q = fmaf(w * w, q, Q);
       }
     }
+  }
+
+  if constexpr (IQ) {
+    // per angle: the transmit phasor exp(2 pi i r (LT + off_t + tx(p) - LT - off_t))
+    // times the angle's sum; BB-DMAS squares it; the angles add
+    float yr = 0.f, yi = 0.f;
+#pragma unroll
+    for (int a = 0; a < AM; ++a) {
+      if (!PRED || a < A) {
+        float tr = S[a], ti = SI[a];
+        for (int off = ppw; off < kWave; off <<= 1) {
+          tr += __shfl_xor(tr, off);
+          ti += __shfl_xor(ti, off);
+        }
+        const float2 tp = s_tph[a];
+        const float rho = P.iq_r * txl[a];
+        const float ct = __builtin_amdgcn_cosf(rho), st = __builtin_amdgcn_sinf(rho);
+        const float Tx = tp.x * ct - tp.y * st, Ty = tp.x * st + tp.y * ct;
+        const float zr = Tx * tr - Ty * ti, zi = Tx * ti + Ty * tr;
+        if constexpr (MODE == kBbdmas) {
+          yr += zr * zr - zi * zi;
+          yi += 2.f * zr * zi;
+        } else {
+          yr += zr;
+          yi += zi;
+        }
+      }
+    }
+    const bool mine = grp == 0 && ix < P.nx && iz < P.nz;
+    const float env = sqrtf(yr * yr + yi * yi);
+    if (mine) {
+      const size_t o = (size_t)ix * P.nz + iz;
+      P.out[o] = yr;
+      if (P.out_imag) P.out_imag[o] = yi;
+      if (P.out_env) P.out_env[o] = env;
+    }
+    if (P.ws_max) {  // the frame maximum of |y| for the log image
+      __shared__ float s_wmax[kMaxWavesPerBlock];
+      float m = mine ? env : 0.f;
+      for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
+      if (lane == 0) s_wmax[wave] = m;
+      __syncthreads();
+      if (tid == 0) {
+        for (int w = 1; w < (int)(blockDim.x / kWave); ++w) m = fmaxf(m, s_wmax[w]);
+        atomicMax(P.ws_max, __float_as_uint(m));
+      }
+    }
+    return;
   }
 
   float y;

@@ -46,7 +46,9 @@ void split(double v, float *hi, float *lo) {
 
 }  // namespace
 
-size_t dtype_bytes(int dtype) { return dtype == kF32 ? 4 : 2; }
+void split_double(double v, float *hi, float *lo) { split(v, hi, lo); }
+
+size_t dtype_bytes(int dtype) { return dtype == kC32 ? 8 : (dtype == kF32 ? 4 : 2); }
 
 int validate_geometry(const pwbf_geometry *g, std::string *err) {
   if (!g) return fail(err, PWBF_E_INVALID, "geometry is NULL");
@@ -119,15 +121,22 @@ size_t workspace_bytes(const pwbf_geometry *g, const pwbf_outputs *o) {
 }
 
 int validate_outputs(const pwbf_geometry *g, const pwbf_outputs *o, void *ws, size_t ws_bytes,
-                     std::string *err) {
+                     std::string *err, int mode) {
   if (!o) return fail(err, PWBF_E_INVALID, "outputs is NULL");
   if (!o->rf) return fail(err, PWBF_E_INVALID, "outputs->rf is NULL");
-  const float *planes[4] = {o->rf, o->filtered, o->env, o->logimg};
+  const float *planes[5] = {o->rf, o->filtered, o->env, o->logimg, o->imag};
   for (const float *p : planes)
     if (p && ((uintptr_t)p % 4)) return fail(err, PWBF_E_INVALID, "output plane not 4-byte aligned");
+  if (is_iq_mode(mode)) {
+    // the complex image's magnitude is the envelope: no depth post-processing
+    if (o->filtered || g->bandpass)
+      return fail(err, PWBF_E_INVALID, "band-pass applies to RF images, not to the IQ modes");
+  } else if (o->imag) {
+    return fail(err, PWBF_E_INVALID, "imag output is for the IQ modes only");
+  }
   if (o->filtered && !g->bandpass)
     return fail(err, PWBF_E_INVALID, "filtered output requested without bandpass");
-  if (post_requested(o) || g->bandpass) {
+  if (!is_iq_mode(mode) && (post_requested(o) || g->bandpass)) {
     if (!is_pow2(g->nz) || g->nz > kMaxNzPost || g->nz < 2)
       return fail(err, PWBF_E_UNSUPPORTED,
                   "depth post-processing needs nz a power of two in 2..%d (nz = %d)", kMaxNzPost,
@@ -213,7 +222,8 @@ static int fit_tile(const pwbf_geometry *g, pwbf_tile t, FramePlan *P, std::stri
   P->tile_x = TX;
   // a tile's pixels never extend past the grid (edge lanes repeat the edge pixel)
   P->win = window_entries(*P, std::min(TZ, g->nz), std::min(TX, g->nx));
-  const size_t per_channel = (size_t)P->n_angles * P->win * 8 + 20;
+  const size_t per_channel =
+      (size_t)P->n_angles * P->win * P->entry_bytes + (is_iq_mode(P->mode) ? 28 : 20);
   const size_t fixed = kLdsAngleBytes + 16;
   int chunk = t.chunk;
   if (chunk == 0) {
@@ -236,10 +246,13 @@ static int plan_frame_uncached(const pwbf_geometry *g, int dtype, int mode, int 
                                int waves) {
   int rc = validate_geometry(g, err);
   if (rc) return rc;
-  if (dtype != kI16 && dtype != kF16 && dtype != kF32)
+  if (dtype != kI16 && dtype != kF16 && dtype != kF32 && dtype != kC32)
     return fail(err, PWBF_E_INVALID, "rf_dtype %d unknown", dtype);
-  if (mode != kDas && mode != kDmas && mode != kPdas)
-    return fail(err, PWBF_E_INVALID, "mode %d unknown", mode);
+  if (mode < kDas || mode > kBbdmas) return fail(err, PWBF_E_INVALID, "mode %d unknown", mode);
+  if (is_iq_mode(mode) != (dtype == kC32))
+    return fail(err, PWBF_E_INVALID, "the IQ modes take complex IQ input (PWBF_C32), the others RF");
+  if (is_iq_mode(mode) && !(g->f0 > 0.0 && finite(g->f0)))
+    return fail(err, PWBF_E_INVALID, "the IQ modes need f0 > 0 (the demodulation frequency)");
   if (mode == kPdas && !(g->pdas_p >= 1.0 && g->pdas_p <= 16.0))
     return fail(err, PWBF_E_INVALID, "pdas_p = %g outside 1..16", g->pdas_p);
   if (angle < -1 || angle >= g->n_angles)
@@ -270,6 +283,8 @@ static int plan_frame_uncached(const pwbf_geometry *g, int dtype, int mode, int 
   P->ap_k = g->apod == kNone ? 0.0f : (float)(2.0 * g->f_number);
   P->pdas_p = mode == kPdas ? (float)g->pdas_p : 1.0f;
   P->pdas_inv_p = mode == kPdas ? (float)(1.0 / g->pdas_p) : 1.0f;
+  P->entry_bytes = is_iq_mode(mode) ? 16 : 8;
+  if (is_iq_mode(mode)) split(g->f0 / g->fs, &P->iq_r, &P->iq_rl);
   for (int e = 0; e < kMaxChannels; ++e)
     split(g->elem_x[std::min(e, g->n_channels - 1)] * scale, &P->xe[e], &P->xel[e]);
   for (int k = 0; k < na; ++k) {
@@ -405,12 +420,15 @@ int build_plan(const pwbf_geometry *g, const void *rf, int dtype, int mode, int 
   if (!rf) return fail(err, PWBF_E_INVALID, "rf is NULL");
   if ((uintptr_t)rf % dtype_bytes(dtype))
     return fail(err, PWBF_E_INVALID, "rf not aligned to its element size");
-  rc = validate_outputs(g, o, ws, ws_bytes, err);
+  rc = validate_outputs(g, o, ws, ws_bytes, err, mode);
   if (rc) return rc;
   const size_t slab = (size_t)g->n_channels * g->n_samples * dtype_bytes(dtype);
   P->rf = (const char *)rf + (size_t)(angle < 0 ? 0 : angle) * slab;
   P->out = o->rf;
   P->ws_max = o->logimg ? (uint32_t *)ws : nullptr;
+  P->out_imag = o->imag;
+  P->out_env = nullptr;
+  if (is_iq_mode(mode)) P->out_env = o->env ? o->env : (o->logimg ? (float *)((char *)ws + 256) : nullptr);
   return PWBF_OK;
 }
 

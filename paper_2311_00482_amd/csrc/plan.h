@@ -28,14 +28,19 @@ constexpr int kMaxLdsBytes = 64 * 1024;
 constexpr int kDefaultLdsBytes = 52 * 1024;
 constexpr int kMaxNzPost = 4096;
 
-enum Dtype : int32_t { kI16 = 0, kF16 = 1, kF32 = 2 };
-enum Mode : int32_t { kDas = 0, kDmas = 1, kPdas = 2 };
+enum Dtype : int32_t { kI16 = 0, kF16 = 1, kF32 = 2, kC32 = 3 };
+enum Mode : int32_t { kDas = 0, kDmas = 1, kPdas = 2, kIqdas = 3, kBbdmas = 4 };
+
+PWBF_HD constexpr bool is_iq_mode(int mode) { return mode == kIqdas || mode == kBbdmas; }
 enum Apod : int32_t { kHann = 0, kBoxcar = 1, kNone = 2 };
 
 struct FramePlan {
   const void *rf;  // RF[n_angles][n_channels][n_samples] of dtype (single angle: its slab)
-  float *out;      // [nx][nz] beamformed image
-  uint32_t *ws_max;  // cleared by the beamform kernel when the log image is requested
+  float *out;      // [nx][nz] beamformed image (IQ modes: real part)
+  uint32_t *ws_max;  // RF modes: cleared by the beamform kernel when the log image is
+                     // requested; IQ modes: the frame maximum of |image| (cleared before)
+  float *out_imag;   // IQ modes: imaginary part, or null
+  float *out_env;    // IQ modes: |image| (the caller's env plane or workspace), or null
   int32_t dtype, mode, apod;
   int32_t n_angles, n_channels, n_samples;
   int32_t nx, nz;
@@ -45,6 +50,8 @@ struct FramePlan {
   float X0l, DXl, Z0l, DZl;  // ... and their lo parts
   float ap_k;            // 2 F#: normalised aperture distance r = |X - Xe| * ap_k / Z
   float pdas_p, pdas_inv_p;  // pDAS root order p and 1 / p (mode kPdas)
+  float iq_r, iq_rl;         // IQ modes: f0 / fs, carrier revolutions per sample (hi, lo)
+  int32_t entry_bytes;       // LDS bytes per window entry: 8 (RF), 16 (complex IQ)
   // launch shape
   int32_t cpw, lz, lx, wz, wx, chunk;  // lane groups, lanes along z/x per group, waves
   int32_t win;           // LDS entries per (channel, angle) window
@@ -70,13 +77,21 @@ struct PostPlan {
 
 // LDS layout of one block: per-angle tile constants (float txl, int origin),
 // per-channel tile constants (float4) and origins (int), then the windows.
-constexpr size_t kLdsAngleBytes = kMaxAngles * 8;
-PWBF_HD inline size_t plan_lds_chan_bytes(const FramePlan &p) { return (size_t)p.chunk * 20; }
+// LDS of a block: per angle {tx(q) - LT, LT, transmit phasor} (16 bytes), per
+// channel of the chunk {Dq, rq^2, rq, rx(q) - LR} (16), the receive phasor (8,
+// IQ modes only) and LR (4), then the windows.
+constexpr size_t kLdsAngleBytes = kMaxAngles * 16;
+PWBF_HD inline size_t plan_lds_ph_offset(const FramePlan &p) {
+  return kLdsAngleBytes + (size_t)p.chunk * 16;
+}
+PWBF_HD inline size_t plan_lds_lr_offset(const FramePlan &p) {
+  return plan_lds_ph_offset(p) + (is_iq_mode(p.mode) ? (size_t)p.chunk * 8 : 0);
+}
 PWBF_HD inline size_t plan_lds_win_offset(const FramePlan &p) {
-  return (kLdsAngleBytes + plan_lds_chan_bytes(p) + 15) / 16 * 16;
+  return (plan_lds_lr_offset(p) + (size_t)p.chunk * 4 + 15) / 16 * 16;
 }
 PWBF_HD inline size_t plan_lds_bytes(const FramePlan &p) {
-  return plan_lds_win_offset(p) + (size_t)p.chunk * p.n_angles * p.win * 8;
+  return plan_lds_win_offset(p) + (size_t)p.chunk * p.n_angles * p.win * p.entry_bytes;
 }
 
 }  // namespace pwbf

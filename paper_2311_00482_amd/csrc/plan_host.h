@@ -9,9 +9,12 @@
 namespace pwbf {
 
 size_t dtype_bytes(int dtype);
+// v as a float-float pair (hi = v rounded to float, lo = the rest)
+void split_double(double v, float *hi, float *lo);
 int validate_geometry(const pwbf_geometry *g, std::string *err);
+// mode decides which planes apply (IQ modes: no band-pass, imag allowed)
 int validate_outputs(const pwbf_geometry *g, const pwbf_outputs *o, void *ws, size_t ws_bytes,
-                     std::string *err);
+                     std::string *err, int mode = kDas);
 size_t workspace_bytes(const pwbf_geometry *g, const pwbf_outputs *o);
 pwbf_tile default_tile(const pwbf_geometry *g, int n_angles_used, int mode);
 // Geometry and launch shape only (no pointers). angle < 0: all angles

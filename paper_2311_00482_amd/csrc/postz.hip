@@ -35,6 +35,16 @@ __global__ void k_logc(const float *__restrict__ env, float *__restrict__ out,
 }
 
 }  // namespace
+
+hipError_t launch_logc(const float *env, float *logimg, const uint32_t *ws_max, size_t n,
+                       float floor_db, hipStream_t stream) {
+  const int threads = 256;
+  const int blocks = (int)std::min<size_t>((n + threads - 1) / threads, 4096);
+  hipLaunchKernelGGL(k_logc, dim3(blocks), dim3(threads), 0, stream, env, logimg, ws_max, n,
+                     floor_db);
+  return hipGetLastError();
+}
+
 hipError_t launch_post(const PostPlan &Q, hipStream_t stream) {
   const size_t lds = (size_t)Q.nz * sizeof(float2) + (size_t)(Q.nz / 2) * sizeof(float2);
   hipLaunchKernelGGL(k_postz, dim3(Q.nx), dim3(kPostThreads), lds, stream, Q);

@@ -18,27 +18,22 @@ __device__ __forceinline__ int bitrev(int k, int log2n) {
   return (int)(__brev((unsigned)k) >> (32 - log2n));
 }
 
-// Post-process column ix of the frame described by Q, with LDS at sm
-// (nz + nz/2 float2).
-__device__ __forceinline__ void postz_column(const PostPlan &Q, int ix, float2 *sm) {
-  const int nz = Q.nz, L = Q.log2nz, half_n = nz >> 1;
-  float2 *x = sm;
-  float2 *tw = sm + nz;  // W^k = exp(-2 pi i k / nz), k < nz / 2
-  const int tid = threadIdx.x;
-  const float *src = Q.src + (size_t)ix * nz;
-
-  for (int k = tid; k < half_n; k += kPostThreads) {
+// Radix-2 FFT of n = 2^L points in LDS, by a block of kPostThreads threads.
+// tw holds W^k = exp(-2 pi i k / n) for k < n / 2.
+__device__ __forceinline__ void fft_twiddles(float2 *tw, int n) {
+  for (int k = threadIdx.x; k < (n >> 1); k += kPostThreads) {
     float s, c;
-    sincospif(-2.0f * (float)k / (float)nz, &s, &c);
+    sincospif(-2.0f * (float)k / (float)n, &s, &c);
     tw[k] = make_float2(c, s);
   }
-  for (int k = tid; k < nz; k += kPostThreads) x[bitrev(k, L)] = make_float2(src[k], 0.f);
-  __syncthreads();
+}
 
-  // forward transform, decimation in time
+// Forward transform, decimation in time: x in bit-reversed order -> natural order.
+__device__ __forceinline__ void fft_forward(float2 *x, const float2 *tw, int L) {
+  const int half_n = 1 << (L - 1);
   for (int s = 0; s < L; ++s) {
     const int half = 1 << s;
-    for (int b = tid; b < half_n; b += kPostThreads) {
+    for (int b = threadIdx.x; b < half_n; b += kPostThreads) {
       const int pos = b & (half - 1);
       const int i0 = ((b >> s) << (s + 1)) + pos, i1 = i0 + half;
       const float2 t = cmul(tw[pos << (L - 1 - s)], x[i1]);
@@ -48,24 +43,15 @@ __device__ __forceinline__ void postz_column(const PostPlan &Q, int ix, float2 *
     }
     __syncthreads();
   }
+}
 
-  // analytic-signal weights, band mask, and the 1/nz of the inverse
-  const float inv_n = 1.0f / (float)nz;
-  for (int k = tid; k < nz; k += kPostThreads) {
-    float h = (k == 0 || k == half_n) ? 1.f : (k < half_n ? 2.f : 0.f);
-    if (Q.bandpass) {
-      const int ak = k <= half_n ? k : nz - k;
-      if (ak < Q.k_lo || ak > Q.k_hi) h = 0.f;
-    }
-    const float2 v = x[k];
-    x[k] = make_float2(v.x * h * inv_n, v.y * h * inv_n);
-  }
-  __syncthreads();
-
-  // inverse transform, decimation in frequency (conjugate twiddles)
+// Inverse transform without the 1/n, decimation in frequency (conjugate
+// twiddles): x in natural order -> bit-reversed order.
+__device__ __forceinline__ void fft_inverse(float2 *x, const float2 *tw, int L) {
+  const int half_n = 1 << (L - 1);
   for (int s = L - 1; s >= 0; --s) {
     const int half = 1 << s;
-    for (int b = tid; b < half_n; b += kPostThreads) {
+    for (int b = threadIdx.x; b < half_n; b += kPostThreads) {
       const int pos = b & (half - 1);
       const int i0 = ((b >> s) << (s + 1)) + pos, i1 = i0 + half;
       const float2 w0 = tw[pos << (L - 1 - s)];
@@ -75,6 +61,42 @@ __device__ __forceinline__ void postz_column(const PostPlan &Q, int ix, float2 *
     }
     __syncthreads();
   }
+}
+
+// One-sided weight of the analytic signal at bin k of n: 1 at DC and Nyquist,
+// 2 on positive bins, 0 on negative ones.
+__device__ __forceinline__ float analytic_weight(int k, int n) {
+  const int half_n = n >> 1;
+  return (k == 0 || k == half_n) ? 1.f : (k < half_n ? 2.f : 0.f);
+}
+
+// Post-process column ix of the frame described by Q, with LDS at sm
+// (nz + nz/2 float2).
+__device__ __forceinline__ void postz_column(const PostPlan &Q, int ix, float2 *sm) {
+  const int nz = Q.nz, L = Q.log2nz, half_n = nz >> 1;
+  float2 *x = sm;
+  float2 *tw = sm + nz;  // W^k = exp(-2 pi i k / nz), k < nz / 2
+  const int tid = threadIdx.x;
+  const float *src = Q.src + (size_t)ix * nz;
+
+  fft_twiddles(tw, nz);
+  for (int k = tid; k < nz; k += kPostThreads) x[bitrev(k, L)] = make_float2(src[k], 0.f);
+  __syncthreads();
+  fft_forward(x, tw, L);
+
+  // analytic-signal weights, band mask, and the 1/nz of the inverse
+  const float inv_n = 1.0f / (float)nz;
+  for (int k = tid; k < nz; k += kPostThreads) {
+    float h = analytic_weight(k, nz);
+    if (Q.bandpass) {
+      const int ak = k <= half_n ? k : nz - k;
+      if (ak < Q.k_lo || ak > Q.k_hi) h = 0.f;
+    }
+    const float2 v = x[k];
+    x[k] = make_float2(v.x * h * inv_n, v.y * h * inv_n);
+  }
+  __syncthreads();
+  fft_inverse(x, tw, L);
 
   float m = 0.f;
   for (int k = tid; k < nz; k += kPostThreads) {

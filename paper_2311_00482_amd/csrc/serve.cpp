@@ -313,6 +313,9 @@ int pwbf_server_create(const pwbf_probe *probes, int32_t n, size_t hbm_budget_by
         (p.want_log != 0 && p.want_log != 1))
       return api_set_error(PWBF_E_INVALID, "probe " + std::to_string(i) +
                                                ": slots 0..64, want_* 0/1, reserved 0");
+    if (pwbf::is_iq_mode(p.mode))
+      return api_set_error(PWBF_E_UNSUPPORTED,
+                           "probe " + std::to_string(i) + ": the IQ modes are single-frame only");
     pwbf::FramePlan P;
     int rc = pwbf::plan_frame(p.geom, pwbf::kF16, p.mode, p.angle, nullptr, &P, &err,
                               pwbf::serve_waves());

@@ -229,6 +229,51 @@ def _create(frames, flags=0):
     return rc, _abi.lib().pwbf_last_error().decode()
 
 
+def test_iq_mode_and_dtype_rules():
+    g = GeometryArg(config_c1())
+    C = _abi.C32
+    assert _call(g, dtype=C, mode=_abi.IQDAS) == (0, "")
+    assert _call(g, dtype=C, mode=_abi.BBDMAS, angle=0) == (0, "")
+    for mode, dtype in ((_abi.IQDAS, _abi.F32), (_abi.BBDMAS, _abi.I16), (_abi.DAS, C),
+                        (_abi.PDAS, C)):
+        rc, msg = _call(g, dtype=dtype, mode=mode)
+        assert rc == _abi.E_INVALID and "IQ" in msg
+    assert _call(g, dtype=C, mode=5)[0] == _abi.E_INVALID
+    assert _call(g, rf=FAKE + 4, dtype=C, mode=_abi.IQDAS)[0] == _abi.E_INVALID  # 8-byte samples
+    # the complex image: imag only in the IQ modes, no band-pass there
+    assert _call(g, dtype=C, mode=_abi.IQDAS, out=_abi.Outputs(FAKE, None, FAKE, None, FAKE)) \
+        == (0, "")
+    rc, msg = _call(g, out=_abi.Outputs(FAKE, None, None, None, FAKE))
+    assert rc == _abi.E_INVALID and "imag" in msg
+    g2 = GeometryArg(config_c2(), bandpass=True)
+    rc, msg = _call(g2, dtype=C, mode=_abi.IQDAS)
+    assert rc == _abi.E_INVALID and "band-pass" in msg
+    # |image| needs no depth FFT: any nz
+    g3 = GeometryArg(config_c1().replace(nz=250))
+    assert _call(g3, dtype=C, mode=_abi.IQDAS, out=_abi.Outputs(FAKE, None, FAKE, None)) == (0, "")
+    g4 = GeometryArg(config_c1().replace(f0=0.0))
+    rc, msg = _call(g4, dtype=C, mode=_abi.IQDAS)
+    assert rc == _abi.E_INVALID and "f0" in msg
+
+
+def test_iq_demodulate_argument_errors():
+    L = _abi.lib()
+    g = GeometryArg(config_c1())
+    assert L.pwbf_iq_demodulate(None, FAKE, 0, FAKE, None) == _abi.E_INVALID
+    assert L.pwbf_iq_demodulate(g.ref, FAKE, _abi.C32, FAKE, None) == _abi.E_INVALID
+    assert L.pwbf_iq_demodulate(g.ref, None, 0, FAKE, None) == _abi.E_INVALID
+    assert L.pwbf_iq_demodulate(g.ref, FAKE + 1, 0, FAKE, None) == _abi.E_INVALID
+    assert L.pwbf_iq_demodulate(g.ref, FAKE, 0, FAKE + 4, None) == _abi.E_INVALID
+    for ns in (600, 8192):
+        gb = GeometryArg(config_c1().replace(n_samples=ns))
+        assert L.pwbf_iq_demodulate(gb.ref, FAKE, 0, FAKE, None) == _abi.E_UNSUPPORTED
+    gf = GeometryArg(config_c1().replace(f0=-1.0))
+    assert L.pwbf_iq_demodulate(gf.ref, FAKE, 0, FAKE, None) == _abi.E_INVALID
+    o = ctypes.byref(_abi.Outputs(FAKE, None, None, None))
+    assert L.pwbf_beamform_iqdas(g.ref, FAKE, -1, o, None, 0, None) == _abi.E_INVALID
+    assert L.pwbf_beamform_bbdmas(None, FAKE, 0, o, None, 0, None) == _abi.E_INVALID
+
+
 def test_batch_create_rejects_before_touching_the_device():
     g = GeometryArg(config_c1())
     ok = _frame(g)
@@ -240,6 +285,8 @@ def test_batch_create_rejects_before_touching_the_device():
     g20 = GeometryArg(config_c1().replace(angles_deg=tuple(range(-10, 10))))
     rc, msg = _create([_frame(g20)])
     assert rc == _abi.E_UNSUPPORTED and "16 angles" in msg
+    rc, msg = _create([_frame(g, dtype=_abi.C32, mode=_abi.IQDAS)])
+    assert rc == _abi.E_UNSUPPORTED and "single-frame" in msg
     bad = GeometryArg(config_c1())
     bad.s.dz = -1.0
     assert _create([ok, _frame(bad)])[0] == _abi.E_INVALID
@@ -281,6 +328,8 @@ def test_server_create_rejects_before_touching_the_device():
     assert rc == _abi.E_UNSUPPORTED and "16 angles" in msg and "probe 1" in msg
     rc, msg = _server_create([_probe(GeometryArg(config_c1().replace(nz=300)))])
     assert rc == _abi.E_UNSUPPORTED and "power of two" in msg
+    rc, msg = _server_create([_probe(g, mode=_abi.BBDMAS)])
+    assert rc == _abi.E_UNSUPPORTED and "single-frame" in msg
     slot = 64 * 2048 * 2 + 3 * 128 * 256 * 4 + 256  # FP16 RF, rf/env/log planes, frame max
     rc, msg = _server_create([ok], budget=slot - 1)
     assert rc == _abi.E_INVALID and f"needs {slot} bytes" in msg

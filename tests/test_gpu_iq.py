@@ -1,0 +1,124 @@
+"""GPU parity of the IQ path against the FP64 oracle: baseband demodulation,
+IQ-DAS and BB-DMAS (Eq. 4).
+
+The oracle demodulates the RF itself (numpy FFT in float64) and beamforms its own
+IQ data, so each test checks the whole GPU path (demodulation kernel and IQ
+beamformer) end to end. Bars, max-normalised over the complex plane
+(max |gpu - oracle| / max |oracle|): 1e-5 for the demodulated records and
+IQ-DAS; BB-DMAS takes the square root of each sample's amplitude, steep at
+zero like the signed root of DMAS, and uses the same widening (3e-5 below 16
+channels). The envelope is |y| and the log image follows from it.
+"""
+
+import zlib
+
+import numpy as np
+import pytest
+
+import oracle
+from synth import config_c1, config_c3, make_frame
+
+from cases import geom, rand_rf
+
+pytestmark = pytest.mark.gpu
+
+TOL32 = 1e-5
+TOL_DB = 0.1
+
+
+def _torch():
+    import torch
+    assert torch.cuda.is_available(), "these tests need the GPU"
+    return torch
+
+
+def cerr(gpu, ora):
+    m = np.abs(ora).max()
+    return float(np.abs(gpu - ora).max() / m) if m > 0 else float(np.abs(gpu).max())
+
+
+def tol_for(g, mode, angle):
+    from paper_2311_00482_amd import describe_plan
+    win = describe_plan(g, mode, angle)["win"]
+    tol = TOL32 * max(1.0, win / 64.0)
+    if mode == "bbdmas" and g.n_channels < 16:
+        tol = max(tol, 3e-5)
+    return tol
+
+
+def gpu_iq(g, rf):
+    from paper_2311_00482_amd import iq_demodulate
+    torch = _torch()
+    iq = iq_demodulate(g, torch.from_numpy(np.ascontiguousarray(rf)).cuda())
+    torch.cuda.synchronize()
+    return iq
+
+
+def run(g, iq, mode, angle, want=("rf", "imag", "env", "log")):
+    from paper_2311_00482_amd import beamform
+    torch = _torch()
+    out = beamform(g, iq, mode, angle, want=want)
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy().astype(np.float64) for k, v in out.items()}
+
+
+@pytest.mark.parametrize("kind", ["i16", "f32"])
+def test_demodulated_records_match_the_oracle(kind):
+    g = geom(n_samples=512, angles_deg=(-5.0, 4.0), n_channels=12)
+    rf = rand_rf(g, 5 if kind == "i16" else 6, kind)
+    got = gpu_iq(g, rf).cpu().numpy().astype(np.complex128)
+    ref = oracle.iq_demodulate(g, rf.astype(np.float64))
+    assert cerr(got, ref) <= TOL32
+
+
+IQ_SMALL = [
+    # name, geometry kwargs, mode, angle
+    ("iqdas_one_angle", dict(n_samples=512), "iqdas", 0),
+    ("iqdas_compound_3a", dict(n_samples=512, angles_deg=(-9.0, 0.0, 7.0), nx=21, nz=77),
+     "iqdas", -1),
+    ("iqdas_generic_7a", dict(n_samples=512, angles_deg=(-12., -8., -4., 0., 4., 8., 12.),
+                              nx=11, nz=40, n_channels=20), "iqdas", -1),
+    ("bbdmas_one_angle", dict(n_samples=512, n_channels=24), "bbdmas", 0),
+    ("bbdmas_compound_5a", dict(n_samples=1024, angles_deg=(-10., -5., 0., 5., 10.),
+                                n_channels=20), "bbdmas", -1),
+    ("bbdmas_few_channels", dict(n_samples=512, n_channels=6, nx=9, nz=33), "bbdmas", 0),
+]
+
+
+@pytest.mark.parametrize("name,kw,mode,angle", IQ_SMALL, ids=[c[0] for c in IQ_SMALL])
+def test_iq_small_cases_whole_image(name, kw, mode, angle):
+    g = geom(**kw)
+    rf = rand_rf(g, zlib.crc32(name.encode()) % 1000, "f32")
+    out = run(g, gpu_iq(g, rf), mode, angle)
+    ref = oracle.iq_beamform(g, oracle.iq_demodulate(g, rf.astype(np.float64)), mode, angle)
+    tol = tol_for(g, mode, angle)
+    e = cerr(out["rf"] + 1j * out["imag"], ref)
+    assert e <= tol, e
+    env = np.abs(ref)
+    assert cerr(out["env"], env) <= tol
+    lg = np.maximum(20 * np.log10(np.maximum(env, 1e-300) / out["env"].max()), -70.0)
+    m = lg >= -40.0
+    assert float(np.abs(out["log"][m] - lg[m]).max()) <= TOL_DB
+
+
+@pytest.mark.parametrize("mode", ["iqdas", "bbdmas"])
+def test_iq_single_frame_workload_whole_image(mode):
+    # 64 channels, 0 deg, 128 x 256 pixels, 10-bit int16 RF
+    g = config_c1()
+    fr = make_frame(g, 1001, "c1")
+    out = run(g, gpu_iq(g, fr["i16"]), mode, 0)
+    ref = oracle.iq_beamform(g, oracle.iq_demodulate(g, fr["master"]), mode, 0)
+    assert cerr(out["rf"] + 1j * out["imag"], ref) <= tol_for(g, mode, 0)
+
+
+def test_iq_das_compound_full_size_sampled():
+    # the 11-angle 128-channel 1024 x 1024 workload, FP32 RF, sampled pixels
+    g = config_c3()
+    fr = make_frame(g, 1003, "c3", quantize=False)
+    out = run(g, gpu_iq(g, fr["f32"]), "iqdas", -1, want=("rf", "imag", "env"))
+    rng = np.random.default_rng(9)
+    pix = rng.choice(g.nx * g.nz, 1500, replace=False)
+    ref = oracle.iq_beamform(g, oracle.iq_demodulate(g, fr["master"]), "iqdas", -1, pix=pix)
+    got = (out["rf"] + 1j * out["imag"]).ravel()[pix]
+    norm = out["env"].max()
+    assert float(np.abs(got - ref).max() / norm) <= tol_for(g, "iqdas", -1)
