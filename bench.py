@@ -69,8 +69,16 @@ def aperture_pairs(g) -> int:
 # weighted accumulate = 10; per (pixel, channel) the DAS terms without the
 # weighted accumulate = 8; per (pixel, angle) the transmit delay and the signed
 # p-th power (|t|, log2, times p, exp2, sign, add) = 8.
+# IQ-DAS: delay add, floor, two interpolation FMAs (real and imaginary lines),
+# complex multiply-accumulate with the receive phasor (4) = 8 per gather; per
+# (pixel, channel) the DAS terms plus the receive phase (multiply, cos, sin,
+# complex multiply by the tile's integer-part phasor, weight) = 18; per (pixel,
+# angle) the transmit delay, its phasor (multiply, cos, sin, complex multiply),
+# the complex multiply of the angle's sum and the add = 14. BB-DMAS adds |q|^2,
+# square root, reciprocal square root, a select and two scalings per gather
+# (14) and the square of each angle's sum (17 per (pixel, angle)).
 MODE_OPS = {"das": (OPS_PER_GATHER, OPS_PER_PIX_CH, OPS_PER_PIX_ANGLE), "dmas": (9, 10, 3),
-            "pdas": (10, 8, 8)}
+            "pdas": (10, 8, 8), "iqdas": (8, 18, 14), "bbdmas": (14, 18, 17)}
 
 
 def algorithmic_ops(g, mode: str = "das") -> float:
@@ -184,6 +192,57 @@ def other_modes(dev, torch, steps: int, warmup: int) -> dict:
                      "rf_storage": "int16" if quant else "f32"}
         print(f"[bench] {name}: {res[name]['kernel_ms']:.3f} ms kernel, "
               f"frac {res[name]['roofline']['frac']:.2f}", file=sys.stderr, flush=True)
+    res.update(iq_modes(dev, torch, steps, warmup))
+    return res
+
+
+def iq_modes(dev, torch, steps: int, warmup: int) -> dict:
+    """The IQ path on the 11-angle compound workload (FP32 RF): the demodulation
+    kernel (HBM-bound: reads the RF once, writes 8-byte complex samples), and
+    IQ-DAS / BB-DMAS from the demodulated records (kernel time, roofline, and the
+    frame rate of demodulation + beamforming + log)."""
+    from paper_2311_00482_amd import GeometryArg, beamform, iq_demodulate
+    from synth import config_c3, make_frame
+
+    gs = config_c3()
+    g = GeometryArg(gs)
+    rf = torch.from_numpy(make_frame(gs, 1003, "c3", quantize=False)["f32"]).to(dev)
+    iq = iq_demodulate(g, rf)
+    n = max(20, steps // 3)
+    w = max(5, warmup // 3)
+    _, dlat, _ = time_steps(lambda: iq_demodulate(g, rf, out=iq), n, w, torch)
+    d_ms = float(np.mean(dlat))
+    bytes_moved = rf.numel() * 4 + iq.numel() * 8
+    res = {"iq_demod_11a_128ch_4096": {
+        "kernel_ms": d_ms, "records": gs.n_angles * gs.n_channels,
+        "roofline": {"bound": "hbm", "achieved": bytes_moved / (d_ms * 1e-3) / 1e9,
+                     "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                     "frac": bytes_moved / (d_ms * 1e-3) / HBM_PEAK,
+                     "bytes_per_launch": float(bytes_moved)}}}
+    want = ("rf", "imag", "env", "log")
+    outs = {k: torch.empty((g.nx, g.nz), dtype=torch.float32, device=dev) for k in want}
+    ws = torch.empty(4096, dtype=torch.uint8, device=dev)
+    rf_only = {"rf": outs["rf"], "imag": outs["imag"]}
+    for mode in ("iqdas", "bbdmas"):
+        def frame():
+            iq_demodulate(g, rf, out=iq)
+            beamform(g, iq, mode, -1, want=want, out=outs, workspace=ws)
+        wall, lat, _ = time_steps(frame, n, w, torch)
+        _, klat, _ = time_steps(lambda: beamform(g, iq, mode, -1, want=("rf", "imag"),
+                                                 out=rf_only), n, w, torch)
+        k_ms = float(np.mean(klat))
+        ops = algorithmic_ops(gs, mode)
+        name = f"{mode}_compound_11a_1024x1024"
+        res[name] = {"frames_per_s": n / wall, "p50_ms": float(np.percentile(lat, 50)),
+                     "p99_ms": float(np.percentile(lat, 99)), "kernel_ms": k_ms,
+                     "value": gs.gathers / (k_ms * 1e-3) / 1e9, "unit": UNIT,
+                     "roofline": {"bound": "alu", "achieved": ops / (k_ms * 1e-3) / 1e12,
+                                  "peak": VALU_LANE_OPS_PEAK / 1e12, "unit": "Tlane-op/s",
+                                  "frac": ops / (k_ms * 1e-3) / VALU_LANE_OPS_PEAK,
+                                  "ops_per_launch": ops},
+                     "rf_storage": "f32 -> complex64 IQ"}
+        print(f"[bench] {name}: {k_ms:.3f} ms kernel, frac {res[name]['roofline']['frac']:.2f}",
+              file=sys.stderr, flush=True)
     return res
 
 
@@ -306,7 +365,8 @@ def main():
                     help="skip the batched and served FP16 measurements")
     ap.add_argument("--no-modes", action="store_true",
                     help="skip the DMAS and pDAS measurements")
-    ap.add_argument("--profile-mode", default="das", choices=("das", "pdas", "dmas"),
+    ap.add_argument("--profile-mode", default="das",
+                    choices=("das", "pdas", "dmas", "iqdas", "bbdmas"),
                     help="with --profile-only: the beamformer of the timed loop (dmas and "
                          "pdas run on the 128-channel 512 x 512 DMAS workload, pdas also "
                          "takes the compound workload with --profile-compound)")
@@ -362,6 +422,19 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    if args.profile_only and args.profile_mode in ("iqdas", "bbdmas"):
+        from paper_2311_00482_amd import iq_demodulate
+        iq = iq_demodulate(g, rf32)
+        wantq = ("rf", "imag", "env", "log")
+        outq = {k: torch.empty((g.nx, g.nz), dtype=torch.float32, device=dev) for k in wantq}
+
+        def iq_step():
+            iq_demodulate(g, rf32, out=iq)
+            beamform(g, iq, args.profile_mode, -1, want=wantq, out=outq, workspace=ws)
+        wall, _, _ = time_steps(iq_step, args.steps, args.warmup, torch)
+        print(json.dumps({"profile_only": True, "mode": args.profile_mode,
+                          "ms_per_step": wall / args.steps * 1e3}))
+        return
     if args.profile_only and args.profile_mode != "das":
         from synth import config_c2
         if args.profile_mode == "pdas" and args.profile_compound:
