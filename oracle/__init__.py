@@ -12,6 +12,8 @@ as the transform. Geometry objects are duck-typed: anything with the attributes
 of ``synth.Geometry`` (elem_x, angles_rad, t0_s, c, fs, nx, nz, x0, dx, z0, dz,
 f_number, apod_code, n_samples, f0).
 
+Image metrics (FWHM, Eq. (5) CR, Eq. (6) CNR) are in ``oracle/metrics.py``.
+
 Paper passages followed: Eq. (1) and the delay text after it (DAS); Eq. (2) and
 Eq. (4) for the signed-root compression and the squared-sum form of DMAS;
 Eqs. (2)-(3) for pDAS (p-th root before the sum, signed p-th power after);
