@@ -246,6 +246,46 @@ def iq_modes(dev, torch, steps: int, warmup: int) -> dict:
     return res
 
 
+def image_metrics(dev, torch, g, gs, phantom, env32, env16) -> dict:
+    """CR / CNR (Eqs. 5-6) of the phantom's anechoic cysts and the FWHM of its
+    point targets on the FP32- and FP16-stored frames' envelopes, with the
+    metric kernels' time (HIP events, mean of 20 launches each)."""
+    from paper_2311_00482_amd import _abi
+    from paper_2311_00482_amd import contrast_metrics, resolution_metrics
+    import ctypes
+
+    cysts = []
+    for cx, cz, r in phantom.cysts:
+        side = 1.0 if cx < 0 else -1.0
+        cysts.append(((cx, cz, 0.8 * r), (cx + side * 2.2 * r, cz, 0.8 * r)))
+    targets = [(float(x), float(z), 1.0e-3) for x, z in phantom.points]
+    res = {}
+    for name, env in (("f32", env32), ("f16", env16)):
+        c = contrast_metrics(g, env, cysts)
+        t = resolution_metrics(g, env, targets)
+        fx = [v["fwhm_x"] for v in t if v["fwhm_x"] == v["fwhm_x"]]
+        fz = [v["fwhm_z"] for v in t if v["fwhm_z"] == v["fwhm_z"]]
+        res[name] = {"cr_db": [v["cr_db"] for v in c], "cnr": [v["cnr"] for v in c],
+                     "fwhm_x_mm_median": float(np.median(fx)) * 1e3 if fx else None,
+                     "fwhm_z_mm_median": float(np.median(fz)) * 1e3 if fz else None}
+    # kernel time
+    L = _abi.lib()
+    arr_c = (_abi.Cyst * len(cysts))(*[_abi.Cyst(_abi.Disc(*a), _abi.Disc(*b)) for a, b in cysts])
+    arr_t = (_abi.Disc * len(targets))(*[_abi.Disc(*t) for t in targets])
+    out = torch.empty(4096, dtype=torch.uint8, device=dev)
+    stream = ctypes.c_void_p(int(torch.cuda.current_stream().cuda_stream))
+    _, lc, _ = time_steps(lambda: L.pwbf_contrast_metrics(g.ref, env32.data_ptr(), arr_c,
+                                                          len(cysts), out.data_ptr(), stream),
+                          20, 3, torch)
+    _, lt, _ = time_steps(lambda: L.pwbf_resolution_metrics(g.ref, env32.data_ptr(), arr_t,
+                                                            len(targets), out.data_ptr(), stream),
+                          20, 3, torch)
+    res["contrast_kernel_ms"] = float(np.mean(lc))
+    res["resolution_kernel_ms"] = float(np.mean(lt))
+    res["regions"] = {"cysts": len(cysts), "targets": len(targets)}
+    return res
+
+
 def systems(dev, torch, steps: int, warmup: int) -> dict:
     """Single-frame FP32 against batched and served FP16 on the same GPU.
 
@@ -504,6 +544,13 @@ def main():
                                      "latency_ms": {"p50": float(np.percentile(lat16, 50)),
                                                     "p99": float(np.percentile(lat16, 99))}}},
     }
+    print("[bench] image metrics", file=sys.stderr, flush=True)
+    env16 = torch.empty_like(outs["env"])
+    beamform(g, rf16, "das", -1, want=("rf", "env"), out={"rf": torch.empty_like(env16),
+                                                           "env": env16})
+    beamform(g, rf32, "das", -1, want=want, out=outs, workspace=ws)
+    torch.cuda.synchronize()
+    line["image_metrics"] = image_metrics(dev, torch, g, gs, fr["phantom"], outs["env"], env16)
     if not args.no_modes:
         print("[bench] DMAS and pDAS", file=sys.stderr, flush=True)
         line["modes"] = other_modes(dev, torch, args.steps, args.warmup)

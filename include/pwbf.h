@@ -203,6 +203,51 @@ PWBF_API int pwbf_beamform_bbdmas(const pwbf_geometry *g, const void *iq, int32_
                                   const pwbf_outputs *out, void *workspace,
                                   size_t workspace_bytes, void *stream);
 
+/* Image metrics of the evaluation (Section II-D) on an envelope image env,
+ * device float32 [nx][nz] of the grid in g (any plane of the calls above).
+ * Regions are discs (centre x, z and radius r in m); a pixel belongs to a disc
+ * when ((ix - cx) sx)^2 + ((iz - cz) sz)^2 <= 1 in separately rounded float32
+ * operations, with cx = (x - x0)/dx, cz = (z - z0)/dz, sx = dx/r, sz = dz/r
+ * rounded to float32 once. Results go to caller-owned device memory; at most
+ * PWBF_MAX_METRIC_REGIONS cysts or targets per call. */
+#define PWBF_MAX_METRIC_REGIONS 32
+
+typedef struct pwbf_disc {
+  double x, z, r; /* centre and radius, m (r > 0) */
+} pwbf_disc;
+
+typedef struct pwbf_cyst {
+  pwbf_disc in;  /* inside the cyst */
+  pwbf_disc out; /* background */
+} pwbf_cyst;
+
+typedef struct pwbf_contrast {
+  float mu_in, mu_out;       /* mean envelope inside / background */
+  float sigma_in, sigma_out; /* population standard deviations */
+  float cr_db;               /* Eq. (5): 20 log10(mu_in / mu_out) */
+  float cnr;                 /* Eq. (6), denominator read as sqrt((sigma_in^2 + sigma_out^2) / 2) */
+  int32_t n_in, n_out;       /* pixels in each disc (NaN statistics when 0) */
+} pwbf_contrast;
+
+typedef struct pwbf_resolution {
+  float peak;           /* envelope maximum in the target disc (first flat index on ties) */
+  float fwhm_x, fwhm_z; /* full widths at half the peak (-6.02 dB) of the lateral and axial
+                           profiles through the peak, m, crossings interpolated linearly
+                           between pixels; NaN when a side never falls below half */
+  int32_t ix, iz;       /* pixel of the peak; -1 when the disc holds no pixel */
+} pwbf_resolution;
+
+/* CR and CNR (Eqs. (5)-(6)) for n cysts; out: device pwbf_contrast[n]. */
+PWBF_API int pwbf_contrast_metrics(const pwbf_geometry *g, const float *env,
+                                   const pwbf_cyst *cysts, int32_t n, pwbf_contrast *out,
+                                   void *stream);
+
+/* FWHM of n point targets (the peak is searched inside each target disc);
+ * out: device pwbf_resolution[n]. */
+PWBF_API int pwbf_resolution_metrics(const pwbf_geometry *g, const float *env,
+                                     const pwbf_disc *targets, int32_t n, pwbf_resolution *out,
+                                     void *stream);
+
 /* Coherent compounding: the unweighted sum over all n_angles of the per-angle
  * DAS (mode PWBF_DAS), DMAS (PWBF_DMAS), pDAS (PWBF_PDAS) images, or of the
  * complex IQ-DAS (PWBF_IQDAS) or BB-DMAS (PWBF_BBDMAS) values, in one pass that shares

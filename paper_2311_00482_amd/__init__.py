@@ -21,8 +21,10 @@ from .api import (  # noqa: F401
     beamform_iqdas,
     beamform_pdas,
     compound,
+    contrast_metrics,
     describe_plan,
     iq_demodulate,
+    resolution_metrics,
     tune,
     tune_clear,
     tune_load,

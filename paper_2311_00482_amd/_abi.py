@@ -74,6 +74,28 @@ class BatchInfo(ctypes.Structure):
 BATCH_TUNE = 1
 
 
+class Disc(ctypes.Structure):
+    _fields_ = [("x", ctypes.c_double), ("z", ctypes.c_double), ("r", ctypes.c_double)]
+
+
+class Cyst(ctypes.Structure):
+    _fields_ = [("inside", Disc), ("out", Disc)]
+
+
+class Contrast(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_float) for n in ("mu_in", "mu_out", "sigma_in", "sigma_out",
+                                               "cr_db", "cnr")] + \
+               [("n_in", ctypes.c_int32), ("n_out", ctypes.c_int32)]
+
+
+class Resolution(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_float) for n in ("peak", "fwhm_x", "fwhm_z")] + \
+               [("ix", ctypes.c_int32), ("iz", ctypes.c_int32)]
+
+
+MAX_METRIC_REGIONS = 32
+
+
 class Probe(ctypes.Structure):
     _fields_ = [("geom", ctypes.POINTER(Geometry)), ("mode", ctypes.c_int32),
                 ("angle", ctypes.c_int32), ("want_env", ctypes.c_int32),
@@ -147,6 +169,10 @@ def lib():
         f = getattr(L, name)
         f.restype = ctypes.c_int
         f.argtypes = [G, vp, i32, i32, O, vp, sz, vp]
+    L.pwbf_contrast_metrics.restype = ctypes.c_int
+    L.pwbf_contrast_metrics.argtypes = [G, vp, ctypes.POINTER(Cyst), i32, vp, vp]
+    L.pwbf_resolution_metrics.restype = ctypes.c_int
+    L.pwbf_resolution_metrics.argtypes = [G, vp, ctypes.POINTER(Disc), i32, vp, vp]
     L.pwbf_iq_demodulate.restype = ctypes.c_int
     L.pwbf_iq_demodulate.argtypes = [G, vp, i32, vp, vp]
     for name in ("pwbf_beamform_iqdas", "pwbf_beamform_bbdmas"):

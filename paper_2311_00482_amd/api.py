@@ -204,6 +204,48 @@ def iq_demodulate(g, rf, out=None, stream=None):
     return out
 
 
+def _metric_out(torch, n, struct, dev):
+    return torch.empty(n * ctypes.sizeof(struct), dtype=torch.uint8, device=dev)
+
+
+def _read_structs(buf, struct, n):
+    raw = bytes(buf.cpu().numpy().tobytes())
+    arr = (struct * n).from_buffer_copy(raw)
+    return [{k: getattr(a, k) for k, _ in struct._fields_} for a in arr]
+
+
+def contrast_metrics(g, env, cysts, stream=None):
+    """pwbf_contrast_metrics: CR (Eq. 5) and CNR (Eq. 6) of cysts on an envelope
+    image (float32 CUDA [nx, nz]). ``cysts``: ((x, z, r) inside, (x, z, r)
+    background) in metres. Waits for the stream and returns one dict per cyst."""
+    import torch
+    ga = _as_geom(g)
+    n = len(cysts)
+    arr = (_abi.Cyst * max(1, n))(*[_abi.Cyst(_abi.Disc(*c[0]), _abi.Disc(*c[1])) for c in cysts])
+    out = _metric_out(torch, max(1, n), _abi.Contrast, env.device)
+    _abi.check(_abi.lib().pwbf_contrast_metrics(ga.ref, _ptr(env), arr, n, _ptr(out),
+                                                _stream_ptr(stream, env.device)))
+    torch.cuda.synchronize(env.device)
+    res = _read_structs(out, _abi.Contrast, n)
+    for r in res:
+        r["mu_in"], r["mu_out"] = float(r["mu_in"]), float(r["mu_out"])
+    return res
+
+
+def resolution_metrics(g, env, targets, stream=None):
+    """pwbf_resolution_metrics: peak and lateral / axial FWHM (m) of point
+    targets searched inside discs (x, z, r) in metres. Waits for the stream."""
+    import torch
+    ga = _as_geom(g)
+    n = len(targets)
+    arr = (_abi.Disc * max(1, n))(*[_abi.Disc(*t) for t in targets])
+    out = _metric_out(torch, max(1, n), _abi.Resolution, env.device)
+    _abi.check(_abi.lib().pwbf_resolution_metrics(ga.ref, _ptr(env), arr, n, _ptr(out),
+                                                  _stream_ptr(stream, env.device)))
+    torch.cuda.synchronize(env.device)
+    return _read_structs(out, _abi.Resolution, n)
+
+
 def beamform_iqdas(g, iq, angle: int, **kw) -> Dict:
     """pwbf_beamform_iqdas: DAS of the delay-compensated IQ samples for one angle."""
     if angle < 0:

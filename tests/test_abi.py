@@ -274,6 +274,25 @@ def test_iq_demodulate_argument_errors():
     assert L.pwbf_beamform_bbdmas(None, FAKE, 0, o, None, 0, None) == _abi.E_INVALID
 
 
+def test_metrics_argument_errors():
+    L = _abi.lib()
+    g = GeometryArg(config_c1())
+    d = _abi.Disc(0.0, 20e-3, 1e-3)
+    cy = (_abi.Cyst * 1)(_abi.Cyst(d, d))
+    tg = (_abi.Disc * 1)(d)
+    assert L.pwbf_contrast_metrics(None, FAKE, cy, 1, FAKE, None) == _abi.E_INVALID
+    assert L.pwbf_contrast_metrics(g.ref, None, cy, 1, FAKE, None) == _abi.E_INVALID
+    assert L.pwbf_contrast_metrics(g.ref, FAKE, cy, 0, FAKE, None) == _abi.E_INVALID
+    assert L.pwbf_contrast_metrics(g.ref, FAKE, cy, 33, FAKE, None) == _abi.E_INVALID
+    assert L.pwbf_contrast_metrics(g.ref, FAKE, None, 1, FAKE, None) == _abi.E_INVALID
+    assert L.pwbf_contrast_metrics(g.ref, FAKE, cy, 1, None, None) == _abi.E_INVALID
+    bad = (_abi.Cyst * 1)(_abi.Cyst(_abi.Disc(0.0, 20e-3, 0.0), d))
+    assert L.pwbf_contrast_metrics(g.ref, FAKE, bad, 1, FAKE, None) == _abi.E_INVALID
+    nan = (_abi.Disc * 1)(_abi.Disc(float("nan"), 20e-3, 1e-3))
+    assert L.pwbf_resolution_metrics(g.ref, FAKE, nan, 1, FAKE, None) == _abi.E_INVALID
+    assert L.pwbf_resolution_metrics(g.ref, FAKE + 2, tg, 1, FAKE, None) == _abi.E_INVALID
+
+
 def test_batch_create_rejects_before_touching_the_device():
     g = GeometryArg(config_c1())
     ok = _frame(g)
