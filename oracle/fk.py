@@ -18,8 +18,11 @@ array of uniform pitch p (element e at x_e = x_first + e p):
     kx_m = m / (Nx p) for m < Nx / 2, (m - Nx) / (Nx p) otherwise.
  3. Stolt mapping with an exploding-reflector velocity v: the image spectrum at
     (kx_m, kz_j = j df / v), 0 <= j <= Nt / 2, is the data spectrum at
-    f = v sqrt(kx^2 + kz^2), linearly interpolated between bins (zero at or past
-    Nt / 2), times kz / sqrt(kx^2 + kz^2) (the Jacobian; 0 at the origin).
+    f = v sqrt(kx^2 + kz^2), linearly interpolated between bins of the one-sided
+    spectrum extended by zeros past bin Nt / 2 (so it falls linearly to zero
+    between bins Nt / 2 and Nt / 2 + 1 and is zero beyond; the value is then
+    continuous in f, and rounding of f at exactly Nt / 2 cannot change it),
+    times kz / sqrt(kx^2 + kz^2) (the Jacobian; 0 at the origin).
     v and the coordinate map are chosen so that the exploding-reflector
     hyperbola matches t'(x) at its apex in position, time and curvature: the
     apex is at x0 + z0 tan th, t' = 2 z0 cos th / c, curvature cos^3 th / (z0 c),
@@ -84,11 +87,13 @@ def migrate_angle(g, rf_a: np.ndarray, a: int) -> np.ndarray:
     rho = np.hypot(kx[:, None], kz[None, :])
     u = v * rho / df
     i0 = np.floor(u).astype(np.int64)
-    ok = (rho > 0) & (i0 + 1 <= Nt // 2)
+    ok = (rho > 0) & (i0 <= Nt // 2)
     i0c = np.where(ok, i0, 0)
     w = u - i0
-    lo = np.take_along_axis(Psi, i0c, axis=1)
-    hi = np.take_along_axis(Psi, i0c + 1, axis=1)
+    # the spectrum extended by one zero bin past Nt / 2
+    Psi_z = np.concatenate([Psi, np.zeros((Nx, 1), dtype=complex)], axis=1)
+    lo = np.take_along_axis(Psi_z, i0c, axis=1)
+    hi = np.take_along_axis(Psi_z, i0c + 1, axis=1)
     jac = np.divide(kz[None, :], rho, out=np.zeros_like(rho), where=rho > 0)
     I = np.where(ok, ((1.0 - w) * lo + w * hi) * jac, 0.0)
     img_kz = np.fft.ifft(I, axis=0)  # back to x1 positions

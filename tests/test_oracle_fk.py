@@ -77,10 +77,11 @@ def _brute_migrate(g, rf_a, a):
                 continue
             u = v * rho / df
             i0 = math.floor(u)
-            if i0 + 1 > Nt // 2:
+            if i0 > Nt // 2:
                 continue
             w = u - i0
-            I[m][j] = ((1 - w) * Psi[m][i0] + w * Psi[m][i0 + 1]) * kz / rho
+            nxt = Psi[m][i0 + 1] if i0 + 1 <= Nt // 2 else 0j  # zero past the last bin
+            I[m][j] = ((1 - w) * Psi[m][i0] + w * nxt) * kz / rho
     M = np.zeros((Nx, Nt), dtype=complex)
     for xe in range(Nx):
         for l in range(Nt):
@@ -100,3 +101,18 @@ def test_migration_matches_explicit_sums(deg):
     got = fk.migrate_angle(g, rf[0], 0)
     ref = _brute_migrate(g, rf[0], 0)
     np.testing.assert_allclose(got, ref, atol=1e-12 * np.abs(ref).max())
+
+
+@pytest.mark.parametrize("deg", [-9.0, 0.0, 7.0])
+def test_stolt_map_is_continuous_at_the_band_edge(deg):
+    """The source bin of the (kx = 0, Nyquist) cell is exactly Nt / 2; a change of
+    the angle far below any physical meaning (1e-12 rad) moves it across that
+    bin by rounding and must not change the migrated image."""
+    g = Geometry(n_channels=16, n_samples=1024, angles_deg=(deg,), nx=8, nz=8,
+                 x_min=-1e-3, x_max=1e-3, z_min=5e-3, z_max=7e-3)
+    rf = np.random.default_rng(5).standard_normal((16, 1024))
+    a = fk.migrate_angle(g, rf, 0)
+    eps = math.degrees(1e-12)
+    for d in (-eps, eps):
+        b = fk.migrate_angle(g.replace(angles_deg=(deg + d,)), rf, 0)
+        assert np.abs(a - b).max() <= 1e-9 * np.abs(a).max()
