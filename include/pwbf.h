@@ -248,6 +248,45 @@ PWBF_API int pwbf_resolution_metrics(const pwbf_geometry *g, const float *env,
                                      const pwbf_disc *targets, int32_t n, pwbf_resolution *out,
                                      void *stream);
 
+/* Stolt f-k migration of steered plane waves (listed among the beamformers of
+ * Section II-B; the paper gives no formula, so this is the reading the library
+ * implements). Per angle th, with Nt = n_samples, Nx = the power of two >= 2 n_channels
+ * and p the (uniform) element pitch:
+ *  1. temporal spectrum of every trace (e^{-2 pi i f t}), bins f_k = k fs / Nt for
+ *     0 <= k <= Nt / 2, times exp(2 pi i f_k (tau_e - t0[a])) where tau_e =
+ *     (x_e sin th - min_k x_k sin th) / c is the element's firing delay;
+ *  2. spectrum along the array zero-padded to Nx (kx_m = m / (Nx p), signed);
+ *  3. Stolt mapping with v = c / (sqrt2 cos^2 th): the image spectrum at
+ *     (kx, kz_j = j fs / (Nt v)) is the data spectrum at f = v sqrt(kx^2 + kz^2),
+ *     linearly interpolated between bins of the one-sided spectrum extended by
+ *     zeros past bin Nt / 2 (continuous in f), times kz / sqrt(kx^2 + kz^2)
+ *     (0 at the origin);
+ *  4. inverse transforms along kx (Nx) and along kz with the one-sided spectrum
+ *     zero-filled to Nt, scaled by 1 / (Nx Nt): the complex migrated image on
+ *     x1 = elem_x[0] + e' p, z1 = l v / fs;
+ *  5. output pixel (x, z) takes that image at (x + z tan th, sqrt2 z / cos th) by
+ *     bilinear interpolation (zero outside); angles add (complex).
+ * v and the map in step 5 put the migrated point of a scatterer where the
+ * plane-wave travel-time curve has its apex, with matching curvature.
+ *  rf        device RF[n_angles][n_channels][n_samples] (int16, FP16 or FP32)
+ *  angle     0..n_angles-1, or -1 for the sum over all angles
+ *  out       rf = real part, imag = imaginary part, env = magnitude (the image),
+ *            logimg from env; filtered must be NULL and bandpass 0
+ *  workspace device, 256-byte aligned, >= pwbf_fk_workspace_bytes(g, angle, out)
+ *            bytes: the spectra and migrated images of every angle of the call
+ *            (about 16 (Nt/2 + 1) Nx + 8 Nx Nt bytes per angle; 17 MB per angle at
+ *            128 channels x 4096 samples)
+ * Needs n_channels >= 2 with a uniform pitch (within 1e-6 p; the element
+ * positions used are elem_x[0] + e p), n_samples a power of two in 2..4096
+ * (PWBF_E_UNSUPPORTED otherwise). apod and f_number are unused. Work is enqueued
+ * on stream. pwbf_fk_workspace_bytes returns 0 (and sets the last error) when the
+ * call is not supported. */
+PWBF_API size_t pwbf_fk_workspace_bytes(const pwbf_geometry *g, int32_t angle,
+                                        const pwbf_outputs *out);
+PWBF_API int pwbf_fk_migrate(const pwbf_geometry *g, const void *rf, int32_t rf_dtype,
+                             int32_t angle, const pwbf_outputs *out, void *workspace,
+                             size_t workspace_bytes, void *stream);
+
 /* Coherent compounding: the unweighted sum over all n_angles of the per-angle
  * DAS (mode PWBF_DAS), DMAS (PWBF_DMAS), pDAS (PWBF_PDAS) images, or of the
  * complex IQ-DAS (PWBF_IQDAS) or BB-DMAS (PWBF_BBDMAS) values, in one pass that shares

@@ -23,6 +23,8 @@ from .api import (  # noqa: F401
     compound,
     contrast_metrics,
     describe_plan,
+    fk_migrate,
+    fk_workspace_bytes,
     iq_demodulate,
     resolution_metrics,
     tune,

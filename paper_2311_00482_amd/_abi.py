@@ -175,6 +175,10 @@ def lib():
     L.pwbf_resolution_metrics.argtypes = [G, vp, ctypes.POINTER(Disc), i32, vp, vp]
     L.pwbf_iq_demodulate.restype = ctypes.c_int
     L.pwbf_iq_demodulate.argtypes = [G, vp, i32, vp, vp]
+    L.pwbf_fk_workspace_bytes.restype = sz
+    L.pwbf_fk_workspace_bytes.argtypes = [G, i32, O]
+    L.pwbf_fk_migrate.restype = ctypes.c_int
+    L.pwbf_fk_migrate.argtypes = [G, vp, i32, i32, O, vp, sz, vp]
     for name in ("pwbf_beamform_iqdas", "pwbf_beamform_bbdmas"):
         f = getattr(L, name)
         f.restype = ctypes.c_int

@@ -204,6 +204,50 @@ def iq_demodulate(g, rf, out=None, stream=None):
     return out
 
 
+def fk_workspace_bytes(g, want: Iterable[str] = ("rf",), angle: int = -1) -> int:
+    """pwbf_fk_workspace_bytes: device workspace of an f-k migration call."""
+    ga = _as_geom(g)
+    want = set(want)
+    o = _abi.Outputs(1, None, 1 if "env" in want else None, 1 if "log" in want else None,
+                     1 if "imag" in want else None)
+    n = _abi.lib().pwbf_fk_workspace_bytes(ga.ref, angle, ctypes.byref(o))
+    if n == 0:
+        raise _abi.PwbfError(_abi.E_UNSUPPORTED, _abi.lib().pwbf_last_error().decode())
+    return int(n)
+
+
+def fk_migrate(g, rf, angle: int = -1, want: Iterable[str] = ("rf", "imag", "env"),
+               out: Optional[Dict] = None, workspace=None, stream=None,
+               log_floor_db: float = -70.0) -> Dict:
+    """pwbf_fk_migrate: Stolt f-k migration of RF [A, N, Ns] (int16/float16/float32),
+    one angle or (angle -1) the complex sum over all angles. Planes "rf" (real
+    part), "imag", "env" (magnitude) and "log"."""
+    import torch
+    ga = _as_geom(g, False, log_floor_db)
+    if not rf.is_cuda or not rf.is_contiguous() or tuple(rf.shape) != ga.shape_rf:
+        raise ValueError(f"rf must be a contiguous CUDA tensor {ga.shape_rf}")
+    want = set(want) | {"rf"}
+    unknown = want - {"rf", "imag", "env", "log"}
+    if unknown:
+        raise ValueError(f"unknown output planes {sorted(unknown)}")
+    out = dict(out or {})
+    for k in want:
+        if k not in out:
+            out[k] = torch.empty((ga.nx, ga.nz), dtype=torch.float32, device=rf.device)
+    o = _abi.Outputs(_ptr(out.get("rf")), None, _ptr(out.get("env")), _ptr(out.get("log")),
+                     _ptr(out.get("imag")))
+    need = _abi.lib().pwbf_fk_workspace_bytes(ga.ref, angle, ctypes.byref(o))
+    if need == 0:
+        raise _abi.PwbfError(_abi.E_UNSUPPORTED, _abi.lib().pwbf_last_error().decode())
+    if workspace is None:
+        workspace = torch.empty(need, dtype=torch.uint8, device=rf.device)
+    ws_bytes = workspace.numel() * workspace.element_size()
+    _abi.check(_abi.lib().pwbf_fk_migrate(ga.ref, _ptr(rf), _rf_code(rf), angle,
+                                          ctypes.byref(o), _ptr(workspace), ws_bytes,
+                                          _stream_ptr(stream, rf.device)))
+    return out
+
+
 def _metric_out(torch, n, struct, dev):
     return torch.empty(n * ctypes.sizeof(struct), dtype=torch.uint8, device=dev)
 

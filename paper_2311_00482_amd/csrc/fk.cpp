@@ -1,0 +1,213 @@
+// Host side of the Stolt f-k migration (Section II-B): validation, workspace
+// layout and the per-angle constants, taken in float64 and split once into
+// float-float pairs.
+//
+// Per steering angle th the exploding-reflector velocity is v = c / (sqrt2 cos^2 th)
+// and an output pixel (x0, z0) reads the migrated image at
+// (x0 + z0 tan th, sqrt2 z0 / cos th): the exploding-reflector hyperbola of that
+// velocity then has the apex position, apex time and apex curvature of the
+// plane-wave travel time of a scatterer at (x0, z0).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <string>
+
+#include "../../include/pwbf.h"
+#include "fk.h"
+#include "plan_host.h"
+
+namespace pwbf {
+int api_set_error(int code, const std::string &msg);
+void api_clear_error();
+}  // namespace pwbf
+
+using pwbf::api_set_error;
+
+namespace {
+
+int log2_exact(int n) {
+  int l = 0;
+  while ((1 << l) < n) ++l;
+  return (1 << l) == n ? l : -1;
+}
+
+struct FkShape {
+  int log2nt, log2nx, nt, nx, kbins;
+  double pitch;
+};
+
+int fk_shape(const pwbf_geometry *g, FkShape *s, std::string *err) {
+  int rc = pwbf::validate_geometry(g, err);
+  if (rc) return rc;
+  const int n = g->n_channels, ns = g->n_samples;
+  if (n < 2) {
+    *err = "f-k migration needs at least 2 channels";
+    return PWBF_E_UNSUPPORTED;
+  }
+  s->log2nt = log2_exact(ns);
+  if (s->log2nt < 1 || ns > pwbf::kFkMaxSamples) {
+    *err = "f-k migration needs n_samples a power of two in 2.." +
+           std::to_string(pwbf::kFkMaxSamples) + " (n_samples = " + std::to_string(ns) + ")";
+    return PWBF_E_UNSUPPORTED;
+  }
+  s->nt = ns;
+  s->nx = 1;
+  while (s->nx < 2 * n) s->nx *= 2;
+  s->log2nx = log2_exact(s->nx);
+  if (s->nx > pwbf::kFkMaxNx) {
+    *err = "f-k migration: padded array length exceeds " + std::to_string(pwbf::kFkMaxNx);
+    return PWBF_E_UNSUPPORTED;
+  }
+  s->kbins = ns / 2 + 1;
+  // the spatial transform needs a uniform pitch
+  const double p = (g->elem_x[n - 1] - g->elem_x[0]) / (n - 1);
+  if (!(p > 0)) {
+    *err = "f-k migration needs elem_x increasing with a uniform pitch";
+    return PWBF_E_UNSUPPORTED;
+  }
+  for (int e = 0; e < n; ++e)
+    if (std::fabs(g->elem_x[e] - (g->elem_x[0] + e * p)) > 1e-6 * p) {
+      *err = "f-k migration needs a uniform pitch (elem_x[" + std::to_string(e) + "] is off)";
+      return PWBF_E_UNSUPPORTED;
+    }
+  s->pitch = p;
+  return PWBF_OK;
+}
+
+size_t round256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// workspace: [max word | S | P | M | envelope scratch], S and P [A][Nt/2 + 1][Nx]
+// and M [A][Nx][Nt] complex float32 for the A angles of the call
+struct FkLayout {
+  size_t S, P, M, env, total;
+};
+
+FkLayout fk_layout(const pwbf_geometry *g, const FkShape &s, const pwbf_outputs *o, int n_ang) {
+  FkLayout L;
+  const size_t npix = (size_t)g->nx * g->nz;
+  L.S = 256;
+  L.P = L.S + round256((size_t)n_ang * s.kbins * s.nx * 8);
+  L.M = L.P + round256((size_t)n_ang * s.kbins * s.nx * 8);
+  L.env = L.M + round256((size_t)n_ang * s.nx * s.nt * 8);
+  L.total = L.env + ((o && o->logimg && !o->env) ? round256(npix * 4) : 0);
+  return L;
+}
+
+int check_outputs(const pwbf_geometry *g, const pwbf_outputs *o, std::string *err) {
+  if (!o) {
+    *err = "outputs is NULL";
+    return PWBF_E_INVALID;
+  }
+  if (!o->rf) {
+    *err = "outputs->rf is NULL";
+    return PWBF_E_INVALID;
+  }
+  for (const float *p : {o->rf, o->filtered, o->env, o->logimg, o->imag})
+    if (p && (uintptr_t)p % 4) {
+      *err = "output plane not 4-byte aligned";
+      return PWBF_E_INVALID;
+    }
+  if (o->filtered || g->bandpass) {
+    *err = "band-pass does not apply to the f-k image (its magnitude is the envelope)";
+    return PWBF_E_INVALID;
+  }
+  return PWBF_OK;
+}
+
+void split(double v, float *hi, float *lo) { pwbf::split_double(v, hi, lo); }
+
+}  // namespace
+
+extern "C" {
+
+size_t pwbf_fk_workspace_bytes(const pwbf_geometry *g, int32_t angle, const pwbf_outputs *out) {
+  pwbf::api_clear_error();
+  std::string err;
+  FkShape s;
+  int rc = fk_shape(g, &s, &err);
+  if (rc) {
+    api_set_error(rc, err);
+    return 0;
+  }
+  if (angle < -1 || angle >= g->n_angles) {
+    api_set_error(PWBF_E_INVALID, "angle must be -1 (all) or in 0..n_angles-1");
+    return 0;
+  }
+  return fk_layout(g, s, out, angle < 0 ? g->n_angles : 1).total;
+}
+
+int pwbf_fk_migrate(const pwbf_geometry *g, const void *rf, int32_t rf_dtype, int32_t angle,
+                    const pwbf_outputs *out, void *workspace, size_t workspace_bytes,
+                    void *stream) {
+  pwbf::api_clear_error();
+  std::string err;
+  FkShape s;
+  int rc = fk_shape(g, &s, &err);
+  if (rc) return api_set_error(rc, err);
+  if (rf_dtype != pwbf::kI16 && rf_dtype != pwbf::kF16 && rf_dtype != pwbf::kF32)
+    return api_set_error(PWBF_E_INVALID, "rf_dtype must be PWBF_I16, PWBF_F16 or PWBF_F32");
+  const size_t esz = pwbf::dtype_bytes(rf_dtype);
+  if (!rf || (uintptr_t)rf % esz)
+    return api_set_error(PWBF_E_INVALID, "rf is NULL or not aligned to its element size");
+  if (angle < -1 || angle >= g->n_angles)
+    return api_set_error(PWBF_E_INVALID, "angle must be -1 (all) or in 0..n_angles-1");
+  rc = check_outputs(g, out, &err);
+  if (rc) return api_set_error(rc, err);
+  const int a0 = angle < 0 ? 0 : angle, n_ang = angle < 0 ? g->n_angles : 1;
+  const FkLayout L = fk_layout(g, s, out, n_ang);
+  if (!workspace || (uintptr_t)workspace % 256)
+    return api_set_error(PWBF_E_INVALID, "workspace is NULL or not 256-byte aligned");
+  if (workspace_bytes < L.total)
+    return api_set_error(PWBF_E_INVALID, "workspace " + std::to_string(workspace_bytes) +
+                                             " bytes < " + std::to_string(L.total) + " required");
+
+  char *ws = (char *)workspace;
+  const int n = g->n_channels;
+  const double fs = g->fs, c = g->c, nt = s.nt, p = s.pitch, xf = g->elem_x[0];
+  pwbf::FkPlan F = {};
+  F.rf = (const char *)rf + (size_t)a0 * n * s.nt * esz;
+  F.dtype = rf_dtype;
+  F.n_ang = n_ang;
+  F.n_ch = n;
+  F.log2nt = s.log2nt;
+  F.log2nx = s.log2nx;
+  F.nx_img = g->nx;
+  F.nz_img = g->nz;
+  F.S = (float2 *)(ws + L.S);
+  F.P = (float2 *)(ws + L.P);
+  F.M = (float2 *)(ws + L.M);
+  F.out_rf = out->rf;
+  F.out_imag = out->imag;
+  F.out_env = out->env ? out->env : (out->logimg ? (float *)(ws + L.env) : nullptr);
+  F.ws_max = out->logimg ? (uint32_t *)ws : nullptr;
+  for (int k = 0; k < n_ang; ++k) {
+    const int a = a0 + k;
+    const double th = g->angle_rad[a], sn = std::sin(th), cs = std::cos(th);
+    const double v = c / (std::sqrt(2.0) * cs * cs);
+    const double t0 = g->t0 ? g->t0[a] : 0.0;
+    // firing delay of element e on the uniform array: (xf + e p) sin th - min, over c
+    const double fmin = std::min(xf * sn, (xf + (n - 1) * p) * sn);
+    pwbf::FkAngleConst &A = F.ang[k];
+    split(((xf * sn - fmin) / c - t0) * fs / nt, &A.c0_hi, &A.c0_lo);
+    split(p * sn / c * fs / nt, &A.c1_hi, &A.c1_lo);
+    split(v * nt / (s.nx * p * fs), &A.alpha_hi, &A.alpha_lo);
+    // column: (x + z tan th - x_first) / p; row: sqrt2 z / cos th / (v / fs)
+    const double tn = std::tan(th), kz = std::sqrt(2.0) / cs / (v / fs);
+    split((g->x0 + g->z0 * tn - xf) / p, &A.ux0_hi, &A.ux0_lo);
+    split(g->dx / p, &A.uxi_hi, &A.uxi_lo);
+    split(g->dz * tn / p, &A.uxk_hi, &A.uxk_lo);
+    split(g->z0 * kz, &A.uz0_hi, &A.uz0_lo);
+    split(g->dz * kz, &A.uzk_hi, &A.uzk_lo);
+  }
+  hipError_t e = pwbf::launch_fk(F, (hipStream_t)stream);
+  const size_t npix = (size_t)g->nx * g->nz;
+  if (e == hipSuccess && out->logimg)
+    e = pwbf::launch_logc(F.out_env, out->logimg, F.ws_max, npix, (float)g->log_floor_db,
+                          (hipStream_t)stream);
+  if (e != hipSuccess)
+    return api_set_error(PWBF_E_DEVICE, std::string("f-k launch: ") + hipGetErrorString(e));
+  return PWBF_OK;
+}
+
+}  // extern "C"
