@@ -197,13 +197,14 @@ def other_modes(dev, torch, steps: int, warmup: int) -> dict:
     return res
 
 
-def fk_stage_bytes(gs, rf_bytes: int) -> float:
+def fk_stage_bytes(gs, rf_bytes: int, method: str = "stolt") -> float:
     """HBM bytes of one f-k call as staged (each stage reads its input and writes
     its output once; the image stage reads each angle's migrated image once and
-    writes three planes): the algorithmic traffic of the six-kernel path."""
+    writes three planes): the algorithmic traffic of the six-kernel path. The
+    array is padded to 2 N (Stolt) or 4 N (Lu)."""
     n_ang, n, nt = gs.n_angles, gs.n_channels, gs.n_samples
     nx = 1
-    while nx < 2 * n:
+    while nx < (4 if method == "lu" else 2) * n:
         nx *= 2
     kb = nt // 2 + 1
     spec_n = n_ang * kb * n * 8      # shifted temporal spectra (channel columns only)
@@ -218,10 +219,10 @@ def fk_stage_bytes(gs, rf_bytes: int) -> float:
 
 
 def fk_mode(dev, torch, steps: int, warmup: int) -> dict:
-    """Stolt f-k migration on the 11-angle compound workload (FP32 RF, 1024 x 1024
-    pixels): the whole call (six kernels over all angles at once, plus the log
-    image), timed with HIP events around each call; the path is HBM-bound, so the
-    roofline is the staged traffic per call over the call time."""
+    """Stolt's and Lu's f-k migrations on the 11-angle compound workload (FP32 RF,
+    1024 x 1024 pixels): the whole call (six kernels over all angles at once,
+    plus the log image), timed with HIP events around each call; the path is
+    HBM-bound, so the roofline is the staged traffic per call over the call time."""
     from paper_2311_00482_amd import GeometryArg, fk_migrate, fk_workspace_bytes
     from synth import config_c3, make_frame
 
@@ -230,22 +231,26 @@ def fk_mode(dev, torch, steps: int, warmup: int) -> dict:
     rf = torch.from_numpy(make_frame(gs, 1003, "c3", quantize=False)["f32"]).to(dev)
     want = ("rf", "imag", "env", "log")
     outs = {k: torch.empty((g.nx, g.nz), dtype=torch.float32, device=dev) for k in want}
-    ws = torch.empty(fk_workspace_bytes(g, want, -1), dtype=torch.uint8, device=dev)
-    n = max(20, steps // 3)
-    wall, lat, _ = time_steps(lambda: fk_migrate(g, rf, -1, want=want, out=outs, workspace=ws),
-                              n, max(5, warmup // 3), torch)
-    ms = float(np.mean(lat))
-    b = fk_stage_bytes(gs, rf.numel() * 4)
-    name = "fk_stolt_compound_11a_1024x1024"
-    res = {name: {"frames_per_s": n / wall, "p50_ms": float(np.percentile(lat, 50)),
-                  "p99_ms": float(np.percentile(lat, 99)), "call_ms": ms,
-                  "roofline": {"bound": "hbm", "achieved": b / (ms * 1e-3) / 1e9,
-                               "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-                               "frac": b / (ms * 1e-3) / HBM_PEAK, "bytes_per_call": b,
-                               "scope": "whole call (six kernels + log image)"},
-                  "workspace_bytes": int(ws.numel()), "rf_storage": "f32"}}
-    print(f"[bench] {name}: {ms:.3f} ms per call, frac {res[name]['roofline']['frac']:.2f}",
-          file=sys.stderr, flush=True)
+    res = {}
+    for method in ("stolt", "lu"):
+        ws = torch.empty(fk_workspace_bytes(g, want, -1, method), dtype=torch.uint8, device=dev)
+        n = max(20, steps // 3)
+        wall, lat, _ = time_steps(lambda: fk_migrate(g, rf, -1, want=want, out=outs,
+                                                     workspace=ws, method=method),
+                                  n, max(5, warmup // 3), torch)
+        ms = float(np.mean(lat))
+        b = fk_stage_bytes(gs, rf.numel() * 4, method)
+        name = f"fk_{method}_compound_11a_1024x1024"
+        res[name] = {"frames_per_s": n / wall, "p50_ms": float(np.percentile(lat, 50)),
+                     "p99_ms": float(np.percentile(lat, 99)), "call_ms": ms,
+                     "roofline": {"bound": "hbm", "achieved": b / (ms * 1e-3) / 1e9,
+                                  "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                                  "frac": b / (ms * 1e-3) / HBM_PEAK, "bytes_per_call": b,
+                                  "scope": "whole call (six kernels + log image)"},
+                     "workspace_bytes": int(ws.numel()), "rf_storage": "f32"}
+        print(f"[bench] {name}: {ms:.3f} ms per call, "
+              f"frac {res[name]['roofline']['frac']:.2f}", file=sys.stderr, flush=True)
+        del ws
     return res
 
 
@@ -459,7 +464,7 @@ def main():
     ap.add_argument("--no-modes", action="store_true",
                     help="skip the DMAS and pDAS measurements")
     ap.add_argument("--profile-mode", default="das",
-                    choices=("das", "pdas", "dmas", "iqdas", "bbdmas", "fk"),
+                    choices=("das", "pdas", "dmas", "iqdas", "bbdmas", "fk", "fklu"),
                     help="with --profile-only: the beamformer of the timed loop (dmas and "
                          "pdas run on the 128-channel 512 x 512 DMAS workload, pdas also "
                          "takes the compound workload with --profile-compound)")
@@ -515,15 +520,16 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    if args.profile_only and args.profile_mode == "fk":
+    if args.profile_only and args.profile_mode in ("fk", "fklu"):
         from paper_2311_00482_amd import fk_migrate, fk_workspace_bytes
+        meth = "lu" if args.profile_mode == "fklu" else "stolt"
         wantk = ("rf", "imag", "env", "log")
         outk = {k: torch.empty((g.nx, g.nz), dtype=torch.float32, device=dev) for k in wantk}
-        wsk = torch.empty(fk_workspace_bytes(g, wantk, -1), dtype=torch.uint8, device=dev)
+        wsk = torch.empty(fk_workspace_bytes(g, wantk, -1, meth), dtype=torch.uint8, device=dev)
         wall, _, _ = time_steps(lambda: fk_migrate(g, rf32, -1, want=wantk, out=outk,
-                                                   workspace=wsk),
+                                                   workspace=wsk, method=meth),
                                 args.steps, args.warmup, torch)
-        print(json.dumps({"profile_only": True, "mode": "fk",
+        print(json.dumps({"profile_only": True, "mode": args.profile_mode,
                           "ms_per_step": wall / args.steps * 1e3}))
         return
     if args.profile_only and args.profile_mode in ("iqdas", "bbdmas"):

@@ -248,44 +248,56 @@ PWBF_API int pwbf_resolution_metrics(const pwbf_geometry *g, const float *env,
                                      const pwbf_disc *targets, int32_t n, pwbf_resolution *out,
                                      void *stream);
 
-/* Stolt f-k migration of steered plane waves (listed among the beamformers of
- * Section II-B; the paper gives no formula, so this is the reading the library
- * implements). Per angle th, with Nt = n_samples, Nx = the power of two >= 2 n_channels
- * and p the (uniform) element pitch:
+/* f-k migrations of steered plane waves: Stolt's (reflector model) and Lu's
+ * (scattering model), both listed among the beamformers of Section II-B without
+ * formulas, so what follows is the reading the library implements. Per angle th,
+ * with Nt = n_samples, p the (uniform) element pitch, k = f / c and all
+ * wavenumbers in cycles per metre:
  *  1. temporal spectrum of every trace (e^{-2 pi i f t}), bins f_k = k fs / Nt for
- *     0 <= k <= Nt / 2, times exp(2 pi i f_k (tau_e - t0[a])) where tau_e =
- *     (x_e sin th - min_k x_k sin th) / c is the element's firing delay;
- *  2. spectrum along the array zero-padded to Nx (kx_m = m / (Nx p), signed);
- *  3. Stolt mapping with v = c / (sqrt2 cos^2 th): the image spectrum at
- *     (kx, kz_j = j fs / (Nt v)) is the data spectrum at f = v sqrt(kx^2 + kz^2),
- *     linearly interpolated between bins of the one-sided spectrum extended by
- *     zeros past bin Nt / 2 (continuous in f), times kz / sqrt(kx^2 + kz^2)
- *     (0 at the origin);
+ *     0 <= k <= Nt / 2, times exp(2 pi i f_k (tau - t0[a])); Stolt: tau = tau_e,
+ *     the element's firing delay (x_e sin th - min_k x_k sin th) / c; Lu: tau =
+ *     tau_0, the moment the wave crosses the first element, for every trace;
+ *  2. spectrum along the array zero-padded to Nx, the power of two >= 2 N
+ *     (Stolt) or >= 4 N (Lu, whose remap reads it at fractional bins);
+ *     kx_m = m / (Nx p), signed;
+ *  3. remap onto the image spectrum, the one-sided data spectrum extended by zeros
+ *     past bin Nt / 2 and read by linear interpolation:
+ *     Stolt: v = c / (sqrt2 cos^2 th); the image spectrum at (kx, kz_j =
+ *     j fs / (Nt v)) is the data at f = v sqrt(kx^2 + kz^2), times
+ *     kz / sqrt(kx^2 + kz^2) (0 at the origin);
+ *     Lu: the image spectrum at (kx', kz'_j = 2 j fs / (Nt c)) is the data at
+ *     k = (kx'^2 + kz'^2) / (2 (kx' sin th + kz' cos th)), kx = kx' - k sin th
+ *     (bilinear, periodic in the spatial bin), times kz_r / (kx' sin th +
+ *     kz' cos th) with kz_r = kz' - k cos th; zero where kz_r < 0 or the
+ *     denominator is <= 0;
  *  4. inverse transforms along kx (Nx) and along kz with the one-sided spectrum
  *     zero-filled to Nt, scaled by 1 / (Nx Nt): the complex migrated image on
- *     x1 = elem_x[0] + e' p, z1 = l v / fs;
- *  5. output pixel (x, z) takes that image at (x + z tan th, sqrt2 z / cos th) by
- *     bilinear interpolation (zero outside); angles add (complex).
- * v and the map in step 5 put the migrated point of a scatterer where the
- * plane-wave travel-time curve has its apex, with matching curvature.
+ *     x1 = elem_x[0] + e' p and z1 = l v / fs (Stolt) or l c / (2 fs) (Lu);
+ *  5. output pixel (x, z) takes that image bilinearly (zero outside) at
+ *     (x + z tan th, sqrt2 z / cos th) (Stolt: v and this map put the migrated
+ *     point where the plane-wave travel-time curve has its apex, with matching
+ *     curvature) or at (x, z) (Lu); angles add (complex).
  *  rf        device RF[n_angles][n_channels][n_samples] (int16, FP16 or FP32)
+ *  method    PWBF_FK_STOLT or PWBF_FK_LU
  *  angle     0..n_angles-1, or -1 for the sum over all angles
  *  out       rf = real part, imag = imaginary part, env = magnitude (the image),
  *            logimg from env; filtered must be NULL and bandpass 0
- *  workspace device, 256-byte aligned, >= pwbf_fk_workspace_bytes(g, angle, out)
- *            bytes: the spectra and migrated images of every angle of the call
- *            (about 16 (Nt/2 + 1) Nx + 8 Nx Nt bytes per angle; 17 MB per angle at
- *            128 channels x 4096 samples)
+ *  workspace device, 256-byte aligned, >= pwbf_fk_workspace_bytes(g, method,
+ *            angle, out) bytes: the spectra and migrated images of every angle
+ *            of the call (16 (Nt/2 + 1) Nx + 8 Nx Nt bytes per angle: 17 MB
+ *            (Stolt) or 34 MB (Lu) per angle at 128 channels x 4096 samples)
  * Needs n_channels >= 2 with a uniform pitch (within 1e-6 p; the element
  * positions used are elem_x[0] + e p), n_samples a power of two in 2..4096
  * (PWBF_E_UNSUPPORTED otherwise). apod and f_number are unused. Work is enqueued
  * on stream. pwbf_fk_workspace_bytes returns 0 (and sets the last error) when the
  * call is not supported. */
-PWBF_API size_t pwbf_fk_workspace_bytes(const pwbf_geometry *g, int32_t angle,
+#define PWBF_FK_STOLT 0
+#define PWBF_FK_LU 1
+PWBF_API size_t pwbf_fk_workspace_bytes(const pwbf_geometry *g, int32_t method, int32_t angle,
                                         const pwbf_outputs *out);
 PWBF_API int pwbf_fk_migrate(const pwbf_geometry *g, const void *rf, int32_t rf_dtype,
-                             int32_t angle, const pwbf_outputs *out, void *workspace,
-                             size_t workspace_bytes, void *stream);
+                             int32_t method, int32_t angle, const pwbf_outputs *out,
+                             void *workspace, size_t workspace_bytes, void *stream);
 
 /* Coherent compounding: the unweighted sum over all n_angles of the per-angle
  * DAS (mode PWBF_DAS), DMAS (PWBF_DMAS), pDAS (PWBF_PDAS) images, or of the

@@ -14,6 +14,7 @@ LIB_PATH = os.path.join(HERE, "libpwbf.so")
 
 ABI_VERSION = 3
 OK, E_INVALID, E_UNSUPPORTED, E_NOMEM, E_DEVICE, E_BUSY = 0, -1, -2, -3, -4, -5
+FK_STOLT, FK_LU = 0, 1
 I16, F16, F32, C32 = 0, 1, 2, 3
 DAS, DMAS, PDAS, IQDAS, BBDMAS = 0, 1, 2, 3, 4
 APOD_HANN, APOD_BOXCAR, APOD_NONE = 0, 1, 2
@@ -176,9 +177,9 @@ def lib():
     L.pwbf_iq_demodulate.restype = ctypes.c_int
     L.pwbf_iq_demodulate.argtypes = [G, vp, i32, vp, vp]
     L.pwbf_fk_workspace_bytes.restype = sz
-    L.pwbf_fk_workspace_bytes.argtypes = [G, i32, O]
+    L.pwbf_fk_workspace_bytes.argtypes = [G, i32, i32, O]
     L.pwbf_fk_migrate.restype = ctypes.c_int
-    L.pwbf_fk_migrate.argtypes = [G, vp, i32, i32, O, vp, sz, vp]
+    L.pwbf_fk_migrate.argtypes = [G, vp, i32, i32, i32, O, vp, sz, vp]
     for name in ("pwbf_beamform_iqdas", "pwbf_beamform_bbdmas"):
         f = getattr(L, name)
         f.restype = ctypes.c_int

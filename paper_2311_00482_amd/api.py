@@ -204,13 +204,17 @@ def iq_demodulate(g, rf, out=None, stream=None):
     return out
 
 
-def fk_workspace_bytes(g, want: Iterable[str] = ("rf",), angle: int = -1) -> int:
+_FK_METHODS = {"stolt": _abi.FK_STOLT, "lu": _abi.FK_LU}
+
+
+def fk_workspace_bytes(g, want: Iterable[str] = ("rf",), angle: int = -1,
+                       method: str = "stolt") -> int:
     """pwbf_fk_workspace_bytes: device workspace of an f-k migration call."""
     ga = _as_geom(g)
     want = set(want)
     o = _abi.Outputs(1, None, 1 if "env" in want else None, 1 if "log" in want else None,
                      1 if "imag" in want else None)
-    n = _abi.lib().pwbf_fk_workspace_bytes(ga.ref, angle, ctypes.byref(o))
+    n = _abi.lib().pwbf_fk_workspace_bytes(ga.ref, _FK_METHODS[method], angle, ctypes.byref(o))
     if n == 0:
         raise _abi.PwbfError(_abi.E_UNSUPPORTED, _abi.lib().pwbf_last_error().decode())
     return int(n)
@@ -218,10 +222,10 @@ def fk_workspace_bytes(g, want: Iterable[str] = ("rf",), angle: int = -1) -> int
 
 def fk_migrate(g, rf, angle: int = -1, want: Iterable[str] = ("rf", "imag", "env"),
                out: Optional[Dict] = None, workspace=None, stream=None,
-               log_floor_db: float = -70.0) -> Dict:
-    """pwbf_fk_migrate: Stolt f-k migration of RF [A, N, Ns] (int16/float16/float32),
-    one angle or (angle -1) the complex sum over all angles. Planes "rf" (real
-    part), "imag", "env" (magnitude) and "log"."""
+               log_floor_db: float = -70.0, method: str = "stolt") -> Dict:
+    """pwbf_fk_migrate: Stolt's ("stolt") or Lu's ("lu") f-k migration of RF
+    [A, N, Ns] (int16/float16/float32), one angle or (angle -1) the complex sum
+    over all angles. Planes "rf" (real part), "imag", "env" (magnitude), "log"."""
     import torch
     ga = _as_geom(g, False, log_floor_db)
     if not rf.is_cuda or not rf.is_contiguous() or tuple(rf.shape) != ga.shape_rf:
@@ -236,14 +240,15 @@ def fk_migrate(g, rf, angle: int = -1, want: Iterable[str] = ("rf", "imag", "env
             out[k] = torch.empty((ga.nx, ga.nz), dtype=torch.float32, device=rf.device)
     o = _abi.Outputs(_ptr(out.get("rf")), None, _ptr(out.get("env")), _ptr(out.get("log")),
                      _ptr(out.get("imag")))
-    need = _abi.lib().pwbf_fk_workspace_bytes(ga.ref, angle, ctypes.byref(o))
+    need = _abi.lib().pwbf_fk_workspace_bytes(ga.ref, _FK_METHODS[method], angle,
+                                              ctypes.byref(o))
     if need == 0:
         raise _abi.PwbfError(_abi.E_UNSUPPORTED, _abi.lib().pwbf_last_error().decode())
     if workspace is None:
         workspace = torch.empty(need, dtype=torch.uint8, device=rf.device)
     ws_bytes = workspace.numel() * workspace.element_size()
-    _abi.check(_abi.lib().pwbf_fk_migrate(ga.ref, _ptr(rf), _rf_code(rf), angle,
-                                          ctypes.byref(o), _ptr(workspace), ws_bytes,
+    _abi.check(_abi.lib().pwbf_fk_migrate(ga.ref, _ptr(rf), _rf_code(rf), _FK_METHODS[method],
+                                          angle, ctypes.byref(o), _ptr(workspace), ws_bytes,
                                           _stream_ptr(stream, rf.device)))
     return out
 

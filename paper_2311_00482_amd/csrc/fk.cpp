@@ -1,12 +1,18 @@
-// Host side of the Stolt f-k migration (Section II-B): validation, workspace
-// layout and the per-angle constants, taken in float64 and split once into
-// float-float pairs.
+// Host side of the f-k migrations (Section II-B): validation, workspace layout
+// and the per-angle constants, taken in float64 and split once into float-float
+// pairs.
 //
-// Per steering angle th the exploding-reflector velocity is v = c / (sqrt2 cos^2 th)
-// and an output pixel (x0, z0) reads the migrated image at
-// (x0 + z0 tan th, sqrt2 z0 / cos th): the exploding-reflector hyperbola of that
-// velocity then has the apex position, apex time and apex curvature of the
+// Stolt's: per steering angle th the exploding-reflector velocity is
+// v = c / (sqrt2 cos^2 th) and an output pixel (x0, z0) reads the migrated image
+// at (x0 + z0 tan th, sqrt2 z0 / cos th): the exploding-reflector hyperbola of
+// that velocity then has the apex position, apex time and apex curvature of the
 // plane-wave travel time of a scatterer at (x0, z0).
+//
+// Lu's: the exact plane-wave relation between the data spectrum and the image
+// spectrum; the time origin is the moment the transmitted wave crosses the first
+// element, the migrated image lies on true coordinates (x1 = x0, z1 = z0 on the
+// grid x_first + e p, l c / (2 fs)), and the array is padded to 4 N because the
+// remap reads the spatial spectrum at fractional bins.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -37,9 +43,13 @@ struct FkShape {
   double pitch;
 };
 
-int fk_shape(const pwbf_geometry *g, FkShape *s, std::string *err) {
+int fk_shape(const pwbf_geometry *g, int method, FkShape *s, std::string *err) {
   int rc = pwbf::validate_geometry(g, err);
   if (rc) return rc;
+  if (method != pwbf::kFkStolt && method != pwbf::kFkLu) {
+    *err = "method must be PWBF_FK_STOLT or PWBF_FK_LU";
+    return PWBF_E_INVALID;
+  }
   const int n = g->n_channels, ns = g->n_samples;
   if (n < 2) {
     *err = "f-k migration needs at least 2 channels";
@@ -53,7 +63,7 @@ int fk_shape(const pwbf_geometry *g, FkShape *s, std::string *err) {
   }
   s->nt = ns;
   s->nx = 1;
-  while (s->nx < 2 * n) s->nx *= 2;
+  while (s->nx < (method == pwbf::kFkLu ? 4 : 2) * n) s->nx *= 2;
   s->log2nx = log2_exact(s->nx);
   if (s->nx > pwbf::kFkMaxNx) {
     *err = "f-k migration: padded array length exceeds " + std::to_string(pwbf::kFkMaxNx);
@@ -121,11 +131,12 @@ void split(double v, float *hi, float *lo) { pwbf::split_double(v, hi, lo); }
 
 extern "C" {
 
-size_t pwbf_fk_workspace_bytes(const pwbf_geometry *g, int32_t angle, const pwbf_outputs *out) {
+size_t pwbf_fk_workspace_bytes(const pwbf_geometry *g, int32_t method, int32_t angle,
+                               const pwbf_outputs *out) {
   pwbf::api_clear_error();
   std::string err;
   FkShape s;
-  int rc = fk_shape(g, &s, &err);
+  int rc = fk_shape(g, method, &s, &err);
   if (rc) {
     api_set_error(rc, err);
     return 0;
@@ -137,13 +148,13 @@ size_t pwbf_fk_workspace_bytes(const pwbf_geometry *g, int32_t angle, const pwbf
   return fk_layout(g, s, out, angle < 0 ? g->n_angles : 1).total;
 }
 
-int pwbf_fk_migrate(const pwbf_geometry *g, const void *rf, int32_t rf_dtype, int32_t angle,
-                    const pwbf_outputs *out, void *workspace, size_t workspace_bytes,
-                    void *stream) {
+int pwbf_fk_migrate(const pwbf_geometry *g, const void *rf, int32_t rf_dtype, int32_t method,
+                    int32_t angle, const pwbf_outputs *out, void *workspace,
+                    size_t workspace_bytes, void *stream) {
   pwbf::api_clear_error();
   std::string err;
   FkShape s;
-  int rc = fk_shape(g, &s, &err);
+  int rc = fk_shape(g, method, &s, &err);
   if (rc) return api_set_error(rc, err);
   if (rf_dtype != pwbf::kI16 && rf_dtype != pwbf::kF16 && rf_dtype != pwbf::kF32)
     return api_set_error(PWBF_E_INVALID, "rf_dtype must be PWBF_I16, PWBF_F16 or PWBF_F32");
@@ -168,6 +179,7 @@ int pwbf_fk_migrate(const pwbf_geometry *g, const void *rf, int32_t rf_dtype, in
   pwbf::FkPlan F = {};
   F.rf = (const char *)rf + (size_t)a0 * n * s.nt * esz;
   F.dtype = rf_dtype;
+  F.method = method;
   F.n_ang = n_ang;
   F.n_ch = n;
   F.log2nt = s.log2nt;
@@ -184,11 +196,29 @@ int pwbf_fk_migrate(const pwbf_geometry *g, const void *rf, int32_t rf_dtype, in
   for (int k = 0; k < n_ang; ++k) {
     const int a = a0 + k;
     const double th = g->angle_rad[a], sn = std::sin(th), cs = std::cos(th);
-    const double v = c / (std::sqrt(2.0) * cs * cs);
     const double t0 = g->t0 ? g->t0[a] : 0.0;
     // firing delay of element e on the uniform array: (xf + e p) sin th - min, over c
     const double fmin = std::min(xf * sn, (xf + (n - 1) * p) * sn);
     pwbf::FkAngleConst &A = F.ang[k];
+    if (method == pwbf::kFkLu) {
+      // every trace shifted to the moment the wave crosses the first element
+      split(((xf * sn - fmin) / c - t0) * fs / nt, &A.c0_hi, &A.c0_lo);
+      split(0.0, &A.c1_hi, &A.c1_lo);
+      const double beta = c * nt / (2.0 * fs * s.nx * p);  // c / (2 df Nx p)
+      split(beta, &A.beta_hi, &A.beta_lo);
+      split(sn, &A.sn_hi, &A.sn_lo);
+      split(cs, &A.cs_hi, &A.cs_lo);
+      split(sn / (2.0 * beta), &A.sb_hi, &A.sb_lo);
+      // true coordinates: column (x - x_first) / p, row z / (c / (2 fs))
+      const double kz = 2.0 * fs / c;
+      split((g->x0 - xf) / p, &A.ux0_hi, &A.ux0_lo);
+      split(g->dx / p, &A.uxi_hi, &A.uxi_lo);
+      split(0.0, &A.uxk_hi, &A.uxk_lo);
+      split(g->z0 * kz, &A.uz0_hi, &A.uz0_lo);
+      split(g->dz * kz, &A.uzk_hi, &A.uzk_lo);
+      continue;
+    }
+    const double v = c / (std::sqrt(2.0) * cs * cs);
     split(((xf * sn - fmin) / c - t0) * fs / nt, &A.c0_hi, &A.c0_lo);
     split(p * sn / c * fs / nt, &A.c1_hi, &A.c1_lo);
     split(v * nt / (s.nx * p * fs), &A.alpha_hi, &A.alpha_lo);

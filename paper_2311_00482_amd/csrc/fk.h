@@ -1,5 +1,5 @@
-// Stolt f-k migration: launch parameters shared by the host code and the
-// kernels (passed by value).
+// f-k migrations (Stolt's and Lu's): launch parameters shared by the host code
+// and the kernels (passed by value).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -9,24 +9,30 @@
 namespace pwbf {
 
 constexpr int kFkMaxSamples = 4096;  // one LDS FFT along time per block
-constexpr int kFkMaxNx = 512;        // zero-padded array length (>= 2 channels)
+constexpr int kFkMaxNx = 1024;       // zero-padded array length (2 or 4 x channels)
+
+enum FkMethod { kFkStolt = 0, kFkLu = 1 };
 
 // Per-angle constants, float-float (hi, lo) pairs.
 //  c0, c1  shift of the temporal spectrum of channel e: bin k is multiplied by
 //          exp(2 pi i k (c0 + e c1)), i.e. (firing delay - t0) fs / Nt
-//  alpha   Stolt source bin per signed kx index: v Nt / (Nx p fs)
+//  alpha   Stolt: source bin per signed kx index, v Nt / (Nx p fs)
+//  beta    Lu: kx' step over kz' step, c / (2 df Nx p)
+//  sn, cs  Lu: sin and cos of the angle
+//  sb      Lu: sin / (2 beta), the kx shift per frequency bin in spatial bins
 //  ux*     column of the migrated image read by pixel (ix, iz): ux0 + ix uxi + iz uxk
 //  uz*     its row: uz0 + iz uzk
 struct FkAngleConst {
   float c0_hi, c0_lo, c1_hi, c1_lo;
   float alpha_hi, alpha_lo;
+  float beta_hi, beta_lo, sn_hi, sn_lo, cs_hi, cs_lo, sb_hi, sb_lo;
   float ux0_hi, ux0_lo, uxi_hi, uxi_lo, uxk_hi, uxk_lo;
   float uz0_hi, uz0_lo, uzk_hi, uzk_lo;
 };
 
 struct FkPlan {
   const void *rf;  // records [n_ang][n_ch][Nt] of the first angle handled
-  int dtype;
+  int dtype, method;
   int n_ang, n_ch, log2nt, log2nx;
   int nx_img, nz_img;
   float2 *S;  // [n_ang][Nt/2 + 1][Nx]: shifted temporal spectra, then the remapped spectrum
@@ -36,6 +42,9 @@ struct FkPlan {
   uint32_t *ws_max;                    // maximum magnitude (bits of a float), or NULL
   FkAngleConst ang[kMaxAngles];
 };
+
+// passed by value to every kernel: keep it inside the 4 KB kernel-argument budget
+static_assert(sizeof(FkPlan) <= 4000, "FkPlan too large for a kernel argument");
 
 hipError_t launch_fk(const FkPlan &F, hipStream_t s);
 hipError_t launch_logc(const float *env, float *logimg, const uint32_t *ws_max, size_t n,

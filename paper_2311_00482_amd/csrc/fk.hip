@@ -1,6 +1,7 @@
-// Stolt f-k migration for steered plane waves. Every stage runs over all angles
-// of the call in one launch (blockIdx.y or the flat index selects the angle), so
-// even a single frame gives the chip thousands of blocks:
+// f-k migrations (Stolt's and Lu's) for steered plane waves. Every stage runs
+// over all angles of the call in one launch (blockIdx.y or the flat index
+// selects the angle), so even a single frame gives the chip thousands of blocks.
+// The two methods share every stage but the remap:
 //
 //  k_fk_time      block per (channel, angle): FFT of the trace (Nt samples); the
 //                 positive bins times exp(2 pi i k c_e) (the trace advanced by its
@@ -9,6 +10,12 @@
 //  k_fk_stolt     thread per (kz_j, kx_m, angle): the spectrum at the bin
 //                 u = sqrt((alpha m')^2 + j^2) (m' the signed index), linearly
 //                 interpolated (zeros past the last bin), times the Jacobian j / u
+//  k_fk_lu        (Lu's remap instead) thread per (kz'_j, kx'_m, angle): the data
+//                 spectrum at frequency bin u = (beta^2 m'^2 + j^2) /
+//                 (beta m' sin + j cos) and spatial bin m' - u sin / (2 beta),
+//                 bilinearly (periodic in the spatial bin), times the Jacobian
+//                 (j - u cos / 2) / (beta m' sin + j cos); zero where the
+//                 receive wavenumber j - u cos / 2 is negative
 //  k_fk_ispace    block per (kz_j, angle): inverse FFT along kx
 //  k_fk_itime     block per (x1 column, angle): inverse FFT along kz with the
 //                 one-sided spectrum zero-filled to Nt, scaled by 1/(Nx Nt)
@@ -65,6 +72,14 @@ __device__ __forceinline__ int split_index(ff u, float *frac) {
   }
   *frac = f;
   return i;
+}
+
+// a / b in float-float (one correction step)
+__device__ __forceinline__ ff ff_div(ff a, ff b) {
+#pragma clang fp contract(off)
+  const float q1 = a.hi / b.hi;
+  const ff r = dev::ff_add(a, dev::ff_neg(dev::ff_mul({q1, 0.f}, b)));
+  return dev::two_sum(q1, r.hi / b.hi);
 }
 
 __device__ __forceinline__ size_t spec_elems(const FkPlan &F) {
@@ -129,6 +144,51 @@ __global__ void __launch_bounds__(256) k_fk_stolt(FkPlan F) {
         const float2 hi = i0 + 1 <= kbins - 1 ? P[(size_t)(i0 + 1) * nx] : make_float2(0.f, 0.f);
         const float jac = (float)j / dev::ff_f(u);
         val = make_float2(((1.f - w) * lo.x + w * hi.x) * jac, ((1.f - w) * lo.y + w * hi.y) * jac);
+      }
+    }
+    F.S[t] = val;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_fk_lu(FkPlan F) {
+  const int nx = 1 << F.log2nx, kbins = (1 << F.log2nt) / 2 + 1;
+  const size_t per = spec_elems(F), n = per * F.n_ang;
+  for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
+       t += (size_t)gridDim.x * blockDim.x) {
+    const int a = (int)(t / per);
+    const size_t r = t - (size_t)a * per;
+    const int j = (int)(r >> F.log2nx), m = (int)(r & (nx - 1));
+    const int ms = m < nx / 2 ? m : m - nx;  // signed kx' index
+    const FkAngleConst &A = F.ang[a];
+    const ff bm = dev::ff_mul(ffi(ms), {A.beta_hi, A.beta_lo});
+    const ff den = dev::ff_add(dev::ff_mul(bm, {A.sn_hi, A.sn_lo}),
+                               dev::ff_mul(ffi(j), {A.cs_hi, A.cs_lo}));
+    float2 val = make_float2(0.f, 0.f);
+    if (den.hi > 0.f) {
+      const ff num = dev::ff_add(dev::ff_mul(bm, bm), dev::ff_mul(ffi(j), ffi(j)));
+      const ff u = ff_div(num, den);  // source frequency bin
+      // receive wavenumber in kz' steps: j - u cos / 2 (>= 0 on the wave's branch)
+      const ff kzr = dev::ff_add(ffi(j), dev::ff_neg(dev::ff_mul(u, {0.5f * A.cs_hi, 0.5f * A.cs_lo})));
+      if (kzr.hi >= 0.f && u.hi < (float)kbins) {
+        const ff mf = dev::ff_add(ffi(ms), dev::ff_neg(dev::ff_mul(u, {A.sb_hi, A.sb_lo})));
+        float wu, wm;
+        const int i0 = split_index(u, &wu);
+        const int m0 = split_index(mf, &wm);
+        if (i0 >= 0 && i0 <= kbins - 1) {
+          const float2 *P = F.P + (size_t)a * per;
+          const int ma = m0 & (nx - 1), mb = (m0 + 1) & (nx - 1);  // periodic in kx
+          const float2 p00 = P[(size_t)i0 * nx + ma], p01 = P[(size_t)i0 * nx + mb];
+          float2 p10 = make_float2(0.f, 0.f), p11 = p10;  // zeros past the last bin
+          if (i0 + 1 <= kbins - 1) {
+            p10 = P[(size_t)(i0 + 1) * nx + ma];
+            p11 = P[(size_t)(i0 + 1) * nx + mb];
+          }
+          const float w00 = (1.f - wm) * (1.f - wu), w01 = wm * (1.f - wu);
+          const float w10 = (1.f - wm) * wu, w11 = wm * wu;
+          const float jac = dev::ff_f(kzr) / dev::ff_f(den);
+          val = make_float2((w00 * p00.x + w01 * p01.x + w10 * p10.x + w11 * p11.x) * jac,
+                            (w00 * p00.y + w01 * p01.y + w10 * p10.y + w11 * p11.y) * jac);
+        }
       }
     }
     F.S[t] = val;
@@ -241,8 +301,11 @@ hipError_t launch_fk(const FkPlan &F, hipStream_t s) {
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(k_fk_space, dim3(kbins, F.n_ang), blk, lds_x, s, F);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_fk_stolt, dim3(grid_for((size_t)kbins * nx * F.n_ang)), dim3(256), 0, s,
-                     F);
+  if (F.method == kFkLu)
+    hipLaunchKernelGGL(k_fk_lu, dim3(grid_for((size_t)kbins * nx * F.n_ang)), dim3(256), 0, s, F);
+  else
+    hipLaunchKernelGGL(k_fk_stolt, dim3(grid_for((size_t)kbins * nx * F.n_ang)), dim3(256), 0, s,
+                       F);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   hipLaunchKernelGGL(k_fk_ispace, dim3(kbins, F.n_ang), blk, lds_x, s, F);
   if ((e = hipGetLastError()) != hipSuccess) return e;

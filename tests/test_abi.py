@@ -410,41 +410,53 @@ def test_fk_workspace_and_argument_errors():
     o = _abi.Outputs(FAKE, None, FAKE, None, FAKE)
     r256 = lambda b: (b + 255) // 256 * 256  # noqa: E731
     W = L.pwbf_fk_workspace_bytes
-    # per angle: S and P [2049][256], M [256][4096], complex float32
-    per = lambda a: 2 * r256(a * 2049 * 256 * 8) + r256(a * 256 * 4096 * 8)  # noqa: E731
-    need = 256 + per(11)
-    assert W(g.ref, -1, ctypes.byref(o)) == need
-    assert W(g.ref, 3, ctypes.byref(o)) == 256 + per(1)
-    assert W(g.ref, 11, ctypes.byref(o)) == 0 and W(g.ref, -2, ctypes.byref(o)) == 0
+    ST, LU = _abi.FK_STOLT, _abi.FK_LU
+
+    # per angle: S and P [2049][Nx], M [Nx][4096], complex float32; Nx = 256 / 512
+    def per(a, nx):
+        return 2 * r256(a * 2049 * nx * 8) + r256(a * nx * 4096 * 8)
+    need = 256 + per(11, 256)
+    assert W(g.ref, ST, -1, ctypes.byref(o)) == need
+    assert W(g.ref, ST, 3, ctypes.byref(o)) == 256 + per(1, 256)
+    assert W(g.ref, LU, -1, ctypes.byref(o)) == 256 + per(11, 512)
+    assert W(g.ref, ST, 11, ctypes.byref(o)) == 0 and W(g.ref, ST, -2, ctypes.byref(o)) == 0
+    assert W(g.ref, 2, -1, ctypes.byref(o)) == 0 and b"method" in L.pwbf_last_error()
     # a log image without an envelope plane needs the envelope in the workspace
     olog = _abi.Outputs(FAKE, None, None, FAKE)
-    assert W(g.ref, -1, ctypes.byref(olog)) == need + 1024 * 1024 * 4
+    assert W(g.ref, ST, -1, ctypes.byref(olog)) == need + 1024 * 1024 * 4
     # unsupported shapes: record length, one channel, non-uniform pitch
     for bad in (g3.replace(n_samples=600), g3.replace(n_samples=8192), g3.replace(n_channels=1)):
-        assert W(GeometryArg(bad).ref, -1, ctypes.byref(o)) == 0
-        assert L.pwbf_last_error()
+        for meth in (ST, LU):
+            assert W(GeometryArg(bad).ref, meth, -1, ctypes.byref(o)) == 0
+            assert L.pwbf_last_error()
     ga = GeometryArg(g3)
     ga.elem_x[5] += 0.01 * (ga.elem_x[1] - ga.elem_x[0])
-    assert W(ga.ref, -1, ctypes.byref(o)) == 0
+    assert W(ga.ref, LU, -1, ctypes.byref(o)) == 0
     assert b"pitch" in L.pwbf_last_error()
+    # Lu pads to 4 N: 256 channels need 1024 (supported)
+    g256 = GeometryArg(g3.replace(n_channels=256, n_samples=1024))
+    assert W(g256.ref, LU, 0, ctypes.byref(o)) == 256 + 2 * r256(513 * 1024 * 8) + r256(1024 * 1024 * 8)
     # every call below fails a host check before any HIP call (workspace is NULL
     # or too small, so none reaches the launches)
     oo = ctypes.byref(o)
     M = L.pwbf_fk_migrate
-    assert M(None, FAKE, 0, -1, oo, None, 0, None) == _abi.E_INVALID
-    assert M(ga.ref, FAKE, 0, -1, oo, FAKE, need, None) == _abi.E_UNSUPPORTED
-    assert M(g.ref, FAKE, _abi.C32, -1, oo, None, 0, None) == _abi.E_INVALID
-    assert M(g.ref, None, 0, -1, oo, None, 0, None) == _abi.E_INVALID
-    assert M(g.ref, FAKE + 1, 0, -1, oo, None, 0, None) == _abi.E_INVALID
-    assert M(g.ref, FAKE, 0, 11, oo, None, 0, None) == _abi.E_INVALID
-    assert M(g.ref, FAKE, 0, -2, oo, None, 0, None) == _abi.E_INVALID
-    assert M(g.ref, FAKE, 0, -1, None, None, 0, None) == _abi.E_INVALID
+    assert M(None, FAKE, 0, ST, -1, oo, None, 0, None) == _abi.E_INVALID
+    assert M(ga.ref, FAKE, 0, ST, -1, oo, FAKE, need, None) == _abi.E_UNSUPPORTED
+    assert M(g.ref, FAKE, 0, 7, -1, oo, FAKE, need, None) == _abi.E_INVALID
+    assert M(g.ref, FAKE, _abi.C32, ST, -1, oo, None, 0, None) == _abi.E_INVALID
+    assert M(g.ref, None, 0, ST, -1, oo, None, 0, None) == _abi.E_INVALID
+    assert M(g.ref, FAKE + 1, 0, LU, -1, oo, None, 0, None) == _abi.E_INVALID
+    assert M(g.ref, FAKE, 0, ST, 11, oo, None, 0, None) == _abi.E_INVALID
+    assert M(g.ref, FAKE, 0, ST, -2, oo, None, 0, None) == _abi.E_INVALID
+    assert M(g.ref, FAKE, 0, ST, -1, None, None, 0, None) == _abi.E_INVALID
     of = _abi.Outputs(FAKE, FAKE, None, None)
-    assert M(g.ref, FAKE, 0, -1, ctypes.byref(of), None, 0, None) == _abi.E_INVALID
+    assert M(g.ref, FAKE, 0, ST, -1, ctypes.byref(of), None, 0, None) == _abi.E_INVALID
     assert b"band-pass" in L.pwbf_last_error()
     gb = GeometryArg(g3, bandpass=True)
-    assert M(gb.ref, FAKE, 0, -1, oo, None, 0, None) == _abi.E_INVALID
-    assert M(g.ref, FAKE, 0, -1, oo, None, 0, None) == _abi.E_INVALID
-    assert M(g.ref, FAKE, 0, -1, oo, FAKE + 128, need, None) == _abi.E_INVALID
-    assert M(g.ref, FAKE, 0, -1, oo, FAKE, need - 1, None) == _abi.E_INVALID
+    assert M(gb.ref, FAKE, 0, LU, -1, oo, None, 0, None) == _abi.E_INVALID
+    assert M(g.ref, FAKE, 0, ST, -1, oo, None, 0, None) == _abi.E_INVALID
+    assert M(g.ref, FAKE, 0, ST, -1, oo, FAKE + 128, need, None) == _abi.E_INVALID
+    assert M(g.ref, FAKE, 0, ST, -1, oo, FAKE, need - 1, None) == _abi.E_INVALID
     assert b"required" in L.pwbf_last_error()
+    # the Stolt-sized workspace is too small for Lu
+    assert M(g.ref, FAKE, 0, LU, -1, oo, FAKE, need, None) == _abi.E_INVALID
