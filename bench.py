@@ -13,6 +13,7 @@ and ~19k speckle scatterers, Gaussian 2-cycle 5 MHz pulse, 30 dB SNR.
 from __future__ import annotations
 
 import argparse
+import gc
 import hashlib
 import json
 import math
@@ -112,7 +113,18 @@ def traffic_bytes():
 
 def time_steps(fn, steps, warmup, torch):
     """Warm up, then time exactly `steps` calls bracketed by synchronisation;
-    per-step latency from HIP events on the launching stream."""
+    per-step latency from HIP events on the launching stream. Python's garbage
+    collector is run before and paused during the warm-up and the timed loop,
+    so a collection cannot stall the host between launches."""
+    gc.collect()
+    gc.disable()
+    try:
+        return _time_steps(fn, steps, warmup, torch)
+    finally:
+        gc.enable()
+
+
+def _time_steps(fn, steps, warmup, torch):
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()

@@ -28,6 +28,9 @@ def lib():
     if _lib is None:
         if not os.path.exists(_LIB):
             build()
+        # worker threads sleep rather than spin between calls, so a caller timing
+        # other work right after a simulation does not share the CPUs with them
+        os.environ.setdefault("OMP_WAIT_POLICY", "PASSIVE")
         _lib = ctypes.CDLL(_LIB)
         _lib.sim_accumulate.restype = None
         _lib.sim_accumulate.argtypes = [
