@@ -46,6 +46,10 @@ KERNEL_SOURCES = ["paper_2311_00482_amd/csrc/beamform.hip",
                   "paper_2311_00482_amd/csrc/beamform_device.h",
                   "paper_2311_00482_amd/csrc/plan.h"]
 COUNTERS = os.path.join(ROOT, "profiles", "k_beamform_c3_compound_f32.counters.json")
+# workspace of the single-frame calls timed here (every call that asks for the log
+# image also asks for the envelope plane, so the workspace holds only the frame
+# maximum's slots); the library checks the size on every call
+WS_BYTES = 64 * 1024
 
 
 def aperture_pairs(g) -> int:
@@ -184,7 +188,7 @@ def other_modes(dev, torch, steps: int, warmup: int) -> dict:
         rf = torch.from_numpy(fr["i16"] if quant else fr["f32"]).to(dev)
         want = ("rf", "filtered", "env", "log") if bp else ("rf", "env", "log")
         outs = {k: torch.empty((g.nx, g.nz), dtype=torch.float32, device=dev) for k in want}
-        ws = torch.empty(4096, dtype=torch.uint8, device=dev)
+        ws = torch.empty(WS_BYTES, dtype=torch.uint8, device=dev)
         rf_only = {"rf": outs["rf"]}
         n = max(20, steps // 3)
         wall, lat, _ = time_steps(
@@ -209,25 +213,52 @@ def other_modes(dev, torch, steps: int, warmup: int) -> dict:
     return res
 
 
-def fk_stage_bytes(gs, rf_bytes: int, method: str = "stolt") -> float:
-    """HBM bytes of one f-k call as staged (each stage reads its input and writes
-    its output once; the image stage reads each angle's migrated image once and
-    writes three planes): the algorithmic traffic of the six-kernel path. The
-    array is padded to 2 N (Stolt) or 4 N (Lu)."""
-    n_ang, n, nt = gs.n_angles, gs.n_channels, gs.n_samples
+def fk_windows(gs, method: str):
+    """Per angle, the columns and rows of the migrated image that the pixel grid
+    reads (the library's window rule: the floor of the extreme tap positions, one
+    more for the upper tap, one more on each side, clipped to the image)."""
+    n, nt = gs.n_channels, gs.n_samples
     nx = 1
     while nx < (4 if method == "lu" else 2) * n:
         nx *= 2
-    kb = nt // 2 + 1
-    spec_n = n_ang * kb * n * 8      # shifted temporal spectra (channel columns only)
-    spec = n_ang * kb * nx * 8       # padded spectra
-    mig = n_ang * nx * nt * 8        # migrated images
-    return float(rf_bytes + spec_n        # time: RF in, S out
-                 + spec_n + spec          # space: S in, P out
-                 + 2 * spec               # Stolt: P in, S out
-                 + 2 * spec               # inverse along kx, in place
-                 + spec + mig             # inverse along kz: S in, M out
-                 + mig + 3 * gs.nx * gs.nz * 4)  # image: M in, planes out
+    p = (gs.elem_x[-1] - gs.elem_x[0]) / (n - 1)
+    xf = gs.elem_x[0]
+
+    def win(v0, di, ni, dk, nk, size):
+        vs = [v0, v0 + (ni - 1) * di, v0 + (nk - 1) * dk, v0 + (ni - 1) * di + (nk - 1) * dk]
+        a = max(0.0, math.floor(min(vs)) - 1.0)
+        b = min(size - 1.0, math.floor(max(vs)) + 2.0)
+        return int(b - a) + 1 if a <= b else 0
+
+    out = []
+    for th in gs.angles_rad:
+        if method == "lu":
+            kz = 2.0 * gs.fs / gs.c
+            nc = win((gs.x0 - xf) / p, gs.dx / p, gs.nx, 0.0, gs.nz, nx)
+        else:
+            v = gs.c / (math.sqrt(2.0) * math.cos(th) ** 2)
+            kz = math.sqrt(2.0) / math.cos(th) / (v / gs.fs)
+            tn = math.tan(th)
+            nc = win((gs.x0 + gs.z0 * tn - xf) / p, gs.dx / p, gs.nx, gs.dz * tn / p, gs.nz, nx)
+        nr = win(gs.z0 * kz, 0.0, gs.nx, gs.dz * kz, gs.nz, nt)
+        out.append((nc, nr) if nc and nr else (0, 0))
+    return nx, out
+
+
+def fk_stage_bytes(gs, rf_bytes: int, method: str = "stolt") -> float:
+    """HBM bytes of one f-k call as staged, each stage reading its input and
+    writing its output once: the RF; the temporal spectra T (written, read); the
+    2-D spectra P (written, read once by the remap); the remapped spectra U of
+    the window's columns (written, read); the window of the migrated images M
+    (written, read); the three output planes. The array is padded to 2 N
+    (Stolt) or 4 N (Lu)."""
+    nx, wins = fk_windows(gs, method)
+    kb = gs.n_samples // 2 + 1
+    t = gs.n_angles * gs.n_channels * kb * 8
+    pp = gs.n_angles * kb * nx * 8
+    u = sum(nc for nc, _ in wins) * kb * 8
+    m = sum(nc * nr for nc, nr in wins) * 8
+    return float(rf_bytes + 2 * t + 2 * pp + 2 * u + 2 * m + 3 * gs.nx * gs.nz * 4)
 
 
 def fk_mode(dev, torch, steps: int, warmup: int) -> dict:
@@ -291,7 +322,7 @@ def iq_modes(dev, torch, steps: int, warmup: int) -> dict:
                      "bytes_per_launch": float(bytes_moved)}}}
     want = ("rf", "imag", "env", "log")
     outs = {k: torch.empty((g.nx, g.nz), dtype=torch.float32, device=dev) for k in want}
-    ws = torch.empty(4096, dtype=torch.uint8, device=dev)
+    ws = torch.empty(WS_BYTES, dtype=torch.uint8, device=dev)
     rf_only = {"rf": outs["rf"], "imag": outs["imag"]}
     for mode in ("iqdas", "bbdmas"):
         def frame():
@@ -381,7 +412,7 @@ def systems(dev, torch, steps: int, warmup: int) -> dict:
         return {k: torch.empty((g.nx, g.nz), dtype=torch.float32, device=dev) for k in want}
 
     out32 = planes()
-    ws = torch.empty(4096, dtype=torch.uint8, device=dev)
+    ws = torch.empty(WS_BYTES, dtype=torch.uint8, device=dev)
     rf32 = i16.to(torch.float32).to(dev)
     wall32, lat32, _ = time_steps(
         lambda: beamform(g, rf32, "das", -1, want=want, out=out32, workspace=ws),
@@ -511,7 +542,7 @@ def main():
     rf16 = torch.from_numpy(fr["f16"]).to(dev)
     want = ("rf", "env", "log")
     outs = {k: torch.empty((g.nx, g.nz), dtype=torch.float32, device=dev) for k in want}
-    ws = torch.empty(4096, dtype=torch.uint8, device=dev)
+    ws = torch.empty(WS_BYTES, dtype=torch.uint8, device=dev)
 
     def step32():
         beamform(g, rf32, "das", -1, want=want, out=outs, workspace=ws)

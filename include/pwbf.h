@@ -287,8 +287,8 @@ PWBF_API int pwbf_resolution_metrics(const pwbf_geometry *g, const float *env,
  *            of the call (16 (Nt/2 + 1) Nx + 8 Nx Nt bytes per angle: 17 MB
  *            (Stolt) or 34 MB (Lu) per angle at 128 channels x 4096 samples)
  * Needs n_channels >= 2 with a uniform pitch (within 1e-6 p; the element
- * positions used are elem_x[0] + e p), n_samples a power of two in 2..4096
- * (PWBF_E_UNSUPPORTED otherwise). apod and f_number are unused. Work is enqueued
+ * positions used are elem_x[0] + e p), n_samples a power of two in 2..4096, and
+ * nx, nz <= 2^24 (PWBF_E_UNSUPPORTED otherwise). apod and f_number are unused. Work is enqueued
  * on stream. pwbf_fk_workspace_bytes returns 0 (and sets the last error) when the
  * call is not supported. */
 #define PWBF_FK_STOLT 0

@@ -30,7 +30,8 @@ constexpr int kBatchMaxAngles = 16;
 __global__ void k_batch_reset(int *counter, const PostPlan *__restrict__ post, int n_frames) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i == 0) *counter = 0;
-  if (i < n_frames && post[i].ws_max) *post[i].ws_max = 0u;
+  if (i < n_frames && post[i].ws_max)
+    for (int s = 0; s < kMaxSlots; ++s) dev::frame_max_clear(post[i].ws_max, s);
 }
 
 // The tile bodies the persistent kernel can run: exact angle counts 1, 5 and 11
@@ -92,7 +93,7 @@ __global__ void __launch_bounds__(256)
     k_batch_logc(const PostPlan *__restrict__ post, const int2 *__restrict__ cols) {
   const int2 c = cols[blockIdx.x];
   const PostPlan &Q = post[c.x];
-  const float m = __uint_as_float(*Q.ws_max);
+  const float m = dev::frame_max_read(Q.ws_max);
   const size_t base = (size_t)c.y * Q.nz;
   for (int k = threadIdx.x; k < Q.nz; k += blockDim.x)
     Q.logimg[base + k] = dev::log_db(Q.env[base + k], m, Q.floor_db);
@@ -122,7 +123,7 @@ hipError_t launch_batch(const FramePlan *plans, const PostPlan *post, const int2
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (n_post_cols > 0) {
-    const size_t plds = (size_t)max_nz * sizeof(float2) + (size_t)(max_nz / 2) * sizeof(float2);
+    const size_t plds = dev::post_lds_bytes(max_nz);
     hipLaunchKernelGGL(k_batch_postz, dim3(n_post_cols), dim3(dev::kPostThreads), plds, stream,
                        post, post_cols);
     e = hipGetLastError();

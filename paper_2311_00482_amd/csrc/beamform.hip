@@ -22,7 +22,7 @@ __global__ void __launch_bounds__(kWave * kMaxWavesPerBlock) k_beamform(const Fr
   const int b = blockIdx.x;
   // RF modes: clear the frame maximum the post-processing folds into (the IQ
   // modes fold it here, so their launch clears it beforehand)
-  if (!is_iq_mode(MODE) && P.ws_max && b == 0 && threadIdx.x == 0) *P.ws_max = 0u;
+  if (!is_iq_mode(MODE) && P.ws_max && b == 0) dev::frame_max_clear(P.ws_max, threadIdx.x);
   const int q = b / P.tiles_x;
   const int tz = P.tiles_z - 1 - q, tx = b - q * P.tiles_x;
   process_tile<AM, PRED, MODE, ONEGRP>(P, tz, tx, smem);
@@ -73,12 +73,12 @@ hipError_t launch_am_iq(const FramePlan &P, hipStream_t stream) {
   return hipGetLastError();
 }
 
-__global__ void k_clear_word(uint32_t *w) { *w = 0u; }
+__global__ void k_clear_max(uint32_t *slots) { dev::frame_max_clear(slots, threadIdx.x); }
 
 // The IQ modes: exact kernels for 1, 5 and 11 angles, predicated ones otherwise.
 hipError_t launch_iq(const FramePlan &P, hipStream_t stream) {
   if (P.ws_max) {
-    hipLaunchKernelGGL(k_clear_word, dim3(1), dim3(1), 0, stream, P.ws_max);
+    hipLaunchKernelGGL(k_clear_max, dim3(1), dim3(kMaxSlots), 0, stream, P.ws_max);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

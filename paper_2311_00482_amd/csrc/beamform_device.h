@@ -27,6 +27,7 @@
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
+#include "frame_max.h"
 #include "plan.h"
 
 namespace pwbf {
@@ -531,7 +532,7 @@ __device__ __forceinline__ void process_tile(const FramePlan &P, int tz, int tx,
       __syncthreads();
       if (tid == 0) {
         for (int w = 1; w < (int)(blockDim.x / kWave); ++w) m = fmaxf(m, s_wmax[w]);
-        atomicMax(P.ws_max, __float_as_uint(m));
+        frame_max_fold(P.ws_max, m);
       }
     }
     return;

@@ -21,6 +21,7 @@
 
 #include "../../include/pwbf.h"
 #include "fk.h"
+#include "frame_max.h"
 #include "plan_host.h"
 
 namespace pwbf {
@@ -70,6 +71,11 @@ int fk_shape(const pwbf_geometry *g, int method, FkShape *s, std::string *err) {
     return PWBF_E_UNSUPPORTED;
   }
   s->kbins = ns / 2 + 1;
+  // pixel indices enter the map as exact float32 integers
+  if (g->nx > (1 << 24) || g->nz > (1 << 24)) {
+    *err = "f-k migration needs nx and nz <= 2^24";
+    return PWBF_E_UNSUPPORTED;
+  }
   // the spatial transform needs a uniform pitch
   const double p = (g->elem_x[n - 1] - g->elem_x[0]) / (n - 1);
   if (!(p > 0)) {
@@ -87,18 +93,20 @@ int fk_shape(const pwbf_geometry *g, int method, FkShape *s, std::string *err) {
 
 size_t round256(size_t b) { return (b + 255) & ~(size_t)255; }
 
-// workspace: [max word | S | P | M | envelope scratch], S and P [A][Nt/2 + 1][Nx]
-// and M [A][Nx][Nt] complex float32 for the A angles of the call
+// workspace: [max slots | T | P | U | M | envelope scratch], complex float32 for
+// the A angles of the call: T [A][N][Nt/2 + 1], P [A][Nt/2 + 1][Nx],
+// U [A][Nx][Nt/2 + 1], M [A][Nx][Nt]
 struct FkLayout {
-  size_t S, P, M, env, total;
+  size_t T, P, U, M, env, total;
 };
 
 FkLayout fk_layout(const pwbf_geometry *g, const FkShape &s, const pwbf_outputs *o, int n_ang) {
   FkLayout L;
   const size_t npix = (size_t)g->nx * g->nz;
-  L.S = 256;
-  L.P = L.S + round256((size_t)n_ang * s.kbins * s.nx * 8);
-  L.M = L.P + round256((size_t)n_ang * s.kbins * s.nx * 8);
+  L.T = pwbf::kMaxSlotBytes;
+  L.P = L.T + round256((size_t)n_ang * g->n_channels * s.kbins * 8);
+  L.U = L.P + round256((size_t)n_ang * s.kbins * s.nx * 8);
+  L.M = L.U + round256((size_t)n_ang * s.nx * s.kbins * 8);
   L.env = L.M + round256((size_t)n_ang * s.nx * s.nt * 8);
   L.total = L.env + ((o && o->logimg && !o->env) ? round256(npix * 4) : 0);
   return L;
@@ -126,6 +134,28 @@ int check_outputs(const pwbf_geometry *g, const pwbf_outputs *o, std::string *er
 }
 
 void split(double v, float *hi, float *lo) { pwbf::split_double(v, hi, lo); }
+
+// The window [lo, lo + n) of indices that bilinear taps at positions
+// v0 + i di + k dk (0 <= i < ni, 0 <= k < nk) can reach inside [0, size): the
+// floor of the extreme positions, one more for the upper tap, and one more on
+// each side for the rounding of the device's float-float positions.
+void tap_window(double v0, double di, int ni, double dk, int nk, int size, int32_t *lo,
+                int32_t *n) {
+  double vmin = v0, vmax = v0;
+  for (double v : {v0 + (ni - 1) * di, v0 + (nk - 1) * dk, v0 + (ni - 1) * di + (nk - 1) * dk}) {
+    vmin = std::min(vmin, v);
+    vmax = std::max(vmax, v);
+  }
+  const double a = std::max(0.0, std::floor(vmin) - 1.0);
+  const double b = std::min((double)(size - 1), std::floor(vmax) + 2.0);
+  if (!(a <= b)) {
+    *lo = 0;
+    *n = 0;
+    return;
+  }
+  *lo = (int32_t)a;
+  *n = (int32_t)(b - a) + 1;
+}
 
 }  // namespace
 
@@ -186,8 +216,9 @@ int pwbf_fk_migrate(const pwbf_geometry *g, const void *rf, int32_t rf_dtype, in
   F.log2nx = s.log2nx;
   F.nx_img = g->nx;
   F.nz_img = g->nz;
-  F.S = (float2 *)(ws + L.S);
+  F.T = (float2 *)(ws + L.T);
   F.P = (float2 *)(ws + L.P);
+  F.U = (float2 *)(ws + L.U);
   F.M = (float2 *)(ws + L.M);
   F.out_rf = out->rf;
   F.out_imag = out->imag;
@@ -205,10 +236,10 @@ int pwbf_fk_migrate(const pwbf_geometry *g, const void *rf, int32_t rf_dtype, in
       split(((xf * sn - fmin) / c - t0) * fs / nt, &A.c0_hi, &A.c0_lo);
       split(0.0, &A.c1_hi, &A.c1_lo);
       const double beta = c * nt / (2.0 * fs * s.nx * p);  // c / (2 df Nx p)
-      split(beta, &A.beta_hi, &A.beta_lo);
-      split(sn, &A.sn_hi, &A.sn_lo);
-      split(cs, &A.cs_hi, &A.cs_lo);
-      split(sn / (2.0 * beta), &A.sb_hi, &A.sb_lo);
+      split(beta, &A.m0_hi, &A.m0_lo);
+      split(sn, &A.m1_hi, &A.m1_lo);
+      split(cs, &A.m2_hi, &A.m2_lo);
+      split(sn / (2.0 * beta), &A.m3_hi, &A.m3_lo);
       // true coordinates: column (x - x_first) / p, row z / (c / (2 fs))
       const double kz = 2.0 * fs / c;
       split((g->x0 - xf) / p, &A.ux0_hi, &A.ux0_lo);
@@ -216,12 +247,14 @@ int pwbf_fk_migrate(const pwbf_geometry *g, const void *rf, int32_t rf_dtype, in
       split(0.0, &A.uxk_hi, &A.uxk_lo);
       split(g->z0 * kz, &A.uz0_hi, &A.uz0_lo);
       split(g->dz * kz, &A.uzk_hi, &A.uzk_lo);
+      tap_window((g->x0 - xf) / p, g->dx / p, g->nx, 0.0, g->nz, s.nx, &A.col0, &A.ncol);
+      tap_window(g->z0 * kz, 0.0, g->nx, g->dz * kz, g->nz, s.nt, &A.row0, &A.nrow);
       continue;
     }
     const double v = c / (std::sqrt(2.0) * cs * cs);
     split(((xf * sn - fmin) / c - t0) * fs / nt, &A.c0_hi, &A.c0_lo);
     split(p * sn / c * fs / nt, &A.c1_hi, &A.c1_lo);
-    split(v * nt / (s.nx * p * fs), &A.alpha_hi, &A.alpha_lo);
+    split(v * nt / (s.nx * p * fs), &A.m0_hi, &A.m0_lo);
     // column: (x + z tan th - x_first) / p; row: sqrt2 z / cos th / (v / fs)
     const double tn = std::tan(th), kz = std::sqrt(2.0) / cs / (v / fs);
     split((g->x0 + g->z0 * tn - xf) / p, &A.ux0_hi, &A.ux0_lo);
@@ -229,8 +262,17 @@ int pwbf_fk_migrate(const pwbf_geometry *g, const void *rf, int32_t rf_dtype, in
     split(g->dz * tn / p, &A.uxk_hi, &A.uxk_lo);
     split(g->z0 * kz, &A.uz0_hi, &A.uz0_lo);
     split(g->dz * kz, &A.uzk_hi, &A.uzk_lo);
+    tap_window((g->x0 + g->z0 * tn - xf) / p, g->dx / p, g->nx, g->dz * tn / p, g->nz, s.nx,
+               &A.col0, &A.ncol);
+    tap_window(g->z0 * kz, 0.0, g->nx, g->dz * kz, g->nz, s.nt, &A.row0, &A.nrow);
   }
-  hipError_t e = pwbf::launch_fk(F, (hipStream_t)stream);
+  int ncol_max = 0;
+  for (int k = 0; k < n_ang; ++k) {
+    pwbf::FkAngleConst &A = F.ang[k];
+    if (A.ncol == 0 || A.nrow == 0) A.ncol = A.nrow = 0;  // no pixel reads this angle
+    ncol_max = std::max(ncol_max, (int)A.ncol);
+  }
+  hipError_t e = pwbf::launch_fk(F, ncol_max, (hipStream_t)stream);
   const size_t npix = (size_t)g->nx * g->nz;
   if (e == hipSuccess && out->logimg)
     e = pwbf::launch_logc(F.out_env, out->logimg, F.ws_max, npix, (float)g->log_floor_db,

@@ -1,24 +1,29 @@
 // f-k migrations (Stolt's and Lu's) for steered plane waves. Every stage runs
-// over all angles of the call in one launch (blockIdx.y or the flat index
-// selects the angle), so even a single frame gives the chip thousands of blocks.
-// The two methods share every stage but the remap:
+// over all angles of the call in one launch (blockIdx.y selects the angle), so
+// even a single frame gives the chip thousands of blocks. The two methods share
+// every stage but the remap. Transforms run in LDS (fft_lds.h); the two
+// transposes between channel-major and bin-major data happen in LDS, inside
+// blocks that hold several rows, so every global access is a contiguous run:
 //
 //  k_fk_time      block per (channel, angle): FFT of the trace (Nt samples); the
 //                 positive bins times exp(2 pi i k c_e) (the trace advanced by its
-//                 element's firing delay and shifted to t = 0) go to S[k][e]
-//  k_fk_space     block per (bin k, angle): FFT along the array, zero-padded to Nx
-//  k_fk_stolt     thread per (kz_j, kx_m, angle): the spectrum at the bin
-//                 u = sqrt((alpha m')^2 + j^2) (m' the signed index), linearly
-//                 interpolated (zeros past the last bin), times the Jacobian j / u
-//  k_fk_lu        (Lu's remap instead) thread per (kz'_j, kx'_m, angle): the data
-//                 spectrum at frequency bin u = (beta^2 m'^2 + j^2) /
-//                 (beta m' sin + j cos) and spatial bin m' - u sin / (2 beta),
-//                 bilinearly (periodic in the spatial bin), times the Jacobian
-//                 (j - u cos / 2) / (beta m' sin + j cos); zero where the
-//                 receive wavenumber j - u cos / 2 is negative
-//  k_fk_ispace    block per (kz_j, angle): inverse FFT along kx
-//  k_fk_itime     block per (x1 column, angle): inverse FFT along kz with the
-//                 one-sided spectrum zero-filled to Nt, scaled by 1/(Nx Nt)
+//                 element's firing delay and shifted to t = 0) go to T[e][k]
+//  k_fk_space     block per (ROWS bins, angle): reads T[e][k0..k0+ROWS) for every
+//                 channel, FFTs along the array zero-padded to Nx, writes P[k][m]
+//  k_fk_remap     block per (ROWS image rows kz_j, angle): each cell (j, m) takes
+//                 the data spectrum from P -
+//                   Stolt: at bin u = sqrt((alpha m')^2 + j^2) (m' the signed
+//                   index), linearly (zeros past the last bin), times j / u;
+//                   Lu: at frequency bin u = (beta^2 m'^2 + j^2) /
+//                   (beta m' sin + j cos) and spatial bin m' - u sin / (2 beta),
+//                   bilinearly (periodic in the spatial bin), times
+//                   (j - u cos / 2) / (beta m' sin + j cos), zero where the
+//                   receive wavenumber j - u cos / 2 is negative -
+//                 then inverse FFTs along kx, and writes the window's columns
+//                 transposed, U[e][j0..j0+ROWS)
+//  k_fk_itime     block per window column x1 (and angle): inverse FFT along kz of
+//                 U[e][.], zero-filled to Nt, scaled by 1/(Nx Nt); stores the
+//                 window's rows of M
 //  k_fk_image     thread per pixel: for every angle the migrated image at
 //                 (x1, z1), affine in the pixel indices, by bilinear interpolation;
 //                 the complex sum over angles gives the real, imaginary and
@@ -82,176 +87,224 @@ __device__ __forceinline__ ff ff_div(ff a, ff b) {
   return dev::two_sum(q1, r.hi / b.hi);
 }
 
-__device__ __forceinline__ size_t spec_elems(const FkPlan &F) {
-  return (size_t)((1 << F.log2nt) / 2 + 1) << F.log2nx;
-}
+__device__ __forceinline__ int kbins_of(const FkPlan &F) { return (1 << F.log2nt) / 2 + 1; }
 
 template <int DT>
 __global__ void __launch_bounds__(kPostThreads) k_fk_time(FkPlan F) {
   extern __shared__ __align__(16) float2 sm[];
-  const int nt = 1 << F.log2nt, nx = 1 << F.log2nx, e = blockIdx.x, a = blockIdx.y;
-  float2 *x = sm, *tw = sm + nt;
-  dev::fft_twiddles(tw, nt);
+  const int nt = 1 << F.log2nt, kbins = kbins_of(F), e = blockIdx.x, a = blockIdx.y;
+  float2 *x = sm, *tw = sm + fft::padded(nt);
+  fft::twiddles(tw, nt);
   const size_t base = ((size_t)a * F.n_ch + e) * nt;
   for (int k = threadIdx.x; k < nt; k += kPostThreads)
-    x[dev::bitrev(k, F.log2nt)] = make_float2(trace_sample<DT>(F.rf, base + k), 0.f);
+    x[fft::pad(k)] = make_float2(trace_sample<DT>(F.rf, base + k), 0.f);
   __syncthreads();
-  dev::fft_forward(x, tw, F.log2nt);
+  fft::transform_any<false>(x, tw, F.log2nt);
   const FkAngleConst &A = F.ang[a];
   const ff c = dev::ff_add({A.c0_hi, A.c0_lo}, dev::ff_mul(ffi(e), {A.c1_hi, A.c1_lo}));
-  float2 *S = F.S + (size_t)a * spec_elems(F);
-  for (int k = threadIdx.x; k <= nt / 2; k += kPostThreads) {
+  float2 *T = F.T + ((size_t)a * F.n_ch + e) * kbins;
+  for (int k = threadIdx.x; k < kbins; k += kPostThreads) {
     float sn, cs;
     sincospif(2.0f * frac_revs(k, c), &sn, &cs);
-    S[(size_t)k * nx + e] = dev::cmul(x[k], make_float2(cs, sn));
+    T[k] = dev::cmul(x[fft::pad(k)], make_float2(cs, sn));
   }
 }
 
+template <int L>
 __global__ void __launch_bounds__(kPostThreads) k_fk_space(FkPlan F) {
+  constexpr int nx = 1 << L, ROWS = kFkRowPoints >> L, stride = fft::padded(nx);
   extern __shared__ __align__(16) float2 sm[];
-  const int nx = 1 << F.log2nx;
-  float2 *x = sm, *tw = sm + nx;
-  dev::fft_twiddles(tw, nx);
-  const size_t row = (size_t)blockIdx.y * spec_elems(F) + (size_t)blockIdx.x * nx;
-  for (int e = threadIdx.x; e < nx; e += kPostThreads)
-    x[dev::bitrev(e, F.log2nx)] = e < F.n_ch ? F.S[row + e] : make_float2(0.f, 0.f);
+  float2 *x = sm, *tw = sm + ROWS * stride;
+  const int kbins = kbins_of(F), k0 = blockIdx.x * ROWS, a = blockIdx.y;
+  fft::twiddles(tw, nx);
+  const float2 *T = F.T + (size_t)a * F.n_ch * kbins;
+  // consecutive threads take consecutive bins of one channel
+  for (int t = threadIdx.x; t < nx * ROWS; t += kPostThreads) {
+    const int e = t / ROWS, r = t - e * ROWS, k = k0 + r;
+    x[r * stride + fft::pad(e)] =
+        (e < F.n_ch && k < kbins) ? T[(size_t)e * kbins + k] : make_float2(0.f, 0.f);
+  }
   __syncthreads();
-  dev::fft_forward(x, tw, F.log2nx);
-  for (int m = threadIdx.x; m < nx; m += kPostThreads) F.P[row + m] = x[m];
-}
-
-__global__ void __launch_bounds__(256) k_fk_stolt(FkPlan F) {
-  const int nx = 1 << F.log2nx, kbins = (1 << F.log2nt) / 2 + 1;
-  const size_t per = spec_elems(F), n = per * F.n_ang;
-  for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
-       t += (size_t)gridDim.x * blockDim.x) {
-    const int a = (int)(t / per);
-    const size_t r = t - (size_t)a * per;
-    const int j = (int)(r >> F.log2nx), m = (int)(r & (nx - 1));
-    const int ms = m < nx / 2 ? m : m - nx;  // signed kx index
-    // u^2 = (alpha ms)^2 + j^2 in float-float, then its square root
-    const ff am = dev::ff_mul(ffi(ms), {F.ang[a].alpha_hi, F.ang[a].alpha_lo});
-    const ff u2 = dev::ff_add(dev::ff_mul(am, am), dev::ff_mul(ffi(j), ffi(j)));
-    float2 val = make_float2(0.f, 0.f);
-    if (u2.hi > 0.f && u2.hi < (float)(kbins + 1) * (float)(kbins + 1)) {
-      const ff u = dev::ff_sqrt(u2);
-      float w;
-      const int i0 = split_index(u, &w);
-      // the one-sided spectrum extended by zeros past its last bin
-      if (i0 >= 0 && i0 <= kbins - 1) {
-        const float2 *P = F.P + (size_t)a * per + m;
-        const float2 lo = P[(size_t)i0 * nx];
-        const float2 hi = i0 + 1 <= kbins - 1 ? P[(size_t)(i0 + 1) * nx] : make_float2(0.f, 0.f);
-        const float jac = (float)j / dev::ff_f(u);
-        val = make_float2(((1.f - w) * lo.x + w * hi.x) * jac, ((1.f - w) * lo.y + w * hi.y) * jac);
-      }
-    }
-    F.S[t] = val;
+  fft::transform<L, false, ROWS>(x, tw);
+  float2 *P = F.P + (size_t)a * kbins * nx;
+  for (int t = threadIdx.x; t < nx * ROWS; t += kPostThreads) {
+    const int r = t >> L, m = t & (nx - 1), k = k0 + r;
+    if (k < kbins) P[(size_t)k * nx + m] = x[r * stride + fft::pad(m)];
   }
 }
 
-__global__ void __launch_bounds__(256) k_fk_lu(FkPlan F) {
-  const int nx = 1 << F.log2nx, kbins = (1 << F.log2nt) / 2 + 1;
-  const size_t per = spec_elems(F), n = per * F.n_ang;
-  for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
-       t += (size_t)gridDim.x * blockDim.x) {
-    const int a = (int)(t / per);
-    const size_t r = t - (size_t)a * per;
-    const int j = (int)(r >> F.log2nx), m = (int)(r & (nx - 1));
-    const int ms = m < nx / 2 ? m : m - nx;  // signed kx' index
-    const FkAngleConst &A = F.ang[a];
-    const ff bm = dev::ff_mul(ffi(ms), {A.beta_hi, A.beta_lo});
-    const ff den = dev::ff_add(dev::ff_mul(bm, {A.sn_hi, A.sn_lo}),
-                               dev::ff_mul(ffi(j), {A.cs_hi, A.cs_lo}));
-    float2 val = make_float2(0.f, 0.f);
-    if (den.hi > 0.f) {
-      const ff num = dev::ff_add(dev::ff_mul(bm, bm), dev::ff_mul(ffi(j), ffi(j)));
-      const ff u = ff_div(num, den);  // source frequency bin
-      // receive wavenumber in kz' steps: j - u cos / 2 (>= 0 on the wave's branch)
-      const ff kzr = dev::ff_add(ffi(j), dev::ff_neg(dev::ff_mul(u, {0.5f * A.cs_hi, 0.5f * A.cs_lo})));
-      if (kzr.hi >= 0.f && u.hi < (float)kbins) {
-        const ff mf = dev::ff_add(ffi(ms), dev::ff_neg(dev::ff_mul(u, {A.sb_hi, A.sb_lo})));
-        float wu, wm;
-        const int i0 = split_index(u, &wu);
-        const int m0 = split_index(mf, &wm);
-        if (i0 >= 0 && i0 <= kbins - 1) {
-          const float2 *P = F.P + (size_t)a * per;
-          const int ma = m0 & (nx - 1), mb = (m0 + 1) & (nx - 1);  // periodic in kx
-          const float2 p00 = P[(size_t)i0 * nx + ma], p01 = P[(size_t)i0 * nx + mb];
-          float2 p10 = make_float2(0.f, 0.f), p11 = p10;  // zeros past the last bin
-          if (i0 + 1 <= kbins - 1) {
-            p10 = P[(size_t)(i0 + 1) * nx + ma];
-            p11 = P[(size_t)(i0 + 1) * nx + mb];
-          }
-          const float w00 = (1.f - wm) * (1.f - wu), w01 = wm * (1.f - wu);
-          const float w10 = (1.f - wm) * wu, w11 = wm * wu;
-          const float jac = dev::ff_f(kzr) / dev::ff_f(den);
-          val = make_float2((w00 * p00.x + w01 * p01.x + w10 * p10.x + w11 * p11.x) * jac,
-                            (w00 * p00.y + w01 * p01.y + w10 * p10.y + w11 * p11.y) * jac);
-        }
-      }
-    }
-    F.S[t] = val;
-  }
+// Stolt's remap of cell (j, m): P is the angle's data spectrum [kbins][nx]
+__device__ __forceinline__ float2 stolt_value(const FkAngleConst &A, const float2 *P, int j,
+                                              int m, int nx, int kbins) {
+  const int ms = m < nx / 2 ? m : m - nx;  // signed kx index
+  // u^2 = (alpha ms)^2 + j^2 in float-float, then its square root
+  const ff am = dev::ff_mul(ffi(ms), {A.m0_hi, A.m0_lo});
+  const ff u2 = dev::ff_add(dev::ff_mul(am, am), dev::ff_mul(ffi(j), ffi(j)));
+  const bool in_band = u2.hi > 0.f && u2.hi < (float)(kbins + 1) * (float)(kbins + 1);
+  const ff u = dev::ff_sqrt(in_band ? u2 : ff{1.f, 0.f});
+  float w;
+  const int i0 = split_index(u, &w);
+  // the one-sided spectrum extended by zeros past its last bin; the loads are
+  // clamped into the spectrum and always issued (so the loads of several cells
+  // can be in flight together), and the taps outside it weigh zero
+  const bool ok = in_band && i0 >= 0 && i0 <= kbins - 1;
+  const int ia = ok ? i0 : 0, ib = min(ia + 1, kbins - 1);
+  const float2 lo = P[(size_t)ia * nx + m], hi = P[(size_t)ib * nx + m];
+  const float jac = ok ? (float)j / dev::ff_f(u) : 0.f;
+  const float wl = (1.f - w) * jac, wh = (ok && i0 + 1 <= kbins - 1) ? w * jac : 0.f;
+  return make_float2(wl * lo.x + wh * hi.x, wl * lo.y + wh * hi.y);
 }
 
-__global__ void __launch_bounds__(kPostThreads) k_fk_ispace(FkPlan F) {
+// Lu's remap of cell (j, m)
+__device__ __forceinline__ float2 lu_value(const FkAngleConst &A, const float2 *P, int j, int m,
+                                           int nx, int kbins) {
+  const int ms = m < nx / 2 ? m : m - nx;  // signed kx' index
+  const ff bm = dev::ff_mul(ffi(ms), {A.m0_hi, A.m0_lo});
+  const ff den = dev::ff_add(dev::ff_mul(bm, {A.m1_hi, A.m1_lo}),
+                             dev::ff_mul(ffi(j), {A.m2_hi, A.m2_lo}));
+  const bool pos = den.hi > 0.f;
+  const ff dn = pos ? den : ff{1.f, 0.f};
+  const ff num = dev::ff_add(dev::ff_mul(bm, bm), dev::ff_mul(ffi(j), ffi(j)));
+  const ff u = ff_div(num, dn);  // source frequency bin
+  // receive wavenumber in kz' steps: j - u cos / 2 (>= 0 on the wave's branch)
+  const ff kzr = dev::ff_add(ffi(j), dev::ff_neg(dev::ff_mul(u, {0.5f * A.m2_hi, 0.5f * A.m2_lo})));
+  const bool branch = pos && kzr.hi >= 0.f && u.hi < (float)kbins;
+  const ff mf = dev::ff_add(ffi(ms), dev::ff_neg(dev::ff_mul(u, {A.m3_hi, A.m3_lo})));
+  float wu, wm;
+  const int i0 = split_index(branch ? u : ff{0.f, 0.f}, &wu);
+  const int m0 = split_index(branch ? mf : ff{0.f, 0.f}, &wm);
+  // clamped loads, always issued; taps outside the spectrum weigh zero
+  const bool ok = branch && i0 >= 0 && i0 <= kbins - 1;
+  const int ia = ok ? i0 : 0, ib = min(ia + 1, kbins - 1);
+  const int ma = m0 & (nx - 1), mb = (m0 + 1) & (nx - 1);  // periodic in kx
+  const float2 p00 = P[(size_t)ia * nx + ma], p01 = P[(size_t)ia * nx + mb];
+  const float2 p10 = P[(size_t)ib * nx + ma], p11 = P[(size_t)ib * nx + mb];
+  const float jac = ok ? dev::ff_f(kzr) / dev::ff_f(dn) : 0.f;
+  const float hw = (ok && i0 + 1 <= kbins - 1) ? wu : 0.f;  // zeros past the last bin
+  const float w00 = (1.f - wm) * (1.f - wu) * jac, w01 = wm * (1.f - wu) * jac;
+  const float w10 = (1.f - wm) * hw * jac, w11 = wm * hw * jac;
+  return make_float2(w00 * p00.x + w01 * p01.x + w10 * p10.x + w11 * p11.x,
+                     w00 * p00.y + w01 * p01.y + w10 * p10.y + w11 * p11.y);
+}
+
+template <int L, int METHOD>
+__global__ void __launch_bounds__(kPostThreads) k_fk_remap(FkPlan F) {
+  constexpr int nx = 1 << L, ROWS = kFkRowPoints >> L, stride = fft::padded(nx);
   extern __shared__ __align__(16) float2 sm[];
-  const int nx = 1 << F.log2nx;
-  float2 *x = sm, *tw = sm + nx;
-  dev::fft_twiddles(tw, nx);
-  float2 *row = F.S + (size_t)blockIdx.y * spec_elems(F) + (size_t)blockIdx.x * nx;
-  for (int m = threadIdx.x; m < nx; m += kPostThreads) x[m] = row[m];
+  float2 *x = sm, *tw = sm + ROWS * stride;
+  const int kbins = kbins_of(F), j0 = blockIdx.x * ROWS, a = blockIdx.y;
+  const FkAngleConst &A = F.ang[a];
+  fft::twiddles(tw, nx);
+  const float2 *P = F.P + (size_t)a * kbins * nx;
+#pragma unroll 4
+  for (int t = threadIdx.x; t < nx * ROWS; t += kPostThreads) {
+    const int r = t >> L, m = t & (nx - 1), j = j0 + r;
+    // rows past the last bin compute row kbins - 1 and store zero
+    const int jc = min(j, kbins - 1);
+    const float2 v = METHOD == kFkLu ? lu_value(A, P, jc, m, nx, kbins)
+                                     : stolt_value(A, P, jc, m, nx, kbins);
+    x[r * stride + fft::pad(m)] = j < kbins ? v : make_float2(0.f, 0.f);
+  }
   __syncthreads();
-  dev::fft_inverse(x, tw, F.log2nx);
-  for (int e = threadIdx.x; e < nx; e += kPostThreads) row[e] = x[dev::bitrev(e, F.log2nx)];
+  fft::transform<L, true, ROWS>(x, tw);
+  // the window's columns, transposed: consecutive threads take consecutive rows
+  float2 *U = F.U + (size_t)a * nx * kbins;
+  for (int t = threadIdx.x; t < A.ncol * ROWS; t += kPostThreads) {
+    const int c = t / ROWS, r = t - c * ROWS, j = j0 + r, e = A.col0 + c;
+    if (j < kbins) U[(size_t)e * kbins + j] = x[r * stride + fft::pad(e)];
+  }
 }
 
 __global__ void __launch_bounds__(kPostThreads) k_fk_itime(FkPlan F) {
   extern __shared__ __align__(16) float2 sm[];
-  const int nt = 1 << F.log2nt, nx = 1 << F.log2nx, kbins = nt / 2 + 1;
-  const int col = blockIdx.x, a = blockIdx.y;
-  float2 *x = sm, *tw = sm + nt;
-  dev::fft_twiddles(tw, nt);
-  const float2 *I = F.S + (size_t)a * spec_elems(F) + col;
+  const int a = blockIdx.y;
+  const FkAngleConst &A = F.ang[a];
+  if ((int)blockIdx.x >= A.ncol) return;  // the whole block: outside this angle's window
+  const int nt = 1 << F.log2nt, nx = 1 << F.log2nx, kbins = kbins_of(F);
+  const int col = A.col0 + blockIdx.x;
+  float2 *x = sm, *tw = sm + fft::padded(nt);
+  fft::twiddles(tw, nt);
+  const float2 *I = F.U + ((size_t)a * nx + col) * kbins;
   for (int j = threadIdx.x; j < nt; j += kPostThreads)
-    x[j] = j < kbins ? I[(size_t)j * nx] : make_float2(0.f, 0.f);
+    x[fft::pad(j)] = j < kbins ? I[j] : make_float2(0.f, 0.f);
   __syncthreads();
-  dev::fft_inverse(x, tw, F.log2nt);
+  fft::transform_any<true>(x, tw, F.log2nt);
   const float scale = 1.0f / ((float)nx * (float)nt);
   float2 *out = F.M + ((size_t)a * nx + col) * nt;
-  for (int l = threadIdx.x; l < nt; l += kPostThreads) {
-    const float2 v = x[dev::bitrev(l, F.log2nt)];
+  for (int l = A.row0 + threadIdx.x; l < A.row0 + A.nrow; l += kPostThreads) {
+    const float2 v = x[fft::pad(l)];
     out[l] = make_float2(v.x * scale, v.y * scale);
   }
 }
 
-__global__ void __launch_bounds__(256) k_fk_image(FkPlan F) {
+// Integer part and fraction of v0 + k1 c1 + k2 c2 for float-float v0, c1, c2
+// and integers 0 <= k1, k2 < 2^24: both products split exactly (one FMA each),
+// the large terms summed with error-free additions, the small ones added once;
+// the fraction is accurate to ~1e-7 of an index step. Returns false when the
+// value is outside (lo, hi), before any conversion to an integer.
+__device__ __forceinline__ bool map_index(float v0h, float v0l, float k1, float c1h, float c1l,
+                                          float k2, float c2h, float c2l, float lo, float hi,
+                                          int *idx, float *frac) {
+#pragma clang fp contract(off)
+  const float p1 = k1 * c1h, e1 = fmaf(k1, c1h, -p1);
+  const float p2 = k2 * c2h, e2 = fmaf(k2, c2h, -p2);
+  const ff s = dev::two_sum(v0h, p1);
+  const ff t = dev::two_sum(s.hi, p2);
+  if (!(t.hi > lo && t.hi < hi)) return false;
+  const float small = ((s.lo + t.lo) + (v0l + (e1 + e2))) + (k1 * c1l + k2 * c2l);
+  const float fl = floorf(t.hi);
+  float f = (t.hi - fl) + small;
+  int i = (int)fl;
+  if (f < 0.f) {
+    f += 1.f;
+    --i;
+  } else if (f >= 1.f) {
+    f -= 1.f;
+    ++i;
+  }
+  *idx = i;
+  *frac = f;
+  return true;
+}
+
+// Blocks run along depth: block b covers pixels (ix, iz0 + threadIdx.x) with
+// ix = b / zchunks and iz0 = (b % zchunks) * 256.
+__global__ void __launch_bounds__(256) k_fk_image(FkPlan F, int zchunks) {
   const int nt = 1 << F.log2nt, nx1 = 1 << F.log2nx;
-  const size_t n = (size_t)F.nx_img * F.nz_img;
-  float m = 0.f;
-  for (size_t t = (size_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
-       t += (size_t)gridDim.x * blockDim.x) {
-    const int ix = (int)(t / F.nz_img), iz = (int)(t - (size_t)ix * F.nz_img);
-    float re = 0.f, im = 0.f;
-    for (int a = 0; a < F.n_ang; ++a) {
-      const FkAngleConst &A = F.ang[a];
-      const ff ux = dev::ff_add(
-          dev::ff_add({A.ux0_hi, A.ux0_lo}, dev::ff_mul(ffi(ix), {A.uxi_hi, A.uxi_lo})),
-          dev::ff_mul(ffi(iz), {A.uxk_hi, A.uxk_lo}));
-      const ff uz = dev::ff_add({A.uz0_hi, A.uz0_lo}, dev::ff_mul(ffi(iz), {A.uzk_hi, A.uzk_lo}));
-      // far outside the migrated image (also keeps the integer parts in range)
-      if (!(ux.hi > -2.f && ux.hi < (float)(nx1 + 1) && uz.hi > -2.f && uz.hi < (float)(nt + 1)))
-        continue;
-      float fx, fz;
-      const int i0 = split_index(ux, &fx), j0 = split_index(uz, &fz);
-      const float2 *M = F.M + (size_t)a * nx1 * nt;
+  const int ix = blockIdx.x / zchunks, iz = (blockIdx.x - ix * zchunks) * 256 + threadIdx.x;
+  const bool mine = iz < F.nz_img;
+  const float fix = (float)ix, fiz = (float)iz;
+  float re = 0.f, im = 0.f;
+  for (int a = 0; a < F.n_ang; ++a) {
+    const FkAngleConst &A = F.ang[a];
+    if (A.ncol == 0) continue;
+    int i0, j0;
+    float fx, fz;
+    // far outside the migrated image: nothing to read (and no integer overflow)
+    if (!map_index(A.ux0_hi, A.ux0_lo, fix, A.uxi_hi, A.uxi_lo, fiz, A.uxk_hi, A.uxk_lo, -2.f,
+                   (float)(nx1 + 1), &i0, &fx))
+      continue;
+    if (!map_index(A.uz0_hi, A.uz0_lo, 0.f, 0.f, 0.f, fiz, A.uzk_hi, A.uzk_lo, -2.f,
+                   (float)(nt + 1), &j0, &fz))
+      continue;
+    const float2 *M = F.M + (size_t)a * nx1 * nt;
+    // taps outside the window are outside [0, Nx) x [0, Nt) too (the window
+    // holds every tap inside, with a margin), so they read as zero
+    const int c1 = A.col0 + A.ncol, r1 = A.row0 + A.nrow;
+    if (i0 >= A.col0 && i0 + 1 < c1 && j0 >= A.row0 && j0 + 1 < r1) {
+      const float2 *q = M + (size_t)i0 * nt + j0;
+      const float2 v00 = q[0], v01 = q[1], v10 = q[nt], v11 = q[nt + 1];
+      const float w00 = (1.f - fx) * (1.f - fz), w01 = (1.f - fx) * fz;
+      const float w10 = fx * (1.f - fz), w11 = fx * fz;
+      re += w00 * v00.x + w01 * v01.x + w10 * v10.x + w11 * v11.x;
+      im += w00 * v00.y + w01 * v01.y + w10 * v10.y + w11 * v11.y;
+    } else {
 #pragma unroll
       for (int di = 0; di < 2; ++di) {
 #pragma unroll
         for (int dj = 0; dj < 2; ++dj) {
           const int i = i0 + di, j = j0 + dj;
-          if (i >= 0 && i < nx1 && j >= 0 && j < nt) {
+          if (i >= A.col0 && i < c1 && j >= A.row0 && j < r1) {
             const float w = (di ? fx : 1.f - fx) * (dj ? fz : 1.f - fz);
             const float2 v = M[(size_t)i * nt + j];
             re = fmaf(w, v.x, re);
@@ -260,36 +313,52 @@ __global__ void __launch_bounds__(256) k_fk_image(FkPlan F) {
         }
       }
     }
-    const float e = sqrtf(re * re + im * im);
+  }
+  const float e = sqrtf(re * re + im * im);
+  if (mine) {
+    const size_t t = (size_t)ix * F.nz_img + iz;
     F.out_rf[t] = re;
     if (F.out_imag) F.out_imag[t] = im;
     if (F.out_env) F.out_env[t] = e;
-    m = fmaxf(m, e);
   }
   if (F.ws_max) {
     __shared__ float wm[4];
+    float m = mine ? e : 0.f;
     for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
     if ((threadIdx.x & 63) == 0) wm[threadIdx.x >> 6] = m;
     __syncthreads();
     if (threadIdx.x == 0)
-      atomicMax(F.ws_max, __float_as_uint(fmaxf(fmaxf(wm[0], wm[1]), fmaxf(wm[2], wm[3]))));
+      dev::frame_max_fold(F.ws_max, fmaxf(fmaxf(wm[0], wm[1]), fmaxf(wm[2], wm[3])));
   }
 }
 
-__global__ void k_fk_clear(uint32_t *w) { *w = 0u; }
+__global__ void k_fk_clear(uint32_t *slots) { dev::frame_max_clear(slots, threadIdx.x); }
 
-int grid_for(size_t n) { return (int)std::min<size_t>((n + 255) / 256, 16384); }
+template <int L>
+hipError_t launch_rows(const FkPlan &F, hipStream_t s) {
+  constexpr int ROWS = kFkRowPoints >> L;
+  const int kbins = (1 << F.log2nt) / 2 + 1;
+  const dim3 grid((kbins + ROWS - 1) / ROWS, F.n_ang), blk(kPostThreads);
+  const size_t lds = fft::lds_bytes(1 << L, ROWS);
+  hipLaunchKernelGGL(k_fk_space<L>, grid, blk, lds, s, F);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (F.method == kFkLu)
+    hipLaunchKernelGGL((k_fk_remap<L, kFkLu>), grid, blk, lds, s, F);
+  else
+    hipLaunchKernelGGL((k_fk_remap<L, kFkStolt>), grid, blk, lds, s, F);
+  return hipGetLastError();
+}
 
 }  // namespace
 
-hipError_t launch_fk(const FkPlan &F, hipStream_t s) {
-  const int nt = 1 << F.log2nt, nx = 1 << F.log2nx, kbins = nt / 2 + 1;
-  const size_t lds_t = (size_t)nt * sizeof(float2) * 3 / 2;
-  const size_t lds_x = (size_t)nx * sizeof(float2) * 3 / 2;
+hipError_t launch_fk(const FkPlan &F, int ncol_max, hipStream_t s) {
+  const int nt = 1 << F.log2nt;
+  const size_t lds_t = fft::lds_bytes(nt, 1);
   const dim3 blk(kPostThreads);
   hipError_t e;
   if (F.ws_max) {
-    hipLaunchKernelGGL(k_fk_clear, dim3(1), dim3(1), 0, s, F.ws_max);
+    hipLaunchKernelGGL(k_fk_clear, dim3(1), dim3(kMaxSlots), 0, s, F.ws_max);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   if (F.dtype == kI16)
@@ -299,20 +368,25 @@ hipError_t launch_fk(const FkPlan &F, hipStream_t s) {
   else
     hipLaunchKernelGGL(k_fk_time<kF32>, dim3(F.n_ch, F.n_ang), blk, lds_t, s, F);
   if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_fk_space, dim3(kbins, F.n_ang), blk, lds_x, s, F);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  if (F.method == kFkLu)
-    hipLaunchKernelGGL(k_fk_lu, dim3(grid_for((size_t)kbins * nx * F.n_ang)), dim3(256), 0, s, F);
-  else
-    hipLaunchKernelGGL(k_fk_stolt, dim3(grid_for((size_t)kbins * nx * F.n_ang)), dim3(256), 0, s,
-                       F);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_fk_ispace, dim3(kbins, F.n_ang), blk, lds_x, s, F);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_fk_itime, dim3(nx, F.n_ang), blk, lds_t, s, F);
-  if ((e = hipGetLastError()) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_fk_image, dim3(grid_for((size_t)F.nx_img * F.nz_img)), dim3(256), 0, s,
-                     F);
+  switch (F.log2nx) {
+    case 2: e = launch_rows<2>(F, s); break;
+    case 3: e = launch_rows<3>(F, s); break;
+    case 4: e = launch_rows<4>(F, s); break;
+    case 5: e = launch_rows<5>(F, s); break;
+    case 6: e = launch_rows<6>(F, s); break;
+    case 7: e = launch_rows<7>(F, s); break;
+    case 8: e = launch_rows<8>(F, s); break;
+    case 9: e = launch_rows<9>(F, s); break;
+    case 10: e = launch_rows<10>(F, s); break;
+    default: return hipErrorInvalidValue;
+  }
+  if (e != hipSuccess) return e;
+  if (ncol_max > 0) {
+    hipLaunchKernelGGL(k_fk_itime, dim3(ncol_max, F.n_ang), blk, lds_t, s, F);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  const int zchunks = (F.nz_img + 255) / 256;
+  hipLaunchKernelGGL(k_fk_image, dim3(F.nx_img * zchunks), dim3(256), 0, s, F, zchunks);
   return hipGetLastError();
 }
 

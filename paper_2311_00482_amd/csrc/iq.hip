@@ -1,6 +1,6 @@
 // Baseband (IQ) demodulation of channel records, one block per record.
 //
-// A record of n = 2^L samples is transformed with the in-LDS radix-2 FFT,
+// A record of n = 2^L samples is transformed with the in-LDS block FFT,
 // multiplied by the one-sided weights of the analytic signal (and the 1/n of
 // the inverse), transformed back, and multiplied by exp(-2 pi i r k) with
 // r = f0 / fs, k the sample index. The carrier phase is formed in revolutions
@@ -31,23 +31,23 @@ __global__ void __launch_bounds__(kPostThreads)
                float r_lo) {
   extern __shared__ __align__(16) float2 sm[];
   const int ns = 1 << log2ns;
-  float2 *x = sm, *tw = sm + ns;
+  float2 *x = sm, *tw = sm + fft::padded(ns);
   const size_t base = (size_t)blockIdx.x * ns;
-  dev::fft_twiddles(tw, ns);
+  fft::twiddles(tw, ns);
   for (int k = threadIdx.x; k < ns; k += kPostThreads)
-    x[dev::bitrev(k, log2ns)] = make_float2(rf_sample<DT>(rf, base + k), 0.f);
+    x[fft::pad(k)] = make_float2(rf_sample<DT>(rf, base + k), 0.f);
   __syncthreads();
-  dev::fft_forward(x, tw, log2ns);
+  fft::transform_any<false>(x, tw, log2ns);
   const float inv_n = 1.0f / (float)ns;
   for (int k = threadIdx.x; k < ns; k += kPostThreads) {
     const float h = dev::analytic_weight(k, ns) * inv_n;
-    const float2 v = x[k];
-    x[k] = make_float2(v.x * h, v.y * h);
+    const float2 v = x[fft::pad(k)];
+    x[fft::pad(k)] = make_float2(v.x * h, v.y * h);
   }
   __syncthreads();
-  dev::fft_inverse(x, tw, log2ns);
+  fft::transform_any<true>(x, tw, log2ns);
   for (int k = threadIdx.x; k < ns; k += kPostThreads) {
-    const float2 z = x[dev::bitrev(k, log2ns)];
+    const float2 z = x[fft::pad(k)];
     const float fk = (float)k;
     const float p = fk * r_hi;
     const float e = fmaf(fk, r_hi, -p);  // exact error of the product
@@ -60,7 +60,7 @@ __global__ void __launch_bounds__(kPostThreads)
 
 }  // namespace
 
-size_t iq_demod_lds_bytes(int ns) { return (size_t)ns * sizeof(float2) * 3 / 2; }
+size_t iq_demod_lds_bytes(int ns) { return fft::lds_bytes(ns, 1); }
 
 hipError_t launch_iq_demod(const void *rf, int dtype, void *iq, int rows, int log2ns, float r_hi,
                            float r_lo, hipStream_t stream) {

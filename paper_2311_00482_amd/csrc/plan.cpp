@@ -10,6 +10,7 @@
 // The kernel starts each window at floor(min transmit) - 1 plus
 // floor(min receive) - 1, so every interpolation pair of every pixel of the
 // tile lies inside ceil(spread) + 6 entries (rounded up to a multiple of 4).
+#include "frame_max.h"
 #include "plan_host.h"
 
 #include <algorithm>
@@ -115,7 +116,7 @@ static bool post_requested(const pwbf_outputs *o) {
 
 size_t workspace_bytes(const pwbf_geometry *g, const pwbf_outputs *o) {
   if (!o || !o->logimg) return 0;
-  size_t b = 256;
+  size_t b = kMaxSlotBytes;  // the frame maximum's slots, then the envelope if not an output
   if (!o->env) b += (size_t)g->nx * g->nz * sizeof(float);
   return b;
 }
@@ -428,7 +429,8 @@ int build_plan(const pwbf_geometry *g, const void *rf, int dtype, int mode, int 
   P->ws_max = o->logimg ? (uint32_t *)ws : nullptr;
   P->out_imag = o->imag;
   P->out_env = nullptr;
-  if (is_iq_mode(mode)) P->out_env = o->env ? o->env : (o->logimg ? (float *)((char *)ws + 256) : nullptr);
+  if (is_iq_mode(mode))
+    P->out_env = o->env ? o->env : (o->logimg ? (float *)((char *)ws + kMaxSlotBytes) : nullptr);
   return PWBF_OK;
 }
 
@@ -458,7 +460,7 @@ int build_post_plan(const pwbf_geometry *g, const pwbf_outputs *o, void *ws, Pos
   Q->src = o->rf;
   Q->filtered = o->filtered;
   Q->ws_max = o->logimg ? (uint32_t *)ws : nullptr;
-  Q->env = o->env ? o->env : (o->logimg ? (float *)((char *)ws + 256) : nullptr);
+  Q->env = o->env ? o->env : (o->logimg ? (float *)((char *)ws + kMaxSlotBytes) : nullptr);
   Q->logimg = o->logimg;
   Q->nx = g->nx;
   Q->nz = g->nz;

@@ -69,7 +69,7 @@ struct PostPlan {
   float *filtered;   // Re(analytic) of the band-passed column, or null
   float *env;        // |analytic|, or null
   float *logimg;     // log image, or null (needs env and ws_max)
-  uint32_t *ws_max;  // bit pattern of the frame's largest envelope value
+  uint32_t *ws_max;  // the frame maximum's slots (frame_max.h), or null
   int32_t nx, nz, log2nz;
   int32_t bandpass, k_lo, k_hi;  // band [k_lo, k_hi] in |signed bin|
   float floor_db;

@@ -22,6 +22,7 @@
 #include <vector>
 
 #include "../../include/pwbf.h"
+#include "frame_max.h"
 #include "plan_host.h"
 #include "serve.h"
 
@@ -268,12 +269,13 @@ void scheduler(pwbf_server *s) {
   }
 }
 
-// device bytes of one ring slot: FP16 RF, the output planes, the frame maximum
+// device bytes of one ring slot: FP16 RF, the output planes, the frame maximum's slots
 size_t slot_bytes(const pwbf_probe &p) {
   const pwbf_geometry &g = *p.geom;
   const size_t plane = (size_t)g.nx * g.nz * sizeof(float);
   const int planes = 1 + ((p.want_env || p.want_log) ? 1 : 0) + (p.want_log ? 1 : 0);
-  return (size_t)g.n_angles * g.n_channels * g.n_samples * 2 + planes * plane + 256;
+  return (size_t)g.n_angles * g.n_channels * g.n_samples * 2 + planes * plane +
+         pwbf::kMaxSlotBytes;
 }
 
 void free_server(pwbf_server *s) {
@@ -326,7 +328,7 @@ int pwbf_server_create(const pwbf_probe *probes, int32_t n, size_t hbm_budget_by
                                                    " angles are summed per frame");
     if ((p.want_env || p.want_log || p.geom->bandpass)) {
       pwbf_outputs o = {(float *)256, nullptr, (float *)256, p.want_log ? (float *)256 : nullptr};
-      static unsigned char fake_ws[512] __attribute__((aligned(256)));
+      static unsigned char fake_ws[pwbf::kMaxSlotBytes] __attribute__((aligned(256)));
       rc = pwbf::validate_outputs(p.geom, &o, fake_ws, sizeof fake_ws, &err);
       if (rc) return api_set_error(rc, "probe " + std::to_string(i) + ": " + err);
     }
@@ -366,7 +368,8 @@ int pwbf_server_create(const pwbf_probe *probes, int32_t n, size_t hbm_budget_by
       if (e == hipSuccess) e = hipMalloc((void **)&sl.out_rf, plane);
       if (e == hipSuccess && p.want_env) e = hipMalloc((void **)&sl.env, plane);
       if (e == hipSuccess && p.want_log) e = hipMalloc((void **)&sl.logimg, plane);
-      if (e == hipSuccess) e = hipMalloc((void **)&sl.ws, 256);  // frame max (env is a slot plane)
+      // the frame maximum's slots (the envelope is a slot plane)
+      if (e == hipSuccess) e = hipMalloc((void **)&sl.ws, pwbf::kMaxSlotBytes);
       if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.uploaded, hipEventDisableTiming);
       if (e != hipSuccess) break;
       const pwbf_outputs o = {sl.out_rf, nullptr, sl.env, sl.logimg};

@@ -44,7 +44,8 @@ __global__ void k_serve_reset(int *counter, const PostPlan *__restrict__ post, A
   if (i == 0) *counter = 0;
   if (i < al.n) {
     const PostPlan &Q = post[al.plan[i]];
-    if (Q.ws_max) *Q.ws_max = 0u;
+    if (Q.ws_max)
+      for (int s = 0; s < kMaxSlots; ++s) dev::frame_max_clear(Q.ws_max, s);
   }
 }
 
@@ -109,7 +110,7 @@ __global__ void __launch_bounds__(256) k_serve_logc(const PostPlan *__restrict__
   const int b = blockIdx.x;
   const int k = find_slot(al.log0, al.n, b);
   const PostPlan &Q = post[al.plan[k]];
-  const float m = __uint_as_float(*Q.ws_max);
+  const float m = dev::frame_max_read(Q.ws_max);
   const size_t base = (size_t)(b - al.log0[k]) * Q.nz;
   for (int i = threadIdx.x; i < Q.nz; i += blockDim.x)
     Q.logimg[base + i] = dev::log_db(Q.env[base + i], m, Q.floor_db);
@@ -144,7 +145,7 @@ hipError_t launch_serve(const FramePlan *plans, const PostPlan *post, const Acti
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (al.col0[al.n] > 0) {
-    const size_t plds = (size_t)max_nz * sizeof(float2) + (size_t)(max_nz / 2) * sizeof(float2);
+    const size_t plds = dev::post_lds_bytes(max_nz);
     hipLaunchKernelGGL(k_serve_postz, dim3(al.col0[al.n]), dim3(dev::kPostThreads), plds, stream,
                        post, al);
     e = hipGetLastError();

@@ -157,9 +157,10 @@ def test_workspace_rules():
     g = GeometryArg(config_c1())
     assert L.pwbf_workspace_bytes(g.ref, ctypes.byref(_abi.Outputs(FAKE, None, None, None))) == 0
     assert L.pwbf_workspace_bytes(g.ref, ctypes.byref(_abi.Outputs(FAKE, None, FAKE, None))) == 0
-    assert L.pwbf_workspace_bytes(g.ref, ctypes.byref(_abi.Outputs(FAKE, None, FAKE, FAKE))) == 256
+    # the frame maximum's 64 slots, one 128-byte line each
+    assert L.pwbf_workspace_bytes(g.ref, ctypes.byref(_abi.Outputs(FAKE, None, FAKE, FAKE))) == 8192
     n = L.pwbf_workspace_bytes(g.ref, ctypes.byref(_abi.Outputs(FAKE, None, None, FAKE)))
-    assert n == 256 + 128 * 256 * 4
+    assert n == 8192 + 128 * 256 * 4
     log = _abi.Outputs(FAKE, None, FAKE, FAKE)
     assert _call(g, out=log)[0] == _abi.E_INVALID  # no workspace
     assert _call(g, out=log, ws=FAKE, ws_bytes=255)[0] == _abi.E_INVALID
@@ -349,7 +350,7 @@ def test_server_create_rejects_before_touching_the_device():
     assert rc == _abi.E_UNSUPPORTED and "power of two" in msg
     rc, msg = _server_create([_probe(g, mode=_abi.BBDMAS)])
     assert rc == _abi.E_UNSUPPORTED and "single-frame" in msg
-    slot = 64 * 2048 * 2 + 3 * 128 * 256 * 4 + 256  # FP16 RF, rf/env/log planes, frame max
+    slot = 64 * 2048 * 2 + 3 * 128 * 256 * 4 + 8192  # FP16 RF, rf/env/log planes, max slots
     rc, msg = _server_create([ok], budget=slot - 1)
     assert rc == _abi.E_INVALID and f"needs {slot} bytes" in msg
     L = _abi.lib()
@@ -412,13 +413,16 @@ def test_fk_workspace_and_argument_errors():
     W = L.pwbf_fk_workspace_bytes
     ST, LU = _abi.FK_STOLT, _abi.FK_LU
 
-    # per angle: S and P [2049][Nx], M [Nx][4096], complex float32; Nx = 256 / 512
-    def per(a, nx):
-        return 2 * r256(a * 2049 * nx * 8) + r256(a * nx * 4096 * 8)
-    need = 256 + per(11, 256)
+    # T [128][2049], P [2049][Nx], U [Nx][2049], M [Nx][4096] per angle, complex
+    # float32; Nx = 256 (Stolt) or 512 (Lu)
+    def per(a, nx, n=128, nt=4096):
+        kb = nt // 2 + 1
+        return (r256(a * n * kb * 8) + r256(a * kb * nx * 8) + r256(a * nx * kb * 8)
+                + r256(a * nx * nt * 8))
+    need = 8192 + per(11, 256)
     assert W(g.ref, ST, -1, ctypes.byref(o)) == need
-    assert W(g.ref, ST, 3, ctypes.byref(o)) == 256 + per(1, 256)
-    assert W(g.ref, LU, -1, ctypes.byref(o)) == 256 + per(11, 512)
+    assert W(g.ref, ST, 3, ctypes.byref(o)) == 8192 + per(1, 256)
+    assert W(g.ref, LU, -1, ctypes.byref(o)) == 8192 + per(11, 512)
     assert W(g.ref, ST, 11, ctypes.byref(o)) == 0 and W(g.ref, ST, -2, ctypes.byref(o)) == 0
     assert W(g.ref, 2, -1, ctypes.byref(o)) == 0 and b"method" in L.pwbf_last_error()
     # a log image without an envelope plane needs the envelope in the workspace
@@ -435,7 +439,7 @@ def test_fk_workspace_and_argument_errors():
     assert b"pitch" in L.pwbf_last_error()
     # Lu pads to 4 N: 256 channels need 1024 (supported)
     g256 = GeometryArg(g3.replace(n_channels=256, n_samples=1024))
-    assert W(g256.ref, LU, 0, ctypes.byref(o)) == 256 + 2 * r256(513 * 1024 * 8) + r256(1024 * 1024 * 8)
+    assert W(g256.ref, LU, 0, ctypes.byref(o)) == 8192 + per(1, 1024, n=256, nt=1024)
     # every call below fails a host check before any HIP call (workspace is NULL
     # or too small, so none reaches the launches)
     oo = ctypes.byref(o)

@@ -134,7 +134,7 @@ def test_budget_admission_and_queue_limit(probes):
     spec, _, host = probes[0]
     g = spec.geom
     plane = g.nx * g.nz * 4
-    slot_bytes = g.n_angles * g.n_channels * g.n_samples * 2 + 3 * plane + 256
+    slot_bytes = g.n_angles * g.n_channels * g.n_samples * 2 + 3 * plane + 8192  # + max slots
     srv = _server(probes, [0], slots=4, budget=2 * slot_bytes, max_queue=3)
     try:
         first = srv.submit(0, host)
