@@ -133,58 +133,137 @@ __global__ void __launch_bounds__(kPostThreads) k_fk_space(FkPlan F) {
   }
 }
 
-// Stolt's remap of cell (j, m): P is the angle's data spectrum [kbins][nx]
-__device__ __forceinline__ float2 stolt_value(const FkAngleConst &A, const float2 *P, int j,
-                                              int m, int nx, int kbins) {
-  const int ms = m < nx / 2 ? m : m - nx;  // signed kx index
-  // u^2 = (alpha ms)^2 + j^2 in float-float, then its square root
-  const ff am = dev::ff_mul(ffi(ms), {A.m0_hi, A.m0_lo});
-  const ff u2 = dev::ff_add(dev::ff_mul(am, am), dev::ff_mul(ffi(j), ffi(j)));
-  const bool in_band = u2.hi > 0.f && u2.hi < (float)(kbins + 1) * (float)(kbins + 1);
-  const ff u = dev::ff_sqrt(in_band ? u2 : ff{1.f, 0.f});
-  float w;
-  const int i0 = split_index(u, &w);
-  // the one-sided spectrum extended by zeros past its last bin; the loads are
-  // clamped into the spectrum and always issued (so the loads of several cells
-  // can be in flight together), and the taps outside it weigh zero
-  const bool ok = in_band && i0 >= 0 && i0 <= kbins - 1;
-  const int ia = ok ? i0 : 0, ib = min(ia + 1, kbins - 1);
-  const float2 lo = P[(size_t)ia * nx + m], hi = P[(size_t)ib * nx + m];
-  const float jac = ok ? (float)j / dev::ff_f(u) : 0.f;
-  const float wl = (1.f - w) * jac, wh = (ok && i0 + 1 <= kbins - 1) ? w * jac : 0.f;
-  return make_float2(wl * lo.x + wh * hi.x, wl * lo.y + wh * hi.y);
+// Float-float helpers with hardware reciprocal and square root in the leading
+// term: the error-free residual of the correction step absorbs their ulp-level
+// error, so the results match the correctly rounded versions to ~1e-14.
+__device__ __forceinline__ ff quick_two_sum(float a, float b) {  // |a| >= |b|
+#pragma clang fp contract(off)
+  const float s = a + b;
+  return {s, b - (s - a)};
 }
 
-// Lu's remap of cell (j, m)
-__device__ __forceinline__ float2 lu_value(const FkAngleConst &A, const float2 *P, int j, int m,
-                                           int nx, int kbins) {
-  const int ms = m < nx / 2 ? m : m - nx;  // signed kx' index
-  const ff bm = dev::ff_mul(ffi(ms), {A.m0_hi, A.m0_lo});
-  const ff den = dev::ff_add(dev::ff_mul(bm, {A.m1_hi, A.m1_lo}),
-                             dev::ff_mul(ffi(j), {A.m2_hi, A.m2_lo}));
-  const bool pos = den.hi > 0.f;
-  const ff dn = pos ? den : ff{1.f, 0.f};
-  const ff num = dev::ff_add(dev::ff_mul(bm, bm), dev::ff_mul(ffi(j), ffi(j)));
-  const ff u = ff_div(num, dn);  // source frequency bin
-  // receive wavenumber in kz' steps: j - u cos / 2 (>= 0 on the wave's branch)
-  const ff kzr = dev::ff_add(ffi(j), dev::ff_neg(dev::ff_mul(u, {0.5f * A.m2_hi, 0.5f * A.m2_lo})));
-  const bool branch = pos && kzr.hi >= 0.f && u.hi < (float)kbins;
-  const ff mf = dev::ff_add(ffi(ms), dev::ff_neg(dev::ff_mul(u, {A.m3_hi, A.m3_lo})));
-  float wu, wm;
-  const int i0 = split_index(branch ? u : ff{0.f, 0.f}, &wu);
-  const int m0 = split_index(branch ? mf : ff{0.f, 0.f}, &wm);
-  // clamped loads, always issued; taps outside the spectrum weigh zero
-  const bool ok = branch && i0 >= 0 && i0 <= kbins - 1;
-  const int ia = ok ? i0 : 0, ib = min(ia + 1, kbins - 1);
-  const int ma = m0 & (nx - 1), mb = (m0 + 1) & (nx - 1);  // periodic in kx
-  const float2 p00 = P[(size_t)ia * nx + ma], p01 = P[(size_t)ia * nx + mb];
-  const float2 p10 = P[(size_t)ib * nx + ma], p11 = P[(size_t)ib * nx + mb];
-  const float jac = ok ? dev::ff_f(kzr) / dev::ff_f(dn) : 0.f;
-  const float hw = (ok && i0 + 1 <= kbins - 1) ? wu : 0.f;  // zeros past the last bin
-  const float w00 = (1.f - wm) * (1.f - wu) * jac, w01 = wm * (1.f - wu) * jac;
-  const float w10 = (1.f - wm) * hw * jac, w11 = wm * hw * jac;
-  return make_float2(w00 * p00.x + w01 * p01.x + w10 * p10.x + w11 * p11.x,
-                     w00 * p00.y + w01 * p01.y + w10 * p10.y + w11 * p11.y);
+__device__ __forceinline__ ff ff_sqrt_hw(ff a) {  // a.hi > 0
+#pragma clang fp contract(off)
+  const float s = __builtin_amdgcn_sqrtf(a.hi);
+  const float r = fmaf(-s, s, a.hi) + a.lo;
+  return quick_two_sum(s, r * (0.5f * __builtin_amdgcn_rcpf(s)));
+}
+
+__device__ __forceinline__ ff ff_div_hw(ff a, ff b) {  // b.hi != 0
+#pragma clang fp contract(off)
+  const float rb = __builtin_amdgcn_rcpf(b.hi);
+  const float q1 = a.hi * rb;
+  const float p = q1 * b.hi, e = fmaf(q1, b.hi, -p);
+  const float r = ((a.hi - p) - e) + (a.lo - q1 * b.lo);
+  return quick_two_sum(q1, r * rb);
+}
+
+// v - u c for float-float v, u, c (c's product split exactly)
+__device__ __forceinline__ ff ff_sub_mul(ff v, ff u, float c_hi, float c_lo) {
+#pragma clang fp contract(off)
+  const float p = u.hi * c_hi, e = fmaf(u.hi, c_hi, -p) + (u.hi * c_lo + u.lo * c_hi);
+  const ff d = dev::two_sum(v.hi, -p);
+  return dev::two_sum(d.hi, d.lo + (v.lo - e));
+}
+
+// The cells of a remap block: per thread a fixed set of kx columns m (one when
+// Nx <= 256) and, for each, every row of the block that falls to the thread.
+template <int L>
+struct RemapCells {
+  static constexpr int nx = 1 << L, ROWS = kFkRowPoints >> L;
+  static constexpr int MPT = nx >= kPostThreads ? nx / kPostThreads : 1;  // columns per thread
+  static constexpr int RSTEP = nx >= kPostThreads ? 1 : kPostThreads / nx;  // rows apart
+  __device__ static int m(int mi) {
+    return nx >= kPostThreads ? (int)threadIdx.x + kPostThreads * mi : (int)threadIdx.x & (nx - 1);
+  }
+  __device__ static int r0() { return nx >= kPostThreads ? 0 : (int)threadIdx.x >> L; }
+};
+
+// Stolt's remap of the block's rows: the cell (j, m) takes the data spectrum at
+// bin u = sqrt((alpha m')^2 + j^2), linearly (zeros past the last bin), times j / u.
+template <int L>
+__device__ __forceinline__ void stolt_rows(const FkAngleConst &A, const float2 *__restrict__ P,
+                                           int j0, int kbins, float2 *x) {
+#pragma clang fp contract(off)
+  using C = RemapCells<L>;
+  constexpr int stride = fft::padded(C::nx);
+  for (int mi = 0; mi < C::MPT; ++mi) {
+    const int m = C::m(mi), ms = m < C::nx / 2 ? m : m - C::nx;
+    const ff am = dev::ff_mul(ffi(ms), {A.m0_hi, A.m0_lo});
+    const ff am2 = dev::ff_mul(am, am);  // (alpha m')^2, per column
+#pragma unroll 4
+    for (int r = C::r0(); r < C::ROWS; r += C::RSTEP) {
+      const int j = min(j0 + r, kbins - 1);  // rows past the last bin store zero below
+      const float fj = (float)j;
+      const ff u2 = dev::two_sum(am2.hi, fj * fj);  // j^2 < 2^24 is exact
+      const ff u2n = dev::two_sum(u2.hi, u2.lo + am2.lo);
+      const bool in_band = u2n.hi > 0.f && u2n.hi < (float)(kbins + 1) * (float)(kbins + 1);
+      const ff u = ff_sqrt_hw(in_band ? u2n : ff{1.f, 0.f});
+      float w;
+      const int i0 = split_index(u, &w);
+      // clamped loads, always issued; taps outside the spectrum weigh zero
+      const bool ok = in_band && i0 >= 0 && i0 <= kbins - 1 && j0 + r < kbins;
+      const int ia = ok ? i0 : 0, ib = min(ia + 1, kbins - 1);
+      const float2 lo = P[(size_t)ia * C::nx + m], hi = P[(size_t)ib * C::nx + m];
+      const float jac = ok ? fj * __builtin_amdgcn_rcpf(u.hi) : 0.f;
+      const float wl = (1.f - w) * jac, wh = (ok && i0 + 1 <= kbins - 1) ? w * jac : 0.f;
+      x[r * stride + fft::pad(m)] = make_float2(wl * lo.x + wh * hi.x, wl * lo.y + wh * hi.y);
+    }
+  }
+}
+
+// Lu's remap of the block's rows: the cell (j, m) takes the data spectrum at
+// frequency bin u = (beta^2 m'^2 + j^2) / (beta m' sin + j cos) and spatial bin
+// m' - u sin / (2 beta), bilinearly (periodic in the spatial bin, zeros past the
+// last frequency bin), times (j - u cos / 2) / (beta m' sin + j cos); zero where
+// the receive wavenumber j - u cos / 2 is negative or the denominator is not
+// positive.
+template <int L>
+__device__ __forceinline__ void lu_rows(const FkAngleConst &A, const float2 *__restrict__ P,
+                                        int j0, int kbins, float2 *x) {
+#pragma clang fp contract(off)
+  using C = RemapCells<L>;
+  constexpr int stride = fft::padded(C::nx);
+  const float ch = 0.5f * A.m2_hi, cl = 0.5f * A.m2_lo;  // cos / 2
+  for (int mi = 0; mi < C::MPT; ++mi) {
+    const int m = C::m(mi), ms = m < C::nx / 2 ? m : m - C::nx;
+    const ff bm = dev::ff_mul(ffi(ms), {A.m0_hi, A.m0_lo});
+    const ff bm2 = dev::ff_mul(bm, bm);                     // beta^2 m'^2
+    const ff bms = dev::ff_mul(bm, {A.m1_hi, A.m1_lo});     // beta m' sin
+#pragma unroll 2
+    for (int r = C::r0(); r < C::ROWS; r += C::RSTEP) {
+      const int j = min(j0 + r, kbins - 1);
+      const float fj = (float)j;
+      // den = beta m' sin + j cos
+      const float pc = fj * A.m2_hi, ec = fmaf(fj, A.m2_hi, -pc) + fj * A.m2_lo;
+      const ff d0 = dev::two_sum(bms.hi, pc);
+      const ff den = dev::two_sum(d0.hi, d0.lo + (bms.lo + ec));
+      const bool pos = den.hi > 0.f;
+      // num = beta^2 m'^2 + j^2
+      const ff n0 = dev::two_sum(bm2.hi, fj * fj);
+      const ff num = dev::two_sum(n0.hi, n0.lo + bm2.lo);
+      const ff u = ff_div_hw(num, pos ? den : ff{1.f, 0.f});  // source frequency bin
+      // the receive wavenumber j - u cos / 2 only weighs the cell: float suffices
+      const float kzr = fmaf(-u.lo, ch, fmaf(-u.hi, ch, fj)) - u.hi * cl;
+      const bool branch = pos && kzr >= 0.f && u.hi < (float)kbins && j0 + r < kbins;
+      const ff mf = ff_sub_mul(ffi(ms), u, A.m3_hi, A.m3_lo);  // spatial bin
+      float wu, wm;
+      const int i0 = split_index(branch ? u : ff{0.f, 0.f}, &wu);
+      const int m0 = split_index(branch ? mf : ff{0.f, 0.f}, &wm);
+      const bool ok = branch && i0 >= 0 && i0 <= kbins - 1;
+      const int ia = ok ? i0 : 0, ib = min(ia + 1, kbins - 1);
+      const int ma = m0 & (C::nx - 1), mb = (m0 + 1) & (C::nx - 1);  // periodic in kx
+      const float2 p00 = P[(size_t)ia * C::nx + ma], p01 = P[(size_t)ia * C::nx + mb];
+      const float2 p10 = P[(size_t)ib * C::nx + ma], p11 = P[(size_t)ib * C::nx + mb];
+      const float jac = ok ? kzr * __builtin_amdgcn_rcpf(den.hi) : 0.f;
+      const float hw = (ok && i0 + 1 <= kbins - 1) ? wu : 0.f;  // zeros past the last bin
+      const float w00 = (1.f - wm) * (1.f - wu) * jac, w01 = wm * (1.f - wu) * jac;
+      const float w10 = (1.f - wm) * hw * jac, w11 = wm * hw * jac;
+      x[r * stride + fft::pad(m)] =
+          make_float2(w00 * p00.x + w01 * p01.x + w10 * p10.x + w11 * p11.x,
+                      w00 * p00.y + w01 * p01.y + w10 * p10.y + w11 * p11.y);
+    }
+  }
 }
 
 template <int L, int METHOD>
@@ -196,15 +275,10 @@ __global__ void __launch_bounds__(kPostThreads) k_fk_remap(FkPlan F) {
   const FkAngleConst &A = F.ang[a];
   fft::twiddles(tw, nx);
   const float2 *P = F.P + (size_t)a * kbins * nx;
-#pragma unroll 4
-  for (int t = threadIdx.x; t < nx * ROWS; t += kPostThreads) {
-    const int r = t >> L, m = t & (nx - 1), j = j0 + r;
-    // rows past the last bin compute row kbins - 1 and store zero
-    const int jc = min(j, kbins - 1);
-    const float2 v = METHOD == kFkLu ? lu_value(A, P, jc, m, nx, kbins)
-                                     : stolt_value(A, P, jc, m, nx, kbins);
-    x[r * stride + fft::pad(m)] = j < kbins ? v : make_float2(0.f, 0.f);
-  }
+  if (METHOD == kFkLu)
+    lu_rows<L>(A, P, j0, kbins, x);
+  else
+    stolt_rows<L>(A, P, j0, kbins, x);
   __syncthreads();
   fft::transform<L, true, ROWS>(x, tw);
   // the window's columns, transposed: consecutive threads take consecutive rows
