@@ -14,11 +14,12 @@
 //
 // LDS positions are padded by one element every 16 (pad(i) = i + i / 16): the
 // first pass writes with a stride of 16 elements, which would otherwise put all
-// lanes of a wave on the same bank. Twiddles come from a half table
-// tw[k] = exp(-2 pi i k / n), k < n / 2 (W^{k + n/2} = -W^k), padded the same
-// way: later passes read it at strides of 16 entries and more. The inverse
-// transform (no 1/n) swaps real and imaginary parts around the forward DFT
-// and conjugates the twiddles.
+// lanes of a wave on the same bank. Twiddles come from one table of
+// W_4096^i = exp(-2 pi i i / 4096), i < 2048 (W^{i + 2048} = -W^i), built at
+// compile time and read through the vector cache: a butterfly reads w, w^2,
+// w^4 and w^8 and forms the other powers with at most two products. The
+// inverse transform (no 1/n) swaps real and imaginary parts around the
+// forward DFT, which conjugates the twiddles.
 #include <hip/hip_runtime.h>
 
 namespace pwbf {
@@ -29,9 +30,72 @@ constexpr int kThreads = 256;
 __host__ __device__ constexpr int pad(int i) { return i + (i >> 4); }
 __host__ __device__ constexpr int padded(int n) { return n + (n >> 4); }
 
-// LDS bytes of `rows` padded rows of n points plus the padded half twiddle table
+// LDS bytes of `rows` padded rows of n points
 __host__ __device__ constexpr size_t lds_bytes(int n, int rows) {
-  return ((size_t)padded(n) * rows + (size_t)padded(n / 2 > 0 ? n / 2 : 1)) * 8;
+  return (size_t)padded(n) * rows * 8;
+}
+
+// Compile-time cos and sin of 2 pi k / n: a double-precision Taylor series on
+// [0, pi / 4] after reduction by the quadrant and octant symmetries, rounded
+// once to float (the table matches correctly rounded values to within one
+// float rounding of a tie).
+namespace detail {
+constexpr double kTwoPi = 6.28318530717958647692528676655900577;
+constexpr double sin_series(double x) {
+  double t = x, s = x;
+  for (int i = 1; i < 13; ++i) {
+    t *= -x * x / ((2.0 * i) * (2.0 * i + 1.0));
+    s += t;
+  }
+  return s;
+}
+constexpr double cos_series(double x) {
+  double t = 1.0, s = 1.0;
+  for (int i = 1; i < 13; ++i) {
+    t *= -x * x / ((2.0 * i - 1.0) * (2.0 * i));
+    s += t;
+  }
+  return s;
+}
+struct Tw {
+  float c, s;
+};
+constexpr Tw w_of(int k, int n) {  // exp(-2 pi i k / n), 0 <= k < n, 8 | n
+  const int q4 = n / 4, q = k / q4, kr = k % q4;
+  double cr = 0.0, sr = 0.0;
+  if (2 * kr <= q4) {
+    const double x = kTwoPi * kr / n;
+    cr = cos_series(x);
+    sr = sin_series(x);
+  } else {
+    const double x = kTwoPi * (q4 - kr) / n;
+    cr = sin_series(x);
+    sr = cos_series(x);
+  }
+  double c = 0.0, s = 0.0;
+  switch (q) {
+    case 0: c = cr; s = sr; break;
+    case 1: c = -sr; s = cr; break;
+    case 2: c = -cr; s = -sr; break;
+    default: c = sr; s = -cr; break;
+  }
+  return {(float)c, (float)-s};
+}
+constexpr int kTwN = 4096;  // the largest transform
+struct alignas(8) TwTable {
+  Tw v[kTwN / 2];
+  constexpr TwTable() : v() {
+    for (int k = 0; k < kTwN / 2; ++k) v[k] = w_of(k, kTwN);
+  }
+};
+}  // namespace detail
+
+__device__ const detail::TwTable kTwTable = detail::TwTable();
+
+// W_4096^i for 0 <= i < 4096
+__device__ __forceinline__ float2 w4096(int i) {
+  const detail::Tw t = kTwTable.v[i & (detail::kTwN / 2 - 1)];
+  return i < detail::kTwN / 2 ? make_float2(t.c, t.s) : make_float2(-t.c, -t.s);
 }
 
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
@@ -42,22 +106,6 @@ __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
 // -i z and the swap of real and imaginary parts
 __device__ __forceinline__ float2 mul_mi(float2 z) { return make_float2(z.y, -z.x); }
 __device__ __forceinline__ float2 swap(float2 z) { return make_float2(z.y, z.x); }
-
-// tw[k] = exp(-2 pi i k / n) for k < n / 2, filled by the whole block
-__device__ __forceinline__ void twiddles(float2 *tw, int n) {
-  for (int k = threadIdx.x; k < (n >> 1); k += kThreads) {
-    float s, c;
-    sincospif(-2.0f * (float)k / (float)n, &s, &c);
-    tw[pad(k)] = make_float2(c, s);
-  }
-}
-
-// W_n^idx for 0 <= idx < n from the half table
-__device__ __forceinline__ float2 twiddle(const float2 *tw, int idx, int n) {
-  const int h = n >> 1;
-  const float2 w = idx < h ? tw[pad(idx)] : tw[pad(idx - h)];
-  return idx < h ? w : make_float2(-w.x, -w.y);
-}
 
 // forward DFTs of 2, 4, 8 and 16 points in registers (radix-2 splits into even
 // and odd halves; the twiddles of 8 and 16 points are cos and sin of multiples
@@ -135,11 +183,35 @@ __device__ __forceinline__ void dft<16>(float2 (&v)[16]) {
   }
 }
 
+// w^r, r = 1 .. R - 1, for w = W_4096^b: w, w^2, w^4, w^8 from the table, the
+// other powers as products of at most two of those
+template <int R>
+__device__ __forceinline__ void powers(int b, float2 (&t)[R]) {
+  t[1] = w4096(b);
+  if constexpr (R >= 4) {
+    t[2] = w4096(2 * b);
+    t[3] = cmul(t[2], t[1]);
+  }
+  if constexpr (R >= 8) {
+    t[4] = w4096(4 * b);
+    t[5] = cmul(t[4], t[1]);
+    t[6] = cmul(t[4], t[2]);
+    t[7] = cmul(t[4], t[3]);
+  }
+  if constexpr (R >= 16) {
+    t[8] = w4096(8 * b);
+#pragma unroll
+    for (int r = 9; r < 16; ++r) t[r] = cmul(t[8], t[r - 8]);
+  }
+}
+
 template <int R, int NS, int L, bool INV, int ROWS>
-__device__ __forceinline__ void pass(float2 *x, const float2 *tw) {
+__device__ __forceinline__ void pass(float2 *x) {
   constexpr int n = 1 << L, nr = n / R, total = nr * ROWS;
   constexpr int K = (total + kThreads - 1) / kThreads;  // butterflies per thread
-  constexpr int stride = padded(n), twstep = n / (NS * R);
+  static_assert(n <= detail::kTwN, "transforms up to 4096 points");
+  // twiddle W_{NS R}^{k r} = W_4096^{k r tw4096}
+  constexpr int stride = padded(n), tw4096 = detail::kTwN / (NS * R);
   float2 v[K][R];
 #pragma unroll
   for (int q = 0; q < K; ++q) {
@@ -153,10 +225,12 @@ __device__ __forceinline__ void pass(float2 *x, const float2 *tw) {
         v[q][r] = INV ? swap(a) : a;
       }
       if constexpr (NS > 1) {
+        float2 t[R];
+        powers<R>(k * tw4096, t);
 #pragma unroll
         for (int r = 1; r < R; ++r)
           // inverse: swap(z conj(w)) = swap(z) w, so the swapped values take w itself
-          v[q][r] = cmul(v[q][r], twiddle(tw, k * r * twstep, n));
+          v[q][r] = cmul(v[q][r], t[r]);
       }
       dft<R>(v[q]);
     }
@@ -177,38 +251,38 @@ __device__ __forceinline__ void pass(float2 *x, const float2 *tw) {
 }
 
 template <int L, int DONE, bool INV, int ROWS>
-__device__ __forceinline__ void passes(float2 *x, const float2 *tw) {
+__device__ __forceinline__ void passes(float2 *x) {
   if constexpr (DONE < L) {
     constexpr int RB = (L - DONE) >= 4 ? 4 : (L - DONE);
-    pass<1 << RB, 1 << DONE, L, INV, ROWS>(x, tw);
-    passes<L, DONE + RB, INV, ROWS>(x, tw);
+    pass<1 << RB, 1 << DONE, L, INV, ROWS>(x);
+    passes<L, DONE + RB, INV, ROWS>(x);
   }
 }
 
-// In-place transform of ROWS rows of 2^L points at x (padded layout), twiddles
-// for n = 2^L at tw. Starts and ends with a barrier-consistent LDS state:
-// callers write x (and tw) and __syncthreads() before, read after.
+// In-place transform of ROWS rows of 2^L points at x (padded layout). Starts
+// and ends with a barrier-consistent LDS state: callers write x and
+// __syncthreads() before, read after.
 template <int L, bool INV, int ROWS = 1>
-__device__ __forceinline__ void transform(float2 *x, const float2 *tw) {
-  passes<L, 0, INV, ROWS>(x, tw);
+__device__ __forceinline__ void transform(float2 *x) {
+  passes<L, 0, INV, ROWS>(x);
 }
 
 // One row, L known only at run time (uniform over the block), 1 <= L <= 12.
 template <bool INV>
-__device__ __forceinline__ void transform_any(float2 *x, const float2 *tw, int L) {
+__device__ __forceinline__ void transform_any(float2 *x, int L) {
   switch (L) {
-    case 1: transform<1, INV>(x, tw); break;
-    case 2: transform<2, INV>(x, tw); break;
-    case 3: transform<3, INV>(x, tw); break;
-    case 4: transform<4, INV>(x, tw); break;
-    case 5: transform<5, INV>(x, tw); break;
-    case 6: transform<6, INV>(x, tw); break;
-    case 7: transform<7, INV>(x, tw); break;
-    case 8: transform<8, INV>(x, tw); break;
-    case 9: transform<9, INV>(x, tw); break;
-    case 10: transform<10, INV>(x, tw); break;
-    case 11: transform<11, INV>(x, tw); break;
-    default: transform<12, INV>(x, tw); break;
+    case 1: transform<1, INV>(x); break;
+    case 2: transform<2, INV>(x); break;
+    case 3: transform<3, INV>(x); break;
+    case 4: transform<4, INV>(x); break;
+    case 5: transform<5, INV>(x); break;
+    case 6: transform<6, INV>(x); break;
+    case 7: transform<7, INV>(x); break;
+    case 8: transform<8, INV>(x); break;
+    case 9: transform<9, INV>(x); break;
+    case 10: transform<10, INV>(x); break;
+    case 11: transform<11, INV>(x); break;
+    default: transform<12, INV>(x); break;
   }
 }
 

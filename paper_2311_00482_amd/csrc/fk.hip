@@ -93,20 +93,25 @@ template <int DT>
 __global__ void __launch_bounds__(kPostThreads) k_fk_time(FkPlan F) {
   extern __shared__ __align__(16) float2 sm[];
   const int nt = 1 << F.log2nt, kbins = kbins_of(F), e = blockIdx.x, a = blockIdx.y;
-  float2 *x = sm, *tw = sm + fft::padded(nt);
-  fft::twiddles(tw, nt);
+  float2 *x = sm;
   const size_t base = ((size_t)a * F.n_ch + e) * nt;
   for (int k = threadIdx.x; k < nt; k += kPostThreads)
     x[fft::pad(k)] = make_float2(trace_sample<DT>(F.rf, base + k), 0.f);
   __syncthreads();
-  fft::transform_any<false>(x, tw, F.log2nt);
+  fft::transform_any<false>(x, F.log2nt);
   const FkAngleConst &A = F.ang[a];
   const ff c = dev::ff_add({A.c0_hi, A.c0_lo}, dev::ff_mul(ffi(e), {A.c1_hi, A.c1_lo}));
   float2 *T = F.T + ((size_t)a * F.n_ch + e) * kbins;
+  // exp(2 pi i k c) at the thread's first bin, then by the step of kPostThreads
+  // bins: a thread's bins are at most 9 products from an accurate phase
+  float sn, cs;
+  sincospif(2.0f * frac_revs(threadIdx.x, c), &sn, &cs);
+  float2 ph = make_float2(cs, sn);
+  sincospif(2.0f * frac_revs(kPostThreads, c), &sn, &cs);
+  const float2 step = make_float2(cs, sn);
   for (int k = threadIdx.x; k < kbins; k += kPostThreads) {
-    float sn, cs;
-    sincospif(2.0f * frac_revs(k, c), &sn, &cs);
-    T[k] = dev::cmul(x[fft::pad(k)], make_float2(cs, sn));
+    T[k] = dev::cmul(x[fft::pad(k)], ph);
+    ph = dev::cmul(ph, step);
   }
 }
 
@@ -114,9 +119,8 @@ template <int L>
 __global__ void __launch_bounds__(kPostThreads) k_fk_space(FkPlan F) {
   constexpr int nx = 1 << L, ROWS = kFkRowPoints >> L, stride = fft::padded(nx);
   extern __shared__ __align__(16) float2 sm[];
-  float2 *x = sm, *tw = sm + ROWS * stride;
+  float2 *x = sm;
   const int kbins = kbins_of(F), k0 = blockIdx.x * ROWS, a = blockIdx.y;
-  fft::twiddles(tw, nx);
   const float2 *T = F.T + (size_t)a * F.n_ch * kbins;
   // consecutive threads take consecutive bins of one channel
   for (int t = threadIdx.x; t < nx * ROWS; t += kPostThreads) {
@@ -125,7 +129,7 @@ __global__ void __launch_bounds__(kPostThreads) k_fk_space(FkPlan F) {
         (e < F.n_ch && k < kbins) ? T[(size_t)e * kbins + k] : make_float2(0.f, 0.f);
   }
   __syncthreads();
-  fft::transform<L, false, ROWS>(x, tw);
+  fft::transform<L, false, ROWS>(x);
   float2 *P = F.P + (size_t)a * kbins * nx;
   for (int t = threadIdx.x; t < nx * ROWS; t += kPostThreads) {
     const int r = t >> L, m = t & (nx - 1), k = k0 + r;
@@ -270,17 +274,16 @@ template <int L, int METHOD>
 __global__ void __launch_bounds__(kPostThreads) k_fk_remap(FkPlan F) {
   constexpr int nx = 1 << L, ROWS = kFkRowPoints >> L, stride = fft::padded(nx);
   extern __shared__ __align__(16) float2 sm[];
-  float2 *x = sm, *tw = sm + ROWS * stride;
+  float2 *x = sm;
   const int kbins = kbins_of(F), j0 = blockIdx.x * ROWS, a = blockIdx.y;
   const FkAngleConst &A = F.ang[a];
-  fft::twiddles(tw, nx);
   const float2 *P = F.P + (size_t)a * kbins * nx;
   if (METHOD == kFkLu)
     lu_rows<L>(A, P, j0, kbins, x);
   else
     stolt_rows<L>(A, P, j0, kbins, x);
   __syncthreads();
-  fft::transform<L, true, ROWS>(x, tw);
+  fft::transform<L, true, ROWS>(x);
   // the window's columns, transposed: consecutive threads take consecutive rows
   float2 *U = F.U + (size_t)a * nx * kbins;
   for (int t = threadIdx.x; t < A.ncol * ROWS; t += kPostThreads) {
@@ -296,13 +299,12 @@ __global__ void __launch_bounds__(kPostThreads) k_fk_itime(FkPlan F) {
   if ((int)blockIdx.x >= A.ncol) return;  // the whole block: outside this angle's window
   const int nt = 1 << F.log2nt, nx = 1 << F.log2nx, kbins = kbins_of(F);
   const int col = A.col0 + blockIdx.x;
-  float2 *x = sm, *tw = sm + fft::padded(nt);
-  fft::twiddles(tw, nt);
+  float2 *x = sm;
   const float2 *I = F.U + ((size_t)a * nx + col) * kbins;
   for (int j = threadIdx.x; j < nt; j += kPostThreads)
     x[fft::pad(j)] = j < kbins ? I[j] : make_float2(0.f, 0.f);
   __syncthreads();
-  fft::transform_any<true>(x, tw, F.log2nt);
+  fft::transform_any<true>(x, F.log2nt);
   const float scale = 1.0f / ((float)nx * (float)nt);
   float2 *out = F.M + ((size_t)a * nx + col) * nt;
   for (int l = A.row0 + threadIdx.x; l < A.row0 + A.nrow; l += kPostThreads) {

@@ -31,13 +31,12 @@ __global__ void __launch_bounds__(kPostThreads)
                float r_lo) {
   extern __shared__ __align__(16) float2 sm[];
   const int ns = 1 << log2ns;
-  float2 *x = sm, *tw = sm + fft::padded(ns);
+  float2 *x = sm;
   const size_t base = (size_t)blockIdx.x * ns;
-  fft::twiddles(tw, ns);
   for (int k = threadIdx.x; k < ns; k += kPostThreads)
     x[fft::pad(k)] = make_float2(rf_sample<DT>(rf, base + k), 0.f);
   __syncthreads();
-  fft::transform_any<false>(x, tw, log2ns);
+  fft::transform_any<false>(x, log2ns);
   const float inv_n = 1.0f / (float)ns;
   for (int k = threadIdx.x; k < ns; k += kPostThreads) {
     const float h = dev::analytic_weight(k, ns) * inv_n;
@@ -45,7 +44,7 @@ __global__ void __launch_bounds__(kPostThreads)
     x[fft::pad(k)] = make_float2(v.x * h, v.y * h);
   }
   __syncthreads();
-  fft::transform_any<true>(x, tw, log2ns);
+  fft::transform_any<true>(x, log2ns);
   for (int k = threadIdx.x; k < ns; k += kPostThreads) {
     const float2 z = x[fft::pad(k)];
     const float fk = (float)k;

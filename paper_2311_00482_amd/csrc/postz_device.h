@@ -13,7 +13,7 @@ namespace dev {
 constexpr int kPostThreads = 256;
 static_assert(kPostThreads == fft::kThreads, "post-processing blocks run the block FFT");
 
-// LDS of one post-processing block: the padded column and the half twiddle table
+// LDS of one post-processing block: the padded column
 __host__ __device__ constexpr size_t post_lds_bytes(int nz) { return fft::lds_bytes(nz, 1); }
 
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
@@ -31,15 +31,13 @@ __device__ __forceinline__ float analytic_weight(int k, int n) {
 // (post_lds_bytes(nz)).
 __device__ __forceinline__ void postz_column(const PostPlan &Q, int ix, float2 *sm) {
   const int nz = Q.nz, L = Q.log2nz, half_n = nz >> 1;
-  float2 *x = sm;                       // the column, padded layout
-  float2 *tw = sm + fft::padded(nz);    // W^k = exp(-2 pi i k / nz), k < nz / 2
+  float2 *x = sm;  // the column, padded layout
   const int tid = threadIdx.x;
   const float *src = Q.src + (size_t)ix * nz;
 
-  fft::twiddles(tw, nz);
   for (int k = tid; k < nz; k += kPostThreads) x[fft::pad(k)] = make_float2(src[k], 0.f);
   __syncthreads();
-  fft::transform_any<false>(x, tw, L);
+  fft::transform_any<false>(x, L);
 
   // analytic-signal weights, band mask, and the 1/nz of the inverse
   const float inv_n = 1.0f / (float)nz;
@@ -53,7 +51,7 @@ __device__ __forceinline__ void postz_column(const PostPlan &Q, int ix, float2 *
     x[fft::pad(k)] = make_float2(v.x * h * inv_n, v.y * h * inv_n);
   }
   __syncthreads();
-  fft::transform_any<true>(x, tw, L);
+  fft::transform_any<true>(x, L);
 
   float m = 0.f;
   for (int k = tid; k < nz; k += kPostThreads) {
