@@ -30,9 +30,16 @@ constexpr int kThreads = 256;
 __host__ __device__ constexpr int pad(int i) { return i + (i >> 4); }
 __host__ __device__ constexpr int padded(int n) { return n + (n >> 4); }
 
-// LDS bytes of `rows` padded rows of n points
+// Distance between the rows of a multi-row block: one element more than the
+// padded row, so that the same position of consecutive rows falls on different
+// banks (transposing loads and stores walk down the rows)
+__host__ __device__ constexpr int row_stride(int n, int rows) {
+  return rows > 1 ? padded(n) + 1 : padded(n);
+}
+
+// LDS bytes of `rows` rows of n points
 __host__ __device__ constexpr size_t lds_bytes(int n, int rows) {
-  return (size_t)padded(n) * rows * 8;
+  return (size_t)row_stride(n, rows) * rows * 8;
 }
 
 // Compile-time cos and sin of 2 pi k / n: a double-precision Taylor series on
@@ -211,7 +218,7 @@ __device__ __forceinline__ void pass(float2 *x) {
   constexpr int K = (total + kThreads - 1) / kThreads;  // butterflies per thread
   static_assert(n <= detail::kTwN, "transforms up to 4096 points");
   // twiddle W_{NS R}^{k r} = W_4096^{k r tw4096}
-  constexpr int stride = padded(n), tw4096 = detail::kTwN / (NS * R);
+  constexpr int stride = row_stride(n, ROWS), tw4096 = detail::kTwN / (NS * R);
   float2 v[K][R];
 #pragma unroll
   for (int q = 0; q < K; ++q) {
@@ -259,7 +266,8 @@ __device__ __forceinline__ void passes(float2 *x) {
   }
 }
 
-// In-place transform of ROWS rows of 2^L points at x (padded layout). Starts
+// In-place transform of ROWS rows of 2^L points at x (padded layout, rows
+// row_stride(2^L, ROWS) apart). Starts
 // and ends with a barrier-consistent LDS state: callers write x and
 // __syncthreads() before, read after.
 template <int L, bool INV, int ROWS = 1>

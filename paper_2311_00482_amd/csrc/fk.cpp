@@ -95,7 +95,7 @@ size_t round256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 // workspace: [max slots | T | P | U | M | envelope scratch], complex float32 for
 // the A angles of the call: T [A][N][Nt/2 + 1], P [A][Nt/2 + 1][Nx],
-// U [A][Nx][Nt/2 + 1], M [A][Nx][Nt]
+// U [A][Nx][Nt/2 + 1], M [A][Nx][Nt] (P is [A][Nx][Nt/2 + 1] for Stolt's method)
 struct FkLayout {
   size_t T, P, U, M, env, total;
 };

@@ -40,7 +40,7 @@ struct FkPlan {
   int n_ang, n_ch, log2nt, log2nx;
   int nx_img, nz_img;
   float2 *T;  // [n_ang][n_ch][Nt/2 + 1]: shifted temporal spectra
-  float2 *P;  // [n_ang][Nt/2 + 1][Nx]: 2-D data spectra
+  float2 *P;  // [n_ang][Nt/2 + 1][Nx] (Lu) or [n_ang][Nx][Nt/2 + 1] (Stolt): 2-D data spectra
   float2 *U;  // [n_ang][Nx][Nt/2 + 1]: remapped spectra after the inverse along kx
   float2 *M;  // [n_ang][Nx][Nt]: migrated complex images on (x1, z1), window only
   float *out_rf, *out_imag, *out_env;  // image planes [nx_img][nz_img]

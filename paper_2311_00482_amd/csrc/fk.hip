@@ -10,6 +10,7 @@
 //                 element's firing delay and shifted to t = 0) go to T[e][k]
 //  k_fk_space     block per (ROWS bins, angle): reads T[e][k0..k0+ROWS) for every
 //                 channel, FFTs along the array zero-padded to Nx, writes P[k][m]
+//                 (Lu) or P[m][k] (Stolt, whose remap reads along frequency)
 //  k_fk_remap     block per (ROWS image rows kz_j, angle): each cell (j, m) takes
 //                 the data spectrum from P -
 //                   Stolt: at bin u = sqrt((alpha m')^2 + j^2) (m' the signed
@@ -115,9 +116,9 @@ __global__ void __launch_bounds__(kPostThreads) k_fk_time(FkPlan F) {
   }
 }
 
-template <int L>
+template <int L, int METHOD>
 __global__ void __launch_bounds__(kPostThreads) k_fk_space(FkPlan F) {
-  constexpr int nx = 1 << L, ROWS = kFkRowPoints >> L, stride = fft::padded(nx);
+  constexpr int nx = 1 << L, ROWS = kFkRowPoints >> L, stride = fft::row_stride(nx, ROWS);
   extern __shared__ __align__(16) float2 sm[];
   float2 *x = sm;
   const int kbins = kbins_of(F), k0 = blockIdx.x * ROWS, a = blockIdx.y;
@@ -131,9 +132,18 @@ __global__ void __launch_bounds__(kPostThreads) k_fk_space(FkPlan F) {
   __syncthreads();
   fft::transform<L, false, ROWS>(x);
   float2 *P = F.P + (size_t)a * kbins * nx;
-  for (int t = threadIdx.x; t < nx * ROWS; t += kPostThreads) {
-    const int r = t >> L, m = t & (nx - 1), k = k0 + r;
-    if (k < kbins) P[(size_t)k * nx + m] = x[r * stride + fft::pad(m)];
+  if (METHOD == kFkStolt) {
+    // Stolt's remap reads along frequency at fixed kx: store P[m][k], consecutive
+    // threads on consecutive bins
+    for (int t = threadIdx.x; t < nx * ROWS; t += kPostThreads) {
+      const int m = t / ROWS, r = t - m * ROWS, k = k0 + r;
+      if (k < kbins) P[(size_t)m * kbins + k] = x[r * stride + fft::pad(m)];
+    }
+  } else {
+    for (int t = threadIdx.x; t < nx * ROWS; t += kPostThreads) {
+      const int r = t >> L, m = t & (nx - 1), k = k0 + r;
+      if (k < kbins) P[(size_t)k * nx + m] = x[r * stride + fft::pad(m)];
+    }
   }
 }
 
@@ -184,35 +194,37 @@ struct RemapCells {
 };
 
 // Stolt's remap of the block's rows: the cell (j, m) takes the data spectrum at
-// bin u = sqrt((alpha m')^2 + j^2), linearly (zeros past the last bin), times j / u.
+// bin u = sqrt((alpha m')^2 + j^2), linearly (zeros past the last bin), times
+// j / u. P is stored [m][k]; consecutive threads take consecutive rows j of one
+// column, so their bins u are close and the gathers contiguous.
 template <int L>
 __device__ __forceinline__ void stolt_rows(const FkAngleConst &A, const float2 *__restrict__ P,
                                            int j0, int kbins, float2 *x) {
 #pragma clang fp contract(off)
-  using C = RemapCells<L>;
-  constexpr int stride = fft::padded(C::nx);
-  for (int mi = 0; mi < C::MPT; ++mi) {
-    const int m = C::m(mi), ms = m < C::nx / 2 ? m : m - C::nx;
-    const ff am = dev::ff_mul(ffi(ms), {A.m0_hi, A.m0_lo});
-    const ff am2 = dev::ff_mul(am, am);  // (alpha m')^2, per column
+  constexpr int nx = 1 << L, ROWS = kFkRowPoints >> L, LR = 12 - L;
+  constexpr int stride = fft::row_stride(nx, ROWS);
+  static_assert((1 << LR) == ROWS, "rows of a block");
 #pragma unroll 4
-    for (int r = C::r0(); r < C::ROWS; r += C::RSTEP) {
-      const int j = min(j0 + r, kbins - 1);  // rows past the last bin store zero below
-      const float fj = (float)j;
-      const ff u2 = dev::two_sum(am2.hi, fj * fj);  // j^2 < 2^24 is exact
-      const ff u2n = dev::two_sum(u2.hi, u2.lo + am2.lo);
-      const bool in_band = u2n.hi > 0.f && u2n.hi < (float)(kbins + 1) * (float)(kbins + 1);
-      const ff u = ff_sqrt_hw(in_band ? u2n : ff{1.f, 0.f});
-      float w;
-      const int i0 = split_index(u, &w);
-      // clamped loads, always issued; taps outside the spectrum weigh zero
-      const bool ok = in_band && i0 >= 0 && i0 <= kbins - 1 && j0 + r < kbins;
-      const int ia = ok ? i0 : 0, ib = min(ia + 1, kbins - 1);
-      const float2 lo = P[(size_t)ia * C::nx + m], hi = P[(size_t)ib * C::nx + m];
-      const float jac = ok ? fj * __builtin_amdgcn_rcpf(u.hi) : 0.f;
-      const float wl = (1.f - w) * jac, wh = (ok && i0 + 1 <= kbins - 1) ? w * jac : 0.f;
-      x[r * stride + fft::pad(m)] = make_float2(wl * lo.x + wh * hi.x, wl * lo.y + wh * hi.y);
-    }
+  for (int t = threadIdx.x; t < kFkRowPoints; t += kPostThreads) {
+    const int r = t & (ROWS - 1), m = t >> LR, ms = m < nx / 2 ? m : m - nx;
+    const int j = min(j0 + r, kbins - 1);  // rows past the last bin store zero below
+    const float fj = (float)j;
+    const ff am = dev::ff_mul(ffi(ms), {A.m0_hi, A.m0_lo});
+    const ff am2 = dev::ff_mul(am, am);  // (alpha m')^2
+    const ff u2 = dev::two_sum(am2.hi, fj * fj);  // j^2 < 2^24 is exact
+    const ff u2n = dev::two_sum(u2.hi, u2.lo + am2.lo);
+    const bool in_band = u2n.hi > 0.f && u2n.hi < (float)(kbins + 1) * (float)(kbins + 1);
+    const ff u = ff_sqrt_hw(in_band ? u2n : ff{1.f, 0.f});
+    float w;
+    const int i0 = split_index(u, &w);
+    // clamped loads, always issued; taps outside the spectrum weigh zero
+    const bool ok = in_band && i0 >= 0 && i0 <= kbins - 1 && j0 + r < kbins;
+    const int ia = ok ? i0 : 0, ib = min(ia + 1, kbins - 1);
+    const float2 *col = P + (size_t)m * kbins;
+    const float2 lo = col[ia], hi = col[ib];
+    const float jac = ok ? fj * __builtin_amdgcn_rcpf(u.hi) : 0.f;
+    const float wl = (1.f - w) * jac, wh = (ok && i0 + 1 <= kbins - 1) ? w * jac : 0.f;
+    x[r * stride + fft::pad(m)] = make_float2(wl * lo.x + wh * hi.x, wl * lo.y + wh * hi.y);
   }
 }
 
@@ -227,7 +239,7 @@ __device__ __forceinline__ void lu_rows(const FkAngleConst &A, const float2 *__r
                                         int j0, int kbins, float2 *x) {
 #pragma clang fp contract(off)
   using C = RemapCells<L>;
-  constexpr int stride = fft::padded(C::nx);
+  constexpr int stride = fft::row_stride(C::nx, C::ROWS);
   const float ch = 0.5f * A.m2_hi, cl = 0.5f * A.m2_lo;  // cos / 2
   for (int mi = 0; mi < C::MPT; ++mi) {
     const int m = C::m(mi), ms = m < C::nx / 2 ? m : m - C::nx;
@@ -272,7 +284,7 @@ __device__ __forceinline__ void lu_rows(const FkAngleConst &A, const float2 *__r
 
 template <int L, int METHOD>
 __global__ void __launch_bounds__(kPostThreads) k_fk_remap(FkPlan F) {
-  constexpr int nx = 1 << L, ROWS = kFkRowPoints >> L, stride = fft::padded(nx);
+  constexpr int nx = 1 << L, ROWS = kFkRowPoints >> L, stride = fft::row_stride(nx, ROWS);
   extern __shared__ __align__(16) float2 sm[];
   float2 *x = sm;
   const int kbins = kbins_of(F), j0 = blockIdx.x * ROWS, a = blockIdx.y;
@@ -416,13 +428,17 @@ hipError_t launch_rows(const FkPlan &F, hipStream_t s) {
   const int kbins = (1 << F.log2nt) / 2 + 1;
   const dim3 grid((kbins + ROWS - 1) / ROWS, F.n_ang), blk(kPostThreads);
   const size_t lds = fft::lds_bytes(1 << L, ROWS);
-  hipLaunchKernelGGL(k_fk_space<L>, grid, blk, lds, s, F);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  if (F.method == kFkLu)
+  if (F.method == kFkLu) {
+    hipLaunchKernelGGL((k_fk_space<L, kFkLu>), grid, blk, lds, s, F);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_fk_remap<L, kFkLu>), grid, blk, lds, s, F);
-  else
+  } else {
+    hipLaunchKernelGGL((k_fk_space<L, kFkStolt>), grid, blk, lds, s, F);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_fk_remap<L, kFkStolt>), grid, blk, lds, s, F);
+  }
   return hipGetLastError();
 }
 
