@@ -507,7 +507,7 @@ def main():
     ap.add_argument("--no-modes", action="store_true",
                     help="skip the DMAS and pDAS measurements")
     ap.add_argument("--profile-mode", default="das",
-                    choices=("das", "pdas", "dmas", "iqdas", "bbdmas", "fk", "fklu"),
+                    choices=("das", "pdas", "dmas", "iqdas", "bbdmas", "fk", "fklu", "batch"),
                     help="with --profile-only: the beamformer of the timed loop (dmas and "
                          "pdas run on the 128-channel 512 x 512 DMAS workload, pdas also "
                          "takes the compound workload with --profile-compound)")
@@ -563,6 +563,19 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    if args.profile_only and args.profile_mode == "batch":
+        from paper_2311_00482_amd import Batch, FrameSpec
+        i16 = torch.from_numpy(fr["i16"]) if "i16" in fr else rf32.cpu().round().to(torch.int16)
+        wantb = ("rf", "env", "log")
+        frames = [FrameSpec(g, torch.roll(i16, 17 * k, dims=2).to(torch.float16).to(dev), "das",
+                            -1, {k2: torch.empty((g.nx, g.nz), dtype=torch.float32, device=dev)
+                                 for k2 in wantb}) for k in range(8)]
+        batch = Batch(frames)
+        wall, _, _ = time_steps(batch.launch, args.steps, args.warmup, torch)
+        batch.close()
+        print(json.dumps({"profile_only": True, "mode": "batch", "frames_per_launch": 8,
+                          "ms_per_step": wall / args.steps * 1e3}))
+        return
     if args.profile_only and args.profile_mode in ("fk", "fklu"):
         from paper_2311_00482_amd import fk_migrate, fk_workspace_bytes
         meth = "lu" if args.profile_mode == "fklu" else "stolt"

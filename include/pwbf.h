@@ -384,11 +384,12 @@ typedef struct pwbf_batch_info {
   int32_t n_frames;
   int32_t n_items;          /* (frame, tile) work items */
   int32_t n_columns;        /* depth columns post-processed */
-  int32_t blocks;           /* persistent blocks launched */
-  int32_t blocks_per_cu;
-  int32_t lds_bytes;        /* LDS per block of the persistent kernel */
+  int32_t blocks;           /* persistent blocks launched, summed over the kernels */
+  int32_t blocks_per_cu;    /* the smallest occupancy among the kernels */
+  int32_t lds_bytes;        /* LDS per block of the persistent kernels */
   int32_t graph_nodes;
-  int32_t reserved;
+  int32_t kernels;          /* persistent beamform kernels: one per class of frames
+                               (beamformer, lane grouping, angle count 1/5/11/other) */
 } pwbf_batch_info;
 
 /* Build a batch of n >= 1 frames; *out receives the handle. flags: 0 or

@@ -69,7 +69,7 @@ class Frame(ctypes.Structure):
 class BatchInfo(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in ("n_frames", "n_items", "n_columns", "blocks",
                                                "blocks_per_cu", "lds_bytes", "graph_nodes",
-                                               "reserved")]
+                                               "kernels")]
 
 
 BATCH_TUNE = 1

@@ -9,17 +9,11 @@
 #include <vector>
 
 #include "../../include/pwbf.h"
+#include "batch.h"
 #include "plan_host.h"
 
 namespace pwbf {
 hipError_t launch_beamform(const FramePlan &P, hipStream_t stream);
-hipError_t launch_batch(const FramePlan *plans, const PostPlan *post, const int2 *items,
-                        int n_items, const int2 *post_cols, int n_post_cols,
-                        const int2 *log_cols, int n_log_cols, int n_frames, int *counter,
-                        int blocks, size_t lds, int max_nz, hipStream_t stream);
-hipError_t batch_occupancy(size_t lds_bytes, int *blocks_per_cu);
-int batch_waves();
-int batch_max_angles();
 int api_set_error(int code, const std::string &msg);
 void api_clear_error();
 }  // namespace pwbf
@@ -34,7 +28,8 @@ struct pwbf_batch {
   pwbf::FramePlan *d_plans = nullptr;
   pwbf::PostPlan *d_post = nullptr;
   int2 *d_items = nullptr, *d_post_cols = nullptr, *d_log_cols = nullptr;
-  int *d_counter = nullptr;
+  int *d_counter = nullptr;  // one work counter per class
+  std::vector<pwbf::BatchClass> classes;
   unsigned char *d_ws = nullptr;  // per-frame workspaces (envelope maximum, envelope plane)
   std::vector<size_t> ws_off;
   void *h_stage = nullptr;  // pinned staging of the descriptor tables for updates
@@ -289,10 +284,23 @@ int pwbf_batch_create(const pwbf_frame *frames, int32_t n, int32_t flags, void *
         for (int ix = 0; ix < f.geom->nx; ++ix) log_cols.push_back(make_int2(i, ix));
     }
   }
-  // longest tiles first over the whole batch, so the cheap ones fill the tail
-  std::stable_sort(order.begin(), order.end(),
-                   [](const Work &a, const Work &b) { return a.cost > b.cost; });
-  for (const Work &w : order) items.push_back(make_int2(w.frame, w.tile));
+  // grouped by class (one persistent kernel each), longest tiles first within a
+  // class, so the cheap ones fill the tail
+  std::vector<int> cls(n);
+  for (int i = 0; i < n; ++i) {
+    const pwbf::FramePlan &P = b->plans[i];
+    cls[i] = pwbf::batch_class(P.mode, P.cpw == 1, P.n_angles);
+  }
+  std::stable_sort(order.begin(), order.end(), [&cls](const Work &a, const Work &b) {
+    return cls[a.frame] != cls[b.frame] ? cls[a.frame] < cls[b.frame] : a.cost > b.cost;
+  });
+  for (size_t k = 0; k < order.size(); ++k) {
+    const int c = cls[order[k].frame];
+    if (b->classes.empty() || b->classes.back().cls != c)
+      b->classes.push_back({c, (int)k, 0, 0});
+    ++b->classes.back().n;
+    items.push_back(make_int2(order[k].frame, order[k].tile));
+  }
   b->n_items = (int)items.size();
   b->n_post_cols = (int)post_cols.size();
   b->n_log_cols = (int)log_cols.size();
@@ -300,19 +308,27 @@ int pwbf_batch_create(const pwbf_frame *frames, int32_t n, int32_t flags, void *
   int dev_id = 0, n_cu = 0;
   e = hipGetDevice(&dev_id);
   if (e == hipSuccess) e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev_id);
-  if (e == hipSuccess) e = pwbf::batch_occupancy((size_t)b->lds, &b->blocks_per_cu);
+  b->blocks = 0;
+  b->blocks_per_cu = 0;
+  for (pwbf::BatchClass &k : b->classes) {
+    int bpc = 0;
+    if (e == hipSuccess) e = pwbf::batch_occupancy(k.cls, (size_t)b->lds, &bpc);
+    k.blocks = std::max(1, std::min(k.n, std::max(1, bpc) * n_cu));
+    b->blocks += k.blocks;
+    b->blocks_per_cu = b->blocks_per_cu ? std::min(b->blocks_per_cu, bpc) : bpc;
+  }
   if (e != hipSuccess) {
     free_batch(b);
     return dev_error(e, "device query");
   }
-  b->blocks = std::max(1, std::min(b->n_items, std::max(1, b->blocks_per_cu) * n_cu));
 
   e = upload(&b->d_plans, b->plans);
   if (e == hipSuccess) e = upload(&b->d_post, b->post);
   if (e == hipSuccess) e = upload(&b->d_items, items);
   if (e == hipSuccess) e = upload(&b->d_post_cols, post_cols);
   if (e == hipSuccess) e = upload(&b->d_log_cols, log_cols);
-  if (e == hipSuccess) e = hipMalloc((void **)&b->d_counter, sizeof(int));
+  if (e == hipSuccess)
+    e = hipMalloc((void **)&b->d_counter, sizeof(int) * std::max<size_t>(1, b->classes.size()));
   if (e == hipSuccess)
     e = hipHostMalloc(&b->h_stage, n * (sizeof(pwbf::FramePlan) + sizeof(pwbf::PostPlan)),
                       hipHostMallocDefault);
@@ -325,10 +341,10 @@ int pwbf_batch_create(const pwbf_frame *frames, int32_t n, int32_t flags, void *
   e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
-    hipError_t le = pwbf::launch_batch(b->d_plans, b->d_post, b->d_items, b->n_items,
-                                       b->d_post_cols, b->n_post_cols, b->d_log_cols,
-                                       b->n_log_cols, n, b->d_counter, b->blocks, b->lds,
-                                       b->max_nz, b->cap);
+    hipError_t le = pwbf::launch_batch(b->d_plans, b->d_post, b->d_items, b->classes.data(),
+                                       (int)b->classes.size(), b->d_post_cols,
+                                       b->n_post_cols, b->d_log_cols, b->n_log_cols, n,
+                                       b->d_counter, b->lds, b->max_nz, b->cap);
     e = hipStreamEndCapture(b->cap, &b->graph);
     if (le != hipSuccess) e = le;
   }
@@ -401,7 +417,7 @@ int pwbf_batch_describe(const pwbf_batch *b, pwbf_batch_info *info) {
   info->blocks_per_cu = b->blocks_per_cu;
   info->lds_bytes = b->lds;
   info->graph_nodes = b->graph_nodes;
-  info->reserved = 0;
+  info->kernels = (int32_t)b->classes.size();
   return PWBF_OK;
 }
 

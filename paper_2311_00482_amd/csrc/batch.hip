@@ -1,13 +1,15 @@
 // Kernels of a batch launch: frames of uneven size, channel count, angle count,
-// storage type and mode in one persistent launch.
+// storage type and mode in one graph-captured sequence of persistent launches.
 //
-//   k_batch_reset      clears the work counter and every frame's envelope maximum
-//                      (a kernel, not a memset node, so graph replays stay exact)
-//   k_batch_beamform   persistent: every block repeatedly claims the next
-//                      (frame, tile) item of a work list sorted by estimated tile
-//                      cost (active aperture x pixels x angles), largest first,
-//                      and runs the tile body for that frame's plan; all
-//                      waves leave when the list is exhausted
+//   k_batch_reset      clears the classes' work counters and every frame's
+//                      envelope maximum (a kernel, not a memset node, so graph
+//                      replays stay exact)
+//   k_batch_beamform   persistent, one kernel per class of frames (beamformer,
+//                      lane grouping, angle count): every block repeatedly claims
+//                      the next (frame, tile) item of its class's work list,
+//                      sorted by estimated tile cost (active aperture x pixels x
+//                      angles), largest first, and runs the tile body for that
+//                      frame's plan; all waves leave when the list is exhausted
 //   k_batch_postz      one block per (frame, depth column) of frames with
 //                      post-processing
 //   k_batch_logc       one block per (frame, depth column) of frames with a log image
@@ -17,6 +19,9 @@
 // scalar load.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
+#include "batch.h"
 #include "beamform_device.h"
 #include "postz_device.h"
 
@@ -27,28 +32,22 @@ namespace {
 constexpr int kBatchWaves = 8;
 constexpr int kBatchMaxAngles = 16;
 
-__global__ void k_batch_reset(int *counter, const PostPlan *__restrict__ post, int n_frames) {
+__global__ void k_batch_reset(int *counters, int n_classes, const PostPlan *__restrict__ post,
+                              int n_frames) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i == 0) *counter = 0;
+  if (i < n_classes) counters[i] = 0;
   if (i < n_frames && post[i].ws_max)
     for (int s = 0; s < kMaxSlots; ++s) dev::frame_max_clear(post[i].ws_max, s);
 }
 
-// The tile bodies the persistent kernel can run: exact angle counts 1, 5 and 11
-// (the batch workloads), any other count up to kBatchMaxAngles through a
-// predicated body (a larger bucket would raise the register budget of the
-// whole kernel, and with it lower the occupancy of every frame).
-template <int MODE, bool ONEGRP>
-__device__ __forceinline__ void run_tile_mode(const FramePlan &P, int tz, int tx,
-                                              unsigned char *smem) {
-  switch (P.n_angles) {
-    case 1: dev::process_tile<1, false, MODE, ONEGRP>(P, tz, tx, smem); break;
-    case 5: dev::process_tile<5, false, MODE, ONEGRP>(P, tz, tx, smem); break;
-    case 11: dev::process_tile<11, false, MODE, ONEGRP>(P, tz, tx, smem); break;
-    default: dev::process_tile<kBatchMaxAngles, true, MODE, ONEGRP>(P, tz, tx, smem); break;
-  }
-}
-
+// Frames fall into classes by beamformer, lane grouping (one lane group per
+// wavefront or several) and angle count (exactly 1, 5 or 11, the batch
+// workloads, or any other count up to kBatchMaxAngles through a predicated
+// body). Each class has its own persistent kernel holding only that class's
+// tile body: a kernel's register budget is that of its largest body, and one
+// kernel for every class (the DMAS and pDAS bodies need up to ~130 VGPRs)
+// would run the 74-VGPR compound DAS body at two blocks per CU instead of three.
+template <int MODE, bool ONEGRP, int AB>
 __global__ void __launch_bounds__(kWave * kBatchWaves)
     k_batch_beamform(const FramePlan *__restrict__ plans, const int2 *__restrict__ items,
                      int n_items, int *__restrict__ counter) {
@@ -63,24 +62,30 @@ __global__ void __launch_bounds__(kWave * kBatchWaves)
     const int2 w = items[it];
     const FramePlan &P = plans[w.x];
     const int tz = w.y / P.tiles_x, tx = w.y - tz * P.tiles_x;
-    if (P.mode == kDas) {
-      if (P.cpw == 1)
-        run_tile_mode<kDas, true>(P, tz, tx, smem);
-      else
-        run_tile_mode<kDas, false>(P, tz, tx, smem);
-    } else if (P.mode == kDmas) {
-      if (P.cpw == 1)
-        run_tile_mode<kDmas, true>(P, tz, tx, smem);
-      else
-        run_tile_mode<kDmas, false>(P, tz, tx, smem);
-    } else {
-      if (P.cpw == 1)
-        run_tile_mode<kPdas, true>(P, tz, tx, smem);
-      else
-        run_tile_mode<kPdas, false>(P, tz, tx, smem);
-    }
+    if constexpr (AB == 3)
+      dev::process_tile<kBatchMaxAngles, true, MODE, ONEGRP>(P, tz, tx, smem);
+    else
+      dev::process_tile<AB == 0 ? 1 : (AB == 1 ? 5 : 11), false, MODE, ONEGRP>(P, tz, tx, smem);
   }
 }
+
+template <int C>
+hipError_t launch_class_kernel(dim3 grid, size_t lds, hipStream_t s, const FramePlan *plans,
+                               const int2 *items, int n_items, int *counter) {
+  hipLaunchKernelGGL((k_batch_beamform<C / 8, (C / 4) % 2 == 1, C % 4>), grid,
+                     dim3(kWave * kBatchWaves), lds, s, plans, items, n_items, counter);
+  return hipGetLastError();
+}
+
+template <int C>
+hipError_t class_occupancy(size_t lds, int *blocks_per_cu) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+      blocks_per_cu, k_batch_beamform<C / 8, (C / 4) % 2 == 1, C % 4>, kWave * kBatchWaves, lds);
+}
+
+#define PWBF_BATCH_CLASSES(X) \
+  X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) \
+  X(16) X(17) X(18) X(19) X(20) X(21) X(22) X(23)
 
 __global__ void __launch_bounds__(dev::kPostThreads)
     k_batch_postz(const PostPlan *__restrict__ post, const int2 *__restrict__ cols) {
@@ -104,24 +109,44 @@ __global__ void __launch_bounds__(256)
 int batch_waves() { return kBatchWaves; }
 int batch_max_angles() { return kBatchMaxAngles; }
 
-hipError_t batch_occupancy(size_t lds_bytes, int *blocks_per_cu) {
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_batch_beamform,
-                                                      kWave * kBatchWaves, lds_bytes);
+int batch_class(int mode, bool one_group, int n_angles) {
+  const int ab = n_angles == 1 ? 0 : (n_angles == 5 ? 1 : (n_angles == 11 ? 2 : 3));
+  return (mode * 2 + (one_group ? 1 : 0)) * 4 + ab;
+}
+
+hipError_t batch_occupancy(int cls, size_t lds_bytes, int *blocks_per_cu) {
+  switch (cls) {
+#define PWBF_OCC(C) \
+  case C: return class_occupancy<C>(lds_bytes, blocks_per_cu);
+    PWBF_BATCH_CLASSES(PWBF_OCC)
+#undef PWBF_OCC
+    default: return hipErrorInvalidValue;
+  }
 }
 
 // Enqueue the batch sequence on `stream` (captured into a graph by the caller).
 hipError_t launch_batch(const FramePlan *plans, const PostPlan *post, const int2 *items,
-                        int n_items, const int2 *post_cols, int n_post_cols,
-                        const int2 *log_cols, int n_log_cols, int n_frames, int *counter,
-                        int blocks, size_t lds, int max_nz, hipStream_t stream) {
-  hipLaunchKernelGGL(k_batch_reset, dim3((n_frames + 255) / 256), dim3(256), 0, stream, counter,
-                     post, n_frames);
+                        const BatchClass *classes, int n_classes, const int2 *post_cols,
+                        int n_post_cols, const int2 *log_cols, int n_log_cols, int n_frames,
+                        int *counters, size_t lds, int max_nz, hipStream_t stream) {
+  hipLaunchKernelGGL(k_batch_reset, dim3((std::max(n_frames, n_classes) + 255) / 256), dim3(256),
+                     0, stream, counters, n_classes, post, n_frames);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_batch_beamform, dim3(blocks), dim3(kWave * kBatchWaves), lds, stream,
-                     plans, items, n_items, counter);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  for (int c = 0; c < n_classes; ++c) {
+    const BatchClass &k = classes[c];
+    switch (k.cls) {
+#define PWBF_LAUNCH(C)                                                                  \
+  case C:                                                                               \
+    e = launch_class_kernel<C>(dim3(k.blocks), lds, stream, plans, items + k.first, k.n, \
+                               counters + c);                                           \
+    break;
+      PWBF_BATCH_CLASSES(PWBF_LAUNCH)
+#undef PWBF_LAUNCH
+      default: e = hipErrorInvalidValue; break;
+    }
+    if (e != hipSuccess) return e;
+  }
   if (n_post_cols > 0) {
     const size_t plds = dev::post_lds_bytes(max_nz);
     hipLaunchKernelGGL(k_batch_postz, dim3(n_post_cols), dim3(dev::kPostThreads), plds, stream,
