@@ -289,7 +289,7 @@ int pwbf_batch_create(const pwbf_frame *frames, int32_t n, int32_t flags, void *
   std::vector<int> cls(n);
   for (int i = 0; i < n; ++i) {
     const pwbf::FramePlan &P = b->plans[i];
-    cls[i] = pwbf::batch_class(P.mode, P.cpw == 1, P.n_angles);
+    cls[i] = pwbf::tile_class(P.mode, P.cpw == 1, P.n_angles);
   }
   std::stable_sort(order.begin(), order.end(), [&cls](const Work &a, const Work &b) {
     return cls[a.frame] != cls[b.frame] ? cls[a.frame] < cls[b.frame] : a.cost > b.cost;

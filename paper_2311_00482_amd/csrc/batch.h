@@ -5,12 +5,9 @@
 #include <hip/hip_runtime.h>
 
 #include "plan.h"
+#include "tile_class.h"
 
 namespace pwbf {
-
-// classes of frames: beamformer (3) x one lane group per wavefront or several (2)
-// x angle count 1, 5, 11 or other (4); each has its own persistent kernel
-constexpr int kBatchClasses = 24;
 
 // the work of one class: items [first, first + n) of the batch's list, run by a
 // persistent kernel of `blocks` blocks
@@ -20,7 +17,6 @@ struct BatchClass {
 
 int batch_waves();
 int batch_max_angles();
-int batch_class(int mode, bool one_group, int n_angles);
 hipError_t batch_occupancy(int cls, size_t lds_bytes, int *blocks_per_cu);
 hipError_t launch_batch(const FramePlan *plans, const PostPlan *post, const int2 *items,
                         const BatchClass *classes, int n_classes, const int2 *post_cols,

@@ -40,13 +40,10 @@ __global__ void k_batch_reset(int *counters, int n_classes, const PostPlan *__re
     for (int s = 0; s < kMaxSlots; ++s) dev::frame_max_clear(post[i].ws_max, s);
 }
 
-// Frames fall into classes by beamformer, lane grouping (one lane group per
-// wavefront or several) and angle count (exactly 1, 5 or 11, the batch
-// workloads, or any other count up to kBatchMaxAngles through a predicated
-// body). Each class has its own persistent kernel holding only that class's
-// tile body: a kernel's register budget is that of its largest body, and one
-// kernel for every class (the DMAS and pDAS bodies need up to ~130 VGPRs)
-// would run the 74-VGPR compound DAS body at two blocks per CU instead of three.
+// One persistent kernel per class of frames (tile_class.h): one kernel for every
+// class (the DMAS and pDAS bodies need up to ~130 VGPRs) would run the
+// compound DAS body at two 8-wave blocks per CU instead of three. Angle counts
+// other than 1, 5 and 11 run the predicated body of up to kBatchMaxAngles.
 template <int MODE, bool ONEGRP, int AB>
 __global__ void __launch_bounds__(kWave * kBatchWaves)
     k_batch_beamform(const FramePlan *__restrict__ plans, const int2 *__restrict__ items,
@@ -108,11 +105,6 @@ __global__ void __launch_bounds__(256)
 
 int batch_waves() { return kBatchWaves; }
 int batch_max_angles() { return kBatchMaxAngles; }
-
-int batch_class(int mode, bool one_group, int n_angles) {
-  const int ab = n_angles == 1 ? 0 : (n_angles == 5 ? 1 : (n_angles == 11 ? 2 : 3));
-  return (mode * 2 + (one_group ? 1 : 0)) * 4 + ab;
-}
 
 hipError_t batch_occupancy(int cls, size_t lds_bytes, int *blocks_per_cu) {
   switch (cls) {

@@ -87,9 +87,11 @@ struct pwbf_server {
   std::vector<Slot> slots;
   pwbf::FramePlan *d_plans = nullptr;
   pwbf::PostPlan *d_post = nullptr;
-  int *d_counter = nullptr;
+  int *d_counter = nullptr;           // one work counter per tile class
+  std::vector<int> plan_class;        // tile class of each slot's plan
+  int class_blocks[pwbf::kTileClasses] = {};  // persistent blocks per class
   hipStream_t copy_s = nullptr, comp_s = nullptr;
-  int device = 0, blocks = 0, lds = 0, max_nz = 0;
+  int device = 0, lds = 0, max_nz = 0;
   size_t budget = 0, in_use = 0, peak = 0;
   int max_queue = 1024;
 
@@ -259,8 +261,8 @@ void scheduler(pwbf_server *s) {
     for (const auto &r : ready)
       if (e == hipSuccess) e = hipStreamWaitEvent(s->comp_s, s->slots[r.second].uploaded, 0);
     if (e == hipSuccess)
-      e = pwbf::launch_serve(s->d_plans, s->d_post, al, s->d_counter, s->blocks, s->lds,
-                             s->max_nz, s->comp_s);
+      e = pwbf::launch_serve(s->d_plans, s->d_post, al, s->plan_class.data(), s->class_blocks,
+                             s->d_counter, s->lds, s->max_nz, s->comp_s);
     if (e == hipSuccess) e = hipLaunchHostFunc(s->comp_s, on_batch_done, arg);
     if (e != hipSuccess) {
       delete arg;
@@ -399,15 +401,22 @@ int pwbf_server_create(const pwbf_probe *probes, int32_t n, size_t hbm_budget_by
       post.push_back(Q);
     }
   }
-  int n_cu = 0, bpc = 0;
+  int n_cu = 0;
   if (e == hipSuccess) e = hipGetDevice(&s->device);
   if (e == hipSuccess)
     e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, s->device);
-  if (e == hipSuccess) e = pwbf::serve_occupancy((size_t)s->lds, &bpc);
-  s->blocks = std::max(1, bpc) * std::max(1, n_cu);
+  for (const pwbf::FramePlan &P : plans) {
+    const int c = pwbf::tile_class(P.mode, P.cpw == 1, P.n_angles);
+    s->plan_class.push_back(c);
+    int bpc = 0;
+    if (e == hipSuccess && !s->class_blocks[c]) {
+      e = pwbf::serve_occupancy(c, (size_t)s->lds, &bpc);
+      s->class_blocks[c] = std::max(1, bpc) * std::max(1, n_cu);
+    }
+  }
   if (e == hipSuccess) e = hipMalloc((void **)&s->d_plans, plans.size() * sizeof(pwbf::FramePlan));
   if (e == hipSuccess) e = hipMalloc((void **)&s->d_post, post.size() * sizeof(pwbf::PostPlan));
-  if (e == hipSuccess) e = hipMalloc((void **)&s->d_counter, sizeof(int));
+  if (e == hipSuccess) e = hipMalloc((void **)&s->d_counter, sizeof(int) * pwbf::kTileClasses);
   if (e == hipSuccess)
     e = hipMemcpy(s->d_plans, plans.data(), plans.size() * sizeof(pwbf::FramePlan),
                   hipMemcpyHostToDevice);

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include "plan.h"
+#include "tile_class.h"
 
 namespace pwbf {
 
@@ -19,9 +20,12 @@ struct ActiveList {
 
 int serve_waves();
 int serve_max_angles();
-hipError_t serve_occupancy(size_t lds_bytes, int *blocks_per_cu);
+hipError_t serve_occupancy(int cls, size_t lds_bytes, int *blocks_per_cu);
 hipError_t launch_i16_to_f16(void *buf, size_t n, hipStream_t stream);
+// plan_class[p]: tile class of plan p; class_blocks[c]: persistent blocks of class c
+// (host arrays); counters: kTileClasses device words
 hipError_t launch_serve(const FramePlan *plans, const PostPlan *post, const ActiveList &al,
-                        int *counter, int blocks, size_t lds, int max_nz, hipStream_t stream);
+                        const int *plan_class, const int *class_blocks, int *counters,
+                        size_t lds, int max_nz, hipStream_t stream);
 
 }  // namespace pwbf

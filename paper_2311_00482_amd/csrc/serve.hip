@@ -1,9 +1,12 @@
 // Kernels of the serving loop. A serving batch is a list of active ring slots
 // passed by value; prefix sums of the slots' tile and column counts map a
 // global work index to (slot, tile) or (slot, column), so no per-batch table is
-// uploaded and any mix of probes runs in one persistent launch.
+// uploaded. The slots' tiles run in one persistent kernel per class of probe
+// (tile_class.h), their columns in one post-processing and one log launch.
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 
 #include "beamform_device.h"
 #include "postz_device.h"
@@ -39,9 +42,9 @@ __global__ void k_i16_to_f16(void *buf, size_t n) {
   }
 }
 
-__global__ void k_serve_reset(int *counter, const PostPlan *__restrict__ post, ActiveList al) {
+__global__ void k_serve_reset(int *counters, const PostPlan *__restrict__ post, ActiveList al) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i == 0) *counter = 0;
+  if (i < kTileClasses) counters[i] = 0;
   if (i < al.n) {
     const PostPlan &Q = post[al.plan[i]];
     if (Q.ws_max)
@@ -49,17 +52,7 @@ __global__ void k_serve_reset(int *counter, const PostPlan *__restrict__ post, A
   }
 }
 
-template <int MODE, bool ONEGRP>
-__device__ __forceinline__ void serve_tile_mode(const FramePlan &P, int tz, int tx,
-                                                unsigned char *smem) {
-  switch (P.n_angles) {
-    case 1: dev::process_tile<1, false, MODE, ONEGRP>(P, tz, tx, smem); break;
-    case 5: dev::process_tile<5, false, MODE, ONEGRP>(P, tz, tx, smem); break;
-    case 11: dev::process_tile<11, false, MODE, ONEGRP>(P, tz, tx, smem); break;
-    default: dev::process_tile<kServeMaxAngles, true, MODE, ONEGRP>(P, tz, tx, smem); break;
-  }
-}
-
+template <int MODE, bool ONEGRP, int AB>
 __global__ void __launch_bounds__(kWave * kServeWaves)
     k_serve_beamform(const FramePlan *__restrict__ plans, const ActiveList al,
                      int *__restrict__ counter) {
@@ -78,24 +71,17 @@ __global__ void __launch_bounds__(kWave * kServeWaves)
     const int t = it - al.tile0[k];
     const int q = t / P.tiles_x;
     const int tz = P.tiles_z - 1 - q, tx = t - q * P.tiles_x;
-    if (P.mode == kDas) {
-      if (P.cpw == 1)
-        serve_tile_mode<kDas, true>(P, tz, tx, smem);
-      else
-        serve_tile_mode<kDas, false>(P, tz, tx, smem);
-    } else if (P.mode == kDmas) {
-      if (P.cpw == 1)
-        serve_tile_mode<kDmas, true>(P, tz, tx, smem);
-      else
-        serve_tile_mode<kDmas, false>(P, tz, tx, smem);
-    } else {
-      if (P.cpw == 1)
-        serve_tile_mode<kPdas, true>(P, tz, tx, smem);
-      else
-        serve_tile_mode<kPdas, false>(P, tz, tx, smem);
-    }
+    if constexpr (AB == 3)
+      dev::process_tile<kServeMaxAngles, true, MODE, ONEGRP>(P, tz, tx, smem);
+    else
+      dev::process_tile<AB == 0 ? 1 : (AB == 1 ? 5 : 11), false, MODE, ONEGRP>(P, tz, tx, smem);
   }
 }
+
+#define PWBF_SERVE_CLASSES(X) \
+  X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) \
+  X(16) X(17) X(18) X(19) X(20) X(21) X(22) X(23)
+static_assert(kTileClasses == 24, "one kernel per class");
 
 __global__ void __launch_bounds__(dev::kPostThreads)
     k_serve_postz(const PostPlan *__restrict__ post, const ActiveList al) {
@@ -121,9 +107,17 @@ __global__ void __launch_bounds__(256) k_serve_logc(const PostPlan *__restrict__
 int serve_waves() { return kServeWaves; }
 int serve_max_angles() { return kServeMaxAngles; }
 
-hipError_t serve_occupancy(size_t lds_bytes, int *blocks_per_cu) {
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_serve_beamform,
-                                                      kWave * kServeWaves, lds_bytes);
+hipError_t serve_occupancy(int cls, size_t lds_bytes, int *blocks_per_cu) {
+  switch (cls) {
+#define PWBF_OCC(C)                                                                        \
+  case C:                                                                                  \
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(                                   \
+        blocks_per_cu, k_serve_beamform<C / 8, (C / 4) % 2 == 1, C % 4>, kWave * kServeWaves, \
+        lds_bytes);
+    PWBF_SERVE_CLASSES(PWBF_OCC)
+#undef PWBF_OCC
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_i16_to_f16(void *buf, size_t n, hipStream_t stream) {
@@ -134,16 +128,37 @@ hipError_t launch_i16_to_f16(void *buf, size_t n, hipStream_t stream) {
 }
 
 hipError_t launch_serve(const FramePlan *plans, const PostPlan *post, const ActiveList &al,
-                        int *counter, int blocks, size_t lds, int max_nz, hipStream_t stream) {
-  hipLaunchKernelGGL(k_serve_reset, dim3((al.n + 255) / 256), dim3(256), 0, stream, counter,
-                     post, al);
+                        const int *plan_class, const int *class_blocks, int *counters,
+                        size_t lds, int max_nz, hipStream_t stream) {
+  hipLaunchKernelGGL(k_serve_reset, dim3((std::max(al.n, kTileClasses) + 255) / 256), dim3(256),
+                     0, stream, counters, post, al);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const int tiles = al.tile0[al.n];
-  hipLaunchKernelGGL(k_serve_beamform, dim3(std::max(1, std::min(blocks, tiles))),
-                     dim3(kWave * kServeWaves), lds, stream, plans, al, counter);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  // the slots of each class, with their own tile prefix sums
+  for (int c = 0; c < kTileClasses; ++c) {
+    ActiveList sub;
+    sub.n = 0;
+    sub.tile0[0] = 0;
+    for (int k = 0; k < al.n; ++k) {
+      if (plan_class[al.plan[k]] != c) continue;
+      sub.plan[sub.n] = al.plan[k];
+      sub.tile0[sub.n + 1] = sub.tile0[sub.n] + (al.tile0[k + 1] - al.tile0[k]);
+      ++sub.n;
+    }
+    if (sub.n == 0) continue;
+    const dim3 grid(std::max(1, std::min(class_blocks[c], sub.tile0[sub.n])));
+    switch (c) {
+#define PWBF_LAUNCH(C)                                                                     \
+  case C:                                                                                  \
+    hipLaunchKernelGGL((k_serve_beamform<C / 8, (C / 4) % 2 == 1, C % 4>), grid,           \
+                       dim3(kWave * kServeWaves), lds, stream, plans, sub, counters + c);  \
+    break;
+      PWBF_SERVE_CLASSES(PWBF_LAUNCH)
+#undef PWBF_LAUNCH
+    }
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   if (al.col0[al.n] > 0) {
     const size_t plds = dev::post_lds_bytes(max_nz);
     hipLaunchKernelGGL(k_serve_postz, dim3(al.col0[al.n]), dim3(dev::kPostThreads), plds, stream,
