@@ -387,6 +387,53 @@ def image_metrics(dev, torch, g, gs, phantom, env32, env16) -> dict:
     return res
 
 
+def uneven_batch(dev, torch, steps: int, warmup: int) -> dict:
+    """The uneven 32-frame workload (seeded: 64/128 channels, 1/5/11 angles,
+    grids 256..1024 per axis, 2048/4096 samples, DAS and DMAS with band-pass,
+    int16 RF, RF + envelope + log per frame) as one tuned batch launch, against
+    the same frames launched one after another as single frames with default
+    launch shapes. The RF is seeded noise of the frames' shapes: the kernels'
+    time does not depend on the values."""
+    from paper_2311_00482_amd import Batch, FrameSpec, GeometryArg, beamform
+    from synth import config_c4_frames
+
+    specs = config_c4_frames()
+    want = ("rf", "filtered", "env", "log")
+    gen = torch.Generator().manual_seed(2000)
+    frames, singles, gathers = [], [], 0
+    for sp in specs:
+        bp = sp.mode == "dmas"
+        g = GeometryArg(sp.geom, bandpass=bp)
+        w = want if bp else ("rf", "env", "log")
+        shape = (sp.geom.n_angles, sp.geom.n_channels, sp.geom.n_samples)
+        rf = torch.randint(-511, 512, shape, generator=gen, dtype=torch.int16).to(dev)
+        out = {k: torch.empty((g.nx, g.nz), dtype=torch.float32, device=dev) for k in w}
+        frames.append(FrameSpec(g, rf, sp.mode, -1, out, bp))
+        ws = torch.empty(WS_BYTES, dtype=torch.uint8, device=dev)
+        singles.append((g, rf, sp.mode, w, out, ws, bp))
+        gathers += sp.geom.gathers
+    t0 = time.perf_counter()
+    batch = Batch(frames, tune=True)
+    torch.cuda.synchronize()
+    t_create = time.perf_counter() - t0
+    info = batch.describe()
+    n = max(5, steps // 32)
+    wallb, latb, _ = time_steps(batch.launch, n, max(2, warmup // 16), torch)
+
+    def one_by_one():
+        for g, rf, mode, w, out, ws, bp in singles:
+            beamform(g, rf, mode, -1, want=w, out=out, workspace=ws, bandpass=bp)
+    walls, lats, _ = time_steps(one_by_one, n, max(2, warmup // 16), torch)
+    batch.close()
+    nf = len(specs)
+    return {"frames": nf, "tuned_create_s": t_create, "kernels": info["kernels"],
+            "batched": {"frames_per_s": nf * n / wallb, "ms_per_launch": float(np.mean(latb)),
+                        "value": gathers * n / wallb / 1e9, "unit": UNIT},
+            "single_frames": {"frames_per_s": nf * n / walls,
+                              "ms_per_32": float(np.mean(lats)),
+                              "value": gathers * n / walls / 1e9, "unit": UNIT}}
+
+
 def systems(dev, torch, steps: int, warmup: int) -> dict:
     """Single-frame FP32 against batched and served FP16 on the same GPU.
 
@@ -434,6 +481,8 @@ def systems(dev, torch, steps: int, warmup: int) -> dict:
                           "max_rel_diff_vs_single_f32": dev_max}
     batch.close()
     del frames
+
+    res["uneven_batch_32"] = uneven_batch(dev, torch, steps, warmup)
 
     specs = config_c5_probes()
     hosts = []
