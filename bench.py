@@ -73,7 +73,10 @@ def aperture_pairs(g) -> int:
 # fraction, interpolation FMA, |v|, log2, times 1/p, exp2, signed root,
 # weighted accumulate = 10; per (pixel, channel) the DAS terms without the
 # weighted accumulate = 8; per (pixel, angle) the transmit delay and the signed
-# p-th power (|t|, log2, times p, exp2, sign, add) = 8.
+# p-th power (|t|, log2, times p, exp2, sign, add) = 8. At p = 2 the root is a
+# square root and the power t |t|: 8 per gather (delay add, floor, fraction,
+# interpolation FMA, |v|, square root, signed root, weighted accumulate), 8 per
+# (pixel, channel), 4 per (pixel, angle) (transmit delay, |t|, multiply, add).
 # IQ-DAS: delay add, floor, two interpolation FMAs (real and imaginary lines),
 # complex multiply-accumulate with the receive phasor (4) = 8 per gather; per
 # (pixel, channel) the DAS terms plus the receive phase (multiply, cos, sin,
@@ -83,11 +86,13 @@ def aperture_pairs(g) -> int:
 # square root, reciprocal square root, a select and two scalings per gather
 # (14) and the square of each angle's sum (17 per (pixel, angle)).
 MODE_OPS = {"das": (OPS_PER_GATHER, OPS_PER_PIX_CH, OPS_PER_PIX_ANGLE), "dmas": (9, 10, 3),
-            "pdas": (10, 8, 8), "iqdas": (8, 18, 14), "bbdmas": (14, 18, 17)}
+            "pdas": (10, 8, 8), "pdas2": (8, 8, 4), "iqdas": (8, 18, 14),
+            "bbdmas": (14, 18, 17)}
 
 
-def algorithmic_ops(g, mode: str = "das") -> float:
-    per_gather, per_pix_ch, per_pix_angle = MODE_OPS[mode]
+def algorithmic_ops(g, mode: str = "das", p: float = 2.0) -> float:
+    key = "pdas2" if mode == "pdas" and p == 2.0 else mode
+    per_gather, per_pix_ch, per_pix_angle = MODE_OPS[key]
     P = g.nx * g.nz
     pairs = aperture_pairs(g)
     return float(pairs * g.n_angles * per_gather + pairs * per_pix_ch

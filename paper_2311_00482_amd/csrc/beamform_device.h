@@ -22,7 +22,7 @@
 // angle) the DAS gather costs an add, a floor, an address, one LDS read and two
 // accumulate operations. DMAS adds the fraction, a square root and the
 // signed-root accumulation per gather; pDAS takes the p-th root through the
-// hardware base-2 logarithm and exponential instead of the square root.
+// hardware base-2 logarithm and exponential (the square root at p = 2).
 
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
@@ -456,18 +456,34 @@ __device__ __forceinline__ void process_tile(const FramePlan &P, int tz, int tx,
           }
         }
       } else if constexpr (MODE == kPdas) {
-        // sign(v) |v|^(1/p) = sign(v) 2^(log2|v| / p); |v| = 0 gives 2^-inf = 0
+        // sign(v) |v|^(1/p) = sign(v) 2^(log2|v| / p); |v| = 0 gives 2^-inf = 0.
+        // p = 2 takes the square root instead: one transcendental operation per
+        // gather instead of two (the branch is uniform over the block)
         const float ip = P.pdas_inv_p;
+        if (P.pdas_p == 2.0f) {
 #pragma unroll
-        for (int a = 0; a < AM; ++a) {
-          if (!PRED || a < A) {
-            const float s = txl[a] + rxl;
-            const int n = floor_i32(s);
-            const float f = __builtin_amdgcn_fractf(s);
-            const float2 p = *(const float2 *)(wb + a * wstride + (n << 3));
-            const float v = fmaf(f, p.y, p.x);
-            const float r = __builtin_amdgcn_exp2f(ip * __builtin_amdgcn_logf(fabsf(v)));
-            S[a] = fmaf(w, copysignf(r, v), S[a]);
+          for (int a = 0; a < AM; ++a) {
+            if (!PRED || a < A) {
+              const float s = txl[a] + rxl;
+              const int n = floor_i32(s);
+              const float f = __builtin_amdgcn_fractf(s);
+              const float2 p = *(const float2 *)(wb + a * wstride + (n << 3));
+              const float v = fmaf(f, p.y, p.x);
+              S[a] = fmaf(w, copysignf(__builtin_amdgcn_sqrtf(fabsf(v)), v), S[a]);
+            }
+          }
+        } else {
+#pragma unroll
+          for (int a = 0; a < AM; ++a) {
+            if (!PRED || a < A) {
+              const float s = txl[a] + rxl;
+              const int n = floor_i32(s);
+              const float f = __builtin_amdgcn_fractf(s);
+              const float2 p = *(const float2 *)(wb + a * wstride + (n << 3));
+              const float v = fmaf(f, p.y, p.x);
+              const float r = __builtin_amdgcn_exp2f(ip * __builtin_amdgcn_logf(fabsf(v)));
+              S[a] = fmaf(w, copysignf(r, v), S[a]);
+            }
           }
         }
       } else {
@@ -550,7 +566,9 @@ __device__ __forceinline__ void process_tile(const FramePlan &P, int tz, int tx,
       if (!PRED || a < A) {
         float t = S[a];
         for (int off = ppw; off < kWave; off <<= 1) t += __shfl_xor(t, off);
-        y += copysignf(__builtin_amdgcn_exp2f(P.pdas_p * __builtin_amdgcn_logf(fabsf(t))), t);
+        y += P.pdas_p == 2.0f
+                 ? t * fabsf(t)
+                 : copysignf(__builtin_amdgcn_exp2f(P.pdas_p * __builtin_amdgcn_logf(fabsf(t))), t);
       }
     }
   } else {

@@ -122,3 +122,16 @@ def test_iq_das_compound_full_size_sampled():
     got = (out["rf"] + 1j * out["imag"]).ravel()[pix]
     norm = out["env"].max()
     assert float(np.abs(got - ref).max() / norm) <= tol_for(g, "iqdas", -1)
+
+
+def test_bbdmas_compound_full_size_sampled():
+    # the measured BB-DMAS workload: 11 angles, 128 channels, 1024 x 1024, FP32 RF
+    g = config_c3()
+    fr = make_frame(g, 1003, "c3", quantize=False)
+    out = run(g, gpu_iq(g, fr["f32"]), "bbdmas", -1, want=("rf", "imag", "env"))
+    rng = np.random.default_rng(10)
+    pix = rng.choice(g.nx * g.nz, 1500, replace=False)
+    ref = oracle.iq_beamform(g, oracle.iq_demodulate(g, fr["master"]), "bbdmas", -1, pix=pix)
+    got = (out["rf"] + 1j * out["imag"]).ravel()[pix]
+    norm = out["env"].max()
+    assert float(np.abs(got - ref).max() / norm) <= tol_for(g, "bbdmas", -1)

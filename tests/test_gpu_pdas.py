@@ -105,3 +105,20 @@ def test_pdas_odd_in_the_data():
     b = run(g, torch.from_numpy(-rf).cuda(), -1, 2.5)["rf"]
     # negating int16 data negates every sample exactly; the image flips sign bit for bit
     assert np.array_equal(a, -b)
+
+
+def test_pdas_compound_full_size_sampled():
+    """The measured compound workload (11 angles, 128 channels x 4096 samples,
+    1024 x 1024 pixels, FP32 RF, p = 2) in the benchmark's launch shape, on
+    sampled pixels (the oracle computes them one by one); max-normalised over
+    the whole GPU image."""
+    from synth import config_c3
+    torch = _torch()
+    g = config_c3()
+    fr = make_frame(g, 1003, "c3", quantize=False)
+    rf_t = torch.from_numpy(fr["f32"]).cuda()
+    out = run(g, rf_t, -1, 2.0)["rf"]
+    pix = np.random.default_rng(13).choice(g.nx * g.nz, 1500, replace=False)
+    ref = oracle.pdas(g, fr["master"], -1, 2.0, pix=pix)
+    e = float(np.abs(out.ravel()[pix] - ref).max() / np.abs(out).max())
+    assert e <= tol_pdas(g, 2.0, -1), e
