@@ -63,117 +63,146 @@ struct RfT<kF32> {
 // Buffer resource word 3 for raw (unformatted, unswizzled) loads on gfx9.
 constexpr int kRawBufferWord3 = 0x00020000;
 
-// Stage the windows of channels e0 .. e0 + nch - 1: nch * A rows (channel c,
-// angle a) of win entries (win a multiple of 4). Entry j of a row covers
-// samples n = LT_a + LR_c + j and n + 1, i.e. kernel delays s in [m, m + 1)
-// with m = j - off_t - off_r, and holds, with du = u[n+1] - u[n],
+// Stage the windows of a chunk: rows r = c A + a (channel e0 + c, angle a) of
+// win entries each (win a multiple of 4), described by the row table s_row:
+// {offset of the record of (angle, channel) in elements, first sample n0 of the
+// window}. Entry j of a row covers samples n = n0 + j and n + 1, i.e. kernel
+// delays s in [m, m + 1) with m = j - off, and holds, with du = u[n+1] - u[n],
 //   DAS:  the line through both samples in s:  (u[n] - m du, du),
 //         so the interpolated value is b + s du (no fraction needed);
 //   DMAS: (u[n], du), interpolated as u[n] + frac(s) du, which keeps the
 //         rounding of v small where the signed square root is steep.
-// Samples outside [0, n_samples) read as zero; rows of channels >= e_end are zero.
+// Samples outside [0, n_samples) read as zero (the table gives rows that must
+// be all zero a first sample far below 0).
 //
 // Each thread fills 4 consecutive entries of a row from 5 consecutive samples,
 // read through one 32-bit buffer offset with immediate increments; where the 5
 // samples straddle an end of the record the reads are clamped into it and the
 // outside samples replaced by zero. Every read stays inside the RF buffer.
+//
+// Threads keep a fixed column of quads: with W4 = win / 4 quads per row and
+// R = blockDim / W4 >= 1, thread t stages quad t mod W4 of rows t / W4, + R,
+// + 2R, ..., so its entry offsets are set up once (the fewer than W4 threads
+// past R W4 stay idle). If a row has more quads than the block has threads,
+// each thread takes quads t, t + blockDim, ... of every row.
+struct QuadWalk {
+  int row0, drow, jq, djq;
+  bool active;
+};
+__device__ __forceinline__ QuadWalk quad_walk(int W4) {
+  const int bs = blockDim.x, t = threadIdx.x;
+  QuadWalk w;
+  if (W4 <= bs) {
+    // t / W4 through a float reciprocal: (t + 0.5) / W4 lies at least 0.5 / W4
+    // from an integer and t < 2^10, so truncation yields the exact quotient
+    const float rw = __builtin_amdgcn_rcpf((float)W4);
+    w.row0 = (int)fmaf((float)t, rw, 0.5f * rw);
+    w.jq = t - w.row0 * W4;
+    w.drow = bs / W4;
+    w.djq = W4;
+    w.active = w.row0 < w.drow;
+  } else {
+    w.row0 = 0;
+    w.jq = t;
+    w.drow = 1;
+    w.djq = bs;
+    w.active = true;
+  }
+  return w;
+}
+
 template <int DT, int MODE>
-__device__ __forceinline__ void stage_windows(const FramePlan &P, int e0, int nch, int e_end,
-                                              const int *s_lt, const int *s_lr, float2 *s_pairs) {
+__device__ __forceinline__ void stage_windows(const FramePlan &P, int rows, int off,
+                                              const int2 *s_row, float2 *s_pairs) {
   using R = RfT<DT>;
   constexpr int B = R::kBytes;
-  const int A = P.n_angles, N = P.n_channels, Ns = P.n_samples, win = P.win;
-  const int off = P.off_t + P.off_r;
-  const int W4 = win >> 2;
-  const int total = nch * A * W4;  // at most kMaxLdsBytes / 32 = 2^11 quads
-  // row = q / W4 and c = row / A through a float reciprocal: (q + 0.5) / W4
-  // lies at least 0.5 / W4 from an integer, and for q < 2^11 the product errs
-  // by under 1e-3 / W4, so truncation yields the exact quotient.
-  const float rw = __builtin_amdgcn_rcpf((float)W4), ra = __builtin_amdgcn_rcpf((float)A);
-  const float hw = 0.5f * rw, ha = 0.5f * ra;
-  const int last = min(e_end, N) - 1;  // channels past it stage zeros
+  const int Ns = P.n_samples, win = P.win;
+  const unsigned lim = (unsigned)max(Ns - 4, 0);  // n in [0, lim): all 5 samples inside
   // the plan's angles only: A * N * Ns * B < 2^31 bytes (checked on the host)
   const __amdgpu_buffer_rsrc_t res = __builtin_amdgcn_make_buffer_rsrc(
-      const_cast<void *>(P.rf), (short)0, A * N * Ns * B, kRawBufferWord3);
-  for (int q = threadIdx.x; q < total; q += blockDim.x) {
-    const int row = (int)fmaf((float)q, rw, hw);
-    const int j0 = (q - __mul24(row, W4)) << 2;
-    const int c = (int)fmaf((float)row, ra, ha);
-    const int a = row - __mul24(c, A);
-    const int e = e0 + c;
-    const int n = s_lt[a] + s_lr[c] + j0;
-    const unsigned base = __umul24((unsigned)(__mul24(a, N) + min(e, last)), (unsigned)Ns);
-    float u[5];
-    if (n >= 0 && n + 4 < Ns) {
-      const unsigned vo = (base + (unsigned)n) * B;
+      const_cast<void *>(P.rf), (short)0, P.n_angles * P.n_channels * Ns * B, kRawBufferWord3);
+  const QuadWalk w = quad_walk(win >> 2);
+  if (!w.active) return;
+  for (int jq = w.jq; jq < (win >> 2); jq += w.djq) {
+    const int j0 = jq << 2;
+    const float m0 = (float)(off - j0);  // delay coordinate of entry j0
+    for (int row = w.row0; row < rows; row += w.drow) {
+      const int2 rb = s_row[row];
+      const int n = rb.y + j0;
+      float u[5];
+      if ((unsigned)n < lim) {
+        const unsigned vo = (unsigned)(rb.x + n) * B;
 #pragma unroll
-      for (int k = 0; k < 5; ++k) u[k] = R::load(res, vo + k * B);
-    } else {
+        for (int k = 0; k < 5; ++k) u[k] = R::load(res, vo + k * B);
+      } else {
 #pragma unroll
-      for (int k = 0; k < 5; ++k) {
-        const int i = n + k;
-        const float v = R::load(res, (base + (unsigned)min(max(i, 0), Ns - 1)) * B);
-        u[k] = (unsigned)i < (unsigned)Ns ? v : 0.f;
+        for (int k = 0; k < 5; ++k) {
+          const int i = n + k;
+          const float v = R::load(res, (unsigned)(rb.x + min(max(i, 0), Ns - 1)) * B);
+          u[k] = (unsigned)i < (unsigned)Ns ? v : 0.f;
+        }
       }
-    }
-    if (e > last) {
+      float v8[8];
 #pragma unroll
-      for (int k = 0; k < 5; ++k) u[k] = 0.f;
+      for (int k = 0; k < 4; ++k) {
+        const float du = u[k + 1] - u[k];
+        v8[2 * k] = MODE == kDas ? fmaf(m0 - (float)k, du, u[k]) : u[k];
+        v8[2 * k + 1] = du;
+      }
+      float4 *dst = (float4 *)(s_pairs + __mul24(row, win) + j0);
+      dst[0] = make_float4(v8[0], v8[1], v8[2], v8[3]);
+      dst[1] = make_float4(v8[4], v8[5], v8[6], v8[7]);
     }
-    float v8[8];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const float du = u[k + 1] - u[k];
-      v8[2 * k] = MODE == kDas ? fmaf((float)(off - j0 - k), du, u[k]) : u[k];
-      v8[2 * k + 1] = du;
-    }
-    float4 *dst = (float4 *)(s_pairs + __mul24(row, win) + j0);
-    dst[0] = make_float4(v8[0], v8[1], v8[2], v8[3]);
-    dst[1] = make_float4(v8[4], v8[5], v8[6], v8[7]);
   }
 }
 
 // Stage the complex windows of the IQ modes: as stage_windows for DAS, with
 // each entry the lines of the real and imaginary parts, (b_re, d_re, b_im, d_im)
 // (16 bytes), from complex float32 samples.
-__device__ __forceinline__ void stage_windows_iq(const FramePlan &P, int e0, int nch, int e_end,
-                                                 const int *s_lt, const int *s_lr,
-                                                 float4 *s_ent) {
-  const int A = P.n_angles, N = P.n_channels, Ns = P.n_samples, win = P.win;
-  const int off = P.off_t + P.off_r;
-  const int W4 = win >> 2;
-  const int total = nch * A * W4;  // at most kMaxLdsBytes / 64 = 2^10 quads
-  const float rw = __builtin_amdgcn_rcpf((float)W4), ra = __builtin_amdgcn_rcpf((float)A);
-  const float hw = 0.5f * rw, ha = 0.5f * ra;
-  const int last = min(e_end, N) - 1;
+__device__ __forceinline__ void stage_windows_iq(const FramePlan &P, int rows, int off,
+                                                 const int2 *s_row, float4 *s_ent) {
+  const int Ns = P.n_samples, win = P.win;
+  const unsigned lim = (unsigned)max(Ns - 4, 0);
   const __amdgpu_buffer_rsrc_t res = __builtin_amdgcn_make_buffer_rsrc(
-      const_cast<void *>(P.rf), (short)0, A * N * Ns * 8, kRawBufferWord3);
-  for (int q = threadIdx.x; q < total; q += blockDim.x) {
-    const int row = (int)fmaf((float)q, rw, hw);
-    const int j0 = (q - __mul24(row, W4)) << 2;
-    const int c = (int)fmaf((float)row, ra, ha);
-    const int a = row - __mul24(c, A);
-    const int e = e0 + c;
-    const int n = s_lt[a] + s_lr[c] + j0;
-    const unsigned base = __umul24((unsigned)(__mul24(a, N) + min(e, last)), (unsigned)Ns);
-    float ur[5], ui[5];
+      const_cast<void *>(P.rf), (short)0, P.n_angles * P.n_channels * Ns * 8, kRawBufferWord3);
+  const QuadWalk w = quad_walk(win >> 2);
+  if (!w.active) return;
+  for (int jq = w.jq; jq < (win >> 2); jq += w.djq) {
+    const int j0 = jq << 2;
+    const float m0 = (float)(off - j0);
+    for (int row = w.row0; row < rows; row += w.drow) {
+      const int2 rb = s_row[row];
+      const int n = rb.y + j0;
+      float ur[5], ui[5];
+      if ((unsigned)n < lim) {
+        const unsigned vo = (unsigned)(rb.x + n) * 8u;
 #pragma unroll
-    for (int k = 0; k < 5; ++k) {
-      const int i = n + k;
-      const unsigned vo = (base + (unsigned)min(max(i, 0), Ns - 1)) * 8u;
-      const float re = __int_as_float((int)__builtin_amdgcn_raw_buffer_load_b32(res, (int)vo, 0, 0));
-      const float im =
-          __int_as_float((int)__builtin_amdgcn_raw_buffer_load_b32(res, (int)(vo + 4u), 0, 0));
-      const bool in = (unsigned)i < (unsigned)Ns && e <= last;
-      ur[k] = in ? re : 0.f;
-      ui[k] = in ? im : 0.f;
-    }
-    float4 *dst = s_ent + __mul24(row, win) + j0;
+        for (int k = 0; k < 5; ++k) {
+          ur[k] = __int_as_float((int)__builtin_amdgcn_raw_buffer_load_b32(res, (int)(vo + 8 * k), 0, 0));
+          ui[k] = __int_as_float(
+              (int)__builtin_amdgcn_raw_buffer_load_b32(res, (int)(vo + 8 * k + 4), 0, 0));
+        }
+      } else {
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const float m = (float)(off - j0 - k);
-      const float dr = ur[k + 1] - ur[k], di = ui[k + 1] - ui[k];
-      dst[k] = make_float4(fmaf(m, dr, ur[k]), dr, fmaf(m, di, ui[k]), di);
+        for (int k = 0; k < 5; ++k) {
+          const int i = n + k;
+          const unsigned vo = (unsigned)(rb.x + min(max(i, 0), Ns - 1)) * 8u;
+          const float re =
+              __int_as_float((int)__builtin_amdgcn_raw_buffer_load_b32(res, (int)vo, 0, 0));
+          const float im =
+              __int_as_float((int)__builtin_amdgcn_raw_buffer_load_b32(res, (int)(vo + 4u), 0, 0));
+          const bool in = (unsigned)i < (unsigned)Ns;
+          ur[k] = in ? re : 0.f;
+          ui[k] = in ? im : 0.f;
+        }
+      }
+      float4 *dst = s_ent + __mul24(row, win) + j0;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const float m = m0 - (float)k;
+        const float dr = ur[k + 1] - ur[k], di = ui[k + 1] - ui[k];
+        dst[k] = make_float4(fmaf(m, dr, ur[k]), dr, fmaf(m, di, ui[k]), di);
+      }
     }
   }
 }
@@ -197,14 +226,33 @@ __device__ __forceinline__ int floor_i32(float s) {
   return n;
 }
 
-// Apodization weight for r = |x - x_e| / half-aperture: hk cos(pi r) + hb inside
-// the aperture (Hann: hk = hb = 1/2; boxcar: hk = 0, hb = 1), 0 outside. r is NaN
-// or inf when z <= 0, which falls outside. "none" passes r = 0, so w = 1. The
-// hardware cosine takes its argument in revolutions; clamping keeps it in range
-// and makes the evaluation unconditional.
-__device__ __forceinline__ float apod_weight(float r, float hk, float hb) {
-  const float c = __builtin_amdgcn_cosf(0.5f * fminf(r, 1.f));
-  return r < 1.f ? fmaf(hk, c, hb) : 0.f;
+// Apodization weight for h = |x - x_e| / (2 half-apertures), i.e. half the
+// normalised aperture distance r: hk cos(pi r) + hb inside the aperture (Hann:
+// hk = hb = 1/2; boxcar: hk = 0, hb = 1), 0 outside. h is NaN or inf when
+// z <= 0, which falls outside. "none" passes h = 0, so w = 1. The hardware
+// cosine takes its argument in revolutions (cos(pi r) = cos(2 pi h)); clamping
+// keeps it in range and makes the evaluation unconditional. The pixel's scale
+// carries the factor 1/2 (exact), so h < 1/2 holds exactly where r < 1 does.
+template <bool SEL>
+__device__ __forceinline__ float apod_weight(float h, float hk, float hb) {
+  const float c = __builtin_amdgcn_cosf(fminf(h, 0.5f));
+  // Hann and "none" need no aperture test: at h >= 1/2 the clamped cosine is
+  // that of half a revolution, which the hardware returns as exactly -1, so the
+  // Hann weight 1/2 + c/2 is exactly 0 (and "none" has h = 0). Boxcar does.
+  if constexpr (SEL) return h < 0.5f ? fmaf(hk, c, hb) : 0.f;
+  return fmaf(hk, c, hb);
+}
+
+// Window origin LR = floor(min over the tile of rx) - 1 for an element at
+// lateral offset dq = Xq - Xe from the tile's reference column: the tile point
+// nearest the element, over lateral offsets [dq + dxlo, dq + dxhi] and depths
+// [zlo, zhi]. The margin of one sample absorbs the float rounding, including
+// the hardware square root's (under 1 ulp).
+__device__ __forceinline__ float window_lr(float dq, float dxlo, float dxhi, float zlo,
+                                           float zhi) {
+  const float ddx = fmaxf(fmaxf(dq + dxlo, -(dq + dxhi)), 0.f);
+  const float ddz = zlo > 0.f ? zlo : (zhi < 0.f ? -zhi : 0.f);
+  return floorf(__builtin_amdgcn_sqrtf(fmaf(ddx, ddx, ddz * ddz))) - 1.f;
 }
 
 // Float-float arithmetic (value = hi + lo) from error-free transformations; used
@@ -246,6 +294,7 @@ __device__ __forceinline__ float ff_f(ff a) { return a.hi + a.lo; }
 // skipped (generic bucket), else exactly AM == A angles, fully unrolled.
 // ONEGRP: one lane group per wavefront (cpw == 1), so the LDS window of a
 // channel is the same for the whole wavefront and its address stays scalar.
+// SEL: the apodization weight carries the aperture test (needed for boxcar).
 //
 // Delays of pixel p are formed relative to the tile's reference pixel q:
 //   transmit  tx(p) - LT - off_t = [tx(q) - LT - off_t] + dx sin + dz cos,
@@ -257,31 +306,41 @@ __device__ __forceinline__ float ff_f(ff a) { return a.hi + a.lo; }
 // quantity on the per-gather path is then a small offset inside the tile's
 // window, accurate to ~1e-6 samples, instead of an absolute delay rounded at
 // ~1e-4 samples.
-template <int AM, bool PRED, int MODE, bool ONEGRP>
-__device__ __forceinline__ void process_tile(const FramePlan &P, int tz, int tx,
-                                             unsigned char *smem) {
+template <int AM, bool PRED, int MODE, bool ONEGRP, bool SEL>
+__device__ __forceinline__ void process_tile_body(const FramePlan &P, int tz, int tx,
+                                                  unsigned char *smem) {
   constexpr bool IQ = is_iq_mode(MODE);
   float *s_txq = (float *)smem;                        // [kMaxAngles] tx(q) - LT
   int *s_lt = (int *)(smem + kMaxAngles * 4);          // [kMaxAngles] LT
   float2 *s_tph = (float2 *)(smem + kMaxAngles * 8);   // [kMaxAngles] IQ: exp(2 pi i r (LT + off_t))
   float4 *s_ch = (float4 *)(smem + kLdsAngleBytes);    // [chunk] {Dq, rq^2, rq, rx(q) - LR}
   float2 *s_ph = (float2 *)(smem + plan_lds_ph_offset(P));  // [chunk] IQ: exp(2 pi i r (LR + off_r))
-  int *s_lr = (int *)(smem + plan_lds_lr_offset(P));   // [chunk] LR
+  int2 *s_row = (int2 *)(smem + plan_lds_row_offset(P));  // [chunk * A] window rows
   float2 *s_pairs = (float2 *)(smem + plan_lds_win_offset(P));
 
   const int tid = threadIdx.x;
-  const int lane = tid & (kWave - 1), wave = tid / kWave;
+  const int lane = tid & (kWave - 1);
+  const int wave = __builtin_amdgcn_readfirstlane(tid / kWave);  // uniform
   const int cpw = ONEGRP ? 1 : P.cpw;
   const int ppw = kWave / cpw;  // lanes per group
   const int pl = lane & (ppw - 1), grp = ONEGRP ? 0 : lane / ppw;
   const int lz = P.lz, lx = P.lx;  // a group's pixels: lz along depth by lx along x
-  const int wzi = wave % P.wz, wxi = wave / P.wz;
+  // wave / wz for wave < 8 and wz <= 8 through a float reciprocal ((wave + 0.5) /
+  // wz lies at least 1 / 16 from an integer); lz is a power of two
+  const int wxi = (int)((wave + 0.5f) * __builtin_amdgcn_rcpf((float)P.wz));
+  const int wzi = wave - wxi * P.wz;
+  const int lzs = __builtin_ctz(lz);
   const int TZ = P.tile_z, TX = P.tile_x;
   const int iz0 = tz * TZ, ix0 = tx * TX;
-  const int iz = iz0 + wzi * lz + (pl & (lz - 1)), ix = ix0 + wxi * lx + pl / lz;
+  const int iz = iz0 + wzi * lz + (pl & (lz - 1)), ix = ix0 + wxi * lx + (pl >> lzs);
   const int A = PRED ? P.n_angles : AM;
   const int N = P.n_channels, win = P.win, chunk = P.chunk;
-  const float hk = P.apod == kHann ? 0.5f : 0.f, hb = 1.f - hk;
+  // hk in a scalar register, hb in a vector one: the weight's FMA may read only
+  // one scalar operand, and an opaque hb is not re-derived in every iteration
+  const float hk = __int_as_float(
+      __builtin_amdgcn_readfirstlane(__float_as_int(P.apod == kHann ? 0.5f : 0.f)));
+  float hb = P.apod == kHann ? 0.5f : 1.f;
+  asm("" : "+v"(hb));
 
   // Tile extent, clipped to the grid: lanes past the edge evaluate the edge
   // pixel again and write nothing, so every window only spans grid pixels.
@@ -297,9 +356,11 @@ __device__ __forceinline__ void process_tile(const FramePlan &P, int tz, int tx,
   const ff Zq = ff_add(ff_mul({(float)izq, 0.f}, {P.DZ, P.DZl}), {P.Z0, P.Z0l});
   const float Zqf = ff_f(Zq);
   const float Zp = Zqf + dz;
-  const float invA = P.apod == kNone ? 0.f : (Zp > 0.f ? P.ap_k / Zp : __builtin_inff());
+  // half the aperture scale: |x - x_e| * hA is half the normalised distance r
+  const float hA = P.apod == kNone ? 0.f : (Zp > 0.f ? 0.5f * (P.ap_k / Zp) : __builtin_inff());
   const float cp = fmaf(2.f * Zqf, dz, fmaf(dx, dx, dz * dz));
-  const float dx2 = 2.f * dx;
+  float dx2 = 2.f * dx;
+  asm("" : "+v"(dx2));  // computed once, not again in every channel iteration
 
   // Active aperture of the tile. A channel whose apodization weight is zero at
   // every pixel of the tile adds exactly nothing to any sum (w * acc with w = 0
@@ -372,36 +433,43 @@ __device__ __forceinline__ void process_tile(const FramePlan &P, int tz, int tx,
     if (e0 > e_lo) __syncthreads();  // the previous chunk's windows have been read
     const int cnt = min(chunk, e_hi - e0);                   // channels of this chunk
     const int cnt_pad = ONEGRP ? cnt : (cnt + cpw - 1) / cpw * cpw;  // rows read
-    // Per-channel tile constants: window origin LR = floor(min_tile rx) - 1 (the
-    // tile point nearest the element), the reference delay rx(q) in
-    // float-float, and the terms of the receive-delay difference.
-    for (int c = tid; c < cnt_pad; c += blockDim.x) {
+    // Per-channel tile constants: the window origin LR, the reference delay
+    // rx(q) in float-float, and the terms of the receive-delay difference;
+    // channel c is taken by thread blockDim - 1 - c, so that these run in other
+    // wavefronts than the row table below, which starts at thread 0.
+    for (int c = (int)blockDim.x - 1 - tid; c < cnt_pad; c += blockDim.x) {
       const int e = min(e0 + c, N - 1);
       const ff xe = {P.xe[e], P.xel[e]};
       const ff dq = ff_add(Xq, ff_neg(xe));
       const ff rq2 = ff_add(ff_mul(dq, dq), ff_mul(Zq, Zq));
       const ff rq = ff_sqrt(rq2);
       const float dqf = ff_f(dq);
-      // lateral offsets X - Xe over the tile span [dq + dxlo, dq + dxhi]
-      const float ddx = fmaxf(fmaxf(dqf + dxlo, -(dqf + dxhi)), 0.f);
-      const float zlo = Zqf + dzlo, zhi = Zqf + dzhi;
-      const float ddz = zlo > 0.f ? zlo : (zhi < 0.f ? -zhi : 0.f);
-      const float rmin = sqrtf(fmaf(ddx, ddx, ddz * ddz));
-      const float lr = floorf(rmin) - 1.f;
+      const float lr = window_lr(dqf, dxlo, dxhi, Zqf + dzlo, Zqf + dzhi);
       s_ch[c] = make_float4(dqf, ff_f(rq2), ff_f(rq) + 1e-20f,
                             ff_f(ff_add(rq, {-(lr + (float)P.off_r), 0.f})));
-      s_lr[c] = (int)lr;
       if constexpr (IQ) s_ph[c] = carrier_phasor((int)lr + P.off_r, P.iq_r, P.iq_rl);
+    }
+    // Window rows r = c A + a: the record of (angle a, channel e0 + c) and the
+    // first sample LT_a + LR (LR from the same expression as above); rows of
+    // padding channels (past e_hi) read all zero.
+    const int rows = cnt_pad * A, off = P.off_t + P.off_r;
+    for (int r = tid; r < rows; r += blockDim.x) {
+      const int c = r / A, a = r - c * A;
+      const int e = min(e0 + c, N - 1);
+      const float dqf = ff_f(ff_add(Xq, ff_neg({P.xe[e], P.xel[e]})));
+      const float lr = window_lr(dqf, dxlo, dxhi, Zqf + dzlo, Zqf + dzhi);
+      s_row[r] = make_int2(__mul24(__mul24(a, N) + e, P.n_samples),
+                           e0 + c < e_hi ? s_lt[a] + (int)lr : -(1 << 30));
     }
     __syncthreads();
     if constexpr (IQ)
-      stage_windows_iq(P, e0, cnt_pad, e_hi, s_lt, s_lr, (float4 *)s_pairs);
+      stage_windows_iq(P, rows, off, s_row, (float4 *)s_pairs);
     else if (P.dtype == kI16)
-      stage_windows<kI16, MODE>(P, e0, cnt_pad, e_hi, s_lt, s_lr, s_pairs);
+      stage_windows<kI16, MODE>(P, rows, off, s_row, s_pairs);
     else if (P.dtype == kF16)
-      stage_windows<kF16, MODE>(P, e0, cnt_pad, e_hi, s_lt, s_lr, s_pairs);
+      stage_windows<kF16, MODE>(P, rows, off, s_row, s_pairs);
     else
-      stage_windows<kF32, MODE>(P, e0, cnt_pad, e_hi, s_lt, s_lr, s_pairs);
+      stage_windows<kF32, MODE>(P, rows, off, s_row, s_pairs);
     __syncthreads();
 
     const int wstride = win * P.entry_bytes;  // bytes between angle windows
@@ -412,7 +480,7 @@ __device__ __forceinline__ void process_tile(const FramePlan &P, int tz, int tx,
       const float num = fmaf(dx2, ch.x, cp);
       const float den = __builtin_amdgcn_sqrtf(ch.y + num) + ch.z;
       const float rxl = fmaf(num, __builtin_amdgcn_rcpf(den), ch.w);
-      const float w = apod_weight(fabsf(ch.x + dx) * invA, hk, hb);
+      const float w = apod_weight<SEL>(fabsf(ch.x + dx) * hA, hk, hb);
       // delays are centred: entry n of the window is read as n + off_t + off_r
       const char *wb = (const char *)s_pairs +
                        ((size_t)c * A * win + P.off_t + P.off_r) * (IQ ? 16 : 8);
@@ -585,6 +653,22 @@ __device__ __forceinline__ void process_tile(const FramePlan &P, int tz, int tx,
     y = 0.5f * (sq - Q);
   }
   if (grp == 0 && ix < P.nx && iz < P.nz) P.out[(size_t)ix * P.nz + iz] = y;
+}
+
+// The tile body for plan P. The exact-angle DAS kernels of one lane group
+// carry a second body without the aperture test in the weight (Hann, none),
+// two fewer instructions per (pixel, channel); every other kernel and boxcar
+// apodization take the general one.
+template <int AM, bool PRED, int MODE, bool ONEGRP>
+__device__ __forceinline__ void process_tile(const FramePlan &P, int tz, int tx,
+                                             unsigned char *smem) {
+  if constexpr (MODE == kDas && ONEGRP && !PRED) {
+    if (P.apod != kBoxcar) {
+      process_tile_body<AM, PRED, MODE, ONEGRP, false>(P, tz, tx, smem);
+      return;
+    }
+  }
+  process_tile_body<AM, PRED, MODE, ONEGRP, true>(P, tz, tx, smem);
 }
 
 }  // namespace dev

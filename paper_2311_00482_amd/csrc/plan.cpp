@@ -224,7 +224,7 @@ static int fit_tile(const pwbf_geometry *g, pwbf_tile t, FramePlan *P, std::stri
   // a tile's pixels never extend past the grid (edge lanes repeat the edge pixel)
   P->win = window_entries(*P, std::min(TZ, g->nz), std::min(TX, g->nx));
   const size_t per_channel =
-      (size_t)P->n_angles * P->win * P->entry_bytes + (is_iq_mode(P->mode) ? 28 : 20);
+      (size_t)P->n_angles * (P->win * P->entry_bytes + 8) + (is_iq_mode(P->mode) ? 24 : 16);
   const size_t fixed = kLdsAngleBytes + 16;
   int chunk = t.chunk;
   if (chunk == 0) {

@@ -75,20 +75,19 @@ struct PostPlan {
   float floor_db;
 };
 
-// LDS layout of one block: per-angle tile constants (float txl, int origin),
-// per-channel tile constants (float4) and origins (int), then the windows.
 // LDS of a block: per angle {tx(q) - LT, LT, transmit phasor} (16 bytes), per
-// channel of the chunk {Dq, rq^2, rq, rx(q) - LR} (16), the receive phasor (8,
-// IQ modes only) and LR (4), then the windows.
+// channel of the chunk {Dq, rq^2, rq, rx(q) - LR} (16) and the receive phasor
+// (8, IQ modes only), per window row (channel, angle) of the chunk its record
+// offset and first sample (8), then the windows.
 constexpr size_t kLdsAngleBytes = kMaxAngles * 16;
 PWBF_HD inline size_t plan_lds_ph_offset(const FramePlan &p) {
   return kLdsAngleBytes + (size_t)p.chunk * 16;
 }
-PWBF_HD inline size_t plan_lds_lr_offset(const FramePlan &p) {
+PWBF_HD inline size_t plan_lds_row_offset(const FramePlan &p) {
   return plan_lds_ph_offset(p) + (is_iq_mode(p.mode) ? (size_t)p.chunk * 8 : 0);
 }
 PWBF_HD inline size_t plan_lds_win_offset(const FramePlan &p) {
-  return (plan_lds_lr_offset(p) + (size_t)p.chunk * 4 + 15) / 16 * 16;
+  return (plan_lds_row_offset(p) + (size_t)p.chunk * p.n_angles * 8 + 15) / 16 * 16;
 }
 PWBF_HD inline size_t plan_lds_bytes(const FramePlan &p) {
   return plan_lds_win_offset(p) + (size_t)p.chunk * p.n_angles * p.win * p.entry_bytes;

@@ -41,6 +41,9 @@ SMALL = [
     ("das_one_column", dict(nx=1, nz=300), "das", 0, (1, 64, 3, 1, 0), "f32"),
     ("das_boxcar", dict(apod="boxcar"), "das", 0, None, "f32"),
     ("das_no_apod_near_array", dict(apod="none", z_min=-1e-3, z_max=4e-3), "das", 0, None, "f32"),
+    ("das_hann_near_array_cpw1", dict(z_min=-1e-3, z_max=4e-3), "das", 0, (1, 16, 1, 2, 0), "f32"),
+    ("compound_3a_boxcar_cpw1", dict(apod="boxcar", angles_deg=(-12.0, 0.0, 9.0)), "das", -1,
+     (1, 16, 1, 2, 0), "f32"),
     ("das_record_too_short", dict(n_samples=120), "das", 0, None, "f32"),
     ("compound_3a", dict(angles_deg=(-12.0, 0.0, 9.0)), "das", -1, None, "f32"),
     ("compound_7a_t0", dict(angles_deg=(-15., -10., -5., 0., 5., 10., 15.),

@@ -73,6 +73,28 @@ def log_err_db(gpu_log, ora_log, above=-40.0):
     return float(np.abs(gpu_log[m] - ora_log[m]).max())
 
 
+@pytest.mark.parametrize("apod", ["hann", "boxcar"])
+def test_outside_aperture_adds_exact_zero(apod):
+    # One live channel: every pixel whose normalised aperture distance from it,
+    # r = |x - x_e| 2 F# / z, is 1 or more (or z <= 0) must come out exactly 0.
+    g = geom(n_channels=16, nx=64, nz=80, x_min=-6e-3, x_max=6e-3, z_min=-0.5e-3,
+             z_max=9e-3, angles_deg=(-7.0, 0.0, 7.0), apod=apod)
+    rf = rand_rf(g, 21)
+    live = 11
+    rf[:, np.arange(g.n_channels) != live] = 0.0
+    # one lane group per wavefront: the exact-angle DAS kernels (both bodies)
+    from paper_2311_00482_amd import Tile
+    out = run(g, to_dev(rf), "das", -1, ("rf",), tile=Tile(1, 8, 2, 4, 0))["rf"]
+    X, Z = np.meshgrid(g.x_pix, g.z_pix, indexing="ij")
+    with np.errstate(divide="ignore", invalid="ignore"):
+        r = np.abs(X - g.elem_x[live]) * 2.0 * g.f_number / Z
+    # a margin of 1e-6 keeps pixels whose r rounds across 1 out of the check
+    outside = (Z <= 0) | (r >= 1.0 + 1e-6)
+    assert outside.sum() > 100 and (~outside).sum() > 100
+    assert np.all(out[outside] == 0.0)
+    assert np.abs(out[~outside]).max() > 0.0
+
+
 # ---------------------------------------------------------------- C1: 64 ch, 0 deg
 @pytest.fixture(scope="module")
 def c1():
