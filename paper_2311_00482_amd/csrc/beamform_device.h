@@ -658,7 +658,8 @@ __device__ __forceinline__ void process_tile_body(const FramePlan &P, int tz, in
 // The tile body for plan P. The exact-angle DAS kernels of one lane group
 // carry a second body without the aperture test in the weight (Hann, none),
 // two fewer instructions per (pixel, channel); every other kernel and boxcar
-// apodization take the general one.
+// apodization take the general one. (The persistent batch and serve kernels
+// call the general body directly: there the second body costs registers.)
 template <int AM, bool PRED, int MODE, bool ONEGRP>
 __device__ __forceinline__ void process_tile(const FramePlan &P, int tz, int tx,
                                              unsigned char *smem) {

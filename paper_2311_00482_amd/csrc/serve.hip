@@ -71,10 +71,11 @@ __global__ void __launch_bounds__(kWave * kServeWaves)
     const int t = it - al.tile0[k];
     const int q = t / P.tiles_x;
     const int tz = P.tiles_z - 1 - q, tx = t - q * P.tiles_x;
+    // the general tile body, as in the batch kernels
     if constexpr (AB == 3)
-      dev::process_tile<kServeMaxAngles, true, MODE, ONEGRP>(P, tz, tx, smem);
+      dev::process_tile_body<kServeMaxAngles, true, MODE, ONEGRP, true>(P, tz, tx, smem);
     else
-      dev::process_tile<AB == 0 ? 1 : (AB == 1 ? 5 : 11), false, MODE, ONEGRP>(P, tz, tx, smem);
+      dev::process_tile_body<AB == 0 ? 1 : (AB == 1 ? 5 : 11), false, MODE, ONEGRP, true>(P, tz, tx, smem);
   }
 }
 
