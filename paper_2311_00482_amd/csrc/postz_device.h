@@ -28,16 +28,21 @@ __device__ __forceinline__ float analytic_weight(int k, int n) {
 }
 
 // Post-process column ix of the frame described by Q, with LDS at sm
-// (post_lds_bytes(nz)).
+// (post_lds_bytes(nz)). LZ > 0: the column length is 2^LZ, known at compile
+// time (loop bounds and the transform fixed); LZ = 0: Q.log2nz at run time.
+template <int LZ = 0>
 __device__ __forceinline__ void postz_column(const PostPlan &Q, int ix, float2 *sm) {
-  const int nz = Q.nz, L = Q.log2nz, half_n = nz >> 1;
+  const int L = LZ ? LZ : Q.log2nz, nz = 1 << L, half_n = nz >> 1;
   float2 *x = sm;  // the column, padded layout
   const int tid = threadIdx.x;
   const float *src = Q.src + (size_t)ix * nz;
 
   for (int k = tid; k < nz; k += kPostThreads) x[fft::pad(k)] = make_float2(src[k], 0.f);
   __syncthreads();
-  fft::transform_any<false>(x, L);
+  if constexpr (LZ > 0)
+    fft::transform<LZ, false>(x);
+  else
+    fft::transform_any<false>(x, L);
 
   // analytic-signal weights, band mask, and the 1/nz of the inverse
   const float inv_n = 1.0f / (float)nz;
@@ -51,7 +56,10 @@ __device__ __forceinline__ void postz_column(const PostPlan &Q, int ix, float2 *
     x[fft::pad(k)] = make_float2(v.x * h * inv_n, v.y * h * inv_n);
   }
   __syncthreads();
-  fft::transform_any<true>(x, L);
+  if constexpr (LZ > 0)
+    fft::transform<LZ, true>(x);
+  else
+    fft::transform_any<true>(x, L);
 
   float m = 0.f;
   for (int k = tid; k < nz; k += kPostThreads) {
