@@ -325,43 +325,45 @@ __global__ void __launch_bounds__(kPostThreads) k_fk_itime(FkPlan F) {
   }
 }
 
-// Integer part and fraction of v0 + k1 c1 + k2 c2 for float-float v0, c1, c2
-// and integers 0 <= k1, k2 < 2^24: both products split exactly (one FMA each),
-// the large terms summed with error-free additions, the small ones added once;
-// the fraction is accurate to ~1e-7 of an index step. Returns false when the
-// value is outside (lo, hi), before any conversion to an integer.
-__device__ __forceinline__ bool map_index(float v0h, float v0l, float k1, float c1h, float c1l,
-                                          float k2, float c2h, float c2l, float lo, float hi,
-                                          int *idx, float *frac) {
+// Integer part and fraction of v0 + k c for float-float v0, c and an integer
+// 0 <= k < 2^24: the product split exactly (one FMA), the large terms summed
+// with an error-free addition, the small ones added once; the fraction is
+// accurate to ~1e-7 of an index step. Returns false when the value is outside
+// (lo, hi), before any conversion to an integer.
+__device__ __forceinline__ bool map_index(float v0h, float v0l, float k, float ch, float cl,
+                                          float lo, float hi, int *idx, float *frac) {
 #pragma clang fp contract(off)
-  const float p1 = k1 * c1h, e1 = fmaf(k1, c1h, -p1);
-  const float p2 = k2 * c2h, e2 = fmaf(k2, c2h, -p2);
-  const ff s = dev::two_sum(v0h, p1);
-  const ff t = dev::two_sum(s.hi, p2);
+  const float p = k * ch, e = fmaf(k, ch, -p);
+  const ff t = dev::two_sum(v0h, p);
   if (!(t.hi > lo && t.hi < hi)) return false;
-  const float small = ((s.lo + t.lo) + (v0l + (e1 + e2))) + (k1 * c1l + k2 * c2l);
+  const float small = (t.lo + (v0l + e)) + k * cl;
   const float fl = floorf(t.hi);
-  float f = (t.hi - fl) + small;
-  int i = (int)fl;
-  if (f < 0.f) {
-    f += 1.f;
-    --i;
-  } else if (f >= 1.f) {
-    f -= 1.f;
-    ++i;
-  }
-  *idx = i;
-  *frac = f;
+  const float f = (t.hi - fl) + small;
+  const float c = floorf(f);  // -1, 0 or 1: the small terms crossed an integer
+  *idx = (int)fl + (int)c;
+  *frac = f - c;
   return true;
 }
 
-// Blocks run along depth: block b covers pixels (ix, iz0 + threadIdx.x) with
-// ix = b / zchunks and iz0 = (b % zchunks) * 256.
+// Pixel (ix, iz) reads column ux0 + ix uxi + iz uxk and row uz0 + iz uzk of the
+// migrated image of each angle. A block is one image column: its lateral base
+// ux0 + ix uxi (float-float) is formed once per angle and shared through LDS.
 __global__ void __launch_bounds__(256) k_fk_image(FkPlan F, int zchunks) {
   const int nt = 1 << F.log2nt, nx1 = 1 << F.log2nx;
   const int ix = blockIdx.x / zchunks, iz = (blockIdx.x - ix * zchunks) * 256 + threadIdx.x;
   const bool mine = iz < F.nz_img;
-  const float fix = (float)ix, fiz = (float)iz;
+  const float fiz = (float)iz;
+  __shared__ float2 s_xb[kMaxAngles];
+  if (threadIdx.x < F.n_ang) {
+#pragma clang fp contract(off)
+    const FkAngleConst &A = F.ang[threadIdx.x];
+    const float fix = (float)ix;
+    const float p = fix * A.uxi_hi, e = fmaf(fix, A.uxi_hi, -p);
+    const ff t = dev::two_sum(A.ux0_hi, p);
+    const ff b = dev::two_sum(t.hi, (t.lo + (A.ux0_lo + e)) + fix * A.uxi_lo);
+    s_xb[threadIdx.x] = make_float2(b.hi, b.lo);
+  }
+  __syncthreads();
   float re = 0.f, im = 0.f;
   for (int a = 0; a < F.n_ang; ++a) {
     const FkAngleConst &A = F.ang[a];
@@ -369,18 +371,17 @@ __global__ void __launch_bounds__(256) k_fk_image(FkPlan F, int zchunks) {
     int i0, j0;
     float fx, fz;
     // far outside the migrated image: nothing to read (and no integer overflow)
-    if (!map_index(A.ux0_hi, A.ux0_lo, fix, A.uxi_hi, A.uxi_lo, fiz, A.uxk_hi, A.uxk_lo, -2.f,
-                   (float)(nx1 + 1), &i0, &fx))
+    const float2 xb = s_xb[a];
+    if (!map_index(xb.x, xb.y, fiz, A.uxk_hi, A.uxk_lo, -2.f, (float)(nx1 + 1), &i0, &fx))
       continue;
-    if (!map_index(A.uz0_hi, A.uz0_lo, 0.f, 0.f, 0.f, fiz, A.uzk_hi, A.uzk_lo, -2.f,
-                   (float)(nt + 1), &j0, &fz))
+    if (!map_index(A.uz0_hi, A.uz0_lo, fiz, A.uzk_hi, A.uzk_lo, -2.f, (float)(nt + 1), &j0, &fz))
       continue;
     const float2 *M = F.M + (size_t)a * nx1 * nt;
     // taps outside the window are outside [0, Nx) x [0, Nt) too (the window
     // holds every tap inside, with a margin), so they read as zero
     const int c1 = A.col0 + A.ncol, r1 = A.row0 + A.nrow;
     if (i0 >= A.col0 && i0 + 1 < c1 && j0 >= A.row0 && j0 + 1 < r1) {
-      const float2 *q = M + (size_t)i0 * nt + j0;
+      const float2 *q = M + (unsigned)(i0 * nt + j0);
       const float2 v00 = q[0], v01 = q[1], v10 = q[nt], v11 = q[nt + 1];
       const float w00 = (1.f - fx) * (1.f - fz), w01 = (1.f - fx) * fz;
       const float w10 = fx * (1.f - fz), w11 = fx * fz;
@@ -394,7 +395,7 @@ __global__ void __launch_bounds__(256) k_fk_image(FkPlan F, int zchunks) {
           const int i = i0 + di, j = j0 + dj;
           if (i >= A.col0 && i < c1 && j >= A.row0 && j < r1) {
             const float w = (di ? fx : 1.f - fx) * (dj ? fz : 1.f - fz);
-            const float2 v = M[(size_t)i * nt + j];
+            const float2 v = M[(unsigned)(i * nt + j)];
             re = fmaf(w, v.x, re);
             im = fmaf(w, v.y, im);
           }
