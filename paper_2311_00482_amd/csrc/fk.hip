@@ -65,19 +65,14 @@ __device__ __forceinline__ float frac_revs(int k, ff c) {
   return (p - floorf(p)) + fmaf(fk, c.lo, fmaf(fk, c.hi, -p));
 }
 
-// integer part and fraction of a float-float value (fraction in [0, 1))
+// integer part and fraction of a float-float value (fraction in [0, 1)),
+// |u| < 2^24
 __device__ __forceinline__ int split_index(ff u, float *frac) {
-  int i = (int)floorf(u.hi);
-  float f = (u.hi - (float)i) + u.lo;
-  if (f < 0.f) {
-    f += 1.f;
-    --i;
-  } else if (f >= 1.f) {
-    f -= 1.f;
-    ++i;
-  }
-  *frac = f;
-  return i;
+  const float fl = floorf(u.hi);
+  const float f = (u.hi - fl) + u.lo;
+  const float c = floorf(f);  // -1, 0 or 1: the low part crossed an integer
+  *frac = f - c;
+  return (int)fl + (int)c;
 }
 
 // a / b in float-float (one correction step)
@@ -180,6 +175,10 @@ __device__ __forceinline__ ff ff_sub_mul(ff v, ff u, float c_hi, float c_lo) {
   return dev::two_sum(d.hi, d.lo + (v.lo - e));
 }
 
+// The remap bodies below leave floating-point contraction on (their weights
+// and sums may fuse into FMAs); every error-free step sits in a helper that
+// turns it off.
+
 // The cells of a remap block: per thread a fixed set of kx columns m (one when
 // Nx <= 256) and, for each, every row of the block that falls to the thread.
 template <int L>
@@ -200,7 +199,6 @@ struct RemapCells {
 template <int L>
 __device__ __forceinline__ void stolt_rows(const FkAngleConst &A, const float2 *__restrict__ P,
                                            int j0, int kbins, float2 *x) {
-#pragma clang fp contract(off)
   constexpr int nx = 1 << L, ROWS = kFkRowPoints >> L, LR = 12 - L;
   constexpr int stride = fft::row_stride(nx, ROWS);
   static_assert((1 << LR) == ROWS, "rows of a block");
@@ -220,8 +218,8 @@ __device__ __forceinline__ void stolt_rows(const FkAngleConst &A, const float2 *
     // clamped loads, always issued; taps outside the spectrum weigh zero
     const bool ok = in_band && i0 >= 0 && i0 <= kbins - 1 && j0 + r < kbins;
     const int ia = ok ? i0 : 0, ib = min(ia + 1, kbins - 1);
-    const float2 *col = P + (size_t)m * kbins;
-    const float2 lo = col[ia], hi = col[ib];
+    const unsigned cb = (unsigned)(m * kbins);  // < 2^21 cells per angle
+    const float2 lo = P[cb + ia], hi = P[cb + ib];
     const float jac = ok ? fj * __builtin_amdgcn_rcpf(u.hi) : 0.f;
     const float wl = (1.f - w) * jac, wh = (ok && i0 + 1 <= kbins - 1) ? w * jac : 0.f;
     x[r * stride + fft::pad(m)] = make_float2(wl * lo.x + wh * hi.x, wl * lo.y + wh * hi.y);
@@ -237,7 +235,6 @@ __device__ __forceinline__ void stolt_rows(const FkAngleConst &A, const float2 *
 template <int L>
 __device__ __forceinline__ void lu_rows(const FkAngleConst &A, const float2 *__restrict__ P,
                                         int j0, int kbins, float2 *x) {
-#pragma clang fp contract(off)
   using C = RemapCells<L>;
   constexpr int stride = fft::row_stride(C::nx, C::ROWS);
   const float ch = 0.5f * A.m2_hi, cl = 0.5f * A.m2_lo;  // cos / 2
@@ -269,8 +266,8 @@ __device__ __forceinline__ void lu_rows(const FkAngleConst &A, const float2 *__r
       const bool ok = branch && i0 >= 0 && i0 <= kbins - 1;
       const int ia = ok ? i0 : 0, ib = min(ia + 1, kbins - 1);
       const int ma = m0 & (C::nx - 1), mb = (m0 + 1) & (C::nx - 1);  // periodic in kx
-      const float2 p00 = P[(size_t)ia * C::nx + ma], p01 = P[(size_t)ia * C::nx + mb];
-      const float2 p10 = P[(size_t)ib * C::nx + ma], p11 = P[(size_t)ib * C::nx + mb];
+      const unsigned ra = (unsigned)(ia * C::nx), rb = (unsigned)(ib * C::nx);  // < 2^21
+      const float2 p00 = P[ra + ma], p01 = P[ra + mb], p10 = P[rb + ma], p11 = P[rb + mb];
       const float jac = ok ? kzr * __builtin_amdgcn_rcpf(den.hi) : 0.f;
       const float hw = (ok && i0 + 1 <= kbins - 1) ? wu : 0.f;  // zeros past the last bin
       const float w00 = (1.f - wm) * (1.f - wu) * jac, w01 = wm * (1.f - wu) * jac;
