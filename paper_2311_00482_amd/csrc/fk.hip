@@ -5,9 +5,11 @@
 // transposes between channel-major and bin-major data happen in LDS, inside
 // blocks that hold several rows, so every global access is a contiguous run:
 //
-//  k_fk_time      block per (channel, angle): FFT of the trace (Nt samples); the
-//                 positive bins times exp(2 pi i k c_e) (the trace advanced by its
-//                 element's firing delay and shifted to t = 0) go to T[e][k]
+//  k_fk_time      block per (channel pair, angle): one complex FFT of two traces
+//                 (Nt samples each, as real and imaginary parts), split into the
+//                 two spectra; the positive bins times exp(2 pi i k c_e) (the trace
+//                 advanced by its element's firing delay and shifted to t = 0) go
+//                 to T[e][k]
 //  k_fk_space     block per (ROWS bins, angle): reads T[e][k0..k0+ROWS) for every
 //                 channel, FFTs along the array zero-padded to Nx, writes P[k][m]
 //                 (Lu) or P[m][k] (Stolt, whose remap reads along frequency)
@@ -85,29 +87,47 @@ __device__ __forceinline__ ff ff_div(ff a, ff b) {
 
 __device__ __forceinline__ int kbins_of(const FkPlan &F) { return (1 << F.log2nt) / 2 + 1; }
 
+// Two traces per block: channels e0 = 2 blockIdx.x and e0 + 1 go in as the
+// real and imaginary parts of one complex sequence z (a missing second trace
+// is zero). With Z its DFT and Z(Nt) = Z(0), the traces' spectra are
+// X0(k) = (Z(k) + conj Z(Nt - k)) / 2 and X1(k) = (Z(k) - conj Z(Nt - k)) / (2i).
 template <int DT>
 __global__ void __launch_bounds__(kPostThreads) k_fk_time(FkPlan F) {
   extern __shared__ __align__(16) float2 sm[];
-  const int nt = 1 << F.log2nt, kbins = kbins_of(F), e = blockIdx.x, a = blockIdx.y;
+  const int nt = 1 << F.log2nt, kbins = kbins_of(F), e0 = 2 * blockIdx.x, a = blockIdx.y;
+  const bool two = e0 + 1 < F.n_ch;
   float2 *x = sm;
-  const size_t base = ((size_t)a * F.n_ch + e) * nt;
-  for (int k = threadIdx.x; k < nt; k += kPostThreads)
-    x[fft::pad(k)] = make_float2(trace_sample<DT>(F.rf, base + k), 0.f);
+  const size_t base = ((size_t)a * F.n_ch + e0) * nt;
+  const size_t base1 = two ? base + nt : base;  // every read inside the record array
+  for (int k = threadIdx.x; k < nt; k += kPostThreads) {
+    const float v1 = trace_sample<DT>(F.rf, base1 + k);
+    x[fft::pad(k)] = make_float2(trace_sample<DT>(F.rf, base + k), two ? v1 : 0.f);
+  }
   __syncthreads();
   fft::transform_any<false>(x, F.log2nt);
   const FkAngleConst &A = F.ang[a];
-  const ff c = dev::ff_add({A.c0_hi, A.c0_lo}, dev::ff_mul(ffi(e), {A.c1_hi, A.c1_lo}));
-  float2 *T = F.T + ((size_t)a * F.n_ch + e) * kbins;
+  const ff c0 = dev::ff_add({A.c0_hi, A.c0_lo}, dev::ff_mul(ffi(e0), {A.c1_hi, A.c1_lo}));
+  const ff c1 = dev::ff_add({A.c0_hi, A.c0_lo}, dev::ff_mul(ffi(e0 + 1), {A.c1_hi, A.c1_lo}));
+  float2 *T0 = F.T + ((size_t)a * F.n_ch + e0) * kbins, *T1 = T0 + kbins;
   // exp(2 pi i k c) at the thread's first bin, then by the step of kPostThreads
   // bins: a thread's bins are at most 9 products from an accurate phase
   float sn, cs;
-  sincospif(2.0f * frac_revs(threadIdx.x, c), &sn, &cs);
-  float2 ph = make_float2(cs, sn);
-  sincospif(2.0f * frac_revs(kPostThreads, c), &sn, &cs);
-  const float2 step = make_float2(cs, sn);
+  sincospif(2.0f * frac_revs(threadIdx.x, c0), &sn, &cs);
+  float2 ph0 = make_float2(cs, sn);
+  sincospif(2.0f * frac_revs(kPostThreads, c0), &sn, &cs);
+  const float2 step0 = make_float2(cs, sn);
+  sincospif(2.0f * frac_revs(threadIdx.x, c1), &sn, &cs);
+  float2 ph1 = make_float2(cs, sn);
+  sincospif(2.0f * frac_revs(kPostThreads, c1), &sn, &cs);
+  const float2 step1 = make_float2(cs, sn);
   for (int k = threadIdx.x; k < kbins; k += kPostThreads) {
-    T[k] = dev::cmul(x[fft::pad(k)], ph);
-    ph = dev::cmul(ph, step);
+    const float2 z = x[fft::pad(k)], w = x[fft::pad((nt - k) & (nt - 1))];  // Z(k), Z(Nt - k)
+    const float2 x0 = make_float2(0.5f * (z.x + w.x), 0.5f * (z.y - w.y));
+    const float2 x1 = make_float2(0.5f * (z.y + w.y), 0.5f * (w.x - z.x));
+    T0[k] = dev::cmul(x0, ph0);
+    if (two) T1[k] = dev::cmul(x1, ph1);
+    ph0 = dev::cmul(ph0, step0);
+    ph1 = dev::cmul(ph1, step1);
   }
 }
 
@@ -451,12 +471,13 @@ hipError_t launch_fk(const FkPlan &F, int ncol_max, hipStream_t s) {
     hipLaunchKernelGGL(k_fk_clear, dim3(1), dim3(kMaxSlots), 0, s, F.ws_max);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
+  const dim3 pairs((F.n_ch + 1) / 2, F.n_ang);  // two traces per block
   if (F.dtype == kI16)
-    hipLaunchKernelGGL(k_fk_time<kI16>, dim3(F.n_ch, F.n_ang), blk, lds_t, s, F);
+    hipLaunchKernelGGL(k_fk_time<kI16>, pairs, blk, lds_t, s, F);
   else if (F.dtype == kF16)
-    hipLaunchKernelGGL(k_fk_time<kF16>, dim3(F.n_ch, F.n_ang), blk, lds_t, s, F);
+    hipLaunchKernelGGL(k_fk_time<kF16>, pairs, blk, lds_t, s, F);
   else
-    hipLaunchKernelGGL(k_fk_time<kF32>, dim3(F.n_ch, F.n_ang), blk, lds_t, s, F);
+    hipLaunchKernelGGL(k_fk_time<kF32>, pairs, blk, lds_t, s, F);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   switch (F.log2nx) {
     case 2: e = launch_rows<2>(F, s); break;
