@@ -96,6 +96,8 @@ __global__ void __launch_bounds__(kPostThreads) k_fk_time(FkPlan F) {
   extern __shared__ __align__(16) float2 sm[];
   const int nt = 1 << F.log2nt, kbins = kbins_of(F), e0 = 2 * blockIdx.x, a = blockIdx.y;
   const bool two = e0 + 1 < F.n_ch;
+  // the frame maximum that the image kernel, last of the call, folds into
+  if (F.ws_max && blockIdx.x == 0 && blockIdx.y == 0) dev::frame_max_clear(F.ws_max, threadIdx.x);
   float2 *x = sm;
   const size_t base = ((size_t)a * F.n_ch + e0) * nt;
   const size_t base1 = two ? base + nt : base;  // every read inside the record array
@@ -438,8 +440,6 @@ __global__ void __launch_bounds__(256) k_fk_image(FkPlan F, int zchunks) {
   }
 }
 
-__global__ void k_fk_clear(uint32_t *slots) { dev::frame_max_clear(slots, threadIdx.x); }
-
 template <int L>
 hipError_t launch_rows(const FkPlan &F, hipStream_t s) {
   constexpr int ROWS = kFkRowPoints >> L;
@@ -467,10 +467,6 @@ hipError_t launch_fk(const FkPlan &F, int ncol_max, hipStream_t s) {
   const size_t lds_t = fft::lds_bytes(nt, 1);
   const dim3 blk(kPostThreads);
   hipError_t e;
-  if (F.ws_max) {
-    hipLaunchKernelGGL(k_fk_clear, dim3(1), dim3(kMaxSlots), 0, s, F.ws_max);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-  }
   const dim3 pairs((F.n_ch + 1) / 2, F.n_ang);  // two traces per block
   if (F.dtype == kI16)
     hipLaunchKernelGGL(k_fk_time<kI16>, pairs, blk, lds_t, s, F);
