@@ -94,8 +94,9 @@ int fk_shape(const pwbf_geometry *g, int method, FkShape *s, std::string *err) {
 size_t round256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 // workspace: [max slots | T | P | U | M | envelope scratch], complex float32 for
-// the A angles of the call: T [A][N][Nt/2 + 1], P [A][Nt/2 + 1][Nx],
-// U [A][Nx][Nt/2 + 1], M [A][Nx][Nt] (P is [A][Nx][Nt/2 + 1] for Stolt's method)
+// the A angles of the call: T [A][Kb][N][R] (Kb R = Nt/2 + 1 rounded up to a
+// multiple of R = 4096 / Nx), P [A][Nt/2 + 1][Nx], U [A][Nx][Nt/2 + 1],
+// M [A][Nx][Nt] (P is [A][Nx][Nt/2 + 1] for Stolt's method)
 struct FkLayout {
   size_t T, P, U, M, env, total;
 };
@@ -104,7 +105,7 @@ FkLayout fk_layout(const pwbf_geometry *g, const FkShape &s, const pwbf_outputs 
   FkLayout L;
   const size_t npix = (size_t)g->nx * g->nz;
   L.T = pwbf::kMaxSlotBytes;
-  L.P = L.T + round256((size_t)n_ang * g->n_channels * s.kbins * 8);
+  L.P = L.T + round256((size_t)n_ang * g->n_channels * pwbf::fk_kbins_padded(s.log2nt, s.log2nx) * 8);
   L.U = L.P + round256((size_t)n_ang * s.kbins * s.nx * 8);
   L.M = L.U + round256((size_t)n_ang * s.nx * s.kbins * 8);
   L.env = L.M + round256((size_t)n_ang * s.nx * s.nt * 8);

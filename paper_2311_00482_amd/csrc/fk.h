@@ -39,7 +39,9 @@ struct FkPlan {
   int dtype, method;
   int n_ang, n_ch, log2nt, log2nx;
   int nx_img, nz_img;
-  float2 *T;  // [n_ang][n_ch][Nt/2 + 1]: shifted temporal spectra
+  float2 *T;  // [n_ang][Kb][n_ch][R]: shifted temporal spectra, bin k of channel e at
+              // block k / R, row k mod R, with R = kFkRowPoints / Nx (the bins of one
+              // kx-transform block) and Kb = ceil((Nt/2 + 1) / R)
   float2 *P;  // [n_ang][Nt/2 + 1][Nx] (Lu) or [n_ang][Nx][Nt/2 + 1] (Stolt): 2-D data spectra
   float2 *U;  // [n_ang][Nx][Nt/2 + 1]: remapped spectra after the inverse along kx
   float2 *M;  // [n_ang][Nx][Nt]: migrated complex images on (x1, z1), window only
@@ -50,6 +52,13 @@ struct FkPlan {
 
 // passed by value to every kernel: keep it inside the 4 KB kernel-argument budget
 static_assert(sizeof(FkPlan) <= 4000, "FkPlan too large for a kernel argument");
+
+// bins per block of T (and rows of a kx-transform block) for Nx = 2^log2nx, and
+// the bins of T per channel rounded up to whole blocks
+__host__ __device__ constexpr int fk_rows(int log2nx) { return kFkRowPoints >> log2nx; }
+__host__ __device__ constexpr int fk_kbins_padded(int log2nt, int log2nx) {
+  return ((1 << log2nt) / 2 + fk_rows(log2nx)) / fk_rows(log2nx) * fk_rows(log2nx);
+}
 
 hipError_t launch_fk(const FkPlan &F, int ncol_max, hipStream_t s);
 hipError_t launch_logc(const float *env, float *logimg, const uint32_t *ws_max, size_t n,

@@ -9,9 +9,10 @@
 //                 (Nt samples each, as real and imaginary parts), split into the
 //                 two spectra; the positive bins times exp(2 pi i k c_e) (the trace
 //                 advanced by its element's firing delay and shifted to t = 0) go
-//                 to T[e][k]
-//  k_fk_space     block per (ROWS bins, angle): reads T[e][k0..k0+ROWS) for every
-//                 channel, FFTs along the array zero-padded to Nx, writes P[k][m]
+//                 to T, blocked by the ROWS bins of one kx-transform block
+//  k_fk_space     block per (ROWS bins, angle): reads the bins k0..k0+ROWS of every
+//                 channel (one contiguous block of T), FFTs along the array
+//                 zero-padded to Nx, writes P[k][m]
 //                 (Lu) or P[m][k] (Stolt, whose remap reads along frequency)
 //  k_fk_remap     block per (ROWS image rows kz_j, angle): each cell (j, m) takes
 //                 the data spectrum from P -
@@ -110,7 +111,9 @@ __global__ void __launch_bounds__(kPostThreads) k_fk_time(FkPlan F) {
   const FkAngleConst &A = F.ang[a];
   const ff c0 = dev::ff_add({A.c0_hi, A.c0_lo}, dev::ff_mul(ffi(e0), {A.c1_hi, A.c1_lo}));
   const ff c1 = dev::ff_add({A.c0_hi, A.c0_lo}, dev::ff_mul(ffi(e0 + 1), {A.c1_hi, A.c1_lo}));
-  float2 *T0 = F.T + ((size_t)a * F.n_ch + e0) * kbins, *T1 = T0 + kbins;
+  // T[a][k / R][e][k mod R]: the pair's rows of a block are adjacent, 2 R bins
+  const int LR = 12 - F.log2nx, R = 1 << LR;
+  float2 *T0 = F.T + (size_t)a * F.n_ch * fk_kbins_padded(F.log2nt, F.log2nx) + e0 * R;
   // exp(2 pi i k c) at the thread's first bin, then by the step of kPostThreads
   // bins: a thread's bins are at most 9 products from an accurate phase
   float sn, cs;
@@ -126,8 +129,9 @@ __global__ void __launch_bounds__(kPostThreads) k_fk_time(FkPlan F) {
     const float2 z = x[fft::pad(k)], w = x[fft::pad((nt - k) & (nt - 1))];  // Z(k), Z(Nt - k)
     const float2 x0 = make_float2(0.5f * (z.x + w.x), 0.5f * (z.y - w.y));
     const float2 x1 = make_float2(0.5f * (z.y + w.y), 0.5f * (w.x - z.x));
-    T0[k] = dev::cmul(x0, ph0);
-    if (two) T1[k] = dev::cmul(x1, ph1);
+    float2 *t = T0 + (size_t)(k >> LR) * F.n_ch * R + (k & (R - 1));
+    t[0] = dev::cmul(x0, ph0);
+    if (two) t[R] = dev::cmul(x1, ph1);
     ph0 = dev::cmul(ph0, step0);
     ph1 = dev::cmul(ph1, step1);
   }
@@ -139,12 +143,12 @@ __global__ void __launch_bounds__(kPostThreads) k_fk_space(FkPlan F) {
   extern __shared__ __align__(16) float2 sm[];
   float2 *x = sm;
   const int kbins = kbins_of(F), k0 = blockIdx.x * ROWS, a = blockIdx.y;
-  const float2 *T = F.T + (size_t)a * F.n_ch * kbins;
-  // consecutive threads take consecutive bins of one channel
+  // the block's bins of every channel are one contiguous run of T (bins past
+  // the last are never written and read as zero)
+  const float2 *T = F.T + ((size_t)a * fk_kbins_padded(F.log2nt, L) + k0) * F.n_ch;
   for (int t = threadIdx.x; t < nx * ROWS; t += kPostThreads) {
     const int e = t / ROWS, r = t - e * ROWS, k = k0 + r;
-    x[r * stride + fft::pad(e)] =
-        (e < F.n_ch && k < kbins) ? T[(size_t)e * kbins + k] : make_float2(0.f, 0.f);
+    x[r * stride + fft::pad(e)] = (e < F.n_ch && k < kbins) ? T[t] : make_float2(0.f, 0.f);
   }
   __syncthreads();
   fft::transform<L, false, ROWS>(x);

@@ -413,11 +413,13 @@ def test_fk_workspace_and_argument_errors():
     W = L.pwbf_fk_workspace_bytes
     ST, LU = _abi.FK_STOLT, _abi.FK_LU
 
-    # T [128][2049], P [2049][Nx], U [Nx][2049], M [Nx][4096] per angle, complex
-    # float32; Nx = 256 (Stolt) or 512 (Lu)
+    # T [128][2049 rounded up to blocks of 4096 / Nx bins], P [2049][Nx],
+    # U [Nx][2049], M [Nx][4096] per angle, complex float32; Nx = 256 (Stolt)
+    # or 512 (Lu)
     def per(a, nx, n=128, nt=4096):
-        kb = nt // 2 + 1
-        return (r256(a * n * kb * 8) + r256(a * kb * nx * 8) + r256(a * nx * kb * 8)
+        kb, rows = nt // 2 + 1, 4096 // nx
+        kpad = -(-kb // rows) * rows
+        return (r256(a * n * kpad * 8) + r256(a * kb * nx * 8) + r256(a * nx * kb * 8)
                 + r256(a * nx * nt * 8))
     need = 8192 + per(11, 256)
     assert W(g.ref, ST, -1, ctypes.byref(o)) == need
