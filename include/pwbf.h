@@ -284,8 +284,9 @@ PWBF_API int pwbf_resolution_metrics(const pwbf_geometry *g, const float *env,
  *            logimg from env; filtered must be NULL and bandpass 0
  *  workspace device, 256-byte aligned, >= pwbf_fk_workspace_bytes(g, method,
  *            angle, out) bytes: the spectra and migrated images of every angle
- *            of the call (16 (Nt/2 + 1) Nx + 8 Nx Nt bytes per angle: 17 MB
- *            (Stolt) or 34 MB (Lu) per angle at 128 channels x 4096 samples)
+ *            of the call (8 N Kb + 16 (Nt/2 + 1) Nx + 8 Nx Nt bytes per angle,
+ *            Kb = Nt/2 + 1 rounded up to a multiple of 4096 / Nx: 19 MB (Stolt)
+ *            or 36 MB (Lu) per angle at 128 channels x 4096 samples)
  * Needs n_channels >= 2 with a uniform pitch (within 1e-6 p; the element
  * positions used are elem_x[0] + e p), n_samples a power of two in 2..4096, and
  * nx, nz <= 2^24 (PWBF_E_UNSUPPORTED otherwise). apod and f_number are unused. Work is enqueued
