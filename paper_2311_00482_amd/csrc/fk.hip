@@ -28,10 +28,11 @@
 //  k_fk_itime     block per window column x1 (and angle): inverse FFT along kz of
 //                 U[e][.], zero-filled to Nt, scaled by 1/(Nx Nt); stores the
 //                 window's rows of M
-//  k_fk_image     thread per pixel: for every angle the migrated image at
-//                 (x1, z1), affine in the pixel indices, by bilinear interpolation;
-//                 the complex sum over angles gives the real, imaginary and
-//                 magnitude planes and the frame maximum
+//  k_fk_image     thread per two pixels (adjacent columns, one depth): for every
+//                 angle the migrated image at (x1, z1), affine in the pixel
+//                 indices, by bilinear interpolation; the complex sum over angles
+//                 gives the real, imaginary and magnitude planes and the frame
+//                 maximum
 //
 // Interpolation positions are float-float: neighbouring spectral bins of an echo
 // differ by up to a half turn of phase, so a weight off by 1e-4 (a float32
@@ -368,74 +369,95 @@ __device__ __forceinline__ bool map_index(float v0h, float v0l, float k, float c
   return true;
 }
 
-// Pixel (ix, iz) reads column ux0 + ix uxi + iz uxk and row uz0 + iz uzk of the
-// migrated image of each angle. A block is one image column: its lateral base
-// ux0 + ix uxi (float-float) is formed once per angle and shared through LDS.
-__global__ void __launch_bounds__(256) k_fk_image(FkPlan F, int zchunks) {
-  const int nt = 1 << F.log2nt, nx1 = 1 << F.log2nx;
-  const int ix = blockIdx.x / zchunks, iz = (blockIdx.x - ix * zchunks) * 256 + threadIdx.x;
-  const bool mine = iz < F.nz_img;
-  const float fiz = (float)iz;
-  __shared__ float2 s_xb[kMaxAngles];
-  if (threadIdx.x < F.n_ang) {
-#pragma clang fp contract(off)
-    const FkAngleConst &A = F.ang[threadIdx.x];
-    const float fix = (float)ix;
-    const float p = fix * A.uxi_hi, e = fmaf(fix, A.uxi_hi, -p);
-    const ff t = dev::two_sum(A.ux0_hi, p);
-    const ff b = dev::two_sum(t.hi, (t.lo + (A.ux0_lo + e)) + fix * A.uxi_lo);
-    s_xb[threadIdx.x] = make_float2(b.hi, b.lo);
-  }
-  __syncthreads();
-  float re = 0.f, im = 0.f;
-  for (int a = 0; a < F.n_ang; ++a) {
-    const FkAngleConst &A = F.ang[a];
-    if (A.ncol == 0) continue;
-    int i0, j0;
-    float fx, fz;
-    // far outside the migrated image: nothing to read (and no integer overflow)
-    const float2 xb = s_xb[a];
-    if (!map_index(xb.x, xb.y, fiz, A.uxk_hi, A.uxk_lo, -2.f, (float)(nx1 + 1), &i0, &fx))
-      continue;
-    if (!map_index(A.uz0_hi, A.uz0_lo, fiz, A.uzk_hi, A.uzk_lo, -2.f, (float)(nt + 1), &j0, &fz))
-      continue;
-    const float2 *M = F.M + (size_t)a * nx1 * nt;
-    // taps outside the window are outside [0, Nx) x [0, Nt) too (the window
-    // holds every tap inside, with a margin), so they read as zero
-    const int c1 = A.col0 + A.ncol, r1 = A.row0 + A.nrow;
-    if (i0 >= A.col0 && i0 + 1 < c1 && j0 >= A.row0 && j0 + 1 < r1) {
-      const float2 *q = M + (unsigned)(i0 * nt + j0);
-      const float2 v00 = q[0], v01 = q[1], v10 = q[nt], v11 = q[nt + 1];
-      const float w00 = (1.f - fx) * (1.f - fz), w01 = (1.f - fx) * fz;
-      const float w10 = fx * (1.f - fz), w11 = fx * fz;
-      re += w00 * v00.x + w01 * v01.x + w10 * v10.x + w11 * v11.x;
-      im += w00 * v00.y + w01 * v01.y + w10 * v10.y + w11 * v11.y;
-    } else {
+// Adds the bilinear value of one angle's migrated image M at column i0 + fx,
+// row j0 + fz to (re, im); taps outside the angle's window are outside
+// [0, Nx) x [0, Nt) too (the window holds every tap inside, with a margin), so
+// they read as zero.
+__device__ __forceinline__ void add_taps(const float2 *M, int nt, const FkAngleConst &A, int i0,
+                                         float fx, int j0, float fz, float &re, float &im) {
+  const int c1 = A.col0 + A.ncol, r1 = A.row0 + A.nrow;
+  if (i0 >= A.col0 && i0 + 1 < c1 && j0 >= A.row0 && j0 + 1 < r1) {
+    const float2 *q = M + (unsigned)(i0 * nt + j0);
+    const float2 v00 = q[0], v01 = q[1], v10 = q[nt], v11 = q[nt + 1];
+    const float w00 = (1.f - fx) * (1.f - fz), w01 = (1.f - fx) * fz;
+    const float w10 = fx * (1.f - fz), w11 = fx * fz;
+    re += w00 * v00.x + w01 * v01.x + w10 * v10.x + w11 * v11.x;
+    im += w00 * v00.y + w01 * v01.y + w10 * v10.y + w11 * v11.y;
+  } else {
 #pragma unroll
-      for (int di = 0; di < 2; ++di) {
+    for (int di = 0; di < 2; ++di) {
 #pragma unroll
-        for (int dj = 0; dj < 2; ++dj) {
-          const int i = i0 + di, j = j0 + dj;
-          if (i >= A.col0 && i < c1 && j >= A.row0 && j < r1) {
-            const float w = (di ? fx : 1.f - fx) * (dj ? fz : 1.f - fz);
-            const float2 v = M[(unsigned)(i * nt + j)];
-            re = fmaf(w, v.x, re);
-            im = fmaf(w, v.y, im);
-          }
+      for (int dj = 0; dj < 2; ++dj) {
+        const int i = i0 + di, j = j0 + dj;
+        if (i >= A.col0 && i < c1 && j >= A.row0 && j < r1) {
+          const float w = (di ? fx : 1.f - fx) * (dj ? fz : 1.f - fz);
+          const float2 v = M[(unsigned)(i * nt + j)];
+          re = fmaf(w, v.x, re);
+          im = fmaf(w, v.y, im);
         }
       }
     }
   }
-  const float e = sqrtf(re * re + im * im);
+}
+
+// Pixel (ix, iz) reads column ux0 + ix uxi + iz uxk and row uz0 + iz uzk of the
+// migrated image of each angle. A block is a depth run of two image columns:
+// each column's lateral base ux0 + ix uxi (float-float) is formed once per
+// angle and shared through LDS, and a thread's two pixels share the row map.
+__global__ void __launch_bounds__(256) k_fk_image(FkPlan F, int zchunks) {
+  const int nt = 1 << F.log2nt, nx1 = 1 << F.log2nx;
+  const int px = blockIdx.x / zchunks, iz = (blockIdx.x - px * zchunks) * 256 + threadIdx.x;
+  const int ix0 = 2 * px;
+  const bool two = ix0 + 1 < F.nx_img, mine = iz < F.nz_img;
+  const float fiz = (float)iz;
+  __shared__ float2 s_xb[2][kMaxAngles];
+  {
+    const int c = threadIdx.x >> 5, a = threadIdx.x & 31;  // column c of the pair, angle a
+    if (c < 2 && a < F.n_ang) {
+#pragma clang fp contract(off)
+      const FkAngleConst &A = F.ang[a];
+      const float fix = (float)(ix0 + c);
+      const float p = fix * A.uxi_hi, e = fmaf(fix, A.uxi_hi, -p);
+      const ff t = dev::two_sum(A.ux0_hi, p);
+      const ff b = dev::two_sum(t.hi, (t.lo + (A.ux0_lo + e)) + fix * A.uxi_lo);
+      s_xb[c][a] = make_float2(b.hi, b.lo);
+    }
+  }
+  __syncthreads();
+  float re0 = 0.f, im0 = 0.f, re1 = 0.f, im1 = 0.f;
+  for (int a = 0; a < F.n_ang; ++a) {
+    const FkAngleConst &A = F.ang[a];
+    if (A.ncol == 0) continue;
+    // far outside the migrated image: nothing to read (and no integer overflow)
+    int j0;
+    float fz;
+    if (!map_index(A.uz0_hi, A.uz0_lo, fiz, A.uzk_hi, A.uzk_lo, -2.f, (float)(nt + 1), &j0, &fz))
+      continue;
+    const float2 *M = F.M + (size_t)a * nx1 * nt;
+    int i0;
+    float fx;
+    const float2 xb0 = s_xb[0][a], xb1 = s_xb[1][a];
+    if (map_index(xb0.x, xb0.y, fiz, A.uxk_hi, A.uxk_lo, -2.f, (float)(nx1 + 1), &i0, &fx))
+      add_taps(M, nt, A, i0, fx, j0, fz, re0, im0);
+    if (two && map_index(xb1.x, xb1.y, fiz, A.uxk_hi, A.uxk_lo, -2.f, (float)(nx1 + 1), &i0, &fx))
+      add_taps(M, nt, A, i0, fx, j0, fz, re1, im1);
+  }
+  const float e0 = sqrtf(re0 * re0 + im0 * im0), e1 = sqrtf(re1 * re1 + im1 * im1);
   if (mine) {
-    const size_t t = (size_t)ix * F.nz_img + iz;
-    F.out_rf[t] = re;
-    if (F.out_imag) F.out_imag[t] = im;
-    if (F.out_env) F.out_env[t] = e;
+    const size_t t = (size_t)ix0 * F.nz_img + iz;
+    F.out_rf[t] = re0;
+    if (F.out_imag) F.out_imag[t] = im0;
+    if (F.out_env) F.out_env[t] = e0;
+    if (two) {
+      const size_t t1 = t + F.nz_img;
+      F.out_rf[t1] = re1;
+      if (F.out_imag) F.out_imag[t1] = im1;
+      if (F.out_env) F.out_env[t1] = e1;
+    }
   }
   if (F.ws_max) {
     __shared__ float wm[4];
-    float m = mine ? e : 0.f;
+    float m = mine ? fmaxf(e0, two ? e1 : 0.f) : 0.f;
     for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
     if ((threadIdx.x & 63) == 0) wm[threadIdx.x >> 6] = m;
     __syncthreads();
@@ -497,7 +519,8 @@ hipError_t launch_fk(const FkPlan &F, int ncol_max, hipStream_t s) {
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   const int zchunks = (F.nz_img + 255) / 256;
-  hipLaunchKernelGGL(k_fk_image, dim3(F.nx_img * zchunks), dim3(256), 0, s, F, zchunks);
+  hipLaunchKernelGGL(k_fk_image, dim3((F.nx_img + 1) / 2 * zchunks), dim3(256), 0, s, F,
+                     zchunks);
   return hipGetLastError();
 }
 
