@@ -167,7 +167,8 @@ int validate_outputs(const pwbf_geometry *g, const pwbf_outputs *o, void *ws, si
 // the per-pixel delay offsets small, which keeps float32 delays accurate. A
 // wavefront covers 8 x 8 pixels (2 x 4 wavefronts per 16 x 32 tile): its lanes'
 // delays then span fewer window entries per gather than a 16 x 4 column
-// layout, which measured ~10% faster on gfx950. Small frames split channels
+// layout (~10% faster with an earlier kernel; with the current one the two
+// shapes time within 0.5% on every benchmark workload). Small frames split channels
 // across lane groups so there are enough waves.
 pwbf_tile default_tile(const pwbf_geometry *g, int n_angles_used, int mode) {
   (void)mode;
