@@ -577,7 +577,7 @@ def main():
                          "(a reference kernel for calibrating HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
+        print("bench.py measures one GPU: the library has no multi-GPU path "
               "(frames would be sharded across GPUs with no exchange); run with --gpus 1.",
               file=sys.stderr)
         sys.exit(2)

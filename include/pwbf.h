@@ -79,7 +79,7 @@ extern "C" {
 #define PWBF_APOD_BOXCAR 1
 #define PWBF_APOD_NONE 2
 
-/* Limits of this build. */
+/* Library limits. */
 #define PWBF_MAX_ANGLES 32
 #define PWBF_MAX_CHANNELS 256
 #define PWBF_MAX_NZ_POST 4096 /* longest depth column the post-processing handles */
