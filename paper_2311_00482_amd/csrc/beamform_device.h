@@ -392,8 +392,10 @@ __device__ __forceinline__ void process_tile_body(const FramePlan &P, int tz, in
   }
 
   // Per-angle tile constants: window origin LT = floor(min_tile tx) - 1 and
-  // tx(q) - LT. tx is linear, so its tile minimum is at a corner.
-  for (int a = tid; a < A; a += blockDim.x) {
+  // tx(q) - LT. tx is linear, so its tile minimum is at a corner. Angle a is
+  // taken by thread blockDim - 1 - a: another wavefront than the aperture hull
+  // above, which starts at thread 0, so the two run side by side.
+  for (int a = (int)blockDim.x - 1 - tid; a < A; a += blockDim.x) {
     const ff sa = {P.sa[a], P.sal[a]}, ca = {P.ca[a], P.cal[a]}, to = {P.to[a], P.tol[a]};
     const ff txq = ff_add(ff_add(ff_mul(Xq, sa), ff_mul(Zq, ca)), ff_neg(to));
     const float dmin = fminf(dxlo * sa.hi, dxhi * sa.hi) + fminf(dzlo * ca.hi, dzhi * ca.hi);
