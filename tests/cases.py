@@ -45,6 +45,13 @@ SMALL = [
     ("compound_3a_boxcar_cpw1", dict(apod="boxcar", angles_deg=(-12.0, 0.0, 9.0)), "das", -1,
      (1, 16, 1, 2, 0), "f32"),
     ("das_record_too_short", dict(n_samples=120), "das", 0, None, "f32"),
+    # a one-wavefront block whose window (264 entries, 66 quads) is wider than
+    # the block: the staging threads walk several quads of every row
+    ("das_window_wider_than_block", dict(nz=64, z_min=3e-3, z_max=13e-3, nx=5), "das", 0,
+     (1, 64, 1, 1, 0), "f32"),
+    ("compound_3a_window_wider_than_block", dict(nz=64, z_min=3e-3, z_max=13e-3, nx=5,
+                                                 angles_deg=(-10.0, 0.0, 10.0)), "das", -1,
+     (1, 64, 1, 1, 0), "i16"),
     ("compound_3a", dict(angles_deg=(-12.0, 0.0, 9.0)), "das", -1, None, "f32"),
     ("compound_7a_t0", dict(angles_deg=(-15., -10., -5., 0., 5., 10., 15.),
                             t0=(0.5e-6, 0.0, -0.3e-6, 1e-6, 0.0, 0.2e-6, 0.0)), "das", -1,
@@ -55,6 +62,8 @@ SMALL = [
                                   n_channels=8), "das", -1, (1, 32, 1, 2, 0), "f32"),
     ("angle_slab", dict(angles_deg=(-8.0, 4.0, 11.0)), "das", 2, None, "i16"),
     ("dmas_2ch", dict(n_channels=2), "dmas", 0, None, "f32"),
+    ("dmas_window_wider_than_block", dict(nz=64, z_min=3e-3, z_max=13e-3, nx=5), "dmas", 0,
+     (1, 64, 1, 1, 0), "f32"),
     ("dmas_ragged_cpw2", dict(nx=21, nz=77, n_channels=12), "dmas", 0, (2, 16, 1, 4, 4), "f32"),
     ("dmas_compound_5a", dict(angles_deg=(-10., -5., 0., 5., 10.)), "dmas", -1, None, "i16"),
     ("dmas_compound_generic", dict(angles_deg=tuple(range(-18, 18, 2)), nx=7, nz=40,
