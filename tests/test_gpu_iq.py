@@ -37,9 +37,9 @@ def cerr(gpu, ora):
     return float(np.abs(gpu - ora).max() / m) if m > 0 else float(np.abs(gpu).max())
 
 
-def tol_for(g, mode, angle):
+def tol_for(g, mode, angle, tile=None):
     from paper_2311_00482_amd import describe_plan
-    win = describe_plan(g, mode, angle)["win"]
+    win = describe_plan(g, mode, angle, tile)["win"]
     tol = TOL32 * max(1.0, win / 64.0)
     if mode == "bbdmas" and g.n_channels < 16:
         tol = max(tol, 3e-5)
@@ -54,10 +54,10 @@ def gpu_iq(g, rf):
     return iq
 
 
-def run(g, iq, mode, angle, want=("rf", "imag", "env", "log")):
+def run(g, iq, mode, angle, want=("rf", "imag", "env", "log"), tile=None):
     from paper_2311_00482_amd import beamform
     torch = _torch()
-    out = beamform(g, iq, mode, angle, want=want)
+    out = beamform(g, iq, mode, angle, want=want, tile=tile)
     torch.cuda.synchronize()
     return {k: v.cpu().numpy().astype(np.float64) for k, v in out.items()}
 
@@ -72,8 +72,17 @@ def test_demodulated_records_match_the_oracle(kind):
 
 
 IQ_SMALL = [
-    # name, geometry kwargs, mode, angle
+    # name, geometry kwargs, mode, angle[, launch shape]
     ("iqdas_one_angle", dict(n_samples=512), "iqdas", 0),
+    # one-wavefront blocks whose 264-entry windows are wider than the block
+    ("iqdas_window_wider_than_block", dict(n_samples=512, nz=64, z_min=3e-3, z_max=13e-3, nx=5),
+     "iqdas", 0, (1, 64, 1, 1, 0)),
+    ("bbdmas_compound_window_wider_than_block",
+     dict(n_samples=1024, nz=64, z_min=3e-3, z_max=13e-3, nx=5, angles_deg=(-10.0, 0.0, 10.0)),
+     "bbdmas", -1, (1, 64, 1, 1, 0)),
+    # one lane group per wavefront at a small size (the exact-angle kernels)
+    ("iqdas_compound_3a_cpw1", dict(n_samples=512, angles_deg=(-9.0, 0.0, 7.0), nx=21, nz=77),
+     "iqdas", -1, (1, 16, 1, 2, 0)),
     ("iqdas_compound_3a", dict(n_samples=512, angles_deg=(-9.0, 0.0, 7.0), nx=21, nz=77),
      "iqdas", -1),
     ("iqdas_generic_7a", dict(n_samples=512, angles_deg=(-12., -8., -4., 0., 4., 8., 12.),
@@ -85,13 +94,16 @@ IQ_SMALL = [
 ]
 
 
-@pytest.mark.parametrize("name,kw,mode,angle", IQ_SMALL, ids=[c[0] for c in IQ_SMALL])
-def test_iq_small_cases_whole_image(name, kw, mode, angle):
+@pytest.mark.parametrize("case", IQ_SMALL, ids=[c[0] for c in IQ_SMALL])
+def test_iq_small_cases_whole_image(case):
+    from paper_2311_00482_amd import Tile
+    name, kw, mode, angle = case[:4]
+    tile = Tile(*case[4]) if len(case) > 4 else None
     g = geom(**kw)
     rf = rand_rf(g, zlib.crc32(name.encode()) % 1000, "f32")
-    out = run(g, gpu_iq(g, rf), mode, angle)
+    out = run(g, gpu_iq(g, rf), mode, angle, tile=tile)
     ref = oracle.iq_beamform(g, oracle.iq_demodulate(g, rf.astype(np.float64)), mode, angle)
-    tol = tol_for(g, mode, angle)
+    tol = tol_for(g, mode, angle, tile)
     e = cerr(out["rf"] + 1j * out["imag"], ref)
     assert e <= tol, e
     env = np.abs(ref)
