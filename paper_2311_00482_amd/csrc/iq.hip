@@ -1,8 +1,13 @@
-// Baseband (IQ) demodulation of channel records, one block per record.
+// Baseband (IQ) demodulation of channel records, two records per block.
 //
-// A record of n = 2^L samples is transformed with the in-LDS block FFT,
-// multiplied by the one-sided weights of the analytic signal (and the 1/n of
-// the inverse), transformed back, and multiplied by exp(-2 pi i r k) with
+// The analytic signal of a record x of n = 2^L samples is the inverse DFT of
+// its spectrum times the one-sided weights w(k) (1 at DC and Nyquist, 2 on
+// positive bins, 0 on negative ones); since w(k) + w(n - k) = 2, its real part
+// is x itself and its imaginary part is the discrete Hilbert transform H(x).
+// Two records x1, x2 go through one transform pair: the inverse DFT of w(k)
+// times the DFT of x1 + i x2 is (x1 + i H(x1)) + i (x2 + i H(x2)), so
+// H(x1) = Im - x2 and H(x2) = x1 - Re, with x1 and x2 the samples kept in
+// registers. Each analytic record is then multiplied by exp(-2 pi i r k) with
 // r = f0 / fs, k the sample index. The carrier phase is formed in revolutions
 // from r as a float-float pair: k * r_hi splits exactly into a rounded product
 // and its error (one FMA), so frac(k r) is accurate to ~1e-7 revolutions for
@@ -25,16 +30,28 @@ __device__ __forceinline__ float rf_sample(const void *rf, size_t i) {
   return ((const float *)rf)[i];
 }
 
+constexpr int kIqMaxPerThread = 4096 / kPostThreads;  // samples of a record per thread
+
 template <int DT>
 __global__ void __launch_bounds__(kPostThreads)
-    k_iq_demod(const void *__restrict__ rf, float2 *__restrict__ iq, int log2ns, float r_hi,
-               float r_lo) {
+    k_iq_demod(const void *__restrict__ rf, float2 *__restrict__ iq, int rows, int log2ns,
+               float r_hi, float r_lo) {
   extern __shared__ __align__(16) float2 sm[];
   const int ns = 1 << log2ns;
   float2 *x = sm;
-  const size_t base = (size_t)blockIdx.x * ns;
-  for (int k = threadIdx.x; k < ns; k += kPostThreads)
-    x[fft::pad(k)] = make_float2(rf_sample<DT>(rf, base + k), 0.f);
+  const int r0 = 2 * blockIdx.x;
+  const bool two = r0 + 1 < rows;  // a missing second record is zero
+  const size_t base0 = (size_t)r0 * ns, base1 = two ? base0 + ns : base0;
+  float2 keep[kIqMaxPerThread];  // (x1, x2) at the thread's samples
+#pragma unroll
+  for (int i = 0; i < kIqMaxPerThread; ++i) {
+    const int k = threadIdx.x + i * kPostThreads;
+    if (k < ns) {
+      const float v1 = rf_sample<DT>(rf, base1 + k);
+      keep[i] = make_float2(rf_sample<DT>(rf, base0 + k), two ? v1 : 0.f);
+      x[fft::pad(k)] = keep[i];
+    }
+  }
   __syncthreads();
   fft::transform_any<false>(x, log2ns);
   const float inv_n = 1.0f / (float)ns;
@@ -45,15 +62,21 @@ __global__ void __launch_bounds__(kPostThreads)
   }
   __syncthreads();
   fft::transform_any<true>(x, log2ns);
-  for (int k = threadIdx.x; k < ns; k += kPostThreads) {
-    const float2 z = x[fft::pad(k)];
-    const float fk = (float)k;
-    const float p = fk * r_hi;
-    const float e = fmaf(fk, r_hi, -p);  // exact error of the product
-    const float rho = (p - floorf(p)) + fmaf(fk, r_lo, e);
-    float s, c;
-    sincospif(-2.0f * rho, &s, &c);
-    iq[base + k] = dev::cmul(z, make_float2(c, s));
+#pragma unroll
+  for (int i = 0; i < kIqMaxPerThread; ++i) {
+    const int k = threadIdx.x + i * kPostThreads;
+    if (k < ns) {
+      const float2 w = x[fft::pad(k)];
+      const float fk = (float)k;
+      const float p = fk * r_hi;
+      const float e = fmaf(fk, r_hi, -p);  // exact error of the product
+      const float rho = (p - floorf(p)) + fmaf(fk, r_lo, e);
+      float sn, cs;
+      sincospif(-2.0f * rho, &sn, &cs);
+      const float2 ph = make_float2(cs, sn);
+      iq[base0 + k] = dev::cmul(make_float2(keep[i].x, w.y - keep[i].y), ph);
+      if (two) iq[base1 + k] = dev::cmul(make_float2(keep[i].y, keep[i].x - w.x), ph);
+    }
   }
 }
 
@@ -65,14 +88,15 @@ hipError_t launch_iq_demod(const void *rf, int dtype, void *iq, int rows, int lo
                            float r_lo, hipStream_t stream) {
   const size_t lds = iq_demod_lds_bytes(1 << log2ns);
   float2 *out = (float2 *)iq;
+  const dim3 pairs((rows + 1) / 2);  // two records per block
   if (dtype == kI16)
-    hipLaunchKernelGGL(k_iq_demod<kI16>, dim3(rows), dim3(kPostThreads), lds, stream, rf, out,
+    hipLaunchKernelGGL(k_iq_demod<kI16>, pairs, dim3(kPostThreads), lds, stream, rf, out, rows,
                        log2ns, r_hi, r_lo);
   else if (dtype == kF16)
-    hipLaunchKernelGGL(k_iq_demod<kF16>, dim3(rows), dim3(kPostThreads), lds, stream, rf, out,
+    hipLaunchKernelGGL(k_iq_demod<kF16>, pairs, dim3(kPostThreads), lds, stream, rf, out, rows,
                        log2ns, r_hi, r_lo);
   else
-    hipLaunchKernelGGL(k_iq_demod<kF32>, dim3(rows), dim3(kPostThreads), lds, stream, rf, out,
+    hipLaunchKernelGGL(k_iq_demod<kF32>, pairs, dim3(kPostThreads), lds, stream, rf, out, rows,
                        log2ns, r_hi, r_lo);
   return hipGetLastError();
 }
