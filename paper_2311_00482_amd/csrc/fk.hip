@@ -79,14 +79,6 @@ __device__ __forceinline__ int split_index(ff u, float *frac) {
   return (int)fl + (int)c;
 }
 
-// a / b in float-float (one correction step)
-__device__ __forceinline__ ff ff_div(ff a, ff b) {
-#pragma clang fp contract(off)
-  const float q1 = a.hi / b.hi;
-  const ff r = dev::ff_add(a, dev::ff_neg(dev::ff_mul({q1, 0.f}, b)));
-  return dev::two_sum(q1, r.hi / b.hi);
-}
-
 __device__ __forceinline__ int kbins_of(const FkPlan &F) { return (1 << F.log2nt) / 2 + 1; }
 
 // Two traces per block: channels e0 = 2 blockIdx.x and e0 + 1 go in as the
