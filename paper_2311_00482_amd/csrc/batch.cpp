@@ -99,20 +99,22 @@ int plan_batch_frame(const pwbf_frame &f, unsigned char *ws, pwbf::FramePlan *P,
   return PWBF_OK;
 }
 
+// Release everything a batch holds; errors on the way are not actionable here
+// (best-effort teardown), so their codes are dropped explicitly.
 void free_batch(pwbf_batch *b) {
   if (!b) return;
-  if (b->exec) hipGraphExecDestroy(b->exec);
-  if (b->graph) hipGraphDestroy(b->graph);
-  if (b->cap) hipStreamDestroy(b->cap);
-  if (b->staged) hipEventDestroy(b->staged);
-  if (b->h_stage) hipHostFree(b->h_stage);
-  hipFree(b->d_plans);
-  hipFree(b->d_post);
-  hipFree(b->d_items);
-  hipFree(b->d_post_cols);
-  hipFree(b->d_log_cols);
-  hipFree(b->d_counter);
-  hipFree(b->d_ws);
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->cap) (void)hipStreamDestroy(b->cap);
+  if (b->staged) (void)hipEventDestroy(b->staged);
+  if (b->h_stage) (void)hipHostFree(b->h_stage);
+  (void)hipFree(b->d_plans);
+  (void)hipFree(b->d_post);
+  (void)hipFree(b->d_items);
+  (void)hipFree(b->d_post_cols);
+  (void)hipFree(b->d_log_cols);
+  (void)hipFree(b->d_counter);
+  (void)hipFree(b->d_ws);
   delete b;
 }
 
@@ -135,7 +137,7 @@ int pwbf_tune(const pwbf_geometry *g, const void *rf, int32_t rf_dtype, int32_t 
   if (waves != 0 && waves != pwbf::batch_waves())
     return api_set_error(PWBF_E_INVALID, "waves must be 0 or 8");
   if (!out || !out->rf) return api_set_error(PWBF_E_INVALID, "out->rf is required as scratch");
-  const pwbf_outputs rf_only = {out->rf, nullptr, nullptr, nullptr};
+  const pwbf_outputs rf_only = {out->rf, nullptr, nullptr, nullptr, nullptr};
   out = &rf_only;
   pwbf::FramePlan P;
   std::string err;
@@ -163,26 +165,26 @@ int pwbf_tune(const pwbf_geometry *g, const void *rf, int32_t rf_dtype, int32_t 
     if (waves && Q.wz * Q.wx != waves) continue;
     hipError_t e = pwbf::launch_beamform(Q, s);  // warm-up
     for (int k = 0; k < 3 && e == hipSuccess; ++k) {
-      if (k == 0) hipEventRecord(e0, s);
-      e = pwbf::launch_beamform(Q, s);
+      if (k == 0) e = hipEventRecord(e0, s);
+      if (e == hipSuccess) e = pwbf::launch_beamform(Q, s);
     }
-    hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
     if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
     if (e != hipSuccess) {
-      hipEventDestroy(e0);
-      hipEventDestroy(e1);
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
       return dev_error(e, "tuning launch");
     }
-    float ms = 0;
-    hipEventElapsedTime(&ms, e0, e1);
     ms /= 3;
     if (ms < best_t) {
       best_t = ms;
       best_tile = {Q.cpw, Q.lz, Q.wz, Q.wx, 0};
     }
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   if (best_t >= 1e30f) return api_set_error(PWBF_E_UNSUPPORTED, "no launch shape fits");
   pwbf::tune_store(pwbf::shape_key(g, rf_dtype, mode, angle, waves), best_tile);
   if (best) *best = best_tile;
@@ -236,7 +238,7 @@ int pwbf_batch_create(const pwbf_frame *frames, int32_t n, int32_t flags, void *
       if (!tile_is_zero(f.tile) ||
           pwbf::tune_lookup(pwbf::shape_key(f.geom, f.rf_dtype, f.mode, f.angle, 8), &t))
         continue;
-      pwbf_outputs scratch = {f.out.rf, nullptr, nullptr, nullptr};
+      pwbf_outputs scratch = {f.out.rf, nullptr, nullptr, nullptr, nullptr};
       int rc = pwbf_tune(f.geom, f.rf, f.rf_dtype, f.mode, f.angle, &scratch, 8, stream,
                          nullptr, nullptr);
       if (rc) return rc;
@@ -351,7 +353,7 @@ int pwbf_batch_create(const pwbf_frame *frames, int32_t n, int32_t flags, void *
   if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
   if (e == hipSuccess) {
     size_t nodes = 0;
-    hipGraphGetNodes(b->graph, nullptr, &nodes);
+    e = hipGraphGetNodes(b->graph, nullptr, &nodes);
     b->graph_nodes = (int)nodes;
   }
   if (e != hipSuccess) {

@@ -329,7 +329,8 @@ int pwbf_server_create(const pwbf_probe *probes, int32_t n, size_t hbm_budget_by
                                                    std::to_string(pwbf::serve_max_angles()) +
                                                    " angles are summed per frame");
     if ((p.want_env || p.want_log || p.geom->bandpass)) {
-      pwbf_outputs o = {(float *)256, nullptr, (float *)256, p.want_log ? (float *)256 : nullptr};
+      pwbf_outputs o = {(float *)256, nullptr, (float *)256, p.want_log ? (float *)256 : nullptr,
+                        nullptr};
       static unsigned char fake_ws[pwbf::kMaxSlotBytes] __attribute__((aligned(256)));
       rc = pwbf::validate_outputs(p.geom, &o, fake_ws, sizeof fake_ws, &err);
       if (rc) return api_set_error(rc, "probe " + std::to_string(i) + ": " + err);
@@ -374,7 +375,7 @@ int pwbf_server_create(const pwbf_probe *probes, int32_t n, size_t hbm_budget_by
       if (e == hipSuccess) e = hipMalloc((void **)&sl.ws, pwbf::kMaxSlotBytes);
       if (e == hipSuccess) e = hipEventCreateWithFlags(&sl.uploaded, hipEventDisableTiming);
       if (e != hipSuccess) break;
-      const pwbf_outputs o = {sl.out_rf, nullptr, sl.env, sl.logimg};
+      const pwbf_outputs o = {sl.out_rf, nullptr, sl.env, sl.logimg, nullptr};
       pwbf::FramePlan P;
       pwbf::PostPlan Q;
       std::memset(&Q, 0, sizeof Q);
