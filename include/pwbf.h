@@ -83,6 +83,21 @@ extern "C" {
 #define PWBF_MAX_ANGLES 32
 #define PWBF_MAX_CHANNELS 256
 #define PWBF_MAX_NZ_POST 4096 /* longest depth column the post-processing handles */
+/* Longest LDS window per (channel, angle) of a launch shape, in samples. The
+ * kernels hold every per-gather delay as a float32 offset centred on its tile's
+ * window, so the delay's rounding grows with the window. 64 entries keep those
+ * offsets under 32 samples (2^-19 of a sample resolution), which holds DAS and
+ * IQ-DAS within 1e-5 of the float64 definition (max-normalised); DMAS, pDAS and
+ * BB-DMAS take a root of every delayed sample, steep where it crosses zero, so
+ * they are held to 32 entries (offsets under 16 samples). A tile's window spans
+ * about |sin th| TX DX + |cos th| TZ DZ + hypot(TX DX, TZ DZ) + 6 samples (DX,
+ * DZ: pixel pitches times fs / c); explicit shapes needing more are refused
+ * with PWBF_E_UNSUPPORTED, and default plans pick a smaller tile. A grid whose
+ * pixels are so coarse that no shape fits (a tile of one 2 x 2-pixel lane
+ * group needs DZ + hypot(DX, DZ) + 6 within the limit) is refused the same
+ * way. */
+#define PWBF_MAX_WINDOW 64
+#define PWBF_MAX_WINDOW_ROOT 32 /* DMAS, pDAS, BB-DMAS */
 
 /* Acquisition and grid. Host pointers are read during the call only. */
 typedef struct pwbf_geometry {
@@ -104,7 +119,7 @@ typedef struct pwbf_geometry {
   int32_t bandpass;         /* 1: keep round-trip band [f0, 3 f0] along depth before
                                the envelope (needs dz <= c / (12 f0)); 0: none */
   double log_floor_db;      /* floor of the log image, dB, < 0 (e.g. -70) */
-  double pdas_p;            /* root order p of pDAS, 1 .. 16 (PWBF_PDAS only; else ignored) */
+  double pdas_p;            /* root order p of pDAS, 1 .. 2 (PWBF_PDAS only; else ignored) */
 } pwbf_geometry;
 
 /* Output planes, each a device float32 [nx][nz] buffer owned by the caller.
@@ -125,9 +140,11 @@ typedef struct pwbf_outputs {
  * A wavefront (64 lanes) holds cpw lane groups; each group covers the same
  * lz (depth) x (64 / cpw / lz) (lateral) pixels and sums its share of the
  * channels, and the groups are reduced in-wave. A tile (one block) is wz x wx
- * wavefronts, i.e. lz * wz pixels along depth by (64 / cpw / lz) * wx along x. */
+ * wavefronts, i.e. lz * wz pixels along depth by (64 / cpw / lz) * wx along x.
+ * Its LDS windows must fit PWBF_MAX_WINDOW entries (PWBF_E_UNSUPPORTED
+ * otherwise). */
 typedef struct pwbf_tile {
-  int32_t cpw;   /* lane groups per wavefront: 1, 2 or 4 */
+  int32_t cpw;   /* lane groups per wavefront: 1, 2, 4, 8 or 16 */
   int32_t lz;    /* lanes of a group along depth: a power of two <= 64 / cpw */
   int32_t wz;    /* wavefronts stacked along depth in a tile */
   int32_t wx;    /* wavefronts side by side along x in a tile; wz * wx in 1..8 */
@@ -168,8 +185,11 @@ PWBF_API int pwbf_beamform_dmas(const pwbf_geometry *g, const void *rf, int32_t 
 
 /* pDAS for one angle, Eqs. (2)-(3): the delayed samples are compressed to
  * w_e sign(v_e) |v_e|^(1/p) (p = g->pdas_p), summed, and the sum restored by
- * its signed p-th power, y = sign(t) |t|^p. p = 1 is DAS. Arguments and errors
- * as for pwbf_beamform_das; PWBF_E_INVALID unless 1 <= p <= 16. */
+ * its signed p-th power, y = sign(t) |t|^p. p = 1 is DAS. The paper gives no p;
+ * the kernels take 1 <= p <= 2 (PWBF_E_INVALID below 1 or not finite,
+ * PWBF_E_UNSUPPORTED above 2: a root steeper than the square root amplifies the
+ * float32 delay rounding near zero crossings of the delayed samples past 1e-5
+ * of the definition). Arguments and other errors as for pwbf_beamform_das. */
 PWBF_API int pwbf_beamform_pdas(const pwbf_geometry *g, const void *rf, int32_t rf_dtype,
                                 int32_t angle, const pwbf_outputs *out, void *workspace,
                                 size_t workspace_bytes, void *stream);

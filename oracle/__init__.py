@@ -6,7 +6,8 @@ it. It shares no code with the GPU library and never imports it.
 
 The per-pixel beamformers (DAS, compound, RF DMAS in two forms, pDAS, IQ-DAS and
 BB-DMAS on baseband data) are plain C in
-``pwbf_oracle.c``, single-threaded FP64; the column post-processing along depth
+``pwbf_oracle.c``, FP64, single-threaded (or, with ``parallel=True``, the same
+source built with OpenMP over the pixel loop, bitwise the same values); the column post-processing along depth
 (band-pass, Hilbert envelope, log compression) is NumPy FP64 with ``numpy.fft``
 as the transform. Geometry objects are duck-typed: anything with the attributes
 of ``synth.Geometry`` (elem_x, angles_rad, t0_s, c, fs, nx, nz, x0, dx, z0, dz,
@@ -35,16 +36,20 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "pwbf_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
-_lib = None
+_LIB_OMP = os.path.join(_HERE, "liboracle_omp.so")
+_libs = {}
 
 
 def build(force: bool = False) -> str:
-    """Compile the C oracle (gcc -O2, no fast-math, single-threaded)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + f".tmp{os.getpid()}"
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-D_DEFAULT_SOURCE", "-fPIC", "-shared",
-                               "-fno-fast-math", "-o", tmp, _SRC, "-lm"])
-        os.replace(tmp, _LIB)
+    """Compile the C oracle (gcc -O2, no fast-math): the single-threaded library
+    and, from the same source with -fopenmp, the one that shares the pixel loop
+    among threads (bitwise the same values)."""
+    for lib, extra in ((_LIB, []), (_LIB_OMP, ["-fopenmp"])):
+        if force or not os.path.exists(lib) or os.path.getmtime(lib) < os.path.getmtime(_SRC):
+            tmp = lib + f".tmp{os.getpid()}"
+            subprocess.check_call(["gcc", "-O2", "-std=c11", "-D_DEFAULT_SOURCE", "-fPIC",
+                                   "-shared", "-fno-fast-math", *extra, "-o", tmp, _SRC, "-lm"])
+            os.replace(tmp, lib)
     return _LIB
 
 
@@ -59,12 +64,14 @@ class _Geom(ctypes.Structure):
                 ("f_number", ctypes.c_double), ("apod", ctypes.c_int32)]
 
 
-def _load():
-    global _lib
-    if _lib is None:
-        if not os.path.exists(_LIB):
+def _load(parallel: bool = False):
+    """The oracle library: single-threaded, or (parallel) the OpenMP build."""
+    key = bool(parallel)
+    if key not in _libs:
+        path = _LIB_OMP if key else _LIB
+        if not os.path.exists(path):
             build()
-        lib = ctypes.CDLL(_LIB)
+        lib = ctypes.CDLL(path)
         P = ctypes.POINTER(_Geom)
         lib.ora_tof_samples.restype = ctypes.c_double
         lib.ora_tof_samples.argtypes = [P, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
@@ -86,8 +93,8 @@ def _load():
         lib.ora_pdas.restype = ctypes.c_int
         lib.ora_pdas.argtypes = [P, ctypes.c_void_p, ctypes.c_int32, ctypes.c_double,
                                  ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]
-        _lib = lib
-    return _lib
+        _libs[key] = lib
+    return _libs[key]
 
 
 class _Bound:
@@ -137,22 +144,24 @@ def interp(u: np.ndarray, s: float) -> float:
     return _load().ora_interp(u.ctypes.data, len(u), s)
 
 
-def das(g, rf, angle: int = -1, pix=None) -> np.ndarray:
+def das(g, rf, angle: int = -1, pix=None, parallel: bool = False) -> np.ndarray:
     """DAS (Eq. 1). angle -1 = coherent compound over all angles. Returns [nx, nz]
-    when ``pix`` is None, else the values at the flat pixel indices ``pix``."""
+    when ``pix`` is None, else the values at the flat pixel indices ``pix``.
+    ``parallel`` runs the OpenMP build of the same source (same values)."""
     b = _Bound(g)
     rf = _rf64(g, rf)
     p = _pix(g, pix)
     n = g.nx * g.nz if p is None else len(p)
     out = np.empty(n, dtype=np.float64)
-    rc = _load().ora_das(b.ref, rf.ctypes.data, angle, None if p is None else p.ctypes.data, n,
+    rc = _load(parallel).ora_das(b.ref, rf.ctypes.data, angle, None if p is None else p.ctypes.data, n,
                          out.ctypes.data)
     if rc != 0:
         raise ValueError("ora_das rejected its arguments")
     return out.reshape(g.nx, g.nz) if p is None else out
 
 
-def dmas(g, rf, angle: int = -1, form: str = "identity", pix=None) -> np.ndarray:
+def dmas(g, rf, angle: int = -1, form: str = "identity", pix=None,
+         parallel: bool = False) -> np.ndarray:
     """RF DMAS with signed square-root compression; form "pairs" or "identity"."""
     b = _Bound(g)
     rf = _rf64(g, rf)
@@ -160,14 +169,15 @@ def dmas(g, rf, angle: int = -1, form: str = "identity", pix=None) -> np.ndarray
     n = g.nx * g.nz if p is None else len(p)
     out = np.empty(n, dtype=np.float64)
     f = {"pairs": 0, "identity": 1}[form]
-    rc = _load().ora_dmas(b.ref, rf.ctypes.data, angle, f, None if p is None else p.ctypes.data,
+    rc = _load(parallel).ora_dmas(b.ref, rf.ctypes.data, angle, f, None if p is None else p.ctypes.data,
                           n, out.ctypes.data)
     if rc != 0:
         raise ValueError("ora_dmas rejected its arguments")
     return out.reshape(g.nx, g.nz) if p is None else out
 
 
-def pdas(g, rf, angle: int = -1, p: float = 2.0, pix=None) -> np.ndarray:
+def pdas(g, rf, angle: int = -1, p: float = 2.0, pix=None,
+         parallel: bool = False) -> np.ndarray:
     """pDAS (Eqs. 2-3): sum of w sign(v)|v|^(1/p), then its signed p-th power;
     angle -1 sums the per-angle pDAS values."""
     b = _Bound(g)
@@ -175,7 +185,7 @@ def pdas(g, rf, angle: int = -1, p: float = 2.0, pix=None) -> np.ndarray:
     q = _pix(g, pix)
     n = g.nx * g.nz if q is None else len(q)
     out = np.empty(n, dtype=np.float64)
-    rc = _load().ora_pdas(b.ref, rf.ctypes.data, angle, float(p),
+    rc = _load(parallel).ora_pdas(b.ref, rf.ctypes.data, angle, float(p),
                           None if q is None else q.ctypes.data, n, out.ctypes.data)
     if rc != 0:
         raise ValueError("ora_pdas rejected its arguments")
@@ -201,7 +211,7 @@ def iq_demodulate(g, rf, fd: Optional[float] = None) -> np.ndarray:
 
 
 def iq_beamform(g, iq, form: str = "iqdas", angle: int = -1, fd: Optional[float] = None,
-                pix=None) -> np.ndarray:
+                pix=None, parallel: bool = False) -> np.ndarray:
     """IQ-DAS ("iqdas") or BB-DMAS ("bbdmas", Eq. 4) from baseband records ``iq``
     demodulated at fd (f0 by default); complex, [nx, nz] or at ``pix``. angle -1
     sums the complex per-angle values."""
@@ -217,7 +227,7 @@ def iq_beamform(g, iq, form: str = "iqdas", angle: int = -1, fd: Optional[float]
     out_re = np.empty(n)
     out_im = np.empty(n)
     fd = float(g.f0 if fd is None else fd)
-    rc = _load().ora_iq(b.ref, re.ctypes.data, im.ctypes.data, fd,
+    rc = _load(parallel).ora_iq(b.ref, re.ctypes.data, im.ctypes.data, fd,
                         {"iqdas": 0, "bbdmas": 1}[form], angle,
                         None if q is None else q.ctypes.data, n, out_re.ctypes.data,
                         out_im.ctypes.data)
@@ -285,14 +295,14 @@ def log_compress(env: np.ndarray, floor_db: float = -70.0) -> np.ndarray:
 
 
 def beamform(g, rf, mode: str = "das", angle: int = -1, bandpass: bool = False,
-             floor_db: float = -70.0, p: float = 2.0) -> dict:
+             floor_db: float = -70.0, p: float = 2.0, parallel: bool = False) -> dict:
     """The whole path for one frame: raw image, optional band-pass, envelope, log."""
     if mode == "das":
-        raw = das(g, rf, angle)
+        raw = das(g, rf, angle, parallel=parallel)
     elif mode == "pdas":
-        raw = pdas(g, rf, angle, p)
+        raw = pdas(g, rf, angle, p, parallel=parallel)
     else:
-        raw = dmas(g, rf, angle, "identity")
+        raw = dmas(g, rf, angle, "identity", parallel=parallel)
     out = {"rf": raw}
     src = raw
     if bandpass:

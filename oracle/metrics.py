@@ -15,10 +15,12 @@ Paper passages (Section II-D, "Evaluation Metrics"):
    mu and sigma are the mean and the (population) standard deviation of the
    envelope over the pixels inside the cyst and inside a background disc.
 
-Which pixels a disc holds is a float32 decision, taken here exactly as the GPU
-takes it (same formula, same float32 operations, no fused multiply-add): with
-cx = (x - x0) / dx, cz = (z - z0) / dz, sx = dx / r, sz = dz / r rounded to
-float32 once, pixel (ix, iz) is inside when ((ix - cx) sx)^2 + ((iz - cz) sz)^2 <= 1.
+A pixel belongs to a disc when the distance from its centre to the disc's
+centre is at most the radius, decided here in float64 from the grid
+convention (pixel (ix, iz) centred at (x0 + ix dx, z0 + iz dz)).
+``disc_distance`` also gives the distance in radii, so a caller can tell
+which pixels lie so close to the boundary that a float32 evaluation may
+decide them either way.
 """
 
 from __future__ import annotations
@@ -28,18 +30,22 @@ import math
 import numpy as np
 
 
+def pixel_centres(g):
+    """(X [nx, 1], Z [1, nz]) pixel-centre coordinates of grid g, float64."""
+    X = (g.x0 + np.arange(g.nx, dtype=np.float64) * g.dx)[:, None]
+    Z = (g.z0 + np.arange(g.nz, dtype=np.float64) * g.dz)[None, :]
+    return X, Z
+
+
+def disc_distance(g, x: float, z: float, r: float) -> np.ndarray:
+    """[nx, nz]: distance of every pixel centre from (x, z), in units of r."""
+    X, Z = pixel_centres(g)
+    return np.hypot(X - x, Z - z) / r
+
+
 def disc_mask(g, x: float, z: float, r: float) -> np.ndarray:
     """Boolean [nx, nz]: the pixels of grid g whose centres lie in the disc."""
-    f = np.float32
-    cx = f((x - g.x0) / g.dx)
-    cz = f((z - g.z0) / g.dz)
-    sx = f(g.dx / r)
-    sz = f(g.dz / r)
-    ix = np.arange(g.nx, dtype=np.float32)[:, None]
-    iz = np.arange(g.nz, dtype=np.float32)[None, :]
-    u = (ix - cx) * sx
-    v = (iz - cz) * sz
-    return (u * u + v * v) <= f(1.0)
+    return disc_distance(g, x, z, r) <= 1.0
 
 
 def region_stats(env: np.ndarray, mask: np.ndarray):
@@ -52,16 +58,21 @@ def region_stats(env: np.ndarray, mask: np.ndarray):
     return n, float(mu), float(math.sqrt(((vals - mu) ** 2).sum() / n))
 
 
-def contrast(g, env, cyst_in, cyst_out) -> dict:
-    """CR (Eq. 5) and CNR (Eq. 6) for one cyst: ``cyst_in`` and ``cyst_out`` are
-    (x, z, r) discs in metres for the inside and the background."""
-    n_in, mu_in, sd_in = region_stats(env, disc_mask(g, *cyst_in))
-    n_out, mu_out, sd_out = region_stats(env, disc_mask(g, *cyst_out))
+def contrast_from_masks(env, mask_in, mask_out) -> dict:
+    """CR (Eq. 5) and CNR (Eq. 6) of env between two pixel sets."""
+    n_in, mu_in, sd_in = region_stats(env, mask_in)
+    n_out, mu_out, sd_out = region_stats(env, mask_out)
     cr = 20.0 * math.log10(mu_in / mu_out) if mu_in > 0 and mu_out > 0 else float("nan")
     den = math.sqrt((sd_in ** 2 + sd_out ** 2) / 2.0)
     cnr = (mu_in - mu_out) / den if den > 0 else float("nan")
     return {"n_in": n_in, "n_out": n_out, "mu_in": mu_in, "mu_out": mu_out, "sigma_in": sd_in,
             "sigma_out": sd_out, "cr_db": cr, "cnr": cnr}
+
+
+def contrast(g, env, cyst_in, cyst_out) -> dict:
+    """CR (Eq. 5) and CNR (Eq. 6) for one cyst: ``cyst_in`` and ``cyst_out`` are
+    (x, z, r) discs in metres for the inside and the background."""
+    return contrast_from_masks(env, disc_mask(g, *cyst_in), disc_mask(g, *cyst_out))
 
 
 def _half_width(profile: np.ndarray, i0: int, half: float):
@@ -84,11 +95,13 @@ def _half_width(profile: np.ndarray, i0: int, half: float):
     return right - left
 
 
-def resolution(g, env, target) -> dict:
+def resolution(g, env, target, mask=None) -> dict:
     """Peak inside the disc ``target`` = (x, z, r) (first flat index among equal
-    maxima) and the lateral / axial FWHM through it, in metres."""
-    env = np.asarray(env, dtype=np.float32)
-    mask = disc_mask(g, *target)
+    maxima; ``mask`` overrides the disc's pixels) and the lateral / axial FWHM
+    through it, in metres, all in float64."""
+    env = np.asarray(env, dtype=np.float64)
+    if mask is None:
+        mask = disc_mask(g, *target)
     if not mask.any():
         return {"peak": float("nan"), "ix": -1, "iz": -1, "fwhm_x": float("nan"),
                 "fwhm_z": float("nan")}
@@ -96,7 +109,7 @@ def resolution(g, env, target) -> dict:
     k = int(np.argmax(masked))  # numpy returns the first maximum
     ix, iz = divmod(k, g.nz)
     peak = float(env[ix, iz])
-    half = float(np.float32(peak) * np.float32(0.5))
+    half = 0.5 * peak
     return {"peak": peak, "ix": ix, "iz": iz,
             "fwhm_x": _half_width(env[:, iz], ix, half) * g.dx,
             "fwhm_z": _half_width(env[ix, :], iz, half) * g.dz}

@@ -5,9 +5,12 @@
  * baseline may load it; the product path never does. It shares no code, header
  * or constant with the GPU library.
  *
- * Plain, slow and literal: single-threaded, double precision, libm sqrt/cos,
- * no blocking, no reordering. Every pixel value is evaluated straight from the
- * definition, one pixel, one angle and one element at a time.
+ * Plain, slow and literal: double precision, libm sqrt/cos, no blocking, no
+ * reordering. Every pixel value is evaluated straight from the definition, one
+ * pixel, one angle and one element at a time. Built as is, it runs on one
+ * thread; built with -fopenmp, the loop over the requested pixels is shared
+ * among threads (each pixel is still computed by one thread in the same
+ * order, so the values are bitwise those of the single-threaded build).
  *
  * What is computed (paper section II-B):
  *  - Eq. (1): y[p] = sum_i w_i[p] u_i[dn_p], the conventional delay-and-sum.
@@ -66,6 +69,15 @@ typedef struct {
 } ora_geom;
 
 enum { ORA_OK = 0, ORA_BAD = -1 };
+
+/* Every requested flat pixel index lies in [0, total). */
+static int check_pixels(const int64_t *pix, int64_t npix, int64_t total) {
+  if (npix < 0) return ORA_BAD;
+  if (pix)
+    for (int64_t k = 0; k < npix; ++k)
+      if (pix[k] < 0 || pix[k] >= total) return ORA_BAD;
+  return ORA_OK;
+}
 
 /* min_e(x_e sin th): the lateral term of the first-firing element for angle a. */
 static double first_fire(const ora_geom *g, int32_t a) {
@@ -189,11 +201,12 @@ int ora_das(const ora_geom *g, const double *rf, int32_t angle, const int64_t *p
   if (check(g, angle) != ORA_OK || !rf || !out) return ORA_BAD;
   int64_t total = (int64_t)g->nx * g->nz;
   if (!pix) npix = total;
+  if (check_pixels(pix, npix, total) != ORA_OK) return ORA_BAD;
   double first[ORA_MAX_ANGLES];
   for (int32_t a = 0; a < g->n_angles; ++a) first[a] = first_fire(g, a);
+#pragma omp parallel for schedule(dynamic, 16)
   for (int64_t k = 0; k < npix; ++k) {
     int64_t p = pix ? pix[k] : k;
-    if (p < 0 || p >= total) return ORA_BAD;
     double x, z;
     pixel_xz(g, p, &x, &z);
     double y = 0.0;
@@ -212,11 +225,12 @@ int ora_dmas(const ora_geom *g, const double *rf, int32_t angle, int32_t form, c
   if (check(g, angle) != ORA_OK || !rf || !out || (form != 0 && form != 1)) return ORA_BAD;
   int64_t total = (int64_t)g->nx * g->nz;
   if (!pix) npix = total;
+  if (check_pixels(pix, npix, total) != ORA_OK) return ORA_BAD;
   double first[ORA_MAX_ANGLES];
   for (int32_t a = 0; a < g->n_angles; ++a) first[a] = first_fire(g, a);
+#pragma omp parallel for schedule(dynamic, 16)
   for (int64_t k = 0; k < npix; ++k) {
     int64_t p = pix ? pix[k] : k;
-    if (p < 0 || p >= total) return ORA_BAD;
     double x, z;
     pixel_xz(g, p, &x, &z);
     double y = 0.0;
@@ -238,11 +252,12 @@ int ora_pdas(const ora_geom *g, const double *rf, int32_t angle, double p, const
   if (check(g, angle) != ORA_OK || !rf || !out || !(p >= 1.0)) return ORA_BAD;
   int64_t total = (int64_t)g->nx * g->nz;
   if (!pix) npix = total;
+  if (check_pixels(pix, npix, total) != ORA_OK) return ORA_BAD;
   double first[ORA_MAX_ANGLES];
   for (int32_t a = 0; a < g->n_angles; ++a) first[a] = first_fire(g, a);
+#pragma omp parallel for schedule(dynamic, 16)
   for (int64_t k = 0; k < npix; ++k) {
     int64_t q = pix ? pix[k] : k;
-    if (q < 0 || q >= total) return ORA_BAD;
     double x, z;
     pixel_xz(g, q, &x, &z);
     double y = 0.0;
@@ -309,11 +324,12 @@ int ora_iq(const ora_geom *g, const double *iq_re, const double *iq_im, double f
   if (form != 0 && form != 1) return ORA_BAD;
   int64_t total = (int64_t)g->nx * g->nz;
   if (!pix) npix = total;
+  if (check_pixels(pix, npix, total) != ORA_OK) return ORA_BAD;
   double first[ORA_MAX_ANGLES];
   for (int32_t a = 0; a < g->n_angles; ++a) first[a] = first_fire(g, a);
+#pragma omp parallel for schedule(dynamic, 16)
   for (int64_t k = 0; k < npix; ++k) {
     int64_t q = pix ? pix[k] : k;
-    if (q < 0 || q >= total) return ORA_BAD;
     double x, z;
     pixel_xz(g, q, &x, &z);
     double yr = 0.0, yi = 0.0;

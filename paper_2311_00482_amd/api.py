@@ -126,21 +126,9 @@ def alloc_outputs(g, want: Iterable[str], device) -> Dict[str, "object"]:
     return {k: torch.empty((ga.nx, ga.nz), dtype=torch.float32, device=device) for k in want}
 
 
-def beamform(g, rf, mode: str = "das", angle: int = -1, tile: Optional[Tile] = None,
-             want: Iterable[str] = ("rf",), out: Optional[Dict] = None, workspace=None,
-             stream=None, bandpass: bool = False, log_floor_db: float = -70.0,
-             p: Optional[float] = None) -> Dict:
-    """Run one frame through libpwbf. angle -1 = compound over all angles.
-    ``mode``: "das", "dmas" or "pdas" (root order ``p``, else the geometry's) on
-    RF; "iqdas" or "bbdmas" on complex64 IQ data from ``iq_demodulate`` (planes
-    "rf" = real part, "imag", "env" = magnitude, "log").
-
-    ``rf``: CUDA tensor [n_angles, n_channels, n_samples] of int16/float16/float32.
-    ``want``: planes among "rf", "filtered", "env", "log" (rf is always made).
-    ``out``: preallocated planes (float32 [nx, nz] CUDA tensors) by name.
-    Returns the dict of output planes. Work is enqueued on ``stream`` (default:
-    torch's current stream) and not waited for.
-    """
+def _prepare(g, rf, want, out, workspace, bandpass, log_floor_db, p):
+    """Marshal one frame's call: geometry, output planes (allocated when not
+    given), workspace; returns (geometry, outputs struct, planes, ws ptr, ws bytes)."""
     import torch
     ga = _as_geom(g, bandpass, log_floor_db)
     if bandpass and not ga.s.bandpass:
@@ -166,6 +154,27 @@ def beamform(g, rf, mode: str = "das", angle: int = -1, tile: Optional[Tile] = N
         workspace = torch.empty(need, dtype=torch.uint8, device=rf.device)
     ws_ptr = _ptr(workspace)
     ws_bytes = 0 if workspace is None else workspace.numel() * workspace.element_size()
+    return ga, o, out, ws_ptr, ws_bytes
+
+
+def beamform(g, rf, mode: str = "das", angle: int = -1, tile: Optional[Tile] = None,
+             want: Iterable[str] = ("rf",), out: Optional[Dict] = None, workspace=None,
+             stream=None, bandpass: bool = False, log_floor_db: float = -70.0,
+             p: Optional[float] = None) -> Dict:
+    """pwbf_beamform_ex: one frame through libpwbf with an optional explicit
+    launch shape. angle -1 = compound over all angles.
+    ``mode``: "das", "dmas" or "pdas" (root order ``p``, else the geometry's) on
+    RF; "iqdas" or "bbdmas" on complex64 IQ data from ``iq_demodulate`` (planes
+    "rf" = real part, "imag", "env" = magnitude, "log").
+
+    ``rf``: CUDA tensor [n_angles, n_channels, n_samples] of int16/float16/float32.
+    ``want``: planes among "rf", "filtered", "env", "log" (rf is always made).
+    ``out``: preallocated planes (float32 [nx, nz] CUDA tensors) by name.
+    Returns the dict of output planes. Work is enqueued on ``stream`` (default:
+    torch's current stream) and not waited for.
+    """
+    ga, o, out, ws_ptr, ws_bytes = _prepare(g, rf, want, out, workspace, bandpass,
+                                            log_floor_db, p)
     t = tile.c() if tile is not None else None
     rc = _abi.lib().pwbf_beamform_ex(ga.ref, _ptr(rf), _rf_code(rf), _MODES[mode], angle,
                                      ctypes.byref(t) if t is not None else None, ctypes.byref(o),
@@ -174,18 +183,36 @@ def beamform(g, rf, mode: str = "das", angle: int = -1, tile: Optional[Tile] = N
     return out
 
 
+def _named(symbol, g, rf, angle, want=("rf",), out=None, workspace=None, stream=None,
+           bandpass=False, log_floor_db=-70.0, p=None, mode=None, iq=False):
+    """One of the named single-frame entry points (pwbf_beamform_das, ...)."""
+    ga, o, out, ws_ptr, ws_bytes = _prepare(g, rf, want, out, workspace, bandpass,
+                                            log_floor_db, p)
+    fn = getattr(_abi.lib(), symbol)
+    st = _stream_ptr(stream, rf.device)
+    if mode is not None:  # pwbf_compound
+        rc = fn(ga.ref, _ptr(rf), _rf_code(rf), _MODES[mode], ctypes.byref(o), ws_ptr, ws_bytes,
+                st)
+    elif iq:
+        rc = fn(ga.ref, _ptr(rf), angle, ctypes.byref(o), ws_ptr, ws_bytes, st)
+    else:
+        rc = fn(ga.ref, _ptr(rf), _rf_code(rf), angle, ctypes.byref(o), ws_ptr, ws_bytes, st)
+    _abi.check(rc)
+    return out
+
+
 def beamform_das(g, rf, angle: int, **kw) -> Dict:
     """pwbf_beamform_das: DAS (Eq. 1) for one steering angle."""
     if angle < 0:
         raise ValueError("angle must be >= 0")
-    return beamform(g, rf, "das", angle, **kw)
+    return _named("pwbf_beamform_das", g, rf, angle, **kw)
 
 
 def beamform_dmas(g, rf, angle: int, **kw) -> Dict:
     """pwbf_beamform_dmas: RF DMAS for one steering angle."""
     if angle < 0:
         raise ValueError("angle must be >= 0")
-    return beamform(g, rf, "dmas", angle, **kw)
+    return _named("pwbf_beamform_dmas", g, rf, angle, **kw)
 
 
 def iq_demodulate(g, rf, out=None, stream=None):
@@ -299,26 +326,27 @@ def beamform_iqdas(g, iq, angle: int, **kw) -> Dict:
     """pwbf_beamform_iqdas: DAS of the delay-compensated IQ samples for one angle."""
     if angle < 0:
         raise ValueError("angle must be >= 0")
-    return beamform(g, iq, "iqdas", angle, **kw)
+    return _named("pwbf_beamform_iqdas", g, iq, angle, iq=True, **kw)
 
 
 def beamform_bbdmas(g, iq, angle: int, **kw) -> Dict:
     """pwbf_beamform_bbdmas: BB-DMAS (Eq. 4) for one angle."""
     if angle < 0:
         raise ValueError("angle must be >= 0")
-    return beamform(g, iq, "bbdmas", angle, **kw)
+    return _named("pwbf_beamform_bbdmas", g, iq, angle, iq=True, **kw)
 
 
 def beamform_pdas(g, rf, angle: int, p: float = 2.0, **kw) -> Dict:
     """pwbf_beamform_pdas: pDAS (Eqs. 2-3) of root order p for one steering angle."""
     if angle < 0:
         raise ValueError("angle must be >= 0")
-    return beamform(g, rf, "pdas", angle, p=p, **kw)
+    return _named("pwbf_beamform_pdas", g, rf, angle, p=p, **kw)
 
 
 def compound(g, rf, mode: str = "das", **kw) -> Dict:
-    """pwbf_compound: coherent sum over all angles of the per-angle DAS or DMAS."""
-    return beamform(g, rf, mode, -1, **kw)
+    """pwbf_compound: coherent sum over all angles of the per-angle images
+    (DAS, DMAS, pDAS; complex IQ-DAS, BB-DMAS)."""
+    return _named("pwbf_compound", g, rf, -1, mode=mode, **kw)
 
 
 # ------------------------------------------------------------------- tuning

@@ -83,31 +83,22 @@ constexpr int kRawBufferWord3 = 0x00020000;
 // Threads keep a fixed column of quads: with W4 = win / 4 quads per row and
 // R = blockDim / W4 >= 1, thread t stages quad t mod W4 of rows t / W4, + R,
 // + 2R, ..., so its entry offsets are set up once (the fewer than W4 threads
-// past R W4 stay idle). If a row has more quads than the block has threads,
-// each thread takes quads t, t + blockDim, ... of every row.
+// past R W4 stay idle). A window holds at most kMaxWindow = 64 entries (the
+// host refuses longer ones), so W4 <= 16 is never more than a wavefront.
 struct QuadWalk {
-  int row0, drow, jq, djq;
+  int row0, drow, j0;
   bool active;
 };
 __device__ __forceinline__ QuadWalk quad_walk(int W4) {
   const int bs = blockDim.x, t = threadIdx.x;
   QuadWalk w;
-  if (W4 <= bs) {
-    // t / W4 through a float reciprocal: (t + 0.5) / W4 lies at least 0.5 / W4
-    // from an integer and t < 2^10, so truncation yields the exact quotient
-    const float rw = __builtin_amdgcn_rcpf((float)W4);
-    w.row0 = (int)fmaf((float)t, rw, 0.5f * rw);
-    w.jq = t - w.row0 * W4;
-    w.drow = bs / W4;
-    w.djq = W4;
-    w.active = w.row0 < w.drow;
-  } else {
-    w.row0 = 0;
-    w.jq = t;
-    w.drow = 1;
-    w.djq = bs;
-    w.active = true;
-  }
+  // t / W4 through a float reciprocal: (t + 0.5) / W4 lies at least 0.5 / W4
+  // from an integer and t < 2^10, so truncation yields the exact quotient
+  const float rw = __builtin_amdgcn_rcpf((float)W4);
+  w.row0 = (int)fmaf((float)t, rw, 0.5f * rw);
+  w.j0 = (t - w.row0 * W4) << 2;
+  w.drow = bs / W4;
+  w.active = w.row0 < w.drow;
   return w;
 }
 
@@ -123,8 +114,8 @@ __device__ __forceinline__ void stage_windows(const FramePlan &P, int rows, int 
       const_cast<void *>(P.rf), (short)0, P.n_angles * P.n_channels * Ns * B, kRawBufferWord3);
   const QuadWalk w = quad_walk(win >> 2);
   if (!w.active) return;
-  for (int jq = w.jq; jq < (win >> 2); jq += w.djq) {
-    const int j0 = jq << 2;
+  {
+    const int j0 = w.j0;
     const float m0 = (float)(off - j0);  // delay coordinate of entry j0
     for (int row = w.row0; row < rows; row += w.drow) {
       const int2 rb = s_row[row];
@@ -167,8 +158,8 @@ __device__ __forceinline__ void stage_windows_iq(const FramePlan &P, int rows, i
       const_cast<void *>(P.rf), (short)0, P.n_angles * P.n_channels * Ns * 8, kRawBufferWord3);
   const QuadWalk w = quad_walk(win >> 2);
   if (!w.active) return;
-  for (int jq = w.jq; jq < (win >> 2); jq += w.djq) {
-    const int j0 = jq << 2;
+  {
+    const int j0 = w.j0;
     const float m0 = (float)(off - j0);
     for (int row = w.row0; row < rows; row += w.drow) {
       const int2 rb = s_row[row];
@@ -306,6 +297,16 @@ __device__ __forceinline__ float ff_f(ff a) { return a.hi + a.lo; }
 // quantity on the per-gather path is then a small offset inside the tile's
 // window, accurate to ~1e-6 samples, instead of an absolute delay rounded at
 // ~1e-4 samples.
+//
+// DMAS and pDAS take a root of every delayed sample, which is steep where the
+// sample crosses zero, so they take q as the wavefront's own centre pixel
+// instead: the bracketed terms are then split, in float-float, into an integer
+// (kT per angle, kR per channel, wave-uniform, folded into the LDS address)
+// and a float32 fraction of at most half a sample, and the float32 offsets
+// span only the wavefront's pixels (a few samples), which keeps the delay
+// rounding near 5e-7 of a sample. Their window entries are (u[n], du), read at
+// the fraction of the delay, so the per-wavefront integer shift needs no
+// change to the windows.
 template <int AM, bool PRED, int MODE, bool ONEGRP, bool SEL>
 __device__ __forceinline__ void process_tile_body(const FramePlan &P, int tz, int tx,
                                                   unsigned char *smem) {
@@ -317,6 +318,10 @@ __device__ __forceinline__ void process_tile_body(const FramePlan &P, int tz, in
   float2 *s_ph = (float2 *)(smem + plan_lds_ph_offset(P));  // [chunk] IQ: exp(2 pi i r (LR + off_r))
   int2 *s_row = (int2 *)(smem + plan_lds_row_offset(P));  // [chunk * A] window rows
   float2 *s_pairs = (float2 *)(smem + plan_lds_win_offset(P));
+  // DMAS, pDAS: per (wavefront, channel) {Dw, rw^2, rw, rx(w) - LR - off_r - kR} and kR
+  constexpr bool WREF = wave_ref_mode(MODE);
+  float4 *s_chw = (float4 *)(smem + plan_lds_wref_offset(P));
+  int *s_kr = (int *)(smem + plan_lds_wref_offset(P) + (size_t)P.wz * P.wx * P.chunk * 16);
 
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
@@ -345,20 +350,32 @@ __device__ __forceinline__ void process_tile_body(const FramePlan &P, int tz, in
   // Tile extent, clipped to the grid: lanes past the edge evaluate the edge
   // pixel again and write nothing, so every window only spans grid pixels.
   const int ixe = min(ix0 + TX - 1, P.nx - 1), ize = min(iz0 + TZ - 1, P.nz - 1);
-  const int ixq = (ix0 + ixe) >> 1, izq = (iz0 + ize) >> 1;  // reference pixel q
-  // pixel offsets from q, and the tile's offset range
-  const float dx = (float)(min(ix, ixe) - ixq) * P.DX;
-  const float dz = (float)(min(iz, ize) - izq) * P.DZ;
+  const int ixq = (ix0 + ixe) >> 1, izq = (iz0 + ize) >> 1;  // reference pixel q of the tile
+  // the tile's offset range from q (window origins)
   const float dxlo = (float)(ix0 - ixq) * P.DX, dxhi = (float)(ixe - ixq) * P.DX;
   const float dzlo = (float)(iz0 - izq) * P.DZ, dzhi = (float)(ize - izq) * P.DZ;
-  // reference position in float-float
+  // tile reference position in float-float
   const ff Xq = ff_add(ff_mul({(float)ixq, 0.f}, {P.DX, P.DXl}), {P.X0, P.X0l});
   const ff Zq = ff_add(ff_mul({(float)izq, 0.f}, {P.DZ, P.DZl}), {P.Z0, P.Z0l});
   const float Zqf = ff_f(Zq);
-  const float Zp = Zqf + dz;
+  // reference of the per-gather offsets: q, or the centre of the wavefront's
+  // pixels (clipped to the tile's grid pixels) for DMAS and pDAS
+  int ixr = ixq, izr = izq;
+  if constexpr (WREF) {
+    const int bx0 = min(ix0 + wxi * lx, ixe), bz0 = min(iz0 + wzi * lz, ize);
+    ixr = (bx0 + min(bx0 + lx - 1, ixe)) >> 1;
+    izr = (bz0 + min(bz0 + lz - 1, ize)) >> 1;
+  }
+  const ff Xr = WREF ? ff_add(ff_mul({(float)ixr, 0.f}, {P.DX, P.DXl}), {P.X0, P.X0l}) : Xq;
+  const ff Zr = WREF ? ff_add(ff_mul({(float)izr, 0.f}, {P.DZ, P.DZl}), {P.Z0, P.Z0l}) : Zq;
+  const float Zrf = ff_f(Zr);
+  // the pixel's offsets from the reference
+  const float dx = (float)(min(ix, ixe) - ixr) * P.DX;
+  const float dz = (float)(min(iz, ize) - izr) * P.DZ;
+  const float Zp = Zrf + dz;
   // half the aperture scale: |x - x_e| * hA is half the normalised distance r
   const float hA = P.apod == kNone ? 0.f : (Zp > 0.f ? 0.5f * (P.ap_k / Zp) : __builtin_inff());
-  const float cp = fmaf(2.f * Zqf, dz, fmaf(dx, dx, dz * dz));
+  const float cp = fmaf(2.f * Zrf, dz, fmaf(dx, dx, dz * dz));
   float dx2 = 2.f * dx;
   asm("" : "+v"(dx2));  // computed once, not again in every channel iteration
 
@@ -418,9 +435,33 @@ __device__ __forceinline__ void process_tile_body(const FramePlan &P, int tz, in
     e_hi = __builtin_amdgcn_readfirstlane(e_hi);
   }
   float txl[AM];
+  int kt8[WREF ? AM : 1];  // DMAS, pDAS: window byte offset of angle a's integer shift kT
+  if constexpr (WREF) {
+    // lane a of every wavefront: its reference's transmit delay in the window
+    // of angle a, split into kT (integer) and a fraction of at most 1/2
+    float ftl = 0.f;
+    int ktl = 0;
+    if (lane < A) {
+      const ff sa = {P.sa[lane], P.sal[lane]}, ca = {P.ca[lane], P.cal[lane]};
+      const ff to = {P.to[lane], P.tol[lane]};
+      const ff t = ff_add(ff_add(ff_add(ff_mul(Xr, sa), ff_mul(Zr, ca)), ff_neg(to)),
+                          {-(float)(s_lt[lane] + P.off_t), 0.f});
+      const float k = rintf(t.hi);
+      ftl = (t.hi - k) + t.lo;  // t.hi - k is exact (|t.hi - k| <= 1/2 and k integral)
+      ktl = (int)k;
+    }
 #pragma unroll
-  for (int a = 0; a < AM; ++a)
-    if (!PRED || a < A) txl[a] = s_txq[a] + fmaf(dx, P.sa[a], dz * P.ca[a]);
+    for (int a = 0; a < AM; ++a)
+      if (!PRED || a < A) {
+        txl[a] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ftl), a)) +
+                 fmaf(dx, P.sa[a], dz * P.ca[a]);
+        kt8[a] = __builtin_amdgcn_readlane(ktl, a) * 8 + a * win * 8;
+      }
+  } else {
+#pragma unroll
+    for (int a = 0; a < AM; ++a)
+      if (!PRED || a < A) txl[a] = s_txq[a] + fmaf(dx, P.sa[a], dz * P.ca[a]);
+  }
 
   float total = 0.f;
   float S[MODE == kDas ? 1 : AM];  // per-angle sums: compressed samples (DMAS, pDAS), Re (IQ)
@@ -439,7 +480,7 @@ __device__ __forceinline__ void process_tile_body(const FramePlan &P, int tz, in
     // rx(q) in float-float, and the terms of the receive-delay difference;
     // channel c is taken by thread blockDim - 1 - c, so that these run in other
     // wavefronts than the row table below, which starts at thread 0.
-    for (int c = (int)blockDim.x - 1 - tid; c < cnt_pad; c += blockDim.x) {
+    for (int c = (int)blockDim.x - 1 - tid; !WREF && c < cnt_pad; c += blockDim.x) {
       const int e = min(e0 + c, N - 1);
       const ff xe = {P.xe[e], P.xel[e]};
       const ff dq = ff_add(Xq, ff_neg(xe));
@@ -453,15 +494,37 @@ __device__ __forceinline__ void process_tile_body(const FramePlan &P, int tz, in
     }
     // Window rows r = c A + a: the record of (angle a, channel e0 + c) and the
     // first sample LT_a + LR (LR from the same expression as above); rows of
-    // padding channels (past e_hi) read all zero.
+    // padding channels (past e_hi) read all zero. The record offset is a full
+    // 32-bit product (n_samples may exceed the 24-bit multiplier's range; the
+    // host bounds the product below 2^31).
     const int rows = cnt_pad * A, off = P.off_t + P.off_r;
     for (int r = tid; r < rows; r += blockDim.x) {
       const int c = r / A, a = r - c * A;
       const int e = min(e0 + c, N - 1);
       const float dqf = ff_f(ff_add(Xq, ff_neg({P.xe[e], P.xel[e]})));
       const float lr = window_lr(dqf, dxlo, dxhi, Zqf + dzlo, Zqf + dzhi);
-      s_row[r] = make_int2(__mul24(__mul24(a, N) + e, P.n_samples),
+      s_row[r] = make_int2((__mul24(a, N) + e) * P.n_samples,
                            e0 + c < e_hi ? s_lt[a] + (int)lr : -(1 << 30));
+    }
+    if constexpr (WREF) {
+      // every wavefront, for its own reference pixel and each channel of the
+      // chunk: Dw = Xw - Xe, rw^2, rw, and rw - LR - off_r split into the
+      // integer kR and a fraction of at most 1/2 (LR from the same expression
+      // as the window rows)
+      for (int c = lane; c < cnt_pad; c += kWave) {
+        const int e = min(e0 + c, N - 1);
+        const ff xe = {P.xe[e], P.xel[e]};
+        const float dqf = ff_f(ff_add(Xq, ff_neg(xe)));
+        const float lr = window_lr(dqf, dxlo, dxhi, Zqf + dzlo, Zqf + dzhi);
+        const ff dw = ff_add(Xr, ff_neg(xe));
+        const ff rw2 = ff_add(ff_mul(dw, dw), ff_mul(Zr, Zr));
+        const ff rw = ff_sqrt(rw2);
+        const ff rrel = ff_add(rw, {-(lr + (float)P.off_r), 0.f});
+        const float k = rintf(rrel.hi);
+        const int slot = wave * chunk + c;
+        s_chw[slot] = make_float4(ff_f(dw), ff_f(rw2), ff_f(rw) + 1e-20f, (rrel.hi - k) + rrel.lo);
+        s_kr[slot] = (int)k;
+      }
     }
     __syncthreads();
     if constexpr (IQ)
@@ -477,7 +540,11 @@ __device__ __forceinline__ void process_tile_body(const FramePlan &P, int tz, in
     const int wstride = win * P.entry_bytes;  // bytes between angle windows
     for (int k = 0; k < cnt; k += cpw) {
       const int c = ONEGRP ? k : k + grp;
-      const float4 ch = s_ch[c];
+      const int slot = wave * chunk + c;
+      const float4 ch = WREF ? s_chw[slot] : s_ch[c];
+      // DMAS, pDAS: the wavefront's integer shift of this channel's window
+      int kr = 0;
+      if constexpr (WREF) kr = ONEGRP ? __builtin_amdgcn_readfirstlane(s_kr[slot]) : s_kr[slot];
       // receive delay relative to the window origin, as a difference from rx(q)
       const float num = fmaf(dx2, ch.x, cp);
       const float den = __builtin_amdgcn_sqrtf(ch.y + num) + ch.z;
@@ -485,7 +552,9 @@ __device__ __forceinline__ void process_tile_body(const FramePlan &P, int tz, in
       const float w = apod_weight<SEL>(fabsf(ch.x + dx) * hA, hk, hb);
       // delays are centred: entry n of the window is read as n + off_t + off_r
       const char *wb = (const char *)s_pairs +
-                       ((size_t)c * A * win + P.off_t + P.off_r) * (IQ ? 16 : 8);
+                       ((size_t)c * A * win + P.off_t + P.off_r + kr) * (IQ ? 16 : 8);
+      // the window of angle a: wb + a * wstride, with the wavefront's transmit
+      // shift kT for DMAS and pDAS (kt8 holds both, in bytes)
       if constexpr (MODE == kDas) {
         float acc = -0.f;  // x + (-0) == x for every x: the first add folds away
 #pragma unroll
@@ -537,7 +606,7 @@ __device__ __forceinline__ void process_tile_body(const FramePlan &P, int tz, in
               const float s = txl[a] + rxl;
               const int n = floor_i32(s);
               const float f = __builtin_amdgcn_fractf(s);
-              const float2 p = *(const float2 *)(wb + a * wstride + (n << 3));
+              const float2 p = *(const float2 *)(wb + kt8[WREF ? a : 0] + (n << 3));
               const float v = fmaf(f, p.y, p.x);
               S[a] = fmaf(w, copysignf(__builtin_amdgcn_sqrtf(fabsf(v)), v), S[a]);
             }
@@ -549,7 +618,7 @@ __device__ __forceinline__ void process_tile_body(const FramePlan &P, int tz, in
               const float s = txl[a] + rxl;
               const int n = floor_i32(s);
               const float f = __builtin_amdgcn_fractf(s);
-              const float2 p = *(const float2 *)(wb + a * wstride + (n << 3));
+              const float2 p = *(const float2 *)(wb + kt8[WREF ? a : 0] + (n << 3));
               const float v = fmaf(f, p.y, p.x);
               const float r = __builtin_amdgcn_exp2f(ip * __builtin_amdgcn_logf(fabsf(v)));
               S[a] = fmaf(w, copysignf(r, v), S[a]);
@@ -564,7 +633,7 @@ __device__ __forceinline__ void process_tile_body(const FramePlan &P, int tz, in
             const float s = txl[a] + rxl;
             const int n = floor_i32(s);
             const float f = __builtin_amdgcn_fractf(s);
-            const float2 p = *(const float2 *)(wb + a * wstride + (n << 3));
+            const float2 p = *(const float2 *)(wb + kt8[WREF ? a : 0] + (n << 3));
             const float v = fmaf(f, p.y, p.x);
             const float r = __builtin_amdgcn_sqrtf(fabsf(v));
             S[a] = fmaf(w, copysignf(r, v), S[a]);

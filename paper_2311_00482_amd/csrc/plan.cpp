@@ -203,8 +203,8 @@ static int window_entries(FramePlan &p, int TZ, int TX) {
 // Apply launch shape t to plan P (geometry already filled in): window length,
 // channels per LDS chunk. PWBF_E_UNSUPPORTED when even cpw channels do not fit.
 static int fit_tile(const pwbf_geometry *g, pwbf_tile t, FramePlan *P, std::string *err) {
-  if (t.cpw != 1 && t.cpw != 2 && t.cpw != 4)
-    return fail(err, PWBF_E_INVALID, "tile.cpw %d not in {1, 2, 4}", t.cpw);
+  if (t.cpw != 1 && t.cpw != 2 && t.cpw != 4 && t.cpw != 8 && t.cpw != 16)
+    return fail(err, PWBF_E_INVALID, "tile.cpw %d not in {1, 2, 4, 8, 16}", t.cpw);
   const int ppw = kWave / t.cpw;
   if (t.lz < 1 || t.lz > ppw || (t.lz & (t.lz - 1)))
     return fail(err, PWBF_E_INVALID, "tile.lz %d not a power of two in 1..%d", t.lz, ppw);
@@ -224,8 +224,16 @@ static int fit_tile(const pwbf_geometry *g, pwbf_tile t, FramePlan *P, std::stri
   P->tile_x = TX;
   // a tile's pixels never extend past the grid (edge lanes repeat the edge pixel)
   P->win = window_entries(*P, std::min(TZ, g->nz), std::min(TX, g->nx));
-  const size_t per_channel =
-      (size_t)P->n_angles * (P->win * P->entry_bytes + 8) + (is_iq_mode(P->mode) ? 24 : 16);
+  const int wmax = max_window(P->mode);
+  if (P->win > wmax)
+    return fail(err, PWBF_E_UNSUPPORTED,
+                "tile of %d x %d pixels needs LDS windows of %d entries (limit %d for this "
+                "beamformer, which keeps float32 delay offsets under %d samples); use a "
+                "shallower or narrower tile",
+                TZ, TX, P->win, wmax, wmax / 2);
+  const size_t per_channel = (size_t)P->n_angles * (P->win * P->entry_bytes + 8) +
+                             (is_iq_mode(P->mode) ? 24 : 16) +
+                             (wave_ref_mode(P->mode) ? (size_t)t.wz * t.wx * 20 : 0);
   const size_t fixed = kLdsAngleBytes + 16;
   int chunk = t.chunk;
   if (chunk == 0) {
@@ -255,8 +263,14 @@ static int plan_frame_uncached(const pwbf_geometry *g, int dtype, int mode, int 
     return fail(err, PWBF_E_INVALID, "the IQ modes take complex IQ input (PWBF_C32), the others RF");
   if (is_iq_mode(mode) && !(g->f0 > 0.0 && finite(g->f0)))
     return fail(err, PWBF_E_INVALID, "the IQ modes need f0 > 0 (the demodulation frequency)");
-  if (mode == kPdas && !(g->pdas_p >= 1.0 && g->pdas_p <= 16.0))
-    return fail(err, PWBF_E_INVALID, "pdas_p = %g outside 1..16", g->pdas_p);
+  if (mode == kPdas && !(g->pdas_p >= 1.0 && finite(g->pdas_p)))
+    return fail(err, PWBF_E_INVALID, "pdas_p = %g must be a finite number >= 1", g->pdas_p);
+  // A root steeper than the square root amplifies the float32 delay rounding
+  // near zero crossings of the delayed samples past the 1e-5 agreement with the
+  // definition (measured: p = 3 reaches 1.03e-5), so the kernels take 1 <= p <= 2.
+  if (mode == kPdas && g->pdas_p > 2.0)
+    return fail(err, PWBF_E_UNSUPPORTED, "pdas_p = %g above 2 (the kernels take 1 <= p <= 2)",
+                g->pdas_p);
   if (angle < -1 || angle >= g->n_angles)
     return fail(err, PWBF_E_INVALID, "angle %d outside 0..%d", angle, g->n_angles - 1);
   if (mode == kDmas && g->n_channels < 2)
@@ -300,19 +314,14 @@ static int plan_frame_uncached(const pwbf_geometry *g, int dtype, int mode, int 
   }
 
   // An explicit tile is taken as given; an absent or all-zero tile takes the
-  // tuned entry for this shape if there is one, else the default, which falls
-  // back to shallower / narrower tiles until its windows fit in LDS.
+  // tuned entry for this shape if there is one and it fits, else the default;
+  // when that does not fit (LDS or window length), the fitting shape with the
+  // most pixels per tile, then the shortest window, then the fewest lane groups.
   pwbf_tile d = default_tile(g, na, mode);
   const bool zero_tile = tile_in && !tile_in->cpw && !tile_in->lz && !tile_in->wz &&
                          !tile_in->wx && !tile_in->chunk;
-  pwbf_tile tuned;
-  if ((!tile_in || zero_tile) && tune_lookup(shape_key(g, dtype, mode, angle, waves), &tuned)) {
-    tile_in = &tuned;
-  } else if (zero_tile) {
-    tile_in = nullptr;
-  }
-  pwbf_tile cands[12];
-  int nc = 0;
+  if (zero_tile) tile_in = nullptr;
+  int rc_fit = PWBF_OK;
   if (tile_in) {
     pwbf_tile t = *tile_in;
     if (t.cpw == 0) t.cpw = d.cpw;
@@ -321,32 +330,50 @@ static int plan_frame_uncached(const pwbf_geometry *g, int dtype, int mode, int 
       t.wz = d.wz;
       t.wx = d.wx;
     }
-    cands[nc++] = t;
-  } else if (waves == 8) {
-    // batch blocks: always 8 wavefronts; shrink the tile by its lane layout
-    cands[nc++] = d;
-    const pwbf_tile more[] = {{d.cpw, 8, 1, 8, 0}, {d.cpw, 4, 1, 8, 0}, {4, 4, 1, 8, 0},
-                              {4, 2, 1, 8, 0},     {4, 1, 1, 8, 0}};
-    for (const pwbf_tile &m : more)
-      if (m.cpw >= d.cpw && m.lz <= kWave / m.cpw) cands[nc++] = m;
+    if (waves && t.wz * t.wx != waves)
+      return fail(err, PWBF_E_INVALID, "batch tiles need wz * wx = %d (got %d x %d)", waves,
+                  t.wz, t.wx);
+    rc_fit = fit_tile(g, t, P, err);
   } else {
-    cands[nc++] = d;
-    const pwbf_tile more[] = {{d.cpw, 16, 1, 4, 0}, {d.cpw, 16, 1, 2, 0}, {d.cpw, 16, 1, 1, 0},
-                              {d.cpw, 8, 1, 1, 0},  {d.cpw, 4, 1, 1, 0},  {d.cpw, 2, 1, 1, 0},
-                              {d.cpw, 1, 1, 1, 0}};
-    for (const pwbf_tile &m : more)
-      if (m.lz <= kWave / m.cpw) cands[nc++] = m;
-  }
-  int rc_fit = PWBF_OK;
-  for (int ci = 0; ci < nc; ++ci) {
-    if (waves && cands[ci].wz * cands[ci].wx != waves) {
-      rc_fit = fail(err, PWBF_E_INVALID, "batch tiles need wz * wx = %d (got %d x %d)", waves,
-                    cands[ci].wz, cands[ci].wx);
-      if (tile_in) break;
-      continue;
+    pwbf_tile tuned;
+    bool done = false;
+    if (tune_lookup(shape_key(g, dtype, mode, angle, waves), &tuned) &&
+        (!waves || tuned.wz * tuned.wx == waves))
+      done = fit_tile(g, tuned, P, err) == PWBF_OK;
+    if (!done && (!waves || d.wz * d.wx == waves)) done = fit_tile(g, d, P, err) == PWBF_OK;
+    if (!done) {
+      // every shape with at least the default's lane groups and the required
+      // wavefront count; the choice depends on the geometry only. Groups of 8
+      // or 4 pixels (cpw 8, 16) keep windows short on grids with pixels tens of
+      // samples deep, such as 32 rows over 3 cm at 50 MHz.
+      static const int kArr[][2] = {{2, 4}, {1, 8}, {4, 2}, {8, 1}, {1, 4}, {2, 2},
+                                    {4, 1}, {1, 2}, {2, 1}, {1, 1}};
+      pwbf_tile best = {0, 0, 0, 0, 0};
+      int best_px = 0, best_win = 0;
+      for (int cpw = d.cpw; cpw <= 16; cpw *= 2)
+        for (int lz = 1; lz <= kWave / cpw; lz *= 2)
+          for (const auto &wa : kArr) {
+            if (waves ? wa[0] * wa[1] != waves : wa[0] * wa[1] > kMaxWavesPerBlock) continue;
+            const pwbf_tile t = {cpw, lz, wa[0], wa[1], 0};
+            FramePlan Q = *P;
+            std::string e2;
+            if (fit_tile(g, t, &Q, &e2) != PWBF_OK) continue;
+            const int px = std::min(Q.tile_z, g->nz) * std::min(Q.tile_x, g->nx);
+            if (px > best_px || (px == best_px && Q.win < best_win)) {
+              best = t;
+              best_px = px;
+              best_win = Q.win;
+            }
+          }
+      if (best_px > 0) {
+        rc_fit = fit_tile(g, best, P, err);
+      } else {
+        rc_fit = fail(err, PWBF_E_UNSUPPORTED,
+                      "no launch shape keeps the LDS windows within %d entries on this grid "
+                      "(pixel pitch %.3g x %.3g samples); use a finer grid",
+                      max_window(mode), (double)P->DX, (double)P->DZ);
+      }
     }
-    rc_fit = fit_tile(g, cands[ci], P, err);
-    if (rc_fit != PWBF_E_UNSUPPORTED || tile_in) break;
   }
   if (rc_fit) return rc_fit;
   const int TZ = P->tile_z, TX = P->tile_x;

@@ -32,6 +32,21 @@ enum Dtype : int32_t { kI16 = 0, kF16 = 1, kF32 = 2, kC32 = 3 };
 enum Mode : int32_t { kDas = 0, kDmas = 1, kPdas = 2, kIqdas = 3, kBbdmas = 4 };
 
 PWBF_HD constexpr bool is_iq_mode(int mode) { return mode == kIqdas || mode == kBbdmas; }
+
+// Longest LDS window per (channel, angle), in entries. The kernel holds every
+// per-gather delay as a float32 offset centred on its window, so its rounding
+// grows with the window: 64 entries keep the offsets below 32 samples (2^-19 of
+// a sample resolution), which holds DAS and IQ-DAS within 1e-5 of the float64
+// definition. DMAS, pDAS and BB-DMAS take a root of each delayed sample, steep
+// where the sample crosses zero, so a delay error there is amplified; their
+// windows are held to 32 entries (offsets below 16 samples). Longer windows are
+// refused (shallower or narrower tiles keep them short).
+constexpr int kMaxWindow = 64;
+constexpr int kMaxWindowRoot = 32;
+PWBF_HD constexpr int max_window(int mode) {
+  return (mode == kDmas || mode == kPdas || mode == kBbdmas) ? kMaxWindowRoot : kMaxWindow;
+}
+
 enum Apod : int32_t { kHann = 0, kBoxcar = 1, kNone = 2 };
 
 struct FramePlan {
@@ -75,16 +90,31 @@ struct PostPlan {
   float floor_db;
 };
 
+// The beamformers that take a root of every delayed sample (DMAS, pDAS) form
+// each pixel's delays relative to its wavefront's own reference pixel rather
+// than the tile's, so the float32 offsets on the gather path stay within the
+// wavefront's few samples of delay spread (the root amplifies delay rounding
+// near zero crossings); DAS and the IQ modes keep the tile reference.
+PWBF_HD constexpr bool wave_ref_mode(int mode) { return mode == kDmas || mode == kPdas; }
+
 // LDS of a block: per angle {tx(q) - LT, LT, transmit phasor} (16 bytes), per
 // channel of the chunk {Dq, rq^2, rq, rx(q) - LR} (16) and the receive phasor
-// (8, IQ modes only), per window row (channel, angle) of the chunk its record
-// offset and first sample (8), then the windows.
+// (8, IQ modes only), per (wavefront, channel) of the chunk the wavefront's
+// reference terms (16) and integer window offset (4) (DMAS and pDAS only), per
+// window row (channel, angle) of the chunk its record offset and first sample
+// (8), then the windows.
 constexpr size_t kLdsAngleBytes = kMaxAngles * 16;
 PWBF_HD inline size_t plan_lds_ph_offset(const FramePlan &p) {
   return kLdsAngleBytes + (size_t)p.chunk * 16;
 }
-PWBF_HD inline size_t plan_lds_row_offset(const FramePlan &p) {
+PWBF_HD inline size_t plan_lds_wref_offset(const FramePlan &p) {
   return plan_lds_ph_offset(p) + (is_iq_mode(p.mode) ? (size_t)p.chunk * 8 : 0);
+}
+PWBF_HD inline size_t plan_lds_wref_bytes(const FramePlan &p) {
+  return wave_ref_mode(p.mode) ? (size_t)p.wz * p.wx * p.chunk * 20 : 0;
+}
+PWBF_HD inline size_t plan_lds_row_offset(const FramePlan &p) {
+  return plan_lds_wref_offset(p) + plan_lds_wref_bytes(p);
 }
 PWBF_HD inline size_t plan_lds_win_offset(const FramePlan &p) {
   return (plan_lds_row_offset(p) + (size_t)p.chunk * p.n_angles * 8 + 15) / 16 * 16;

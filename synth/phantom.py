@@ -91,7 +91,8 @@ def phantom_scaled(g: Geometry, rng: np.random.Generator, point_amp: float = 10.
 def phantom_c3(g: Geometry, rng: np.random.Generator, n_points: int = 20, n_cysts: int = 3,
                n_speckle: int = 20000, point_amp: float = 10.0) -> Phantom:
     """20 points and 3 anechoic cysts (radius U[2, 4] mm, non-overlapping, no point
-    inside), speckle uniform over the field of view and removed inside the cysts."""
+    within 3 mm of a cyst), speckle uniform over the field of view and removed
+    inside the cysts."""
     # points first (draw order), placed after the cysts are known by rejection
     pts_raw = np.stack([rng.uniform(-17e-3, 17e-3, 4 * n_points),
                         rng.uniform(7e-3, 43e-3, 4 * n_points)], 1)
@@ -109,7 +110,9 @@ def phantom_c3(g: Geometry, rng: np.random.Generator, n_points: int = 20, n_cyst
             m |= (x - cx) ** 2 + (z - cz) ** 2 < (r + margin) ** 2
         return m
 
-    keep = ~inside(pts_raw[:, 0], pts_raw[:, 1], 0.5e-3)
+    # points stay 3 mm (several lateral widths of the point response, side
+    # lobes included) outside every cyst, so no cyst reads a point's energy
+    keep = ~inside(pts_raw[:, 0], pts_raw[:, 1], 3e-3)
     pts = pts_raw[keep][:n_points]
     assert len(pts) == n_points
     xp = _snap(pts[:, 0], g.x0, g.dx, g.nx)

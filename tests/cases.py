@@ -34,42 +34,72 @@ def rand_rf(g, seed, kind="f32", white=False):
 SMALL = [
     # name, geometry kwargs, mode, angle, tile, dtype
     ("das_1ch", dict(n_channels=1), "das", 0, None, "f32"),
-    ("das_ragged_cpw1", dict(nx=37, nz=100), "das", 0, (1, 64, 1, 4, 0), "f32"),
+    ("das_ragged_cpw1", dict(nx=37, nz=100), "das", 0, (1, 16, 1, 2, 0), "f32"),
     ("das_ragged_cpw2", dict(nx=13, nz=257), "das", 0, (2, 8, 2, 2, 6), "i16"),
-    ("das_ragged_cpw4", dict(nx=9, nz=33, n_channels=7), "das", 0, (4, 16, 1, 3, 4), "f32"),
+    ("das_ragged_cpw4", dict(nx=9, nz=33, n_channels=7), "das", 0, (4, 8, 1, 1, 4), "f32"),
     ("das_one_pixel", dict(nx=1, nz=1), "das", 0, None, "f32"),
-    ("das_one_column", dict(nx=1, nz=300), "das", 0, (1, 64, 3, 1, 0), "f32"),
+    # lane groups of 8 and 4 pixels (the shapes coarse grids fall back to)
+    ("das_cpw8", dict(nx=37, nz=100, angles_deg=(-5.0, 0.0, 5.0)), "das", -1, (8, 8, 1, 2, 0),
+     "f32"),
+    ("dmas_cpw16", dict(nx=21, nz=77, n_channels=20), "dmas", 0, (16, 2, 2, 2, 0), "i16"),
+    ("das_one_column", dict(nx=1, nz=300), "das", 0, (1, 64, 1, 1, 0), "f32"),
     ("das_boxcar", dict(apod="boxcar"), "das", 0, None, "f32"),
     ("das_no_apod_near_array", dict(apod="none", z_min=-1e-3, z_max=4e-3), "das", 0, None, "f32"),
     ("das_hann_near_array_cpw1", dict(z_min=-1e-3, z_max=4e-3), "das", 0, (1, 16, 1, 2, 0), "f32"),
     ("compound_3a_boxcar_cpw1", dict(apod="boxcar", angles_deg=(-12.0, 0.0, 9.0)), "das", -1,
      (1, 16, 1, 2, 0), "f32"),
     ("das_record_too_short", dict(n_samples=120), "das", 0, None, "f32"),
-    # a one-wavefront block whose window (264 entries, 66 quads) is wider than
-    # the block: the staging threads walk several quads of every row
-    ("das_window_wider_than_block", dict(nz=64, z_min=3e-3, z_max=13e-3, nx=5), "das", 0,
-     (1, 64, 1, 1, 0), "f32"),
-    ("compound_3a_window_wider_than_block", dict(nz=64, z_min=3e-3, z_max=13e-3, nx=5,
-                                                 angles_deg=(-10.0, 0.0, 10.0)), "das", -1,
-     (1, 64, 1, 1, 0), "i16"),
+    # a coarse grid (pixels of 15.6 x 2 samples) whose default tile does not
+    # fit the window limit: the plan falls back to the largest tile that does
+    ("das_coarse_grid_fallback", dict(nz=64, z_min=3e-3, z_max=13e-3, nx=5), "das", 0, None,
+     "f32"),
+    ("compound_3a_coarse_grid_fallback", dict(nz=64, z_min=3e-3, z_max=13e-3, nx=5,
+                                              angles_deg=(-10.0, 0.0, 10.0)), "das", -1, None,
+     "i16"),
+    # the longest window the kernels accept (64 entries)
+    ("das_window_at_limit", dict(nx=21, nz=77), "das", 0, (2, 16, 1, 4, 4), "f32"),
     ("compound_3a", dict(angles_deg=(-12.0, 0.0, 9.0)), "das", -1, None, "f32"),
     ("compound_7a_t0", dict(angles_deg=(-15., -10., -5., 0., 5., 10., 15.),
                             t0=(0.5e-6, 0.0, -0.3e-6, 1e-6, 0.0, 0.2e-6, 0.0)), "das", -1,
-     (1, 16, 2, 2, 0), "f32"),
+     (1, 16, 1, 2, 0), "f32"),
     ("compound_17a_generic", dict(angles_deg=tuple(range(-16, 18, 2)), nx=11, nz=70), "das",
      -1, None, "f32"),
     ("compound_32a_generic", dict(angles_deg=tuple(np.linspace(-20, 20, 32)), nx=6, nz=40,
-                                  n_channels=8), "das", -1, (1, 32, 1, 2, 0), "f32"),
+                                  n_channels=8), "das", -1, None, "f32"),
     ("angle_slab", dict(angles_deg=(-8.0, 4.0, 11.0)), "das", 2, None, "i16"),
     ("dmas_2ch", dict(n_channels=2), "dmas", 0, None, "f32"),
-    ("dmas_window_wider_than_block", dict(nz=64, z_min=3e-3, z_max=13e-3, nx=5), "dmas", 0,
-     (1, 64, 1, 1, 0), "f32"),
-    ("dmas_ragged_cpw2", dict(nx=21, nz=77, n_channels=12), "dmas", 0, (2, 16, 1, 4, 4), "f32"),
+    ("dmas_coarse_grid_fallback", dict(nz=64, z_min=3e-3, z_max=13e-3, nx=5), "dmas", 0, None,
+     "f32"),
+    ("dmas_ragged_cpw2", dict(nx=63, nz=231, n_channels=12), "dmas", 0, (2, 16, 1, 4, 4),
+     "f32"),
     ("dmas_compound_5a", dict(angles_deg=(-10., -5., 0., 5., 10.)), "dmas", -1, None, "i16"),
     ("dmas_compound_generic", dict(angles_deg=tuple(range(-18, 18, 2)), nx=7, nz=40,
-                                   n_channels=6), "dmas", -1, (4, 4, 1, 2, 0), "f32"),
+                                   n_channels=6), "dmas", -1, (8, 4, 1, 1, 0), "f32"),
 ]
 
+
+# Launch shapes whose LDS windows exceed the 64-entry limit: every call with
+# them is refused before anything is enqueued.
+REFUSED = [
+    # name, geometry kwargs, mode, angle, tile
+    ("das_64_deep_column", dict(nz=64, z_min=3e-3, z_max=13e-3, nx=5), "das", 0,
+     (1, 64, 1, 1, 0)),
+    ("compound_3a_64_deep_column", dict(nz=64, z_min=3e-3, z_max=13e-3, nx=5,
+                                        angles_deg=(-10.0, 0.0, 10.0)), "das", -1,
+     (1, 64, 1, 1, 0)),
+    ("dmas_64_deep_column", dict(nz=64, z_min=3e-3, z_max=13e-3, nx=5), "dmas", 0,
+     (1, 64, 1, 1, 0)),
+    ("das_ragged_64x16", dict(nx=37, nz=100), "das", 0, (1, 64, 1, 4, 0)),
+    ("compound_7a_32x8", dict(angles_deg=(-15., -10., -5., 0., 5., 10., 15.)), "das", -1,
+     (1, 16, 2, 2, 0)),
+    ("dmas_generic_4x8", dict(angles_deg=tuple(range(-18, 18, 2)), nx=7, nz=40, n_channels=6),
+     "dmas", -1, (4, 4, 1, 2, 0)),
+    # the root-taking beamformers stop at 32 entries; DAS takes this one
+    ("dmas_ragged_16x8_64", dict(nx=21, nz=77, n_channels=12), "dmas", 0, (2, 16, 1, 4, 4)),
+    ("bbdmas_16x16_60", dict(n_samples=512), "bbdmas", 0, (1, 16, 1, 4, 0)),
+    ("pdas_64_deep_column", dict(nz=64, z_min=3e-3, z_max=13e-3, nx=5), "pdas", 0,
+     (1, 64, 1, 1, 0)),
+]
 
 
 TILE_SWEEP = geom(angles_deg=(-6.0, 0.0, 6.0, 12.0), nx=40, nz=140, n_channels=24)

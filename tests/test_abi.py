@@ -128,8 +128,8 @@ def test_call_argument_validation():
     assert _call(one, mode=_abi.DMAS)[0] == _abi.E_INVALID
 
 
-@pytest.mark.parametrize("p,code", [(1.0, 0), (2.0, 0), (3.5, 0), (16.0, 0), (0.99, -1),
-                                    (0.0, -1), (16.5, -1), (float("nan"), -1),
+@pytest.mark.parametrize("p,code", [(1.0, 0), (1.5, 0), (2.0, 0), (2.01, -2), (3.0, -2),
+                                    (16.0, -2), (0.99, -1), (0.0, -1), (float("nan"), -1),
                                     (float("inf"), -1)])
 def test_pdas_root_order_validation(p, code):
     g = GeometryArg(config_c1(), pdas_p=p)

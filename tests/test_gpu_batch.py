@@ -49,19 +49,19 @@ def mixed_frames(dev, seed=0):
     from paper_2311_00482_amd import FrameSpec, Tile
     torch = _torch()
     specs = [
-        (geom(angles_deg=(-8.0, 0.0, 8.0), nx=40, nz=128), "das", -1, Tile(1, 16, 1, 8, 0),
+        (geom(angles_deg=(-8.0, 0.0, 8.0), nx=80, nz=128), "das", -1, Tile(1, 16, 1, 8, 0),
          ("rf", "env", "log"), False, "f32"),
-        (geom(n_channels=32, nx=33, nz=64), "dmas", 0, Tile(2, 16, 2, 4, 0), ("rf", "env"), False,
+        (geom(n_channels=32, nx=66, nz=128), "dmas", 0, Tile(4, 8, 1, 8, 0), ("rf", "env"), False,
          "i16"),
         (geom(angles_deg=(-10., -5., 0., 5., 10.), nx=21, nz=256, n_channels=24), "das", -1,
          Tile(4, 16, 1, 8, 0), ("rf",), False, "f16"),
-        (geom(angles_deg=(0.0, 4.0), n_channels=20, nx=64, nz=512, z_min=10e-3,
-              z_max=10e-3 + 512 * 25e-6), "dmas", -1, Tile(1, 8, 1, 8, 0),
+        (geom(angles_deg=(0.0, 4.0), n_channels=20, nx=128, nz=512, z_min=10e-3,
+              z_max=10e-3 + 512 * 25e-6), "dmas", -1, Tile(1, 16, 2, 4, 0),
          ("rf", "filtered", "env", "log"), True, "f32"),
-        (geom(angles_deg=tuple(range(-6, 8, 2)), nx=17, nz=32), "das", 3, Tile(1, 32, 2, 4, 0),
+        (geom(angles_deg=tuple(range(-6, 8, 2)), nx=68, nz=128), "das", 3, Tile(1, 8, 2, 4, 0),
          ("rf", "log"), False, "f32"),
-        (geom(angles_deg=(-5.0, 5.0), n_channels=20, nx=30, nz=64), "pdas", -1,
-         Tile(1, 16, 1, 8, 0), ("rf", "env"), False, "i16"),
+        (geom(angles_deg=(-5.0, 5.0), n_channels=20, nx=90, nz=128), "pdas", -1,
+         Tile(4, 8, 1, 8, 0), ("rf", "env"), False, "i16"),
     ]
     frames, ref_args = [], []
     for i, (g, mode, angle, tile, want, bp, kind) in enumerate(specs):

@@ -1,14 +1,18 @@
-"""GPU image metrics (FWHM, Eq. (5) CR, Eq. (6) CNR) against the oracle's metrics
-on the same float32 envelope image.
+"""GPU image metrics (FWHM, Eq. (5) CR, Eq. (6) CNR) against the float64 oracle
+metrics on the same float32 envelope image.
 
-Disc membership and the peak (argmax, first flat index on ties) are float32
-decisions both sides take identically, so pixel counts and peak positions must
-match exactly; means, deviations and widths are float32 sums and
-interpolations on the GPU against float64 in the oracle: relative 1e-5 (CR to
-1e-4 dB). The benchmark phantom's anechoic cysts must also read darker than
-their background.
+The oracle decides disc membership in float64 (distance of the pixel centre
+at most the radius); the GPU decides it in float32. Pixels whose centres lie
+within a relative 1e-5 of a boundary (BAND) may go either way: every other
+pixel must be decided alike, the GPU's pixel count must lie between the two
+extremes, and its statistics must equal the oracle's over some choice of the
+boundary pixels that gives that count. Means, deviations and widths are
+float32 sums and interpolations on the GPU against float64 in the oracle:
+relative 1e-5 (CR to 1e-4 dB). The benchmark phantom's anechoic cysts must read
+at least 10 dB darker than their background.
 """
 
+import itertools
 import math
 
 import numpy as np
@@ -19,11 +23,44 @@ from synth import config_c3, make_frame
 
 pytestmark = pytest.mark.gpu
 
+BAND = 1e-5
+
 
 def _torch():
     import torch
     assert torch.cuda.is_available(), "these tests need the GPU"
     return torch
+
+
+def _split(g, disc):
+    """Pixels surely inside the disc, and those within BAND of its boundary."""
+    d = om.disc_distance(g, *disc)
+    return d <= 1.0 - BAND, np.abs(d - 1.0) < BAND
+
+
+def _masks_with_count(g, disc, n):
+    """Every pixel set the float32 decision may give for this disc with n pixels."""
+    sure, band = _split(g, disc)
+    extra = np.argwhere(band)
+    k = n - int(sure.sum())
+    assert 0 <= k <= len(extra), (n, int(sure.sum()), len(extra))
+    assert len(extra) <= 12, "too many boundary pixels to enumerate"
+    for pick in itertools.combinations(range(len(extra)), k):
+        m = sure.copy()
+        for i in pick:
+            m[tuple(extra[i])] = True
+        yield m
+
+
+def _contrast_matches(g, env, cyst, got):
+    for mi in _masks_with_count(g, cyst[0], got["n_in"]):
+        for mo in _masks_with_count(g, cyst[1], got["n_out"]):
+            ref = om.contrast_from_masks(env, mi, mo)
+            ok = all(got[k] == pytest.approx(ref[k], rel=1e-5)
+                     for k in ("mu_in", "mu_out", "sigma_in", "sigma_out", "cnr"))
+            if ok and abs(got["cr_db"] - ref["cr_db"]) <= 1e-4:
+                return ref
+    return None
 
 
 @pytest.fixture(scope="module")
@@ -38,10 +75,20 @@ def c3_env():
 
 
 def _regions(g, ph):
+    # background disc beside each cyst, on the side farther from the point
+    # targets (left, right, above or below); the inside disc is 0.8 r
     cysts = []
+    pts = np.asarray(ph.points)
     for cx, cz, r in ph.cysts:
-        side = 1.0 if cx < 0 else -1.0
-        cysts.append(((cx, cz, 0.8 * r), (cx + side * 2.2 * r, cz, 0.8 * r)))
+        best = None
+        for ox, oz in ((-1, 0), (1, 0), (0, -1), (0, 1)):
+            bx, bz = cx + ox * 2.2 * r, cz + oz * 2.2 * r
+            if not (g.x_min + r < bx < g.x_max - r and g.z_min + r < bz < g.z_max - r):
+                continue
+            clear = float(np.hypot(pts[:, 0] - bx, pts[:, 1] - bz).min()) - 0.8 * r
+            if best is None or clear > best[0]:
+                best = (clear, bx, bz)
+        cysts.append(((cx, cz, 0.8 * r), (best[1], best[2], 0.8 * r)))
     targets = [(float(x), float(z), 1.0e-3) for x, z in ph.points]
     return cysts, targets
 
@@ -53,14 +100,11 @@ def test_contrast_matches_oracle_and_cysts_are_dark(c3_env):
     got = contrast_metrics(g, env, cysts)
     host = env.cpu().numpy()
     for c, r in zip(cysts, got):
-        ref = om.contrast(g, host, c[0], c[1])
-        assert (r["n_in"], r["n_out"]) == (ref["n_in"], ref["n_out"])
-        for k in ("mu_in", "mu_out", "sigma_in", "sigma_out", "cnr"):
-            assert r[k] == pytest.approx(ref[k], rel=1e-5), k
-        assert abs(r["cr_db"] - ref["cr_db"]) <= 1e-4
+        ref = _contrast_matches(g, host, c, r)
+        assert ref is not None, (c, r, om.contrast(g, host, c[0], c[1]))
         print(f"cyst at ({c[0][0] * 1e3:.1f}, {c[0][1] * 1e3:.1f}) mm: CR {r['cr_db']:.2f} dB, "
               f"CNR {r['cnr']:.2f}")
-        assert r["cr_db"] < 0.0  # the anechoic region reads darker than the speckle
+        assert r["cr_db"] < -10.0  # the anechoic region reads well below the speckle
 
 
 def test_resolution_matches_oracle(c3_env):
@@ -71,9 +115,16 @@ def test_resolution_matches_oracle(c3_env):
     host = env.cpu().numpy()
     n_finite = 0
     for t, r in zip(targets, got):
-        ref = om.resolution(g, host, t)
+        sure, band = _split(g, t)
+        # the GPU's peak is the first maximum over its own pixel set, which holds
+        # every sure pixel and possibly boundary ones
+        assert sure[r["ix"], r["iz"]] or band[r["ix"], r["iz"]]
+        m = sure.copy()
+        m[r["ix"], r["iz"]] = True
+        ref = om.resolution(g, host, t, mask=m)
         assert (r["ix"], r["iz"]) == (ref["ix"], ref["iz"])
         assert r["peak"] == ref["peak"]
+        assert r["peak"] >= host[sure].max()
         for k in ("fwhm_x", "fwhm_z"):
             if math.isnan(ref[k]):
                 assert math.isnan(r[k])
@@ -95,5 +146,7 @@ def test_metrics_on_exact_images():
     g, env, cyst, back = two_level_image()
     got = contrast_metrics(g, torch.from_numpy(env).cuda(), [(cyst, back)])[0]
     ref = om.contrast(g, env, cyst, back)
+    # radii off the pixel lattice: no boundary pixel, so the sets agree exactly
+    assert not _split(g, cyst)[1].any() and not _split(g, back)[1].any()
     assert (got["n_in"], got["n_out"]) == (ref["n_in"], ref["n_out"])
     assert got["cnr"] == pytest.approx(ref["cnr"], rel=1e-6)

@@ -3,8 +3,8 @@
 Bars (max-normalised error e = max|gpu - oracle| / max|oracle| per plane):
 float32 compute on int16 or float32 RF: e <= 1e-5; float16-stored RF:
 e <= 1e-3 and |dL| <= 0.1 dB on the log image where the oracle is at or above
--40 dB. Full-size workloads are checked on sampled pixels and whole sampled
-depth columns in the launch configuration the benchmark times.
+-40 dB. The 11-angle 1024 x 1024 workload is checked whole, in the launch
+configuration the benchmark times.
 """
 
 import json
@@ -77,7 +77,7 @@ def log_err_db(gpu_log, ora_log, above=-40.0):
 def test_outside_aperture_adds_exact_zero(apod):
     # One live channel: every pixel whose normalised aperture distance from it,
     # r = |x - x_e| 2 F# / z, is 1 or more (or z <= 0) must come out exactly 0.
-    g = geom(n_channels=16, nx=64, nz=80, x_min=-6e-3, x_max=6e-3, z_min=-0.5e-3,
+    g = geom(n_channels=16, nx=256, nz=320, x_min=-6e-3, x_max=6e-3, z_min=-0.5e-3,
              z_max=9e-3, angles_deg=(-7.0, 0.0, 7.0), apod=apod)
     rf = rand_rf(g, 21)
     live = 11
@@ -190,61 +190,38 @@ def c3():
     return make_frame(config_c3(), 1003, "c3", quantize=False)
 
 
-def _c3_check(c3, key, rf_t, tol, tol_db):
+@pytest.fixture(scope="module")
+def c3_ref(c3):
+    """The whole 1024 x 1024 compound image from the oracle (its OpenMP build:
+    the same values as the single-threaded one), with envelope and log image."""
+    g = config_c3()
+    return oracle.beamform(g, c3["master"], "das", -1, parallel=True)
+
+
+def _c3_check(c3_ref, key, rf_t, tol, tol_db):
+    """Every pixel of the benchmark's compound frame, in the launch configuration
+    the benchmark times: raw image, envelope and log image."""
     g = config_c3()
     out = run(g, rf_t, "das", -1, ("rf", "env", "log"))
-    rng = np.random.default_rng(7)
-    pts = c3["phantom"].points
-    pix_pts = [int(round((x - g.x0) / g.dx)) * g.nz + int(round((z - g.z0) / g.dz))
-               for x, z in pts]
-    amax = int(np.argmax(np.abs(out["rf"])))
-    pix = np.unique(np.concatenate([rng.choice(g.nx * g.nz, 3000, replace=False), pix_pts,
-                                    [amax]]))
-    ref = oracle.das(g, c3["master"], -1, pix)
-    norm = np.abs(out["rf"]).max()
-    # the image maximum seen by the GPU is the oracle's at that pixel
-    assert abs(oracle.das(g, c3["master"], -1, [amax])[0]) == pytest.approx(norm, rel=tol)
-    e_rf = float(np.abs(out["rf"].ravel()[pix] - ref).max() / norm)
-    # whole depth columns through three point targets for the envelope and log
-    cols = sorted({int(round((x - g.x0) / g.dx)) for x, _ in pts[:3]})
-    col_pix = np.concatenate([np.arange(g.nz) + ix * g.nz for ix in cols])
-    ref_cols = oracle.das(g, c3["master"], -1, col_pix).reshape(len(cols), g.nz)
-    env_ref = oracle.envelope_z(ref_cols)
-    env_max = out["env"].max()
-    e_env = float(np.abs(out["env"][cols] - env_ref).max() / env_max)
-    lg_ref = np.maximum(20 * np.log10(np.maximum(env_ref, 1e-300) / env_max), -70.0)
-    e_db = log_err_db(out["log"][cols], lg_ref)
-    REPORT[key] = {"rf_sampled": e_rf, "env_columns": e_env, "log_db_columns": e_db,
-                   "n_pixels": int(len(pix)), "columns": cols}
+    e_rf = err(out["rf"], c3_ref["rf"])
+    e_env = err(out["env"], c3_ref["env"])
+    e_db = log_err_db(out["log"], c3_ref["log"])
+    REPORT[key] = {"rf": e_rf, "env": e_env, "log_db": e_db, "n_pixels": g.nx * g.nz}
     assert e_rf <= tol and e_env <= tol and e_db <= tol_db
+    # the brightest pixel of the GPU image is the oracle's
+    amax = int(np.argmax(np.abs(out["rf"])))
+    assert abs(c3_ref["rf"].ravel()[amax]) == pytest.approx(np.abs(c3_ref["rf"]).max(), rel=tol)
 
 
-def test_c3_compound_fp32_full_size(c3):
-    _c3_check(c3, "c3_compound_f32", to_dev(c3["f32"]), TOL32, TOL_DB)
+def test_c3_compound_fp32_full_size(c3, c3_ref):
+    _c3_check(c3_ref, "c3_compound_f32", to_dev(c3["f32"]), TOL32, TOL_DB)
 
 
-def test_c3_compound_fp16_full_size(c3):
-    _c3_check(c3, "c3_compound_f16", to_dev(c3["f16"]), TOL16, TOL_DB)
+def test_c3_compound_fp16_full_size(c3, c3_ref):
+    _c3_check(c3_ref, "c3_compound_f16", to_dev(c3["f16"]), TOL16, TOL_DB)
 
 
 # -------------------------------------------------------- small cases, whole images
-def tol_for(g, mode, angle, tile=None):
-    """The float32 bar, widened where the arithmetic says it must be:
-    - the kernel resolves a delay to about half an ulp of the centred window
-      offset, i.e. one bit less per doubling of the window past 64 entries
-      (the default 16-deep tiles stay under it on every benchmark grid);
-    - DMAS takes sqrt|v| per channel, whose slope is unbounded at zero, so an
-      input perturbation dv moves a term by up to sqrt(dv); with fewer than 16
-      channels nothing averages that out, and the bar is 3e-5 (the 1e-5 bar is
-      checked on the 128-channel DMAS configuration)."""
-    from paper_2311_00482_amd import describe_plan
-    win = describe_plan(g, mode, angle, tile)["win"]
-    tol = TOL32 * max(1.0, win / 64.0)
-    if mode == "dmas" and g.n_channels < 16:
-        tol = max(tol, 3e-5)
-    return tol
-
-
 @pytest.mark.parametrize("name,kw,mode,angle,tile,kind", SMALL, ids=[s[0] for s in SMALL])
 def test_small_cases_whole_image(name, kw, mode, angle, tile, kind):
     from paper_2311_00482_amd import Tile
@@ -258,7 +235,7 @@ def test_small_cases_whole_image(name, kw, mode, angle, tile, kind):
     ref = f(g, rf.astype(np.float64), angle)
     e = err(out, ref)
     REPORT[f"small_{name}"] = e
-    assert e <= tol_for(g, mode, angle, t), e
+    assert e <= TOL32, e
     if kind == "f32" and g.nx * g.nz >= 256:
         # the same values stored as float16 (inputs rounded) stay within the fp16 bar
         # (on images large enough that the maximum is not a single cancelling sum)
@@ -287,7 +264,7 @@ def test_tile_sweep_same_image():
         t = Tile(*shape)
         out = run(g, rf_t, "das", -1, ("rf",), t)["rf"]
         e = err(out, ref)
-        assert e <= tol_for(g, "das", -1, t), (shape, e)
+        assert e <= TOL32, (shape, e)
 
 
 @pytest.mark.parametrize("nx,nz", [(128, 32), (256, 32), (512, 64), (1024, 64), (1750, 64)])
@@ -305,12 +282,22 @@ def test_paper_grids(nx, nz):
 
 # --------------------------------------------------------------------- properties
 def test_compound_equals_sum_of_single_angle_calls():
-    g = geom(angles_deg=(-10.0, -3.0, 5.0, 10.0))
-    rf_t = to_dev(rand_rf(g, 9))
-    for mode in ("das", "dmas"):
-        comp = run(g, rf_t, mode, -1)["rf"]
-        parts = sum(run(g, rf_t, mode, a)["rf"] for a in range(g.n_angles))
-        assert err(comp, parts) <= 1e-6
+    # compound = sum over angles (Eq. (1) per angle, unweighted sum). The calls
+    # run the same tile shape; their window centring differs with the angle set,
+    # so the float32 delays round differently: DAS agrees to 1e-6, and DMAS, whose
+    # root amplifies delay rounding near zero crossings, to the 1e-5 parity bar
+    # that each side meets against the oracle
+    from paper_2311_00482_amd import Tile
+    g = geom(angles_deg=(-10.0, -3.0, 5.0, 10.0), nx=74, nz=200)
+    rf = rand_rf(g, 9)
+    rf_t = to_dev(rf)
+    t = Tile(4, 8, 1, 8, 0)
+    for mode, bar in (("das", 1e-6), ("dmas", 1e-5)):
+        comp = run(g, rf_t, mode, -1, tile=t)["rf"]
+        parts = sum(run(g, rf_t, mode, a, tile=t)["rf"] for a in range(g.n_angles))
+        assert err(comp, parts) <= bar
+        f = oracle.das if mode == "das" else oracle.dmas
+        assert err(comp, f(g, rf.astype(np.float64), -1)) <= TOL32
 
 
 def test_int16_and_exact_fp16_storage_are_bitwise_equal(c1):
@@ -343,3 +330,46 @@ def test_linearity_on_gpu():
     yb = run(g, to_dev(rb), "das", -1)["rf"]
     yab = run(g, to_dev(2.0 * ra - 0.5 * rb), "das", -1)["rf"]
     assert err(yab, 2.0 * ya - 0.5 * yb) <= 2e-6
+
+
+def test_named_entry_points_match_the_oracle():
+    # pwbf_beamform_das, pwbf_beamform_dmas, pwbf_beamform_pdas, pwbf_compound,
+    # pwbf_beamform_iqdas and pwbf_beamform_bbdmas themselves (not the
+    # explicit-shape entry), with valid arguments, against the oracle
+    from paper_2311_00482_amd import (beamform_bbdmas, beamform_das, beamform_dmas,
+                                      beamform_iqdas, beamform_pdas, compound, iq_demodulate)
+    torch = _torch()
+    g = geom(angles_deg=(-7.0, 0.0, 7.0), nx=74, nz=256, n_channels=24)
+    rf = rand_rf(g, 31, "i16")
+    rf_t = to_dev(rf)
+    rf64 = rf.astype(np.float64)
+
+    def host(o):
+        torch.cuda.synchronize()
+        return {k: v.cpu().numpy().astype(np.float64) for k, v in o.items()}
+
+    def cerr(a, b):
+        return float(np.abs(a - b).max() / np.abs(b).max())
+
+    got = host(beamform_das(g, rf_t, 1, want=("rf", "env")))
+    ref = oracle.das(g, rf64, 1)
+    assert err(got["rf"], ref) <= TOL32 and err(got["env"], oracle.envelope_z(ref)) <= TOL32
+    assert err(host(beamform_dmas(g, rf_t, 2))["rf"], oracle.dmas(g, rf64, 2)) <= TOL32
+    assert err(host(beamform_pdas(g, rf_t, 0, p=2.0))["rf"], oracle.pdas(g, rf64, 0, 2.0)) <= TOL32
+    for mode, f in (("das", lambda: oracle.das(g, rf64, -1)),
+                    ("dmas", lambda: oracle.dmas(g, rf64, -1)),
+                    ("pdas", lambda: oracle.pdas(g, rf64, -1, 2.0))):
+        out = host(compound(g, rf_t, mode, want=("rf", "env", "log")))
+        ref = f()
+        assert err(out["rf"], ref) <= TOL32, mode
+        assert log_err_db(out["log"], oracle.log_compress(oracle.envelope_z(ref))) <= TOL_DB
+    g2 = g.replace(n_samples=512)
+    rf2 = rand_rf(g2, 32, "f32")
+    iq = iq_demodulate(g2, to_dev(rf2))
+    iq_ref = oracle.iq_demodulate(g2, rf2.astype(np.float64))
+    for fn, form in ((beamform_iqdas, "iqdas"), (beamform_bbdmas, "bbdmas")):
+        o = host(fn(g2, iq, 1, want=("rf", "imag", "env")))
+        ref = oracle.iq_beamform(g2, iq_ref, form, 1)
+        assert cerr(o["rf"] + 1j * o["imag"], ref) <= TOL32, form
+    o = host(compound(g2, iq, "iqdas", want=("rf", "imag")))
+    assert cerr(o["rf"] + 1j * o["imag"], oracle.iq_beamform(g2, iq_ref, "iqdas", -1)) <= TOL32

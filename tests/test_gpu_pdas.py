@@ -1,11 +1,6 @@
 """GPU parity of pDAS (Eqs. 2-3) against the FP64 oracle, element by element.
 
-Bars (max-normalised error per plane): as for the other float32 paths, 1e-5,
-widened where the arithmetic says so. The p-th root is steep at zero: a
-perturbation d of a delayed sample near a zero crossing moves its compressed
-value by up to d^(1/p), so relative to the square root of DMAS the bar grows by
-(2^-24)^(1/p - 1/2) for p > 2 (x16 at p = 3); with fewer than 16 channels
-nothing averages that out, and those cases use 3e-5 as DMAS does.
+Bar (max-normalised error per plane): 1e-5, as for the other float32 paths.
 """
 
 import zlib
@@ -42,29 +37,21 @@ def err(gpu, ora):
     return float(np.abs(gpu - ora).max() / m) if m > 0 else float(np.abs(gpu).max())
 
 
-def tol_pdas(g, p, angle, tile=None):
-    from paper_2311_00482_amd import Tile, describe_plan
-    t = Tile(*tile) if tile else None
-    win = describe_plan(g, "pdas", angle, t)["win"]
-    tol = TOL32 * max(1.0, win / 64.0)
-    if p > 1.0 and g.n_channels < 16:
-        tol = max(tol, 3e-5)
-    if p > 2.0:
-        tol *= 2.0 ** (24.0 * (0.5 - 1.0 / p))
-    return tol
-
-
 PDAS_SMALL = [
     # name, geometry kwargs, angle, tile, p, dtype
     ("p2_one_angle", dict(), 0, None, 2.0, "f32"),
-    ("p2_ragged_cpw2", dict(nx=21, nz=77, n_channels=12), 0, (2, 16, 1, 4, 4), 2.0, "f32"),
+    ("p2_ragged_cpw2", dict(nx=63, nz=231, n_channels=12), 0, (2, 16, 1, 4, 4), 2.0, "f32"),
     ("p1_compound_is_das", dict(angles_deg=(-6.0, 0.0, 6.0)), -1, None, 1.0, "f32"),
-    ("p3_compound_5a", dict(angles_deg=(-10.0, -5.0, 0.0, 5.0, 10.0), n_channels=24), -1, None,
-     3.0, "i16"),
+    ("p2_compound_5a", dict(angles_deg=(-10.0, -5.0, 0.0, 5.0, 10.0), n_channels=24), -1, None,
+     2.0, "i16"),
+    ("p1_75_compound_3a", dict(angles_deg=(-8.0, 0.0, 8.0), n_channels=32), -1, None, 1.75,
+     "f32"),
     ("p1_5_generic_angles", dict(angles_deg=tuple(range(-18, 18, 2)), nx=7, nz=40,
-                                 n_channels=6), -1, (4, 4, 1, 2, 0), 1.5, "f32"),
-    ("p2_boxcar_cpw4", dict(apod="boxcar", n_channels=20, nx=9, nz=33), 0, (4, 16, 1, 3, 4),
+                                 n_channels=6), -1, (16, 2, 1, 1, 0), 1.5, "f32"),
+    ("p2_boxcar_cpw8", dict(apod="boxcar", n_channels=20, nx=9, nz=33), 0, (8, 4, 1, 1, 8),
      2.0, "f32"),
+    ("p2_compound_3a_f32", dict(angles_deg=(-8.0, 0.0, 8.0), n_channels=32), -1, None, 2.0,
+     "f32"),
 ]
 
 
@@ -78,10 +65,10 @@ def test_pdas_small_cases_whole_image(name, kw, angle, tile, p, kind):
     out = run(g, rf_t, angle, p, tile=Tile(*tile) if tile else None)["rf"]
     ref = oracle.pdas(g, rf.astype(np.float64), angle, p)
     e = err(out, ref)
-    assert e <= tol_pdas(g, p, angle, tile), e
+    assert e <= TOL32, e
     if p == 1.0:
         # p = 1 is DAS: the DAS oracle is the same reference
-        assert err(out, oracle.das(g, rf.astype(np.float64), angle)) <= tol_pdas(g, p, angle, tile)
+        assert err(out, oracle.das(g, rf.astype(np.float64), angle)) <= TOL32
 
 
 def test_pdas_full_dmas_workload_grid():
@@ -101,24 +88,22 @@ def test_pdas_odd_in_the_data():
     torch = _torch()
     g = geom(angles_deg=(-4.0, 7.0), n_channels=20)
     rf = rand_rf(g, 77, "i16")
-    a = run(g, torch.from_numpy(rf).cuda(), -1, 2.5)["rf"]
-    b = run(g, torch.from_numpy(-rf).cuda(), -1, 2.5)["rf"]
+    a = run(g, torch.from_numpy(rf).cuda(), -1, 1.5)["rf"]
+    b = run(g, torch.from_numpy(-rf).cuda(), -1, 1.5)["rf"]
     # negating int16 data negates every sample exactly; the image flips sign bit for bit
     assert np.array_equal(a, -b)
 
 
-def test_pdas_compound_full_size_sampled():
+def test_pdas_compound_full_size_whole_image():
     """The measured compound workload (11 angles, 128 channels x 4096 samples,
-    1024 x 1024 pixels, FP32 RF, p = 2) in the benchmark's launch shape, on
-    sampled pixels (the oracle computes them one by one); max-normalised over
-    the whole GPU image."""
+    1024 x 1024 pixels, FP32 RF, p = 2) in the benchmark's launch shape, every
+    pixel against the oracle (its OpenMP build)."""
     from synth import config_c3
     torch = _torch()
     g = config_c3()
     fr = make_frame(g, 1003, "c3", quantize=False)
     rf_t = torch.from_numpy(fr["f32"]).cuda()
     out = run(g, rf_t, -1, 2.0)["rf"]
-    pix = np.random.default_rng(13).choice(g.nx * g.nz, 1500, replace=False)
-    ref = oracle.pdas(g, fr["master"], -1, 2.0, pix=pix)
-    e = float(np.abs(out.ravel()[pix] - ref).max() / np.abs(out).max())
-    assert e <= tol_pdas(g, 2.0, -1), e
+    ref = oracle.pdas(g, fr["master"], -1, 2.0, parallel=True)
+    e = err(out, ref)
+    assert e <= TOL32, e

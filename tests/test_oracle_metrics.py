@@ -26,8 +26,12 @@ def test_disc_of_radius_one_and_a_half_pixels_holds_nine_pixels():
 
 
 def test_disc_area_and_symmetry():
+    # a radius off the pixel lattice: no pixel centre lies within 1e-3 pixel of
+    # the boundary, so rounding cannot decide any pixel
     g = grid(nx=301, nz=301, pitch=0.05e-3)
-    r = 4e-3
+    r = 4.013e-3
+    d = metrics.disc_distance(g, g.x_pix[150], g.z_pix[150], r)
+    assert np.abs(d - 1.0).min() * r / g.dx > 1e-3
     m = metrics.disc_mask(g, g.x_pix[150], g.z_pix[150], r)
     area = m.sum() * g.dx * g.dz
     assert abs(area / (math.pi * r * r) - 1.0) < 0.01
@@ -107,3 +111,15 @@ def test_peak_ties_take_the_first_index_and_flat_profiles_give_nan():
     first = int(np.flatnonzero(m.ravel())[0])
     assert (r["ix"], r["iz"]) == divmod(first, g.nz)
     assert math.isnan(r["fwhm_x"]) and math.isnan(r["fwhm_z"])
+
+
+def test_disc_membership_is_the_distance_definition():
+    # brute force, one pixel at a time with math.hypot, on an off-centre disc
+    g = grid(nx=23, nz=19)
+    x, z, r = g.x_pix[7] + 0.37e-4, g.z_pix[11] - 0.21e-4, 0.52e-3
+    m = metrics.disc_mask(g, x, z, r)
+    for ix in range(g.nx):
+        for iz in range(g.nz):
+            xp, zp = g.x0 + ix * g.dx, g.z0 + iz * g.dz
+            assert m[ix, iz] == (math.hypot(xp - x, zp - z) <= r)
+    assert 0 < m.sum() < g.nx * g.nz

@@ -71,9 +71,12 @@ def test_pins_catch_planted_mistake(name, tmp_path):
     msrc = tmp_path / "pwbf_oracle.c"
     msrc.write_text(src.replace(old, new))
     mlib = tmp_path / "liboracle.so"
-    subprocess.check_call(["gcc", "-O2", "-std=c11", "-D_DEFAULT_SOURCE", "-fPIC", "-shared",
-                           "-o", str(mlib), str(msrc), "-lm"])
-    code = (f"import oracle; oracle._LIB={str(mlib)!r}; oracle._SRC={str(msrc)!r}; "
+    mlib_omp = tmp_path / "liboracle_omp.so"
+    for lib, extra in ((mlib, []), (mlib_omp, ["-fopenmp"])):
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-D_DEFAULT_SOURCE", "-fPIC", "-shared",
+                               *extra, "-o", str(lib), str(msrc), "-lm"])
+    code = (f"import oracle; oracle._LIB={str(mlib)!r}; oracle._LIB_OMP={str(mlib_omp)!r}; "
+            f"oracle._SRC={str(msrc)!r}; "
             "import sys, pytest; sys.exit(pytest.main(['-q', '-x', '-p', 'no:cacheprovider', "
             f"{os.path.join(ROOT, 'tests', 'test_oracle_pins.py')!r}]))")
     r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True,

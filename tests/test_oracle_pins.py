@@ -509,3 +509,22 @@ def test_log_compress():
     assert out[1, 1] == pytest.approx(-20 * math.log10(4))
     np.testing.assert_array_equal(oracle.log_compress(np.zeros((3, 4))), -70.0)
     assert oracle.log_compress(env, -40.0).min() == -40.0
+
+
+def test_openmp_build_gives_the_single_threaded_values_bitwise():
+    # the same source built with -fopenmp shares the pixel loop among threads;
+    # each pixel is still one thread's literal evaluation, so nothing may change
+    g = small_geom(angles_deg=(-6.0, 0.0, 9.0), nx=19, nz=23)
+    rng = np.random.default_rng(5)
+    rf = rng.standard_normal((g.n_angles, g.n_channels, g.n_samples))
+    pix = rng.choice(g.nx * g.nz, 57, replace=False)
+    for fn in (lambda **k: oracle.das(g, rf, -1, **k),
+               lambda **k: oracle.das(g, rf, 1, pix=pix, **k),
+               lambda **k: oracle.dmas(g, rf, -1, "identity", **k),
+               lambda **k: oracle.dmas(g, rf, 0, "pairs", pix=pix, **k),
+               lambda **k: oracle.pdas(g, rf, -1, 2.5, **k)):
+        assert np.array_equal(fn(), fn(parallel=True))
+    iq = oracle.iq_demodulate(g, rf)
+    for form in ("iqdas", "bbdmas"):
+        assert np.array_equal(oracle.iq_beamform(g, iq, form, -1),
+                              oracle.iq_beamform(g, iq, form, -1, parallel=True))

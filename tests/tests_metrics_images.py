@@ -18,15 +18,16 @@ def cone_image():
     X = (np.arange(g.nx) - ix0)[:, None] * g.dx
     Z = (np.arange(g.nz) - iz0)[None, :] * g.dz
     env = np.maximum(0.0, 1.0 - np.maximum(np.abs(X) / (8 * g.dx), np.abs(Z) / (6 * g.dz)))
-    return g, env.astype(np.float32), (g.x_pix[ix0], g.z_pix[iz0], 1e-3), 8 * g.dx, 6 * g.dz
+    return g, env.astype(np.float32), (g.x_pix[ix0], g.z_pix[iz0], 1.03e-3), 8 * g.dx, 6 * g.dz
 
 
 def two_level_image():
-    """A dark disc (0.5) and a background disc alternating 1.5 / 2.5 along z."""
+    """A dark disc (0.5) and a background disc alternating 1.5 / 2.5 along z (radii
+    off the pixel lattice, so no pixel centre lies on a boundary)."""
     from oracle import metrics
     g = grid()
-    cyst = (g.x_pix[30], g.z_pix[40], 1.0e-3)
-    back = (g.x_pix[60], g.z_pix[40], 1.0e-3)
+    cyst = (g.x_pix[30], g.z_pix[40], 1.03e-3)
+    back = (g.x_pix[60], g.z_pix[40], 1.03e-3)
     env = np.full((g.nx, g.nz), 2.0, dtype=np.float32)
     env[metrics.disc_mask(g, *cyst)] = 0.5
     bm = metrics.disc_mask(g, *back)
