@@ -330,6 +330,24 @@ PWBF_API int pwbf_compound(const pwbf_geometry *g, const void *rf, int32_t rf_dt
                   const pwbf_outputs *out, void *workspace, size_t workspace_bytes,
                   void *stream);
 
+/* pwbf_compound without a workspace argument, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid allocation. The same kernels and results as pwbf_compound; the
+ * scratch they need (the frame maximum for the log image, and the envelope
+ * plane when logimg is requested without env) lives in a device array of the
+ * library, one per GPU, held until the process ends: 8 KiB plus
+ * PWBF_NOALLOC_ENV_PIXELS * 4 bytes (16 MiB). Its device address is looked up
+ * once per device on the first call that needs it (with that device current).
+ * A log image without env on a grid of more than PWBF_NOALLOC_ENV_PIXELS pixels
+ * returns PWBF_E_UNSUPPORTED. The call allocates and frees nothing. Every call
+ * on one GPU shares that GPU's array, which keeps the last call's contents (the
+ * kernels clear what must start at zero): calls that overlap on one GPU (other
+ * streams, other threads) race and must be ordered by the caller. Other
+ * arguments and errors as for pwbf_compound. */
+#define PWBF_NOALLOC_ENV_PIXELS (1 << 22)
+PWBF_API int pwbf_compound_noalloc(const pwbf_geometry *g, const void *rf, int32_t rf_dtype,
+                                   int32_t mode, const pwbf_outputs *out, void *stream);
+
 /* pwbf_compound (angle == -1) or the single-angle call (angle >= 0) with an explicit
  * launch shape; tile == NULL behaves as the plain calls. Used by the tuner and
  * by tests that sweep launch shapes. */

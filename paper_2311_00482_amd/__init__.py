@@ -21,6 +21,7 @@ from .api import (  # noqa: F401
     beamform_iqdas,
     beamform_pdas,
     compound,
+    compound_noalloc,
     contrast_metrics,
     describe_plan,
     fk_migrate,

@@ -19,6 +19,7 @@ I16, F16, F32, C32 = 0, 1, 2, 3
 DAS, DMAS, PDAS, IQDAS, BBDMAS = 0, 1, 2, 3, 4
 APOD_HANN, APOD_BOXCAR, APOD_NONE = 0, 1, 2
 MAX_ANGLES, MAX_CHANNELS, MAX_NZ_POST = 32, 256, 4096
+NOALLOC_ENV_PIXELS = 1 << 22
 
 ERROR_NAMES = {E_INVALID: "PWBF_E_INVALID", E_UNSUPPORTED: "PWBF_E_UNSUPPORTED",
                E_NOMEM: "PWBF_E_NOMEM", E_DEVICE: "PWBF_E_DEVICE", E_BUSY: "PWBF_E_BUSY"}
@@ -186,6 +187,8 @@ def lib():
         f.argtypes = [G, vp, i32, O, vp, sz, vp]
     L.pwbf_compound.restype = ctypes.c_int
     L.pwbf_compound.argtypes = [G, vp, i32, i32, O, vp, sz, vp]
+    L.pwbf_compound_noalloc.restype = ctypes.c_int
+    L.pwbf_compound_noalloc.argtypes = [G, vp, i32, i32, O, vp]
     L.pwbf_beamform_ex.restype = ctypes.c_int
     L.pwbf_beamform_ex.argtypes = [G, vp, i32, i32, i32, T, O, vp, sz, vp]
     L.pwbf_validate_call.restype = ctypes.c_int

@@ -126,7 +126,7 @@ def alloc_outputs(g, want: Iterable[str], device) -> Dict[str, "object"]:
     return {k: torch.empty((ga.nx, ga.nz), dtype=torch.float32, device=device) for k in want}
 
 
-def _prepare(g, rf, want, out, workspace, bandpass, log_floor_db, p):
+def _prepare(g, rf, want, out, workspace, bandpass, log_floor_db, p, workspace_needed=True):
     """Marshal one frame's call: geometry, output planes (allocated when not
     given), workspace; returns (geometry, outputs struct, planes, ws ptr, ws bytes)."""
     import torch
@@ -149,7 +149,7 @@ def _prepare(g, rf, want, out, workspace, bandpass, log_floor_db, p):
             out[k] = torch.empty((ga.nx, ga.nz), dtype=torch.float32, device=rf.device)
     o = _abi.Outputs(_ptr(out.get("rf")), _ptr(out.get("filtered")), _ptr(out.get("env")),
                      _ptr(out.get("log")), _ptr(out.get("imag")))
-    need = _abi.lib().pwbf_workspace_bytes(ga.ref, ctypes.byref(o))
+    need = _abi.lib().pwbf_workspace_bytes(ga.ref, ctypes.byref(o)) if workspace_needed else 0
     if need and workspace is None:
         workspace = torch.empty(need, dtype=torch.uint8, device=rf.device)
     ws_ptr = _ptr(workspace)
@@ -347,6 +347,20 @@ def compound(g, rf, mode: str = "das", **kw) -> Dict:
     """pwbf_compound: coherent sum over all angles of the per-angle images
     (DAS, DMAS, pDAS; complex IQ-DAS, BB-DMAS)."""
     return _named("pwbf_compound", g, rf, -1, mode=mode, **kw)
+
+
+def compound_noalloc(g, rf, mode: str = "das", want: Iterable[str] = ("rf",),
+                     out: Optional[Dict] = None, stream=None, bandpass: bool = False,
+                     log_floor_db: float = -70.0, p: Optional[float] = None) -> Dict:
+    """pwbf_compound_noalloc: pwbf_compound without a workspace (the library's
+    own per-GPU scratch array); planes not given in ``out`` are allocated here,
+    by torch, before the call."""
+    ga, o, out, _, _ = _prepare(g, rf, want, out, None, bandpass, log_floor_db, p,
+                                workspace_needed=False)
+    rc = _abi.lib().pwbf_compound_noalloc(ga.ref, _ptr(rf), _rf_code(rf), _MODES[mode],
+                                          ctypes.byref(o), _stream_ptr(stream, rf.device))
+    _abi.check(rc)
+    return out
 
 
 # ------------------------------------------------------------------- tuning

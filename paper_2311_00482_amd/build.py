@@ -23,7 +23,8 @@ ARCH = os.environ.get("PWBF_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["plan.cpp", "tune.cpp", "api.cpp", "batch.cpp", "serve.cpp", "metrics.cpp", "fk.cpp",
            "beamform.hip",
-           "postz.hip", "batch.hip", "serve.hip", "iq.hip", "metrics.hip", "fk.hip"]
+           "postz.hip", "batch.hip", "serve.hip", "iq.hip", "metrics.hip", "fk.hip",
+           "noalloc.hip"]
 
 COMMON = [
     "-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}",

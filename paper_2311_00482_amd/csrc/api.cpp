@@ -32,10 +32,13 @@ int api_set_error(int code, const std::string &msg) { return set_error(code, msg
 void api_clear_error() { g_last_error.clear(); }
 }  // namespace pwbf
 
-namespace {
+namespace pwbf {
 
-int run(const pwbf_geometry *g, const void *rf, int32_t dtype, int32_t mode, int32_t angle,
-        const pwbf_tile *tile, const pwbf_outputs *out, void *ws, size_t ws_bytes, void *stream) {
+// One single-frame call: validate, plan, enqueue (every public single-frame
+// entry point, and the allocation-free one, come through here).
+int run_frame(const pwbf_geometry *g, const void *rf, int32_t dtype, int32_t mode, int32_t angle,
+              const pwbf_tile *tile, const pwbf_outputs *out, void *ws, size_t ws_bytes,
+              void *stream) {
   g_last_error.clear();
   pwbf::FramePlan P;
   std::string err;
@@ -67,6 +70,14 @@ int run(const pwbf_geometry *g, const void *rf, int32_t dtype, int32_t mode, int
   return PWBF_OK;
 }
 
+}  // namespace pwbf
+
+namespace {
+using pwbf::run_frame;
+int run(const pwbf_geometry *g, const void *rf, int32_t dtype, int32_t mode, int32_t angle,
+        const pwbf_tile *tile, const pwbf_outputs *out, void *ws, size_t ws_bytes, void *stream) {
+  return run_frame(g, rf, dtype, mode, angle, tile, out, ws, ws_bytes, stream);
+}
 }  // namespace
 
 extern "C" {

@@ -466,3 +466,17 @@ def test_fk_workspace_and_argument_errors():
     assert b"required" in L.pwbf_last_error()
     # the Stolt-sized workspace is too small for Lu
     assert M(g.ref, FAKE, 0, LU, -1, oo, FAKE, need, None) == _abi.E_INVALID
+
+
+def test_noalloc_entry_refuses_envelope_beyond_its_scratch():
+    # a log image without an envelope output on a grid of more than 2^22 pixels
+    # needs more scratch than the allocation-free call holds: refused on the
+    # host, before any HIP call, with the reason
+    L = _abi.lib()
+    g = GeometryArg(config_c3().replace(nx=4096, nz=2048))
+    o = _abi.Outputs(FAKE, None, None, FAKE, None)
+    rc = L.pwbf_compound_noalloc(g.ref, FAKE, _abi.F32, _abi.DAS, ctypes.byref(o), None)
+    assert rc == _abi.E_UNSUPPORTED
+    assert "scratch" in L.pwbf_last_error().decode()
+    assert L.pwbf_compound_noalloc(None, FAKE, _abi.F32, _abi.DAS, ctypes.byref(o),
+                                   None) == _abi.E_INVALID
