@@ -49,7 +49,7 @@
 extern "C" {
 #endif
 
-#define PWBF_ABI_VERSION 3u
+#define PWBF_ABI_VERSION 4u
 
 #ifndef PWBF_API
 #define PWBF_API __attribute__((visibility("default")))
@@ -395,9 +395,12 @@ PWBF_API int pwbf_describe_plan(const pwbf_geometry *g, int32_t mode, int32_t an
 
 /* ------------------------------------------------------------------ batches
  * Frames of uneven size, channel count, angle count, storage type and mode go
- * into one persistent launch: blocks pull (frame, pixel tile) items, largest
- * first, from a device work list; the launch sequence (reset, beamform,
- * depth post-processing, log) is captured once in a HIP graph and replayed.
+ * into one graph launch: the frames are split into up to four branches of about
+ * equal estimated cost, each running one beamform kernel per class of its
+ * frames (one block per (frame, pixel tile) item, largest tiles first), then
+ * the depth post-processing and the log image of its frames; the branches run
+ * side by side. The launch sequence is captured once in a HIP graph and
+ * replayed.
  * The batch keeps the frames' device pointers until it is updated or
  * destroyed; creating it allocates the graph, the descriptor tables and a
  * small per-frame workspace (PWBF_E_NOMEM on failure). Launch and update must
@@ -423,12 +426,14 @@ typedef struct pwbf_batch_info {
   int32_t n_frames;
   int32_t n_items;          /* (frame, tile) work items */
   int32_t n_columns;        /* depth columns post-processed */
-  int32_t blocks;           /* persistent blocks launched, summed over the kernels */
+  int32_t blocks;           /* blocks launched (one per item), summed over the kernels */
   int32_t blocks_per_cu;    /* the smallest occupancy among the kernels */
-  int32_t lds_bytes;        /* LDS per block of the persistent kernels */
+  int32_t lds_bytes;        /* LDS per block of the beamform kernels */
   int32_t graph_nodes;
-  int32_t kernels;          /* persistent beamform kernels: one per class of frames
-                               (beamformer, lane grouping, angle count 1/5/11/other) */
+  int32_t kernels;          /* beamform kernel launches: one per class of frames
+                               (beamformer, lane grouping, angle count 1/5/11/other)
+                               in each branch */
+  int32_t branches;         /* parallel branches of the graph (frames balanced by cost) */
 } pwbf_batch_info;
 
 /* Build a batch of n >= 1 frames; *out receives the handle. flags: 0 or

@@ -12,7 +12,7 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpwbf.so")
 
-ABI_VERSION = 3
+ABI_VERSION = 4
 OK, E_INVALID, E_UNSUPPORTED, E_NOMEM, E_DEVICE, E_BUSY = 0, -1, -2, -3, -4, -5
 FK_STOLT, FK_LU = 0, 1
 I16, F16, F32, C32 = 0, 1, 2, 3
@@ -70,7 +70,7 @@ class Frame(ctypes.Structure):
 class BatchInfo(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in ("n_frames", "n_items", "n_columns", "blocks",
                                                "blocks_per_cu", "lds_bytes", "graph_nodes",
-                                               "kernels")]
+                                               "kernels", "branches")]
 
 
 BATCH_TUNE = 1

@@ -410,7 +410,7 @@ class FrameSpec:
 
 
 class Batch:
-    """pwbf_batch: uneven frames in one persistent, graph-captured launch."""
+    """pwbf_batch: uneven frames in one graph-captured launch (up to four branches)."""
 
     def __init__(self, frames, tune: bool = False, stream=None):
         self._keep = []

@@ -28,8 +28,15 @@ struct pwbf_batch {
   pwbf::FramePlan *d_plans = nullptr;
   pwbf::PostPlan *d_post = nullptr;
   int2 *d_items = nullptr, *d_post_cols = nullptr, *d_log_cols = nullptr;
-  int *d_counter = nullptr;  // one work counter per class
-  std::vector<pwbf::BatchClass> classes;
+  std::vector<pwbf::BatchClass> classes;  // every branch's class launches, branch by branch
+  struct Branch {
+    int class_first = 0, class_n = 0;
+    int post_first = 0, post_n = 0, log_first = 0, log_n = 0;
+    double cost = 0;
+  };
+  std::vector<Branch> branches;
+  std::vector<hipStream_t> fork_streams;  // used only while capturing the graph
+  std::vector<hipEvent_t> fork_events;
   unsigned char *d_ws = nullptr;  // per-frame workspaces (envelope maximum, envelope plane)
   std::vector<size_t> ws_off;
   void *h_stage = nullptr;  // pinned staging of the descriptor tables for updates
@@ -43,6 +50,10 @@ struct pwbf_batch {
 };
 
 namespace {
+
+// Graph branches of a batch: at most the device's hardware queues per process
+// (four by default), so the branches run side by side.
+constexpr int kMaxBranches = 4;
 
 int dev_error(hipError_t e, const char *what) {
   return api_set_error(PWBF_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
@@ -106,6 +117,8 @@ void free_batch(pwbf_batch *b) {
   if (b->exec) (void)hipGraphExecDestroy(b->exec);
   if (b->graph) (void)hipGraphDestroy(b->graph);
   if (b->cap) (void)hipStreamDestroy(b->cap);
+  for (hipStream_t st : b->fork_streams) (void)hipStreamDestroy(st);
+  for (hipEvent_t ev : b->fork_events) (void)hipEventDestroy(ev);
   if (b->staged) (void)hipEventDestroy(b->staged);
   if (b->h_stage) (void)hipHostFree(b->h_stage);
   (void)hipFree(b->d_plans);
@@ -113,7 +126,6 @@ void free_batch(pwbf_batch *b) {
   (void)hipFree(b->d_items);
   (void)hipFree(b->d_post_cols);
   (void)hipFree(b->d_log_cols);
-  (void)hipFree(b->d_counter);
   (void)hipFree(b->d_ws);
   delete b;
 }
@@ -261,12 +273,14 @@ int pwbf_batch_create(const pwbf_frame *frames, int32_t n, int32_t flags, void *
     free_batch(b);
     return api_set_error(PWBF_E_NOMEM, "batch workspace allocation failed");
   }
-  std::vector<int2> items, post_cols, log_cols;
+  // Plan every frame; estimate its cost (the sum of its tiles' costs).
   struct Work {
     double cost;
     int frame, tile;
   };
-  std::vector<Work> order;
+  std::vector<std::vector<Work>> frame_work(n);
+  std::vector<double> frame_cost(n, 0.0);
+  std::vector<int> cls(n);
   for (int i = 0; i < n; ++i) {
     const pwbf_frame &f = frames[i];
     unsigned char *ws = b->d_ws ? b->d_ws + b->ws_off[i] : nullptr;
@@ -278,30 +292,68 @@ int pwbf_batch_create(const pwbf_frame *frames, int32_t n, int32_t flags, void *
     const pwbf::FramePlan &P = b->plans[i];
     b->sig[i] = frame_signature(f, P);
     b->lds = std::max(b->lds, (int)pwbf::plan_lds_bytes(P));
-    for (int t = 0; t < P.n_tiles; ++t) order.push_back({pwbf::tile_cost(f.geom, P, t), i, t});
-    if (pwbf::post_needed(&f.out)) {
-      b->max_nz = std::max(b->max_nz, f.geom->nz);
+    cls[i] = pwbf::tile_class(P.mode, P.cpw == 1, P.n_angles);
+    for (int t = 0; t < P.n_tiles; ++t) {
+      const double c = pwbf::tile_cost(f.geom, P, t);
+      frame_work[i].push_back({c, i, t});
+      frame_cost[i] += c;
+    }
+    if (pwbf::post_needed(&f.out)) b->max_nz = std::max(b->max_nz, f.geom->nz);
+  }
+  // Frames go to up to kMaxBranches graph branches, longest first, each to the
+  // branch with the least work so far; branches run side by side, so each
+  // branch's post-processing and tail overlap the others' beamforming.
+  const int n_br = std::min(n, kMaxBranches);
+  b->branches.assign(n_br, pwbf_batch::Branch());
+  std::vector<int> by_cost(n), branch_of(n);
+  for (int i = 0; i < n; ++i) by_cost[i] = i;
+  std::stable_sort(by_cost.begin(), by_cost.end(),
+                   [&frame_cost](int a, int c) { return frame_cost[a] > frame_cost[c]; });
+  for (int i : by_cost) {
+    int best = 0;
+    for (int k = 1; k < n_br; ++k)
+      if (b->branches[k].cost < b->branches[best].cost) best = k;
+    branch_of[i] = best;
+    b->branches[best].cost += frame_cost[i];
+  }
+  // Per branch: its items grouped by class, the costliest class first and the
+  // longest tiles first within a class; then its frames' columns.
+  std::vector<int2> items, post_cols, log_cols;
+  for (int k = 0; k < n_br; ++k) {
+    pwbf_batch::Branch &br = b->branches[k];
+    std::vector<Work> order;
+    std::vector<double> class_cost(pwbf::kTileClasses, 0.0);
+    for (int i = 0; i < n; ++i)
+      if (branch_of[i] == k) {
+        order.insert(order.end(), frame_work[i].begin(), frame_work[i].end());
+        class_cost[cls[i]] += frame_cost[i];
+      }
+    std::stable_sort(order.begin(), order.end(), [&](const Work &a, const Work &c) {
+      const int ca = cls[a.frame], cc = cls[c.frame];
+      if (ca != cc) return class_cost[ca] != class_cost[cc] ? class_cost[ca] > class_cost[cc]
+                                                            : ca < cc;
+      return a.cost > c.cost;
+    });
+    br.class_first = (int)b->classes.size();
+    for (size_t q = 0; q < order.size(); ++q) {
+      const int c = cls[order[q].frame];
+      if ((int)b->classes.size() == br.class_first || b->classes.back().cls != c)
+        b->classes.push_back({c, (int)items.size(), 0, 0});
+      ++b->classes.back().n;
+      items.push_back(make_int2(order[q].frame, order[q].tile));
+    }
+    br.class_n = (int)b->classes.size() - br.class_first;
+    br.post_first = (int)post_cols.size();
+    br.log_first = (int)log_cols.size();
+    for (int i = 0; i < n; ++i) {
+      const pwbf_frame &f = frames[i];
+      if (branch_of[i] != k || !pwbf::post_needed(&f.out)) continue;
       for (int ix = 0; ix < f.geom->nx; ++ix) post_cols.push_back(make_int2(i, ix));
       if (f.out.logimg)
         for (int ix = 0; ix < f.geom->nx; ++ix) log_cols.push_back(make_int2(i, ix));
     }
-  }
-  // grouped by class (one persistent kernel each), longest tiles first within a
-  // class, so the cheap ones fill the tail
-  std::vector<int> cls(n);
-  for (int i = 0; i < n; ++i) {
-    const pwbf::FramePlan &P = b->plans[i];
-    cls[i] = pwbf::tile_class(P.mode, P.cpw == 1, P.n_angles);
-  }
-  std::stable_sort(order.begin(), order.end(), [&cls](const Work &a, const Work &b) {
-    return cls[a.frame] != cls[b.frame] ? cls[a.frame] < cls[b.frame] : a.cost > b.cost;
-  });
-  for (size_t k = 0; k < order.size(); ++k) {
-    const int c = cls[order[k].frame];
-    if (b->classes.empty() || b->classes.back().cls != c)
-      b->classes.push_back({c, (int)k, 0, 0});
-    ++b->classes.back().n;
-    items.push_back(make_int2(order[k].frame, order[k].tile));
+    br.post_n = (int)post_cols.size() - br.post_first;
+    br.log_n = (int)log_cols.size() - br.log_first;
   }
   b->n_items = (int)items.size();
   b->n_post_cols = (int)post_cols.size();
@@ -315,7 +367,7 @@ int pwbf_batch_create(const pwbf_frame *frames, int32_t n, int32_t flags, void *
   for (pwbf::BatchClass &k : b->classes) {
     int bpc = 0;
     if (e == hipSuccess) e = pwbf::batch_occupancy(k.cls, (size_t)b->lds, &bpc);
-    k.blocks = std::max(1, std::min(k.n, std::max(1, bpc) * n_cu));
+    k.blocks = k.n;  // one block per item
     b->blocks += k.blocks;
     b->blocks_per_cu = b->blocks_per_cu ? std::min(b->blocks_per_cu, bpc) : bpc;
   }
@@ -330,8 +382,6 @@ int pwbf_batch_create(const pwbf_frame *frames, int32_t n, int32_t flags, void *
   if (e == hipSuccess) e = upload(&b->d_post_cols, post_cols);
   if (e == hipSuccess) e = upload(&b->d_log_cols, log_cols);
   if (e == hipSuccess)
-    e = hipMalloc((void **)&b->d_counter, sizeof(int) * std::max<size_t>(1, b->classes.size()));
-  if (e == hipSuccess)
     e = hipHostMalloc(&b->h_stage, n * (sizeof(pwbf::FramePlan) + sizeof(pwbf::PostPlan)),
                       hipHostMallocDefault);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&b->staged, hipEventDisableTiming);
@@ -339,14 +389,35 @@ int pwbf_batch_create(const pwbf_frame *frames, int32_t n, int32_t flags, void *
     free_batch(b);
     return api_set_error(PWBF_E_NOMEM, std::string("batch tables: ") + hipGetErrorString(e));
   }
-  // capture the launch sequence once
+  // capture the launch sequence once: reset, fork into the branches, join
   e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
+  for (int k = 0; k < n_br + 1 && e == hipSuccess; ++k) {
+    hipEvent_t ev = nullptr;
+    e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e == hipSuccess) b->fork_events.push_back(ev);
+  }
+  for (int k = 0; k < n_br && e == hipSuccess; ++k) {
+    hipStream_t st = nullptr;
+    e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+    if (e == hipSuccess) b->fork_streams.push_back(st);
+  }
   if (e == hipSuccess) e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
   if (e == hipSuccess) {
-    hipError_t le = pwbf::launch_batch(b->d_plans, b->d_post, b->d_items, b->classes.data(),
-                                       (int)b->classes.size(), b->d_post_cols,
-                                       b->n_post_cols, b->d_log_cols, b->n_log_cols, n,
-                                       b->d_counter, b->lds, b->max_nz, b->cap);
+    hipError_t le = pwbf::launch_batch_reset(b->d_post, n, b->cap);
+    if (le == hipSuccess) le = hipEventRecord(b->fork_events[n_br], b->cap);
+    for (int k = 0; k < n_br && le == hipSuccess; ++k) {
+      const pwbf_batch::Branch &br = b->branches[k];
+      hipStream_t st = b->fork_streams[k];
+      le = hipStreamWaitEvent(st, b->fork_events[n_br], 0);
+      if (le == hipSuccess)
+        le = pwbf::launch_batch_branch(b->d_plans, b->d_post, b->d_items,
+                                       b->classes.data() + br.class_first, br.class_n,
+                                       b->d_post_cols + br.post_first, br.post_n,
+                                       b->d_log_cols + br.log_first, br.log_n, b->lds, b->max_nz,
+                                       st);
+      if (le == hipSuccess) le = hipEventRecord(b->fork_events[k], st);
+      if (le == hipSuccess) le = hipStreamWaitEvent(b->cap, b->fork_events[k], 0);
+    }
     e = hipStreamEndCapture(b->cap, &b->graph);
     if (le != hipSuccess) e = le;
   }
@@ -420,6 +491,7 @@ int pwbf_batch_describe(const pwbf_batch *b, pwbf_batch_info *info) {
   info->lds_bytes = b->lds;
   info->graph_nodes = b->graph_nodes;
   info->kernels = (int32_t)b->classes.size();
+  info->branches = (int32_t)b->branches.size();
   return PWBF_OK;
 }
 

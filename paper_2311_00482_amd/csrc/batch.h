@@ -9,8 +9,8 @@
 
 namespace pwbf {
 
-// the work of one class: items [first, first + n) of the batch's list, run by a
-// persistent kernel of `blocks` blocks
+// the work of one class within a branch: items [first, first + n) of the
+// batch's list, one block each
 struct BatchClass {
   int cls, first, n, blocks;
 };
@@ -18,9 +18,13 @@ struct BatchClass {
 int batch_waves();
 int batch_max_angles();
 hipError_t batch_occupancy(int cls, size_t lds_bytes, int *blocks_per_cu);
-hipError_t launch_batch(const FramePlan *plans, const PostPlan *post, const int2 *items,
-                        const BatchClass *classes, int n_classes, const int2 *post_cols,
-                        int n_post_cols, const int2 *log_cols, int n_log_cols, int n_frames,
-                        int *counters, size_t lds, int max_nz, hipStream_t stream);
+// clears every frame's envelope-maximum slots (a kernel, not a memset node)
+hipError_t launch_batch_reset(const PostPlan *post, int n_frames, hipStream_t stream);
+// one branch of the batch graph: its class kernels in order, then the depth
+// post-processing and the log image of its frames' columns
+hipError_t launch_batch_branch(const FramePlan *plans, const PostPlan *post, const int2 *items,
+                               const BatchClass *classes, int n_classes, const int2 *post_cols,
+                               int n_post_cols, const int2 *log_cols, int n_log_cols, size_t lds,
+                               int max_nz, hipStream_t stream);
 
 }  // namespace pwbf

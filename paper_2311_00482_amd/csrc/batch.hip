@@ -1,22 +1,22 @@
 // Kernels of a batch launch: frames of uneven size, channel count, angle count,
-// storage type and mode in one graph-captured sequence of persistent launches.
+// storage type and mode in one graph-captured launch.
 //
-//   k_batch_reset      clears the classes' work counters and every frame's
-//                      envelope maximum (a kernel, not a memset node, so graph
-//                      replays stay exact)
-//   k_batch_beamform   persistent, one kernel per class of frames (beamformer,
-//                      lane grouping, angle count): every block repeatedly claims
-//                      the next (frame, tile) item of its class's work list,
-//                      sorted by estimated tile cost (active aperture x pixels x
-//                      angles), largest first, and runs the tile body for that
-//                      frame's plan; all waves leave when the list is exhausted
-//   k_batch_postz      one block per (frame, depth column) of frames with
-//                      post-processing
-//   k_batch_logc       one block per (frame, depth column) of frames with a log image
+// The graph forks into up to four branches of frames balanced by estimated
+// cost; each branch runs, in order,
+//   k_batch_beamform   one launch per class of its frames (beamformer, lane
+//                      grouping, angle count), one block per (frame, tile) item
+//                      of its list, the items sorted by estimated tile cost
+//                      (active aperture x pixels x angles), largest first, so the
+//                      hardware dispatcher starts the longest tiles first
+//   k_batch_postz      one block per (frame, depth column) of its frames
+//   k_batch_logc       one block per (frame, depth column) with a log image
+// and the branches run side by side on the device, so one branch's
+// post-processing and tail overlap the others' beamforming. k_batch_reset
+// clears every frame's envelope maximum before the fork.
 //
 // Frame descriptors (FramePlan, PostPlan) live in device tables; a block reads
-// the claimed item through a wave-uniform index, so every descriptor field is a
-// scalar load.
+// its item through a wave-uniform index, so every descriptor field is a scalar
+// load.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -32,48 +32,38 @@ namespace {
 constexpr int kBatchWaves = 8;
 constexpr int kBatchMaxAngles = 16;
 
-__global__ void k_batch_reset(int *counters, int n_classes, const PostPlan *__restrict__ post,
-                              int n_frames) {
+__global__ void k_batch_reset(const PostPlan *__restrict__ post, int n_frames) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n_classes) counters[i] = 0;
   if (i < n_frames && post[i].ws_max)
     for (int s = 0; s < kMaxSlots; ++s) dev::frame_max_clear(post[i].ws_max, s);
 }
 
-// One persistent kernel per class of frames (tile_class.h): one kernel for every
-// class (the DMAS and pDAS bodies need up to ~130 VGPRs) would run the
-// compound DAS body at two 8-wave blocks per CU instead of three. Angle counts
-// other than 1, 5 and 11 run the predicated body of up to kBatchMaxAngles.
-// Every class runs the general tile body (with the aperture test in the
-// weight): a second, select-free body inside the persistent loop raised the
-// compound DAS kernel to 84 VGPRs, and even held to 80 it ran 10% slower.
+// One kernel per class of frames (tile_class.h): one kernel for every class
+// (the DMAS and pDAS bodies need up to ~130 VGPRs) would run the compound DAS
+// body at two 8-wave blocks per CU instead of three. Angle counts other than 1,
+// 5 and 11 run the predicated body of up to kBatchMaxAngles. Every class runs
+// the general tile body (with the aperture test in the weight): a second,
+// select-free body raised the compound DAS kernel to 84 VGPRs.
 template <int MODE, bool ONEGRP, int AB>
 __global__ void __launch_bounds__(kWave * kBatchWaves)
-    k_batch_beamform(const FramePlan *__restrict__ plans, const int2 *__restrict__ items,
-                     int n_items, int *__restrict__ counter) {
+    k_batch_beamform(const FramePlan *__restrict__ plans, const int2 *__restrict__ items) {
   extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ int s_item;
-  for (;;) {
-    __syncthreads();  // the previous item's LDS and s_item are no longer read
-    if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
-    __syncthreads();
-    const int it = __builtin_amdgcn_readfirstlane(s_item);
-    if (it >= n_items) break;  // uniform over the block: every wave leaves here
-    const int2 w = items[it];
-    const FramePlan &P = plans[w.x];
-    const int tz = w.y / P.tiles_x, tx = w.y - tz * P.tiles_x;
-    if constexpr (AB == 3)
-      dev::process_tile_body<kBatchMaxAngles, true, MODE, ONEGRP, true>(P, tz, tx, smem);
-    else
-      dev::process_tile_body<AB == 0 ? 1 : (AB == 1 ? 5 : 11), false, MODE, ONEGRP, true>(P, tz, tx, smem);
-  }
+  const int2 w = items[blockIdx.x];
+  const FramePlan &P = plans[__builtin_amdgcn_readfirstlane(w.x)];
+  const int tile = __builtin_amdgcn_readfirstlane(w.y);
+  const int tz = tile / P.tiles_x, tx = tile - tz * P.tiles_x;
+  if constexpr (AB == 3)
+    dev::process_tile_body<kBatchMaxAngles, true, MODE, ONEGRP, true>(P, tz, tx, smem);
+  else
+    dev::process_tile_body<AB == 0 ? 1 : (AB == 1 ? 5 : 11), false, MODE, ONEGRP, true>(P, tz, tx,
+                                                                                        smem);
 }
 
 template <int C>
 hipError_t launch_class_kernel(dim3 grid, size_t lds, hipStream_t s, const FramePlan *plans,
-                               const int2 *items, int n_items, int *counter) {
+                               const int2 *items) {
   hipLaunchKernelGGL((k_batch_beamform<C / 8, (C / 4) % 2 == 1, C % 4>), grid,
-                     dim3(kWave * kBatchWaves), lds, s, plans, items, n_items, counter);
+                     dim3(kWave * kBatchWaves), lds, s, plans, items);
   return hipGetLastError();
 }
 
@@ -119,22 +109,24 @@ hipError_t batch_occupancy(int cls, size_t lds_bytes, int *blocks_per_cu) {
   }
 }
 
-// Enqueue the batch sequence on `stream` (captured into a graph by the caller).
-hipError_t launch_batch(const FramePlan *plans, const PostPlan *post, const int2 *items,
-                        const BatchClass *classes, int n_classes, const int2 *post_cols,
-                        int n_post_cols, const int2 *log_cols, int n_log_cols, int n_frames,
-                        int *counters, size_t lds, int max_nz, hipStream_t stream) {
-  hipLaunchKernelGGL(k_batch_reset, dim3((std::max(n_frames, n_classes) + 255) / 256), dim3(256),
-                     0, stream, counters, n_classes, post, n_frames);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+hipError_t launch_batch_reset(const PostPlan *post, int n_frames, hipStream_t stream) {
+  hipLaunchKernelGGL(k_batch_reset, dim3((std::max(n_frames, 1) + 255) / 256), dim3(256), 0,
+                     stream, post, n_frames);
+  return hipGetLastError();
+}
+
+// Enqueue one branch on `stream` (captured into the batch graph by the caller).
+hipError_t launch_batch_branch(const FramePlan *plans, const PostPlan *post, const int2 *items,
+                               const BatchClass *classes, int n_classes, const int2 *post_cols,
+                               int n_post_cols, const int2 *log_cols, int n_log_cols, size_t lds,
+                               int max_nz, hipStream_t stream) {
+  hipError_t e = hipSuccess;
   for (int c = 0; c < n_classes; ++c) {
     const BatchClass &k = classes[c];
     switch (k.cls) {
-#define PWBF_LAUNCH(C)                                                                  \
-  case C:                                                                               \
-    e = launch_class_kernel<C>(dim3(k.blocks), lds, stream, plans, items + k.first, k.n, \
-                               counters + c);                                           \
+#define PWBF_LAUNCH(C)                                                                    \
+  case C:                                                                                 \
+    e = launch_class_kernel<C>(dim3(k.n), lds, stream, plans, items + k.first);           \
     break;
       PWBF_BATCH_CLASSES(PWBF_LAUNCH)
 #undef PWBF_LAUNCH
