@@ -561,7 +561,8 @@ def main():
     ap.add_argument("--no-modes", action="store_true",
                     help="skip the DMAS and pDAS measurements")
     ap.add_argument("--profile-mode", default="das",
-                    choices=("das", "pdas", "dmas", "iqdas", "bbdmas", "fk", "fklu", "batch"),
+                    choices=("das", "pdas", "dmas", "iqdas", "bbdmas", "fk", "fklu", "batch",
+                             "uneven"),
                     help="with --profile-only: the beamformer of the timed loop (dmas and "
                          "pdas run on the 128-channel 512 x 512 DMAS workload, pdas also "
                          "takes the compound workload with --profile-compound)")
@@ -617,6 +618,11 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    if args.profile_only and args.profile_mode == "uneven":
+        r = uneven_batch(dev, torch, args.steps * 32, args.warmup * 16)
+        print(json.dumps({"profile_only": True, "mode": "uneven",
+                          "ms_per_launch": r["batched"]["ms_per_launch"]}))
+        return
     if args.profile_only and args.profile_mode == "batch":
         from paper_2311_00482_amd import Batch, FrameSpec
         i16 = torch.from_numpy(fr["i16"]) if "i16" in fr else rf32.cpu().round().to(torch.int16)

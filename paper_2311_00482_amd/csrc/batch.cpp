@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -51,9 +52,16 @@ struct pwbf_batch {
 
 namespace {
 
-// Graph branches of a batch: at most the device's hardware queues per process
-// (four by default), so the branches run side by side.
+// Graph branches of a batch: they run side by side only while each has a
+// hardware queue of its own, and the process's queues (four by default) also
+// serve the launching stream, so the default is three. PWBF_BATCH_BRANCHES
+// (1..4) overrides it when the batch is created.
 constexpr int kMaxBranches = 4;
+int branch_limit() {
+  const char *v = getenv("PWBF_BATCH_BRANCHES");
+  const int k = v ? atoi(v) : 3;
+  return k >= 1 && k <= kMaxBranches ? k : 3;
+}
 
 int dev_error(hipError_t e, const char *what) {
   return api_set_error(PWBF_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
@@ -303,7 +311,7 @@ int pwbf_batch_create(const pwbf_frame *frames, int32_t n, int32_t flags, void *
   // Frames go to up to kMaxBranches graph branches, longest first, each to the
   // branch with the least work so far; branches run side by side, so each
   // branch's post-processing and tail overlap the others' beamforming.
-  const int n_br = std::min(n, kMaxBranches);
+  const int n_br = std::min(n, branch_limit());
   b->branches.assign(n_br, pwbf_batch::Branch());
   std::vector<int> by_cost(n), branch_of(n);
   for (int i = 0; i < n; ++i) by_cost[i] = i;

@@ -41,9 +41,9 @@ __global__ void k_batch_reset(const PostPlan *__restrict__ post, int n_frames) {
 // One kernel per class of frames (tile_class.h): one kernel for every class
 // (the DMAS and pDAS bodies need up to ~130 VGPRs) would run the compound DAS
 // body at two 8-wave blocks per CU instead of three. Angle counts other than 1,
-// 5 and 11 run the predicated body of up to kBatchMaxAngles. Every class runs
-// the general tile body (with the aperture test in the weight): a second,
-// select-free body raised the compound DAS kernel to 84 VGPRs.
+// 5 and 11 run the predicated body of up to kBatchMaxAngles. The tile body is
+// chosen per frame as in the single-frame kernels (the select-free Hann body
+// for DAS with one lane group).
 template <int MODE, bool ONEGRP, int AB>
 __global__ void __launch_bounds__(kWave * kBatchWaves)
     k_batch_beamform(const FramePlan *__restrict__ plans, const int2 *__restrict__ items) {
@@ -53,10 +53,9 @@ __global__ void __launch_bounds__(kWave * kBatchWaves)
   const int tile = __builtin_amdgcn_readfirstlane(w.y);
   const int tz = tile / P.tiles_x, tx = tile - tz * P.tiles_x;
   if constexpr (AB == 3)
-    dev::process_tile_body<kBatchMaxAngles, true, MODE, ONEGRP, true>(P, tz, tx, smem);
+    dev::process_tile<kBatchMaxAngles, true, MODE, ONEGRP>(P, tz, tx, smem);
   else
-    dev::process_tile_body<AB == 0 ? 1 : (AB == 1 ? 5 : 11), false, MODE, ONEGRP, true>(P, tz, tx,
-                                                                                        smem);
+    dev::process_tile<AB == 0 ? 1 : (AB == 1 ? 5 : 11), false, MODE, ONEGRP>(P, tz, tx, smem);
 }
 
 template <int C>

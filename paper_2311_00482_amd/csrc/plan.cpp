@@ -477,10 +477,24 @@ int tile_active_channels(const pwbf_geometry *g, const FramePlan &P, int tile) {
 }
 
 double tile_cost(const pwbf_geometry *g, const FramePlan &P, int tile) {
-  // a DMAS gather costs about twice a DAS one, a pDAS gather (log and exp) 2.5 times
-  const double mode_factor = P.mode == kDmas ? 2.0 : (P.mode == kPdas ? 2.5 : 1.0);
-  return (double)tile_active_channels(g, P, tile) * P.tile_z * P.tile_x * (P.n_angles + 2) *
-         mode_factor;
+  // Estimated vector lane-operations of the tile, from the kernel's instruction
+  // mix: per (pixel, active channel) the receive delay, weight and its
+  // per-angle gathers (DAS 5 per angle, DMAS 10, pDAS 9 at p = 2 and 12
+  // otherwise; the transcendental operations issue at a quarter of the rate),
+  // the window staging (about 5.5 per entry) and the per-tile constants.
+  const double px = (double)P.tile_z * P.tile_x;
+  const double ch = tile_active_channels(g, P, tile);
+  const double A = P.n_angles;
+  double per_gather = 5, per_pair = 20;
+  if (P.mode == kDmas) {
+    per_gather = 10;
+    per_pair = 22;
+  } else if (P.mode == kPdas) {
+    per_gather = P.pdas_p == 2.0f ? 9 : 12;
+  }
+  const double staging = ch * A * P.win * 5.5;
+  const double constants = A * 64 + ch * (wave_ref_mode(P.mode) ? P.wz * P.wx * 64.0 : 64.0);
+  return px * ch * (A * per_gather + per_pair) + staging + constants;
 }
 
 int build_post_plan(const pwbf_geometry *g, const pwbf_outputs *o, void *ws, PostPlan *Q) {
