@@ -272,12 +272,15 @@ __device__ __forceinline__ ff ff_mul(ff a, ff b) {
   return two_sum(p, e);
 }
 __device__ __forceinline__ ff ff_neg(ff a) { return {-a.hi, -a.lo}; }
+// sqrt(a) from the hardware square root s of a.hi (within an ulp) and one
+// correction step: the residual a - s^2 is exact through the FMA, and its
+// quotient by 2 s needs only float32 relative accuracy (it is ~2^-24 of s)
 __device__ __forceinline__ ff ff_sqrt(ff a) {
 #pragma clang fp contract(off)
   if (!(a.hi > 0.f)) return {0.f, 0.f};
-  const float s = sqrtf(a.hi);
+  const float s = __builtin_amdgcn_sqrtf(a.hi);
   const float r = fmaf(-s, s, a.hi) + a.lo;
-  return two_sum(s, r / (2.f * s));
+  return two_sum(s, r * (0.5f * __builtin_amdgcn_rcpf(s)));
 }
 __device__ __forceinline__ float ff_f(ff a) { return a.hi + a.lo; }
 
@@ -318,10 +321,9 @@ __device__ __forceinline__ void process_tile_body(const FramePlan &P, int tz, in
   float2 *s_ph = (float2 *)(smem + plan_lds_ph_offset(P));  // [chunk] IQ: exp(2 pi i r (LR + off_r))
   int2 *s_row = (int2 *)(smem + plan_lds_row_offset(P));  // [chunk * A] window rows
   float2 *s_pairs = (float2 *)(smem + plan_lds_win_offset(P));
-  // DMAS, pDAS: per (wavefront, channel) {Dw, rw^2, rw, rx(w) - LR - off_r - kR} and kR
+  // DMAS, pDAS: per (wavefront, channel) {Dw, kR (int bits), rw, rx(w) - LR - off_r - kR}
   constexpr bool WREF = wave_ref_mode(MODE);
   float4 *s_chw = (float4 *)(smem + plan_lds_wref_offset(P));
-  int *s_kr = (int *)(smem + plan_lds_wref_offset(P) + (size_t)P.wz * P.wx * P.chunk * 16);
 
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
@@ -522,8 +524,8 @@ __device__ __forceinline__ void process_tile_body(const FramePlan &P, int tz, in
         const ff rrel = ff_add(rw, {-(lr + (float)P.off_r), 0.f});
         const float k = rintf(rrel.hi);
         const int slot = wave * chunk + c;
-        s_chw[slot] = make_float4(ff_f(dw), ff_f(rw2), ff_f(rw) + 1e-20f, (rrel.hi - k) + rrel.lo);
-        s_kr[slot] = (int)k;
+        s_chw[slot] = make_float4(ff_f(dw), __int_as_float((int)k), ff_f(rw) + 1e-20f,
+                                  (rrel.hi - k) + rrel.lo);
       }
     }
     __syncthreads();
@@ -544,10 +546,13 @@ __device__ __forceinline__ void process_tile_body(const FramePlan &P, int tz, in
       const float4 ch = WREF ? s_chw[slot] : s_ch[c];
       // DMAS, pDAS: the wavefront's integer shift of this channel's window
       int kr = 0;
-      if constexpr (WREF) kr = ONEGRP ? __builtin_amdgcn_readfirstlane(s_kr[slot]) : s_kr[slot];
+      if constexpr (WREF)
+        kr = ONEGRP ? __builtin_amdgcn_readfirstlane(__float_as_int(ch.y)) : __float_as_int(ch.y);
       // receive delay relative to the window origin, as a difference from rx(q)
       const float num = fmaf(dx2, ch.x, cp);
-      const float den = __builtin_amdgcn_sqrtf(ch.y + num) + ch.z;
+      // rx(p) + rx(ref): rx(ref)^2 + num in one rounding (the sum only needs
+      // float32 relative accuracy); DMAS and pDAS keep kR where DAS keeps rx(q)^2
+      const float den = __builtin_amdgcn_sqrtf(WREF ? fmaf(ch.z, ch.z, num) : ch.y + num) + ch.z;
       const float rxl = fmaf(num, __builtin_amdgcn_rcpf(den), ch.w);
       const float w = apod_weight<SEL>(fabsf(ch.x + dx) * hA, hk, hb);
       // delays are centred: entry n of the window is read as n + off_t + off_r
@@ -726,15 +731,15 @@ __device__ __forceinline__ void process_tile_body(const FramePlan &P, int tz, in
   if (grp == 0 && ix < P.nx && iz < P.nz) P.out[(size_t)ix * P.nz + iz] = y;
 }
 
-// The tile body for plan P. The exact-angle DAS kernels of one lane group
+// The tile body for plan P. The exact-angle RF kernels of one lane group
 // carry a second body without the aperture test in the weight (Hann, none),
 // two fewer instructions per (pixel, channel); every other kernel and boxcar
-// apodization take the general one. (The persistent batch and serve kernels
-// call the general body directly: there the second body costs registers.)
+// apodization take the general one. (The serve kernels call the general body
+// directly: there the second body costs registers.)
 template <int AM, bool PRED, int MODE, bool ONEGRP>
 __device__ __forceinline__ void process_tile(const FramePlan &P, int tz, int tx,
                                              unsigned char *smem) {
-  if constexpr (MODE == kDas && ONEGRP && !PRED) {
+  if constexpr ((MODE == kDas || MODE == kDmas || MODE == kPdas) && ONEGRP && !PRED) {
     if (P.apod != kBoxcar) {
       process_tile_body<AM, PRED, MODE, ONEGRP, false>(P, tz, tx, smem);
       return;

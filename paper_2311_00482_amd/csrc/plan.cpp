@@ -233,7 +233,7 @@ static int fit_tile(const pwbf_geometry *g, pwbf_tile t, FramePlan *P, std::stri
                 TZ, TX, P->win, wmax, wmax / 2);
   const size_t per_channel = (size_t)P->n_angles * (P->win * P->entry_bytes + 8) +
                              (is_iq_mode(P->mode) ? 24 : 16) +
-                             (wave_ref_mode(P->mode) ? (size_t)t.wz * t.wx * 20 : 0);
+                             (wave_ref_mode(P->mode) ? (size_t)t.wz * t.wx * 16 : 0);
   const size_t fixed = kLdsAngleBytes + 16;
   int chunk = t.chunk;
   if (chunk == 0) {

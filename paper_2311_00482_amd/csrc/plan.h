@@ -100,7 +100,7 @@ PWBF_HD constexpr bool wave_ref_mode(int mode) { return mode == kDmas || mode ==
 // LDS of a block: per angle {tx(q) - LT, LT, transmit phasor} (16 bytes), per
 // channel of the chunk {Dq, rq^2, rq, rx(q) - LR} (16) and the receive phasor
 // (8, IQ modes only), per (wavefront, channel) of the chunk the wavefront's
-// reference terms (16) and integer window offset (4) (DMAS and pDAS only), per
+// reference terms and integer window offset (16, DMAS and pDAS only), per
 // window row (channel, angle) of the chunk its record offset and first sample
 // (8), then the windows.
 constexpr size_t kLdsAngleBytes = kMaxAngles * 16;
@@ -111,7 +111,7 @@ PWBF_HD inline size_t plan_lds_wref_offset(const FramePlan &p) {
   return plan_lds_ph_offset(p) + (is_iq_mode(p.mode) ? (size_t)p.chunk * 8 : 0);
 }
 PWBF_HD inline size_t plan_lds_wref_bytes(const FramePlan &p) {
-  return wave_ref_mode(p.mode) ? (size_t)p.wz * p.wx * p.chunk * 20 : 0;
+  return wave_ref_mode(p.mode) ? (size_t)p.wz * p.wx * p.chunk * 16 : 0;
 }
 PWBF_HD inline size_t plan_lds_row_offset(const FramePlan &p) {
   return plan_lds_wref_offset(p) + plan_lds_wref_bytes(p);
