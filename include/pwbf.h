@@ -49,7 +49,7 @@
 extern "C" {
 #endif
 
-#define PWBF_ABI_VERSION 4u
+#define PWBF_ABI_VERSION 5u
 
 #ifndef PWBF_API
 #define PWBF_API __attribute__((visibility("default")))
@@ -480,33 +480,45 @@ PWBF_API int pwbf_tune_clear(void);
  * FP16 and its output planes. submit() queues a frame of int16 RF from pinned
  * host memory; a scheduler thread admits queued requests into free slots while
  * the HBM budget ledger allows (the bytes of the slots in use), uploads them on
- * a copy stream and converts them to FP16 on the device, and, whenever fewer
- * than two batches are on the GPU, launches every uploaded request as one
- * batch (continuous batching: requests that arrive while others run join the
- * next batch). A frame runs the same kernels with the same plan whether it is
- * alone or in a mix, so its planes do not depend on the mix. */
+ * one of two copy streams (the one with fewer bytes outstanding) and converts
+ * them to FP16 on the device, and, whenever fewer than two batches are on the
+ * GPU, launches every uploaded request as one batch (continuous batching:
+ * requests that arrive while others run join the next batch). A frame runs the
+ * same kernels with the same plan whether it is alone or in a mix, so its
+ * planes do not depend on the mix. The decisions (ledger, admission, deadlines,
+ * batching) are a device-free core that the CPU tests drive with a fake clock. */
 typedef struct pwbf_probe {
   const pwbf_geometry *geom; /* host; copied at creation */
-  int32_t mode;              /* PWBF_DAS / PWBF_DMAS */
+  int32_t mode;              /* PWBF_DAS / PWBF_DMAS / PWBF_PDAS */
   int32_t angle;             /* -1: compound; else that angle */
   int32_t want_env;          /* 1: envelope plane */
   int32_t want_log;          /* 1: log image (implies the envelope) */
   int32_t slots;             /* ring slots (0 = 4) */
-  int32_t reserved;          /* 0 */
+  int32_t want_quality;      /* 1: a quality check of every served frame (implies the
+                                envelope): its envelope maximum and the CR and CNR
+                                (Eqs. (5)-(6), Section II-D) of quality_region, with
+                                quality_ok = frame maximum > 0 and CR <= quality_max_cr_db */
+  pwbf_cyst quality_region;  /* inside and background discs (m), as for pwbf_contrast_metrics */
+  double quality_max_cr_db;  /* e.g. -10 for an anechoic cyst */
 } pwbf_probe;
 
 typedef struct pwbf_server pwbf_server;
 
 typedef struct pwbf_result {
   uint64_t id;            /* as returned by submit */
-  int32_t probe, slot;
+  int32_t probe, slot;    /* slot -1 when the request expired */
   double t_arrival;       /* seconds on the server clock (pwbf_server_now) */
   double t_admit;         /* slot assigned, upload enqueued */
   double t_launch;        /* batch enqueued */
-  double t_done;          /* output planes complete on the device */
-  const float *rf;        /* device planes of the slot, valid until released */
+  double t_done;          /* output planes complete on the device (or the expiry time) */
+  const float *rf;        /* device planes of the slot, valid until released (NULL when
+                             the request expired) */
   const float *env;
   const float *logimg;
+  int32_t status;         /* PWBF_OK, or PWBF_E_TIMEOUT: not admitted by its deadline */
+  int32_t quality_ok;     /* want_quality: the frame passed the probe's check (else 0) */
+  float frame_max;        /* want_quality: maximum of the envelope */
+  float cr_db, cnr;       /* want_quality: Eqs. (5)-(6) over the probe's quality_region */
 } pwbf_result;
 
 typedef struct pwbf_server_stats {
@@ -514,9 +526,11 @@ typedef struct pwbf_server_stats {
   int64_t queued, in_flight;   /* right now */
   double mean_batch;           /* requests per batch */
   size_t budget_bytes, budget_in_use, budget_peak;
+  int64_t expired;             /* dropped at their deadline before admission */
 } pwbf_server_stats;
 
-#define PWBF_E_BUSY (-5) /* serving: the probe's queue is full */
+#define PWBF_E_BUSY (-5)    /* serving: the probe's queue is full */
+#define PWBF_E_TIMEOUT (-6) /* serving: the request was not admitted by its deadline */
 
 /* Create a server for n probes. A slot of a probe costs its FP16 RF
  * (2 n_angles n_channels n_samples bytes), its float32 planes (rf, plus env
@@ -537,6 +551,13 @@ PWBF_API int pwbf_server_create(const pwbf_probe *probes, int32_t n, size_t hbm_
  * PWBF_E_BUSY when the probe's queue is full (the request is dropped). */
 PWBF_API int pwbf_server_submit(pwbf_server *s, int32_t probe, const int16_t *host_rf,
                                 double t_arrival, uint64_t *id);
+
+/* pwbf_server_submit with a deadline: deadline >= 0 is the server time (seconds,
+ * pwbf_server_now) by which the request must be admitted; one still queued then
+ * is dropped, and poll returns it with status PWBF_E_TIMEOUT and no planes (its
+ * release frees nothing). deadline < 0: none. */
+PWBF_API int pwbf_server_submit_ex(pwbf_server *s, int32_t probe, const int16_t *host_rf,
+                                   double t_arrival, double deadline, uint64_t *id);
 
 /* Collect up to max completed requests into results (*n receives the count),
  * waiting up to wait_ms for at least one. Their slots stay reserved until

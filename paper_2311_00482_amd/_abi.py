@@ -12,8 +12,8 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpwbf.so")
 
-ABI_VERSION = 4
-OK, E_INVALID, E_UNSUPPORTED, E_NOMEM, E_DEVICE, E_BUSY = 0, -1, -2, -3, -4, -5
+ABI_VERSION = 5
+OK, E_INVALID, E_UNSUPPORTED, E_NOMEM, E_DEVICE, E_BUSY, E_TIMEOUT = 0, -1, -2, -3, -4, -5, -6
 FK_STOLT, FK_LU = 0, 1
 I16, F16, F32, C32 = 0, 1, 2, 3
 DAS, DMAS, PDAS, IQDAS, BBDMAS = 0, 1, 2, 3, 4
@@ -22,7 +22,8 @@ MAX_ANGLES, MAX_CHANNELS, MAX_NZ_POST = 32, 256, 4096
 NOALLOC_ENV_PIXELS = 1 << 22
 
 ERROR_NAMES = {E_INVALID: "PWBF_E_INVALID", E_UNSUPPORTED: "PWBF_E_UNSUPPORTED",
-               E_NOMEM: "PWBF_E_NOMEM", E_DEVICE: "PWBF_E_DEVICE", E_BUSY: "PWBF_E_BUSY"}
+               E_NOMEM: "PWBF_E_NOMEM", E_DEVICE: "PWBF_E_DEVICE", E_BUSY: "PWBF_E_BUSY",
+               E_TIMEOUT: "PWBF_E_TIMEOUT"}
 
 
 class Geometry(ctypes.Structure):
@@ -102,14 +103,18 @@ class Probe(ctypes.Structure):
     _fields_ = [("geom", ctypes.POINTER(Geometry)), ("mode", ctypes.c_int32),
                 ("angle", ctypes.c_int32), ("want_env", ctypes.c_int32),
                 ("want_log", ctypes.c_int32), ("slots", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("want_quality", ctypes.c_int32), ("quality_region", Cyst),
+                ("quality_max_cr_db", ctypes.c_double)]
 
 
 class Result(ctypes.Structure):
     _fields_ = [("id", ctypes.c_uint64), ("probe", ctypes.c_int32), ("slot", ctypes.c_int32),
                 ("t_arrival", ctypes.c_double), ("t_admit", ctypes.c_double),
                 ("t_launch", ctypes.c_double), ("t_done", ctypes.c_double),
-                ("rf", ctypes.c_void_p), ("env", ctypes.c_void_p), ("logimg", ctypes.c_void_p)]
+                ("rf", ctypes.c_void_p), ("env", ctypes.c_void_p), ("logimg", ctypes.c_void_p),
+                ("status", ctypes.c_int32), ("quality_ok", ctypes.c_int32),
+                ("frame_max", ctypes.c_float), ("cr_db", ctypes.c_float),
+                ("cnr", ctypes.c_float)]
 
 
 class ServerStats(ctypes.Structure):
@@ -117,7 +122,8 @@ class ServerStats(ctypes.Structure):
                 ("completed", ctypes.c_int64), ("batches", ctypes.c_int64),
                 ("queued", ctypes.c_int64), ("in_flight", ctypes.c_int64),
                 ("mean_batch", ctypes.c_double), ("budget_bytes", ctypes.c_size_t),
-                ("budget_in_use", ctypes.c_size_t), ("budget_peak", ctypes.c_size_t)]
+                ("budget_in_use", ctypes.c_size_t), ("budget_peak", ctypes.c_size_t),
+                ("expired", ctypes.c_int64)]
 
 
 class PlanInfo(ctypes.Structure):
@@ -218,6 +224,9 @@ def lib():
     L.pwbf_server_submit.restype = ctypes.c_int
     L.pwbf_server_submit.argtypes = [vp, i32, vp, ctypes.c_double,
                                      ctypes.POINTER(ctypes.c_uint64)]
+    L.pwbf_server_submit_ex.restype = ctypes.c_int
+    L.pwbf_server_submit_ex.argtypes = [vp, i32, vp, ctypes.c_double, ctypes.c_double,
+                                        ctypes.POINTER(ctypes.c_uint64)]
     L.pwbf_server_poll.restype = ctypes.c_int
     L.pwbf_server_poll.argtypes = [vp, ctypes.POINTER(Result), i32, ctypes.POINTER(i32), i32]
     L.pwbf_server_release.restype = ctypes.c_int

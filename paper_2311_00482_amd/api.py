@@ -10,7 +10,7 @@ from __future__ import annotations
 
 import ctypes
 from dataclasses import dataclass
-from typing import Dict, Iterable, Optional
+from typing import Dict, Iterable, Optional, Tuple
 
 import numpy as np
 
@@ -481,6 +481,11 @@ class ProbeSpec:
     slots: int = 4
     bandpass: bool = False
     p: Optional[float] = None  # pDAS root order (mode "pdas")
+    # a quality check of every served frame: ((x, z, r) inside, (x, z, r)
+    # background) in m; passes when the frame maximum is > 0 and the CR of that
+    # region (Eq. (5)) is at most quality_max_cr_db
+    quality_region: Optional[Tuple] = None
+    quality_max_cr_db: float = -10.0
 
 
 @dataclass
@@ -493,9 +498,14 @@ class Completed:
     t_admit: float
     t_launch: float
     t_done: float
-    rf: int
+    rf: Optional[int]
     env: Optional[int]
     logimg: Optional[int]
+    status: int = 0          # 0, or E_TIMEOUT: dropped at its deadline (no planes)
+    quality_ok: bool = False  # the probe's quality check (when it has one)
+    frame_max: float = 0.0
+    cr_db: float = 0.0
+    cnr: float = 0.0
 
 
 class Server:
@@ -513,9 +523,13 @@ class Server:
         arr = (_abi.Probe * len(probes))()
         for i, (p, ga) in enumerate(zip(probes, self._geoms)):
             want = set(p.want)
+            q = _abi.Cyst()
+            if p.quality_region is not None:
+                q = _abi.Cyst(_abi.Disc(*p.quality_region[0]), _abi.Disc(*p.quality_region[1]))
             arr[i] = _abi.Probe(ctypes.pointer(ga.s), _MODES[p.mode], p.angle,
                                 1 if "env" in want else 0, 1 if "log" in want else 0,
-                                p.slots, 0)
+                                p.slots, 0 if p.quality_region is None else 1, q,
+                                float(p.quality_max_cr_db))
         handle = ctypes.c_void_p()
         _abi.check(_abi.lib().pwbf_server_create(arr, len(probes), hbm_budget_bytes, max_queue,
                                                  ctypes.byref(handle)))
@@ -523,15 +537,18 @@ class Server:
         self.probes = list(probes)
         self._pending = {}
 
-    def submit(self, probe: int, host_rf, t_arrival: float = -1.0) -> int:
+    def submit(self, probe: int, host_rf, t_arrival: float = -1.0,
+               deadline: float = -1.0) -> int:
+        """Queue a frame; ``deadline`` >= 0 is the server time (``now()``) by
+        which it must be admitted, else it comes back expired (status E_TIMEOUT)."""
         import torch
         ga = self._geoms[probe]
         if (host_rf.dtype != torch.int16 or host_rf.is_cuda or not host_rf.is_contiguous()
                 or tuple(host_rf.shape) != ga.shape_rf):
             raise ValueError(f"host_rf must be a contiguous host int16 tensor {ga.shape_rf}")
         rid = ctypes.c_uint64()
-        _abi.check(_abi.lib().pwbf_server_submit(self.handle, probe, host_rf.data_ptr(),
-                                                 t_arrival, ctypes.byref(rid)))
+        _abi.check(_abi.lib().pwbf_server_submit_ex(self.handle, probe, host_rf.data_ptr(),
+                                                    t_arrival, deadline, ctypes.byref(rid)))
         self._pending[rid.value] = host_rf
         return rid.value
 
@@ -541,7 +558,8 @@ class Server:
         _abi.check(_abi.lib().pwbf_server_poll(self.handle, res, max_results, ctypes.byref(n),
                                                wait_ms))
         return [Completed(r.id, r.probe, r.slot, r.t_arrival, r.t_admit, r.t_launch, r.t_done,
-                          r.rf, r.env, r.logimg) for r in res[:n.value]]
+                          r.rf, r.env, r.logimg, r.status, bool(r.quality_ok), r.frame_max,
+                          r.cr_db, r.cnr) for r in res[:n.value]]
 
     def planes(self, result: Completed) -> Dict:
         """Copies of a completed request's device planes as [nx, nz] float32 tensors."""

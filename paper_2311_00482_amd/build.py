@@ -21,7 +21,7 @@ LIB = os.path.join(HERE, "libpwbf.so")
 ROOT = os.path.dirname(HERE)
 ARCH = os.environ.get("PWBF_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["plan.cpp", "tune.cpp", "api.cpp", "batch.cpp", "serve.cpp", "metrics.cpp", "fk.cpp",
+SOURCES = ["plan.cpp", "tune.cpp", "api.cpp", "batch.cpp", "serve.cpp", "serve_core.cpp", "metrics.cpp", "fk.cpp",
            "beamform.hip",
            "postz.hip", "batch.hip", "serve.hip", "iq.hip", "metrics.hip", "fk.hip",
            "noalloc.hip"]

@@ -8,14 +8,9 @@
 // took 49 us per launch against 4 us over 64 lines.
 #include <hip/hip_runtime.h>
 
-#include <cstddef>
-#include <cstdint>
+#include "frame_max_layout.h"
 
 namespace pwbf {
-
-constexpr int kMaxSlots = 64;
-constexpr int kMaxSlotStride = 32;  // uint32 words between slots: one 128-byte line each
-constexpr size_t kMaxSlotBytes = (size_t)kMaxSlots * kMaxSlotStride * sizeof(uint32_t);
 
 namespace dev {
 

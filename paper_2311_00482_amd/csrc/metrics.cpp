@@ -21,9 +21,12 @@ bool finite_disc(const pwbf_disc &d) {
   return std::isfinite(d.x) && std::isfinite(d.z) && std::isfinite(d.r) && d.r > 0;
 }
 
-// The disc in pixel units (the float32 constants of the membership test) and a
-// bounding box one pixel wider than the exact one, clipped to the grid.
-pwbf::DiscPix to_pixels(const pwbf_geometry *g, const pwbf_disc &d) {
+}  // namespace
+
+namespace pwbf {
+
+// The bounding box is one pixel wider than the exact one, then clipped.
+DiscPix disc_to_pixels(const pwbf_geometry *g, const pwbf_disc &d) {
   pwbf::DiscPix p;
   const double cx = (d.x - g->x0) / g->dx, cz = (d.z - g->z0) / g->dz;
   p.cx = (float)cx;
@@ -44,6 +47,10 @@ pwbf::DiscPix to_pixels(const pwbf_geometry *g, const pwbf_disc &d) {
   }
   return p;
 }
+
+}  // namespace pwbf
+
+namespace {
 
 int check_common(const pwbf_geometry *g, const float *env, int32_t n, const void *regions,
                  const void *out, size_t out_align) {
@@ -73,8 +80,8 @@ int pwbf_contrast_metrics(const pwbf_geometry *g, const float *env, const pwbf_c
   for (int k = 0; k < n; ++k) {
     if (!finite_disc(cysts[k].in) || !finite_disc(cysts[k].out))
       return api_set_error(PWBF_E_INVALID, "cyst " + std::to_string(k) + ": bad disc");
-    cs.in[k] = to_pixels(g, cysts[k].in);
-    cs.out[k] = to_pixels(g, cysts[k].out);
+    cs.in[k] = pwbf::disc_to_pixels(g, cysts[k].in);
+    cs.out[k] = pwbf::disc_to_pixels(g, cysts[k].out);
   }
   hipError_t e = pwbf::launch_contrast(env, g->nz, cs, n, out, (hipStream_t)stream);
   if (e != hipSuccess)
@@ -91,7 +98,7 @@ int pwbf_resolution_metrics(const pwbf_geometry *g, const float *env, const pwbf
   for (int k = 0; k < n; ++k) {
     if (!finite_disc(targets[k]))
       return api_set_error(PWBF_E_INVALID, "target " + std::to_string(k) + ": bad disc");
-    ts.t[k] = to_pixels(g, targets[k]);
+    ts.t[k] = pwbf::disc_to_pixels(g, targets[k]);
   }
   hipError_t e = pwbf::launch_resolution(env, g->nx, g->nz, (float)g->dx, (float)g->dz, ts, n,
                                          out, (hipStream_t)stream);

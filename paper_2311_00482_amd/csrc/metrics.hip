@@ -10,6 +10,7 @@
 // so results do not depend on scheduling.
 #include <hip/hip_runtime.h>
 
+#include "frame_max.h"
 #include "metrics.h"
 
 namespace pwbf {
@@ -68,26 +69,49 @@ __device__ void disc_stats(const float *env, int nz, const DiscPix &d, float *sh
   *sd_out = n > 0.f ? sqrtf(var) : __builtin_nanf("");
 }
 
+// CR (Eq. (5)) and CNR (Eq. (6)) of env between two discs; the result is
+// complete in thread 0
+__device__ pwbf_contrast disc_contrast(const float *env, int nz, const DiscPix &in,
+                                       const DiscPix &bg, float *sh) {
+  int n_in, n_bg;
+  float mu_in, sd_in, mu_bg, sd_bg;
+  disc_stats(env, nz, in, sh, &n_in, &mu_in, &sd_in);
+  disc_stats(env, nz, bg, sh, &n_bg, &mu_bg, &sd_bg);
+  pwbf_contrast r;
+  r.mu_in = mu_in;
+  r.mu_out = mu_bg;
+  r.sigma_in = sd_in;
+  r.sigma_out = sd_bg;
+  r.cr_db = (mu_in > 0.f && mu_bg > 0.f) ? 20.0f * log10f(mu_in / mu_bg) : __builtin_nanf("");
+  const float den = sqrtf(0.5f * (sd_in * sd_in + sd_bg * sd_bg));
+  r.cnr = den > 0.f ? (mu_in - mu_bg) / den : __builtin_nanf("");
+  r.n_in = n_in;
+  r.n_out = n_bg;
+  return r;
+}
+
 __global__ void __launch_bounds__(kThreads)
     k_contrast(const float *__restrict__ env, int nz, CystSet cs, pwbf_contrast *__restrict__ out) {
   __shared__ float sh[kThreads];
   const int k = blockIdx.x;
-  int n_in, n_bg;
-  float mu_in, sd_in, mu_bg, sd_bg;
-  disc_stats(env, nz, cs.in[k], sh, &n_in, &mu_in, &sd_in);
-  disc_stats(env, nz, cs.out[k], sh, &n_bg, &mu_bg, &sd_bg);
+  const pwbf_contrast r = disc_contrast(env, nz, cs.in[k], cs.out[k], sh);
+  if (threadIdx.x == 0) out[k] = r;
+}
+
+// one block per slot of the list
+__global__ void __launch_bounds__(kThreads)
+    k_quality(const QualityPlan *__restrict__ plans, QualityList ql, QualityOut *__restrict__ out) {
+  __shared__ float sh[kThreads];
+  const QualityPlan &Q = plans[ql.plan[blockIdx.x]];
+  const float m = dev::frame_max_read(Q.ws_max);
+  const pwbf_contrast c = disc_contrast(Q.env, Q.nz, Q.in, Q.out, sh);
   if (threadIdx.x == 0) {
-    pwbf_contrast r;
-    r.mu_in = mu_in;
-    r.mu_out = mu_bg;
-    r.sigma_in = sd_in;
-    r.sigma_out = sd_bg;
-    r.cr_db = (mu_in > 0.f && mu_bg > 0.f) ? 20.0f * log10f(mu_in / mu_bg) : __builtin_nanf("");
-    const float den = sqrtf(0.5f * (sd_in * sd_in + sd_bg * sd_bg));
-    r.cnr = den > 0.f ? (mu_in - mu_bg) / den : __builtin_nanf("");
-    r.n_in = n_in;
-    r.n_out = n_bg;
-    out[k] = r;
+    QualityOut r;
+    r.frame_max = m;
+    r.cr_db = c.cr_db;
+    r.cnr = c.cnr;
+    r.ok = (m > 0.f && c.cr_db <= Q.max_cr_db) ? 1 : 0;  // a NaN CR fails
+    out[blockIdx.x] = r;
   }
 }
 
@@ -176,6 +200,13 @@ __global__ void __launch_bounds__(kThreads)
 }
 
 }  // namespace
+
+hipError_t launch_quality(const QualityPlan *plans, const QualityList &ql, QualityOut *out,
+                          hipStream_t stream) {
+  if (ql.n < 1) return hipSuccess;
+  hipLaunchKernelGGL(k_quality, dim3(ql.n), dim3(kThreads), 0, stream, plans, ql, out);
+  return hipGetLastError();
+}
 
 hipError_t launch_contrast(const float *env, int nz, const CystSet &cs, int n, pwbf_contrast *out,
                            hipStream_t stream) {

@@ -10,7 +10,7 @@
 // The kernel starts each window at floor(min transmit) - 1 plus
 // floor(min receive) - 1, so every interpolation pair of every pixel of the
 // tile lies inside ceil(spread) + 6 entries (rounded up to a multiple of 4).
-#include "frame_max.h"
+#include "frame_max_layout.h"
 #include "plan_host.h"
 
 #include <algorithm>
@@ -107,6 +107,11 @@ int validate_geometry(const pwbf_geometry *g, std::string *err) {
   if (smax >= (double)(1 << 20))
     return fail(err, PWBF_E_UNSUPPORTED,
                 "delays reach %.0f samples; float32 delays need < 2^20", smax);
+  // the pitches bound the window of a tile even where the grid is one pixel
+  // wide or deep (the delay bound above does not see them then)
+  if (g->dx * scale >= (double)(1 << 20) || g->dz * scale >= (double)(1 << 20))
+    return fail(err, PWBF_E_UNSUPPORTED, "pixel pitch of %.3g x %.3g samples exceeds 2^20",
+                g->dx * scale, g->dz * scale);
   return PWBF_OK;
 }
 
@@ -200,6 +205,9 @@ static int window_entries(FramePlan &p, int TZ, int TX) {
   return ((int)std::ceil(rt + rr) + 6 + 3) & ~3;
 }
 
+// Wavefronts of a tile, without overflow for any field values.
+static int64_t tile_waves(const pwbf_tile &t) { return (int64_t)t.wz * t.wx; }
+
 // Apply launch shape t to plan P (geometry already filled in): window length,
 // channels per LDS chunk. PWBF_E_UNSUPPORTED when even cpw channels do not fit.
 static int fit_tile(const pwbf_geometry *g, pwbf_tile t, FramePlan *P, std::string *err) {
@@ -208,7 +216,7 @@ static int fit_tile(const pwbf_geometry *g, pwbf_tile t, FramePlan *P, std::stri
   const int ppw = kWave / t.cpw;
   if (t.lz < 1 || t.lz > ppw || (t.lz & (t.lz - 1)))
     return fail(err, PWBF_E_INVALID, "tile.lz %d not a power of two in 1..%d", t.lz, ppw);
-  if (t.wz < 1 || t.wx < 1 || t.wz * t.wx > kMaxWavesPerBlock)
+  if (t.wz < 1 || t.wx < 1 || tile_waves(t) > kMaxWavesPerBlock)
     return fail(err, PWBF_E_INVALID, "tile %d x %d wavefronts outside 1..%d", t.wz, t.wx,
                 kMaxWavesPerBlock);
   if (t.chunk < 0 || t.chunk % t.cpw)
@@ -330,7 +338,7 @@ static int plan_frame_uncached(const pwbf_geometry *g, int dtype, int mode, int 
       t.wz = d.wz;
       t.wx = d.wx;
     }
-    if (waves && t.wz * t.wx != waves)
+    if (waves && tile_waves(t) != waves)
       return fail(err, PWBF_E_INVALID, "batch tiles need wz * wx = %d (got %d x %d)", waves,
                   t.wz, t.wx);
     rc_fit = fit_tile(g, t, P, err);
@@ -338,7 +346,7 @@ static int plan_frame_uncached(const pwbf_geometry *g, int dtype, int mode, int 
     pwbf_tile tuned;
     bool done = false;
     if (tune_lookup(shape_key(g, dtype, mode, angle, waves), &tuned) &&
-        (!waves || tuned.wz * tuned.wx == waves))
+        (!waves || tile_waves(tuned) == waves))
       done = fit_tile(g, tuned, P, err) == PWBF_OK;
     if (!done && (!waves || d.wz * d.wx == waves)) done = fit_tile(g, d, P, err) == PWBF_OK;
     if (!done) {

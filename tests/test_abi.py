@@ -318,9 +318,11 @@ def test_batch_create_rejects_before_touching_the_device():
     assert L.pwbf_batch_destroy(None) == 0
 
 
-def _probe(g, mode=_abi.DAS, angle=-1, env=1, log=1, slots=2, reserved=0):
+def _probe(g, mode=_abi.DAS, angle=-1, env=1, log=1, slots=2, quality=0, region=None,
+           max_cr=-10.0):
+    q = _abi.Cyst() if region is None else _abi.Cyst(_abi.Disc(*region[0]), _abi.Disc(*region[1]))
     return _abi.Probe(ctypes.pointer(g.s) if g is not None else None, mode, angle, env, log,
-                      slots, reserved)
+                      slots, quality, q, max_cr)
 
 
 def _server_create(probes, budget=0, max_queue=0):
@@ -337,7 +339,15 @@ def test_server_create_rejects_before_touching_the_device():
     ok = _probe(g)
     assert _server_create([])[0] == _abi.E_INVALID
     assert _server_create([ok], max_queue=-1)[0] == _abi.E_INVALID
-    assert _server_create([ok, _probe(g, reserved=1)])[0] == _abi.E_INVALID
+    assert _server_create([ok, _probe(g, quality=2)])[0] == _abi.E_INVALID
+    good = ((0.0, 0.02, 2e-3), (5e-3, 0.02, 2e-3))
+    assert _server_create([_probe(g, quality=1)])[0] == _abi.E_INVALID  # no region
+    rc, msg = _server_create([_probe(g, quality=1, region=((0.0, 0.02, 0.0), good[1]))])
+    assert rc == _abi.E_INVALID and "quality check" in msg
+    rc, _ = _server_create([_probe(g, quality=1, region=good, max_cr=float("nan"))])
+    assert rc == _abi.E_INVALID
+    rc, _ = _server_create([_probe(g, quality=1, region=((float("inf"), 0.02, 1e-3), good[1]))])
+    assert rc == _abi.E_INVALID
     assert _server_create([_probe(g, slots=65)])[0] == _abi.E_INVALID
     assert _server_create([_probe(g, env=2)])[0] == _abi.E_INVALID
     assert _server_create([_probe(None)])[0] == _abi.E_INVALID
@@ -357,6 +367,7 @@ def test_server_create_rejects_before_touching_the_device():
     assert L.pwbf_server_create(None, 1, 0, 0, None) == _abi.E_INVALID
     rid = ctypes.c_uint64()
     assert L.pwbf_server_submit(None, 0, FAKE, -1.0, ctypes.byref(rid)) == _abi.E_INVALID
+    assert L.pwbf_server_submit_ex(None, 0, FAKE, -1.0, 1.0, ctypes.byref(rid)) == _abi.E_INVALID
     n = ctypes.c_int32()
     assert L.pwbf_server_poll(None, None, 1, ctypes.byref(n), 0) == _abi.E_INVALID
     assert L.pwbf_server_release(None, 1) == _abi.E_INVALID

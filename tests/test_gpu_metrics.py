@@ -12,55 +12,22 @@ relative 1e-5 (CR to 1e-4 dB). The benchmark phantom's anechoic cysts must read
 at least 10 dB darker than their background.
 """
 
-import itertools
 import math
 
 import numpy as np
 import pytest
 
+from metric_checks import _contrast_matches, _regions, _split
 from oracle import metrics as om
 from synth import config_c3, make_frame
 
 pytestmark = pytest.mark.gpu
-
-BAND = 1e-5
 
 
 def _torch():
     import torch
     assert torch.cuda.is_available(), "these tests need the GPU"
     return torch
-
-
-def _split(g, disc):
-    """Pixels surely inside the disc, and those within BAND of its boundary."""
-    d = om.disc_distance(g, *disc)
-    return d <= 1.0 - BAND, np.abs(d - 1.0) < BAND
-
-
-def _masks_with_count(g, disc, n):
-    """Every pixel set the float32 decision may give for this disc with n pixels."""
-    sure, band = _split(g, disc)
-    extra = np.argwhere(band)
-    k = n - int(sure.sum())
-    assert 0 <= k <= len(extra), (n, int(sure.sum()), len(extra))
-    assert len(extra) <= 12, "too many boundary pixels to enumerate"
-    for pick in itertools.combinations(range(len(extra)), k):
-        m = sure.copy()
-        for i in pick:
-            m[tuple(extra[i])] = True
-        yield m
-
-
-def _contrast_matches(g, env, cyst, got):
-    for mi in _masks_with_count(g, cyst[0], got["n_in"]):
-        for mo in _masks_with_count(g, cyst[1], got["n_out"]):
-            ref = om.contrast_from_masks(env, mi, mo)
-            ok = all(got[k] == pytest.approx(ref[k], rel=1e-5)
-                     for k in ("mu_in", "mu_out", "sigma_in", "sigma_out", "cnr"))
-            if ok and abs(got["cr_db"] - ref["cr_db"]) <= 1e-4:
-                return ref
-    return None
 
 
 @pytest.fixture(scope="module")
@@ -72,25 +39,6 @@ def c3_env():
     out = beamform(g, torch.from_numpy(fr["f32"]).cuda(), "das", -1, want=("rf", "env"))
     torch.cuda.synchronize()
     return g, fr["phantom"], out["env"]
-
-
-def _regions(g, ph):
-    # background disc beside each cyst, on the side farther from the point
-    # targets (left, right, above or below); the inside disc is 0.8 r
-    cysts = []
-    pts = np.asarray(ph.points)
-    for cx, cz, r in ph.cysts:
-        best = None
-        for ox, oz in ((-1, 0), (1, 0), (0, -1), (0, 1)):
-            bx, bz = cx + ox * 2.2 * r, cz + oz * 2.2 * r
-            if not (g.x_min + r < bx < g.x_max - r and g.z_min + r < bz < g.z_max - r):
-                continue
-            clear = float(np.hypot(pts[:, 0] - bx, pts[:, 1] - bz).min()) - 0.8 * r
-            if best is None or clear > best[0]:
-                best = (clear, bx, bz)
-        cysts.append(((cx, cz, 0.8 * r), (best[1], best[2], 0.8 * r)))
-    targets = [(float(x), float(z), 1.0e-3) for x, z in ph.points]
-    return cysts, targets
 
 
 def test_contrast_matches_oracle_and_cysts_are_dark(c3_env):

@@ -6,7 +6,11 @@ which other frames share the launch: a frame's planes must be bitwise equal
 alone and in a mix of probes. int16 RF of 10 bits converts to float16
 exactly, so the served planes meet the float32 bars against the FP64 oracle.
 Admission holds the slot bytes in use under the HBM budget; a full probe queue
-rejects with PWBF_E_BUSY.
+rejects with PWBF_E_BUSY; a request still queued at its deadline comes back
+with PWBF_E_TIMEOUT and no planes. A probe's per-frame quality check (frame
+maximum, CR and CNR of one region, pass or fail against a CR bound) equals the
+metrics of the served envelope, checked against the float64 oracle metrics on
+that envelope and on the oracle's own envelope.
 """
 
 import time
@@ -208,3 +212,86 @@ def test_close_with_requests_in_flight(probes):
         srv.submit(0, probes[2][2])
         srv.submit(1, probes[3][2])
     srv.close()  # stops the scheduler, waits for the device, frees the rings
+
+
+def _contrast_of(g, env, region):
+    from paper_2311_00482_amd import contrast_metrics
+    return contrast_metrics(g, env, [region])[0]
+
+
+def test_quality_check_matches_the_metrics_and_the_oracle(probes):
+    """Probe c (the compound benchmark frame with its cysts) served twice: with a
+    CR bound of -10 dB the first cyst passes, with -200 dB it fails."""
+    from metric_checks import _matching_masks, _regions
+    from oracle import metrics as om
+    from paper_2311_00482_amd import ProbeSpec, Server
+    torch = _torch()
+    spec, fr, host = probes[2]
+    g = spec.geom
+    region = _regions(g, fr["phantom"])[0][0]
+    specs = [ProbeSpec(g, "das", -1, ("rf", "env"), 2, quality_region=region,
+                       quality_max_cr_db=bound) for bound in (-10.0, -200.0)]
+    srv = Server(specs)
+    try:
+        for i in range(2):
+            srv.submit(i, host)
+        got = sorted(_collect(srv, 2).values(), key=lambda t: t[0].probe)
+    finally:
+        srv.close()
+    # the oracle's envelope over the columns both discs touch (full depth)
+    X, _ = om.pixel_centres(g)
+    cols = np.nonzero(np.any([np.abs(X[:, 0] - d[0]) <= d[2] + g.dx for d in region], 0))[0]
+    pix = (cols[:, None] * g.nz + np.arange(g.nz)[None, :]).ravel()
+    rf_cols = oracle.das(g, fr["master"], -1, pix, parallel=True).reshape(len(cols), g.nz)
+    env_ref = np.zeros((g.nx, g.nz))
+    env_ref[cols] = oracle.envelope_z(rf_cols)
+    for (r, planes), bound in zip(got, (-10.0, -200.0)):
+        env = planes["env"]
+        assert r.status == 0
+        # the frame maximum is the envelope's, bit for bit
+        assert r.frame_max == float(env.max())
+        # CR and CNR are those of the metrics call on the same plane, bit for bit
+        c = _contrast_of(g, torch.from_numpy(env).cuda(), region)
+        assert np.float32(r.cr_db) == np.float32(c["cr_db"])
+        assert np.float32(r.cnr) == np.float32(c["cnr"])
+        # ... which are the float64 oracle metrics of that plane
+        m = _matching_masks(g, env, region, c)
+        assert m is not None, (c, om.contrast(g, env, *region))
+        ref, mi, mo = m
+        # and, within what the envelope's 1e-5 bar allows, of the oracle's envelope
+        o = om.contrast_from_masks(env_ref, mi, mo)
+        d_env = TOL32 * float(env.max())
+        tol_cr = 1.5 * 20.0 / np.log(10.0) * d_env * (1.0 / o["mu_in"] + 1.0 / o["mu_out"])
+        s = np.sqrt((o["sigma_in"] ** 2 + o["sigma_out"] ** 2) / 2.0)
+        tol_cnr = 1.5 * (2.0 + abs(o["cnr"])) * d_env / s
+        assert abs(r.cr_db - o["cr_db"]) <= tol_cr, (r.cr_db, o["cr_db"], tol_cr)
+        assert abs(r.cnr - o["cnr"]) <= tol_cnr, (r.cnr, o["cnr"], tol_cnr)
+        assert r.quality_ok == (r.frame_max > 0 and r.cr_db <= bound)
+    assert got[0][0].quality_ok and not got[1][0].quality_ok
+    assert got[0][0].cr_db < -10.0
+
+
+def test_deadline_expires_queued_requests(probes):
+    from paper_2311_00482_amd import PwbfError
+    spec, _, host = probes[0]
+    srv = _server(probes, [0], slots=1)
+    try:
+        first = srv.submit(0, host)
+        (r, _), = _collect(srv, 1, release=False).values()  # holds the only slot
+        late = srv.submit(0, host, deadline=srv.now() + 0.05)
+        time.sleep(0.3)
+        (e, planes), = _collect(srv, 1, release=False).values()
+        assert e.id == late and e.status == -6 and e.slot == -1 and planes == {}
+        assert e.rf is None and e.t_done >= e.t_arrival + 0.05
+        st = srv.stats()
+        assert st["expired"] == 1 and st["completed"] == 1 and st["queued"] == 0
+        srv.release(late)  # frees nothing: the slot is still held
+        assert srv.stats()["budget_in_use"] == st["budget_in_use"]
+        srv.release(first)
+        ok = srv.submit(0, host, deadline=srv.now() + 30.0)
+        (r2, planes2), = _collect(srv, 1).values()
+        assert r2.id == ok and r2.status == 0 and "rf" in planes2
+        with pytest.raises(PwbfError):
+            srv.submit(0, host, deadline=float("nan"))
+    finally:
+        srv.close()
