@@ -33,11 +33,22 @@
  *    enqueued on the caller's HIP stream (NULL = the null stream) and the call
  *    returns once it is enqueued. Device faults surface at the caller's next
  *    synchronisation. No single-frame call allocates or frees device memory,
- *    keeps a pointer after it returns, prints, or throws (the batch, tuning and
- *    serving objects below own memory and say so). Calls on different streams from
- *    different threads may overlap; calls that share a workspace must not.
+ *    keeps a pointer after it returns, prints (unless PWBF_DEBUG is set), or
+ *    throws (the batch, tuning and serving objects below own memory and say
+ *    so). Calls on different streams from different threads may overlap; calls
+ *    that share a workspace must not.
  *  - Return value: PWBF_OK (0) or a negative PWBF_E_* code; pwbf_last_error()
  *    gives a thread-local description of the last failure on the calling thread.
+ *
+ * Environment (read once, at first use)
+ *  - PWBF_DEBUG=1: every launch shape the planner picks (and whether it came
+ *    from the caller, the tuning table, the default or the fallback search) and
+ *    every error a call returns are printed to stderr as "pwbf: ..." lines.
+ *    Unset or "0": the library prints nothing.
+ *  - PWBF_TUNE_CACHE=<path>: the tuning table starts from that file (the format
+ *    of pwbf_tune_save) when it exists, and each shape pwbf_tune measures is
+ *    written back to it at once (through a side file and a rename).
+ *  - PWBF_BATCH_BRANCHES=1..4: the branches of a batch graph (default 3).
  */
 #ifndef PWBF_H
 #define PWBF_H

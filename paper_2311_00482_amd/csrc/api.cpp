@@ -22,6 +22,7 @@ thread_local std::string g_last_error;
 
 int set_error(int code, const std::string &msg) {
   g_last_error = msg;
+  if (code != PWBF_OK) pwbf::debug_log("error %d: %s", code, msg.c_str());
   return code;
 }
 

@@ -330,6 +330,7 @@ static int plan_frame_uncached(const pwbf_geometry *g, int dtype, int mode, int 
                          !tile_in->wx && !tile_in->chunk;
   if (zero_tile) tile_in = nullptr;
   int rc_fit = PWBF_OK;
+  const char *source = "explicit";
   if (tile_in) {
     pwbf_tile t = *tile_in;
     if (t.cpw == 0) t.cpw = d.cpw;
@@ -348,8 +349,13 @@ static int plan_frame_uncached(const pwbf_geometry *g, int dtype, int mode, int 
     if (tune_lookup(shape_key(g, dtype, mode, angle, waves), &tuned) &&
         (!waves || tile_waves(tuned) == waves))
       done = fit_tile(g, tuned, P, err) == PWBF_OK;
-    if (!done && (!waves || d.wz * d.wx == waves)) done = fit_tile(g, d, P, err) == PWBF_OK;
+    source = "tuned";
+    if (!done && (!waves || d.wz * d.wx == waves)) {
+      done = fit_tile(g, d, P, err) == PWBF_OK;
+      source = "default";
+    }
     if (!done) {
+      source = "fallback";
       // every shape with at least the default's lane groups and the required
       // wavefront count; the choice depends on the geometry only. Groups of 8
       // or 4 pixels (cpw 8, 16) keep windows short on grids with pixels tens of
@@ -388,6 +394,11 @@ static int plan_frame_uncached(const pwbf_geometry *g, int dtype, int mode, int 
   P->tiles_z = (g->nz + TZ - 1) / TZ;
   P->tiles_x = (g->nx + TX - 1) / TX;
   P->n_tiles = P->tiles_z * P->tiles_x;
+  if (debug_enabled())
+    debug_log("plan mode %d dtype %d angle %d grid %d x %d: %s shape cpw %d lz %d wz %d wx %d "
+              "chunk %d, window %d, %d x %d tiles, %zu B LDS",
+              mode, dtype, angle, g->nx, g->nz, source, P->cpw, P->lz, P->wz, P->wx, P->chunk,
+              P->win, P->tiles_z, P->tiles_x, plan_lds_bytes(*P));
   return PWBF_OK;
 }
 

@@ -34,6 +34,10 @@ int tune_save(const char *path, std::string *err);
 int tune_load(const char *path, std::string *err);
 void tune_clear();
 uint32_t tune_generation();  // changes whenever the table does
+const std::string &tune_cache_path();  // PWBF_TUNE_CACHE ("" when unset)
+// PWBF_DEBUG: whether it is set (to anything but "0"), and a line to stderr when it is
+bool debug_enabled();
+void debug_log(const char *fmt, ...) __attribute__((format(printf, 1, 2)));
 // Channels whose receive aperture reaches tile `tile` of plan P (all of them
 // without apodization), and the tile's relative cost for work ordering.
 int tile_active_channels(const pwbf_geometry *g, const FramePlan &P, int tile);

@@ -84,3 +84,46 @@ def test_oracle_asan_ubsan(tmp_path):
                  ["gcc", "-std=gnu11", "-Wall", "-Wno-unknown-pragmas", *SAN,
                   os.path.join(NATIVE, "oracle_san.c"), "-lm"])
     _run(exe)
+
+
+def test_tune_cache_environment(tmp_path):
+    """PWBF_TUNE_CACHE: a shape stored in one process is planned in the next."""
+    exe = _build(tmp_path, "tune_env_test",
+                 ["g++", "-std=c++17", "-Wall", "-pthread", *SAN, f"-I{INC}",
+                  os.path.join(NATIVE, "tune_env_test.cpp"), os.path.join(CSRC, "plan.cpp"),
+                  os.path.join(CSRC, "tune.cpp")])
+    cache = tmp_path / "shapes.json"
+    env = dict(os.environ, PWBF_TUNE_CACHE=str(cache), PWBF_DEBUG="1")
+    r = subprocess.run([exe, "store"], capture_output=True, text=True, timeout=120, env=env)
+    assert r.returncode == 0 and "all ok" in r.stdout, r.stderr
+    assert "default shape" in r.stderr and "tuned shape cpw 2 lz 4 wz 2 wx 4" in r.stderr
+    assert cache.exists() and "[2, 4, 2, 4, 0]" in cache.read_text()
+    r = subprocess.run([exe, "load"], capture_output=True, text=True, timeout=120, env=env)
+    assert r.returncode == 0 and "all ok" in r.stdout, r.stderr
+    assert "tune cache" in r.stderr and "1 shapes" in r.stderr
+    # without the variable the stored shape is not seen, and nothing is printed
+    env.pop("PWBF_TUNE_CACHE")
+    env.pop("PWBF_DEBUG")
+    r = subprocess.run([exe, "load"], capture_output=True, text=True, timeout=120, env=env)
+    assert r.returncode != 0 and "pwbf:" not in r.stderr
+
+
+def test_debug_environment_reports_errors_and_plans():
+    """PWBF_DEBUG=1 through the built library: plans and errors go to stderr."""
+    code = (
+        "import ctypes\n"
+        "from paper_2311_00482_amd import _abi\n"
+        "from paper_2311_00482_amd.api import GeometryArg\n"
+        "from synth import config_c1\n"
+        "L = _abi.lib()\n"
+        "g = GeometryArg(config_c1())\n"
+        "info = _abi.PlanInfo()\n"
+        "assert L.pwbf_describe_plan(g.ref, _abi.DAS, -1, None, ctypes.byref(info)) == 0\n"
+        "g.s.n_angles = 0\n"
+        "assert L.pwbf_describe_plan(g.ref, _abi.DAS, -1, None, ctypes.byref(info)) == -1\n")
+    env = dict(os.environ, PWBF_DEBUG="1", PYTHONPATH=ROOT)
+    r = subprocess.run(["python", "-c", code], capture_output=True, text=True, timeout=300,
+                       env=env, cwd=ROOT)
+    assert r.returncode == 0, r.stderr[-3000:]
+    assert "pwbf: plan mode 0" in r.stderr and " shape cpw " in r.stderr
+    assert "pwbf: error -1: n_angles 0 outside" in r.stderr
