@@ -153,28 +153,152 @@ def _time_steps(fn, steps, warmup, torch):
     return wall, lat, span
 
 
+def cpu_model() -> str:
+    """The host CPU's model name (first processor in /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def _columns(g, n_cols):
+    """n_cols whole depth columns spread over the grid, and their flat pixel indices."""
+    cols = np.unique(np.linspace(0, g.nx - 1, max(1, min(g.nx, n_cols))).astype(int))
+    return cols, (cols[:, None] * g.nz + np.arange(g.nz)[None, :]).ravel()
+
+
 def cpu_baseline(g, rf_master, budget_s: float):
-    """The FP64 oracle on a bounded sample of whole depth columns, single thread."""
+    """The FP64 oracle timed on the host's cores: the OpenMP build of the same
+    source over every thread it is given (the reported value), and the
+    single-threaded build, each on whole depth columns sized to about budget_s
+    seconds (the OpenMP leg takes the whole image when it fits). Returns the
+    baseline record and the OpenMP leg's (columns, pixels, values) for the
+    accuracy figures."""
     import oracle
-    cols_all = np.arange(g.nx)
-    t0 = time.perf_counter()
-    oracle.das(g, rf_master, -1, np.arange(g.nz) + (g.nx // 2) * g.nz)
-    per_col = time.perf_counter() - t0
-    n_cols = int(max(1, min(g.nx, budget_s / max(per_col, 1e-6))))
-    cols = cols_all[np.linspace(0, g.nx - 1, n_cols).astype(int)]
-    pix = (cols[:, None] * g.nz + np.arange(g.nz)[None, :]).ravel()
-    t0 = time.perf_counter()
-    oracle.das(g, rf_master, -1, pix)
-    dt = time.perf_counter() - t0
-    gathers = len(pix) * g.n_channels * g.n_angles
-    return {"value": gathers / dt / 1e9, "unit": UNIT, "cores": 1, "kind": "oracle",
-            "sample": f"{n_cols} of {g.nx} depth columns ({len(pix)} pixels x "
-                      f"{g.n_channels} ch x {g.n_angles} angles), compound DAS only, "
-                      f"{dt:.1f} s", "seconds": dt,
-            "frames_per_s_equiv": gathers / dt / g.gathers}
+    mid = np.arange(g.nz) + (g.nx // 2) * g.nz
+    legs = {}
+    for parallel in (False, True):
+        t0 = time.perf_counter()
+        oracle.das(g, rf_master, -1, mid, parallel=parallel)
+        per_col = time.perf_counter() - t0
+        cols, pix = _columns(g, int(budget_s / max(per_col, 1e-6)))
+        t0 = time.perf_counter()
+        vals = oracle.das(g, rf_master, -1, pix, parallel=parallel)
+        dt = time.perf_counter() - t0
+        legs[parallel] = (cols, pix, vals, dt)
+    gathers_per_pixel = g.n_channels * g.n_angles
+
+    def rate(leg):
+        return len(leg[1]) * gathers_per_pixel / leg[3] / 1e9
+
+    def sample(leg):
+        return (f"{len(leg[0])} of {g.nx} depth columns ({len(leg[1])} pixels x "
+                f"{g.n_channels} ch x {g.n_angles} angles), compound DAS only, {leg[3]:.1f} s")
+
+    omp, one = legs[True], legs[False]
+    threads = oracle.threads(True)
+    note = ("the oracle evaluates every channel of every pixel, including those outside "
+            "the receive aperture (zero weight); the GPU kernel visits only the in-aperture "
+            f"(pixel, channel) pairs, {aperture_pairs(g) / (g.nx * g.nz * g.n_channels):.1%} "
+            "of them here. The unit counts all channels for both, as defined.")
+    rec = {"value": rate(omp), "unit": UNIT, "cores": threads, "kind": "oracle",
+           "sample": sample(omp), "seconds": omp[3],
+           "frames_per_s_equiv": len(omp[1]) * gathers_per_pixel / omp[3] / g.gathers,
+           "build": f"OpenMP, {threads} threads", "cpu_model": cpu_model(),
+           "host_cores_available": os.cpu_count(),
+           "single_thread": {"value": rate(one), "unit": UNIT, "cores": 1,
+                             "sample": sample(one), "seconds": one[3],
+                             "frames_per_s_equiv":
+                                 len(one[1]) * gathers_per_pixel / one[3] / g.gathers},
+           "channels_note": note}
+    return rec, omp[:3]
 
 
-def other_modes(dev, torch, steps: int, warmup: int) -> dict:
+def _max_norm(gpu, ref) -> float:
+    """max |gpu - ref| / max |ref| (the per-pixel max-normalised error)."""
+    ref = np.asarray(ref, dtype=np.float64)
+    return float(np.abs(np.asarray(gpu, dtype=np.float64) - ref).max()
+                 / max(float(np.abs(ref).max()), 1e-300))
+
+
+def _plane_errors(gpu: dict, ref_rf: np.ndarray, cols=None) -> dict:
+    """rf and envelope errors (max-normalised) and the log image's largest dB
+    difference where the oracle's log image is at or above -40 dB, over whole
+    depth columns (all of them when cols is None)."""
+    import oracle
+    sel = slice(None) if cols is None else cols
+    ref_env = oracle.envelope_z(ref_rf)
+    out = {"rf": _max_norm(gpu["rf"][sel], ref_rf)}
+    if "env" in gpu:
+        out["env"] = _max_norm(gpu["env"][sel], ref_env)
+    if "log" in gpu and cols is None:
+        ref_log = oracle.log_compress(ref_env)
+        m = ref_log >= -40.0
+        out["log_db_max_abs"] = float(np.abs(gpu["log"][m] - ref_log[m]).max())
+    return out
+
+
+def error_vs_oracle(gs, fr, sample, gpu32: dict, gpu16: dict) -> dict:
+    """The headline frame's planes against the FP64 oracle on the OpenMP
+    baseline's sample (whole depth columns), for each RF storage type: FP32
+    against the oracle on the simulated (float64) record, FP16 against it too
+    (storage rounding included) and against the oracle on the FP16-stored
+    samples themselves (the kernel's own arithmetic)."""
+    import oracle
+    cols, pix, vals = sample
+    ref = vals.reshape(len(cols), gs.nz)
+    whole = len(cols) == gs.nx
+    res = {"sample": f"{len(cols)} of {gs.nx} depth columns", "norm": "max |oracle| over the "
+           "sample, per plane", "bar": {"f32": 1e-5, "f16": 1e-3, "log_db": 0.1},
+           "f32": _plane_errors(gpu32, ref, None if whole else cols),
+           "f16": _plane_errors(gpu16, ref, None if whole else cols)}
+    ref16 = oracle.das(gs, fr["f16"], -1, pix, parallel=True).reshape(len(cols), gs.nz)
+    res["f16_vs_oracle_on_stored_samples"] = _plane_errors(gpu16, ref16,
+                                                           None if whole else cols)
+    return res
+
+
+def _mode_error(gs, fr, mode: str, quant: bool, rf_plane) -> dict:
+    """The raw beamformed plane of a DMAS or pDAS (p = 2) frame against the
+    oracle on the stored samples: the whole image on 512 x 512 grids, 64 depth
+    columns on larger ones."""
+    import oracle
+    rf_in = fr["i16"] if quant else fr["f32"]
+    whole = gs.nx * gs.nz <= 512 * 512
+    cols, pix = _columns(gs, gs.nx if whole else 64)
+    if mode == "dmas":
+        ref = oracle.dmas(gs, rf_in, -1, "identity", pix, parallel=True)
+    else:
+        ref = oracle.pdas(gs, rf_in, -1, 2.0, pix, parallel=True)
+    gpu = rf_plane.cpu().numpy()[cols]
+    return {"rf": _max_norm(gpu, ref.reshape(len(cols), gs.nz)),
+            "sample": "whole image" if whole else f"{len(cols)} of {gs.nx} depth columns",
+            "rf_storage": "int16" if quant else "f32"}
+
+
+def c1_error(dev, torch) -> dict:
+    """The single-frame DAS workload (1 angle, 64 ch x 2048 int16 samples,
+    128 x 256 pixels) against the oracle on the whole image."""
+    import oracle
+    from paper_2311_00482_amd import GeometryArg, beamform
+    from synth import config_c1, make_frame
+    gs = config_c1()
+    fr = make_frame(gs, 1001, "c1", quantize=True)
+    g = GeometryArg(gs)
+    out = beamform(g, torch.from_numpy(fr["i16"]).to(dev), "das", -1, want=("rf", "env", "log"))
+    gpu = {k: v.cpu().numpy() for k, v in out.items()}
+    ref = oracle.das(gs, fr["i16"], -1, parallel=True)
+    res = _plane_errors(gpu, ref)
+    res.update({"rf_storage": "int16", "sample": "whole image"})
+    return res
+
+
+def other_modes(dev, torch, steps: int, warmup: int, check: bool = True) -> dict:
     """DMAS and pDAS (p = 2) kernels on the DMAS workload (128 ch, 512 x 512 at
     dz = 25 um, int16 RF) and pDAS on the 11-angle compound workload (FP32 RF):
     kernel time from HIP events, the frame rate of the whole path (band-pass,
@@ -211,6 +335,8 @@ def other_modes(dev, torch, steps: int, warmup: int) -> dict:
                                   "frac": ops / (k_ms * 1e-3) / VALU_LANE_OPS_PEAK,
                                   "ops_per_launch": ops},
                      "rf_storage": "int16" if quant else "f32"}
+        if check:
+            res[name]["error_vs_oracle"] = _mode_error(gs, fr, mode, quant, rf_only["rf"])
         print(f"[bench] {name}: {res[name]['kernel_ms']:.3f} ms kernel, "
               f"frac {res[name]['roofline']['frac']:.2f}", file=sys.stderr, flush=True)
     res.update(iq_modes(dev, torch, steps, warmup))
@@ -360,10 +486,8 @@ def image_metrics(dev, torch, g, gs, phantom, env32, env16) -> dict:
     from paper_2311_00482_amd import contrast_metrics, resolution_metrics
     import ctypes
 
-    cysts = []
-    for cx, cz, r in phantom.cysts:
-        side = 1.0 if cx < 0 else -1.0
-        cysts.append(((cx, cz, 0.8 * r), (cx + side * 2.2 * r, cz, 0.8 * r)))
+    from synth.phantom import cyst_regions
+    cysts = cyst_regions(gs, phantom)
     targets = [(float(x), float(z), 1.0e-3) for x, z in phantom.points]
     res = {}
     for name, env in (("f32", env32), ("f16", env16)):
@@ -392,20 +516,24 @@ def image_metrics(dev, torch, g, gs, phantom, env32, env16) -> dict:
     return res
 
 
-def uneven_batch(dev, torch, steps: int, warmup: int) -> dict:
+def uneven_batch(dev, torch, steps: int, warmup: int, check: bool = False) -> dict:
     """The uneven 32-frame workload (seeded: 64/128 channels, 1/5/11 angles,
     grids 256..1024 per axis, 2048/4096 samples, DAS and DMAS with band-pass,
     int16 RF, RF + envelope + log per frame) as one tuned batch launch, against
     the same frames launched one after another as single frames with default
     launch shapes. The RF is seeded noise of the frames' shapes: the kernels'
-    time does not depend on the values."""
+    time does not depend on the values. The roofline fraction divides the
+    frames' algorithmic operations (the single-frame op model) by the whole
+    launch's time, post-processing included. With check, the raw planes of the
+    four frames cheapest to evaluate are compared with the oracle."""
+    import oracle
     from paper_2311_00482_amd import Batch, FrameSpec, GeometryArg, beamform
     from synth import config_c4_frames
 
     specs = config_c4_frames()
     want = ("rf", "filtered", "env", "log")
     gen = torch.Generator().manual_seed(2000)
-    frames, singles, gathers = [], [], 0
+    frames, singles, gathers, ops = [], [], 0, 0.0
     for sp in specs:
         bp = sp.mode == "dmas"
         g = GeometryArg(sp.geom, bandpass=bp)
@@ -417,6 +545,7 @@ def uneven_batch(dev, torch, steps: int, warmup: int) -> dict:
         ws = torch.empty(WS_BYTES, dtype=torch.uint8, device=dev)
         singles.append((g, rf, sp.mode, w, out, ws, bp))
         gathers += sp.geom.gathers
+        ops += algorithmic_ops(sp.geom, sp.mode)
     t0 = time.perf_counter()
     batch = Batch(frames, tune=True)
     torch.cuda.synchronize()
@@ -424,6 +553,20 @@ def uneven_batch(dev, torch, steps: int, warmup: int) -> dict:
     info = batch.describe()
     n = max(5, steps // 32)
     wallb, latb, _ = time_steps(batch.launch, n, max(2, warmup // 16), torch)
+    ms_b = float(np.mean(latb))
+    err = None
+    if check:
+        cheap = sorted(range(len(specs)), key=lambda i: specs[i].geom.gathers)[:4]
+        err = {}
+        for i in cheap:
+            sp = specs[i]
+            host = frames[i].rf.cpu().numpy()
+            if sp.mode == "dmas":
+                ref = oracle.dmas(sp.geom, host, -1, "identity", parallel=True)
+            else:
+                ref = oracle.das(sp.geom, host, -1, parallel=True)
+            err[f"frame{i}_{sp.mode}_{sp.geom.n_angles}a_{sp.geom.n_channels}ch_"
+                f"{sp.geom.nx}x{sp.geom.nz}"] = _max_norm(frames[i].out["rf"].cpu().numpy(), ref)
 
     def one_by_one():
         for g, rf, mode, w, out, ws, bp in singles:
@@ -431,29 +574,109 @@ def uneven_batch(dev, torch, steps: int, warmup: int) -> dict:
     walls, lats, _ = time_steps(one_by_one, n, max(2, warmup // 16), torch)
     batch.close()
     nf = len(specs)
-    return {"frames": nf, "tuned_create_s": t_create, "kernels": info["kernels"],
-            "batched": {"frames_per_s": nf * n / wallb, "ms_per_launch": float(np.mean(latb)),
-                        "value": gathers * n / wallb / 1e9, "unit": UNIT},
-            "single_frames": {"frames_per_s": nf * n / walls,
-                              "ms_per_32": float(np.mean(lats)),
-                              "value": gathers * n / walls / 1e9, "unit": UNIT}}
+    res = {"frames": nf, "tuned_create_s": t_create, "kernels": info["kernels"],
+           "branches": info.get("branches"),
+           "batched": {"frames_per_s": nf * n / wallb, "ms_per_launch": ms_b,
+                       "value": gathers * n / wallb / 1e9, "unit": UNIT},
+           "roofline": {"bound": "alu", "achieved": ops / (ms_b * 1e-3) / 1e12,
+                        "peak": VALU_LANE_OPS_PEAK / 1e12, "unit": "Tlane-op/s",
+                        "frac": ops / (ms_b * 1e-3) / VALU_LANE_OPS_PEAK,
+                        "ops_per_launch": ops,
+                        "scope": "whole graph launch (beamform, band-pass, envelope, log)"},
+           "single_frames": {"frames_per_s": nf * n / walls,
+                             "ms_per_32": float(np.mean(lats)),
+                             "value": gathers * n / walls / 1e9, "unit": UNIT}}
+    if err is not None:
+        res["error_vs_oracle"] = {"rf": err, "sample": "whole images of the four frames "
+                                  "cheapest to evaluate", "rf_storage": "int16"}
+    return res
 
 
-def systems(dev, torch, steps: int, warmup: int) -> dict:
-    """Single-frame FP32 against batched and served FP16 on the same GPU.
+def _serve_rate(srv, hosts, n_probes, rate, seconds, warmup, rng, keep=None):
+    """Poisson arrivals at rate for warmup + seconds; requests arriving in the
+    first warmup seconds are served but not counted. keep(r, srv) may copy a
+    result's planes before its release."""
+    from paper_2311_00482_amd import PwbfError
+    horizon = warmup + seconds
+    n = int(rate * horizon * 1.2) + 16
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, n))
+    arrivals = arrivals[arrivals < horizon]
+    n = len(arrivals)
+    which = rng.integers(0, n_probes, n)
+    t0 = srv.now() + 0.01
+    t_measure = t0 + warmup
+    before = None
+    lat, parts, quality, k, accepted, done = [], [], [], 0, 0, 0
+    limit = time.time() + horizon + 60
+    while k < n or done < accepted:
+        if time.time() > limit:
+            raise RuntimeError(f"serving run at {rate}/s did not drain")
+        now = srv.now()
+        if before is None and now >= t_measure:
+            before = srv.stats()
+        while k < n and t0 + arrivals[k] <= now:
+            try:
+                srv.submit(int(which[k]), hosts[which[k]], t0 + arrivals[k])
+                accepted += 1
+            except PwbfError as e:  # a full probe queue drops the request
+                if e.code != -5:
+                    raise
+            k += 1
+        got = srv.poll(64, wait_ms=0 if k < n else 5)
+        for r in got:
+            done += 1
+            if r.t_arrival >= t_measure:
+                lat.append(r.t_done - r.t_arrival)
+                parts.append((r.t_admit - r.t_arrival, r.t_launch - r.t_admit,
+                              r.t_done - r.t_launch))
+                if srv.probes[r.probe].quality_region is not None:
+                    quality.append(r.quality_ok)
+            if keep is not None:
+                keep(r, srv)
+            srv.release(r.id)
+        if not got and k < n:  # sleep only when the next arrival is far off
+            gap = t0 + arrivals[k] - srv.now()
+            if gap > 3e-3:  # host sleeps can overshoot by a millisecond or more
+                time.sleep(gap - 2e-3)
+    after = srv.stats()
+    before = before or after
+    wall = seconds
+    pq = np.percentile(np.array(parts) * 1e3, 50, axis=0)
+    pq99 = np.percentile(np.array(parts) * 1e3, 99, axis=0)
+    return {"offered_per_s": rate, "measured_s": seconds, "warmup_s": warmup,
+            "requests": len(lat), "completed_per_s": len(lat) / wall,
+            "p50_ms": float(np.percentile(lat, 50) * 1e3),
+            "p99_ms": float(np.percentile(lat, 99) * 1e3),
+            "p50_parts_ms": {"queue": float(pq[0]), "upload": float(pq[1]), "gpu": float(pq[2])},
+            "p99_parts_ms": {"queue": float(pq99[0]), "upload": float(pq99[1]),
+                             "gpu": float(pq99[2])},
+            "mean_batch": (after["completed"] - before["completed"])
+            / max(1, after["batches"] - before["batches"]),
+            "rejected": after["rejected"] - before["rejected"],
+            "quality_pass": float(np.mean(quality)) if quality else None}
+
+
+def systems(dev, torch, steps: int, warmup: int, check: bool = False,
+            serve_seconds: float = 10.0, serve_warmup: float = 1.0) -> dict:
+    """Single-frame FP32 against batched FP32, batched FP16 and served FP16 on
+    the same GPU.
 
     The RF is the 11-angle frame quantised to 10-bit int16, which FP16 holds
     exactly, so every form computes on identical sample values (equal accuracy
     by construction; the batched planes are checked against the single-frame
     ones). Batched: B frames of the workload (the frame rolled along samples so
-    each is distinct) in one graph-captured persistent launch. Served: four
-    probes (1 angle 64 ch 256x512; 5 angles 128 ch 512x512; the 11-angle
-    1024x1024 workload; DMAS 64 ch 512x512) under Poisson arrivals, int16 RF
-    uploaded from pinned host memory per request; latency = done - arrival.
+    each is distinct) in one graph launch, FP32- and FP16-stored (the FP32
+    batch isolates what the storage type contributes). Served: four probes
+    (1 angle 64 ch 256x512; 5 angles 128 ch 512x512; the 11-angle 1024x1024
+    workload, with a quality check of its first cyst on every frame; DMAS 64 ch
+    512x512) under Poisson arrivals at 500, 1000, 2000, 3500 and 5000 frames/s,
+    each a measured window after a warm-up, int16 RF uploaded from pinned host
+    memory per request; latency = done - arrival.
     """
-    from paper_2311_00482_amd import (Batch, FrameSpec, GeometryArg, ProbeSpec, PwbfError,
-                                      Server, beamform)
+    import oracle
+    from paper_2311_00482_amd import Batch, FrameSpec, GeometryArg, ProbeSpec, Server, beamform
     from synth import config_c3, config_c5_probes, make_frame
+    from synth.phantom import cyst_regions
 
     gs = config_c3()
     g = GeometryArg(gs)
@@ -472,83 +695,79 @@ def systems(dev, torch, steps: int, warmup: int) -> dict:
     res = {"single_frame_f32": {"frames_per_s": steps / wall32,
                                 "p50_ms": float(np.percentile(lat32, 50)),
                                 "p99_ms": float(np.percentile(lat32, 99))}}
+    del rf32
 
     B = 8
-    frames = [FrameSpec(g, torch.roll(i16, 17 * k, dims=2).to(torch.float16).to(dev), "das", -1,
-                        planes()) for k in range(B)]
-    batch = Batch(frames)
     nb = max(10, steps // B)
-    wallb, latb, _ = time_steps(batch.launch, nb, max(2, warmup // B), torch)
-    dev_max = max(float((frames[0].out[k] - out32[k]).abs().max()
-                        / out32[k].abs().max().clamp_min(1e-30)) for k in ("rf", "env"))
-    res["batched_f16"] = {"frames_per_launch": B, "frames_per_s": B * nb / wallb,
-                          "ms_per_launch": float(np.percentile(latb, 50)),
-                          "max_rel_diff_vs_single_f32": dev_max}
-    batch.close()
-    del frames
+    for name, dt in (("batched_f32", torch.float32), ("batched_f16", torch.float16)):
+        frames = [FrameSpec(g, torch.roll(i16, 17 * k, dims=2).to(dt).to(dev), "das", -1,
+                            planes()) for k in range(B)]
+        batch = Batch(frames)
+        wallb, latb, _ = time_steps(batch.launch, nb, max(2, warmup // B), torch)
+        dev_max = max(float((frames[0].out[k] - out32[k]).abs().max()
+                            / out32[k].abs().max().clamp_min(1e-30)) for k in ("rf", "env"))
+        res[name] = {"frames_per_launch": B, "frames_per_s": B * nb / wallb,
+                     "ms_per_launch": float(np.percentile(latb, 50)),
+                     "max_rel_diff_vs_single_f32": dev_max}
+        batch.close()
+        del frames
+    res["f16_storage_gain_batched"] = (res["batched_f16"]["frames_per_s"]
+                                       / res["batched_f32"]["frames_per_s"])
 
-    res["uneven_batch_32"] = uneven_batch(dev, torch, steps, warmup)
+    res["uneven_batch_32"] = uneven_batch(dev, torch, steps, warmup, check=check)
+    ub = res["uneven_batch_32"]
+    print(f"[bench] uneven batch: {ub['batched']['ms_per_launch']:.3f} ms per launch, "
+          f"frac {ub['roofline']['frac']:.2f}", file=sys.stderr, flush=True)
 
     specs = config_c5_probes()
-    hosts = []
+    hosts, phantoms = [], []
     for k, sp in enumerate(specs):
         kind = "c3" if sp.geom.name == "probe_c" else "scaled"
-        hosts.append(torch.from_numpy(make_frame(sp.geom, sp.seed, kind, quantize=True)["i16"])
-                     .pin_memory())
-    srv = Server([ProbeSpec(sp.geom, sp.mode, -1, want, 8, bandpass=(sp.mode == "dmas"))
-                  for sp in specs])
+        f = make_frame(sp.geom, sp.seed, kind, quantize=True)
+        hosts.append(torch.from_numpy(f["i16"]).pin_memory())
+        phantoms.append(f["phantom"])
+    probe_specs = []
+    for sp, ph in zip(specs, phantoms):
+        region = cyst_regions(sp.geom, ph)[0] if sp.geom.name == "probe_c" else None
+        probe_specs.append(ProbeSpec(sp.geom, sp.mode, -1, want, 8,
+                                     bandpass=(sp.mode == "dmas"), quality_region=region,
+                                     quality_max_cr_db=-10.0))
+    srv = Server(probe_specs)
     rng = np.random.default_rng(42)
+    kept = {}
+
+    def keep(r, s):  # the first result of each probe, for the accuracy check
+        if check and r.status == 0 and r.probe not in kept:
+            kept[r.probe] = {k: v.cpu().numpy() for k, v in s.planes(r).items()}
+
     served = []
     try:
-        for rate in (500.0, 2000.0, 5000.0):
-            n = int(rate * 1.0)
-            arrivals = np.cumsum(rng.exponential(1.0 / rate, n))
-            which = rng.integers(0, len(specs), n)
-            before = srv.stats()
-            t0 = srv.now() + 0.01
-            lat, parts, k, accepted = [], [], 0, 0
-            deadline = time.time() + 60
-            while k < n or len(lat) < accepted:
-                if time.time() > deadline:
-                    raise RuntimeError(f"serving run at {rate}/s did not drain")
-                now = srv.now()
-                while k < n and t0 + arrivals[k] <= now:
-                    try:
-                        srv.submit(int(which[k]), hosts[which[k]], t0 + arrivals[k])
-                        accepted += 1
-                    except PwbfError as e:  # a full probe queue drops the request
-                        if e.code != -5:
-                            raise
-                    k += 1
-                got = srv.poll(64, wait_ms=0 if k < n else 5)
-                for r in got:
-                    lat.append(r.t_done - r.t_arrival)
-                    parts.append((r.t_admit - r.t_arrival, r.t_launch - r.t_admit,
-                                  r.t_done - r.t_launch))
-                    srv.release(r.id)
-                if not got and k < n:  # sleep only when the next arrival is far off
-                    gap = t0 + arrivals[k] - srv.now()
-                    if gap > 3e-3:  # host sleeps can overshoot by a millisecond or more
-                        time.sleep(gap - 2e-3)
-            wall = srv.now() - t0
-            pq = np.percentile(np.array(parts) * 1e3, 50, axis=0)
-            pq99 = np.percentile(np.array(parts) * 1e3, 99, axis=0)
-            after = srv.stats()
-            served.append({"offered_per_s": rate, "requests": n,
-                           "completed_per_s": len(lat) / wall,
-                           "p50_ms": float(np.percentile(lat, 50) * 1e3),
-                           "p99_ms": float(np.percentile(lat, 99) * 1e3),
-                           "p50_parts_ms": {"queue": float(pq[0]), "upload": float(pq[1]),
-                                            "gpu": float(pq[2])},
-                           "p99_parts_ms": {"queue": float(pq99[0]), "upload": float(pq99[1]),
-                                            "gpu": float(pq99[2])},
-                           "mean_batch": (after["completed"] - before["completed"])
-                           / max(1, after["batches"] - before["batches"]),
-                           "rejected": after["rejected"] - before["rejected"]})
+        for rate in (500.0, 1000.0, 2000.0, 3500.0, 5000.0):
+            served.append(_serve_rate(srv, hosts, len(specs), rate, serve_seconds,
+                                      serve_warmup, rng, keep))
             print(f"[bench] served {rate:.0f}/s: {served[-1]}", file=sys.stderr, flush=True)
     finally:
         srv.close()
-    res["served_f16"] = {"probes": [sp.geom.name for sp in specs], "runs": served}
+    res["served_f16"] = {"probes": [sp.geom.name for sp in specs], "runs": served,
+                         "quality_check": "probe_c: frame maximum > 0 and CR of its first "
+                                          "cyst <= -10 dB, per request"}
+    if check:
+        err = {}
+        for i, sp in enumerate(specs):
+            if i not in kept:
+                continue
+            host = hosts[i].numpy()
+            whole = sp.geom.nx * sp.geom.nz <= 512 * 512
+            cols, pix = _columns(sp.geom, sp.geom.nx if whole else 64)
+            if sp.mode == "dmas":
+                ref = oracle.dmas(sp.geom, host, -1, "identity", pix, parallel=True)
+            else:
+                ref = oracle.das(sp.geom, host, -1, pix, parallel=True)
+            err[sp.geom.name] = _max_norm(kept[i]["rf"][cols], ref.reshape(len(cols),
+                                                                          sp.geom.nz))
+        res["served_f16"]["error_vs_oracle"] = {
+            "rf": err, "sample": "whole image (64 depth columns for 1024 x 1024)",
+            "rf_storage": "int16 uploaded, FP16 on the device"}
     return res
 
 
@@ -568,9 +787,14 @@ def main():
                          "takes the compound workload with --profile-compound)")
     ap.add_argument("--profile-compound", action="store_true")
     ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-budget", type=float, default=15.0,
-                    help="seconds of oracle work for the CPU baseline sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true",
+                    help="skip the oracle: no CPU baseline and no accuracy figures")
+    ap.add_argument("--serve-seconds", type=float, default=10.0,
+                    help="measured seconds per arrival rate of the serving run")
+    ap.add_argument("--serve-warmup", type=float, default=1.0,
+                    help="seconds of arrivals before each measured serving window")
+    ap.add_argument("--cpu-budget", type=float, default=8.0,
+                    help="seconds of oracle work per CPU baseline leg")
     ap.add_argument("--profile-only", action="store_true",
                     help="run only the timed FP32 compound loop (for rocprofv3)")
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -739,15 +963,34 @@ def main():
     line["image_metrics"] = image_metrics(dev, torch, g, gs, fr["phantom"], outs["env"], env16)
     if not args.no_modes:
         print("[bench] DMAS and pDAS", file=sys.stderr, flush=True)
-        line["modes"] = other_modes(dev, torch, args.steps, args.warmup)
+        line["modes"] = other_modes(dev, torch, args.steps, args.warmup,
+                                    check=not args.no_cpu_baseline)
     if not args.no_systems:
         print("[bench] batched and served FP16 vs single-frame FP32", file=sys.stderr, flush=True)
-        line["systems"] = systems(dev, torch, args.steps, args.warmup)
+        line["systems"] = systems(dev, torch, args.steps, args.warmup,
+                                  check=not args.no_cpu_baseline,
+                                  serve_seconds=args.serve_seconds,
+                                  serve_warmup=args.serve_warmup)
     if not args.no_cpu_baseline:
         print("[bench] timing the oracle on the host", file=sys.stderr, flush=True)
-        cb = cpu_baseline(gs, fr["master"], args.cpu_budget)
-        cb["host_cores_available"] = os.cpu_count()
+        cb, sample = cpu_baseline(gs, fr["master"], args.cpu_budget)
         line["cpu_baseline"] = cb
+        print("[bench] accuracy against the oracle", file=sys.stderr, flush=True)
+        step32()
+        gpu32 = {k: v.cpu().numpy() for k, v in outs.items()}
+        step16()
+        gpu16 = {k: v.cpu().numpy() for k, v in outs.items()}
+        err = error_vs_oracle(gs, fr, sample, gpu32, gpu16)
+        err["single_frame_64ch_128x256"] = c1_error(dev, torch)
+        for name, rec in line.get("modes", {}).items():
+            if "error_vs_oracle" in rec:
+                err[name] = rec["error_vs_oracle"]
+        sysrec = line.get("systems", {})
+        if "error_vs_oracle" in sysrec.get("uneven_batch_32", {}):
+            err["uneven_batch_32"] = sysrec["uneven_batch_32"]["error_vs_oracle"]
+        if "error_vs_oracle" in sysrec.get("served_f16", {}):
+            err["served_f16"] = sysrec["served_f16"]["error_vs_oracle"]
+        line["error_vs_oracle"] = err
     print(json.dumps(line))
 
 

@@ -93,8 +93,15 @@ def _load(parallel: bool = False):
         lib.ora_pdas.restype = ctypes.c_int
         lib.ora_pdas.argtypes = [P, ctypes.c_void_p, ctypes.c_int32, ctypes.c_double,
                                  ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]
+        lib.ora_threads.restype = ctypes.c_int
+        lib.ora_threads.argtypes = []
         _libs[key] = lib
     return _libs[key]
+
+
+def threads(parallel: bool = True) -> int:
+    """Threads the (parallel or single-threaded) build shares a call among."""
+    return int(_load(parallel).ora_threads())
 
 
 class _Bound:

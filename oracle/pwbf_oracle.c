@@ -55,6 +55,9 @@
 #include <math.h>
 #include <stddef.h>
 #include <stdint.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 typedef struct {
   int32_t n_angles, n_channels, n_samples;
@@ -69,6 +72,16 @@ typedef struct {
 } ora_geom;
 
 enum { ORA_OK = 0, ORA_BAD = -1 };
+
+/* Threads a call of this build shares its pixel loop among (1 unless built
+ * with -fopenmp). */
+int ora_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
 
 /* Every requested flat pixel index lies in [0, total). */
 static int check_pixels(const int64_t *pix, int64_t npix, int64_t total) {

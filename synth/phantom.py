@@ -126,6 +126,30 @@ def phantom_c3(g: Geometry, rng: np.random.Generator, n_points: int = 20, n_cyst
                    points=np.stack([xp, zp], 1), cysts=cysts)
 
 
+def cyst_regions(g: Geometry, ph: Phantom, inside: float = 0.8, offset: float = 2.2):
+    """The contrast regions of each cyst (Section II-D): the inside disc of
+    radius inside * r at the cyst's centre, and a background disc of the same
+    radius offset * r away, on whichever of the four sides (left, right, above,
+    below) that stays on the grid and clear of every cyst lies farthest from the
+    point targets. Returns [((x, z, r_in), (x, z, r_in)), ...] in metres."""
+    out = []
+    pts = np.asarray(ph.points, dtype=np.float64).reshape(-1, 2)
+    for cx, cz, r in ph.cysts:
+        best = None
+        for ox, oz in ((-1, 0), (1, 0), (0, -1), (0, 1)):
+            bx, bz = cx + ox * offset * r, cz + oz * offset * r
+            if not (g.x_min + r < bx < g.x_max - r and g.z_min + r < bz < g.z_max - r):
+                continue
+            if any(math.hypot(bx - ax, bz - az) < ar + inside * r for ax, az, ar in ph.cysts):
+                continue
+            clear = (float(np.hypot(pts[:, 0] - bx, pts[:, 1] - bz).min()) if len(pts)
+                     else math.inf) - inside * r
+            if best is None or clear > best[0]:
+                best = (clear, bx, bz)
+        out.append(((cx, cz, inside * r), (best[1], best[2], inside * r)))
+    return out
+
+
 def echo_times(g: Geometry, angle_index: int, xs: np.ndarray, zs: np.ndarray,
                elem: Optional[np.ndarray] = None) -> np.ndarray:
     """Arrival time (s, relative to the time of sample 0) of each scatterer's echo

@@ -56,19 +56,8 @@ def _contrast_matches(g, env, cyst, got):
 
 
 def _regions(g, ph):
-    # background disc beside each cyst, on the side farther from the point
-    # targets (left, right, above or below); the inside disc is 0.8 r
-    cysts = []
-    pts = np.asarray(ph.points)
-    for cx, cz, r in ph.cysts:
-        best = None
-        for ox, oz in ((-1, 0), (1, 0), (0, -1), (0, 1)):
-            bx, bz = cx + ox * 2.2 * r, cz + oz * 2.2 * r
-            if not (g.x_min + r < bx < g.x_max - r and g.z_min + r < bz < g.z_max - r):
-                continue
-            clear = float(np.hypot(pts[:, 0] - bx, pts[:, 1] - bz).min()) - 0.8 * r
-            if best is None or clear > best[0]:
-                best = (clear, bx, bz)
-        cysts.append(((cx, cz, 0.8 * r), (best[1], best[2], 0.8 * r)))
+    """Each cyst's inside and background discs, and a 1 mm disc around each
+    point target."""
+    from synth.phantom import cyst_regions
     targets = [(float(x), float(z), 1.0e-3) for x, z in ph.points]
-    return cysts, targets
+    return cyst_regions(g, ph), targets
