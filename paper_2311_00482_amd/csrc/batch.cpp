@@ -413,17 +413,29 @@ int pwbf_batch_create(const pwbf_frame *frames, int32_t n, int32_t flags, void *
   if (e == hipSuccess) {
     hipError_t le = pwbf::launch_batch_reset(b->d_post, n, b->cap);
     if (le == hipSuccess) le = hipEventRecord(b->fork_events[n_br], b->cap);
+    std::vector<int> steps(n_br);
+    int max_steps = 0;
     for (int k = 0; k < n_br && le == hipSuccess; ++k) {
       const pwbf_batch::Branch &br = b->branches[k];
-      hipStream_t st = b->fork_streams[k];
-      le = hipStreamWaitEvent(st, b->fork_events[n_br], 0);
-      if (le == hipSuccess)
-        le = pwbf::launch_batch_branch(b->d_plans, b->d_post, b->d_items,
-                                       b->classes.data() + br.class_first, br.class_n,
-                                       b->d_post_cols + br.post_first, br.post_n,
-                                       b->d_log_cols + br.log_first, br.log_n, b->lds, b->max_nz,
-                                       st);
-      if (le == hipSuccess) le = hipEventRecord(b->fork_events[k], st);
+      steps[k] = pwbf::batch_branch_steps(br.class_n, br.post_n, br.log_n);
+      max_steps = std::max(max_steps, steps[k]);
+      le = hipStreamWaitEvent(b->fork_streams[k], b->fork_events[n_br], 0);
+    }
+    // the launches are captured round robin over the branches (step 0 of each,
+    // then step 1, ...): the graph enqueues its nodes in about that order, so
+    // every branch starts at once instead of after the others' launches
+    for (int step = 0; step < max_steps && le == hipSuccess; ++step)
+      for (int k = 0; k < n_br && le == hipSuccess; ++k) {
+        if (step >= steps[k]) continue;
+        const pwbf_batch::Branch &br = b->branches[k];
+        le = pwbf::launch_batch_branch_step(b->d_plans, b->d_post, b->d_items,
+                                            b->classes.data() + br.class_first, br.class_n,
+                                            b->d_post_cols + br.post_first, br.post_n,
+                                            b->d_log_cols + br.log_first, br.log_n, b->lds,
+                                            b->max_nz, step, b->fork_streams[k]);
+      }
+    for (int k = 0; k < n_br && le == hipSuccess; ++k) {
+      le = hipEventRecord(b->fork_events[k], b->fork_streams[k]);
       if (le == hipSuccess) le = hipStreamWaitEvent(b->cap, b->fork_events[k], 0);
     }
     e = hipStreamEndCapture(b->cap, &b->graph);

@@ -115,36 +115,38 @@ hipError_t launch_batch_reset(const PostPlan *post, int n_frames, hipStream_t st
 }
 
 // Enqueue one branch on `stream` (captured into the batch graph by the caller).
-hipError_t launch_batch_branch(const FramePlan *plans, const PostPlan *post, const int2 *items,
-                               const BatchClass *classes, int n_classes, const int2 *post_cols,
-                               int n_post_cols, const int2 *log_cols, int n_log_cols, size_t lds,
-                               int max_nz, hipStream_t stream) {
-  hipError_t e = hipSuccess;
-  for (int c = 0; c < n_classes; ++c) {
-    const BatchClass &k = classes[c];
+int batch_branch_steps(int n_classes, int n_post_cols, int n_log_cols) {
+  return n_classes + (n_post_cols > 0 ? 1 : 0) + (n_log_cols > 0 ? 1 : 0);
+}
+
+hipError_t launch_batch_branch_step(const FramePlan *plans, const PostPlan *post,
+                                    const int2 *items, const BatchClass *classes, int n_classes,
+                                    const int2 *post_cols, int n_post_cols, const int2 *log_cols,
+                                    int n_log_cols, size_t lds, int max_nz, int step,
+                                    hipStream_t stream) {
+  if (step < n_classes) {
+    const BatchClass &k = classes[step];
     switch (k.cls) {
-#define PWBF_LAUNCH(C)                                                                    \
-  case C:                                                                                 \
-    e = launch_class_kernel<C>(dim3(k.n), lds, stream, plans, items + k.first);           \
-    break;
+#define PWBF_LAUNCH(C) \
+  case C:              \
+    return launch_class_kernel<C>(dim3(k.n), lds, stream, plans, items + k.first);
       PWBF_BATCH_CLASSES(PWBF_LAUNCH)
 #undef PWBF_LAUNCH
-      default: e = hipErrorInvalidValue; break;
+      default: return hipErrorInvalidValue;
     }
-    if (e != hipSuccess) return e;
   }
-  if (n_post_cols > 0) {
+  step -= n_classes;
+  if (n_post_cols > 0 && step-- == 0) {
     const size_t plds = dev::post_lds_bytes(max_nz);
     hipLaunchKernelGGL(k_batch_postz, dim3(n_post_cols), dim3(dev::kPostThreads), plds, stream,
                        post, post_cols);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    return hipGetLastError();
   }
-  if (n_log_cols > 0) {
+  if (n_log_cols > 0 && step == 0) {
     hipLaunchKernelGGL(k_batch_logc, dim3(n_log_cols), dim3(256), 0, stream, post, log_cols);
-    e = hipGetLastError();
+    return hipGetLastError();
   }
-  return e;
+  return hipErrorInvalidValue;
 }
 
 }  // namespace pwbf

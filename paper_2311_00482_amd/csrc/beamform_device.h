@@ -540,7 +540,7 @@ __device__ __forceinline__ void process_tile_body(const FramePlan &P, int tz, in
     __syncthreads();
 
     const int wstride = win * P.entry_bytes;  // bytes between angle windows
-    for (int k = 0; k < cnt; k += cpw) {
+    auto channel = [&](int k) __attribute__((always_inline)) {
       const int c = ONEGRP ? k : k + grp;
       const int slot = wave * chunk + c;
       const float4 ch = WREF ? s_chw[slot] : s_ch[c];
@@ -647,6 +647,20 @@ __device__ __forceinline__ void process_tile_body(const FramePlan &P, int tz, in
         }
         Q = fmaf(w * w, q, Q);
       }
+    };
+    // One or two exact angles: two channels per iteration, so that the second
+    // channel's table and window reads are in flight while the first computes
+    // (one channel is a chain of two dependent LDS round trips, and a small
+    // grid leaves few wavefronts per SIMD to hide them)
+    if constexpr (AM <= 2 && !PRED) {
+      int k = 0;
+      for (; k + cpw < cnt; k += 2 * cpw) {
+        channel(k);
+        channel(k + cpw);
+      }
+      if (k < cnt) channel(k);
+    } else {
+      for (int k = 0; k < cnt; k += cpw) channel(k);
     }
   }
 
