@@ -432,7 +432,8 @@ def iq_modes(dev, torch, steps: int, warmup: int) -> dict:
     """The IQ path on the 11-angle compound workload (FP32 RF): the demodulation
     kernel (HBM-bound: reads the RF once, writes 8-byte complex samples), and
     IQ-DAS / BB-DMAS from the demodulated records (kernel time, roofline, and the
-    frame rate of demodulation + beamforming + log)."""
+    frame rate of demodulation + beamforming + log), and IQ-DAS from records
+    decimated by 2 (the same algorithmic operations on half the samples)."""
     from paper_2311_00482_amd import GeometryArg, beamform, iq_demodulate
     from synth import config_c3, make_frame
 
@@ -455,16 +456,19 @@ def iq_modes(dev, torch, steps: int, warmup: int) -> dict:
     outs = {k: torch.empty((g.nx, g.nz), dtype=torch.float32, device=dev) for k in want}
     ws = torch.empty(WS_BYTES, dtype=torch.uint8, device=dev)
     rf_only = {"rf": outs["rf"], "imag": outs["imag"]}
-    for mode in ("iqdas", "bbdmas"):
+    g2 = GeometryArg(gs, iq_decimation=2)
+    iq2 = iq_demodulate(g2, rf)
+    for mode, gg, q, tag in (("iqdas", g, iq, ""), ("bbdmas", g, iq, ""),
+                             ("iqdas", g2, iq2, "_decim2")):
         def frame():
-            iq_demodulate(g, rf, out=iq)
-            beamform(g, iq, mode, -1, want=want, out=outs, workspace=ws)
+            iq_demodulate(gg, rf, out=q)
+            beamform(gg, q, mode, -1, want=want, out=outs, workspace=ws)
         wall, lat, _ = time_steps(frame, n, w, torch)
-        _, klat, _ = time_steps(lambda: beamform(g, iq, mode, -1, want=("rf", "imag"),
+        _, klat, _ = time_steps(lambda: beamform(gg, q, mode, -1, want=("rf", "imag"),
                                                  out=rf_only), n, w, torch)
         k_ms = float(np.mean(klat))
         ops = algorithmic_ops(gs, mode)
-        name = f"{mode}_compound_11a_1024x1024"
+        name = f"{mode}{tag}_compound_11a_1024x1024"
         res[name] = {"frames_per_s": n / wall, "p50_ms": float(np.percentile(lat, 50)),
                      "p99_ms": float(np.percentile(lat, 99)), "kernel_ms": k_ms,
                      "value": gs.gathers / (k_ms * 1e-3) / 1e9, "unit": UNIT,
@@ -472,7 +476,7 @@ def iq_modes(dev, torch, steps: int, warmup: int) -> dict:
                                   "peak": VALU_LANE_OPS_PEAK / 1e12, "unit": "Tlane-op/s",
                                   "frac": ops / (k_ms * 1e-3) / VALU_LANE_OPS_PEAK,
                                   "ops_per_launch": ops},
-                     "rf_storage": "f32 -> complex64 IQ"}
+                     "rf_storage": "f32 -> complex64 IQ" + (", decimated by 2" if tag else "")}
         print(f"[bench] {name}: {k_ms:.3f} ms kernel, frac {res[name]['roofline']['frac']:.2f}",
               file=sys.stderr, flush=True)
     return res

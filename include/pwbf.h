@@ -60,7 +60,7 @@
 extern "C" {
 #endif
 
-#define PWBF_ABI_VERSION 5u
+#define PWBF_ABI_VERSION 6u
 
 #ifndef PWBF_API
 #define PWBF_API __attribute__((visibility("default")))
@@ -131,6 +131,9 @@ typedef struct pwbf_geometry {
                                the envelope (needs dz <= c / (12 f0)); 0: none */
   double log_floor_db;      /* floor of the log image, dB, < 0 (e.g. -70) */
   double pdas_p;            /* root order p of pDAS, 1 .. 2 (PWBF_PDAS only; else ignored) */
+  int32_t iq_decimation;    /* baseband records keep every D-th sample: 0 or 1 (none), 2, 4
+                               or 8; n_samples divisible by D (IQ calls only; else ignored) */
+  int32_t reserved;         /* 0 */
 } pwbf_geometry;
 
 /* Output planes, each a device float32 [nx][nz] buffer owned by the caller.
@@ -205,20 +208,25 @@ PWBF_API int pwbf_beamform_pdas(const pwbf_geometry *g, const void *rf, int32_t 
                                 int32_t angle, const pwbf_outputs *out, void *workspace,
                                 size_t workspace_bytes, void *stream);
 
-/* Baseband (IQ) channel data: for every record RF[a][e][:], the analytic signal
- * (one-sided spectrum along samples: 1 at DC and Nyquist, 2 on positive bins, 0
- * on negative ones) times exp(-2 pi i f0 n / fs), sample n of the record; the
- * demodulation of the IQ path of Section II-B, read without decimation.
+/* Baseband (IQ) channel data, the demodulation and decimation of the IQ path
+ * of Section II-B: for every record RF[a][e][:], the analytic signal (one-sided
+ * spectrum along samples: 1 at DC and Nyquist, 2 on positive bins, 0 on
+ * negative ones) times exp(-2 pi i f0 n / fs), sample n of the record. With
+ * g->iq_decimation = D > 1 the analytic spectrum first keeps only the positive
+ * bins within fs / (2 D) of f0 (an ideal low-pass of the baseband signal to the
+ * decimated rate's band), and the record keeps samples n = 0, D, 2D, ...
  *  rf   device RF[n_angles][n_channels][n_samples] of rf_dtype (int16, FP16, FP32)
- *  iq   device complex float32 [n_angles][n_channels][n_samples] (8 bytes per
- *       sample, re then im), owned by the caller, 8-byte aligned; overwritten
+ *  iq   device complex float32 [n_angles][n_channels][n_samples / D] (8 bytes
+ *       per sample, re then im), owned by the caller, 8-byte aligned; overwritten
  * Needs n_samples a power of two in 2..4096 and f0 > 0 (PWBF_E_UNSUPPORTED /
- * PWBF_E_INVALID). No workspace; enqueued on stream. */
+ * PWBF_E_INVALID). No workspace; enqueued on stream. The IQ beamformers read
+ * such records with the same geometry (D included). */
 PWBF_API int pwbf_iq_demodulate(const pwbf_geometry *g, const void *rf, int32_t rf_dtype,
                                 void *iq, void *stream);
 
 /* DAS on IQ data for one angle: with q_e the baseband record of element e
- * interpolated linearly at the delay s_e and rotated back by exp(2 pi i f0 s_e / fs),
+ * interpolated linearly at the delay s_e and rotated back by exp(2 pi i f0 s_e / fs)
+ * (a record decimated by D is read at s_e / D, its own sample rate),
  * y = sum_e w_e q_e (Eq. (1) on the delay-compensated IQ signals). iq from
  * pwbf_iq_demodulate (rf_dtype PWBF_C32). Outputs: rf = Re y, imag = Im y,
  * env = |y|, logimg from env; bandpass must be 0 and filtered NULL. */

@@ -107,14 +107,16 @@ def threads(parallel: bool = True) -> int:
 class _Bound:
     """A ctypes geometry plus the arrays it points into (kept alive together)."""
 
-    def __init__(self, g):
+    def __init__(self, g, decimation: int = 1):
+        # records decimated by D are records at the rate fs / D, n_samples / D long
         self.elem_x = np.ascontiguousarray(g.elem_x, dtype=np.float64)
         self.angle = np.ascontiguousarray(g.angles_rad, dtype=np.float64)
         self.t0 = np.ascontiguousarray(g.t0_s, dtype=np.float64)
-        self.s = _Geom(len(self.angle), len(self.elem_x), int(g.n_samples),
+        self.s = _Geom(len(self.angle), len(self.elem_x), int(g.n_samples) // decimation,
                        self.elem_x.ctypes.data, self.angle.ctypes.data, self.t0.ctypes.data,
-                       float(g.c), float(g.fs), int(g.nx), int(g.nz), float(g.x0), float(g.dx),
-                       float(g.z0), float(g.dz), float(g.f_number), int(g.apod_code))
+                       float(g.c), float(g.fs) / decimation, int(g.nx), int(g.nz), float(g.x0),
+                       float(g.dx), float(g.z0), float(g.dz), float(g.f_number),
+                       int(g.apod_code))
 
     @property
     def ref(self):
@@ -199,34 +201,51 @@ def pdas(g, rf, angle: int = -1, p: float = 2.0, pix=None,
     return out.reshape(g.nx, g.nz) if q is None else out
 
 
-def iq_demodulate(g, rf, fd: Optional[float] = None) -> np.ndarray:
-    """Baseband (IQ) channel records: the analytic signal of each record (one-sided
-    spectrum along samples: 1 at DC and Nyquist, 2 on positive bins, 0 on
-    negative ones) times exp(-2 pi i fd n / fs), fd = f0 by default; complex128
-    [n_angles][n_channels][n_samples]. n_samples must be even."""
+def band_keep(ns: int, fs: float, fd: float, decimation: int) -> np.ndarray:
+    """Boolean [ns]: the DFT bins the decimating demodulation keeps, the positive
+    bins (0..ns/2) whose frequency k fs / ns lies within fs / (2 D) of fd; every
+    bin when D = 1."""
+    if decimation <= 1:
+        return np.ones(ns, dtype=bool)
+    k = np.arange(ns)
+    return (k <= ns // 2) & (np.abs(k * fs / ns - fd) < fs / (2.0 * decimation))
+
+
+def iq_demodulate(g, rf, fd: Optional[float] = None, decimation: int = 1) -> np.ndarray:
+    """Baseband (IQ) channel records (Section II-B's IQ signals; the paper does
+    not give the demodulation, its filter or the decimation, so this is a
+    reading): the analytic signal of each record (one-sided spectrum along
+    samples: 1 at DC and Nyquist, 2 on positive bins, 0 on negative ones) times
+    exp(-2 pi i fd n / fs), fd = f0 by default. Decimation by D keeps, before the
+    inverse transform, only the bins of ``band_keep`` (an ideal low-pass of the
+    baseband signal to the band of the rate fs / D), then every D-th sample.
+    Returns complex128 [n_angles][n_channels][n_samples / D]; n_samples even."""
     rf = _rf64(g, rf)
     ns = rf.shape[-1]
-    assert ns % 2 == 0
+    assert ns % 2 == 0 and ns % decimation == 0
     fd = float(g.f0 if fd is None else fd)
     h = np.zeros(ns)
     h[0] = 1.0
     h[1:ns // 2] = 2.0
     h[ns // 2] = 1.0
+    h = h * band_keep(ns, float(g.fs), fd, decimation)
     analytic = np.fft.ifft(np.fft.fft(rf, axis=-1) * h, axis=-1)
     n = np.arange(ns)
-    return analytic * np.exp(-2j * np.pi * fd * n / g.fs)
+    return (analytic * np.exp(-2j * np.pi * fd * n / g.fs))[..., ::decimation]
 
 
 def iq_beamform(g, iq, form: str = "iqdas", angle: int = -1, fd: Optional[float] = None,
-                pix=None, parallel: bool = False) -> np.ndarray:
+                pix=None, parallel: bool = False, decimation: int = 1) -> np.ndarray:
     """IQ-DAS ("iqdas") or BB-DMAS ("bbdmas", Eq. 4) from baseband records ``iq``
     demodulated at fd (f0 by default); complex, [nx, nz] or at ``pix``. angle -1
-    sums the complex per-angle values."""
-    b = _Bound(g)
+    sums the complex per-angle values. Records decimated by D are read at their
+    own rate: the delay of s samples at fs is s / D samples of the record, and
+    the phase rotation uses the same time."""
+    b = _Bound(g, decimation)
     iq = np.asarray(iq)
     if iq.ndim == 2:
         iq = iq[None]
-    assert iq.shape == (len(g.angles_rad), len(g.elem_x), g.n_samples), iq.shape
+    assert iq.shape == (len(g.angles_rad), len(g.elem_x), g.n_samples // decimation), iq.shape
     re = np.ascontiguousarray(iq.real, dtype=np.float64)
     im = np.ascontiguousarray(iq.imag, dtype=np.float64)
     q = _pix(g, pix)

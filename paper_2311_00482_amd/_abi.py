@@ -12,7 +12,7 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpwbf.so")
 
-ABI_VERSION = 5
+ABI_VERSION = 6
 OK, E_INVALID, E_UNSUPPORTED, E_NOMEM, E_DEVICE, E_BUSY, E_TIMEOUT = 0, -1, -2, -3, -4, -5, -6
 FK_STOLT, FK_LU = 0, 1
 I16, F16, F32, C32 = 0, 1, 2, 3
@@ -48,6 +48,7 @@ class Geometry(ctypes.Structure):
         ("apod", ctypes.c_int32),
         ("bandpass", ctypes.c_int32),
         ("log_floor_db", ctypes.c_double), ("pdas_p", ctypes.c_double),
+        ("iq_decimation", ctypes.c_int32), ("reserved", ctypes.c_int32),
     ]
 
 

@@ -29,11 +29,12 @@ class GeometryArg:
     ``g`` is any object with the attributes elem_x, angles_rad, n_samples, c,
     fs, f0, nx, nz, x0, dx, z0, dz, f_number and apod (name) or apod_code;
     t0_s (per-angle time of sample 0) is optional. ``pdas_p`` is the pDAS root
-    order (used by mode "pdas" only).
+    order (used by mode "pdas" only); ``iq_decimation`` the decimation of
+    baseband records (IQ demodulation and the IQ beamformers only).
     """
 
     def __init__(self, g, bandpass: bool = False, log_floor_db: float = -70.0,
-                 pdas_p: float = 2.0):
+                 pdas_p: float = 2.0, iq_decimation: int = 1):
         self.elem_x = np.ascontiguousarray(g.elem_x, dtype=np.float64)
         self.angles = np.ascontiguousarray(g.angles_rad, dtype=np.float64)
         t0 = getattr(g, "t0_s", None)
@@ -48,9 +49,12 @@ class GeometryArg:
             self.t0.ctypes.data_as(dp) if self.t0 is not None else None,
             float(g.c), float(g.fs), float(g.f0), int(g.nx), int(g.nz), float(g.x0),
             float(g.dx), float(g.z0), float(g.dz), float(g.f_number), int(apod),
-            1 if bandpass else 0, float(log_floor_db), float(pdas_p))
+            1 if bandpass else 0, float(log_floor_db), float(pdas_p), int(iq_decimation), 0)
         self.nx, self.nz = int(g.nx), int(g.nz)
         self.shape_rf = (len(self.angles), len(self.elem_x), int(g.n_samples))
+        # baseband records: decimated by iq_decimation along samples
+        self.shape_iq = (len(self.angles), len(self.elem_x),
+                         int(g.n_samples) // max(1, int(iq_decimation)))
 
     @property
     def ref(self):
@@ -137,8 +141,9 @@ def _prepare(g, rf, want, out, workspace, bandpass, log_floor_db, p, workspace_n
         ga.s.pdas_p = float(p)
     if not rf.is_cuda or not rf.is_contiguous():
         raise ValueError("rf must be a contiguous CUDA tensor")
-    if tuple(rf.shape) != ga.shape_rf:
-        raise ValueError(f"rf shape {tuple(rf.shape)} != {ga.shape_rf}")
+    shape = ga.shape_iq if rf.dtype == torch.complex64 else ga.shape_rf
+    if tuple(rf.shape) != shape:
+        raise ValueError(f"rf shape {tuple(rf.shape)} != {shape}")
     want = set(want) | {"rf"}
     unknown = want - set(PLANES)
     if unknown:
@@ -216,16 +221,16 @@ def beamform_dmas(g, rf, angle: int, **kw) -> Dict:
 
 
 def iq_demodulate(g, rf, out=None, stream=None):
-    """pwbf_iq_demodulate: baseband IQ records (complex64 [A, N, Ns]) of the RF,
-    demodulated at the geometry's f0."""
+    """pwbf_iq_demodulate: baseband IQ records (complex64 [A, N, Ns / D]) of the
+    RF, demodulated at the geometry's f0 and decimated by its iq_decimation D."""
     import torch
     ga = _as_geom(g)
     if not rf.is_cuda or not rf.is_contiguous() or tuple(rf.shape) != ga.shape_rf:
         raise ValueError(f"rf must be a contiguous CUDA tensor {ga.shape_rf}")
     if out is None:
-        out = torch.empty(ga.shape_rf, dtype=torch.complex64, device=rf.device)
-    if out.dtype != torch.complex64 or not out.is_contiguous() or tuple(out.shape) != ga.shape_rf:
-        raise ValueError(f"out must be a contiguous complex64 tensor {ga.shape_rf}")
+        out = torch.empty(ga.shape_iq, dtype=torch.complex64, device=rf.device)
+    if out.dtype != torch.complex64 or not out.is_contiguous() or tuple(out.shape) != ga.shape_iq:
+        raise ValueError(f"out must be a contiguous complex64 tensor {ga.shape_iq}")
     _abi.check(_abi.lib().pwbf_iq_demodulate(ga.ref, _ptr(rf), _rf_code(rf), _ptr(out),
                                              _stream_ptr(stream, rf.device)))
     return out

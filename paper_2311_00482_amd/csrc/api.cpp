@@ -1,6 +1,7 @@
 // extern "C" entry points of libpwbf: validation, plan, enqueue.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <string>
 
@@ -13,7 +14,7 @@ hipError_t launch_post(const PostPlan &Q, hipStream_t stream);
 hipError_t launch_logc(const float *env, float *logimg, const uint32_t *ws_max, size_t n,
                        float floor_db, hipStream_t stream);
 hipError_t launch_iq_demod(const void *rf, int dtype, void *iq, int rows, int log2ns, float r_hi,
-                           float r_lo, hipStream_t stream);
+                           float r_lo, int log2d, int k_lo, int k_hi, hipStream_t stream);
 }  // namespace pwbf
 
 namespace {
@@ -162,8 +163,22 @@ int pwbf_iq_demodulate(const pwbf_geometry *g, const void *rf, int32_t rf_dtype,
   while ((1 << log2ns) < ns) ++log2ns;
   float r_hi, r_lo;
   pwbf::split_double(g->f0 / g->fs, &r_hi, &r_lo);
+  // decimation by D: the positive bins whose frequency lies within fs / (2 D)
+  // of the demodulation frequency f0 (a contiguous range, decided in double)
+  const int D = pwbf::iq_decimation(g);
+  int log2d = 0, k_lo = 1, k_hi = 0;
+  while ((1 << log2d) < D) ++log2d;
+  if (D > 1) {
+    k_lo = ns;
+    k_hi = -1;
+    for (int k = 0; k <= ns / 2; ++k)
+      if (std::fabs((double)k * g->fs / ns - g->f0) < g->fs / (2.0 * D)) {
+        k_lo = std::min(k_lo, k);
+        k_hi = std::max(k_hi, k);
+      }
+  }
   hipError_t e = pwbf::launch_iq_demod(rf, rf_dtype, iq, g->n_angles * g->n_channels, log2ns, r_hi,
-                                       r_lo, (hipStream_t)stream);
+                                       r_lo, log2d, k_lo, k_hi, (hipStream_t)stream);
   if (e != hipSuccess)
     return set_error(PWBF_E_DEVICE, std::string("IQ demodulation launch: ") + hipGetErrorString(e));
   return PWBF_OK;

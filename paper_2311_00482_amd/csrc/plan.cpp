@@ -94,6 +94,13 @@ int validate_geometry(const pwbf_geometry *g, std::string *err) {
     return fail(err, PWBF_E_INVALID, "bandpass must be 0 or 1");
   if (!(g->log_floor_db < 0) || !finite(g->log_floor_db))
     return fail(err, PWBF_E_INVALID, "log_floor_db must be < 0");
+  if (g->reserved != 0) return fail(err, PWBF_E_INVALID, "reserved must be 0");
+  if (g->iq_decimation != 0 && g->iq_decimation != 1 && g->iq_decimation != 2 &&
+      g->iq_decimation != 4 && g->iq_decimation != 8)
+    return fail(err, PWBF_E_INVALID, "iq_decimation %d not in {0, 1, 2, 4, 8}", g->iq_decimation);
+  if (g->n_samples % iq_decimation(g) || g->n_samples / iq_decimation(g) < 2)
+    return fail(err, PWBF_E_INVALID, "n_samples %d not a multiple of iq_decimation %d (with "
+                "at least 2 decimated samples)", g->n_samples, g->iq_decimation);
   // float32 delays lose precision far from the origin: bound the largest
   // sample position any pixel can reach.
   double scale = g->fs / g->c;
@@ -264,6 +271,18 @@ static int plan_frame_uncached(const pwbf_geometry *g, int dtype, int mode, int 
                                int waves) {
   int rc = validate_geometry(g, err);
   if (rc) return rc;
+  // Decimated baseband records are records of the decimated rate: sample m of
+  // one is at time t0 + m D / fs, so the IQ beamformers are planned with fs / D
+  // and n_samples / D (delays, windows and the carrier phase per sample all
+  // follow from those)
+  pwbf_geometry gd;
+  if (is_iq_mode(mode) && iq_decimation(g) > 1) {
+    gd = *g;
+    gd.fs = g->fs / iq_decimation(g);
+    gd.n_samples = g->n_samples / iq_decimation(g);
+    gd.iq_decimation = 1;
+    g = &gd;
+  }
   if (dtype != kI16 && dtype != kF16 && dtype != kF32 && dtype != kC32)
     return fail(err, PWBF_E_INVALID, "rf_dtype %d unknown", dtype);
   if (mode < kDas || mode > kBbdmas) return fail(err, PWBF_E_INVALID, "mode %d unknown", mode);

@@ -9,6 +9,10 @@
 namespace pwbf {
 
 size_t dtype_bytes(int dtype);
+// the decimation factor D of baseband records (1 when the field is 0)
+inline int iq_decimation(const pwbf_geometry *g) {
+  return g->iq_decimation > 1 ? g->iq_decimation : 1;
+}
 // v as a float-float pair (hi = v rounded to float, lo = the rest)
 void split_double(double v, float *hi, float *lo);
 int validate_geometry(const pwbf_geometry *g, std::string *err);

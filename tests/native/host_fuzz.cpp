@@ -92,7 +92,7 @@ Geo make_geo(bool mutate) {
   if (mutate) {
     const int n = 1 + pick(3);
     for (int k = 0; k < n; ++k) {
-      switch (pick(22)) {
+      switch (pick(24)) {
         case 0: g.abi_version = (uint32_t)pick(8); break;
         case 1: g.n_angles = hostile_int(g.n_angles); break;
         case 2: g.n_channels = hostile_int(g.n_channels); break;
@@ -115,6 +115,8 @@ Geo make_geo(bool mutate) {
         case 19: if (!G.angle.empty()) G.angle[pick((int)G.angle.size())] = hostile_double(0.2); break;
         case 20: if (!G.t0.empty()) G.t0[pick((int)G.t0.size())] = hostile_double(1e-6); break;
         case 21: t0_null = true; break;
+        case 22: g.iq_decimation = chance(0.5) ? (1 << pick(4)) : hostile_int(2); break;
+        case 23: g.reserved = hostile_int(0); break;
       }
     }
   }

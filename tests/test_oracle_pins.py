@@ -367,6 +367,79 @@ def test_iq_compound_is_sum_of_angles():
                                    atol=1e-12 * np.abs(per).max())
 
 
+# ------------------------------------------------------------ IQ decimation
+def test_decimation_by_one_is_the_full_rate_demodulation():
+    g = small_geom(n_samples=512)
+    rf = _rand_rf(g, 41)
+    assert np.array_equal(oracle.iq_demodulate(g, rf, decimation=1), oracle.iq_demodulate(g, rf))
+
+
+@pytest.mark.parametrize("D", [2, 4, 8])
+def test_decimated_demodulation_of_an_in_band_tone(D):
+    # a tone on bin k within fs / (2 D) of fd (fd off the bin grid): the band
+    # limit keeps it whole, so sample m of the decimated record is the baseband
+    # exponential at the original sample m D
+    g = small_geom(n_samples=512)
+    fd = 0.21 * g.fs
+    k = int(round(fd * g.n_samples / g.fs)) + 3
+    assert abs(k * g.fs / g.n_samples - fd) < g.fs / (2 * D)
+    theta = 0.4
+    q = oracle.iq_demodulate(g, _tone(g, k, theta), fd=fd, decimation=D)
+    assert q.shape[-1] == g.n_samples // D
+    n = np.arange(0, g.n_samples, D)
+    expect = np.exp(1j * (2 * np.pi * (k / g.n_samples - fd / g.fs) * n + theta))
+    np.testing.assert_allclose(q, np.broadcast_to(expect, q.shape), atol=1e-12)
+
+
+@pytest.mark.parametrize("D", [2, 4, 8])
+def test_decimated_demodulation_removes_an_out_of_band_tone(D):
+    g = small_geom(n_samples=512)
+    fd = 0.21 * g.fs
+    k = int(np.ceil((fd + g.fs / (2 * D)) * g.n_samples / g.fs)) + 1  # just past the band
+    q = oracle.iq_demodulate(g, _tone(g, k, 1.3), fd=fd, decimation=D)
+    assert np.abs(q).max() < 1e-12
+    # ... and the bins kept are exactly the positive ones within the band
+    keep = oracle.band_keep(g.n_samples, g.fs, fd, D)
+    f = np.arange(g.n_samples) * g.fs / g.n_samples
+    assert keep.sum() > 0 and np.all(np.abs(f[keep] - fd) < g.fs / (2 * D))
+    assert np.all(np.nonzero(keep)[0] <= g.n_samples // 2)
+
+
+def test_decimated_iq_das_of_a_tone_at_fd_in_closed_form():
+    # a tone at fd has a constant baseband record, decimated or not; the
+    # beamformer reads it at its own rate and rotates by the delay's time, so the
+    # image is the same closed-form phasor sum as at the full rate
+    g = small_geom(angles_deg=(4.0,), n_samples=512, nx=6, nz=7, n_channels=9)
+    k, theta = 128, -1.1
+    fd = k * g.fs / g.n_samples
+    sums = _tone_sums(g, fd, theta)
+    for D in (2, 4):
+        iq = oracle.iq_demodulate(g, _tone(g, k, theta), fd=fd, decimation=D)
+        np.testing.assert_allclose(oracle.iq_beamform(g, iq, "iqdas", 0, fd=fd, decimation=D),
+                                   sums, atol=1e-9)
+
+
+def test_decimated_iq_das_reads_the_record_at_its_own_rate():
+    # a tone slightly off fd: its baseband record turns slowly, and the decimated
+    # IQ-DAS may differ from the full-rate one only by the linear interpolation
+    # error at the two rates, |q''| h^2 / 8 per sample with h = D or 1 samples
+    # (reading the decimated record at s instead of s / D would be far off)
+    g = small_geom(angles_deg=(-3.0,), n_samples=512, nx=6, nz=9, n_channels=12)
+    k, theta = 126, 0.3
+    fd = 128 * g.fs / g.n_samples
+    w_sum = max(sum(oracle.apod_weight(g, e, x, z) for e in range(g.n_channels))
+                for x in g.x_pix for z in g.z_pix)
+    y1 = oracle.iq_beamform(g, oracle.iq_demodulate(g, _tone(g, k, theta), fd=fd), "iqdas", 0,
+                            fd=fd)
+    for D in (2, 4):
+        iq = oracle.iq_demodulate(g, _tone(g, k, theta), fd=fd, decimation=D)
+        yD = oracle.iq_beamform(g, iq, "iqdas", 0, fd=fd, decimation=D)
+        dphi = 2 * np.pi * abs(k / g.n_samples - fd / g.fs)  # baseband radians per sample
+        bound = (dphi ** 2 / 8) * (D ** 2 + 1) * w_sum
+        assert np.abs(yD - y1).max() <= 1.01 * bound
+        assert np.abs(y1).max() > 100 * bound  # the check is not vacuous
+
+
 # ------------------------------------------------------------ brute force 4x4
 def brute_das_dmas(g, rf, p=2.5):
     """Independent evaluation: numpy.interp on a zero-padded record, Hann as a
