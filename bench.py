@@ -120,26 +120,42 @@ def traffic_bytes():
     return float(c["hbm_bytes_per_dispatch"])
 
 
-def time_steps(fn, steps, warmup, torch):
-    """Warm up, then time exactly `steps` calls bracketed by synchronisation;
-    per-step latency from HIP events on the launching stream. Python's garbage
-    collector is run before and paused during the warm-up and the timed loop,
-    so a collection cannot stall the host between launches."""
+# The device lowers its clocks within milliseconds of idling (measured on
+# MI355X: after 50 ms idle the next steps run 15% slower, after 5 ms 4%) and
+# takes a few milliseconds of load to raise them again, longer than a short
+# warm-up. Each timed loop therefore first runs its step, untimed, for a ramp
+# period, with all host-side preparation (events, garbage collection) done
+# before, so the warm-up and timed steps follow the ramp with no idle gap
+# (--clock-ramp seconds, 0 to skip, as for profiling runs).
+RAMP_S = 0.3
+
+
+def time_steps(fn, steps, warmup, torch, ramp_s=None):
+    """Ramp, warm up, then time exactly `steps` calls bracketed by
+    synchronisation; per-step latency from HIP events on the launching stream.
+    Python's garbage collector is run before and paused during the ramp, the
+    warm-up and the timed loop, so a collection cannot stall the host between
+    launches."""
+    ramp_s = RAMP_S if ramp_s is None else ramp_s
+    stream = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(steps)]
     gc.collect()
     gc.disable()
     try:
-        return _time_steps(fn, steps, warmup, torch)
+        return _time_steps(fn, steps, warmup, torch, stream, ev, ramp_s)
     finally:
         gc.enable()
 
 
-def _time_steps(fn, steps, warmup, torch):
+def _time_steps(fn, steps, warmup, torch, stream, ev, ramp_s):
+    t_ramp = time.perf_counter()
+    while time.perf_counter() - t_ramp < ramp_s:
+        for _ in range(8):
+            fn()
+        torch.cuda.synchronize()
     for _ in range(warmup):
         fn()
-    torch.cuda.synchronize()
-    stream = torch.cuda.current_stream()
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-          for _ in range(steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for a, b in ev:
@@ -307,7 +323,12 @@ def other_modes(dev, torch, steps: int, warmup: int, check: bool = True) -> dict
     from paper_2311_00482_amd import GeometryArg, beamform
     from synth import config_c2, config_c3, make_frame
 
-    res = {}
+    # the floor under any launch timed this way: a one-element fill kernel
+    tiny = torch.zeros(1, device=dev)
+    _, flat, _ = time_steps(lambda: tiny.zero_(), 200, 20, torch)
+    floor_ms = float(np.mean(flat))
+    res = {"launch_floor": {"kernel_ms": floor_ms, "what": "HIP-event duration of a "
+                            "one-element fill kernel, timed like the kernels below"}}
     cases = [("dmas_128ch_512x512", config_c2(), "dmas", True, "c1", True),
              ("pdas_p2_128ch_512x512", config_c2(), "pdas", True, "c1", True),
              ("pdas_p2_compound_11a_1024x1024", config_c3(), "pdas", False, "c3", False)]
@@ -333,7 +354,11 @@ def other_modes(dev, torch, steps: int, warmup: int, check: bool = True) -> dict
                      "roofline": {"bound": "alu", "achieved": ops / (k_ms * 1e-3) / 1e12,
                                   "peak": VALU_LANE_OPS_PEAK / 1e12, "unit": "Tlane-op/s",
                                   "frac": ops / (k_ms * 1e-3) / VALU_LANE_OPS_PEAK,
-                                  "ops_per_launch": ops},
+                                  "ops_per_launch": ops,
+                                  # the same with the launch floor taken off the time
+                                  "frac_above_launch_floor":
+                                      ops / (max(k_ms - floor_ms, 1e-6) * 1e-3)
+                                      / VALU_LANE_OPS_PEAK},
                      "rf_storage": "int16" if quant else "f32"}
         if check:
             res[name]["error_vs_oracle"] = _mode_error(gs, fr, mode, quant, rf_only["rf"])
@@ -791,6 +816,9 @@ def main():
                          "takes the compound workload with --profile-compound)")
     ap.add_argument("--profile-compound", action="store_true")
     ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--clock-ramp", type=float, default=RAMP_S,
+                    help="seconds of untimed steps before each warm-up, so that the "
+                         "device's clocks have settled when the timed steps start")
     ap.add_argument("--no-cpu-baseline", action="store_true",
                     help="skip the oracle: no CPU baseline and no accuracy figures")
     ap.add_argument("--serve-seconds", type=float, default=10.0,
@@ -805,6 +833,7 @@ def main():
                     help="first run 3 plain device-to-device copies of this many MiB "
                          "(a reference kernel for calibrating HBM byte counters)")
     args = ap.parse_args()
+    globals()["RAMP_S"] = args.clock_ramp
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the library has no multi-GPU path "
               "(frames would be sharded across GPUs with no exchange); run with --gpus 1.",
@@ -941,6 +970,7 @@ def main():
                    "angles": gs.n_angles, "samples": gs.n_samples,
                    "tile": {k: plan[k] for k in ("cpw", "lz", "wz", "wx", "tile_z", "tile_x",
                                                   "chunk", "win")}},
+        "clock_ramp_s": args.clock_ramp,
         "frames_per_s": args.steps / wall,
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12,
