@@ -98,20 +98,102 @@ __global__ void __launch_bounds__(kThreads)
   if (threadIdx.x == 0) out[k] = r;
 }
 
-// one block per slot of the list
+// the block's item: the k with block0[k] <= b < block0[k + 1]
+__device__ __forceinline__ int quality_item(const QualityList &ql, int b) {
+  int lo = 0, hi = ql.n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (ql.block0[mid] <= b)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+// (count, sum, sum of squares) of env over the disc's pixels in columns
+// [c0, c1] of its box
+__device__ float4 disc_partial(const float *env, int nz, const DiscPix &d, int c0, int c1,
+                               float *sh) {
+  const int h = d.iz1 - d.iz0 + 1, w = c1 - c0 + 1;
+  const int total = w > 0 && h > 0 ? w * h : 0;
+  float c = 0.f, s = 0.f, q = 0.f;
+  for (int k = threadIdx.x; k < total; k += kThreads) {
+    const int ix = c0 + k / h, iz = d.iz0 + k % h;
+    if (inside(d, ix, iz)) {
+      const float e = env[(size_t)ix * nz + iz];
+      c += 1.f;
+      s += e;
+      q = fmaf(e, e, q);
+    }
+  }
+  const float n = block_sum(c, sh), sum = block_sum(s, sh), sq = block_sum(q, sh);
+  return make_float4(n, sum, sq, 0.f);
+}
+
+// mean and population deviation from combined partials
+__device__ __forceinline__ void stats_of(float n, float s, float q, float *mu, float *sd) {
+  if (!(n > 0.f)) {
+    *mu = __builtin_nanf("");
+    *sd = __builtin_nanf("");
+    return;
+  }
+  const float m = s / n;
+  *mu = m;
+  *sd = sqrtf(fmaxf(q / n - m * m, 0.f));
+}
+
+// one block per column chunk of a disc of a checked slot
 __global__ void __launch_bounds__(kThreads)
-    k_quality(const QualityPlan *__restrict__ plans, QualityList ql, QualityOut *__restrict__ out) {
+    k_quality(const QualityPlan *__restrict__ plans, QualityList ql, QualityOut *__restrict__ out,
+              float4 *__restrict__ partials, int *__restrict__ counters) {
   __shared__ float sh[kThreads];
-  const QualityPlan &Q = plans[ql.plan[blockIdx.x]];
-  const float m = dev::frame_max_read(Q.ws_max);
-  const pwbf_contrast c = disc_contrast(Q.env, Q.nz, Q.in, Q.out, sh);
+  __shared__ bool s_last;
+  const int k = quality_item(ql, blockIdx.x);
+  const QualityPlan &Q = plans[ql.plan[k]];
+  const int b = blockIdx.x - ql.block0[k];
+  const bool in = b < Q.chunks_in;
+  const DiscPix &d = in ? Q.in : Q.out;
+  const int chunk = in ? b : b - Q.chunks_in, cols = in ? Q.cols_in : Q.cols_out;
+  const int c0 = d.ix0 + chunk * cols, c1 = min(d.ix1, c0 + cols - 1);
+  const float4 p = disc_partial(Q.env, Q.nz, d, c0, c1, sh);
   if (threadIdx.x == 0) {
+    partials[blockIdx.x] = p;
+    __threadfence();  // the partial is visible before the count says so
+    const int nb = ql.block0[k + 1] - ql.block0[k];
+    s_last = atomicAdd(&counters[k], 1) == nb - 1;
+  }
+  __syncthreads();
+  if (!s_last) return;  // uniform over the block
+  __threadfence();
+  const float m = dev::frame_max_read(Q.ws_max);
+  if (threadIdx.x == 0) {
+    // the slot's partials in chunk order: inside disc, then background
+    float ni = 0.f, si = 0.f, qi = 0.f, no = 0.f, so = 0.f, qo = 0.f;
+    const int first = ql.block0[k];
+    for (int j = 0; j < Q.chunks_in; ++j) {
+      const float4 v = partials[first + j];
+      ni += v.x;
+      si += v.y;
+      qi += v.z;
+    }
+    for (int j = 0; j < Q.chunks_out; ++j) {
+      const float4 v = partials[first + Q.chunks_in + j];
+      no += v.x;
+      so += v.y;
+      qo += v.z;
+    }
+    float mu_in, sd_in, mu_bg, sd_bg;
+    stats_of(ni, si, qi, &mu_in, &sd_in);
+    stats_of(no, so, qo, &mu_bg, &sd_bg);
     QualityOut r;
     r.frame_max = m;
-    r.cr_db = c.cr_db;
-    r.cnr = c.cnr;
-    r.ok = (m > 0.f && c.cr_db <= Q.max_cr_db) ? 1 : 0;  // a NaN CR fails
-    out[blockIdx.x] = r;
+    r.cr_db = (mu_in > 0.f && mu_bg > 0.f) ? 20.0f * log10f(mu_in / mu_bg) : __builtin_nanf("");
+    const float den = sqrtf(0.5f * (sd_in * sd_in + sd_bg * sd_bg));
+    r.cnr = den > 0.f ? (mu_in - mu_bg) / den : __builtin_nanf("");
+    r.ok = (m > 0.f && r.cr_db <= Q.max_cr_db) ? 1 : 0;  // a NaN CR fails
+    out[k] = r;
+    counters[k] = 0;  // ready for the next batch that uses this buffer
   }
 }
 
@@ -202,9 +284,10 @@ __global__ void __launch_bounds__(kThreads)
 }  // namespace
 
 hipError_t launch_quality(const QualityPlan *plans, const QualityList &ql, QualityOut *out,
-                          hipStream_t stream) {
+                          float4 *partials, int *counters, hipStream_t stream) {
   if (ql.n < 1) return hipSuccess;
-  hipLaunchKernelGGL(k_quality, dim3(ql.n), dim3(kThreads), 0, stream, plans, ql, out);
+  hipLaunchKernelGGL(k_quality, dim3(ql.block0[ql.n]), dim3(kThreads), 0, stream, plans, ql, out,
+                     partials, counters);
   return hipGetLastError();
 }
 

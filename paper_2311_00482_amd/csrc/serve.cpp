@@ -81,6 +81,7 @@ class ServerClock : public pwbf::serve::Clock {
 };
 
 constexpr int kCopyStreams = 2;
+constexpr int kQualityBlocksPerSlot = 2 * pwbf::kQualityMaxChunks;
 constexpr int kInflight = pwbf::serve::Core::kMaxInflight;
 static_assert(pwbf::serve::Core::kMaxBatch <= pwbf::kServeMaxActive, "a batch fits the list");
 static_assert(pwbf::serve::Core::kMaxBatch <= pwbf::kQualityMax, "a batch fits the list");
@@ -112,8 +113,11 @@ struct pwbf_server {
   pwbf::FramePlan *d_plans = nullptr;
   pwbf::PostPlan *d_post = nullptr;
   pwbf::QualityPlan *d_quality = nullptr;  // per slot (unused entries zero)
+  std::vector<pwbf::QualityPlan> quality;  // host copy (chunk counts per slot)
   pwbf::QualityOut *d_qout = nullptr;      // kInflight regions of kMaxBatch
   pwbf::QualityOut *h_qout = nullptr;      // pinned copies of those regions
+  float4 *d_qpart = nullptr;               // kInflight regions of the checks' partials
+  int *d_qcount = nullptr;                 // kInflight regions of kMaxBatch counters (zero)
   int *d_counter = nullptr;                // one work counter per tile class
   std::vector<int> plan_class;             // tile class of each slot's plan
   int class_blocks[pwbf::kTileClasses] = {};  // persistent blocks per class
@@ -188,6 +192,7 @@ int HipLauncher::launch(const pwbf::serve::Batch &batch, std::string *err) {
   std::memset(&al, 0, sizeof al);
   pwbf::QualityList ql;
   ql.n = 0;
+  ql.block0[0] = 0;
   auto arg = std::make_unique<CallbackArg>();
   arg->s = s_;
   // at most kInflight batches are on the device and they finish in order, so
@@ -203,8 +208,11 @@ int HipLauncher::launch(const pwbf::serve::Batch &batch, std::string *err) {
     al.log0[k + 1] = al.log0[k] + p.log_cols;
     arg->ids.push_back(batch[k].first);
     if (p.want_quality) {
+      const pwbf::QualityPlan &qp = s_->quality[slot];
       arg->qpos.push_back(ql.n);
-      ql.plan[ql.n++] = slot;
+      ql.plan[ql.n] = slot;
+      ql.block0[ql.n + 1] = ql.block0[ql.n] + qp.chunks_in + qp.chunks_out;
+      ++ql.n;
     } else {
       arg->qpos.push_back(-1);
     }
@@ -217,7 +225,9 @@ int HipLauncher::launch(const pwbf::serve::Batch &batch, std::string *err) {
                            s_->d_counter, s_->lds, s_->max_nz, s_->comp_s);
   if (e == hipSuccess && ql.n > 0) {
     const size_t off = (size_t)arg->region * pwbf::serve::Core::kMaxBatch;
-    e = pwbf::launch_quality(s_->d_quality, ql, s_->d_qout + off, s_->comp_s);
+    e = pwbf::launch_quality(s_->d_quality, ql, s_->d_qout + off,
+                             s_->d_qpart + off * kQualityBlocksPerSlot, s_->d_qcount + off,
+                             s_->comp_s);
     if (e == hipSuccess)
       e = hipMemcpyAsync(s_->h_qout + off, s_->d_qout + off, ql.n * sizeof(pwbf::QualityOut),
                          hipMemcpyDeviceToHost, s_->comp_s);
@@ -271,6 +281,8 @@ void free_server(pwbf_server *s) {
   (void)hipFree(s->d_post);
   (void)hipFree(s->d_quality);
   (void)hipFree(s->d_qout);
+  (void)hipFree(s->d_qpart);
+  (void)hipFree(s->d_qcount);
   if (s->h_qout) (void)hipHostFree(s->h_qout);
   (void)hipFree(s->d_counter);
   for (hipStream_t &c : s->copy_s)
@@ -390,6 +402,8 @@ int pwbf_server_create(const pwbf_probe *probes, int32_t n, size_t hbm_budget_by
         qp.max_cr_db = (float)pp.quality_max_cr_db;
         qp.in = pwbf::disc_to_pixels(&g, pp.quality_region.in);
         qp.out = pwbf::disc_to_pixels(&g, pp.quality_region.out);
+        pwbf::quality_chunks(qp.in, &qp.chunks_in, &qp.cols_in);
+        pwbf::quality_chunks(qp.out, &qp.chunks_out, &qp.cols_out);
       }
       p.tiles = P.n_tiles;
       p.cols = pwbf::post_needed(&o) ? g.nx : 0;
@@ -425,6 +439,10 @@ int pwbf_server_create(const pwbf_probe *probes, int32_t n, size_t hbm_budget_by
     e = hipMalloc((void **)&s->d_quality, quality.size() * sizeof(pwbf::QualityPlan));
   if (e == hipSuccess) e = hipMalloc((void **)&s->d_qout, qregion * sizeof(pwbf::QualityOut));
   if (e == hipSuccess) e = hipHostMalloc((void **)&s->h_qout, qregion * sizeof(pwbf::QualityOut));
+  if (e == hipSuccess)
+    e = hipMalloc((void **)&s->d_qpart, qregion * kQualityBlocksPerSlot * sizeof(float4));
+  if (e == hipSuccess) e = hipMalloc((void **)&s->d_qcount, qregion * sizeof(int));
+  if (e == hipSuccess) e = hipMemset(s->d_qcount, 0, qregion * sizeof(int));
   if (e == hipSuccess) e = hipMalloc((void **)&s->d_counter, sizeof(int) * pwbf::kTileClasses);
   if (e == hipSuccess)
     e = hipMemcpy(s->d_plans, plans.data(), plans.size() * sizeof(pwbf::FramePlan),
@@ -435,6 +453,7 @@ int pwbf_server_create(const pwbf_probe *probes, int32_t n, size_t hbm_budget_by
   if (e == hipSuccess)
     e = hipMemcpy(s->d_quality, quality.data(), quality.size() * sizeof(pwbf::QualityPlan),
                   hipMemcpyHostToDevice);
+  s->quality = quality;
   for (hipStream_t &c : s->copy_s)
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&c, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->comp_s, hipStreamNonBlocking);

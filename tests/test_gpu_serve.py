@@ -10,7 +10,8 @@ rejects with PWBF_E_BUSY; a request still queued at its deadline comes back
 with PWBF_E_TIMEOUT and no planes. A probe's per-frame quality check (frame
 maximum, CR and CNR of one region, pass or fail against a CR bound) equals the
 metrics of the served envelope, checked against the float64 oracle metrics on
-that envelope and on the oracle's own envelope.
+that envelope and on the oracle's own envelope (the check combines float32
+partial sums per column chunk, so it agrees with the metrics call to rounding).
 """
 
 import time
@@ -236,8 +237,16 @@ def test_quality_check_matches_the_metrics_and_the_oracle(probes):
         for i in range(2):
             srv.submit(i, host)
         got = sorted(_collect(srv, 2).values(), key=lambda t: t[0].probe)
+        # the same frame again, three at once: the check's per-slot counters and
+        # partial buffers are reused and give the same figures every time
+        for _ in range(3):
+            srv.submit(0, host)
+        again = [r for r, _ in _collect(srv, 3).values()]
     finally:
         srv.close()
+    for r in again:
+        assert (r.frame_max, r.cr_db, r.cnr, r.quality_ok) == (
+            got[0][0].frame_max, got[0][0].cr_db, got[0][0].cnr, got[0][0].quality_ok)
     # the oracle's envelope over the columns both discs touch (full depth)
     X, _ = om.pixel_centres(g)
     cols = np.nonzero(np.any([np.abs(X[:, 0] - d[0]) <= d[2] + g.dx for d in region], 0))[0]
@@ -250,10 +259,11 @@ def test_quality_check_matches_the_metrics_and_the_oracle(probes):
         assert r.status == 0
         # the frame maximum is the envelope's, bit for bit
         assert r.frame_max == float(env.max())
-        # CR and CNR are those of the metrics call on the same plane, bit for bit
+        # CR and CNR are those of the metrics call on the same plane (the check
+        # sums per column chunk and combines the chunks; float32 rounding apart)
         c = _contrast_of(g, torch.from_numpy(env).cuda(), region)
-        assert np.float32(r.cr_db) == np.float32(c["cr_db"])
-        assert np.float32(r.cnr) == np.float32(c["cnr"])
+        assert abs(r.cr_db - c["cr_db"]) <= 1e-4
+        assert r.cnr == pytest.approx(c["cnr"], rel=1e-5)
         # ... which are the float64 oracle metrics of that plane
         m = _matching_masks(g, env, region, c)
         assert m is not None, (c, om.contrast(g, env, *region))
