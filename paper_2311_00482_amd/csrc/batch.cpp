@@ -28,7 +28,9 @@ struct pwbf_batch {
   std::vector<std::string> sig;  // per-frame shape signature (update must match)
   pwbf::FramePlan *d_plans = nullptr;
   pwbf::PostPlan *d_post = nullptr;
-  int2 *d_items = nullptr, *d_post_cols = nullptr, *d_log_cols = nullptr;
+  int4 *d_items = nullptr;  // (frame, tile, channel hull lo, hi)
+  std::vector<int4> items;  // host copy (the hulls follow the frames' geometry)
+  int2 *d_post_cols = nullptr, *d_log_cols = nullptr;
   std::vector<pwbf::BatchClass> classes;  // every branch's class launches, branch by branch
   struct Branch {
     int class_first = 0, class_n = 0;
@@ -326,7 +328,8 @@ int pwbf_batch_create(const pwbf_frame *frames, int32_t n, int32_t flags, void *
   }
   // Per branch: its items grouped by class, the costliest class first and the
   // longest tiles first within a class; then its frames' columns.
-  std::vector<int2> items, post_cols, log_cols;
+  std::vector<int4> items;
+  std::vector<int2> post_cols, log_cols;
   for (int k = 0; k < n_br; ++k) {
     pwbf_batch::Branch &br = b->branches[k];
     std::vector<Work> order;
@@ -348,7 +351,10 @@ int pwbf_batch_create(const pwbf_frame *frames, int32_t n, int32_t flags, void *
       if ((int)b->classes.size() == br.class_first || b->classes.back().cls != c)
         b->classes.push_back({c, (int)items.size(), 0, 0});
       ++b->classes.back().n;
-      items.push_back(make_int2(order[q].frame, order[q].tile));
+      int lo, hi;
+      pwbf::tile_channel_hull(frames[order[q].frame].geom, b->plans[order[q].frame],
+                              order[q].tile, &lo, &hi);
+      items.push_back(make_int4(order[q].frame, order[q].tile, lo, hi));
     }
     br.class_n = (int)b->classes.size() - br.class_first;
     br.post_first = (int)post_cols.size();
@@ -364,6 +370,7 @@ int pwbf_batch_create(const pwbf_frame *frames, int32_t n, int32_t flags, void *
     br.log_n = (int)log_cols.size() - br.log_first;
   }
   b->n_items = (int)items.size();
+  b->items = items;
   b->n_post_cols = (int)post_cols.size();
   b->n_log_cols = (int)log_cols.size();
 
@@ -390,7 +397,9 @@ int pwbf_batch_create(const pwbf_frame *frames, int32_t n, int32_t flags, void *
   if (e == hipSuccess) e = upload(&b->d_post_cols, post_cols);
   if (e == hipSuccess) e = upload(&b->d_log_cols, log_cols);
   if (e == hipSuccess)
-    e = hipHostMalloc(&b->h_stage, n * (sizeof(pwbf::FramePlan) + sizeof(pwbf::PostPlan)),
+    e = hipHostMalloc(&b->h_stage,
+                      n * (sizeof(pwbf::FramePlan) + sizeof(pwbf::PostPlan)) +
+                          items.size() * sizeof(int4),
                       hipHostMallocDefault);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&b->staged, hipEventDisableTiming);
   if (e != hipSuccess) {
@@ -475,21 +484,31 @@ int pwbf_batch_update(pwbf_batch *b, const pwbf_frame *frames, int32_t n, void *
       return api_set_error(PWBF_E_INVALID,
                            "frame " + std::to_string(i) + " differs in shape from the batch");
   }
+  // the tiles' channel hulls follow the new geometry (element positions, grid
+  // origin and F-number may differ at the same shape)
+  std::vector<int4> items = b->items;
+  for (int4 &it : items)
+    pwbf::tile_channel_hull(frames[it.x].geom, plans[it.x], it.y, &it.z, &it.w);
   hipStream_t s = (hipStream_t)stream;
   hipError_t e = hipSuccess;
   if (b->stage_pending) e = hipEventSynchronize(b->staged);  // staging buffer free again
   if (e != hipSuccess) return dev_error(e, "batch update");
   unsigned char *h = (unsigned char *)b->h_stage;
   const size_t pb = n * sizeof(pwbf::FramePlan), qb = n * sizeof(pwbf::PostPlan);
+  const size_t ib = items.size() * sizeof(int4);
   std::memcpy(h, plans.data(), pb);
   std::memcpy(h + pb, post.data(), qb);
+  if (ib) std::memcpy(h + pb + qb, items.data(), ib);
   e = hipMemcpyAsync(b->d_plans, h, pb, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipMemcpyAsync(b->d_post, h + pb, qb, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess && ib)
+    e = hipMemcpyAsync(b->d_items, h + pb + qb, ib, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipEventRecord(b->staged, s);
   if (e != hipSuccess) return dev_error(e, "batch update");
   b->stage_pending = true;
   b->plans = plans;
   b->post = post;
+  b->items = items;
   return PWBF_OK;
 }
 

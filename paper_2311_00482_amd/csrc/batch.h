@@ -26,7 +26,7 @@ hipError_t launch_batch_reset(const PostPlan *post, int n_frames, hipStream_t st
 // launch `step` of that sequence on the stream (the caller keeps the order).
 int batch_branch_steps(int n_classes, int n_post_cols, int n_log_cols);
 hipError_t launch_batch_branch_step(const FramePlan *plans, const PostPlan *post,
-                                    const int2 *items, const BatchClass *classes, int n_classes,
+                                    const int4 *items, const BatchClass *classes, int n_classes,
                                     const int2 *post_cols, int n_post_cols, const int2 *log_cols,
                                     int n_log_cols, size_t lds, int max_nz, int step,
                                     hipStream_t stream);

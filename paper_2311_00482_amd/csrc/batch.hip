@@ -46,21 +46,23 @@ __global__ void k_batch_reset(const PostPlan *__restrict__ post, int n_frames) {
 // for DAS with one lane group).
 template <int MODE, bool ONEGRP, int AB>
 __global__ void __launch_bounds__(kWave * kBatchWaves)
-    k_batch_beamform(const FramePlan *__restrict__ plans, const int2 *__restrict__ items) {
+    k_batch_beamform(const FramePlan *__restrict__ plans, const int4 *__restrict__ items) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const int2 w = items[blockIdx.x];
+  const int4 w = items[blockIdx.x];
   const FramePlan &P = plans[__builtin_amdgcn_readfirstlane(w.x)];
   const int tile = __builtin_amdgcn_readfirstlane(w.y);
   const int tz = tile / P.tiles_x, tx = tile - tz * P.tiles_x;
+  // the tile's channel hull, computed on the host (w.z, w.w)
   if constexpr (AB == 3)
-    dev::process_tile<kBatchMaxAngles, true, MODE, ONEGRP>(P, tz, tx, smem);
+    dev::process_tile<kBatchMaxAngles, true, MODE, ONEGRP>(P, tz, tx, smem, w.z, w.w);
   else
-    dev::process_tile<AB == 0 ? 1 : (AB == 1 ? 5 : 11), false, MODE, ONEGRP>(P, tz, tx, smem);
+    dev::process_tile<AB == 0 ? 1 : (AB == 1 ? 5 : 11), false, MODE, ONEGRP>(P, tz, tx, smem,
+                                                                             w.z, w.w);
 }
 
 template <int C>
 hipError_t launch_class_kernel(dim3 grid, size_t lds, hipStream_t s, const FramePlan *plans,
-                               const int2 *items) {
+                               const int4 *items) {
   hipLaunchKernelGGL((k_batch_beamform<C / 8, (C / 4) % 2 == 1, C % 4>), grid,
                      dim3(kWave * kBatchWaves), lds, s, plans, items);
   return hipGetLastError();
@@ -120,7 +122,7 @@ int batch_branch_steps(int n_classes, int n_post_cols, int n_log_cols) {
 }
 
 hipError_t launch_batch_branch_step(const FramePlan *plans, const PostPlan *post,
-                                    const int2 *items, const BatchClass *classes, int n_classes,
+                                    const int4 *items, const BatchClass *classes, int n_classes,
                                     const int2 *post_cols, int n_post_cols, const int2 *log_cols,
                                     int n_log_cols, size_t lds, int max_nz, int step,
                                     hipStream_t stream) {

@@ -310,9 +310,12 @@ __device__ __forceinline__ float ff_f(ff a) { return a.hi + a.lo; }
 // rounding near 5e-7 of a sample. Their window entries are (u[n], du), read at
 // the fraction of the delay, so the per-wavefront integer shift needs no
 // change to the windows.
+// hull_lo >= 0: the tile's channel hull [hull_lo, hull_hi) comes from the
+// caller (the batch computes it on the host); else the block finds it.
 template <int AM, bool PRED, int MODE, bool ONEGRP, bool SEL>
 __device__ __forceinline__ void process_tile_body(const FramePlan &P, int tz, int tx,
-                                                  unsigned char *smem) {
+                                                  unsigned char *smem, int hull_lo = -1,
+                                                  int hull_hi = -1) {
   constexpr bool IQ = is_iq_mode(MODE);
   float *s_txq = (float *)smem;                        // [kMaxAngles] tx(q) - LT
   int *s_lt = (int *)(smem + kMaxAngles * 4);          // [kMaxAngles] LT
@@ -389,7 +392,8 @@ __device__ __forceinline__ void process_tile_body(const FramePlan &P, int tz, in
   // float rounding can only add a channel, never drop one; outputs are those
   // of the loop over all channels.
   __shared__ int s_erange[2 * kMaxWavesPerBlock];
-  if (P.apod != kNone) {
+  const bool given_hull = hull_lo >= 0;
+  if (P.apod != kNone && !given_hull) {
     const float zmax = Zqf + dzhi;
     int lo = N, hi = 0;
     for (int e = tid; e < N; e += blockDim.x) {
@@ -426,7 +430,10 @@ __device__ __forceinline__ void process_tile_body(const FramePlan &P, int tz, in
   }
   __syncthreads();
   int e_lo = 0, e_hi = N;
-  if (P.apod != kNone) {
+  if (given_hull) {
+    e_lo = __builtin_amdgcn_readfirstlane(hull_lo);
+    e_hi = __builtin_amdgcn_readfirstlane(hull_hi);
+  } else if (P.apod != kNone) {
     e_hi = 0;
     e_lo = N;
     for (int w = 0; w < (int)(blockDim.x / kWave); ++w) {
@@ -752,14 +759,15 @@ __device__ __forceinline__ void process_tile_body(const FramePlan &P, int tz, in
 // directly: there the second body costs registers.)
 template <int AM, bool PRED, int MODE, bool ONEGRP>
 __device__ __forceinline__ void process_tile(const FramePlan &P, int tz, int tx,
-                                             unsigned char *smem) {
+                                             unsigned char *smem, int hull_lo = -1,
+                                             int hull_hi = -1) {
   if constexpr ((MODE == kDas || MODE == kDmas || MODE == kPdas) && ONEGRP && !PRED) {
     if (P.apod != kBoxcar) {
-      process_tile_body<AM, PRED, MODE, ONEGRP, false>(P, tz, tx, smem);
+      process_tile_body<AM, PRED, MODE, ONEGRP, false>(P, tz, tx, smem, hull_lo, hull_hi);
       return;
     }
   }
-  process_tile_body<AM, PRED, MODE, ONEGRP, true>(P, tz, tx, smem);
+  process_tile_body<AM, PRED, MODE, ONEGRP, true>(P, tz, tx, smem, hull_lo, hull_hi);
 }
 
 }  // namespace dev

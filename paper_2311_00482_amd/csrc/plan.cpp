@@ -514,6 +514,31 @@ int tile_active_channels(const pwbf_geometry *g, const FramePlan &P, int tile) {
   return n;
 }
 
+void tile_channel_hull(const pwbf_geometry *g, const FramePlan &P, int tile, int *lo, int *hi) {
+  // The test the kernel makes in float32, here in float64: the channels whose
+  // distance to the tile's lateral span is below 1.001 Z_max / (2 F#) (any
+  // channel with a nonzero weight at some pixel of the tile passes it either
+  // way; the others add exact zeros, so the two hulls give the same sums).
+  *lo = 0;
+  *hi = g->n_channels;
+  if (g->apod == kNone) return;
+  const int tz = tile / P.tiles_x, tx = tile - tz * P.tiles_x;
+  const double xlo = g->x0 + (double)tx * P.tile_x * g->dx;
+  const double xhi = g->x0 + (double)(std::min((tx + 1) * P.tile_x, g->nx) - 1) * g->dx;
+  const double zmax = g->z0 + (double)(std::min((tz + 1) * P.tile_z, g->nz) - 1) * g->dz;
+  *lo = g->n_channels;
+  *hi = 0;
+  if (!(zmax > 0)) return;
+  for (int e = 0; e < g->n_channels; ++e) {
+    const double x = g->elem_x[e];
+    const double d = x < xlo ? xlo - x : (x > xhi ? x - xhi : 0.0);
+    if (d * 2.0 * g->f_number < zmax * 1.001) {
+      *lo = std::min(*lo, e);
+      *hi = std::max(*hi, e + 1);
+    }
+  }
+}
+
 double tile_cost(const pwbf_geometry *g, const FramePlan &P, int tile) {
   // Estimated vector lane-operations of the tile, from the kernel's instruction
   // mix: per (pixel, active channel) the receive delay, weight and its

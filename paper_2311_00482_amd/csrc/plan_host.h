@@ -46,6 +46,9 @@ void debug_log(const char *fmt, ...) __attribute__((format(printf, 1, 2)));
 // without apodization), and the tile's relative cost for work ordering.
 int tile_active_channels(const pwbf_geometry *g, const FramePlan &P, int tile);
 double tile_cost(const pwbf_geometry *g, const FramePlan &P, int tile);
+// [lo, hi): the channels whose weight may be nonzero somewhere in the tile
+// (a superset of them; lo >= hi when none), decided in float64
+void tile_channel_hull(const pwbf_geometry *g, const FramePlan &P, int tile, int *lo, int *hi);
 int build_post_plan(const pwbf_geometry *g, const pwbf_outputs *o, void *ws, PostPlan *Q);
 bool post_needed(const pwbf_outputs *o);
 

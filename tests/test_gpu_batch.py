@@ -125,6 +125,24 @@ def test_batch_graph_replays_and_updates():
         ref = single(*a)
         for k, v in f.out.items():
             assert same(v.cpu().numpy(), ref[k], k, a[2]), k
+    # the same shapes on another geometry: the grid moved sideways and deeper
+    # and a tighter F-number change which channels reach each tile, and the
+    # update must follow them (the tiles' channel hulls are recomputed)
+    from paper_2311_00482_amd import FrameSpec
+    frames3, args3 = [], []
+    for f, a in zip(frames2, args2):
+        g3 = f.geom.replace(x_min=f.geom.x_min + 1.1e-3, x_max=f.geom.x_max + 1.1e-3,
+                            z_min=f.geom.z_min + 0.7e-3, z_max=f.geom.z_max + 0.7e-3,
+                            f_number=f.geom.f_number * 1.6)
+        frames3.append(FrameSpec(g3, f.rf, f.mode, f.angle, f.out, f.bandpass, f.tile))
+        args3.append((g3,) + tuple(a[1:]))
+    b.update(frames3)
+    b.launch()
+    torch.cuda.synchronize()
+    for f, a in zip(frames3, args3):
+        ref = single(*a)
+        for k, v in f.out.items():
+            assert same(v.cpu().numpy(), ref[k], k, a[2]), ("moved grid", k)
     # a frame of another shape is refused
     g_other = geom(nx=41, nz=128, angles_deg=(-8.0, 0.0, 8.0))
     frames2[0].geom = g_other
