@@ -585,17 +585,7 @@ def uneven_batch(dev, torch, steps: int, warmup: int, check: bool = False) -> di
     ms_b = float(np.mean(latb))
     err = None
     if check:
-        cheap = sorted(range(len(specs)), key=lambda i: specs[i].geom.gathers)[:4]
-        err = {}
-        for i in cheap:
-            sp = specs[i]
-            host = frames[i].rf.cpu().numpy()
-            if sp.mode == "dmas":
-                ref = oracle.dmas(sp.geom, host, -1, "identity", parallel=True)
-            else:
-                ref = oracle.das(sp.geom, host, -1, parallel=True)
-            err[f"frame{i}_{sp.mode}_{sp.geom.n_angles}a_{sp.geom.n_channels}ch_"
-                f"{sp.geom.nx}x{sp.geom.nz}"] = _max_norm(frames[i].out["rf"].cpu().numpy(), ref)
+        err = _uneven_errors(specs, frames, batch, torch)
 
     def one_by_one():
         for g, rf, mode, w, out, ws, bp in singles:
@@ -616,9 +606,54 @@ def uneven_batch(dev, torch, steps: int, warmup: int, check: bool = False) -> di
                              "ms_per_32": float(np.mean(lats)),
                              "value": gathers * n / walls / 1e9, "unit": UNIT}}
     if err is not None:
-        res["error_vs_oracle"] = {"rf": err, "sample": "whole images of the four frames "
-                                  "cheapest to evaluate", "rf_storage": "int16"}
+        res["error_vs_oracle"] = err
     return res
+
+
+def _uneven_errors(specs, frames, batch, torch) -> dict:
+    """Raw planes of the four frames cheapest to evaluate against the oracle on
+    the same int16 samples: first on the timing run's uniform-noise RF, beside
+    how far the float64 definition itself moves when every delay shifts by
+    3e-8 samples (below the resolution of a float32 delay: the root of DMAS is
+    steep at the near-zero samples that incoherent content has, so that move is
+    the float32 floor there); then on the simulated phantom frames of the same
+    shapes (the batch relaunched on them)."""
+    import dataclasses
+    import oracle
+    from synth import make_frame
+    cheap = sorted(range(len(specs)), key=lambda i: specs[i].geom.gathers)[:4]
+
+    def ref_of(sp, host, g=None):
+        g = g or sp.geom
+        if sp.mode == "dmas":
+            return oracle.dmas(g, host, -1, "identity", parallel=True)
+        return oracle.das(g, host, -1, parallel=True)
+
+    def name(i):
+        g = specs[i].geom
+        return f"frame{i}_{specs[i].mode}_{g.n_angles}a_{g.n_channels}ch_{g.nx}x{g.nz}"
+
+    noise, floor, phantom = {}, {}, {}
+    for i in cheap:
+        sp = specs[i]
+        host = frames[i].rf.cpu().numpy()
+        ref = ref_of(sp, host)
+        noise[name(i)] = _max_norm(frames[i].out["rf"].cpu().numpy(), ref)
+        shifted = dataclasses.replace(sp.geom, t0=tuple(3e-8 / sp.geom.fs for _ in sp.geom.angles_deg))
+        floor[name(i)] = _max_norm(ref_of(sp, host, shifted), ref)
+    sims = {i: make_frame(specs[i].geom, specs[i].seed, "scaled") for i in cheap}
+    for i in cheap:
+        frames[i].rf.copy_(torch.from_numpy(sims[i]["i16"]))
+    batch.launch()
+    torch.cuda.synchronize()
+    for i in cheap:
+        phantom[name(i)] = _max_norm(frames[i].out["rf"].cpu().numpy(),
+                                     ref_of(specs[i], sims[i]["i16"]))
+    return {"rf": phantom, "content": "simulated phantom frames (points and cysts in speckle)",
+            "white_noise_rf": noise,
+            "definition_move_at_3e-8_sample_delay_shift": floor,
+            "sample": "whole images of the four frames cheapest to evaluate",
+            "rf_storage": "int16"}
 
 
 def _serve_rate(srv, hosts, n_probes, rate, seconds, warmup, rng, keep=None):

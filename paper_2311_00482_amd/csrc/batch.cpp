@@ -167,14 +167,29 @@ int pwbf_tune(const pwbf_geometry *g, const void *rf, int32_t rf_dtype, int32_t 
   int rc = pwbf::build_plan(g, rf, rf_dtype, mode, angle, nullptr, out, nullptr, 0, &P, &err);
   if (rc) return api_set_error(rc, err);
   hipStream_t s = (hipStream_t)stream;
-  std::vector<pwbf_tile> cands;
+  // the shape this frame plans with now (it fits, so tuning never fails where
+  // planning succeeds), then a fixed grid of lane groupings, lane-group
+  // depths from 2 to 32 and wavefront arrangements
+  std::vector<pwbf_tile> cands = {{P.cpw, P.lz, P.wz, P.wx, 0}};
+  // DMAS and pDAS: only shapes within their delay-offset bound, when the
+  // frame's own plan (of the required wavefront count) shows that one is
+  bool compact_only = pwbf::root_compact(g, P);
+  if (waves) {
+    pwbf::FramePlan W;
+    std::string e2;
+    compact_only = false;
+    if (pwbf::plan_frame(g, rf_dtype, mode, angle, nullptr, &W, &e2, waves) == PWBF_OK) {
+      cands.insert(cands.begin(), {W.cpw, W.lz, W.wz, W.wx, 0});
+      compact_only = pwbf::root_compact(g, W);
+    }
+  }
+  static const int kArr[][2] = {{1, 8}, {2, 4}, {4, 2}, {8, 1}, {1, 4}};
   for (int cpw : {1, 2, 4})
-    for (int lz : {8, 16, 32})
-      for (int arr = 0; arr < 3; ++arr) {
+    for (int lz : {2, 4, 8, 16, 32})
+      for (const auto &wa : kArr) {
         if (lz > 64 / cpw) continue;
-        int wz = arr == 0 ? 1 : (arr == 1 ? 2 : 1), wx = arr == 0 ? 8 : (arr == 1 ? 4 : 4);
-        if (waves && wz * wx != waves) continue;
-        cands.push_back({cpw, lz, wz, wx, 0});
+        if (waves && wa[0] * wa[1] != waves) continue;
+        cands.push_back({cpw, lz, wa[0], wa[1], 0});
       }
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
@@ -185,6 +200,7 @@ int pwbf_tune(const pwbf_geometry *g, const void *rf, int32_t rf_dtype, int32_t 
     pwbf::FramePlan Q;
     if (pwbf::build_plan(g, rf, rf_dtype, mode, angle, &t, out, nullptr, 0, &Q, &err)) continue;
     if (waves && Q.wz * Q.wx != waves) continue;
+    if (compact_only && !pwbf::root_compact(g, Q)) continue;
     hipError_t e = pwbf::launch_beamform(Q, s);  // warm-up
     for (int k = 0; k < 3 && e == hipSuccess; ++k) {
       if (k == 0) e = hipEventRecord(e0, s);

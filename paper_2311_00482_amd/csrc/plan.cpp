@@ -215,6 +215,21 @@ static int window_entries(FramePlan &p, int TZ, int TX) {
 // Wavefronts of a tile, without overflow for any field values.
 static int64_t tile_waves(const pwbf_tile &t) { return (int64_t)t.wz * t.wx; }
 
+// The bound on a root-mode gather's offset from its wavefront's reference
+// pixel (plan.h), in samples, for lane groups of lz x lx pixels.
+static double root_offset_samples(const pwbf_geometry *g, const FramePlan &P, int lz, int lx) {
+  double smax = 0.0;
+  for (int a = 0; a < P.n_angles; ++a) smax = std::max(smax, std::fabs((double)P.sa[a]));
+  const double sphi =
+      g->apod == kNone ? 1.0 : 1.0 / std::sqrt(1.0 + 4.0 * g->f_number * g->f_number);
+  const double hz = (lz / 2) * std::fabs((double)P.DZ), hx = (lx / 2) * std::fabs((double)P.DX);
+  return 2.0 * hz + hx * (smax + sphi);
+}
+
+bool root_compact(const pwbf_geometry *g, const FramePlan &P) {
+  return !wave_ref_mode(P.mode) || root_offset_samples(g, P, P.lz, P.lx) <= kRootOffsetAuto;
+}
+
 // Apply launch shape t to plan P (geometry already filled in): window length,
 // channels per LDS chunk. PWBF_E_UNSUPPORTED when even cpw channels do not fit.
 static int fit_tile(const pwbf_geometry *g, pwbf_tile t, FramePlan *P, std::string *err) {
@@ -367,10 +382,10 @@ static int plan_frame_uncached(const pwbf_geometry *g, int dtype, int mode, int 
     bool done = false;
     if (tune_lookup(shape_key(g, dtype, mode, angle, waves), &tuned) &&
         (!waves || tile_waves(tuned) == waves))
-      done = fit_tile(g, tuned, P, err) == PWBF_OK;
+      done = fit_tile(g, tuned, P, err) == PWBF_OK && root_compact(g, *P);
     source = "tuned";
     if (!done && (!waves || d.wz * d.wx == waves)) {
-      done = fit_tile(g, d, P, err) == PWBF_OK;
+      done = fit_tile(g, d, P, err) == PWBF_OK && root_compact(g, *P);
       source = "default";
     }
     if (!done) {
@@ -381,8 +396,10 @@ static int plan_frame_uncached(const pwbf_geometry *g, int dtype, int mode, int 
       // samples deep, such as 32 rows over 3 cm at 50 MHz.
       static const int kArr[][2] = {{2, 4}, {1, 8}, {4, 2}, {8, 1}, {1, 4}, {2, 2},
                                     {4, 1}, {1, 2}, {2, 1}, {1, 1}};
+      // (DMAS and pDAS: a shape within their delay-offset bound first)
       pwbf_tile best = {0, 0, 0, 0, 0};
       int best_px = 0, best_win = 0;
+      bool best_compact = false;
       for (int cpw = d.cpw; cpw <= 16; cpw *= 2)
         for (int lz = 1; lz <= kWave / cpw; lz *= 2)
           for (const auto &wa : kArr) {
@@ -392,10 +409,14 @@ static int plan_frame_uncached(const pwbf_geometry *g, int dtype, int mode, int 
             std::string e2;
             if (fit_tile(g, t, &Q, &e2) != PWBF_OK) continue;
             const int px = std::min(Q.tile_z, g->nz) * std::min(Q.tile_x, g->nx);
-            if (px > best_px || (px == best_px && Q.win < best_win)) {
+            const bool compact = root_compact(g, Q);
+            if ((compact && !best_compact) ||
+                (compact == best_compact &&
+                 (px > best_px || (px == best_px && Q.win < best_win)))) {
               best = t;
               best_px = px;
               best_win = Q.win;
+              best_compact = compact;
             }
           }
       if (best_px > 0) {

@@ -30,6 +30,9 @@ int plan_frame(const pwbf_geometry *g, int dtype, int mode, int angle, const pwb
 int build_plan(const pwbf_geometry *g, const void *rf, int dtype, int mode, int angle,
                const pwbf_tile *tile, const pwbf_outputs *o, void *ws, size_t ws_bytes,
                FramePlan *P, std::string *err);
+// DMAS and pDAS: whether plan P's lane groups keep every gather within
+// kRootOffsetAuto samples of its wavefront's reference pixel (other modes: true)
+bool root_compact(const pwbf_geometry *g, const FramePlan &P);
 // tuning table (tune.cpp)
 std::string shape_key(const pwbf_geometry *g, int dtype, int mode, int angle, int waves);
 bool tune_lookup(const std::string &key, pwbf_tile *t);
