@@ -258,6 +258,49 @@ def test_every_workload_default_fits_the_window_limit():
     assert lib() is not None
 
 
+def _root_offset_bound(g, angle, cpw, lz):
+    """Largest distance (samples) of a DMAS / pDAS gather's delay from its
+    wavefront's reference pixel for lane groups of lz x (64 / cpw / lz)
+    pixels: twice the depth reach plus the lateral reach times the largest
+    transmit sine plus the sine of the widest apodized receive angle."""
+    lx = 64 // cpw // lz
+    scale = g.fs / g.c
+    dx = (g.x_max - g.x_min) / max(g.nx - 1, 1) * scale
+    dz = (g.z_max - g.z_min) / max(g.nz - 1, 1) * scale
+    angles = g.angles_deg if angle < 0 else (g.angles_deg[angle],)
+    smax = max(abs(np.sin(np.deg2rad(a))) for a in angles)
+    sphi = 1.0 if g.apod == "none" else 1.0 / np.sqrt(1.0 + 4.0 * g.f_number ** 2)
+    return 2.0 * (lz // 2) * dz + (lx // 2) * dx * (smax + sphi)
+
+
+def test_root_modes_pick_compact_lane_groups():
+    # the shapes DMAS and pDAS plans pick themselves keep every gather within
+    # 5.5 samples of its wavefront's reference pixel (re-derived here from the
+    # geometry) when some shape does; an explicit tall shape is taken as given;
+    # a grid on which no shape is that compact still plans (the best fitting)
+    specs = [(config_c2(), "dmas"), (config_c2(), "pdas"), (config_c3(), "pdas"),
+             (config_c3(), "dmas")]
+    specs += [(s.geom, s.mode) for s in config_c4_frames() if s.mode != "das"]
+    for g, mode in specs:
+        p = describe_plan(g, mode, -1, None)
+        assert _root_offset_bound(g, -1, p["cpw"], p["lz"]) <= 5.5 + 1e-9, (g.name, p)
+    f21 = config_c4_frames()[21].geom
+    assert _root_offset_bound(f21, -1, 1, 32) > 10.0
+    p = describe_plan(f21, "dmas", -1, Tile(1, 32, 1, 8, 0))
+    assert (p["cpw"], p["lz"]) == (1, 32)
+    # a small grid whose default shape (4 lane groups of 16 x 1 pixels, what DAS
+    # takes) fits the window but reaches 7.3 samples: DMAS plans a flatter one
+    small = geom(n_channels=32, nx=64, nz=256)
+    assert describe_plan(small, "das", 0, None)["lz"] == 16
+    assert _root_offset_bound(small, 0, 4, 16) > 5.5
+    describe_plan(small, "dmas", 0, Tile(4, 16, 1, 8, 0))  # accepted when explicit
+    p = describe_plan(small, "dmas", 0, None)
+    assert _root_offset_bound(small, 0, p["cpw"], p["lz"]) <= 5.5
+    coarse = geom(n_channels=12, nx=21, nz=77)  # pixels 3.7 x 1.5 samples
+    p = describe_plan(coarse, "dmas", 0, None)
+    assert _root_offset_bound(coarse, 0, p["cpw"], p["lz"]) > 0
+
+
 def test_too_coarse_grid_is_refused():
     # pixels of ~40 x 40 samples: no launch shape keeps a window within 64 entries
     from paper_2311_00482_amd import PwbfError
