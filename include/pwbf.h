@@ -109,6 +109,13 @@ extern "C" {
  * way. */
 #define PWBF_MAX_WINDOW 64
 #define PWBF_MAX_WINDOW_ROOT 32 /* DMAS, pDAS, BB-DMAS */
+/* DMAS and pDAS take each delay relative to their wavefront's centre pixel.
+ * The shapes the library picks itself (default, fallback, tuner) keep every
+ * gather within 5.5 samples of that pixel's delay whenever some shape does:
+ * 2 (lz / 2) DZ + (lx / 2) DX (max |sin th| + 1 / sqrt(1 + 4 F#^2)) <= 5.5 for
+ * lane groups of lz x lx pixels (halves rounded down; the last term 1 without
+ * apodization), which bounds the float32 rounding of their delays. Explicit
+ * shapes are taken as given. */
 
 /* Acquisition and grid. Host pointers are read during the call only. */
 typedef struct pwbf_geometry {
