@@ -404,13 +404,16 @@ __device__ __forceinline__ void process_tile_body(const FramePlan &P, int tz, in
         hi = max(hi, e + 1);
       }
     }
-    for (int off = 1; off < kWave; off <<= 1) {
-      lo = min(lo, __shfl_xor(lo, off));
-      hi = max(hi, __shfl_xor(hi, off));
-    }
-    if (lane == 0) {
-      s_erange[2 * wave] = lo;
-      s_erange[2 * wave + 1] = hi;
+    // only wavefronts whose threads hold a channel (wave * 64 < N) reduce
+    if (wave * kWave < N) {
+      for (int off = 1; off < kWave; off <<= 1) {
+        lo = min(lo, __shfl_xor(lo, off));
+        hi = max(hi, __shfl_xor(hi, off));
+      }
+      if (lane == 0) {
+        s_erange[2 * wave] = lo;
+        s_erange[2 * wave + 1] = hi;
+      }
     }
   }
 
@@ -436,7 +439,8 @@ __device__ __forceinline__ void process_tile_body(const FramePlan &P, int tz, in
   } else if (P.apod != kNone) {
     e_hi = 0;
     e_lo = N;
-    for (int w = 0; w < (int)(blockDim.x / kWave); ++w) {
+    const int nwr = min((int)(blockDim.x / kWave), (N + kWave - 1) / kWave);
+    for (int w = 0; w < nwr; ++w) {
       e_lo = min(e_lo, s_erange[2 * w]);
       e_hi = max(e_hi, s_erange[2 * w + 1]);
     }
