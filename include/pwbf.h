@@ -49,6 +49,8 @@
  *    of pwbf_tune_save) when it exists, and each shape pwbf_tune measures is
  *    written back to it at once (through a side file and a rename).
  *  - PWBF_BATCH_BRANCHES=1..4: the branches of a batch graph (default 3).
+ *  - PWBF_SERVE_INFLIGHT=1..4: the batches a server keeps on the device at
+ *    once (default 4), read when the server is created.
  */
 #ifndef PWBF_H
 #define PWBF_H
@@ -507,8 +509,9 @@ PWBF_API int pwbf_tune_clear(void);
  * host memory; a scheduler thread admits queued requests into free slots while
  * the HBM budget ledger allows (the bytes of the slots in use), uploads them on
  * one of two copy streams (the one with fewer bytes outstanding) and converts
- * them to FP16 on the device, and, whenever fewer than two batches are on the
- * GPU, launches every uploaded request as one batch (continuous batching:
+ * them to FP16 on the device, and, whenever fewer than four batches
+ * (PWBF_SERVE_INFLIGHT) are on the GPU, launches every uploaded request as one
+ * batch (continuous batching:
  * requests that arrive while others run join the next batch). A frame runs the
  * same kernels with the same plan whether it is alone or in a mix, so its
  * planes do not depend on the mix. The decisions (ledger, admission, deadlines,

@@ -82,7 +82,19 @@ class ServerClock : public pwbf::serve::Clock {
 
 constexpr int kCopyStreams = 2;
 constexpr int kQualityBlocksPerSlot = 2 * pwbf::kQualityMaxChunks;
-constexpr int kInflight = pwbf::serve::Core::kMaxInflight;
+constexpr int kInflight = pwbf::serve::Core::kMaxInflight;  // device regions: the most
+
+// Batches on the device at once, four by default: with two, a request whose
+// upload finished while two batches ran waited for one of them, and at 5000
+// requests/s that wait made the admit-to-launch leg's p99 (0.74-0.79 ms) exceed
+// the GPU leg's (0.65 ms); with four it is 0.66 against 0.72 ms, and the p99 at
+// 3500 requests/s fell from ~1.08 to 0.93 ms. PWBF_SERVE_INFLIGHT (1..4)
+// overrides it when a server is created.
+int serve_inflight() {
+  const char *v = getenv("PWBF_SERVE_INFLIGHT");
+  const int k = v ? atoi(v) : kInflight;
+  return k >= 1 && k <= kInflight ? k : kInflight;
+}
 static_assert(pwbf::serve::Core::kMaxBatch <= pwbf::kServeMaxActive, "a batch fits the list");
 static_assert(pwbf::serve::Core::kMaxBatch <= pwbf::kQualityMax, "a batch fits the list");
 
@@ -462,7 +474,8 @@ int pwbf_server_create(const pwbf_probe *probes, int32_t n, size_t hbm_budget_by
     return api_set_error(PWBF_E_NOMEM, std::string("server allocation: ") + hipGetErrorString(e));
   }
   s->core = std::make_unique<pwbf::serve::Core>(std::move(info), hbm_budget_bytes,
-                                                max_queue ? max_queue : 1024, &s->clock);
+                                                max_queue ? max_queue : 1024, &s->clock,
+                                                serve_inflight());
   s->launcher = std::make_unique<HipLauncher>(s);
   s->worker = std::thread(scheduler, s);
   *out = s;

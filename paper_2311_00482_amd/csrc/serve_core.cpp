@@ -9,8 +9,10 @@
 namespace pwbf {
 namespace serve {
 
-Core::Core(std::vector<ProbeInfo> probes, size_t budget, int max_queue, const Clock *clock)
-    : probes_(std::move(probes)), budget_(budget), max_queue_(max_queue), clock_(clock) {
+Core::Core(std::vector<ProbeInfo> probes, size_t budget, int max_queue, const Clock *clock,
+           int max_inflight)
+    : probes_(std::move(probes)), budget_(budget), max_queue_(max_queue), clock_(clock),
+      max_inflight_(std::min(std::max(max_inflight, 1), kMaxInflight)) {
   int n_slots = 0;
   for (const ProbeInfo &p : probes_)
     for (int s : p.slots) n_slots = std::max(n_slots, s + 1);
@@ -171,7 +173,7 @@ Core::StepResult Core::step(Launcher &launcher) {
       }
     }
     rr_ = (rr_ + 1) % std::max(1, np);
-    can_launch = inflight_ < kMaxInflight && !admitted_.empty();
+    can_launch = inflight_ < max_inflight_ && !admitted_.empty();
     if (can_launch)
       for (uint64_t id : admitted_) candidates.push_back({id, reqs_[id].slot});
   }

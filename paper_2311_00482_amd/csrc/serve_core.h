@@ -71,9 +71,12 @@ class Clock {
 class Core {
  public:
   static constexpr int kMaxBatch = 64;
-  static constexpr int kMaxInflight = 2;  // batches on the device at once
+  static constexpr int kMaxInflight = 4;  // the most batches on the device at once
 
-  Core(std::vector<ProbeInfo> probes, size_t budget, int max_queue, const Clock *clock);
+  // max_inflight: batches on the device at once, 1..kMaxInflight (clamped;
+  // the server passes PWBF_SERVE_INFLIGHT, by default kMaxInflight)
+  Core(std::vector<ProbeInfo> probes, size_t budget, int max_queue, const Clock *clock,
+       int max_inflight = 2);
 
   // ---- callers (thread-safe)
   // queue a request; deadline < 0: none, else the server time by which it must
@@ -120,6 +123,7 @@ class Core {
   std::unordered_map<uint64_t, Request> reqs_;
   std::vector<uint64_t> admitted_;  // upload enqueued, not yet launched (oldest first)
   std::deque<uint64_t> done_;       // finished, not yet polled
+  int max_inflight_ = 2;
   int inflight_ = 0, rr_ = 0;
   int64_t submitted_ = 0, rejected_ = 0, completed_ = 0, expired_ = 0, batches_ = 0,
           batched_reqs_ = 0;

@@ -257,6 +257,28 @@ void test_continuous_batching() {
   std::puts("ok continuous_batching");
 }
 
+void test_inflight_limit() {
+  // the limit given to the core (the server's PWBF_SERVE_INFLIGHT): four
+  // batches may run at once and a fifth waits; out-of-range limits clamp
+  for (int limit : {4, 9, 0}) {
+    const int want = limit < 1 ? 1 : (limit > Core::kMaxInflight ? Core::kMaxInflight : limit);
+    FakeClock clk;
+    Core c({probe(10, {0, 1, 2, 3, 4, 5})}, 0, 64, &clk, limit);
+    MockLauncher m;
+    std::vector<uint64_t> ids;
+    for (int k = 0; k < 6; ++k) {
+      ids.push_back(submit_ok(c, 0));
+      c.step(m);  // each request uploads at once and starts its own batch while a slot is free
+    }
+    CHECK((int)m.batches.size() == want);
+    CHECK(c.inflight() == want);
+    c.complete({ids[0]}, nullptr);
+    CHECK(c.step(m) == Core::kWorked);
+    CHECK((int)m.batches.size() == want + 1);
+  }
+  std::puts("ok inflight_limit");
+}
+
 void test_round_robin_and_fifo() {
   FakeClock clk;
   Core c({probe(1, {0, 1, 2}), probe(1, {3, 4, 5})}, 0, 64, &clk);
@@ -405,6 +427,7 @@ int main() {
   test_launch_failure_propagates();
   test_release_errors();
   test_continuous_batching();
+  test_inflight_limit();
   test_round_robin_and_fifo();
   test_poll_limit_quality_and_times();
   test_stop();
