@@ -85,11 +85,11 @@ constexpr int kQualityBlocksPerSlot = 2 * pwbf::kQualityMaxChunks;
 constexpr int kInflight = pwbf::serve::Core::kMaxInflight;  // device regions: the most
 
 // Batches on the device at once, four by default: with two, a request whose
-// upload finished while two batches ran waited for one of them, and at 5000
-// requests/s that wait made the admit-to-launch leg's p99 (0.74-0.79 ms) exceed
-// the GPU leg's (0.65 ms); with four it is 0.66 against 0.72 ms, and the p99 at
-// 3500 requests/s fell from ~1.08 to 0.93 ms. PWBF_SERVE_INFLIGHT (1..4)
-// overrides it when a server is created.
+// upload finished while two batches ran waited for one of them before its
+// launch; with four it launches and waits in the device queue instead, so the
+// upload leg stays the shorter part of a request's latency up to the rates
+// where the device itself saturates. PWBF_SERVE_INFLIGHT (1..4) overrides it
+// when a server is created.
 int serve_inflight() {
   const char *v = getenv("PWBF_SERVE_INFLIGHT");
   const int k = v ? atoi(v) : kInflight;
