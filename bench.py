@@ -420,8 +420,11 @@ def fk_stage_bytes(gs, rf_bytes: int, method: str = "stolt") -> float:
 def fk_mode(dev, torch, steps: int, warmup: int) -> dict:
     """Stolt's and Lu's f-k migrations on the 11-angle compound workload (FP32 RF,
     1024 x 1024 pixels): the whole call (six kernels over all angles at once,
-    plus the log image), timed with HIP events around each call; the path is
-    HBM-bound, so the roofline is the staged traffic per call over the call time."""
+    plus the log image), timed with HIP events around each call, with the staged
+    traffic per call over the call time as an HBM fraction. That roofline does
+    not bind these calls: counter passes put them at 0.56 (Stolt) and 0.71 (Lu)
+    of the VALU issue peak over their kernels, Lu's remap at 0.87
+    (profiles/fk_c3_compound_f32.sq.md)."""
     from paper_2311_00482_amd import GeometryArg, fk_migrate, fk_workspace_bytes
     from synth import config_c3, make_frame
 
@@ -445,7 +448,9 @@ def fk_mode(dev, torch, steps: int, warmup: int) -> dict:
                      "roofline": {"bound": "hbm", "achieved": b / (ms * 1e-3) / 1e9,
                                   "peak": HBM_PEAK / 1e9, "unit": "GB/s",
                                   "frac": b / (ms * 1e-3) / HBM_PEAK, "bytes_per_call": b,
-                                  "scope": "whole call (six kernels + log image)"},
+                                  "scope": "whole call (six kernels + log image)",
+                                  "binding": "VALU issue (counter passes in "
+                                             "profiles/fk_c3_compound_f32.sq.md), not HBM"},
                      "workspace_bytes": int(ws.numel()), "rf_storage": "f32"}
         print(f"[bench] {name}: {ms:.3f} ms per call, "
               f"frac {res[name]['roofline']['frac']:.2f}", file=sys.stderr, flush=True)
