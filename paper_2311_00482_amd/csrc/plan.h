@@ -33,18 +33,22 @@ enum Mode : int32_t { kDas = 0, kDmas = 1, kPdas = 2, kIqdas = 3, kBbdmas = 4 };
 
 PWBF_HD constexpr bool is_iq_mode(int mode) { return mode == kIqdas || mode == kBbdmas; }
 
-// Longest LDS window per (channel, angle), in entries. The kernel holds every
-// per-gather delay as a float32 offset centred on its window, so its rounding
-// grows with the window: 64 entries keep the offsets below 32 samples (2^-19 of
-// a sample resolution), which holds DAS and IQ-DAS within 1e-5 of the float64
-// definition. DMAS, pDAS and BB-DMAS take a root of each delayed sample, steep
-// where the sample crosses zero, so a delay error there is amplified; their
-// windows are held to 32 entries (offsets below 16 samples). Longer windows are
-// refused (shallower or narrower tiles keep them short).
+// Longest LDS window per (channel, angle), in entries. DAS, IQ-DAS and BB-DMAS
+// hold every per-gather delay as a float32 offset centred on their tile's
+// window, so its rounding grows with the window: 64 entries keep the offsets
+// below 32 samples (2^-19 of a sample resolution), which holds DAS and IQ-DAS
+// within 1e-5 of the float64 definition; BB-DMAS takes a root of each delayed
+// sample's amplitude, steep near zero, so a delay error there is amplified,
+// and its windows are held to 32 entries (offsets below 16 samples). DMAS and
+// pDAS measure their delays from their wavefront's centre pixel instead (the
+// window origin enters only through integer shifts), so their rounding follows
+// the lane group's extent (kRootOffsetAuto below), not the window, and they
+// take windows up to the 64 entries the LDS layout plans for. Longer windows
+// are refused (shallower or narrower tiles keep them short).
 constexpr int kMaxWindow = 64;
 constexpr int kMaxWindowRoot = 32;
 PWBF_HD constexpr int max_window(int mode) {
-  return (mode == kDmas || mode == kPdas || mode == kBbdmas) ? kMaxWindowRoot : kMaxWindow;
+  return mode == kBbdmas ? kMaxWindowRoot : kMaxWindow;
 }
 
 // DMAS and pDAS form every delay as a float32 offset from their wavefront's

@@ -73,6 +73,9 @@ SMALL = [
     ("dmas_ragged_cpw2", dict(nx=63, nz=231, n_channels=12), "dmas", 0, (2, 16, 1, 4, 4),
      "f32"),
     ("dmas_compound_5a", dict(angles_deg=(-10., -5., 0., 5., 10.)), "dmas", -1, None, "i16"),
+    # DMAS windows past 32 entries (40 here): delays are measured from each
+    # wavefront's centre pixel, so the window's length does not enter them
+    ("dmas_window_40", dict(), "dmas", 0, (16, 2, 1, 8, 0), "f32"),
     ("dmas_compound_generic", dict(angles_deg=tuple(range(-18, 18, 2)), nx=7, nz=40,
                                    n_channels=6), "dmas", -1, (8, 4, 1, 1, 0), "f32"),
 ]
@@ -94,8 +97,6 @@ REFUSED = [
      (1, 16, 2, 2, 0)),
     ("dmas_generic_4x8", dict(angles_deg=tuple(range(-18, 18, 2)), nx=7, nz=40, n_channels=6),
      "dmas", -1, (4, 4, 1, 2, 0)),
-    # the root-taking beamformers stop at 32 entries; DAS takes this one
-    ("dmas_ragged_16x8_64", dict(nx=21, nz=77, n_channels=12), "dmas", 0, (2, 16, 1, 4, 4)),
     ("bbdmas_16x16_60", dict(n_samples=512), "bbdmas", 0, (1, 16, 1, 4, 0)),
     ("pdas_64_deep_column", dict(nz=64, z_min=3e-3, z_max=13e-3, nx=5), "pdas", 0,
      (1, 64, 1, 1, 0)),

@@ -52,6 +52,9 @@ PDAS_SMALL = [
      2.0, "f32"),
     ("p2_compound_3a_f32", dict(angles_deg=(-8.0, 0.0, 8.0), n_channels=32), -1, None, 2.0,
      "f32"),
+    # a window of 44 entries (past the 32 that BB-DMAS keeps to)
+    ("p2_compound_3a_window_44", dict(angles_deg=(-8.0, 0.0, 8.0), n_channels=24), -1,
+     (16, 2, 1, 8, 0), 2.0, "f32"),
 ]
 
 
