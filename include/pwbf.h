@@ -100,11 +100,9 @@ extern "C" {
  * DAS, IQ-DAS and BB-DMAS kernels hold every per-gather delay as a float32
  * offset centred on its tile's window, so the delay's rounding grows with the
  * window. 64 entries keep those offsets under 32 samples (2^-19 of a sample
- * resolution), which holds DAS and IQ-DAS within 1e-5 of the float64
- * definition (max-normalised); BB-DMAS takes a root of every delayed sample's
- * amplitude, steep near zero, so it is held to 32 entries (offsets under 16
- * samples). DMAS and pDAS measure delays from their wavefront's centre pixel
- * (below), so their windows may take the 64 entries. A tile's window spans
+ * resolution), which holds them within 1e-5 of the float64 definition
+ * (max-normalised). DMAS and pDAS measure delays from their wavefront's centre
+ * pixel (below). A tile's window spans
  * about |sin th| TX DX + |cos th| TZ DZ + hypot(TX DX, TZ DZ) + 6 samples (DX,
  * DZ: pixel pitches times fs / c); explicit shapes needing more are refused
  * with PWBF_E_UNSUPPORTED, and default plans pick a smaller tile. A grid whose
@@ -112,7 +110,6 @@ extern "C" {
  * group needs DZ + hypot(DX, DZ) + 6 within the limit) is refused the same
  * way. */
 #define PWBF_MAX_WINDOW 64
-#define PWBF_MAX_WINDOW_ROOT 32 /* BB-DMAS */
 /* DMAS and pDAS take each delay relative to their wavefront's centre pixel.
  * The shapes the library picks itself (default, fallback, tuner) keep every
  * gather within 5.5 samples of that pixel's delay whenever some shape does:

@@ -97,7 +97,6 @@ REFUSED = [
      (1, 16, 2, 2, 0)),
     ("dmas_generic_4x8", dict(angles_deg=tuple(range(-18, 18, 2)), nx=7, nz=40, n_channels=6),
      "dmas", -1, (4, 4, 1, 2, 0)),
-    ("bbdmas_16x16_60", dict(n_samples=512), "bbdmas", 0, (1, 16, 1, 4, 0)),
     ("pdas_64_deep_column", dict(nz=64, z_min=3e-3, z_max=13e-3, nx=5), "pdas", 0,
      (1, 64, 1, 1, 0)),
 ]
