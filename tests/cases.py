@@ -73,7 +73,7 @@ SMALL = [
     ("dmas_ragged_cpw2", dict(nx=63, nz=231, n_channels=12), "dmas", 0, (2, 16, 1, 4, 4),
      "f32"),
     ("dmas_compound_5a", dict(angles_deg=(-10., -5., 0., 5., 10.)), "dmas", -1, None, "i16"),
-    # DMAS windows past 32 entries (40 here): delays are measured from each
+    # a DMAS window of 40 entries: delays are measured from each
     # wavefront's centre pixel, so the window's length does not enter them
     ("dmas_window_40", dict(), "dmas", 0, (16, 2, 1, 8, 0), "f32"),
     ("dmas_compound_generic", dict(angles_deg=tuple(range(-18, 18, 2)), nx=7, nz=40,

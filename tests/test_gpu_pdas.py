@@ -52,7 +52,8 @@ PDAS_SMALL = [
      2.0, "f32"),
     ("p2_compound_3a_f32", dict(angles_deg=(-8.0, 0.0, 8.0), n_channels=32), -1, None, 2.0,
      "f32"),
-    # a window of 44 entries (past the 32 that BB-DMAS keeps to)
+    # a window of 44 entries (pDAS measures delays from each wavefront's centre
+    # pixel, so the window's length does not enter them)
     ("p2_compound_3a_window_44", dict(angles_deg=(-8.0, 0.0, 8.0), n_channels=24), -1,
      (16, 2, 1, 8, 0), 2.0, "f32"),
 ]
