@@ -188,9 +188,14 @@ pwbf_tile default_tile(const pwbf_geometry *g, int n_angles_used, int mode) {
   pwbf_tile t;
   int64_t pixels = (int64_t)g->nx * g->nz;
   t.cpw = pixels >= 256 * 1024 ? 1 : (pixels >= 64 * 1024 ? 2 : 4);
-  t.lz = t.cpw == 1 ? 8 : 16;  // one group: 8 x 8 pixels per wavefront, 2 x 4 wavefronts
-  t.wz = t.cpw == 1 ? 2 : 1;
-  t.wx = t.cpw == 1 ? 4 : 8;
+  // one group: 8 x 8 pixels per wavefront, 4 x 2 wavefronts, a tile 32 pixels
+  // deep and 16 wide. A narrower tile reaches fewer channels (its active
+  // aperture is the pixels' apertures widened by the tile's width), so on the
+  // 11-angle 1024 x 1024 frame it beats 16 x 32 by 4-6% (DAS 104 against 110
+  // us, pDAS 215 against 225 us).
+  t.lz = t.cpw == 1 ? 8 : 16;
+  t.wz = t.cpw == 1 ? 4 : 1;
+  t.wx = t.cpw == 1 ? 2 : 8;
   t.chunk = 0;
   return t;
 }
@@ -387,6 +392,14 @@ static int plan_frame_uncached(const pwbf_geometry *g, int dtype, int mode, int 
     if (!done && (!waves || d.wz * d.wx == waves)) {
       done = fit_tile(g, d, P, err) == PWBF_OK && root_compact(g, *P);
       source = "default";
+      if (!done && d.cpw == 1) {
+        // the 32 x 16 tile's window can pass the limit where 16 x 32 fits
+        // (pixels deeper than they are wide, in samples): that one next
+        pwbf_tile wide = d;
+        wide.wz = 2;
+        wide.wx = 4;
+        done = fit_tile(g, wide, P, err) == PWBF_OK && root_compact(g, *P);
+      }
     }
     if (!done) {
       source = "fallback";
