@@ -365,6 +365,11 @@ static int plan_frame_uncached(const pwbf_geometry *g, int dtype, int mode, int 
   // when that does not fit (LDS or window length), the fitting shape with the
   // most pixels per tile, then the shortest window, then the fewest lane groups.
   pwbf_tile d = default_tile(g, na, mode);
+  // Batch and serving kernels (8-wavefront plans) take their tiles in cost
+  // order across frames instead of the single-frame kernel's depth-ordered,
+  // XCD-balanced order; there the 16 x 32 tile is the faster one (8 compound
+  // frames per launch: 9586 against 9355 frames/s for 32 x 16).
+  if (waves && d.cpw == 1) std::swap(d.wz, d.wx);
   const bool zero_tile = tile_in && !tile_in->cpw && !tile_in->lz && !tile_in->wz &&
                          !tile_in->wx && !tile_in->chunk;
   if (zero_tile) tile_in = nullptr;
@@ -393,12 +398,11 @@ static int plan_frame_uncached(const pwbf_geometry *g, int dtype, int mode, int 
       done = fit_tile(g, d, P, err) == PWBF_OK && root_compact(g, *P);
       source = "default";
       if (!done && d.cpw == 1) {
-        // the 32 x 16 tile's window can pass the limit where 16 x 32 fits
-        // (pixels deeper than they are wide, in samples): that one next
-        pwbf_tile wide = d;
-        wide.wz = 2;
-        wide.wx = 4;
-        done = fit_tile(g, wide, P, err) == PWBF_OK && root_compact(g, *P);
+        // one tile's window can pass the limit where the other orientation
+        // fits (pixels much deeper or wider than each other, in samples)
+        pwbf_tile other = d;
+        std::swap(other.wz, other.wx);
+        done = fit_tile(g, other, P, err) == PWBF_OK && root_compact(g, *P);
       }
     }
     if (!done) {
