@@ -188,13 +188,15 @@ pwbf_tile default_tile(const pwbf_geometry *g, int n_angles_used, int mode) {
   pwbf_tile t;
   int64_t pixels = (int64_t)g->nx * g->nz;
   t.cpw = pixels >= 256 * 1024 ? 1 : (pixels >= 64 * 1024 ? 2 : 4);
-  // one group: 8 x 8 pixels per wavefront, 4 x 2 wavefronts, a tile 32 pixels
-  // deep and 16 wide. A narrower tile reaches fewer channels (its active
-  // aperture is the pixels' apertures widened by the tile's width), so on the
-  // 11-angle 1024 x 1024 frame it beats 16 x 32 by 4-6% (DAS 104 against 110
-  // us, pDAS 215 against 225 us).
+  // one group: 8 x 8 pixels per wavefront. A narrower tile reaches fewer
+  // channels (its active aperture is the pixels' apertures widened by the
+  // tile's width): from a million pixels on, 4 x 2 wavefronts (a tile 32
+  // pixels deep and 16 wide; on the 11-angle 1024 x 1024 frame 4-6% faster
+  // than 16 x 32: DAS 104 against 110 us, pDAS 215 against 225 us); below,
+  // 2 x 2 (16 x 16, twice the blocks; on the 512 x 512 frame 3-5% faster than
+  // 32 x 16: DMAS 17.2 against 17.9 us, DAS 14.8 against 15.4 us).
   t.lz = t.cpw == 1 ? 8 : 16;
-  t.wz = t.cpw == 1 ? 4 : 1;
+  t.wz = t.cpw == 1 ? (pixels >= 1024 * 1024 ? 4 : 2) : 1;
   t.wx = t.cpw == 1 ? 2 : 8;
   t.chunk = 0;
   return t;
@@ -369,7 +371,10 @@ static int plan_frame_uncached(const pwbf_geometry *g, int dtype, int mode, int 
   // order across frames instead of the single-frame kernel's depth-ordered,
   // XCD-balanced order; there the 16 x 32 tile is the faster one (8 compound
   // frames per launch: 9586 against 9355 frames/s for 32 x 16).
-  if (waves && d.cpw == 1) std::swap(d.wz, d.wx);
+  if (waves && d.cpw == 1) {
+    d.wz = 2;
+    d.wx = 4;
+  }
   const bool zero_tile = tile_in && !tile_in->cpw && !tile_in->lz && !tile_in->wz &&
                          !tile_in->wx && !tile_in->chunk;
   if (zero_tile) tile_in = nullptr;
