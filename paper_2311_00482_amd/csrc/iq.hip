@@ -34,15 +34,15 @@ __device__ __forceinline__ float rf_sample(const void *rf, size_t i) {
 constexpr int kIqMaxPerThread = 4096 / kPostThreads;  // samples of a record per thread
 
 // exp(-2 pi i r k): the carrier phase at sample k in revolutions, from r as a
-// float-float pair (the FMA gives the exact error of the rounded product)
+// float-float pair (the FMA gives the exact error of the rounded product); the
+// hardware sine and cosine take their argument in revolutions, as the IQ
+// beamformer's phase rotation does
 __device__ __forceinline__ float2 carrier(int k, float r_hi, float r_lo) {
   const float fk = (float)k;
   const float p = fk * r_hi;
   const float e = fmaf(fk, r_hi, -p);  // exact error of the product
   const float rho = (p - floorf(p)) + fmaf(fk, r_lo, e);
-  float sn, cs;
-  sincospif(-2.0f * rho, &sn, &cs);
-  return make_float2(cs, sn);
+  return make_float2(__builtin_amdgcn_cosf(rho), -__builtin_amdgcn_sinf(rho));
 }
 
 template <int DT>
