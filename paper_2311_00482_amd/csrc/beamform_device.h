@@ -284,6 +284,9 @@ __device__ __forceinline__ ff ff_sqrt(ff a) {
 }
 __device__ __forceinline__ float ff_f(ff a) { return a.hi + a.lo; }
 
+// a compile-time flag handed to the generic lambdas of the channel loop
+template <bool B> struct Flag { static constexpr bool value = B; };
+
 // AM: angles handled per pixel; PRED: AM is an upper bound and angles >= A are
 // skipped (generic bucket), else exactly AM == A angles, fully unrolled.
 // ONEGRP: one lane group per wavefront (cpw == 1), so the LDS window of a
@@ -551,7 +554,12 @@ __device__ __forceinline__ void process_tile_body(const FramePlan &P, int tz, in
     __syncthreads();
 
     const int wstride = win * P.entry_bytes;  // bytes between angle windows
-    auto channel = [&](int k) __attribute__((always_inline)) {
+    // SQ: pDAS with p = 2 (square root in place of exp2/log2). The test is
+    // uniform over the kernel; taking it once per chunk rather than per
+    // channel keeps the angle sums in the same registers through the channel
+    // loop (a per-channel branch made the compiler copy all of them at its
+    // join, two moves per angle and channel)
+    auto channel = [&](int k, auto sq) __attribute__((always_inline)) {
       const int c = ONEGRP ? k : k + grp;
       const int slot = wave * chunk + c;
       const float4 ch = WREF ? s_chw[slot] : s_ch[c];
@@ -613,9 +621,9 @@ __device__ __forceinline__ void process_tile_body(const FramePlan &P, int tz, in
       } else if constexpr (MODE == kPdas) {
         // sign(v) |v|^(1/p) = sign(v) 2^(log2|v| / p); |v| = 0 gives 2^-inf = 0.
         // p = 2 takes the square root instead: one transcendental operation per
-        // gather instead of two (the branch is uniform over the block)
+        // gather instead of two
         const float ip = P.pdas_inv_p;
-        if (P.pdas_p == 2.0f) {
+        if constexpr (decltype(sq)::value) {
 #pragma unroll
           for (int a = 0; a < AM; ++a) {
             if (!PRED || a < A) {
@@ -663,15 +671,25 @@ __device__ __forceinline__ void process_tile_body(const FramePlan &P, int tz, in
     // channel's table and window reads are in flight while the first computes
     // (one channel is a chain of two dependent LDS round trips, and a small
     // grid leaves few wavefronts per SIMD to hide them)
-    if constexpr (AM <= 2 && !PRED) {
-      int k = 0;
-      for (; k + cpw < cnt; k += 2 * cpw) {
-        channel(k);
-        channel(k + cpw);
+    auto channels = [&](auto sq) __attribute__((always_inline)) {
+      if constexpr (AM <= 2 && !PRED) {
+        int k = 0;
+        for (; k + cpw < cnt; k += 2 * cpw) {
+          channel(k, sq);
+          channel(k + cpw, sq);
+        }
+        if (k < cnt) channel(k, sq);
+      } else {
+        for (int k = 0; k < cnt; k += cpw) channel(k, sq);
       }
-      if (k < cnt) channel(k);
+    };
+    if constexpr (MODE == kPdas) {
+      if (P.pdas_p == 2.0f)
+        channels(Flag<true>{});
+      else
+        channels(Flag<false>{});
     } else {
-      for (int k = 0; k < cnt; k += cpw) channel(k);
+      channels(Flag<false>{});
     }
   }
 
