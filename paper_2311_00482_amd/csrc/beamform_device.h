@@ -608,9 +608,13 @@ __device__ __forceinline__ void process_tile_body(const FramePlan &P, int tz, in
             const float I = fmaf(s, q.y, q.x), Qv = fmaf(s, q.w, q.z);  // the lines at s
             float cx = Rx, cy = Ry;
             if constexpr (MODE == kBbdmas) {
-              // sqrt(amplitude), phase kept: scale by |q|^(-1/2) (0 for q = 0)
-              const float m2 = fmaf(I, I, Qv * Qv);
-              const float k = m2 > 0.f ? __builtin_amdgcn_rsqf(__builtin_amdgcn_sqrtf(m2)) : 0.f;
+              // sqrt(amplitude), phase kept: scale by |q|^(-1/2). |q|^2 carries
+              // the smallest normal float, 2^-126, so that q = 0 gives a finite
+              // scale (at most 2^31.5) times a zero sample, with no test and
+              // select; above |q| = 2^-50 the added term lies below the float32
+              // rounding of |q|^2
+              const float m2 = fmaf(I, I, fmaf(Qv, Qv, 0x1p-126f));
+              const float k = __builtin_amdgcn_rsqf(__builtin_amdgcn_sqrtf(m2));
               cx *= k;
               cy *= k;
             }
