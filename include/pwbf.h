@@ -112,8 +112,8 @@ extern "C" {
 #define PWBF_MAX_WINDOW 64
 /* DMAS and pDAS take each delay relative to their wavefront's centre pixel.
  * The shapes the library picks itself (default, fallback, tuner) keep every
- * gather within 5.5 samples of that pixel's delay whenever some shape does:
- * 2 (lz / 2) DZ + (lx / 2) DX (max |sin th| + 1 / sqrt(1 + 4 F#^2)) <= 5.5 for
+ * gather within 4 samples of that pixel's delay whenever some shape does:
+ * 2 (lz / 2) DZ + (lx / 2) DX (max |sin th| + 1 / sqrt(1 + 4 F#^2)) <= 4 for
  * lane groups of lz x lx pixels (halves rounded down; the last term 1 without
  * apodization), which bounds the float32 rounding of their delays. Explicit
  * shapes are taken as given. */

@@ -43,27 +43,10 @@ PWBF_HD constexpr bool is_iq_mode(int mode) { return mode == kIqdas || mode == k
 // 2.0e-6 at windows of 28, 36 and 48 entries). DMAS and pDAS measure their
 // delays from their wavefront's centre pixel instead (the window origin enters
 // only through integer shifts), so their rounding follows the lane group's
-// extent (kRootOffsetAuto below), not the window. Longer windows are refused
+// extent (the planner bounds it), not the window. Longer windows are refused
 // (shallower or narrower tiles keep them short).
 constexpr int kMaxWindow = 64;
 PWBF_HD constexpr int max_window(int) { return kMaxWindow; }
-
-// DMAS and pDAS form every delay as a float32 offset from their wavefront's
-// centre pixel (whose own delay is split exactly into an integer and a
-// fraction), so a gather's delay rounding grows with that offset, and their
-// root amplifies it at near-zero delayed samples. For lane groups of lz x lx
-// pixels the offset is at most
-//   2 hz + hx (max |sin th_a| + sin phi_max)   samples,
-// hz, hx the largest depth and lateral distance (samples) from the centre
-// pixel (lz / 2 and lx / 2 pixels, rounded down) and sin phi_max the sine of
-// the widest receive angle with a nonzero weight (1 / sqrt(1 + 4 F#^2), or 1
-// without apodization): transmit and receive each move by at most |dz| in
-// depth. The shapes the library picks itself (default, fallback, tuner) keep
-// it within kRootOffsetAuto whenever some shape does: on uniform-noise RF of
-// a 1024 x 256, 64-channel frame, 32-pixel-deep lane groups (10.5 samples)
-// were 2.4e-5 off the float64 definition where 8- and 16-pixel ones (2.9,
-// 5.4) were 2.0e-6 and 4.9e-6. Explicit shapes are taken as given.
-constexpr double kRootOffsetAuto = 5.5;
 
 enum Apod : int32_t { kHann = 0, kBoxcar = 1, kNone = 2 };
 

@@ -30,6 +30,24 @@ int plan_frame(const pwbf_geometry *g, int dtype, int mode, int angle, const pwb
 int build_plan(const pwbf_geometry *g, const void *rf, int dtype, int mode, int angle,
                const pwbf_tile *tile, const pwbf_outputs *o, void *ws, size_t ws_bytes,
                FramePlan *P, std::string *err);
+// DMAS and pDAS form every delay as a float32 offset from their wavefront's
+// centre pixel (whose own delay is split exactly into an integer and a
+// fraction), so a gather's delay rounding grows with that offset, and their
+// root amplifies it at near-zero delayed samples. For lane groups of lz x lx
+// pixels the offset is at most
+//   2 hz + hx (max |sin th_a| + sin phi_max)   samples,
+// hz, hx the largest depth and lateral distance (samples) from the centre
+// pixel (lz / 2 and lx / 2 pixels, rounded down) and sin phi_max the sine of
+// the widest receive angle with a nonzero weight (1 / sqrt(1 + 4 F#^2), or 1
+// without apodization): transmit and receive each move by at most |dz| in
+// depth. The shapes the library picks itself (default, fallback, tuner) keep
+// it within kRootOffsetAuto whenever some shape does. On uniform-noise RF of
+// 1024 x 256, 64-channel frames, 32-pixel-deep lane groups (10.5 samples)
+// were 2.4e-5 off the float64 definition, 16-pixel-deep ones (5.3 - 5.4)
+// 4.9e-6 to 9.7e-6 depending on the noise, 8-pixel-deep ones (2.9) 2.0e-6 to
+// 3.7e-6: the error grows with the offset, so the bound sits at 4 samples.
+// Explicit shapes are taken as given.
+constexpr double kRootOffsetAuto = 4.0;
 // DMAS and pDAS: whether plan P's lane groups keep every gather within
 // kRootOffsetAuto samples of its wavefront's reference pixel (other modes: true)
 bool root_compact(const pwbf_geometry *g, const FramePlan &P);

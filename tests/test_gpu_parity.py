@@ -294,6 +294,53 @@ def test_root_modes_white_noise_automatic_shapes():
             assert e <= max(TOL32, 5.0 * floor), (seed, mode, e, floor)
 
 
+def test_dmas_white_noise_every_shape_the_library_may_pick():
+    # DMAS on the benchmark's uniform-noise int16 RF of its one-angle 64-channel
+    # 1024 x 256 frame (frame 19 of the uneven batch) in every launch shape
+    # the tuner may choose for it: lane groups whose gathers stay within 4
+    # samples of their wavefront's reference pixel, in every wavefront
+    # arrangement that plans. Each image is within 1e-5 of the float64
+    # definition, or five times the definition's own move under a
+    # 3e-8-sample delay shift, whichever is larger.
+    import dataclasses
+    from paper_2311_00482_amd import GeometryArg, Tile, _abi, describe_plan
+    from synth import config_c4_frames
+    from test_window_bounds import _root_offset_bound
+    torch = _torch()
+    frames = config_c4_frames()
+    gs = frames[19].geom
+    gen = torch.Generator().manual_seed(2000)
+    for sp in frames[:20]:
+        shape = (sp.geom.n_angles, sp.geom.n_channels, sp.geom.n_samples)
+        rf = torch.randint(-511, 512, shape, generator=gen, dtype=torch.int16).numpy()
+    ref = oracle.dmas(gs, rf, -1, "identity", parallel=True)
+    moved = oracle.dmas(dataclasses.replace(gs, t0=(3e-8 / gs.fs,)), rf, -1, "identity",
+                        parallel=True)
+    floor = err(moved, ref)
+    bar = max(TOL32, 5.0 * floor)
+    g = GeometryArg(gs)
+    rf_t = to_dev(rf)
+    shapes = []
+    for cpw in (1, 2, 4):
+        for lz in (2, 4, 8, 16, 32):
+            if lz > 64 // cpw or _root_offset_bound(gs, -1, cpw, lz) > 4.0:
+                continue
+            for wz, wx in ((1, 8), (2, 4), (4, 2), (8, 1), (1, 4)):
+                t = Tile(cpw, lz, wz, wx, 0)
+                try:
+                    describe_plan(g, "dmas", -1, t)
+                except _abi.PwbfError:
+                    continue  # its windows exceed the limit: refused, never picked
+                shapes.append(t)
+    assert len(shapes) >= 40
+    worst = 0.0
+    for t in shapes:
+        e = err(run(g, rf_t, "dmas", -1, ("rf",), t)["rf"], ref)
+        worst = max(worst, e)
+        assert e <= bar, (t, e, bar)
+    print(f"white noise, {len(shapes)} shapes: worst {worst:.2e} (definition's move {floor:.2e})")
+
+
 def test_tile_sweep_same_image():
     from paper_2311_00482_amd import Tile
     g = TILE_SWEEP

@@ -275,7 +275,7 @@ def _root_offset_bound(g, angle, cpw, lz):
 
 def test_root_modes_pick_compact_lane_groups():
     # the shapes DMAS and pDAS plans pick themselves keep every gather within
-    # 5.5 samples of its wavefront's reference pixel (re-derived here from the
+    # 4 samples of its wavefront's reference pixel (re-derived here from the
     # geometry) when some shape does; an explicit tall shape is taken as given;
     # a grid on which no shape is that compact still plans (the best fitting)
     specs = [(config_c2(), "dmas"), (config_c2(), "pdas"), (config_c3(), "pdas"),
@@ -283,7 +283,7 @@ def test_root_modes_pick_compact_lane_groups():
     specs += [(s.geom, s.mode) for s in config_c4_frames() if s.mode != "das"]
     for g, mode in specs:
         p = describe_plan(g, mode, -1, None)
-        assert _root_offset_bound(g, -1, p["cpw"], p["lz"]) <= 5.5 + 1e-9, (g.name, p)
+        assert _root_offset_bound(g, -1, p["cpw"], p["lz"]) <= 4.0 + 1e-9, (g.name, p)
     f21 = config_c4_frames()[21].geom
     assert _root_offset_bound(f21, -1, 1, 32) > 10.0
     p = describe_plan(f21, "dmas", -1, Tile(1, 32, 1, 8, 0))
@@ -292,10 +292,10 @@ def test_root_modes_pick_compact_lane_groups():
     # takes) fits the window but reaches 7.3 samples: DMAS plans a flatter one
     small = geom(n_channels=32, nx=64, nz=256)
     assert describe_plan(small, "das", 0, None)["lz"] == 16
-    assert _root_offset_bound(small, 0, 4, 16) > 5.5
+    assert _root_offset_bound(small, 0, 4, 16) > 4.0
     describe_plan(small, "dmas", 0, Tile(4, 16, 1, 8, 0))  # accepted when explicit
     p = describe_plan(small, "dmas", 0, None)
-    assert _root_offset_bound(small, 0, p["cpw"], p["lz"]) <= 5.5
+    assert _root_offset_bound(small, 0, p["cpw"], p["lz"]) <= 4.0
     coarse = geom(n_channels=12, nx=21, nz=77)  # pixels 3.7 x 1.5 samples
     p = describe_plan(coarse, "dmas", 0, None)
     assert _root_offset_bound(coarse, 0, p["cpw"], p["lz"]) > 0
