@@ -12,7 +12,18 @@ the limit is refused (PWBF_E_UNSUPPORTED) and counted, never compared. Every
 other image is compared whole with the oracle at the FP32 bar, 1e-5 of the
 oracle image's maximum (complex planes for the IQ modes), on band-limited
 speckle RF like the fixed cases.
+
+Boxcar apodization decides each (pixel, channel) pair's membership by a
+threshold, |x - x_e| < z / (2 F#), and its weight jumps from 0 to 1 there: a
+pair within float32 rounding of the edge may fall on either side in the
+kernel (float32) and in the oracle (float64), and either image is the
+definition at the edge. For boxcar cases each pixel is therefore compared
+with the closest of the oracle images at F# and F# (1 +- 2e-6), which moves
+only pairs within 2e-6 of the edge (the kernel's decision is accurate to a
+few float32 roundings, ~3e-7).
 """
+
+import dataclasses
 
 import numpy as np
 import pytest
@@ -25,7 +36,8 @@ from cases import rand_rf
 pytestmark = pytest.mark.gpu
 
 TOL32 = 1e-5
-N_CASES = 40
+N_CASES = 120
+BOXCAR_EDGE = 2e-6
 MODES = ("das", "dmas", "pdas", "iqdas", "bbdmas")
 
 
@@ -67,6 +79,29 @@ def _cerr(gpu, ora):
     return float(np.abs(gpu - ora).max() / m) if m > 0 else float(np.abs(gpu).max())
 
 
+def oracle_image(g, mode, angle, p, rf64):
+    if mode in ("iqdas", "bbdmas"):
+        return oracle.iq_beamform(g, oracle.iq_demodulate(g, rf64), mode, angle)
+    if mode == "das":
+        return oracle.das(g, rf64, angle, parallel=True)
+    if mode == "dmas":
+        return oracle.dmas(g, rf64, angle, "identity", parallel=True)
+    return oracle.pdas(g, rf64, angle, p, parallel=True)
+
+
+def sweep_error(g, mode, angle, p, rf64, got):
+    """Max-normalised error against the oracle; for boxcar apodization per
+    pixel against the closest of the images at F# and F# (1 +- BOXCAR_EDGE)."""
+    ref = oracle_image(g, mode, angle, p, rf64)
+    m = np.abs(ref).max()
+    d = np.abs(got - ref)
+    if g.apod == "boxcar":
+        for s in (-1.0, 1.0):
+            gs = dataclasses.replace(g, f_number=g.f_number * (1.0 + s * BOXCAR_EDGE))
+            d = np.minimum(d, np.abs(got - oracle_image(gs, mode, angle, p, rf64)))
+    return float(d.max() / m) if m > 0 else float(np.abs(got).max())
+
+
 @pytest.mark.parametrize("i", range(N_CASES))
 def test_random_geometry_whole_image(i):
     import torch
@@ -81,23 +116,15 @@ def test_random_geometry_whole_image(i):
         pytest.skip(f"{g.name}: refused ({e})")
     rf = rand_rf(g, 100 + i, kind)
     rf_t = torch.from_numpy(np.ascontiguousarray(rf)).cuda()
-    rf64 = rf.astype(np.float64)
     if mode in ("iqdas", "bbdmas"):
         out = beamform(ga, iq_demodulate(ga, rf_t), mode, angle, want=("rf", "imag"))
         torch.cuda.synchronize()
         got = out["rf"].cpu().numpy().astype(np.float64) + 1j * out["imag"].cpu().numpy()
-        ref = oracle.iq_beamform(g, oracle.iq_demodulate(g, rf64), mode, angle)
     else:
         out = beamform(ga, rf_t, mode, angle, want=("rf",))
         torch.cuda.synchronize()
         got = out["rf"].cpu().numpy().astype(np.float64)
-        if mode == "das":
-            ref = oracle.das(g, rf64, angle, parallel=True)
-        elif mode == "dmas":
-            ref = oracle.dmas(g, rf64, angle, "identity", parallel=True)
-        else:
-            ref = oracle.pdas(g, rf64, angle, p, parallel=True)
-    e = _cerr(got, ref)
+    e = sweep_error(g, mode, angle, p, rf.astype(np.float64), got)
     shape = (plan["cpw"], plan["lz"], plan["wz"], plan["wx"])
     print(f"{g.name}: {g.n_channels} ch, {g.n_angles} angles (angle {angle}), "
           f"{g.nx} x {g.nz}, {g.apod}, {kind}, p {p:.3f}, shape {shape}: {e:.2e}")
