@@ -261,7 +261,14 @@ static int fit_tile(const pwbf_geometry *g, pwbf_tile t, FramePlan *P, std::stri
   P->tile_x = TX;
   // a tile's pixels never extend past the grid (edge lanes repeat the edge pixel)
   P->win = window_entries(*P, std::min(TZ, g->nz), std::min(TX, g->nx));
-  const int wmax = max_window(P->mode);
+  int wmax = max_window(P->mode);
+  // IQ modes: a delay rounding of d samples turns the carrier's phase by
+  // 2 pi r d (r = f0 / fs in cycles per record sample), so above a quarter
+  // cycle per sample (decimated records) the windows shrink to keep r times
+  // the window within 16, the 64-entry limit's product at r = 1/4 (decimated
+  // BB-DMAS at r = 1 with 48- and 56-entry windows measured 1.5e-5 and 2.0e-5)
+  if (is_iq_mode(P->mode) && P->iq_r > 0.25f)
+    wmax = std::min(wmax, std::max(4, (int)(16.0f / P->iq_r) / 4 * 4));
   if (P->win > wmax)
     return fail(err, PWBF_E_UNSUPPORTED,
                 "tile of %d x %d pixels needs LDS windows of %d entries (limit %d for this "
@@ -543,7 +550,9 @@ int build_plan(const pwbf_geometry *g, const void *rf, int dtype, int mode, int 
     return fail(err, PWBF_E_INVALID, "rf not aligned to its element size");
   rc = validate_outputs(g, o, ws, ws_bytes, err, mode);
   if (rc) return rc;
-  const size_t slab = (size_t)g->n_channels * g->n_samples * dtype_bytes(dtype);
+  // one angle's records as the plan reads them: decimated baseband records
+  // hold n_samples / D samples each, not the caller's n_samples
+  const size_t slab = (size_t)g->n_channels * P->n_samples * dtype_bytes(dtype);
   P->rf = (const char *)rf + (size_t)(angle < 0 ? 0 : angle) * slab;
   P->out = o->rf;
   P->ws_max = o->logimg ? (uint32_t *)ws : nullptr;

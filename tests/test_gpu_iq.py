@@ -126,6 +126,13 @@ IQ_DECIMATED = [
     ("bbdmas_compound_5a_d2", dict(n_samples=1024, angles_deg=(-10., -5., 0., 5., 10.),
                                    n_channels=20), "bbdmas", -1, 2),
     ("iqdas_one_angle_d8", dict(n_samples=1024, n_channels=24), "iqdas", 0, 8),
+    # one angle other than the first: its records start at angle x channels x
+    # (n_samples / D) entries (angle x D >= n_angles here, so the full-rate
+    # offset would start past the end of the decimated records)
+    ("iqdas_angle2_of_3_d4", dict(n_samples=512, angles_deg=(-9.0, 0.0, 7.0), nx=21, nz=77),
+     "iqdas", 2, 4),
+    ("bbdmas_angle1_of_2_d2", dict(n_samples=1024, angles_deg=(-6.0, 5.0), n_channels=20),
+     "bbdmas", 1, 2),
 ]
 
 

@@ -139,11 +139,6 @@ DECIMATED = [i for i in range(N_CASES)
              if draw_case(i, True)[1] in ("iqdas", "bbdmas") and draw_case(i, True)[5] > 1]
 
 
-@pytest.mark.skip(reason="the first GPU run of these 37 decimated IQ cases, in one process with "
-                         "the 83 other cases of the sweep, ended with the GPU faulted and every "
-                         "test from the 87th on failing; the cause is not found (every gather of "
-                         "their plans stays inside its LDS window, re-derived on the CPU, and the "
-                         "oracle evaluates all of them), so they stay off the GPU until it is")
 @pytest.mark.parametrize("i", DECIMATED)
 def test_random_geometry_decimated_iq(i):
     import torch
