@@ -101,8 +101,12 @@ extern "C" {
  * offset centred on its tile's window, so the delay's rounding grows with the
  * window. 64 entries keep those offsets under 32 samples (2^-19 of a sample
  * resolution), which holds them within 1e-5 of the float64 definition
- * (max-normalised). DMAS and pDAS measure delays from their wavefront's centre
- * pixel (below). A tile's window spans
+ * (max-normalised). In the IQ modes a delay rounding of d samples also turns
+ * the carrier's phase by 2 pi r d, r = f0 / fs in cycles per record sample
+ * (f0 D / fs for records decimated by D), so there the limit is
+ * min(64, 16 / r) entries, rounded down to a multiple of 4: 32 at D = 2 and
+ * 16 at D = 4 for f0 = fs / 4. DMAS and pDAS measure delays from their
+ * wavefront's centre pixel (below). A tile's window spans
  * about |sin th| TX DX + |cos th| TZ DZ + hypot(TX DX, TZ DZ) + 6 samples (DX,
  * DZ: pixel pitches times fs / c); explicit shapes needing more are refused
  * with PWBF_E_UNSUPPORTED, and default plans pick a smaller tile. A grid whose
