@@ -312,11 +312,44 @@ void fuzz_tune(const char *dir) {
 
 }  // namespace
 
+// One angle's records start at angle x channels x (the plan's record length)
+// entries: n_samples for RF, n_samples / D for IQ records decimated by D.
+void check_single_angle_offsets() {
+  int checked = 0, decimated = 0;
+  for (int it = 0; it < 4000 && checked < 300; ++it) {
+    Geo G = make_geo(false);
+    pwbf_geometry &g = G.g;
+    const bool iq = chance(0.5);
+    const int D = iq ? 1 << pick(3) : 1;
+    g.iq_decimation = D;
+    const int mode = iq ? (chance(0.5) ? pwbf::kIqdas : pwbf::kBbdmas) : pwbf::kDas;
+    const int dtype = iq ? pwbf::kC32 : pwbf::kF32;
+    const int angle = pick(g.n_angles);
+    alignas(16) static float plane[4];
+    alignas(16) static char base[16];
+    pwbf_outputs o;
+    std::memset(&o, 0, sizeof o);
+    o.rf = plane;
+    pwbf::FramePlan P;
+    std::string err;
+    if (pwbf::build_plan(&g, base, dtype, mode, angle, nullptr, &o, nullptr, 0, &P, &err) !=
+        PWBF_OK)
+      continue;
+    const int rec = g.n_samples / D;
+    CHECK(P.n_samples == rec);
+    CHECK((const char *)P.rf == base + (size_t)angle * g.n_channels * rec * (iq ? 8 : 4));
+    ++checked;
+    decimated += D > 1 && angle > 0;
+  }
+  CHECK(checked >= 100 && decimated >= 20);
+}
+
 int main(int argc, char **argv) {
   const int iters = argc > 1 ? std::atoi(argv[1]) : 20000;
   const char *dir = argc > 2 ? argv[2] : ".";
   fuzz_plans(iters);
   fuzz_tune(dir);
+  check_single_angle_offsets();
   std::puts("all ok");
   return 0;
 }
